@@ -1,0 +1,172 @@
+/*
+ * mds.h -- C ABI of the MI355X (gfx950) random-projection classical MDS library.
+ *
+ * Method (Blanchard et al., "A geometric view of Biodiversity: scaling to
+ * metagenomics", Inria RR-9144):
+ *   - Sec. 6.2, step 1: Gram matrix by double centring of the squared
+ *     distances, gamma_ij = -1/2 (d_ij^2 - c_j - r_i + m) with r_i, c_j the
+ *     row/column means of d^2 and m their grand mean.
+ *   - Sec. 3.2-3.3: approximate rank-k eigendecomposition of G by random
+ *     projection (the randomized range finder of Halko, Martinsson and Tropp,
+ *     2011): Gaussian test matrix Omega (n x l, l = k + oversample), q power
+ *     iterations (each = two applications of G, orthonormalised after each
+ *     application), then Rayleigh-Ritz on B = Q^T G Q.
+ *   - Sec. 6.2, steps 2-3: eigenpairs in descending algebraic order and
+ *     coordinates X = U diag(sqrt(max(lambda, 0))), first k columns.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers named "dev" or documented as device memory must be device
+ *     allocations valid on the current HIP device; the library never frees
+ *     caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued on it; calls return once work is enqueued.
+ *   - Errors are reported by status code only; no exception crosses the ABI.
+ *     mds_last_error() gives a thread-local text for the last failure.
+ *   - Argument errors are detected on the host before any device call.
+ *   - A plan is not thread-safe: calls on one plan must be serialised, and
+ *     two runs of one plan on different streams must not overlap.
+ */
+#ifndef MDS_H_
+#define MDS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mds_status {
+  MDS_OK = 0,
+  MDS_PENDING = 1,
+  MDS_ERR_INVALID_ARG = -1, /* bad size, pointer or option */
+  MDS_ERR_NO_DEVICE = -2,   /* no HIP device visible */
+  MDS_ERR_OOM = -3,         /* device allocation failed */
+  MDS_ERR_BUDGET = -4,      /* job can never fit the server's memory budget */
+  MDS_ERR_NONFINITE = -5,   /* D holds NaN or Inf (detected by the centring sums) */
+  MDS_ERR_NUMERICAL = -6,   /* eigensolver did not converge */
+  MDS_ERR_HIP = -7,         /* a HIP runtime call or kernel launch failed */
+  MDS_ERR_CANCELLED = -8,   /* job cancelled before it ran */
+  MDS_ERR_STATE = -9        /* call not valid in the plan's current state */
+} mds_status;
+
+/* Arithmetic form of the G-passes (dtype of the stored Gram matrix).
+ *   FP64: G fp64, fp64 MFMA.
+ *   FP32: G fp32, fp32 MFMA.
+ *   BF16: G bf16 (rounded from fp64 through fp32), bf16 MFMA with fp32
+ *         accumulation for the 2q+1 range passes; the projection pass
+ *         ("refinement") uses an fp32 copy of G and fp32 MFMA.
+ * In every form the centring sums, CholeskyQR2, the Gram products of the
+ * tall matrices and the small eigensolve run in fp64. */
+typedef enum mds_form { MDS_FORM_FP64 = 0, MDS_FORM_FP32 = 1, MDS_FORM_BF16 = 2 } mds_form;
+
+/* Element type of the caller's distance matrix D. */
+typedef enum mds_dtype { MDS_DTYPE_F32 = 0, MDS_DTYPE_F64 = 1 } mds_dtype;
+
+typedef struct mds_opts {
+  int32_t form;        /* mds_form (default MDS_FORM_FP32) */
+  int32_t d_dtype;     /* mds_dtype (default MDS_DTYPE_F32) */
+  int32_t gpass_split; /* K-splits of the G-pass, 0 = automatic */
+  int32_t reserved;    /* must be 0 */
+} mds_opts;
+
+typedef struct mds_plan_s* mds_plan_t;
+
+/* Largest oversampled rank l = k + oversample supported. */
+#define MDS_MAX_L 256
+
+/* Create a plan for n points, k output axes, `oversample` extra sketch
+ * columns, q power iterations and the seed of the test matrix.  Valid:
+ * n >= 2, k >= 1, oversample >= 0, q >= 0, k + oversample <= min(n, MDS_MAX_L).
+ * Makes no device call.  *out receives an opaque handle owned by the caller
+ * (free with mds_destroy).  mds_plan uses default options. */
+mds_status mds_plan(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample, int32_t q, uint64_t seed);
+mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample, int32_t q, uint64_t seed,
+                       const mds_opts* opts);
+
+/* Device workspace needed by mds_run, in bytes (host-only computation). */
+mds_status mds_workspace_size(mds_plan_t plan, size_t* bytes);
+
+/* Hand the plan a caller-owned device buffer of at least mds_workspace_size
+ * bytes (e.g. allocated by PyTorch).  It must stay valid while any run of the
+ * plan is in flight.  Without it, the first run allocates the workspace with
+ * hipMalloc and mds_destroy frees it. */
+mds_status mds_set_workspace(mds_plan_t plan, void* dev_ptr, size_t bytes);
+
+/* Run the whole method on `stream`:
+ *   D       device, n x n row-major (ld = n), dtype from the plan options;
+ *           a finite metric: symmetric with zero diagonal is the contract,
+ *           the centring uses both row and column means as written.
+ *   coords  device, n x k row-major fp64: X = Q V_k diag(sqrt(max(theta,0))),
+ *           each column's entry of largest magnitude made positive.
+ *   eigvals device, k fp64: the k largest Ritz values, algebraic descending.
+ * Returns MDS_OK once enqueued.  Numerical outcome (non-finite input, solver
+ * convergence) is available from mds_get_info after the stream completes. */
+mds_status mds_run(mds_plan_t plan, const void* D, double* coords, double* eigvals, void* stream);
+
+/* Stages for partial runs (tests and diagnostics). */
+typedef enum mds_stage {
+  MDS_STAGE_CENTER = 1, /* stop after the centring pass (G, r, c, m ready) */
+  MDS_STAGE_OMEGA = 2,  /* ... after drawing Omega into the pass operand */
+  MDS_STAGE_RANGE = 3,  /* ... after `range_passes` orthonormalised G-applications */
+  MDS_STAGE_ALL = 100
+} mds_stage;
+
+/* Like mds_run, stopping after `stop_after`.  For MDS_STAGE_RANGE,
+ * range_passes is in [1, 2q+1]; coords/eigvals may be NULL unless
+ * stop_after == MDS_STAGE_ALL. */
+mds_status mds_run_stages(mds_plan_t plan, const void* D, double* coords, double* eigvals, void* stream,
+                          int32_t stop_after, int32_t range_passes);
+
+/* Internal buffers exposed read-only for inspection after a (partial) run. */
+typedef enum mds_buffer_id {
+  MDS_BUF_G = 0,       /* Gram matrix, n_pad x ldg, pass dtype */
+  MDS_BUF_GREF = 1,    /* fp32 copy of G (BF16 form only) */
+  MDS_BUF_ROWMEAN = 2, /* r, n fp64 */
+  MDS_BUF_COLMEAN = 3, /* c, n fp64 */
+  MDS_BUF_MEAN = 4,    /* m, 1 fp64 */
+  MDS_BUF_X = 5,       /* current G-pass operand, transposed l_pad x ldg */
+  MDS_BUF_Q = 6,       /* orthonormal basis, transposed l_pad x ldg fp64 */
+  MDS_BUF_Y = 7,       /* last G-pass product, transposed l_pad x ldg fp64 */
+  MDS_BUF_B = 8,       /* projected matrix Q^T G Q, l_pad x l_pad fp64 */
+  MDS_BUF_THETA = 9,   /* all l Ritz values, descending, fp64 */
+  MDS_BUF_V = 10       /* Ritz vectors in the Q basis, l x l (ld l_pad) fp64 */
+} mds_buffer_id;
+
+typedef struct mds_buffer {
+  void* ptr;      /* device pointer into the workspace */
+  int32_t dtype;  /* 0 fp64, 1 fp32, 2 bf16 */
+  int32_t pad_;
+  int64_t rows, cols, ld; /* logical shape and leading dimension (elements) */
+} mds_buffer;
+
+mds_status mds_get_buffer(mds_plan_t plan, int32_t which, mds_buffer* out);
+
+typedef struct mds_info {
+  int32_t status;            /* numerical outcome of the last run */
+  int32_t nonfinite;         /* 1 if D contained NaN/Inf */
+  int32_t orth_fallbacks;    /* orthonormalisations that used the eigen fallback */
+  int32_t jacobi_sweeps;     /* sweeps of the last small eigensolve */
+  int32_t jacobi_unconverged;
+  int32_t rank_deficient;    /* directions dropped by the last orthonormalisation */
+  int32_t k, l, l_pad, q, form, gpass_split;
+  int64_t n, ldg;
+  double sum_sq;             /* sum_ij d_ij^2 */
+  double frob2;              /* ||G||_F^2 (fp64, before storage rounding) */
+  double trace;              /* tr(G) */
+} mds_info;
+
+/* Synchronise `stream`, then report the plan's last-run diagnostics. */
+mds_status mds_get_info(mds_plan_t plan, mds_info* out, void* stream);
+
+void mds_destroy(mds_plan_t plan);
+const char* mds_status_string(mds_status s);
+const char* mds_last_error(void);
+/* Library version as "major.minor.patch". */
+const char* mds_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDS_H_ */

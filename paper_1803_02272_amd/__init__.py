@@ -1,0 +1,153 @@
+"""MI355X-native random-projection classical MDS.
+
+Python face of the HIP library ``libmds.so`` (C ABI in include/mds.h).  This
+module marshals arguments only: PyTorch supplies device memory and the
+stream; every step of the method runs in the library's kernels.
+
+    import torch, paper_1803_02272_amd as mds
+    plan = mds.Plan(n, k=100, oversample=20, q=2, seed=0, form="bf16")
+    coords, eigvals = plan.run(D)      # D: torch.cuda float32 n x n
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _capi
+from ._capi import MdsError, check
+
+__all__ = ["Plan", "MdsError", "library_version", "FORMS"]
+
+FORMS = _capi.FORMS
+
+
+def library_version() -> str:
+    return _capi.lib().mds_version().decode()
+
+
+def _stream_handle(stream):
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A plan for one problem shape: n points, k axes, oversample p, q power
+    iterations, test-matrix seed, G-pass form ("fp64" | "fp32" | "bf16") and
+    the dtype of D ("f32" | "f64")."""
+
+    def __init__(self, n, k, oversample=10, q=2, seed=0, form="fp32", d_dtype="f32", gpass_split=0,
+                 workspace="torch"):
+        L = _capi.lib()
+        self.n, self.k, self.oversample, self.q, self.seed = int(n), int(k), int(oversample), int(q), int(seed)
+        self.form = form
+        self.d_dtype = d_dtype
+        opts = _capi.MdsOpts(FORMS[form] if isinstance(form, str) else int(form),
+                             _capi.DTYPE_F64 if d_dtype in ("f64", "float64") else _capi.DTYPE_F32,
+                             int(gpass_split), 0)
+        h = ctypes.c_void_p()
+        check(L.mds_plan_ex(ctypes.byref(h), self.n, self.k, self.oversample, self.q, self.seed,
+                            ctypes.byref(opts)), "mds_plan_ex")
+        self._h = h
+        self._ws = None
+        self._workspace_mode = workspace
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _capi.lib().mds_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- workspace -----------------------------------------------------------
+    def workspace_size(self) -> int:
+        b = ctypes.c_size_t()
+        check(_capi.lib().mds_workspace_size(self._h, ctypes.byref(b)), "mds_workspace_size")
+        return int(b.value)
+
+    def attach_workspace(self, device=None):
+        """Allocate the workspace with PyTorch and hand it to the library."""
+        import torch
+
+        if self._ws is None:
+            nbytes = self.workspace_size()
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+            off = (-ws.data_ptr()) % 256
+            check(_capi.lib().mds_set_workspace(self._h, ctypes.c_void_p(ws.data_ptr() + off), nbytes),
+                  "mds_set_workspace")
+            self._ws = ws
+        return self._ws
+
+    # -- runs ----------------------------------------------------------------
+    def _check_D(self, D):
+        import torch
+
+        want = torch.float64 if self.d_dtype in ("f64", "float64") else torch.float32
+        if not (D.is_cuda and D.dtype == want and D.dim() == 2 and D.shape[0] == self.n
+                and D.shape[1] == self.n and D.is_contiguous()):
+            raise ValueError(f"D must be a contiguous cuda {want} tensor of shape ({self.n}, {self.n})")
+
+    def run(self, D, coords=None, eigvals=None, stream=None):
+        """Enqueue the full method; returns (coords n x k fp64, eigvals k fp64)."""
+        import torch
+
+        self._check_D(D)
+        if self._workspace_mode == "torch":
+            self.attach_workspace(D.device)
+        if coords is None:
+            coords = torch.empty((self.n, self.k), dtype=torch.float64, device=D.device)
+        if eigvals is None:
+            eigvals = torch.empty((self.k,), dtype=torch.float64, device=D.device)
+        check(_capi.lib().mds_run(self._h, ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(coords.data_ptr()),
+                                  ctypes.c_void_p(eigvals.data_ptr()), _stream_handle(stream)), "mds_run")
+        return coords, eigvals
+
+    def run_stages(self, D, stop_after, range_passes=0, coords=None, eigvals=None, stream=None):
+        self._check_D(D)
+        if self._workspace_mode == "torch":
+            self.attach_workspace(D.device)
+        cp = ctypes.c_void_p(coords.data_ptr()) if coords is not None else None
+        ep = ctypes.c_void_p(eigvals.data_ptr()) if eigvals is not None else None
+        check(_capi.lib().mds_run_stages(self._h, ctypes.c_void_p(D.data_ptr()), cp, ep, _stream_handle(stream),
+                                         int(stop_after), int(range_passes)), "mds_run_stages")
+
+    def buffer(self, which):
+        """View of an internal buffer (valid once the stream work that wrote
+        it has completed) as a torch tensor of its logical shape.  Needs the
+        torch-allocated workspace."""
+        import torch
+
+        if self._ws is None:
+            raise RuntimeError("buffer() needs a workspace attached with attach_workspace()")
+        b = _capi.MdsBuffer()
+        check(_capi.lib().mds_get_buffer(self._h, int(which), ctypes.byref(b)), "mds_get_buffer")
+        dt = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}[b.dtype]
+        esz = {0: 8, 1: 4, 2: 2}[b.dtype]
+        rows, cols, ld = b.rows, b.cols, b.ld
+        total = (rows - 1) * ld + cols if rows > 0 else 0
+        off = b.ptr - self._ws.data_ptr()
+        if off < 0 or off + total * esz > self._ws.numel():
+            raise RuntimeError("buffer outside the workspace")
+        flat = self._ws[off: off + total * esz].view(dt)
+        return flat.as_strided((rows, cols), (ld, 1))
+
+    def info(self, stream=None):
+        inf = _capi.MdsInfo()
+        check(_capi.lib().mds_get_info(self._h, ctypes.byref(inf), _stream_handle(stream)), "mds_get_info")
+        return inf.as_dict()

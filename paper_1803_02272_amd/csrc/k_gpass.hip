@@ -1,0 +1,292 @@
+// G-pass: Y = G X for the randomized range finder and the projection
+// (Sec. 3.2-3.3; every power iteration and the final Q^T (G Q) need one
+// product of the n x n Gram matrix with an n x l tall matrix).
+//
+// This is the bandwidth-dominant kernel of the method: each pass streams all
+// of G from HBM once while X is small and reused.  Design for gfx950:
+//   * MFMA 16x16 tiles: bf16 (16x16x32, fp32 accumulate), fp32 (16x16x4),
+//     fp64 (16x16x4).  Both operands are contiguous in K because G is
+//     row-major and X is stored transposed (l_pad x ldg).
+//   * A workgroup (4 waves) owns BM = 64 * RG rows of G and *all* l_pad
+//     columns of Y, so each G byte is loaded exactly once per pass.  Each wave
+//     streams its RG x 16 rows of G straight from HBM into MFMA A-operand
+//     registers (16 bytes per lane, one full 128-byte line per row per step),
+//     prefetching one step ahead.
+//   * The X tile of a step (l_pad x 128 bytes) is shared by the four waves
+//     through double-buffered LDS (rows padded to 144 bytes: conflict-free
+//     ds_read_b128 for the B operand).
+//   * Split-K with a deterministic fixed-order reduction (no atomics).  The
+//     split index is blockIdx % split: with split a multiple of 8, every
+//     workgroup on an XCD works on the same K range, so that XCD's slice of X
+//     stays in its own L2 while G streams past.
+#include "mds_internal.h"
+
+namespace mds {
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int GK>
+struct Tr;
+
+template <>
+struct Tr<GK_BF16> {
+  using T = bf16_t;
+  using Acc = floatx4_t;
+  using AccS = float;
+  static __device__ __forceinline__ void mma(Acc& c, const u32x4& a, const u32x4& b) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Tr<GK_F32> {
+  using T = float;
+  using Acc = floatx4_t;
+  using AccS = float;
+  // one 16-byte chunk holds 4 K-values per lane: four K=4 MFMAs, the t-th
+  // taking element t of every lane group (same K pairing for A and B)
+  static __device__ __forceinline__ void mma(Acc& c, const u32x4& a, const u32x4& b) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Tr<GK_F64> {
+  using T = double;
+  using Acc = doublex4_t;
+  using AccS = double;
+  static __device__ __forceinline__ void mma(Acc& c, const u32x4& a, const u32x4& b) {
+    const double a0 = __hiloint2double((int)a.y, (int)a.x), a1 = __hiloint2double((int)a.w, (int)a.z);
+    const double b0 = __hiloint2double((int)b.y, (int)b.x), b1 = __hiloint2double((int)b.w, (int)b.z);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c, 0, 0, 0);
+  }
+};
+
+constexpr int kRowB = 144;  // LDS bytes per X row within a step tile
+
+// 16-row groups per wave, chosen so accumulators + prefetched A operands fit
+// the register file at two workgroups per CU without spilling.
+__host__ __device__ constexpr int rg_for(int gk, int cg) {
+  return gk == GK_F64 ? (cg <= 3 ? 4 : (cg <= 7 ? 2 : 1)) : (cg <= 8 ? 4 : 2);
+}
+__host__ __device__ constexpr int minb_for(int gk, int cg) { return (gk == GK_F64 && cg >= 12) ? 1 : 2; }
+
+template <int GK, int RG, int CG>
+__global__ __launch_bounds__(256, minb_for(GK, CG)) void k_gpass(const typename Tr<GK>::T* __restrict__ G, int64_t ldg,
+                                                  const typename Tr<GK>::T* __restrict__ Xt, int split,
+                                                  int64_t steps_total, int64_t steps_per_split,
+                                                  typename Tr<GK>::AccS* __restrict__ Ypart) {
+  using TT = Tr<GK>;
+  using T = typename TT::T;
+  using Acc = typename TT::Acc;
+  using AccS = typename TT::AccS;
+  constexpr int LPAD = CG * 16;
+  constexpr int PIECES = LPAD * 8;  // 16-byte pieces per X step tile
+  constexpr int PPT = (PIECES + 255) / 256;
+  __shared__ __attribute__((aligned(16))) unsigned char xs[2][LPAD * kRowB];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t bid = blockIdx.x;
+  const int s = (int)(bid % split);
+  const int64_t mb = bid / split;
+  const int64_t row0 = mb * (64 * RG) + (int64_t)wave * (RG * 16);
+  const int64_t st0 = (int64_t)s * steps_per_split;
+  const int64_t st1 = (st0 + steps_per_split < steps_total) ? st0 + steps_per_split : steps_total;
+
+  Acc acc[RG][CG];
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[rg][cg][e] = 0;
+
+  const size_t rowbytes = (size_t)ldg * sizeof(T);
+  const unsigned char* Ab =
+      reinterpret_cast<const unsigned char*>(G) + (size_t)(row0 + (lane & 15)) * rowbytes + (lane >> 4) * 16;
+  const size_t rg_stride = 16 * rowbytes;
+  const unsigned char* Xb = reinterpret_cast<const unsigned char*>(Xt);
+
+  if (st0 < st1) {
+    u32x4 a[RG][2], an[RG][2];
+    u32x4 xr[PPT];
+    auto load_a = [&](u32x4 (&dst)[RG][2], int64_t st) {
+#pragma unroll
+      for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          dst[rg][c] = *reinterpret_cast<const u32x4*>(Ab + rg * rg_stride + (size_t)st * 128 + c * 64);
+    };
+    auto load_x = [&](int64_t st) {
+#pragma unroll
+      for (int u = 0; u < PPT; ++u) {
+        const int p = tid + 256 * u;
+        if (PIECES % 256 == 0 || p < PIECES)
+          xr[u] = *reinterpret_cast<const u32x4*>(Xb + (size_t)(p >> 3) * rowbytes + (size_t)st * 128 +
+                                                  (p & 7) * 16);
+      }
+    };
+    auto store_x = [&](unsigned char* buf) {
+#pragma unroll
+      for (int u = 0; u < PPT; ++u) {
+        const int p = tid + 256 * u;
+        if (PIECES % 256 == 0 || p < PIECES)
+          *reinterpret_cast<u32x4*>(buf + (p >> 3) * kRowB + (p & 7) * 16) = xr[u];
+      }
+    };
+
+    load_a(a, st0);
+    load_x(st0);
+    store_x(xs[0]);
+    __syncthreads();
+    for (int64_t st = st0; st < st1; ++st) {
+      const int buf = (int)((st - st0) & 1);
+      const bool more = st + 1 < st1;
+      if (more) {
+        load_x(st + 1);
+        load_a(an, st + 1);
+      }
+      const unsigned char* xb = xs[buf];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+#pragma unroll
+        for (int cg = 0; cg < CG; ++cg) {
+          const u32x4 b =
+              *reinterpret_cast<const u32x4*>(xb + (cg * 16 + (lane & 15)) * kRowB + c * 64 + (lane >> 4) * 16);
+#pragma unroll
+          for (int rg = 0; rg < RG; ++rg) TT::mma(acc[rg][cg], a[rg][c], b);
+        }
+      }
+      if (more) store_x(xs[buf ^ 1]);
+      __syncthreads();
+      if (more) {
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+          a[rg][0] = an[rg][0];
+          a[rg][1] = an[rg][1];
+        }
+      }
+    }
+  }
+
+  // C layout of a 16x16 MFMA tile: lane l holds rows 4*(l/16) .. +3 of column l%16,
+  // i.e. four consecutive entries of one row of the transposed output.
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg) {
+    const int64_t row = row0 + rg * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg) {
+      const int col = cg * 16 + (lane & 15);
+      AccS* dst = Ypart + ((int64_t)s * LPAD + col) * ldg + row;
+      if constexpr (sizeof(AccS) == 4) {
+        *reinterpret_cast<float4*>(dst) =
+            make_float4(acc[rg][cg][0], acc[rg][cg][1], acc[rg][cg][2], acc[rg][cg][3]);
+      } else {
+        reinterpret_cast<double2*>(dst)[0] = make_double2(acc[rg][cg][0], acc[rg][cg][1]);
+        reinterpret_cast<double2*>(dst)[1] = make_double2(acc[rg][cg][2], acc[rg][cg][3]);
+      }
+    }
+  }
+}
+
+template <typename AccS>
+__global__ __launch_bounds__(256) void k_splitk_reduce(const AccS* __restrict__ Yp, int split, int64_t elems,
+                                                       double* __restrict__ Y) {
+#pragma clang fp contract(off)
+  const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (e >= elems) return;  // elems is a multiple of 4
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (int k = 0; k < split; ++k) {
+    const AccS* p = Yp + (int64_t)k * elems + e;
+    s0 += (double)p[0];
+    s1 += (double)p[1];
+    s2 += (double)p[2];
+    s3 += (double)p[3];
+  }
+  reinterpret_cast<double2*>(Y + e)[0] = make_double2(s0, s1);
+  reinterpret_cast<double2*>(Y + e)[1] = make_double2(s2, s3);
+}
+
+template <int GK, int RG, int CG>
+void launch_one(const void* G, int64_t ldg, const void* Xt, const GPassCfg& cfg, int64_t n_pad, void* Yp,
+                hipStream_t s) {
+  using T = typename Tr<GK>::T;
+  using AccS = typename Tr<GK>::AccS;
+  const int64_t blocks = (n_pad / (64 * RG)) * cfg.split;
+  hipLaunchKernelGGL((k_gpass<GK, RG, CG>), dim3((unsigned)blocks), dim3(256), 0, s, (const T*)G, ldg,
+                     (const T*)Xt, cfg.split, cfg.steps_total, cfg.steps_per_split, (AccS*)Yp);
+}
+
+template <int GK, int CG>
+hipError_t launch_cg(const void* G, int64_t ldg, const void* Xt, const GPassCfg& cfg, int64_t n_pad, void* Yp,
+                     hipStream_t s) {
+  constexpr int RG = rg_for(GK, CG);
+  if (cfg.rg != RG) return hipErrorInvalidValue;
+  launch_one<GK, RG, CG>(G, ldg, Xt, cfg, n_pad, Yp, s);
+  return hipGetLastError();
+}
+
+template <int GK>
+hipError_t launch_gk(const void* G, int64_t ldg, const void* Xt, int l_pad, const GPassCfg& cfg, int64_t n_pad,
+                     void* Yp, hipStream_t s) {
+  switch (l_pad / 16) {
+#define MDS_CG(N) \
+  case N: return launch_cg<GK, N>(G, ldg, Xt, cfg, n_pad, Yp, s);
+    MDS_CG(1) MDS_CG(2) MDS_CG(3) MDS_CG(4) MDS_CG(5) MDS_CG(6) MDS_CG(7) MDS_CG(8)
+    MDS_CG(9) MDS_CG(10) MDS_CG(11) MDS_CG(12) MDS_CG(13) MDS_CG(14) MDS_CG(15) MDS_CG(16)
+#undef MDS_CG
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint) {
+  GPassCfg c{};
+  c.rg = rg_for(gk, l_pad / 16);
+  c.bm = 64 * c.rg;
+  const int64_t esize = gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : 2);
+  c.steps_total = ldg * esize / 128;
+  const int64_t row_blocks = n_pad / c.bm;
+  int64_t split = split_hint > 0 ? split_hint : (2048 + row_blocks - 1) / row_blocks;
+  int64_t max_split = c.steps_total / 16;
+  if (max_split < 1) max_split = 1;
+  if (split > max_split) split = max_split;
+  if (split >= 8 && split_hint <= 0) split = ((split + 7) / 8) * 8;
+  if (split < 1) split = 1;
+  c.split = (int)split;
+  c.steps_per_split = (c.steps_total + split - 1) / split;
+  return c;
+}
+
+hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const void* Xt, int l_pad,
+                        const GPassCfg& cfg, void* Ypart, hipStream_t s) {
+  if (l_pad % 16 != 0 || l_pad < 16 || l_pad > kMaxL || n_pad % cfg.bm != 0) return hipErrorInvalidValue;
+  switch (gk) {
+    case GK_F64: return launch_gk<GK_F64>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, s);
+    case GK_F32: return launch_gk<GK_F32>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, s);
+    case GK_BF16: return launch_gk<GK_BF16>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_splitk_reduce(int gk, const void* Ypart, int split, int64_t elems, double* Y, hipStream_t s) {
+  const unsigned blocks = (unsigned)((elems / 4 + 255) / 256);
+  if (gk == GK_F64)
+    hipLaunchKernelGGL(k_splitk_reduce<double>, dim3(blocks), dim3(256), 0, s, (const double*)Ypart, split,
+                       elems, Y);
+  else
+    hipLaunchKernelGGL(k_splitk_reduce<float>, dim3(blocks), dim3(256), 0, s, (const float*)Ypart, split,
+                       elems, Y);
+  return hipGetLastError();
+}
+
+}  // namespace mds

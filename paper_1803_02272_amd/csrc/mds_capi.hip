@@ -1,0 +1,421 @@
+// Host runtime behind the C ABI: plan validation, workspace layout and the
+// stream-ordered sequence of kernels that make up one run of
+// random-projection classical MDS (see include/mds.h).
+//
+// Sequence of one run (everything enqueued on the caller's stream):
+//   centring stats -> centring write (G in the pass dtype) -> Omega ->
+//   (2q+1) x [G-pass -> split-K reduce -> CholeskyQR2] ->
+//   projection G-pass -> B = Q^T (G Q) -> eigensolve -> coordinates.
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "../../include/mds.h"
+#include "mds_internal.h"
+
+using namespace mds;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mds_status fail(mds_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+mds_status fail(mds_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+int gk_size(int gk) { return gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : 2); }
+
+struct Region {
+  size_t off = 0, bytes = 0;
+};
+
+}  // namespace
+
+struct mds_plan_s {
+  int64_t n = 0, n_pad = 0, ldg = 0;
+  int k = 0, p = 0, q = 0, l = 0, l_pad = 0;
+  uint64_t seed = 0;
+  int form = MDS_FORM_FP32;
+  int d_dtype = MDS_DTYPE_F32;
+  int gk = GK_F32;      // dtype of G and of the range passes
+  int ref_gk = GK_F32;  // dtype of the projection pass
+  GPassCfg cfg{}, ref_cfg{};
+  // workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  Region G, Gref, rowpart, colpart, r, c, rsum, mean, fpart, X, Ypart, Y, Q1, Q, Wpart, W, T, B, V, theta, Tc,
+      small, sval, sidx, status;
+  size_t total = 0;
+  int last_stage = 0;
+
+  template <typename T>
+  T* at(const Region& reg) const {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + reg.off);
+  }
+};
+
+namespace {
+
+void add(mds_plan_s* P, Region& reg, size_t bytes) {
+  reg.off = P->total;
+  reg.bytes = bytes;
+  P->total += (size_t)round_up((int64_t)bytes, 256);
+}
+
+void layout(mds_plan_s* P) {
+  const int64_t n = P->n, n_pad = P->n_pad, ldg = P->ldg, lp = P->l_pad;
+  const size_t e = (size_t)gk_size(P->gk);
+  P->total = 0;
+  add(P, P->G, (size_t)n_pad * ldg * e);
+  add(P, P->Gref, P->form == MDS_FORM_BF16 ? (size_t)n_pad * ldg * 4 : 0);
+  const int64_t ncb = (n + kStatsCols - 1) / kStatsCols, nrb = (n + kStatsRows - 1) / kStatsRows;
+  add(P, P->rowpart, (size_t)ncb * n * 8);
+  add(P, P->colpart, (size_t)nrb * n * 8);
+  add(P, P->r, (size_t)n * 8);
+  add(P, P->c, (size_t)n * 8);
+  add(P, P->rsum, (size_t)n * 8);
+  add(P, P->mean, 8);
+  add(P, P->fpart, (size_t)center_write_blocks(n_pad, ldg) * 2 * 8);
+  const size_t xe = (size_t)(gk_size(P->gk) > gk_size(P->ref_gk) ? gk_size(P->gk) : gk_size(P->ref_gk));
+  add(P, P->X, (size_t)lp * ldg * xe);
+  const size_t acc_main = P->gk == GK_F64 ? 8 : 4, acc_ref = P->ref_gk == GK_F64 ? 8 : 4;
+  const size_t yp_main = (size_t)P->cfg.split * lp * ldg * acc_main;
+  const size_t yp_ref = (size_t)P->ref_cfg.split * lp * ldg * acc_ref;
+  add(P, P->Ypart, yp_main > yp_ref ? yp_main : yp_ref);
+  add(P, P->Y, (size_t)lp * ldg * 8);
+  add(P, P->Q1, (size_t)lp * ldg * 8);
+  add(P, P->Q, (size_t)lp * ldg * 8);
+  add(P, P->Wpart, (size_t)gram_chunks(ldg) * lp * lp * 8);
+  add(P, P->W, (size_t)lp * lp * 8);
+  add(P, P->T, (size_t)lp * lp * 8);
+  add(P, P->B, (size_t)lp * lp * 8);
+  add(P, P->V, (size_t)lp * lp * 8);
+  add(P, P->theta, (size_t)lp * 8);
+  add(P, P->Tc, (size_t)lp * P->k * 8);
+  add(P, P->small, (size_t)2 * lp * lp * 8);
+  const int64_t nblk = (n + 255) / 256;
+  add(P, P->sval, (size_t)(nblk * P->k + P->k) * 8);
+  add(P, P->sidx, (size_t)nblk * P->k * 8);
+  add(P, P->status, sizeof(DevStatus));
+}
+
+__global__ void k_status_init(DevStatus* st) {
+  DevStatus z = {};
+  *st = z;
+}
+
+mds_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return MDS_OK;
+  return fail(MDS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define MDS_TRY(expr, what)                          \
+  do {                                               \
+    mds_status _s = hip_check((expr), (what));       \
+    if (_s != MDS_OK) return _s;                     \
+  } while (0)
+
+mds_status device_present() {
+  int count = 0;
+  const hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= 0) return fail(MDS_ERR_NO_DEVICE, "no HIP device available");
+  return MDS_OK;
+}
+
+mds_status ensure_workspace(mds_plan_s* P) {
+  if (P->ws) return MDS_OK;
+  void* p = nullptr;
+  const hipError_t e = hipMalloc(&p, P->total);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(MDS_ERR_OOM, "hipMalloc(%zu bytes) failed", P->total);
+  }
+  P->ws = p;
+  P->ws_bytes = P->total;
+  P->ws_owned = true;
+  return MDS_OK;
+}
+
+// Orthonormalise the tall matrix Y (fp64, transposed) into Q by CholeskyQR2
+// (with the eigen fallback inside orth_factor); also cast Q into the operand
+// of the next G-pass with kind xk.
+mds_status orthonormalize(mds_plan_s* P, hipStream_t s, int xk) {
+  double* Y = P->at<double>(P->Y);
+  double* Q1 = P->at<double>(P->Q1);
+  double* Q = P->at<double>(P->Q);
+  double* W = P->at<double>(P->W);
+  double* T = P->at<double>(P->T);
+  double* Wp = P->at<double>(P->Wpart);
+  double* sm = P->at<double>(P->small);
+  DevStatus* st = P->at<DevStatus>(P->status);
+  MDS_TRY(launch_gram(Y, Y, P->l_pad, P->ldg, Wp, W, s), "gram(Y)");
+  MDS_TRY(launch_orth_factor(W, P->l, P->l_pad, T, sm, st, s), "orth_factor 1");
+  MDS_TRY(launch_apply(Y, P->l, P->ldg, T, P->l_pad, P->l, P->l_pad, Q1, -1, nullptr, s), "apply 1");
+  MDS_TRY(launch_gram(Q1, Q1, P->l_pad, P->ldg, Wp, W, s), "gram(Q1)");
+  MDS_TRY(launch_orth_factor(W, P->l, P->l_pad, T, sm, st, s), "orth_factor 2");
+  MDS_TRY(launch_apply(Q1, P->l, P->ldg, T, P->l_pad, P->l, P->l_pad, Q, xk, P->at<void>(P->X), s), "apply 2");
+  return MDS_OK;
+}
+
+mds_status gpass(mds_plan_s* P, hipStream_t s, bool ref) {
+  const int gk = ref ? P->ref_gk : P->gk;
+  const GPassCfg& cfg = ref ? P->ref_cfg : P->cfg;
+  const void* G = (ref && P->form == MDS_FORM_BF16) ? P->at<void>(P->Gref) : P->at<void>(P->G);
+  MDS_TRY(launch_gpass(gk, G, P->ldg, P->n_pad, P->at<void>(P->X), P->l_pad, cfg, P->at<void>(P->Ypart), s),
+          "gpass");
+  MDS_TRY(launch_splitk_reduce(gk, P->at<void>(P->Ypart), cfg.split, (int64_t)P->l_pad * P->ldg,
+                               P->at<double>(P->Y), s),
+          "splitk_reduce");
+  return MDS_OK;
+}
+
+mds_status run_impl(mds_plan_s* P, const void* D, double* coords, double* eigvals, hipStream_t s, int stop_after,
+                    int range_passes) {
+  mds_status st0 = device_present();
+  if (st0 != MDS_OK) return st0;
+  st0 = ensure_workspace(P);
+  if (st0 != MDS_OK) return st0;
+  DevStatus* st = P->at<DevStatus>(P->status);
+  P->last_stage = 0;
+  hipLaunchKernelGGL(k_status_init, dim3(1), dim3(1), 0, s, st);
+  MDS_TRY(hipGetLastError(), "status init");
+
+  MDS_TRY(launch_center_stats(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->at<double>(P->rowpart),
+                              P->at<double>(P->colpart), P->at<double>(P->r), P->at<double>(P->c),
+                              P->at<double>(P->rsum), P->at<double>(P->mean), st, s),
+          "centring stats");
+  MDS_TRY(launch_center_write(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->n_pad, P->ldg, P->at<double>(P->r),
+                              P->at<double>(P->c), P->at<double>(P->mean), P->gk, P->at<void>(P->G),
+                              P->form == MDS_FORM_BF16 ? P->at<float>(P->Gref) : nullptr,
+                              P->at<double>(P->fpart), st, s),
+          "centring write");
+  P->last_stage = MDS_STAGE_CENTER;
+  if (stop_after == MDS_STAGE_CENTER) return MDS_OK;
+
+  MDS_TRY(launch_omega(P->seed, P->n, P->l, P->l_pad, P->ldg, P->gk, P->at<void>(P->X), s), "omega");
+  P->last_stage = MDS_STAGE_OMEGA;
+  if (stop_after == MDS_STAGE_OMEGA) return MDS_OK;
+
+  const int total_range = 2 * P->q + 1;
+  const int passes = stop_after == MDS_STAGE_RANGE ? range_passes : total_range;
+  for (int it = 0; it < passes; ++it) {
+    mds_status e = gpass(P, s, false);
+    if (e != MDS_OK) return e;
+    const int next_xk = (it == total_range - 1) ? P->ref_gk : P->gk;
+    e = orthonormalize(P, s, next_xk);
+    if (e != MDS_OK) return e;
+  }
+  P->last_stage = MDS_STAGE_RANGE;
+  if (stop_after == MDS_STAGE_RANGE) return MDS_OK;
+
+  // projection: Y = G_ref Q, B = Q^T Y
+  mds_status e = gpass(P, s, true);
+  if (e != MDS_OK) return e;
+  MDS_TRY(launch_gram(P->at<double>(P->Q), P->at<double>(P->Y), P->l_pad, P->ldg, P->at<double>(P->Wpart),
+                      P->at<double>(P->B), s),
+          "gram(Q, GQ)");
+  MDS_TRY(launch_small_eig(P->at<double>(P->B), P->l, P->l_pad, P->k, P->at<double>(P->theta),
+                           P->at<double>(P->V), P->at<double>(P->Tc), eigvals, P->at<double>(P->small), st, s),
+          "small_eig");
+  MDS_TRY(launch_coords(P->at<double>(P->Q), P->l, P->n, P->ldg, P->at<double>(P->Tc), P->k, coords,
+                        P->at<double>(P->sval), P->at<int64_t>(P->sidx), s),
+          "coords");
+  P->last_stage = MDS_STAGE_ALL;
+  return MDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mds_version(void) { return "0.1.0"; }
+
+const char* mds_last_error(void) { return g_last_error.c_str(); }
+
+const char* mds_status_string(mds_status s) {
+  switch (s) {
+    case MDS_OK: return "ok";
+    case MDS_PENDING: return "pending";
+    case MDS_ERR_INVALID_ARG: return "invalid argument";
+    case MDS_ERR_NO_DEVICE: return "no device";
+    case MDS_ERR_OOM: return "out of device memory";
+    case MDS_ERR_BUDGET: return "exceeds memory budget";
+    case MDS_ERR_NONFINITE: return "non-finite input";
+    case MDS_ERR_NUMERICAL: return "numerical failure";
+    case MDS_ERR_HIP: return "HIP error";
+    case MDS_ERR_CANCELLED: return "cancelled";
+    case MDS_ERR_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample, int32_t q, uint64_t seed,
+                       const mds_opts* opts) {
+  if (!out) return fail(MDS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  mds_opts o = {MDS_FORM_FP32, MDS_DTYPE_F32, 0, 0};
+  if (opts) o = *opts;
+  if (n < 2) return fail(MDS_ERR_INVALID_ARG, "n = %lld < 2", (long long)n);
+  if (n > ((int64_t)1 << 24)) return fail(MDS_ERR_INVALID_ARG, "n = %lld too large", (long long)n);
+  if (k < 1) return fail(MDS_ERR_INVALID_ARG, "k = %d < 1", k);
+  if (oversample < 0) return fail(MDS_ERR_INVALID_ARG, "oversample = %d < 0", oversample);
+  if (q < 0) return fail(MDS_ERR_INVALID_ARG, "q = %d < 0", q);
+  const int64_t l = (int64_t)k + oversample;
+  if (l > n) return fail(MDS_ERR_INVALID_ARG, "k + oversample = %lld > n = %lld", (long long)l, (long long)n);
+  if (l > MDS_MAX_L) return fail(MDS_ERR_INVALID_ARG, "k + oversample = %lld > %d", (long long)l, MDS_MAX_L);
+  if (o.form < MDS_FORM_FP64 || o.form > MDS_FORM_BF16)
+    return fail(MDS_ERR_INVALID_ARG, "unknown form %d", o.form);
+  if (o.d_dtype != MDS_DTYPE_F32 && o.d_dtype != MDS_DTYPE_F64)
+    return fail(MDS_ERR_INVALID_ARG, "unknown D dtype %d", o.d_dtype);
+  if (o.gpass_split < 0 || o.reserved != 0) return fail(MDS_ERR_INVALID_ARG, "bad options");
+  mds_plan_s* P = new (std::nothrow) mds_plan_s();
+  if (!P) return fail(MDS_ERR_OOM, "host allocation failed");
+  P->n = n;
+  P->n_pad = round_up(n, kPadN);
+  P->ldg = P->n_pad;
+  P->k = k;
+  P->p = oversample;
+  P->q = q;
+  P->l = (int)l;
+  P->l_pad = (int)round_up(l, 16);
+  P->seed = seed;
+  P->form = o.form;
+  P->d_dtype = o.d_dtype;
+  P->gk = o.form == MDS_FORM_FP64 ? GK_F64 : (o.form == MDS_FORM_FP32 ? GK_F32 : GK_BF16);
+  P->ref_gk = o.form == MDS_FORM_BF16 ? GK_F32 : P->gk;
+  P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split);
+  P->ref_cfg = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split);
+  layout(P);
+  *out = P;
+  return MDS_OK;
+}
+
+mds_status mds_plan(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample, int32_t q, uint64_t seed) {
+  return mds_plan_ex(out, n, k, oversample, q, seed, nullptr);
+}
+
+mds_status mds_workspace_size(mds_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(MDS_ERR_INVALID_ARG, "NULL argument");
+  *bytes = plan->total;
+  return MDS_OK;
+}
+
+mds_status mds_set_workspace(mds_plan_t plan, void* dev_ptr, size_t bytes) {
+  if (!plan || !dev_ptr) return fail(MDS_ERR_INVALID_ARG, "NULL argument");
+  if (bytes < plan->total)
+    return fail(MDS_ERR_INVALID_ARG, "workspace of %zu bytes < required %zu", bytes, plan->total);
+  if (((uintptr_t)dev_ptr) % 256 != 0) return fail(MDS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (plan->ws_owned) {
+    (void)hipFree(plan->ws);
+    plan->ws_owned = false;
+  }
+  plan->ws = dev_ptr;
+  plan->ws_bytes = bytes;
+  return MDS_OK;
+}
+
+mds_status mds_run_stages(mds_plan_t plan, const void* D, double* coords, double* eigvals, void* stream,
+                          int32_t stop_after, int32_t range_passes) {
+  if (!plan || !D) return fail(MDS_ERR_INVALID_ARG, "NULL plan or D");
+  if (stop_after != MDS_STAGE_CENTER && stop_after != MDS_STAGE_OMEGA && stop_after != MDS_STAGE_RANGE &&
+      stop_after != MDS_STAGE_ALL)
+    return fail(MDS_ERR_INVALID_ARG, "unknown stage %d", stop_after);
+  if (stop_after == MDS_STAGE_RANGE && (range_passes < 1 || range_passes > 2 * plan->q + 1))
+    return fail(MDS_ERR_INVALID_ARG, "range_passes %d outside [1, %d]", range_passes, 2 * plan->q + 1);
+  if (stop_after == MDS_STAGE_ALL && (!coords || !eigvals))
+    return fail(MDS_ERR_INVALID_ARG, "NULL coords or eigvals");
+  return run_impl(plan, D, coords, eigvals, (hipStream_t)stream, stop_after, range_passes);
+}
+
+mds_status mds_run(mds_plan_t plan, const void* D, double* coords, double* eigvals, void* stream) {
+  return mds_run_stages(plan, D, coords, eigvals, stream, MDS_STAGE_ALL, 0);
+}
+
+mds_status mds_get_buffer(mds_plan_t plan, int32_t which, mds_buffer* out) {
+  if (!plan || !out) return fail(MDS_ERR_INVALID_ARG, "NULL argument");
+  if (!plan->ws) return fail(MDS_ERR_STATE, "plan has no workspace yet");
+  mds_buffer b = {};
+  const int64_t lp = plan->l_pad;
+  const int xdt = plan->gk == GK_F64 ? 0 : (plan->gk == GK_F32 ? 1 : 2);
+  switch (which) {
+    case MDS_BUF_G: b = {plan->at<void>(plan->G), xdt, 0, plan->n_pad, plan->ldg, plan->ldg}; break;
+    case MDS_BUF_GREF:
+      if (plan->form != MDS_FORM_BF16) return fail(MDS_ERR_INVALID_ARG, "no fp32 copy of G in this form");
+      b = {plan->at<void>(plan->Gref), 1, 0, plan->n_pad, plan->ldg, plan->ldg};
+      break;
+    case MDS_BUF_ROWMEAN: b = {plan->at<void>(plan->r), 0, 0, plan->n, 1, 1}; break;
+    case MDS_BUF_COLMEAN: b = {plan->at<void>(plan->c), 0, 0, plan->n, 1, 1}; break;
+    case MDS_BUF_MEAN: b = {plan->at<void>(plan->mean), 0, 0, 1, 1, 1}; break;
+    case MDS_BUF_X: {
+      // dtype of the operand depends on which pass wrote it last
+      int dt = xdt;
+      if (plan->last_stage >= MDS_STAGE_ALL && plan->ref_gk != plan->gk) dt = 1;
+      b = {plan->at<void>(plan->X), dt, 0, lp, plan->ldg, plan->ldg};
+      break;
+    }
+    case MDS_BUF_Q: b = {plan->at<void>(plan->Q), 0, 0, lp, plan->ldg, plan->ldg}; break;
+    case MDS_BUF_Y: b = {plan->at<void>(plan->Y), 0, 0, lp, plan->ldg, plan->ldg}; break;
+    case MDS_BUF_B: b = {plan->at<void>(plan->B), 0, 0, lp, lp, lp}; break;
+    case MDS_BUF_THETA: b = {plan->at<void>(plan->theta), 0, 0, plan->l, 1, 1}; break;
+    case MDS_BUF_V: b = {plan->at<void>(plan->V), 0, 0, plan->l, plan->l, lp}; break;
+    default: return fail(MDS_ERR_INVALID_ARG, "unknown buffer %d", which);
+  }
+  *out = b;
+  return MDS_OK;
+}
+
+mds_status mds_get_info(mds_plan_t plan, mds_info* out, void* stream) {
+  if (!plan || !out) return fail(MDS_ERR_INVALID_ARG, "NULL argument");
+  mds_info info = {};
+  info.k = plan->k;
+  info.l = plan->l;
+  info.l_pad = plan->l_pad;
+  info.q = plan->q;
+  info.form = plan->form;
+  info.gpass_split = plan->cfg.split;
+  info.n = plan->n;
+  info.ldg = plan->ldg;
+  info.status = MDS_OK;
+  if (plan->ws && plan->last_stage > 0) {
+    MDS_TRY(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+    DevStatus d = {};
+    MDS_TRY(hipMemcpy(&d, plan->at<void>(plan->status), sizeof(d), hipMemcpyDeviceToHost), "hipMemcpy status");
+    info.nonfinite = d.nonfinite;
+    info.orth_fallbacks = d.orth_fallbacks;
+    info.jacobi_sweeps = d.jacobi_sweeps;
+    info.jacobi_unconverged = d.jacobi_unconv;
+    info.rank_deficient = d.rank_deficient;
+    info.sum_sq = d.sum_sq;
+    info.frob2 = d.frob2;
+    info.trace = d.trace;
+    if (d.nonfinite)
+      info.status = MDS_ERR_NONFINITE;
+    else if (d.jacobi_unconv)
+      info.status = MDS_ERR_NUMERICAL;
+  }
+  *out = info;
+  return MDS_OK;
+}
+
+void mds_destroy(mds_plan_t plan) {
+  if (!plan) return;
+  if (plan->ws_owned && plan->ws) (void)hipFree(plan->ws);
+  delete plan;
+}
+
+}  // extern "C"

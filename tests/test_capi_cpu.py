@@ -1,0 +1,96 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/mds.h, validates arguments on the host, sizes the
+workspace, and reports MDS_ERR_NO_DEVICE instead of touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+torch = pytest.importorskip("torch")
+mds = pytest.importorskip("paper_1803_02272_amd")
+from paper_1803_02272_amd import _capi  # noqa: E402
+
+HEADER = os.path.join(ROOT, "include", "mds.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mds_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _capi.lib()
+    names = declared_functions()
+    assert "mds_plan" in names and "mds_run" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) <= set(_capi.SIGNATURES), set(names) - set(_capi.SIGNATURES)
+
+
+def _plan(n, k, p, q, form=1, dt=0, split=0, reserved=0):
+    L = _capi.lib()
+    h = ctypes.c_void_p()
+    opts = _capi.MdsOpts(form, dt, split, reserved)
+    st = L.mds_plan_ex(ctypes.byref(h), n, k, p, q, 0, ctypes.byref(opts))
+    return st, h
+
+
+@pytest.mark.parametrize("n,k,p,q", [(1, 1, 0, 0), (10, 0, 2, 1), (10, 2, -1, 1), (10, 2, 2, -1),
+                                     (10, 6, 5, 0), (100000, 200, 57, 2)])
+def test_invalid_arguments_rejected(n, k, p, q):
+    st, h = _plan(n, k, p, q)
+    assert st == _capi.ERR_INVALID_ARG
+    assert h.value is None
+    assert _capi.lib().mds_last_error().decode()
+
+
+def test_invalid_options_rejected():
+    assert _plan(100, 4, 4, 1, form=7)[0] == _capi.ERR_INVALID_ARG
+    assert _plan(100, 4, 4, 1, dt=5)[0] == _capi.ERR_INVALID_ARG
+    assert _plan(100, 4, 4, 1, reserved=1)[0] == _capi.ERR_INVALID_ARG
+
+
+def test_workspace_size_scales_with_form():
+    L = _capi.lib()
+    sizes = {}
+    for form in (0, 1, 2):
+        st, h = _plan(20000, 50, 10, 2, form=form)
+        assert st == _capi.OK
+        b = ctypes.c_size_t()
+        assert L.mds_workspace_size(h, ctypes.byref(b)) == _capi.OK
+        sizes[form] = b.value
+        L.mds_destroy(h)
+    npad = 20224
+    assert sizes[0] >= npad * npad * 8
+    assert npad * npad * 4 <= sizes[1] < npad * npad * 8
+    assert sizes[2] >= npad * npad * (2 + 4)  # bf16 G + fp32 refinement copy
+
+
+def test_run_without_device_reports_no_device():
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    L = _capi.lib()
+    st, h = _plan(64, 4, 4, 1)
+    assert st == _capi.OK
+    dummy = ctypes.c_void_p(0x1000)
+    assert L.mds_run(h, dummy, dummy, dummy, None) == _capi.ERR_NO_DEVICE
+    # argument errors are reported before any device query
+    assert L.mds_run(h, None, dummy, dummy, None) == _capi.ERR_INVALID_ARG
+    assert L.mds_run_stages(h, dummy, None, None, None, 3, 9) == _capi.ERR_INVALID_ARG
+    info = _capi.MdsInfo()
+    assert L.mds_get_info(h, ctypes.byref(info), None) == _capi.OK
+    assert info.l == 8 and info.l_pad == 16 and info.n == 64 and info.ldg == 256
+    buf = _capi.MdsBuffer()
+    assert L.mds_get_buffer(h, 0, ctypes.byref(buf)) == _capi.ERR_STATE
+    L.mds_destroy(h)
+
+
+def test_status_strings():
+    L = _capi.lib()
+    for code in range(-9, 2):
+        assert L.mds_status_string(code).decode()
+    assert L.mds_version().decode().count(".") == 2

@@ -1,0 +1,270 @@
+"""GPU parity: every stage of the HIP path against the FP64 CPU oracle on the
+same seeded inputs, through the C ABI.
+
+Sizes span several tiles of every kernel plus ragged tails (n not a multiple
+of 4, 256 or 1024; odd l; l above the LDS limit of the small kernels).
+Bars: fp64 form 1e-10 relative on eigenvalues, fp32 form 1e-5, bf16 form
+1e-3; coordinates after sign + orthogonal Procrustes alignment.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_util import bf16_round, procrustes_err, rel_eig_err, say, sign_aligned_err, span_cos_min
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - collected on CPU only
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1803_02272_amd as mds  # noqa: E402
+from paper_1803_02272_amd import _capi  # noqa: E402
+
+EIG_BAR = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 1e-3}
+COORD_BAR = {"fp64": 1e-8, "fp32": 1e-3, "bf16": 5e-2}
+
+
+def gm_case(n, dim, comps, var, seed, dtype):
+    X, _ = W.gaussian_mixture(n, dim, comps, var, seed)
+    return W.euclidean_distances(X, dtype=dtype)
+
+
+def amp_case(n, refs, seed):
+    reads, _ = W.amplicon_reads(n, refs, seed=seed)
+    return W.hamming_distances(reads)
+
+
+CASES = {
+    # name: (D builder, k, p, q)
+    "gm2000_f64": (lambda: gm_case(2000, 50, 10, 25.0, 0, np.float64), 10, 10, 1),
+    "amp1237_f32": (lambda: amp_case(1237, 20, 1), 12, 9, 2),
+    "amp3001_f32": (lambda: amp_case(3001, 40, 2), 40, 20, 1),
+}
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        build, k, p, q = CASES[name]
+        D = build()
+        _cache[name] = (D, k, p, q)
+    return _cache[name]
+
+
+def oracle_rand(name, seed=0, keep_history=False):
+    key = (name, seed, keep_history)
+    if key not in _cache:
+        D, k, p, q = case(name)
+        _cache[key] = O.rand_mds(D, k, p, q, seed, keep_history=keep_history)
+    return _cache[key]
+
+
+def dtype_of(D):
+    return "f64" if D.dtype == np.float64 else "f32"
+
+
+def gpu_run(D, k, p, q, seed, form, **kw):
+    plan = mds.Plan(D.shape[0], k, p, q, seed, form=form, d_dtype=dtype_of(D), **kw)
+    Dg = torch.from_numpy(np.ascontiguousarray(D)).cuda()
+    coords, eig = plan.run(Dg)
+    info = plan.info()
+    return plan, coords.cpu().numpy(), eig.cpu().numpy(), info
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16"])
+def test_centring_stage(name, form):
+    D, k, p, q = case(name)
+    n = D.shape[0]
+    say(f"[centring] case={name} n={n} form={form}")
+    plan = mds.Plan(n, k, p, q, 0, form=form, d_dtype=dtype_of(D))
+    Dg = torch.from_numpy(D).cuda()
+    plan.run_stages(Dg, _capi.STAGE_CENTER)
+    torch.cuda.synchronize()
+    r, c, m = O.centring_stats(D)
+    r_g = plan.buffer(_capi.BUF_ROWMEAN).double().cpu().numpy()[:, 0]
+    c_g = plan.buffer(_capi.BUF_COLMEAN).double().cpu().numpy()[:, 0]
+    m_g = float(plan.buffer(_capi.BUF_MEAN).cpu()[0, 0])
+    assert np.max(np.abs(r_g - r) / r) < 1e-13
+    assert np.max(np.abs(c_g - c) / c) < 1e-13
+    assert abs(m_g - m) / m < 1e-13
+    G = O.gram_matrix(D)
+    Gb = plan.buffer(_capi.BUF_G)
+    npad = Gb.shape[0]
+    Gg = Gb.double().cpu().numpy()
+    assert np.all(Gg[n:, :] == 0) and np.all(Gg[:, n:] == 0)  # zero padding
+    Gg = Gg[:n, :n]
+    scale = float(np.max(D.astype(np.float64) ** 2))
+    if form == "fp64":
+        assert np.max(np.abs(Gg - G)) <= 1e-13 * scale
+    elif form == "fp32":
+        want = G.astype(np.float32).astype(np.float64)
+        bad = Gg != want
+        assert bad.mean() < 1e-4  # only values on a rounding boundary may differ
+        assert np.max(np.abs(Gg - G)) <= 2.0 ** -23 * np.max(np.abs(G)) + 1e-13 * scale
+    else:
+        want = bf16_round(G).astype(np.float64)
+        bad = Gg != want
+        assert bad.mean() < 1e-4
+        assert np.max(np.abs(Gg - G) / np.maximum(np.abs(G), 1e-30 * scale)) <= 2.0 ** -8
+        Gr = plan.buffer(_capi.BUF_GREF).double().cpu().numpy()[:n, :n]
+        assert (Gr != G.astype(np.float32)).mean() < 1e-4
+    info = plan.info()
+    assert np.isclose(info["sum_sq"], np.sum(D.astype(np.float64) ** 2), rtol=1e-13)
+    assert np.isclose(info["frob2"], np.sum(G * G), rtol=1e-11)
+    assert np.isclose(info["trace"], np.trace(G), rtol=1e-11, atol=1e-12 * scale)
+    assert info["status"] == 0
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16"])
+def test_omega_stage(form):
+    D, k, p, q = case("amp1237_f32")
+    n = D.shape[0]
+    seed = 1234567
+    l = k + p
+    say(f"[omega] n={n} l={l} form={form}")
+    plan = mds.Plan(n, k, p, q, seed, form=form)
+    plan.run_stages(torch.from_numpy(D).cuda(), _capi.STAGE_OMEGA)
+    torch.cuda.synchronize()
+    Xt = plan.buffer(_capi.BUF_X).double().cpu().numpy()
+    Om = O.omega(seed, n, l)
+    got = Xt[:l, :n].T
+    if form == "fp64":
+        assert np.max(np.abs(got - Om) / np.maximum(1.0, np.abs(Om))) < 1e-14
+    elif form == "fp32":
+        assert np.max(np.abs(got - Om.astype(np.float32))) <= 2e-7 * np.max(np.abs(Om))
+    else:
+        assert np.mean(got != bf16_round(Om)) < 1e-3
+    assert np.all(Xt[l:, :] == 0) and np.all(Xt[:, n:] == 0)
+
+
+def test_range_passes_span_fp64():
+    name = "gm2000_f64"
+    D, k, p, q = case(name)
+    ref = oracle_rand(name, keep_history=True)
+    plan = mds.Plan(D.shape[0], k, p, q, 0, form="fp64", d_dtype="f64")
+    Dg = torch.from_numpy(D).cuda()
+    l = k + p
+    for passes in range(1, 2 * q + 2):
+        say(f"[range] case={name} passes={passes}")
+        plan.run_stages(Dg, _capi.STAGE_RANGE, passes)
+        torch.cuda.synchronize()
+        Qt = plan.buffer(_capi.BUF_Q).cpu().numpy()
+        Q = Qt[:l, : D.shape[0]].T
+        assert np.max(np.abs(Q.T @ Q - np.eye(l))) < 1e-12
+        assert np.all(Qt[l:] == 0)
+        assert span_cos_min(Q, ref["history"][passes - 1]) > 1 - 1e-10
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16"])
+def test_full_run_parity(name, form):
+    D, k, p, q = case(name)
+    say(f"[full] case={name} form={form}")
+    ref = oracle_rand(name)
+    plan, X, eig, info = gpu_run(D, k, p, q, 0, form)
+    assert info["status"] == 0, info
+    err = rel_eig_err(eig, ref["eigvals"])
+    cerr = procrustes_err(X, ref["coords"])
+    say(f"    eig rel err {err:.3e}  coords procrustes {cerr:.3e}  fallbacks {info['orth_fallbacks']}")
+    assert err < EIG_BAR[form]
+    assert cerr < COORD_BAR[form]
+    # theta and V are a Rayleigh-Ritz pair of the projected matrix
+    th = plan.buffer(_capi.BUF_THETA).cpu().numpy()[:, 0]
+    assert np.all(np.diff(th) <= 0)
+    assert np.allclose(th[:k], eig, rtol=0, atol=0)
+    # sign convention: largest-magnitude entry of each column is positive
+    idx = np.argmax(np.abs(X), axis=0)
+    assert np.all(X[idx, np.arange(k)] > 0)
+    if form == "fp64":
+        assert sign_aligned_err(X, ref["coords"]) < 1e-7
+
+
+def test_bitwise_repeatable():
+    D, k, p, q = case("amp1237_f32")
+    say("[repeat] amp1237 bf16 twice")
+    plan = mds.Plan(D.shape[0], k, p, q, 3, form="bf16")
+    Dg = torch.from_numpy(D).cuda()
+    c1, e1 = plan.run(Dg)
+    c1, e1 = c1.clone(), e1.clone()
+    c2, e2 = plan.run(Dg)
+    torch.cuda.synchronize()
+    assert torch.equal(c1, c2) and torch.equal(e1, e2)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+def test_zero_distance_matrix():
+    n, k, p = 300, 5, 5
+    say("[edge] all-zero D")
+    D = np.zeros((n, n), dtype=np.float32)
+    _, X, eig, info = gpu_run(D, k, p, 1, 0, "fp32")
+    assert info["status"] == 0
+    assert np.all(eig == 0) and np.all(X == 0)
+    assert info["orth_fallbacks"] > 0
+
+
+def test_nonfinite_input_flagged():
+    say("[edge] NaN in D")
+    D = amp_case(500, 5, 3)
+    D[17, 42] = np.nan
+    _, _, _, info = gpu_run(D, 4, 4, 1, 0, "fp32")
+    assert info["nonfinite"] == 1 and info["status"] == _capi.ERR_NONFINITE
+
+
+def test_rank_deficient_matches_exact():
+    say("[edge] rank 5 < l = 10")
+    X, _ = W.gaussian_mixture(500, 5, 3, 9.0, seed=4)
+    D = W.euclidean_distances(X)
+    full = O.full_mds(D, 4)
+    plan, Xg, eig, info = gpu_run(D, 4, 6, 1, 0, "fp64")
+    assert info["status"] == 0
+    assert info["orth_fallbacks"] > 0
+    assert rel_eig_err(eig, full["eigvals"]) < 1e-10
+    assert procrustes_err(Xg, full["coords"]) < 1e-8
+    # embedding of an exactly rank-5 cloud with k=4 < 5 keeps G_k = X_k X_k^T
+    assert np.allclose(Xg @ Xg.T, full["coords"] @ full["coords"].T, atol=1e-8 * full["eigvals"][0])
+
+
+@pytest.mark.parametrize("k,p,q", [(7, 6, 1), (10, 0, 1), (6, 6, 0), (1, 1, 2)])
+def test_shapes_odd_l_no_oversample_no_power(k, p, q):
+    say(f"[edge] k={k} p={p} q={q}")
+    D = amp_case(777, 15, 5)
+    ref = O.rand_mds(D, k, p, q, 9)
+    _, X, eig, info = gpu_run(D, k, p, q, 9, "fp64")
+    assert info["status"] == 0
+    assert rel_eig_err(eig, ref["eigvals"]) < 1e-10
+    assert procrustes_err(X, ref["coords"]) < 1e-8
+
+
+def test_large_l_global_scratch_path():
+    say("[edge] l = 140 > 128 (small kernels in global memory)")
+    D = amp_case(900, 160, 6)
+    k, p, q = 130, 10, 1
+    ref = O.rand_mds(D, k, p, q, 2)
+    _, X, eig, info = gpu_run(D, k, p, q, 2, "fp64")
+    assert info["status"] == 0
+    assert rel_eig_err(eig, ref["eigvals"]) < 1e-10
+    assert procrustes_err(X, ref["coords"]) < 1e-8
+
+
+def test_tiny_problem():
+    say("[edge] n = 2")
+    D = np.array([[0.0, 3.0], [3.0, 0.0]], dtype=np.float32)
+    _, X, eig, info = gpu_run(D, 1, 1, 1, 0, "fp64")
+    assert info["status"] == 0
+    assert np.isclose(eig[0], 4.5, rtol=1e-12)  # G = [[9/4, -9/4], [-9/4, 9/4]]
+    assert np.allclose(np.abs(X[:, 0]), 1.5, rtol=1e-12)
+
+
+def test_d_f64_with_bf16_form():
+    name = "gm2000_f64"
+    D, k, p, q = case(name)
+    say("[dtype] fp64 D, bf16 form")
+    ref = oracle_rand(name)
+    _, X, eig, info = gpu_run(D, k, p, q, 0, "bf16")
+    assert info["status"] == 0
+    assert rel_eig_err(eig, ref["eigvals"]) < EIG_BAR["bf16"]
