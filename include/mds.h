@@ -130,7 +130,10 @@ typedef enum mds_buffer_id {
   MDS_BUF_Y = 7,       /* last G-pass product, transposed l_pad x ldg fp64 */
   MDS_BUF_B = 8,       /* projected matrix Q^T G Q, l_pad x l_pad fp64 */
   MDS_BUF_THETA = 9,   /* all l Ritz values, descending, fp64 */
-  MDS_BUF_V = 10       /* Ritz vectors in the Q basis, l x l (ld l_pad) fp64 */
+  MDS_BUF_V = 10,      /* Ritz vectors in the Q basis, l x l (ld l_pad) fp64 */
+  MDS_BUF_W = 11,      /* last small Gram product (Y^T Y or Q1^T Q1), l_pad x l_pad fp64 */
+  MDS_BUF_T = 12,      /* last orthonormalising factor, l_pad x l_pad fp64 */
+  MDS_BUF_Q1 = 13      /* first CholeskyQR iterate, transposed l_pad x ldg fp64 */
 } mds_buffer_id;
 
 typedef struct mds_buffer {

@@ -53,6 +53,8 @@ __all__ = [
     "rand_mds",
     "orthonormal_basis",
     "normalise_column_signs",
+    "round_to",
+    "FORMS",
 ]
 
 # ---------------------------------------------------------------------------
@@ -183,6 +185,35 @@ def gram_entries(d_vals, r_i, c_j, m):
 
 
 # ---------------------------------------------------------------------------
+# Storage roundings of the arithmetic forms
+# ---------------------------------------------------------------------------
+
+def round_to(x, dtype: str) -> np.ndarray:
+    """Round float64 values to the storage type of a form and return them as
+    float64: 'f64' keeps them, 'f32' rounds to nearest even, 'bf16' rounds to
+    float32 and then to bfloat16 (8 significant bits), both nearest even."""
+    x = np.asarray(x, dtype=np.float64)
+    if dtype == "f64":
+        return x.copy()
+    f = x.astype(np.float32)
+    if dtype == "f32":
+        return f.astype(np.float64)
+    if dtype != "bf16":
+        raise ValueError(dtype)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + np.uint64(0x7FFF) + ((u >> np.uint64(16)) & np.uint64(1))) >> np.uint64(16)).astype(np.uint32)
+    return (r << np.uint32(16)).view(np.float32).astype(np.float64)
+
+
+# Dtype of (G, X) in the range passes and in the projection pass of each form.
+FORMS = {
+    "fp64": {"range": ("f64", "f64"), "proj": ("f64", "f64")},
+    "fp32": {"range": ("f32", "f32"), "proj": ("f32", "f32")},
+    "bf16": {"range": ("bf16", "bf16"), "proj": ("f32", "f32")},
+}
+
+
+# ---------------------------------------------------------------------------
 # Helpers shared by both MDS variants of the oracle
 # ---------------------------------------------------------------------------
 
@@ -235,8 +266,14 @@ def full_mds(D, k: int):
 # Random-projection MDS (Sec. 3.2-3.3 with the Halko et al. range finder)
 # ---------------------------------------------------------------------------
 
-def rand_mds(D, k: int, p: int, q: int, seed: int, G=None, keep_history=False):
+def rand_mds(D, k: int, p: int, q: int, seed: int, G=None, keep_history=False, form: str = "fp64"):
     """Randomized classical MDS.
+
+    ``form`` names the storage precision of the operands of each product with
+    G (see ``FORMS``): before every application Y = G X both G and X are
+    rounded to that form's dtype and the product is then taken exactly in
+    float64 arithmetic.  Everything else stays float64.  form="fp64" is the
+    plain method.
 
     Steps, in order:
       1. G from D (Sec. 6.2, step 1).
@@ -255,19 +292,23 @@ def rand_mds(D, k: int, p: int, q: int, seed: int, G=None, keep_history=False):
         raise ValueError("need 1 <= k, p >= 0, k + p <= n, q >= 0")
     if G is None:
         G = gram_matrix(D)
+    gr, xr = FORMS[form]["range"]
+    gp, xp = FORMS[form]["proj"]
+    Gr = round_to(G, gr)
+    Gp = round_to(G, gp)
     Om = omega(seed, n, l)
     history = []
-    Y = G @ Om
+    Y = Gr @ round_to(Om, xr)
     Q = orthonormal_basis(Y)
     if keep_history:
         history.append(Q.copy())
     for _ in range(q):
         for _half in range(2):
-            Y = G @ Q
+            Y = Gr @ round_to(Q, xr)
             Q = orthonormal_basis(Y)
             if keep_history:
                 history.append(Q.copy())
-    Y = G @ Q
+    Y = Gp @ round_to(Q, xp)
     B = Q.T @ Y
     B = 0.5 * (B + B.T)
     theta, V = _sorted_eigh(B)

@@ -33,7 +33,8 @@ DTYPE_F32, DTYPE_F64 = 0, 1
 STAGE_CENTER, STAGE_OMEGA, STAGE_RANGE, STAGE_ALL = 1, 2, 3, 100
 
 # buffers
-BUF_G, BUF_GREF, BUF_ROWMEAN, BUF_COLMEAN, BUF_MEAN, BUF_X, BUF_Q, BUF_Y, BUF_B, BUF_THETA, BUF_V = range(11)
+(BUF_G, BUF_GREF, BUF_ROWMEAN, BUF_COLMEAN, BUF_MEAN, BUF_X, BUF_Q, BUF_Y, BUF_B, BUF_THETA, BUF_V, BUF_W, BUF_T,
+ BUF_Q1) = range(14)
 
 MAX_L = 256
 

@@ -177,21 +177,21 @@ __global__ __launch_bounds__(256, minb_for(GK, CG)) void k_gpass(const typename 
     }
   }
 
-  // C layout of a 16x16 MFMA tile: lane l holds rows 4*(l/16) .. +3 of column l%16,
-  // i.e. four consecutive entries of one row of the transposed output.
+  // C layout of a 16x16 MFMA tile (measured on gfx950): column l%16; the
+  // four accumulator registers of lane group g = l/16 hold rows 4g..4g+3 for
+  // the fp32-accumulating instructions and rows g, g+4, g+8, g+12 for fp64.
 #pragma unroll
   for (int rg = 0; rg < RG; ++rg) {
-    const int64_t row = row0 + rg * 16 + 4 * (lane >> 4);
 #pragma unroll
     for (int cg = 0; cg < CG; ++cg) {
       const int col = cg * 16 + (lane & 15);
-      AccS* dst = Ypart + ((int64_t)s * LPAD + col) * ldg + row;
+      AccS* dst = Ypart + ((int64_t)s * LPAD + col) * ldg + row0 + rg * 16;
       if constexpr (sizeof(AccS) == 4) {
-        *reinterpret_cast<float4*>(dst) =
+        *reinterpret_cast<float4*>(dst + 4 * (lane >> 4)) =
             make_float4(acc[rg][cg][0], acc[rg][cg][1], acc[rg][cg][2], acc[rg][cg][3]);
       } else {
-        reinterpret_cast<double2*>(dst)[0] = make_double2(acc[rg][cg][0], acc[rg][cg][1]);
-        reinterpret_cast<double2*>(dst)[1] = make_double2(acc[rg][cg][2], acc[rg][cg][3]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[(lane >> 4) + 4 * r] = acc[rg][cg][r];
       }
     }
   }

@@ -46,7 +46,8 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, cons
   for (int cg = 0; cg < CG; ++cg)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      W[(int64_t)(tr * 16 + 4 * (lane >> 4) + r) * l_pad + cg * 16 + (lane & 15)] = acc[cg][r];
+      // fp64 MFMA accumulator: register r of lane group g is row g + 4r
+      W[(int64_t)(tr * 16 + (lane >> 4) + 4 * r) * l_pad + cg * 16 + (lane & 15)] = acc[cg][r];
 }
 
 __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ parts, int64_t nparts,

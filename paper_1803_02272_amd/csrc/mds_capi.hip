@@ -373,6 +373,9 @@ mds_status mds_get_buffer(mds_plan_t plan, int32_t which, mds_buffer* out) {
     case MDS_BUF_B: b = {plan->at<void>(plan->B), 0, 0, lp, lp, lp}; break;
     case MDS_BUF_THETA: b = {plan->at<void>(plan->theta), 0, 0, plan->l, 1, 1}; break;
     case MDS_BUF_V: b = {plan->at<void>(plan->V), 0, 0, plan->l, plan->l, lp}; break;
+    case MDS_BUF_W: b = {plan->at<void>(plan->W), 0, 0, lp, lp, lp}; break;
+    case MDS_BUF_T: b = {plan->at<void>(plan->T), 0, 0, lp, lp, lp}; break;
+    case MDS_BUF_Q1: b = {plan->at<void>(plan->Q1), 0, 0, lp, plan->ldg, plan->ldg}; break;
     default: return fail(MDS_ERR_INVALID_ARG, "unknown buffer %d", which);
   }
   *out = b;

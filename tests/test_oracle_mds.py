@@ -145,3 +145,26 @@ def test_argument_validation():
         O.rand_mds(D, 4, 2, 0, 0)
     with pytest.raises(ValueError):
         O.rand_mds(D, 0, 2, 0, 0)
+
+
+def test_forms_reduce_to_plain_on_representable_data():
+    # A rank-2 cloud with l >= rank: the range is exact whatever the rounding
+    # of X, so each form equals exact MDS up to its storage roundings of G and
+    # of Q in the projection, which move converged eigenvalues only to second
+    # order.
+    X = np.array([[0, 0], [1, 0], [0, 1], [1, 1], [2, 0], [0, 2], [2, 2], [1, 2]], dtype=np.float64)
+    D = np.sqrt(((X[:, None] - X[None]) ** 2).sum(-1))
+    full = O.full_mds(D, 2)
+    for form, tol in (("fp64", 1e-12), ("fp32", 1e-6), ("bf16", 1e-6)):
+        rnd = O.rand_mds(D, 2, 2, 1, seed=0, form=form)
+        assert np.allclose(rnd["eigvals"], full["eigvals"], rtol=tol)
+
+
+def test_bf16_form_perturbs_like_its_storage():
+    reads, _ = W.amplicon_reads(600, 30, seed=7)
+    D = W.hamming_distances(reads)
+    a = O.rand_mds(D, 20, 10, 1, 0)["eigvals"]
+    b = O.rand_mds(D, 20, 10, 1, 0, form="bf16")["eigvals"]
+    c = O.rand_mds(D, 20, 10, 1, 0, form="fp32")["eigvals"]
+    eb, ec = np.max(np.abs(b - a) / a), np.max(np.abs(c - a) / a)
+    assert 1e-9 < ec < 1e-5 and ec < eb < 2e-2

@@ -102,3 +102,21 @@ def test_uniforms_open_interval():
     w = np.array([0, M64], dtype=np.uint64)
     z0, z1 = O.mds_oracle._box_muller(w, w[::-1].copy())
     assert np.all(np.isfinite(z0)) and np.all(np.isfinite(z1))
+
+
+def test_round_to_bf16_and_f32():
+    # ties to even at 8 significant bits
+    x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -8 + 2.0 ** -20, -2.5e-3, 0.0])
+    want = np.array([1.0, 1.0, 1.0 + 2.0 ** -6, 1.0 + 2.0 ** -7, None, 0.0], dtype=object)
+    got = O.round_to(x, "bf16")
+    for g, w in zip(got, want):
+        if w is not None:
+            assert g == w
+    # against torch's independent float32 -> bfloat16 conversion
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(0)
+    v = (rng.standard_normal(10000) * 10.0 ** rng.integers(-5, 5, 10000)).astype(np.float32)
+    ref = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(O.round_to(v.astype(np.float64), "bf16"), ref)
+    assert np.array_equal(O.round_to(x, "f32"), x.astype(np.float32).astype(np.float64))
+    assert np.array_equal(O.round_to(x, "f64"), x)
