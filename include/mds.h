@@ -77,7 +77,8 @@ typedef struct mds_plan_s* mds_plan_t;
 
 /* Create a plan for n points, k output axes, `oversample` extra sketch
  * columns, q power iterations and the seed of the test matrix.  Valid:
- * n >= 2, k >= 1, oversample >= 0, q >= 0, k + oversample <= min(n, MDS_MAX_L).
+ * 2 <= n <= 1000000, k >= 1, oversample >= 0, q >= 0,
+ * k + oversample <= min(n, MDS_MAX_L).
  * Makes no device call.  *out receives an opaque handle owned by the caller
  * (free with mds_destroy).  mds_plan uses default options. */
 mds_status mds_plan(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample, int32_t q, uint64_t seed);
@@ -161,6 +162,31 @@ typedef struct mds_info {
 
 /* Synchronise `stream`, then report the plan's last-run diagnostics. */
 mds_status mds_get_info(mds_plan_t plan, mds_info* out, void* stream);
+
+/* Per-phase timing with HIP events recorded on the run's stream.  Phases: */
+enum {
+  MDS_PH_STATS = 0,    /* centring statistics (read D) */
+  MDS_PH_WRITE = 1,    /* centring write (read D, write G) */
+  MDS_PH_OMEGA = 2,    /* test matrix */
+  MDS_PH_GPASS = 3,    /* one G-pass kernel of the range finder (per launch) */
+  MDS_PH_REDUCE = 4,   /* split-K reduction of a G-pass */
+  MDS_PH_ORTH = 5,     /* one CholeskyQR2 */
+  MDS_PH_GPASS_REF = 6,/* the projection G-pass kernel */
+  MDS_PH_SMALL = 7,    /* B = Q^T (G Q) and the small eigensolve */
+  MDS_PH_COORDS = 8,   /* coordinates and signs */
+  MDS_NUM_PHASES = 9
+};
+typedef struct mds_phase_time {
+  int32_t count;   /* launches timed since the last read */
+  float total_ms;
+  float min_ms;
+  float max_ms;
+} mds_phase_time;
+/* Enable (1) or disable (0) event timing for subsequent runs of the plan. */
+mds_status mds_set_timing(mds_plan_t plan, int32_t enable);
+/* Synchronise `stream`, then fill out[MDS_NUM_PHASES] with the phases timed
+ * since the previous call, and reset the accumulators. */
+mds_status mds_get_timings(mds_plan_t plan, mds_phase_time* out, void* stream);
 
 void mds_destroy(mds_plan_t plan);
 const char* mds_status_string(mds_status s);

@@ -147,6 +147,15 @@ class Plan:
         flat = self._ws[off: off + total * esz].view(dt)
         return flat.as_strided((rows, cols), (ld, 1))
 
+    def set_timing(self, enable=True):
+        check(_capi.lib().mds_set_timing(self._h, 1 if enable else 0), "mds_set_timing")
+
+    def timings(self, stream=None):
+        """{phase: (count, total_ms, min_ms, max_ms)} since the last call (syncs the stream)."""
+        arr = (_capi.MdsPhaseTime * len(_capi.PHASES))()
+        check(_capi.lib().mds_get_timings(self._h, arr, _stream_handle(stream)), "mds_get_timings")
+        return {name: (t.count, t.total_ms, t.min_ms, t.max_ms) for name, t in zip(_capi.PHASES, arr)}
+
     def info(self, stream=None):
         inf = _capi.MdsInfo()
         check(_capi.lib().mds_get_info(self._h, ctypes.byref(inf), _stream_handle(stream)), "mds_get_info")

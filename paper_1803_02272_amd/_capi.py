@@ -62,6 +62,14 @@ class MdsInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+PHASES = ["stats", "write", "omega", "gpass", "reduce", "orth", "gpass_ref", "small", "coords"]
+
+
+class MdsPhaseTime(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("total_ms", ctypes.c_float), ("min_ms", ctypes.c_float),
+                ("max_ms", ctypes.c_float)]
+
+
 # exported symbol -> (restype, argtypes)
 SIGNATURES = {
     "mds_plan": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64, ctypes.c_int32,
@@ -76,6 +84,8 @@ SIGNATURES = {
                                       ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "mds_get_buffer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(MdsBuffer)]),
     "mds_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MdsInfo), ctypes.c_void_p]),
+    "mds_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "mds_get_timings": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MdsPhaseTime), ctypes.c_void_p]),
     "mds_destroy": (None, [ctypes.c_void_p]),
     "mds_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mds_last_error": (ctypes.c_char_p, []),

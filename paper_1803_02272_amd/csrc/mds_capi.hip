@@ -14,6 +14,7 @@
 
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/mds.h"
 #include "mds_internal.h"
@@ -62,6 +63,10 @@ struct mds_plan_s {
       small, sval, sidx, status;
   size_t total = 0;
   int last_stage = 0;
+  // event timing
+  bool timing = false;
+  std::vector<hipEvent_t> events;  // pool
+  std::vector<int> rec_phase;      // phase of recorded pair i (events 2i, 2i+1)
 
   template <typename T>
   T* at(const Region& reg) const {
@@ -114,6 +119,32 @@ void layout(mds_plan_s* P) {
   add(P, P->status, sizeof(DevStatus));
 }
 
+// Bracket a phase with events on the stream when timing is enabled.
+struct PhaseTimer {
+  mds_plan_s* P;
+  hipStream_t s;
+  int phase;
+  bool on;
+  PhaseTimer(mds_plan_s* P_, hipStream_t s_, int ph) : P(P_), s(s_), phase(ph), on(P_->timing) {
+    if (!on) return;
+    const size_t need = 2 * (P->rec_phase.size() + 1);
+    while (P->events.size() < need) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        on = false;
+        return;
+      }
+      P->events.push_back(e);
+    }
+    (void)hipEventRecord(P->events[2 * P->rec_phase.size()], s);
+  }
+  ~PhaseTimer() {
+    if (!on) return;
+    (void)hipEventRecord(P->events[2 * P->rec_phase.size() + 1], s);
+    P->rec_phase.push_back(phase);
+  }
+};
+
 __global__ void k_status_init(DevStatus* st) {
   DevStatus z = {};
   *st = z;
@@ -163,6 +194,7 @@ mds_status orthonormalize(mds_plan_s* P, hipStream_t s, int xk) {
   double* Wp = P->at<double>(P->Wpart);
   double* sm = P->at<double>(P->small);
   DevStatus* st = P->at<DevStatus>(P->status);
+  PhaseTimer tm(P, s, MDS_PH_ORTH);
   MDS_TRY(launch_gram(Y, Y, P->l_pad, P->ldg, Wp, W, s), "gram(Y)");
   MDS_TRY(launch_orth_factor(W, P->l, P->l_pad, T, sm, st, s), "orth_factor 1");
   MDS_TRY(launch_apply(Y, P->l, P->ldg, T, P->l_pad, P->l, P->l_pad, Q1, -1, nullptr, s), "apply 1");
@@ -176,8 +208,12 @@ mds_status gpass(mds_plan_s* P, hipStream_t s, bool ref) {
   const int gk = ref ? P->ref_gk : P->gk;
   const GPassCfg& cfg = ref ? P->ref_cfg : P->cfg;
   const void* G = (ref && P->form == MDS_FORM_BF16) ? P->at<void>(P->Gref) : P->at<void>(P->G);
-  MDS_TRY(launch_gpass(gk, G, P->ldg, P->n_pad, P->at<void>(P->X), P->l_pad, cfg, P->at<void>(P->Ypart), s),
-          "gpass");
+  {
+    PhaseTimer tm(P, s, ref ? MDS_PH_GPASS_REF : MDS_PH_GPASS);
+    MDS_TRY(launch_gpass(gk, G, P->ldg, P->n_pad, P->at<void>(P->X), P->l_pad, cfg, P->at<void>(P->Ypart), s),
+            "gpass");
+  }
+  PhaseTimer tm(P, s, MDS_PH_REDUCE);
   MDS_TRY(launch_splitk_reduce(gk, P->at<void>(P->Ypart), cfg.split, (int64_t)P->l_pad * P->ldg,
                                P->at<double>(P->Y), s),
           "splitk_reduce");
@@ -195,19 +231,28 @@ mds_status run_impl(mds_plan_s* P, const void* D, double* coords, double* eigval
   hipLaunchKernelGGL(k_status_init, dim3(1), dim3(1), 0, s, st);
   MDS_TRY(hipGetLastError(), "status init");
 
+  {
+  PhaseTimer tm(P, s, MDS_PH_STATS);
   MDS_TRY(launch_center_stats(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->at<double>(P->rowpart),
                               P->at<double>(P->colpart), P->at<double>(P->r), P->at<double>(P->c),
                               P->at<double>(P->rsum), P->at<double>(P->mean), st, s),
           "centring stats");
+  }
+  {
+  PhaseTimer tm(P, s, MDS_PH_WRITE);
   MDS_TRY(launch_center_write(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->n_pad, P->ldg, P->at<double>(P->r),
                               P->at<double>(P->c), P->at<double>(P->mean), P->gk, P->at<void>(P->G),
                               P->form == MDS_FORM_BF16 ? P->at<float>(P->Gref) : nullptr,
                               P->at<double>(P->fpart), st, s),
           "centring write");
+  }
   P->last_stage = MDS_STAGE_CENTER;
   if (stop_after == MDS_STAGE_CENTER) return MDS_OK;
 
-  MDS_TRY(launch_omega(P->seed, P->n, P->l, P->l_pad, P->ldg, P->gk, P->at<void>(P->X), s), "omega");
+  {
+    PhaseTimer tm(P, s, MDS_PH_OMEGA);
+    MDS_TRY(launch_omega(P->seed, P->n, P->l, P->l_pad, P->ldg, P->gk, P->at<void>(P->X), s), "omega");
+  }
   P->last_stage = MDS_STAGE_OMEGA;
   if (stop_after == MDS_STAGE_OMEGA) return MDS_OK;
 
@@ -226,12 +271,16 @@ mds_status run_impl(mds_plan_s* P, const void* D, double* coords, double* eigval
   // projection: Y = G_ref Q, B = Q^T Y
   mds_status e = gpass(P, s, true);
   if (e != MDS_OK) return e;
-  MDS_TRY(launch_gram(P->at<double>(P->Q), P->at<double>(P->Y), P->l_pad, P->ldg, P->at<double>(P->Wpart),
-                      P->at<double>(P->B), s),
-          "gram(Q, GQ)");
-  MDS_TRY(launch_small_eig(P->at<double>(P->B), P->l, P->l_pad, P->k, P->at<double>(P->theta),
-                           P->at<double>(P->V), P->at<double>(P->Tc), eigvals, P->at<double>(P->small), st, s),
-          "small_eig");
+  {
+    PhaseTimer tm(P, s, MDS_PH_SMALL);
+    MDS_TRY(launch_gram(P->at<double>(P->Q), P->at<double>(P->Y), P->l_pad, P->ldg, P->at<double>(P->Wpart),
+                        P->at<double>(P->B), s),
+            "gram(Q, GQ)");
+    MDS_TRY(launch_small_eig(P->at<double>(P->B), P->l, P->l_pad, P->k, P->at<double>(P->theta),
+                             P->at<double>(P->V), P->at<double>(P->Tc), eigvals, P->at<double>(P->small), st, s),
+            "small_eig");
+  }
+  PhaseTimer tm(P, s, MDS_PH_COORDS);
   MDS_TRY(launch_coords(P->at<double>(P->Q), P->l, P->n, P->ldg, P->at<double>(P->Tc), P->k, coords,
                         P->at<double>(P->sval), P->at<int64_t>(P->sidx), s),
           "coords");
@@ -271,7 +320,7 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
   mds_opts o = {MDS_FORM_FP32, MDS_DTYPE_F32, 0, 0};
   if (opts) o = *opts;
   if (n < 2) return fail(MDS_ERR_INVALID_ARG, "n = %lld < 2", (long long)n);
-  if (n > ((int64_t)1 << 24)) return fail(MDS_ERR_INVALID_ARG, "n = %lld too large", (long long)n);
+  if (n > 1000000) return fail(MDS_ERR_INVALID_ARG, "n = %lld > 1000000", (long long)n);
   if (k < 1) return fail(MDS_ERR_INVALID_ARG, "k = %d < 1", k);
   if (oversample < 0) return fail(MDS_ERR_INVALID_ARG, "oversample = %d < 0", oversample);
   if (q < 0) return fail(MDS_ERR_INVALID_ARG, "q = %d < 0", q);
@@ -415,8 +464,33 @@ mds_status mds_get_info(mds_plan_t plan, mds_info* out, void* stream) {
   return MDS_OK;
 }
 
+mds_status mds_set_timing(mds_plan_t plan, int32_t enable) {
+  if (!plan) return fail(MDS_ERR_INVALID_ARG, "NULL plan");
+  plan->timing = enable != 0;
+  return MDS_OK;
+}
+
+mds_status mds_get_timings(mds_plan_t plan, mds_phase_time* out, void* stream) {
+  if (!plan || !out) return fail(MDS_ERR_INVALID_ARG, "NULL argument");
+  for (int i = 0; i < MDS_NUM_PHASES; ++i) out[i] = mds_phase_time{0, 0.f, 0.f, 0.f};
+  if (plan->rec_phase.empty()) return MDS_OK;
+  MDS_TRY(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+  for (size_t i = 0; i < plan->rec_phase.size(); ++i) {
+    float ms = 0.f;
+    MDS_TRY(hipEventElapsedTime(&ms, plan->events[2 * i], plan->events[2 * i + 1]), "hipEventElapsedTime");
+    mds_phase_time& t = out[plan->rec_phase[i]];
+    t.min_ms = t.count ? (ms < t.min_ms ? ms : t.min_ms) : ms;
+    t.max_ms = t.count ? (ms > t.max_ms ? ms : t.max_ms) : ms;
+    t.total_ms += ms;
+    t.count += 1;
+  }
+  plan->rec_phase.clear();
+  return MDS_OK;
+}
+
 void mds_destroy(mds_plan_t plan) {
   if (!plan) return;
+  for (hipEvent_t e : plan->events) (void)hipEventDestroy(e);
   if (plan->ws_owned && plan->ws) (void)hipFree(plan->ws);
   delete plan;
 }
