@@ -50,12 +50,17 @@ typedef enum mds_status {
   MDS_ERR_STATE = -9        /* call not valid in the plan's current state */
 } mds_status;
 
-/* Arithmetic form of the G-passes (dtype of the stored Gram matrix).
- *   FP64: G fp64, fp64 MFMA.
- *   FP32: G fp32, fp32 MFMA.
- *   BF16: G bf16 (rounded from fp64 through fp32), bf16 MFMA with fp32
- *         accumulation for the 2q+1 range passes; the projection pass
- *         ("refinement") uses an fp32 copy of G and fp32 MFMA.
+/* Arithmetic form of the G-passes (dtype of the G operand).
+ *   FP64: G entries in fp64, fp64 MFMA.
+ *   FP32: G entries rounded to fp32, fp32 MFMA.
+ *   BF16: G stored in bf16 (rounded from fp64 through fp32), bf16 MFMA with
+ *         fp32 accumulation for the 2q+1 range passes; the projection pass
+ *         ("refinement") uses fp32 G entries and fp32 MFMA.
+ * G is stored only in the bf16 form.  Every other pass recomputes each
+ * entry from D: fp64 passes with the centring equation in fp64 (the values a
+ * stored fp64 G would hold), fp32 passes as fma(-1/2, fl32(d^2),
+ * fl32(c_j/2) + fl32((r_i - m)/2)) in fp32, within a few fp32 ulps of the
+ * terms of the rounded exact value.
  * In every form the centring sums, CholeskyQR2, the Gram products of the
  * tall matrices and the small eigensolve run in fp64. */
 typedef enum mds_form { MDS_FORM_FP64 = 0, MDS_FORM_FP32 = 1, MDS_FORM_BF16 = 2 } mds_form;
@@ -121,8 +126,8 @@ mds_status mds_run_stages(mds_plan_t plan, const void* D, double* coords, double
 
 /* Internal buffers exposed read-only for inspection after a (partial) run. */
 typedef enum mds_buffer_id {
-  MDS_BUF_G = 0,       /* Gram matrix, n_pad x ldg, pass dtype */
-  MDS_BUF_GREF = 1,    /* fp32 copy of G (BF16 form only) */
+  MDS_BUF_G = 0,       /* stored Gram matrix, n_pad x ldg bf16 (BF16 form only) */
+  MDS_BUF_GREF = 1,    /* reserved (no fp32 copy of G is stored) */
   MDS_BUF_ROWMEAN = 2, /* r, n fp64 */
   MDS_BUF_COLMEAN = 3, /* c, n fp64 */
   MDS_BUF_MEAN = 4,    /* m, 1 fp64 */
@@ -156,7 +161,7 @@ typedef struct mds_info {
   int32_t k, l, l_pad, q, form, gpass_split;
   int64_t n, ldg;
   double sum_sq;             /* sum_ij d_ij^2 */
-  double frob2;              /* ||G||_F^2 (fp64, before storage rounding) */
+  double frob2;              /* ||G||_F^2 (fp64, closed form in the centring sums) */
   double trace;              /* tr(G) */
 } mds_info;
 

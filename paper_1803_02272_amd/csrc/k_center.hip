@@ -50,12 +50,15 @@ __device__ __forceinline__ bool row_vec_ok(bool base_ok, int64_t i, int64_t n) {
 
 constexpr int kWaves = 4;
 constexpr int kRowsPerWave = kStatsRows / kWaves;  // 256
-constexpr int kRowBatch = 4;
 
+// One read of D per 1024 x 1024 tile.  Loads of the next batch of rows are
+// issued before the current batch is reduced (raw values held in registers).
 template <typename DT>
-__global__ __launch_bounds__(256) void k_stats(const DT* __restrict__ D, int64_t n, int base_vec,
-                                               double* __restrict__ rowpart, double* __restrict__ colpart) {
+__global__ __launch_bounds__(256, 2) void k_stats(const DT* __restrict__ D, int64_t n, int base_vec,
+                                                  double* __restrict__ rowpart, double* __restrict__ colpart,
+                                                  double* __restrict__ p4part) {
 #pragma clang fp contract(off)
+  constexpr int RB = 2;  // rows per batch
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t cb = blockIdx.x, rb = blockIdx.y;
@@ -65,81 +68,145 @@ __global__ __launch_bounds__(256) void k_stats(const DT* __restrict__ D, int64_t
   double cacc[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) cacc[t] = 0.0;
+  double acc4 = 0.0;
 
-  for (int64_t i = r0; i < r1; i += kRowBatch) {
-    double v[kRowBatch][16];
+  DT raw[RB][16], rawn[RB][16];
+  auto load_batch = [&](DT (&dst)[RB][16], int64_t i) {
 #pragma unroll
-    for (int rr = 0; rr < kRowBatch; ++rr) {
+    for (int rr = 0; rr < RB; ++rr) {
       const int64_t ii = i + rr;
-      if (ii < r1) {
-        const DT* row = D + ii * n;
-        const bool vec = row_vec_ok<DT>(base_vec != 0, ii, n);
+      const DT* row = D + ii * n;
+      const bool rowok = ii < r1;
+      const bool vec = rowok && row_vec_ok<DT>(base_vec != 0, ii, n);
 #pragma unroll
-        for (int g = 0; g < 4; ++g) load4<DT>(row, c0 + g * 256 + lane * 4, n, vec, &v[rr][g * 4]);
-      } else {
+      for (int g = 0; g < 4; ++g) {
+        const int64_t c = c0 + g * 256 + lane * 4;
+        if (vec && c + 3 < n) {
+          if constexpr (sizeof(DT) == 4) {
+            const float4 f = *reinterpret_cast<const float4*>(row + c);
+            dst[rr][g * 4 + 0] = f.x; dst[rr][g * 4 + 1] = f.y; dst[rr][g * 4 + 2] = f.z; dst[rr][g * 4 + 3] = f.w;
+          } else {
+            const double2 a = *reinterpret_cast<const double2*>(row + c);
+            const double2 b = *reinterpret_cast<const double2*>(row + c + 2);
+            dst[rr][g * 4 + 0] = a.x; dst[rr][g * 4 + 1] = a.y; dst[rr][g * 4 + 2] = b.x; dst[rr][g * 4 + 3] = b.y;
+          }
+        } else {
 #pragma unroll
-        for (int t = 0; t < 16; ++t) v[rr][t] = 0.0;
+          for (int t = 0; t < 4; ++t) dst[rr][g * 4 + t] = (rowok && c + t < n) ? row[c + t] : (DT)0;
+        }
       }
     }
+  };
+
+  if (r0 < r1) load_batch(raw, r0);
+  for (int64_t i = r0; i < r1; i += RB) {
+    const bool more = i + RB < r1;
+    if (more) load_batch(rawn, i + RB);
 #pragma unroll
-    for (int rr = 0; rr < kRowBatch; ++rr) {
+    for (int rr = 0; rr < RB; ++rr) {
       double rs = 0.0;
 #pragma unroll
       for (int t = 0; t < 16; ++t) {
-        const double s = v[rr][t] * v[rr][t];
-        cacc[t] += s;
-        rs += s;
+        const double d = (double)raw[rr][t];
+        const double sq = d * d;
+        cacc[t] += sq;
+        rs += sq;
+        acc4 += sq * sq;
       }
       rs = wave_sum(rs);
       const int64_t ii = i + rr;
       if (lane == 0 && ii < r1) rowpart[cb * n + ii] = rs;
     }
+    if (more) {
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+        for (int t = 0; t < 16; ++t) raw[rr][t] = rawn[rr][t];
+    }
   }
   __shared__ double sh[kWaves][kStatsCols];
+  __shared__ double sh4[kWaves];
 #pragma unroll
   for (int g = 0; g < 4; ++g)
 #pragma unroll
     for (int t = 0; t < 4; ++t) sh[wave][g * 256 + lane * 4 + t] = cacc[g * 4 + t];
+  acc4 = wave_sum(acc4);
+  if (lane == 0) sh4[wave] = acc4;
   __syncthreads();
   for (int cc = threadIdx.x; cc < kStatsCols; cc += 256) {
     const int64_t c = c0 + cc;
     if (c < n) colpart[rb * n + c] = ((sh[0][cc] + sh[1][cc]) + sh[2][cc]) + sh[3][cc];
   }
+  if (threadIdx.x == 0) p4part[rb * gridDim.x + cb] = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
 }
 
+// r_i, c_j (means of d^2), and hc_j = fl32(c_j / 2) for the fp32 recentring
+// of the G-passes (zero beyond n up to ldg).
 __global__ __launch_bounds__(256) void k_stats_reduce(const double* __restrict__ rowpart,
                                                       const double* __restrict__ colpart, int64_t ncb,
-                                                      int64_t nrb, int64_t n, double* __restrict__ r,
-                                                      double* __restrict__ c, double* __restrict__ rsum) {
+                                                      int64_t nrb, int64_t n, int64_t ldg, double* __restrict__ r,
+                                                      double* __restrict__ c, double* __restrict__ rsum,
+                                                      float* __restrict__ hc) {
 #pragma clang fp contract(off)
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
+  if (i >= ldg) return;
+  if (i >= n) {
+    hc[i] = 0.0f;
+    return;
+  }
   double s = 0.0;
+#pragma unroll 8
   for (int64_t b = 0; b < ncb; ++b) s += rowpart[b * n + i];
   double t = 0.0;
+#pragma unroll 8
   for (int64_t b = 0; b < nrb; ++b) t += colpart[b * n + i];
   rsum[i] = s;
   r[i] = s / (double)n;
   c[i] = t / (double)n;
+  hc[i] = (float)(0.5 * (t / (double)n));
 }
 
-__global__ __launch_bounds__(1024) void k_grand(const double* __restrict__ rsum, int64_t n,
+// Grand mean m, and the by-products ||G||_F^2 and tr(G) from their closed
+// forms in the centring statistics: with A = [d_ij^2] and B = J A J,
+// A = B + r 1^T + 1 c^T - m 1 1^T splits into Frobenius-orthogonal parts, so
+// ||B||^2 = ||A||^2 - n ||r||^2 - n ||c||^2 + n^2 m^2 and ||G||^2 = ||B||^2 / 4;
+// tr G = -1/2 (sum_i d_ii^2 - n m).
+template <typename DT>
+__global__ __launch_bounds__(1024) void k_grand(const double* __restrict__ rsum, const double* __restrict__ r,
+                                                const double* __restrict__ c, const double* __restrict__ p4part,
+                                                int64_t np4, const DT* __restrict__ D, int64_t n,
                                                 double* __restrict__ mean_all, DevStatus* st) {
 #pragma clang fp contract(off)
-  __shared__ double sh[1024];
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) s += rsum[i];
-  sh[threadIdx.x] = s;
+  __shared__ double sh[5][1024];
+  double s = 0.0, rr = 0.0, cc = 0.0, q = 0.0, dg = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    s += rsum[i];
+    rr += r[i] * r[i];
+    cc += c[i] * c[i];
+    const double d = (double)D[i * n + i];
+    dg += d * d;
+  }
+  for (int64_t i = threadIdx.x; i < np4; i += 1024) q += p4part[i];
+  sh[0][threadIdx.x] = s;
+  sh[1][threadIdx.x] = rr;
+  sh[2][threadIdx.x] = cc;
+  sh[3][threadIdx.x] = q;
+  sh[4][threadIdx.x] = dg;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double S = sh[0];
-    mean_all[0] = S / ((double)n * (double)n);
+    const double S = sh[0][0];
+    const double dn = (double)n;
+    const double m = S / (dn * dn);
+    mean_all[0] = m;
     st->sum_sq = S;
-    if (!__builtin_isfinite(S)) st->nonfinite = 1;
+    st->frob2 = 0.25 * (((sh[3][0] - dn * sh[1][0]) - dn * sh[2][0]) + (dn * dn) * (m * m));
+    st->trace = -0.5 * (sh[4][0] - dn * m);
+    if (!__builtin_isfinite(S) || !__builtin_isfinite(sh[3][0])) st->nonfinite = 1;
   }
 }
 
@@ -179,8 +246,7 @@ __global__ __launch_bounds__(256) void k_center_write(const DT* __restrict__ D, 
                                                       int base_vec, const double* __restrict__ r,
                                                       const double* __restrict__ c,
                                                       const double* __restrict__ mean_all,
-                                                      GT* __restrict__ G, float* __restrict__ gref,
-                                                      double* __restrict__ fpart) {
+                                                      GT* __restrict__ G, float* __restrict__ gref) {
 #pragma clang fp contract(off)
   const int64_t j0 = (int64_t)blockIdx.x * kWriteCols + threadIdx.x * 4;
   const bool active = j0 < ldg;
@@ -188,7 +254,6 @@ __global__ __launch_bounds__(256) void k_center_write(const DT* __restrict__ D, 
 #pragma unroll
   for (int t = 0; t < 4; ++t) cj[t] = (j0 + t < n) ? c[j0 + t] : 0.0;
   const double m = mean_all[0];
-  double fro = 0.0, tr = 0.0;
   for (int rr = 0; rr < kWriteRows; ++rr) {
     const int64_t i = (int64_t)blockIdx.y * kWriteRows + rr;
     double g[4] = {0.0, 0.0, 0.0, 0.0};
@@ -203,76 +268,33 @@ __global__ __launch_bounds__(256) void k_center_write(const DT* __restrict__ D, 
     if (active) {
       store4<GT>(G + i * ldg + j0, g);
       if constexpr (REF) store4<float>(gref + i * ldg + j0, g);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        fro += g[t] * g[t];
-        if (i == j0 + t) tr += g[t];
-      }
     }
-  }
-  fro = wave_sum(fro);
-  tr = wave_sum(tr);
-  __shared__ double sh[2][4];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) { sh[0][wave] = fro; sh[1][wave] = tr; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int64_t bid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    fpart[2 * bid] = ((sh[0][0] + sh[0][1]) + sh[0][2]) + sh[0][3];
-    fpart[2 * bid + 1] = ((sh[1][0] + sh[1][1]) + sh[1][2]) + sh[1][3];
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_finalize_stats(const double* __restrict__ fpart, int64_t nparts,
-                                                         DevStatus* st) {
-#pragma clang fp contract(off)
-  __shared__ double sa[1024], sb[1024];
-  double a = 0.0, b = 0.0;
-  for (int64_t i = threadIdx.x; i < nparts; i += 1024) {
-    a += fpart[2 * i];
-    b += fpart[2 * i + 1];
-  }
-  sa[threadIdx.x] = a;
-  sb[threadIdx.x] = b;
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      sa[threadIdx.x] += sa[threadIdx.x + w];
-      sb[threadIdx.x] += sb[threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    st->frob2 = sa[0];
-    st->trace = sb[0];
   }
 }
 
 template <typename DT, typename GT>
 hipError_t write_dispatch(const DT* D, int64_t n, int64_t n_pad, int64_t ldg, int vec, const double* r,
-                          const double* c, const double* mean_all, GT* G, float* gref, double* fpart,
-                          hipStream_t s) {
+                          const double* c, const double* mean_all, GT* G, float* gref, hipStream_t s) {
   dim3 grid((unsigned)((ldg + kWriteCols - 1) / kWriteCols), (unsigned)(n_pad / kWriteRows));
   if (gref)
     hipLaunchKernelGGL((k_center_write<DT, GT, true>), grid, dim3(256), 0, s, D, n, ldg, vec, r, c, mean_all,
-                       G, gref, fpart);
+                       G, gref);
   else
     hipLaunchKernelGGL((k_center_write<DT, GT, false>), grid, dim3(256), 0, s, D, n, ldg, vec, r, c,
-                       mean_all, G, gref, fpart);
+                       mean_all, G, gref);
   return hipGetLastError();
 }
 
 template <typename DT>
 hipError_t write_by_g(const DT* D, int64_t n, int64_t n_pad, int64_t ldg, int vec, const double* r,
-                      const double* c, const double* mean_all, int gk, void* G, float* gref, double* fpart,
-                      hipStream_t s) {
+                      const double* c, const double* mean_all, int gk, void* G, float* gref, hipStream_t s) {
   switch (gk) {
     case GK_F64:
-      return write_dispatch<DT, double>(D, n, n_pad, ldg, vec, r, c, mean_all, (double*)G, gref, fpart, s);
+      return write_dispatch<DT, double>(D, n, n_pad, ldg, vec, r, c, mean_all, (double*)G, gref, s);
     case GK_F32:
-      return write_dispatch<DT, float>(D, n, n_pad, ldg, vec, r, c, mean_all, (float*)G, gref, fpart, s);
+      return write_dispatch<DT, float>(D, n, n_pad, ldg, vec, r, c, mean_all, (float*)G, gref, s);
     case GK_BF16:
-      return write_dispatch<DT, bf16_t>(D, n, n_pad, ldg, vec, r, c, mean_all, (bf16_t*)G, gref, fpart, s);
+      return write_dispatch<DT, bf16_t>(D, n, n_pad, ldg, vec, r, c, mean_all, (bf16_t*)G, gref, s);
     default:
       return hipErrorInvalidValue;
   }
@@ -280,20 +302,29 @@ hipError_t write_by_g(const DT* D, int64_t n, int64_t n_pad, int64_t ldg, int ve
 
 }  // namespace
 
-hipError_t launch_center_stats(const void* D, int d_is_f64, int64_t n, double* rowpart, double* colpart,
-                               double* r, double* c, double* rsum, double* mean_all, DevStatus* st,
-                               hipStream_t s) {
+int64_t stats_tiles(int64_t n) {
+  return ((n + kStatsCols - 1) / kStatsCols) * ((n + kStatsRows - 1) / kStatsRows);
+}
+
+hipError_t launch_center_stats(const void* D, int d_is_f64, int64_t n, int64_t ldg, double* rowpart,
+                               double* colpart, double* p4part, double* r, double* c, double* rsum, float* hc,
+                               double* mean_all, DevStatus* st, hipStream_t s) {
   const int64_t ncb = (n + kStatsCols - 1) / kStatsCols;
   const int64_t nrb = (n + kStatsRows - 1) / kStatsRows;
   const int vec = ((uintptr_t)D % 16) == 0;
   dim3 grid((unsigned)ncb, (unsigned)nrb);
   if (d_is_f64)
-    hipLaunchKernelGGL(k_stats<double>, grid, dim3(256), 0, s, (const double*)D, n, vec, rowpart, colpart);
+    hipLaunchKernelGGL(k_stats<double>, grid, dim3(256), 0, s, (const double*)D, n, vec, rowpart, colpart, p4part);
   else
-    hipLaunchKernelGGL(k_stats<float>, grid, dim3(256), 0, s, (const float*)D, n, vec, rowpart, colpart);
-  hipLaunchKernelGGL(k_stats_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rowpart, colpart,
-                     ncb, nrb, n, r, c, rsum);
-  hipLaunchKernelGGL(k_grand, dim3(1), dim3(1024), 0, s, rsum, n, mean_all, st);
+    hipLaunchKernelGGL(k_stats<float>, grid, dim3(256), 0, s, (const float*)D, n, vec, rowpart, colpart, p4part);
+  hipLaunchKernelGGL(k_stats_reduce, dim3((unsigned)((ldg + 255) / 256)), dim3(256), 0, s, rowpart, colpart, ncb,
+                     nrb, n, ldg, r, c, rsum, hc);
+  if (d_is_f64)
+    hipLaunchKernelGGL(k_grand<double>, dim3(1), dim3(1024), 0, s, rsum, r, c, p4part, ncb * nrb,
+                       (const double*)D, n, mean_all, st);
+  else
+    hipLaunchKernelGGL(k_grand<float>, dim3(1), dim3(1024), 0, s, rsum, r, c, p4part, ncb * nrb,
+                       (const float*)D, n, mean_all, st);
   return hipGetLastError();
 }
 
@@ -303,22 +334,10 @@ int64_t center_write_blocks(int64_t n_pad, int64_t ldg) {
 
 hipError_t launch_center_write(const void* D, int d_is_f64, int64_t n, int64_t n_pad, int64_t ldg,
                                const double* r, const double* c, const double* mean_all, int gk, void* G,
-                               float* gref, double* fpart, DevStatus* st, hipStream_t s) {
+                               float* gref, hipStream_t s) {
   const int vec = ((uintptr_t)D % 16) == 0;
-  hipError_t e;
-  if (d_is_f64)
-    e = write_by_g<double>((const double*)D, n, n_pad, ldg, vec, r, c, mean_all, gk, G, gref, fpart, s);
-  else
-    e = write_by_g<float>((const float*)D, n, n_pad, ldg, vec, r, c, mean_all, gk, G, gref, fpart, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finalize_stats, dim3(1), dim3(1024), 0, s, fpart,
-                     center_write_blocks(n_pad, ldg), st);
-  return hipGetLastError();
-}
-
-hipError_t launch_finalize_stats(const double* fpart, int64_t nparts, DevStatus* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_stats, dim3(1), dim3(1024), 0, s, fpart, nparts, st);
-  return hipGetLastError();
+  if (d_is_f64) return write_by_g<double>((const double*)D, n, n_pad, ldg, vec, r, c, mean_all, gk, G, gref, s);
+  return write_by_g<float>((const float*)D, n, n_pad, ldg, vec, r, c, mean_all, gk, G, gref, s);
 }
 
 }  // namespace mds

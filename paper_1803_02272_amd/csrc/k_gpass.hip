@@ -19,6 +19,8 @@
 //     split index is blockIdx % split: with split a multiple of 8, every
 //     workgroup on an XCD works on the same K range, so that XCD's slice of X
 //     stays in its own L2 while G streams past.
+#include <type_traits>
+
 #include "mds_internal.h"
 
 namespace mds {
@@ -34,6 +36,8 @@ struct Tr<GK_BF16> {
   using T = bf16_t;
   using Acc = floatx4_t;
   using AccS = float;
+  static constexpr int kSub = 1;  // MFMAs per 16-byte operand chunk
+  static __device__ __forceinline__ void mma_sub(Acc& c, const u32x4& a, const u32x4& b, int) { mma(c, a, b); }
   static __device__ __forceinline__ void mma(Acc& c, const u32x4& a, const u32x4& b) {
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
                                                 __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
@@ -47,6 +51,10 @@ struct Tr<GK_F32> {
   using AccS = float;
   // one 16-byte chunk holds 4 K-values per lane: four K=4 MFMAs, the t-th
   // taking element t of every lane group (same K pairing for A and B)
+  static constexpr int kSub = 4;
+  static __device__ __forceinline__ void mma_sub(Acc& c, const u32x4& a, const u32x4& b, int t) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[t]), __uint_as_float(b[t]), c, 0, 0, 0);
+  }
   static __device__ __forceinline__ void mma(Acc& c, const u32x4& a, const u32x4& b) {
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
@@ -60,6 +68,12 @@ struct Tr<GK_F64> {
   using T = double;
   using Acc = doublex4_t;
   using AccS = double;
+  static constexpr int kSub = 2;
+  static __device__ __forceinline__ void mma_sub(Acc& c, const u32x4& a, const u32x4& b, int t) {
+    const double av = t == 0 ? __hiloint2double((int)a.y, (int)a.x) : __hiloint2double((int)a.w, (int)a.z);
+    const double bv = t == 0 ? __hiloint2double((int)b.y, (int)b.x) : __hiloint2double((int)b.w, (int)b.z);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+  }
   static __device__ __forceinline__ void mma(Acc& c, const u32x4& a, const u32x4& b) {
     const double a0 = __hiloint2double((int)a.y, (int)a.x), a1 = __hiloint2double((int)a.w, (int)a.z);
     const double b0 = __hiloint2double((int)b.y, (int)b.x), b1 = __hiloint2double((int)b.w, (int)b.z);
@@ -75,20 +89,68 @@ constexpr int kRowB = 144;  // LDS bytes per X row within a step tile
 __host__ __device__ constexpr int rg_for(int gk, int cg) {
   return gk == GK_F64 ? (cg <= 3 ? 4 : (cg <= 7 ? 2 : 1)) : (cg <= 8 ? 4 : 2);
 }
+// Recentring passes hold raw D values and recentring terms in registers as
+// well; fewer row groups keep two workgroups per CU.
+__host__ __device__ constexpr int rg_fd(int gk, int cg) {
+  return gk == GK_F64 ? (cg <= 3 ? 2 : 1) : (cg <= 4 ? 4 : (cg <= 8 ? 2 : 1));
+}
 __host__ __device__ constexpr int minb_for(int gk, int cg) { return (gk == GK_F64 && cg >= 12) ? 1 : 2; }
 
-template <int GK, int RG, int CG>
-__global__ __launch_bounds__(256, minb_for(GK, CG)) void k_gpass(const typename Tr<GK>::T* __restrict__ G, int64_t ldg,
-                                                  const typename Tr<GK>::T* __restrict__ Xt, int split,
-                                                  int64_t steps_total, int64_t steps_per_split,
-                                                  typename Tr<GK>::AccS* __restrict__ Ypart) {
+// Element type of D when the A operand is recentred on the fly (void: G is stored).
+template <typename DT>
+struct DLoad {
+  static constexpr bool kFromD = true;
+};
+template <>
+struct DLoad<void> {
+  static constexpr bool kFromD = false;
+};
+
+template <int GK, typename DT>
+__host__ __device__ constexpr int minb_of(int cg) {
+  return DLoad<DT>::kFromD ? 2 : minb_for(GK, cg);
+}
+
+// E consecutive elements of row i of D starting at column k0 (k0 % E == 0),
+// zero outside the n x n matrix; vector loads when the row start is aligned.
+template <typename DT, int E>
+__device__ __forceinline__ void load_d(const DT* __restrict__ D, int64_t n, int64_t i, int64_t k0, bool rowvec,
+                                       DT (&v)[E]) {
+  const DT* p = D + i * n + k0;
+  if (i < n && rowvec && k0 + E - 1 < n) {
+    if constexpr (sizeof(DT) * E == 16) {
+      const u32x4 w = *reinterpret_cast<const u32x4*>(p);
+      __builtin_memcpy(&v, &w, 16);
+    } else if constexpr (sizeof(DT) * E == 32) {
+      const u32x4 w0 = *reinterpret_cast<const u32x4*>(p);
+      const u32x4 w1 = *reinterpret_cast<const u32x4*>(p + E / 2);
+      __builtin_memcpy(&v, &w0, 16);
+      __builtin_memcpy(reinterpret_cast<char*>(&v) + 16, &w1, 16);
+    } else {  // 8 bytes
+      const uint2 w = *reinterpret_cast<const uint2*>(p);
+      __builtin_memcpy(&v, &w, 8);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < E; ++t) v[t] = (i < n && k0 + t < n) ? p[t] : (DT)0;
+  }
+}
+
+template <int GK, int RG, int CG, typename DT>
+__global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
+    const typename Tr<GK>::T* __restrict__ G, int64_t ldg, const typename Tr<GK>::T* __restrict__ Xt, int split,
+    int64_t steps_total, int64_t steps_per_split, typename Tr<GK>::AccS* __restrict__ Ypart, GPassDSrc src) {
   using TT = Tr<GK>;
   using T = typename TT::T;
   using Acc = typename TT::Acc;
   using AccS = typename TT::AccS;
+  constexpr bool FD = DLoad<DT>::kFromD;
+  using RawT = typename std::conditional<FD, DT, T>::type;
+  constexpr int E = 16 / sizeof(T);  // A elements per lane per 16-byte chunk
   constexpr int LPAD = CG * 16;
   constexpr int PIECES = LPAD * 8;  // 16-byte pieces per X step tile
   constexpr int PPT = (PIECES + 255) / 256;
+  constexpr int BK = 128 / sizeof(T);  // K elements per step
   __shared__ __attribute__((aligned(16))) unsigned char xs[2][LPAD * kRowB];
 
   const int tid = threadIdx.x;
@@ -115,15 +177,57 @@ __global__ __launch_bounds__(256, minb_for(GK, CG)) void k_gpass(const typename 
   const size_t rg_stride = 16 * rowbytes;
   const unsigned char* Xb = reinterpret_cast<const unsigned char*>(Xt);
 
+  // recentring state (only used when FD).  CT: precision of the recentring
+  // terms (fp32 passes use fl32(c/2) and fl32((r - m)/2), fp64 passes c, r, m).
+  using CT = T;
+  const DT* Dp = reinterpret_cast<const DT*>(src.D);
+  const int64_t n = src.n;
+  CT ri[RG];
+  bool rowvec[RG];
+  double mval = 0.0;
+  if constexpr (FD) {
+    mval = src.m[0];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) {
+      const int64_t i = row0 + rg * 16 + (lane & 15);
+      if constexpr (sizeof(T) == 4)
+        ri[rg] = (i < n) ? (float)(0.5 * (src.r[i] - mval)) : 0.0f;
+      else
+        ri[rg] = (i < n) ? src.r[i] : 0.0;
+      rowvec[rg] = src.vec && (((i * n) % E) == 0);
+    }
+  }
+
   if (st0 < st1) {
-    u32x4 a[RG][2], an[RG][2];
+    RawT a[RG][2][E], an[RG][2][E];
+    CT cv[2][E], cvn[2][E];
     u32x4 xr[PPT];
-    auto load_a = [&](u32x4 (&dst)[RG][2], int64_t st) {
+    auto load_a = [&](RawT (&dst)[RG][2][E], CT (&cdst)[2][E], int64_t st) {
+      if constexpr (FD) {
 #pragma unroll
-      for (int rg = 0; rg < RG; ++rg)
+        for (int c = 0; c < 2; ++c) {
+          const int64_t k0 = st * BK + c * (BK / 2) + (lane >> 4) * E;
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-          dst[rg][c] = *reinterpret_cast<const u32x4*>(Ab + rg * rg_stride + (size_t)st * 128 + c * 64);
+          for (int rg = 0; rg < RG; ++rg)
+            load_d<DT, E>(Dp, n, row0 + rg * 16 + (lane & 15), k0, rowvec[rg], dst[rg][c]);
+          if constexpr (sizeof(T) == 4) {
+            // hc holds ldg zero-padded entries: one aligned 16-byte load
+            const u32x4 w = *reinterpret_cast<const u32x4*>(src.hc + k0);
+            __builtin_memcpy(&cdst[c], &w, 16);
+          } else {
+#pragma unroll
+            for (int t = 0; t < E; ++t) cdst[c][t] = (k0 + t < n) ? src.c[k0 + t] : 0.0;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const u32x4 w = *reinterpret_cast<const u32x4*>(Ab + rg * rg_stride + (size_t)st * 128 + c * 64);
+            __builtin_memcpy(&dst[rg][c], &w, 16);
+          }
+      }
     };
     auto load_x = [&](int64_t st) {
 #pragma unroll
@@ -142,8 +246,44 @@ __global__ __launch_bounds__(256, minb_for(GK, CG)) void k_gpass(const typename 
           *reinterpret_cast<u32x4*>(buf + (p >> 3) * kRowB + (p & 7) * 16) = xr[u];
       }
     };
+    // A operand of one chunk in MFMA register form.  Recentring mode, fp64:
+    // gamma = -1/2 (((d^2 - c_k) - r_i) + m); fp32: gamma = fma(-1/2,
+    // fl32(d^2), hc_k + hr_i) (one fma per entry instead of fp64 arithmetic).
+    auto a_operand = [&](int rg, int c, int64_t st) -> u32x4 {
+      if constexpr (FD) {
+#pragma clang fp contract(off)
+        const int64_t k0 = st * BK + c * (BK / 2) + (lane >> 4) * E;
+        const int64_t i = row0 + rg * 16 + (lane & 15);
+        T g[E];
+#pragma unroll
+        for (int t = 0; t < E; ++t) {
+          const bool valid = (i < n) && (k0 + t < n);
+          if constexpr (sizeof(T) == 4) {
+            float d2;
+            if constexpr (sizeof(DT) == 4) {
+              const float d = a[rg][c][t];
+              d2 = d * d;
+            } else {
+              const double d = a[rg][c][t];
+              d2 = (float)(d * d);
+            }
+            g[t] = valid ? __builtin_fmaf(-0.5f, d2, cv[c][t] + ri[rg]) : 0.0f;
+          } else {
+            const double d = (double)a[rg][c][t];
+            g[t] = valid ? -0.5 * (((d * d - cv[c][t]) - ri[rg]) + mval) : 0.0;
+          }
+        }
+        u32x4 w;
+        __builtin_memcpy(&w, &g, 16);
+        return w;
+      } else {
+        u32x4 w;
+        __builtin_memcpy(&w, &a[rg][c], 16);
+        return w;
+      }
+    };
 
-    load_a(a, st0);
+    load_a(a, cv, st0);
     load_x(st0);
     store_x(xs[0]);
     __syncthreads();
@@ -152,26 +292,39 @@ __global__ __launch_bounds__(256, minb_for(GK, CG)) void k_gpass(const typename 
       const bool more = st + 1 < st1;
       if (more) {
         load_x(st + 1);
-        load_a(an, st + 1);
+        load_a(an, cvn, st + 1);
       }
       const unsigned char* xb = xs[buf];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
+        u32x4 av[RG];
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) av[rg] = a_operand(rg, c, st);
 #pragma unroll
         for (int cg = 0; cg < CG; ++cg) {
           const u32x4 b =
               *reinterpret_cast<const u32x4*>(xb + (cg * 16 + (lane & 15)) * kRowB + c * 64 + (lane >> 4) * 16);
+          // consecutive MFMAs go to independent accumulators (row groups)
 #pragma unroll
-          for (int rg = 0; rg < RG; ++rg) TT::mma(acc[rg][cg], a[rg][c], b);
+          for (int t = 0; t < TT::kSub; ++t)
+#pragma unroll
+            for (int rg = 0; rg < RG; ++rg) TT::mma_sub(acc[rg][cg], av[rg], b, t);
         }
       }
       if (more) store_x(xs[buf ^ 1]);
       __syncthreads();
       if (more) {
 #pragma unroll
-        for (int rg = 0; rg < RG; ++rg) {
-          a[rg][0] = an[rg][0];
-          a[rg][1] = an[rg][1];
+        for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int t = 0; t < E; ++t) a[rg][c][t] = an[rg][c][t];
+        if constexpr (FD) {
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int t = 0; t < E; ++t) cv[c][t] = cvn[c][t];
         }
       }
     }
@@ -215,31 +368,42 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const AccS* __restrict__ 
   reinterpret_cast<double2*>(Y + e)[1] = make_double2(s2, s3);
 }
 
-template <int GK, int RG, int CG>
+template <int GK, int RG, int CG, typename DT>
 void launch_one(const void* G, int64_t ldg, const void* Xt, const GPassCfg& cfg, int64_t n_pad, void* Yp,
-                hipStream_t s) {
+                const GPassDSrc& src, hipStream_t s) {
   using T = typename Tr<GK>::T;
   using AccS = typename Tr<GK>::AccS;
   const int64_t blocks = (n_pad / (64 * RG)) * cfg.split;
-  hipLaunchKernelGGL((k_gpass<GK, RG, CG>), dim3((unsigned)blocks), dim3(256), 0, s, (const T*)G, ldg,
-                     (const T*)Xt, cfg.split, cfg.steps_total, cfg.steps_per_split, (AccS*)Yp);
+  hipLaunchKernelGGL((k_gpass<GK, RG, CG, DT>), dim3((unsigned)blocks), dim3(256), 0, s, (const T*)G, ldg,
+                     (const T*)Xt, cfg.split, cfg.steps_total, cfg.steps_per_split, (AccS*)Yp, src);
 }
 
 template <int GK, int CG>
 hipError_t launch_cg(const void* G, int64_t ldg, const void* Xt, const GPassCfg& cfg, int64_t n_pad, void* Yp,
-                     hipStream_t s) {
-  constexpr int RG = rg_for(GK, CG);
-  if (cfg.rg != RG) return hipErrorInvalidValue;
-  launch_one<GK, RG, CG>(G, ldg, Xt, cfg, n_pad, Yp, s);
+                     const GPassDSrc& src, hipStream_t s) {
+  if (!src.D) {
+    constexpr int RG = rg_for(GK, CG);
+    if (cfg.rg != RG) return hipErrorInvalidValue;
+    launch_one<GK, RG, CG, void>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
+  } else if constexpr (GK == GK_BF16) {
+    return hipErrorInvalidValue;  // bf16 passes read the stored bf16 G
+  } else {
+    constexpr int RG = rg_fd(GK, CG);
+    if (cfg.rg != RG) return hipErrorInvalidValue;
+    if (src.d_is_f64)
+      launch_one<GK, RG, CG, double>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
+    else
+      launch_one<GK, RG, CG, float>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
+  }
   return hipGetLastError();
 }
 
 template <int GK>
 hipError_t launch_gk(const void* G, int64_t ldg, const void* Xt, int l_pad, const GPassCfg& cfg, int64_t n_pad,
-                     void* Yp, hipStream_t s) {
+                     void* Yp, const GPassDSrc& src, hipStream_t s) {
   switch (l_pad / 16) {
 #define MDS_CG(N) \
-  case N: return launch_cg<GK, N>(G, ldg, Xt, cfg, n_pad, Yp, s);
+  case N: return launch_cg<GK, N>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
     MDS_CG(1) MDS_CG(2) MDS_CG(3) MDS_CG(4) MDS_CG(5) MDS_CG(6) MDS_CG(7) MDS_CG(8)
     MDS_CG(9) MDS_CG(10) MDS_CG(11) MDS_CG(12) MDS_CG(13) MDS_CG(14) MDS_CG(15) MDS_CG(16)
 #undef MDS_CG
@@ -249,9 +413,9 @@ hipError_t launch_gk(const void* G, int64_t ldg, const void* Xt, int l_pad, cons
 
 }  // namespace
 
-GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint) {
+GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d) {
   GPassCfg c{};
-  c.rg = rg_for(gk, l_pad / 16);
+  c.rg = from_d ? rg_fd(gk, l_pad / 16) : rg_for(gk, l_pad / 16);
   c.bm = 64 * c.rg;
   const int64_t esize = gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : 2);
   c.steps_total = ldg * esize / 128;
@@ -268,15 +432,17 @@ GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_h
 }
 
 hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const void* Xt, int l_pad,
-                        const GPassCfg& cfg, void* Ypart, hipStream_t s) {
+                        const GPassCfg& cfg, void* Ypart, const GPassDSrc& src, hipStream_t s) {
   if (l_pad % 16 != 0 || l_pad < 16 || l_pad > kMaxL || n_pad % cfg.bm != 0) return hipErrorInvalidValue;
   switch (gk) {
-    case GK_F64: return launch_gk<GK_F64>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, s);
-    case GK_F32: return launch_gk<GK_F32>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, s);
-    case GK_BF16: return launch_gk<GK_BF16>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, s);
+    case GK_F64: return launch_gk<GK_F64>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
+    case GK_F32: return launch_gk<GK_F32>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
+    case GK_BF16: return launch_gk<GK_BF16>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
     default: return hipErrorInvalidValue;
   }
 }
+
+int64_t gpass_blocks(const GPassCfg& cfg, int64_t n_pad) { return (n_pad / cfg.bm) * cfg.split; }
 
 hipError_t launch_splitk_reduce(int gk, const void* Ypart, int split, int64_t elems, double* Y, hipStream_t s) {
   const unsigned blocks = (unsigned)((elems / 4 + 255) / 256);

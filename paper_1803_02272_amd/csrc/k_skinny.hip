@@ -32,13 +32,28 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, cons
   for (int cg = 0; cg < CG; ++cg) acc[cg] = doublex4_t{0.0, 0.0, 0.0, 0.0};
   const double* Ar = A + (int64_t)(tr * 16 + (lane & 15)) * ldg + (lane >> 4) * 2;
   const double* Br = B + (int64_t)(lane & 15) * ldg + (lane >> 4) * 2;
+  // software pipeline: the operands of step k+8 are loaded while step k runs
+  double2 a = *reinterpret_cast<const double2*>(Ar + i0);
+  double2 b[CG];
+#pragma unroll
+  for (int cg = 0; cg < CG; ++cg) b[cg] = *reinterpret_cast<const double2*>(Br + (int64_t)cg * 16 * ldg + i0);
   for (int64_t k = i0; k < i1; k += 8) {
-    const double2 a = *reinterpret_cast<const double2*>(Ar + k);
+    const bool more = k + 8 < i1;
+    double2 an = a, bn[CG];
+    if (more) {
+      an = *reinterpret_cast<const double2*>(Ar + k + 8);
+#pragma unroll
+      for (int cg = 0; cg < CG; ++cg) bn[cg] = *reinterpret_cast<const double2*>(Br + (int64_t)cg * 16 * ldg + k + 8);
+    }
 #pragma unroll
     for (int cg = 0; cg < CG; ++cg) {
-      const double2 b = *reinterpret_cast<const double2*>(Br + (int64_t)cg * 16 * ldg + k);
-      acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc[cg], 0, 0, 0);
-      acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, acc[cg], 0, 0, 0);
+      acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[cg].x, acc[cg], 0, 0, 0);
+      acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b[cg].y, acc[cg], 0, 0, 0);
+    }
+    if (more) {
+      a = an;
+#pragma unroll
+      for (int cg = 0; cg < CG; ++cg) b[cg] = bn[cg];
     }
   }
   double* W = Wpart + p * (int64_t)l_pad * l_pad;
@@ -56,11 +71,10 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ pa
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= elems) return;
   double s = 0.0;
+#pragma unroll 8
   for (int64_t p = 0; p < nparts; ++p) s += parts[p * elems + e];
   out[e] = s;
 }
-
-constexpr int kJC = 16;  // output columns per LDS-staged block of T
 
 __device__ __forceinline__ uint16_t bf16_rne(double v) {
   uint32_t u = __float_as_uint((float)v);
@@ -69,39 +83,67 @@ __device__ __forceinline__ uint16_t bf16_rne(double v) {
   return (uint16_t)(u >> 16);
 }
 
+// Out[j][i] = sum_a T[a][j] In[a][i] on fp64 MFMA (16x16x4): A operand = T^T
+// (rows j, K = a) from an LDS block of 64 columns of T, B operand = In (K = a,
+// columns i, 16 consecutive i per lane group: 128-byte loads).  A workgroup
+// covers 256 columns i (64 per wave, four 16-column tiles) and 64 rows j; the
+// l rows of In are padded to a multiple of 4 (In is zero beyond l).
+constexpr int kApJ = 64;
+constexpr int kApRow = kApJ + 2;  // LDS row stride (doubles)
+constexpr int kApN = 4;           // 16-column tiles per wave
+
 __global__ __launch_bounds__(256) void k_apply(const double* __restrict__ In, int l, int64_t ldg,
-                                               const double* __restrict__ T, int ldt, int lt, int l_pad,
+                                               const double* __restrict__ T, int ldt, int lt, int l_out,
                                                double* __restrict__ Out, int xk, void* __restrict__ Xc) {
-  __shared__ double Ts[kMaxL * kJC];
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;  // ldg % 256 == 0
-  for (int j0 = 0; j0 < l_pad; j0 += kJC) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < l * kJC; e += 256) {
-      const int a = e / kJC, j = j0 + e % kJC;
-      Ts[e] = (j < lt) ? T[(int64_t)a * ldt + j] : 0.0;
-    }
-    __syncthreads();
-    double acc[kJC];
+  extern __shared__ double Ts[];  // la x kApRow
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int la = (l + 3) & ~3;
+  const int j0 = blockIdx.y * kApJ;
+  const int64_t i0 = (int64_t)blockIdx.x * (64 * kApN) + wave * (16 * kApN);
+  for (int e = tid; e < la * kApJ; e += 256) {
+    const int a = e / kApJ, jj = e % kApJ, j = j0 + jj;
+    Ts[a * kApRow + jj] = (a < l && j < lt) ? T[(int64_t)a * ldt + j] : 0.0;
+  }
+  __syncthreads();
+  doublex4_t acc[kApN][4];
 #pragma unroll
-    for (int jj = 0; jj < kJC; ++jj) acc[jj] = 0.0;
-#pragma unroll 4
-    for (int a = 0; a < l; ++a) {
-      const double y = In[(int64_t)a * ldg + i];
+  for (int nt = 0; nt < kApN; ++nt)
 #pragma unroll
-      for (int jj = 0; jj < kJC; ++jj) acc[jj] += Ts[a * kJC + jj] * y;
-    }
+    for (int t = 0; t < 4; ++t) acc[nt][t] = doublex4_t{0.0, 0.0, 0.0, 0.0};
+  const double* Ib = In + (int64_t)(lane >> 4) * ldg + i0 + (lane & 15);
+  const int ar = lane >> 4, jc = lane & 15;
+  for (int a0 = 0; a0 < la; a0 += 4) {
+    double b[kApN];
 #pragma unroll
-    for (int jj = 0; jj < kJC; ++jj) {
-      const int64_t o = (int64_t)(j0 + jj) * ldg + i;
-      Out[o] = acc[jj];
-      if (xk == GK_F64)
-        reinterpret_cast<double*>(Xc)[o] = acc[jj];
-      else if (xk == GK_F32)
-        reinterpret_cast<float*>(Xc)[o] = (float)acc[jj];
-      else if (xk == GK_BF16)
-        reinterpret_cast<uint16_t*>(Xc)[o] = bf16_rne(acc[jj]);
+    for (int nt = 0; nt < kApN; ++nt) b[nt] = Ib[(int64_t)a0 * ldg + nt * 16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double av = Ts[(a0 + ar) * kApRow + t * 16 + jc];
+#pragma unroll
+      for (int nt = 0; nt < kApN; ++nt)
+        acc[nt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[nt], acc[nt][t], 0, 0, 0);
     }
   }
+  // fp64 accumulator layout: register r of lane group g is row g + 4r
+#pragma unroll
+  for (int nt = 0; nt < kApN; ++nt)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = j0 + t * 16 + (lane >> 4) + 4 * r;
+        if (j < l_out) {
+          const int64_t o = (int64_t)j * ldg + i0 + nt * 16 + (lane & 15);
+          const double v = acc[nt][t][r];
+          Out[o] = v;
+          if (xk == GK_F64)
+            reinterpret_cast<double*>(Xc)[o] = v;
+          else if (xk == GK_F32)
+            reinterpret_cast<float*>(Xc)[o] = (float)v;
+          else if (xk == GK_BF16)
+            reinterpret_cast<uint16_t*>(Xc)[o] = bf16_rne(v);
+        }
+      }
 }
 
 // Better candidate for the column's sign anchor: larger magnitude, then lower row.
@@ -110,91 +152,91 @@ __device__ __forceinline__ bool better(double va, int64_t ia, double vb, int64_t
   return aa > ab || (aa == ab && ia < ib);
 }
 
-__global__ __launch_bounds__(256) void k_coords(const double* __restrict__ Qt, int l, int64_t n, int64_t ldg,
-                                                const double* __restrict__ Tc, int k,
-                                                double* __restrict__ coords, double* __restrict__ vpart,
-                                                int64_t* __restrict__ ipart) {
-  __shared__ double Ts[kMaxL * kJC];
-  __shared__ double wv[4][kJC];
-  __shared__ int64_t wi[4][kJC];
+constexpr int kAnchorChunk = 4096;
+
+// Per (column a, chunk): entry of largest magnitude of row a of Ct.
+__global__ __launch_bounds__(256) void k_anchor_part(const double* __restrict__ Ct, int64_t n, int64_t ldg,
+                                                     double* __restrict__ vpart, int64_t* __restrict__ ipart,
+                                                     int64_t nchunks) {
+  __shared__ double wv[4];
+  __shared__ int64_t wi[4];
+  const int a = blockIdx.y;
+  const int64_t c0 = (int64_t)blockIdx.x * kAnchorChunk;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  for (int j0 = 0; j0 < k; j0 += kJC) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < l * kJC; e += 256) {
-      const int a = e / kJC, j = j0 + e % kJC;
-      Ts[e] = (j < k) ? Tc[(int64_t)a * k + j] : 0.0;
+  double v = 0.0;
+  int64_t idx = INT64_MAX;
+  for (int64_t i = c0 + threadIdx.x; i < c0 + kAnchorChunk && i < n; i += 256) {
+    const double x = Ct[(int64_t)a * ldg + i];
+    if (better(x, i, v, idx)) {
+      v = x;
+      idx = i;
     }
-    __syncthreads();
-    double acc[kJC];
-#pragma unroll
-    for (int jj = 0; jj < kJC; ++jj) acc[jj] = 0.0;
-    if (i < n) {
-#pragma unroll 4
-      for (int a = 0; a < l; ++a) {
-        const double y = Qt[(int64_t)a * ldg + i];
-#pragma unroll
-        for (int jj = 0; jj < kJC; ++jj) acc[jj] += Ts[a * kJC + jj] * y;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off, 64);
+    const int64_t oi = __shfl_xor(idx, off, 64);
+    if (better(ov, oi, v, idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+  if (lane == 0) {
+    wv[wave] = v;
+    wi[wave] = idx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w)
+      if (better(wv[w], wi[w], v, idx)) {
+        v = wv[w];
+        idx = wi[w];
       }
-#pragma unroll
-      for (int jj = 0; jj < kJC; ++jj)
-        if (j0 + jj < k) coords[i * k + j0 + jj] = acc[jj];
-    }
-    // per-column anchor candidates of this block
-#pragma unroll
-    for (int jj = 0; jj < kJC; ++jj) {
-      double v = (i < n) ? acc[jj] : 0.0;
-      int64_t idx = (i < n) ? i : INT64_MAX;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const int64_t oi = __shfl_xor(idx, off, 64);
-        if (better(ov, oi, v, idx)) {
-          v = ov;
-          idx = oi;
-        }
-      }
-      if (lane == 0) {
-        wv[wave][jj] = v;
-        wi[wave][jj] = idx;
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x < kJC && j0 + (int)threadIdx.x < k) {
-      const int jj = threadIdx.x;
-      double v = wv[0][jj];
-      int64_t idx = wi[0][jj];
-      for (int w = 1; w < 4; ++w)
-        if (better(wv[w][jj], wi[w][jj], v, idx)) {
-          v = wv[w][jj];
-          idx = wi[w][jj];
-        }
-      vpart[(int64_t)blockIdx.x * k + j0 + jj] = v;
-      ipart[(int64_t)blockIdx.x * k + j0 + jj] = idx;
-    }
+    vpart[(int64_t)a * nchunks + blockIdx.x] = v;
+    ipart[(int64_t)a * nchunks + blockIdx.x] = idx;
   }
 }
 
-__global__ __launch_bounds__(256) void k_sign_anchor(const double* __restrict__ vpart,
-                                                     const int64_t* __restrict__ ipart, int64_t nblk, int k,
-                                                     double* __restrict__ sign) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= k) return;
-  double v = vpart[j];
-  int64_t idx = ipart[j];
-  for (int64_t b = 1; b < nblk; ++b)
-    if (better(vpart[b * k + j], ipart[b * k + j], v, idx)) {
-      v = vpart[b * k + j];
-      idx = ipart[b * k + j];
+__global__ __launch_bounds__(64) void k_sign_anchor(const double* __restrict__ vpart,
+                                                    const int64_t* __restrict__ ipart, int64_t nchunks,
+                                                    double* __restrict__ sign) {
+  const int a = blockIdx.x;
+  double v = 0.0;
+  int64_t idx = INT64_MAX;
+  for (int64_t c = threadIdx.x; c < nchunks; c += 64)
+    if (better(vpart[a * nchunks + c], ipart[a * nchunks + c], v, idx)) {
+      v = vpart[a * nchunks + c];
+      idx = ipart[a * nchunks + c];
     }
-  sign[j] = (v < 0.0) ? -1.0 : 1.0;
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off, 64);
+    const int64_t oi = __shfl_xor(idx, off, 64);
+    if (better(ov, oi, v, idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+  if (threadIdx.x == 0) sign[a] = (v < 0.0) ? -1.0 : 1.0;
 }
 
-__global__ __launch_bounds__(256) void k_sign_apply(double* __restrict__ coords, int64_t total, int k,
-                                                    const double* __restrict__ sign) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= total) return;
-  coords[e] *= sign[e % k];
+// coords[i][a] = sign[a] * Ct[a][i], transposed through LDS (64 rows i x k).
+__global__ __launch_bounds__(256) void k_coords_write(const double* __restrict__ Ct, int64_t n, int64_t ldg, int k,
+                                                      const double* __restrict__ sign, double* __restrict__ coords) {
+  __shared__ double tile[16][64 + 1];
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int a0 = blockIdx.y * 16;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 16 * 64; e += 256) {
+    const int aa = e / 64, ii = e % 64;
+    const int a = a0 + aa;
+    tile[aa][ii] = (a < k) ? sign[a] * Ct[(int64_t)a * ldg + i0 + ii] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < 16 * 64; e += 256) {
+    const int ii = e / 16, aa = e % 16;
+    const int64_t i = i0 + ii;
+    const int a = a0 + aa;
+    if (i < n && a < k) coords[i * k + a] = tile[aa][ii];
+  }
 }
 
 template <int CG>
@@ -225,24 +267,35 @@ hipError_t launch_gram(const double* A, const double* B, int l_pad, int64_t ldg,
 
 hipError_t launch_apply(const double* In, int l, int64_t ldg, const double* T, int ldt, int lt, int l_pad,
                         double* Out, int xk, void* Xc, hipStream_t s) {
-  if (l > kMaxL || l_pad > kMaxL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_apply, dim3((unsigned)(ldg / 256)), dim3(256), 0, s, In, l, ldg, T, ldt, lt, l_pad, Out,
-                     Xc ? xk : -1, Xc);
+  if (l > kMaxL || l_pad > kMaxL || ldg % (64 * kApN) != 0) return hipErrorInvalidValue;
+  const int la = (l + 3) & ~3;
+  const size_t shm = (size_t)la * kApRow * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(kMaxL * kApRow * sizeof(double)));
+    attr_set = true;
+  }
+  dim3 grid((unsigned)(ldg / (64 * kApN)), (unsigned)((l_pad + kApJ - 1) / kApJ));
+  hipLaunchKernelGGL(k_apply, grid, dim3(256), shm, s, In, l, ldg, T, ldt, lt, l_pad, Out, Xc ? xk : -1, Xc);
   return hipGetLastError();
 }
 
-hipError_t launch_coords(const double* Qt, int l, int64_t n, int64_t ldg, const double* Tc, int k,
+int64_t coords_anchor_chunks(int64_t n) { return (n + kAnchorChunk - 1) / kAnchorChunk; }
+
+hipError_t launch_coords(const double* Qt, int l, int64_t n, int64_t ldg, const double* Tc, int k, double* Ct,
                          double* coords, double* sign_part, int64_t* idx_part, hipStream_t s) {
-  if (l > kMaxL) return hipErrorInvalidValue;
-  const int64_t nblk = (n + 255) / 256;
-  hipLaunchKernelGGL(k_coords, dim3((unsigned)nblk), dim3(256), 0, s, Qt, l, n, ldg, Tc, k, coords, sign_part,
-                     idx_part);
-  double* sign = sign_part + nblk * k;
-  hipLaunchKernelGGL(k_sign_anchor, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, sign_part, idx_part,
-                     nblk, k, sign);
-  const int64_t total = n * (int64_t)k;
-  hipLaunchKernelGGL(k_sign_apply, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, coords, total, k,
-                     sign);
+  if (l > kMaxL || k > l) return hipErrorInvalidValue;
+  const int k_pad = (k + 15) & ~15;
+  hipError_t e = launch_apply(Qt, l, ldg, Tc, k, k, k_pad, Ct, -1, nullptr, s);
+  if (e != hipSuccess) return e;
+  const int64_t nch = coords_anchor_chunks(n);
+  hipLaunchKernelGGL(k_anchor_part, dim3((unsigned)nch, (unsigned)k), dim3(256), 0, s, Ct, n, ldg, sign_part,
+                     idx_part, nch);
+  double* sign = sign_part + nch * k;
+  hipLaunchKernelGGL(k_sign_anchor, dim3((unsigned)k), dim3(64), 0, s, sign_part, idx_part, nch, sign);
+  hipLaunchKernelGGL(k_coords_write, dim3((unsigned)((n + 63) / 64), (unsigned)((k + 15) / 16)), dim3(256), 0, s,
+                     Ct, n, ldg, k, sign, coords);
   return hipGetLastError();
 }
 

@@ -1,8 +1,10 @@
-// Small dense kernels (one workgroup of 1024 threads, fp64):
+// Small dense kernels (fp64, one workgroup per l x l problem):
 //
 //   orth_factor  From W = Y^T Y build T with Y T orthonormal.  First choice is
 //                Cholesky W = R^T R and T = R^{-1} (one CholeskyQR step;
-//                applied twice this is CholeskyQR2, Fukaya et al. 2014).  When
+//                applied twice this is CholeskyQR2, Fukaya et al. 2014).  In
+//                the second step W is I + E with tiny E; when max|E| < 1e-9
+//                the factor is I - triu(E) (diagonal E/2), exact to O(E^2).  When
 //                a pivot collapses (rank-deficient or too ill-conditioned Y)
 //                it falls back to the eigendecomposition W = V S V^T and
 //                T = V S^{-1/2}, dropping directions with s <= 1e-13 s_max, so
@@ -16,26 +18,42 @@
 // The symmetric eigensolver is cyclic Jacobi with the round-robin parallel
 // ordering: every round rotates l/2 disjoint pairs at once, each thread
 // updating whole 2x2 blocks J_p^T M_pq J_q, so a round needs two barriers.
-// A rotation is skipped when |m_pq| <= 1e-17 ||M||_F; a sweep with no
-// rotation ends the iteration (cap 40 sweeps).  For l <= 128 the working
-// matrix lives in LDS; larger l use a global scratch buffer.
+// A rotation is skipped when |m_pq| <= 1e-17 ||M||_F; the iteration stops
+// after the first sweep that ends with off(M) <= 1e-15 ||M||_F or that
+// rotated nothing (cap 40 sweeps).  In small_eig the rotations are recorded
+// (c, s per pair and round) and the eigenvector matrix is accumulated
+// afterwards by k_rot_apply, one workgroup per row of V, so the sweep loop
+// touches only LDS.  For l_pad <= 128 the working matrix lives in LDS;
+// larger l use a global scratch buffer.
+#include <type_traits>
+
 #include "mds_internal.h"
 
 namespace mds {
 namespace {
 
-constexpr int kThreads = 1024;
+constexpr int kEigThreads = 1024;  // small_eig workgroup
+constexpr int kOrthThreads = 256;  // orth_factor workgroup
+constexpr int kNB = 16;            // panel width of the blocked Cholesky / inverse
 constexpr int kMaxPairs = kMaxL / 2;
 constexpr int kMaxSweeps = 40;
 
+typedef __attribute__((address_space(3))) double lds_double;
+
 struct JacobiShared {
-  int p[kMaxPairs], q[kMaxPairs];
-  double c[kMaxPairs], s[kMaxPairs], t[kMaxPairs];
-  int active[kMaxPairs];
+  int2 pq[kMaxPairs];
+  double2 cs[kMaxPairs];
+  double t[kMaxPairs];
   int nrot;
-  double red[kThreads / 64];
+  double red[kEigThreads / 64];
 };
 
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int kThreads>
 __device__ double block_sum(double v, double* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -48,6 +66,7 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
+template <int kThreads>
 __device__ double block_max(double v, double* red) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -60,207 +79,411 @@ __device__ double block_max(double v, double* red) {
   return s;
 }
 
-// Cyclic Jacobi on the symmetric le x le matrix M (ld ldm), accumulating the
-// rotations into V (ld ldv, identity on entry).  le is even; a padding
-// row/column of zeros is never rotated.  Returns the number of sweeps, or
-// -1 if the sweep cap was reached.
-__device__ int jacobi(double* M, int ldm, double* V, int ldv, int le, JacobiShared& sh) {
+__device__ __forceinline__ void round_robin_pair(int le, int r, int t, int& p, int& q) {
+  if (t == 0) {
+    p = le - 1;
+    q = r;
+  } else {
+    p = (r + t) % (le - 1);
+    q = (r - t + (le - 1)) % (le - 1);
+  }
+  if (p > q) {
+    const int x = p;
+    p = q;
+    q = x;
+  }
+}
+
+template <int kThreads, typename MT>
+__device__ double frob2(MT M, int ldm, int le) {
+  double f = 0.0;
+  for (int e = threadIdx.x; e < le * le; e += kThreads) {
+    const double v = M[(e / le) * ldm + e % le];
+    f += v * v;
+  }
+  return f;
+}
+
+template <int kThreads, typename MT>
+__device__ double off2(MT M, int ldm, int le) {
+  double f = 0.0;
+  for (int e = threadIdx.x; e < le * le; e += kThreads) {
+    const int i = e / le, j = e % le;
+    if (i != j) {
+      const double v = M[i * ldm + j];
+      f += v * v;
+    }
+  }
+  return f;
+}
+
+// Cyclic Jacobi on the symmetric le x le matrix M (ld ldm; le even, a padding
+// row/column of zeros is never rotated).  Either accumulates V <- V J in
+// place (V != nullptr, ld ldv, identity on entry) or records (c, s) of every
+// pair and round in rot (rot != nullptr).  Returns sweeps used (negative if
+// the cap was hit); *rounds receives the number of rounds recorded.
+template <int kThreads, typename MT>
+__device__ int jacobi(MT M, int ldm, double* V, int ldv, double2* rot, int le, JacobiShared& sh, int* rounds) {
+  constexpr int kMaxBlocksPerThread = (kMaxL / 2) * (kMaxL / 2) / kThreads;
   const int tid = threadIdx.x;
   const int np = le / 2;
-  double fro = 0.0;
-  for (int e = tid; e < le * le; e += kThreads) {
-    const double v = M[(e / le) * ldm + e % le];
-    fro += v * v;
-  }
-  fro = sqrt(block_sum(fro, sh.red));
+  // this thread's fixed (pair a, pair b) blocks; pairs are renamed every round
+  // but the block list of a thread is the same in all rounds
+  int nblk = 0;
+  int blk[kMaxBlocksPerThread];
+  for (int e = tid; e < np * np && nblk < kMaxBlocksPerThread; e += kThreads) blk[nblk++] = ((e / np) << 16) | (e % np);
+  const double fro = sqrt(block_sum<kThreads>(frob2<kThreads>(M, ldm, le), sh.red));
   const double thr = 1e-17 * fro;
+  int nr = 0;
   int sweep = 0;
-  for (; sweep < kMaxSweeps; ++sweep) {
+  bool converged = false;
+  for (; sweep < kMaxSweeps && !converged; ++sweep) {
     if (tid == 0) sh.nrot = 0;
     __syncthreads();
-    for (int r = 0; r < le - 1; ++r) {
+    for (int r = 0; r < le - 1; ++r, ++nr) {
       if (tid < np) {
         int p, q;
-        if (tid == 0) {
-          p = le - 1;
-          q = r;
-        } else {
-          p = (r + tid) % (le - 1);
-          q = (r - tid + (le - 1)) % (le - 1);
-        }
-        if (p > q) {
-          const int x = p;
-          p = q;
-          q = x;
-        }
+        round_robin_pair(le, r, tid, p, q);
         const double app = M[p * ldm + p], aqq = M[q * ldm + q], apq = M[p * ldm + q];
         double c = 1.0, s = 0.0, t = 0.0;
-        int act = 0;
         if (fabs(apq) > thr) {
           const double tau = (aqq - app) / (2.0 * apq);
-          if (fabs(tau) > 1e150) {
-            t = 0.5 / tau;
-          } else {
-            t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          }
+          t = fabs(tau) > 1e150 ? 0.5 / tau : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
           s = t * c;
-          act = 1;
           atomicAdd(&sh.nrot, 1);
         }
-        sh.p[tid] = p;
-        sh.q[tid] = q;
-        sh.c[tid] = c;
-        sh.s[tid] = s;
+        sh.pq[tid] = make_int2(p, q);
+        sh.cs[tid] = make_double2(c, s);
         sh.t[tid] = t;
-        sh.active[tid] = act;
+        if (rot) rot[(int64_t)nr * np + tid] = make_double2(c, s);
       }
       __syncthreads();
-      // M <- J^T M J, one 2x2 block (pair a rows, pair b columns) at a time
-      for (int e = tid; e < np * np; e += kThreads) {
-        const int a = e / np, b = e % np;
-        if (!sh.active[a] && !sh.active[b]) continue;
-        const int pa = sh.p[a], qa = sh.q[a], pb = sh.p[b], qb = sh.q[b];
-        const double ca = sh.c[a], sa = sh.s[a], cb = sh.c[b], sb = sh.s[b];
-        const double m00 = M[pa * ldm + pb], m01 = M[pa * ldm + qb];
-        const double m10 = M[qa * ldm + pb], m11 = M[qa * ldm + qb];
-        if (a == b) {
-          const double t = sh.t[a];
-          M[pa * ldm + pa] = m00 - t * m01;
-          M[qa * ldm + qa] = m11 + t * m01;
-          M[pa * ldm + qa] = 0.0;
-          M[qa * ldm + pa] = 0.0;
-        } else {
-          // rows: r_p = c x_p - s x_q, r_q = s x_p + c x_q
-          const double r00 = ca * m00 - sa * m10, r01 = ca * m01 - sa * m11;
-          const double r10 = sa * m00 + ca * m10, r11 = sa * m01 + ca * m11;
-          // columns: y_p = c r_p - s r_q, y_q = s r_p + c r_q
-          M[pa * ldm + pb] = cb * r00 - sb * r01;
-          M[pa * ldm + qb] = sb * r00 + cb * r01;
-          M[qa * ldm + pb] = cb * r10 - sb * r11;
-          M[qa * ldm + qb] = sb * r10 + cb * r11;
+      // M <- J^T M J, one 2x2 block (pair a rows, pair b columns) at a time.
+      // All loads of this thread's blocks are issued before any store (the
+      // blocks are disjoint), so their LDS latencies overlap.
+      for (int u0 = 0; u0 < nblk; u0 += 4) {
+        double m[4][4];
+        int idx[4][4];
+        bool act[4];
+#pragma unroll
+        for (int uu = 0; uu < 4; ++uu) {
+          const int u = u0 + uu;
+          act[uu] = false;
+          if (u < nblk) {
+            const int a = blk[u] >> 16, b = blk[u] & 0xffff;
+            act[uu] = sh.cs[a].y != 0.0 || sh.cs[b].y != 0.0;
+            const int2 pqa = sh.pq[a], pqb = sh.pq[b];
+            idx[uu][0] = pqa.x * ldm + pqb.x;
+            idx[uu][1] = pqa.x * ldm + pqb.y;
+            idx[uu][2] = pqa.y * ldm + pqb.x;
+            idx[uu][3] = pqa.y * ldm + pqb.y;
+            if (act[uu]) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) m[uu][e] = M[idx[uu][e]];
+            }
+          }
+        }
+#pragma unroll
+        for (int uu = 0; uu < 4; ++uu) {
+          if (!act[uu]) continue;
+          const int u = u0 + uu;
+          const int a = blk[u] >> 16, b = blk[u] & 0xffff;
+          const double m00 = m[uu][0], m01 = m[uu][1], m10 = m[uu][2], m11 = m[uu][3];
+          if (a == b) {
+            const double t = sh.t[a];
+            M[idx[uu][0]] = m00 - t * m01;
+            M[idx[uu][3]] = m11 + t * m01;
+            M[idx[uu][1]] = 0.0;
+            M[idx[uu][2]] = 0.0;
+          } else {
+            const double2 csa = sh.cs[a], csb = sh.cs[b];
+            const double ca = csa.x, sa = csa.y, cb = csb.x, sb = csb.y;
+            // rows: r_p = c x_p - s x_q, r_q = s x_p + c x_q
+            const double r00 = ca * m00 - sa * m10, r01 = ca * m01 - sa * m11;
+            const double r10 = sa * m00 + ca * m10, r11 = sa * m01 + ca * m11;
+            // columns: y_p = c r_p - s r_q, y_q = s r_p + c r_q
+            M[idx[uu][0]] = cb * r00 - sb * r01;
+            M[idx[uu][1]] = sb * r00 + cb * r01;
+            M[idx[uu][2]] = cb * r10 - sb * r11;
+            M[idx[uu][3]] = sb * r10 + cb * r11;
+          }
         }
       }
-      // V <- V J
-      for (int e = tid; e < le * np; e += kThreads) {
-        const int i = e / np, b = e % np;
-        if (!sh.active[b]) continue;
-        const int pb = sh.p[b], qb = sh.q[b];
-        const double cb = sh.c[b], sb = sh.s[b];
-        const double vp = V[i * ldv + pb], vq = V[i * ldv + qb];
-        V[i * ldv + pb] = cb * vp - sb * vq;
-        V[i * ldv + qb] = sb * vp + cb * vq;
+      if (V) {
+        for (int i = tid / np; i < le; i += kThreads / np) {
+          const int b = tid % np;
+          if (tid >= (kThreads / np) * np) break;
+          const double2 csb = sh.cs[b];
+          if (csb.y == 0.0) continue;
+          const int2 pqb = sh.pq[b];
+          const double vp = V[i * ldv + pqb.x], vq = V[i * ldv + pqb.y];
+          V[i * ldv + pqb.x] = csb.x * vp - csb.y * vq;
+          V[i * ldv + pqb.y] = csb.y * vp + csb.x * vq;
+        }
       }
       __syncthreads();
     }
-    if (sh.nrot == 0) return sweep + 1;
-    __syncthreads();
+    const int nrot = sh.nrot;
+    const double off = sqrt(block_sum<kThreads>(off2<kThreads>(M, ldm, le), sh.red));
+    converged = (nrot == 0) || (off <= 1e-15 * fro);
   }
-  return -1;
+  *rounds = nr;
+  return converged ? sweep : -sweep;
 }
 
 // ---- orthonormalisation factor ----------------------------------------------
+// Blocked right-looking Cholesky W = R^T R (upper R in M).  Panel rows
+// [k0, k0+16) are factored by wave 0 alone (wave-synchronous, no workgroup
+// barrier); the trailing update M22 -= R12^T R12 is done by all threads with
+// 4x4 register tiles.  Returns false (uniformly) on a collapsed pivot.
+template <int NT, typename MT>
+__device__ bool chol_blocked(MT M, int ldm, int l, const double* wdiag, int* flag) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int k0 = 0; k0 < l; k0 += kNB) {
+    const int nb = (l - k0 < kNB) ? l - k0 : kNB;
+    if (wave == 0) {
+      // left-looking inside the panel: row kk of R from the finished panel
+      // rows above it (loads only, then one store per entry)
+      int ok = 1;
+      for (int kk = k0; kk < k0 + nb; ++kk) {
+        const int nm = kk - k0;  // finished rows in this panel
+        // loads are unconditional from in-bounds addresses (k0 + 15 < l_pad,
+        // columns clamped) and masked by selects, so they issue back to back
+        double col[kNB];  // R[m][kk], m = k0 .. kk-1 (same on every lane)
+#pragma unroll
+        for (int m = 0; m < kNB; ++m) {
+          const double x = M[(k0 + m) * ldm + kk];
+          col[m] = (m < nm) ? x : 0.0;
+        }
+        constexpr int kMaxJ = kMaxL / 64;
+        double row[kMaxJ];
+#pragma unroll
+        for (int c = 0; c < kMaxJ; ++c) {
+          const int j = kk + 1 + lane + 64 * c;
+          const int jc = j < ldm ? j : ldm - 1;
+          double v = M[kk * ldm + jc];
+#pragma unroll
+          for (int m = 0; m < kNB; ++m) v -= col[m] * M[(k0 + m) * ldm + jc];
+          row[c] = v;
+        }
+        double piv = M[kk * ldm + kk];
+#pragma unroll
+        for (int m = 0; m < kNB; ++m) piv -= col[m] * col[m];
+        if (!(piv > 1e-12 * wdiag[kk]) || !(piv > 0.0)) {
+          ok = 0;
+          break;  // uniform within the wave
+        }
+        const double rkk = sqrt(piv), rinv = 1.0 / rkk;
+#pragma unroll
+        for (int c = 0; c < kMaxJ; ++c) {
+          const int j = kk + 1 + lane + 64 * c;
+          if (j < l) M[kk * ldm + j] = row[c] * rinv;
+        }
+        if (lane == 0) M[kk * ldm + kk] = rkk;
+        wave_sync();
+      }
+      if (lane == 0) *flag = ok;
+    }
+    __syncthreads();
+    if (!*flag) return false;
+    const int t0 = k0 + nb;
+    if (t0 < l) {
+      const int ty = tid / 16, tx = tid % 16;  // NT == 256
+      for (int ib = t0; ib < l; ib += 64) {
+        for (int jb = ib; jb < l; jb += 64) {
+          double acc[4][4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+          for (int kk = k0; kk < t0; ++kk) {
+            double ci[4], cj[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const int i = ib + ty + 16 * a;
+              const double x = M[kk * ldm + (i < ldm ? i : ldm - 1)];
+              ci[a] = (i < l) ? x : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const int j = jb + tx + 16 * c;
+              const double x = M[kk * ldm + (j < ldm ? j : ldm - 1)];
+              cj[c] = (j < l) ? x : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+              for (int c = 0; c < 4; ++c) acc[a][c] += ci[a] * cj[c];
+          }
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const int i = ib + ty + 16 * a, j = jb + tx + 16 * c;
+              if (i < l && j < l && j >= i) M[i * ldm + j] -= acc[a][c];
+            }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// In-place blocked inverse of the upper triangular R in M (T = R^{-1}).  For
+// each 16-column block J = [k0, k0+nb):
+//   P = T[0:k0, 0:k0] R[0:k0, J]   (all threads, 4x1 tiles)
+//   T_JJ = R_JJ^{-1}                (wave 0, concurrently)
+//   T[0:k0, J] = -P T_JJ
+template <int NT, typename MT>
+__device__ void trinv_blocked(MT M, int ldm, int l, double* P /* kMaxL x kNB, LDS */) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int k0 = 0; k0 < l; k0 += kNB) {
+    const int nb = (l - k0 < kNB) ? l - k0 : kNB;
+    // P rows i < k0: thread (ty, tx) -> column jj = tx, rows ty + 16a
+    {
+      const int ty = tid / 16, tx = tid % 16;
+      for (int ib = 0; ib < k0; ib += 64) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        const int jcol = k0 + tx;
+        if (tx < nb) {
+          // T upper: row i uses m in [i, k0)
+          const int i_lo = ib + ty;
+          for (int m = i_lo; m < k0; ++m) {
+            const double r = M[m * ldm + jcol];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const int i = i_lo + 16 * a;
+              const double x = M[(i < ldm ? i : ldm - 1) * ldm + m];
+              acc[a] += (i <= m) ? x * r : 0.0;
+            }
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int i = ib + ty + 16 * a;
+          if (i < k0 && tx < nb) P[i * kNB + tx] = acc[a];
+        }
+      }
+    }
+    if (wave == NT / 64 - 1) {
+      // T_JJ = R_JJ^{-1}, column by column, by the last wave
+      for (int j = 0; j < nb; ++j) {
+        const int jj = k0 + j;
+        const double tjj = 1.0 / M[jj * ldm + jj];
+        double acc = 0.0;
+        const int i = lane;  // row within the block
+        if (i < j) {
+#pragma unroll
+          for (int m = 0; m < kNB; ++m) {
+            const double x = M[(k0 + (i < kNB ? i : 0)) * ldm + (k0 + m)] * M[(k0 + m) * ldm + jj];
+            acc += (m >= i && m < j) ? x : 0.0;
+          }
+        }
+        wave_sync();
+        if (i < j) M[(k0 + i) * ldm + jj] = -tjj * acc;
+        if (lane == 0) M[jj * ldm + jj] = tjj;
+        wave_sync();
+      }
+    }
+    __syncthreads();
+    // T[0:k0, J] = -P T_JJ
+    for (int e = tid; e < k0 * kNB; e += NT) {
+      const int i = e / kNB, jj = e % kNB;
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < kNB; ++m) {
+        const double x = P[i * kNB + m] * M[(k0 + m) * ldm + (k0 + jj)];
+        acc += (m <= jj) ? x : 0.0;
+      }
+      if (jj < nb) M[i * ldm + k0 + jj] = -acc;
+    }
+    __syncthreads();
+  }
+}
+
 template <bool IN_LDS>
-__global__ __launch_bounds__(kThreads) void k_orth_factor(const double* __restrict__ W, int l, int l_pad,
-                                                          double* __restrict__ T, double* __restrict__ scratch,
-                                                          DevStatus* st) {
+__global__ __launch_bounds__(kOrthThreads) void k_orth_factor(const double* __restrict__ W, int l, int l_pad,
+                                                              double* __restrict__ T, double* __restrict__ scratch,
+                                                              DevStatus* st, int near_identity) {
+  constexpr int NT = kOrthThreads;
   __shared__ JacobiShared sh;
   __shared__ double Ml[IN_LDS ? kLdsMaxL * kLdsMaxL : 1];
   __shared__ double wdiag[kMaxL];
-  __shared__ double part[kThreads];
-  __shared__ int failed;
+  __shared__ double P[IN_LDS ? kLdsMaxL * kNB : kMaxL * kNB];
+  __shared__ double scale[kMaxL];
+  __shared__ int flag, dropped;
+  using MT = typename std::conditional<IN_LDS, lds_double*, double*>::type;
+  MT M = IN_LDS ? (MT)(void*)Ml : (MT)(void*)scratch;
+  double* V = scratch + (IN_LDS ? 0 : (int64_t)l_pad * l_pad);
   const int tid = threadIdx.x;
   const int ldm = l_pad;
-  double* M = IN_LDS ? Ml : scratch;
-  double* V = scratch + (IN_LDS ? 0 : (int64_t)l_pad * l_pad);
   const int le = l + (l & 1);
 
-  for (int e = tid; e < l_pad * l_pad; e += kThreads) {
-    const int i = e / l_pad, j = e % l_pad;
-    M[e] = (i < l && j < l) ? W[e] : 0.0;
-  }
-  if (tid < l) wdiag[tid] = W[tid * l_pad + tid];
-  if (tid == 0) failed = 0;
+  for (int i = tid / 64; i < l_pad; i += NT / 64)
+    for (int j = tid % 64; j < l_pad; j += 64) M[i * ldm + j] = (i < l && j < l) ? W[i * l_pad + j] : 0.0;
+  for (int i = tid; i < l; i += NT) wdiag[i] = W[i * l_pad + i];
   __syncthreads();
 
-  // Cholesky, upper: W = R^T R, R overwrites the upper triangle of M
-  for (int kk = 0; kk < l; ++kk) {
-    const double piv = M[kk * ldm + kk];
-    if (!(piv > 1e-12 * wdiag[kk]) || !(piv > 0.0)) {
-      if (tid == 0) failed = 1;
-      break;  // uniform: every thread read the same pivot
-    }
-    const double rkk = sqrt(piv);
-    __syncthreads();
-    for (int j = kk + 1 + tid; j < l; j += kThreads) M[kk * ldm + j] /= rkk;
-    if (tid == 0) M[kk * ldm + kk] = rkk;
-    __syncthreads();
-    const int rem = l - kk - 1;
-    for (int e = tid; e < rem * rem; e += kThreads) {
-      const int i = kk + 1 + e / rem, j = kk + 1 + e % rem;
-      if (j >= i) M[i * ldm + j] -= M[kk * ldm + i] * M[kk * ldm + j];
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-
-  if (!failed) {
-    // In-place inverse of the upper triangular R (column by column):
-    // T[j][j] = 1/R[j][j];  T[0:j, j] = -T[j][j] * T[0:j, 0:j] R[0:j, j]
-    constexpr int kSub = 8;  // threads cooperating on one output row
-    constexpr int kRowsPerPass = kThreads / kSub;
-    for (int j = 0; j < l; ++j) {
-      const int sub = tid % kSub;
-      const double tjj = 1.0 / M[j * ldm + j];
-      for (int ib = 0; ib < j; ib += kRowsPerPass) {
-        const int i = ib + tid / kSub;
-        double acc = 0.0;
-        if (i < j) {
-          for (int m = i + sub; m < j; m += kSub) acc += M[i * ldm + m] * M[m * ldm + j];
+  if (near_identity) {
+    // Second CholeskyQR step: W = Q1^T Q1 = I + E.  If max|E| < 1e-9, then
+    // chol(I + E) = I + U + O(|E|^2) with U = triu(E), diag(E)/2 on the
+    // diagonal, and R^{-1} = I - U + O(|E|^2): no factorization needed.
+    double emax = 0.0;
+    for (int i = tid / 64; i < l; i += NT / 64)
+      for (int j = tid % 64; j < l; j += 64) emax = fmax(emax, fabs(M[i * ldm + j] - (i == j ? 1.0 : 0.0)));
+    emax = block_max<NT>(emax, sh.red);
+    if (emax < 1e-9) {
+      for (int i = tid / 64; i < l_pad; i += NT / 64)
+        for (int j = tid % 64; j < l_pad; j += 64) {
+          double t = 0.0;
+          if (i < l && j < l) {
+            const double e = M[i * ldm + j] - (i == j ? 1.0 : 0.0);
+            t = (i == j) ? 1.0 - 0.5 * e : (j > i ? -e : 0.0);
+          }
+          T[i * l_pad + j] = t;
         }
-        for (int off = kSub / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (i < j && sub == 0) part[i] = -tjj * acc;
-      }
-      __syncthreads();
-      if (tid < j) M[tid * ldm + j] = part[tid];
-      if (tid == 0) M[j * ldm + j] = tjj;
-      __syncthreads();
+      if (tid == 0) st->rank_deficient = 0;
+      return;
     }
-    for (int e = tid; e < l_pad * l_pad; e += kThreads) {
-      const int i = e / l_pad, j = e % l_pad;
-      T[e] = (i < l && j < l && j >= i) ? M[i * ldm + j] : 0.0;
-    }
+  }
+
+  if (chol_blocked<NT>(M, ldm, l, wdiag, &flag)) {
+    trinv_blocked<NT>(M, ldm, l, P);
+    for (int i = tid / 64; i < l_pad; i += NT / 64)
+      for (int j = tid % 64; j < l_pad; j += 64)
+        T[i * l_pad + j] = (i < l && j < l && j >= i) ? M[i * ldm + j] : 0.0;
     if (tid == 0) st->rank_deficient = 0;
     return;
   }
 
   // Fallback: T = V diag(s^{-1/2}) over the retained eigen-directions of W.
-  for (int e = tid; e < l_pad * l_pad; e += kThreads) {
-    const int i = e / l_pad, j = e % l_pad;
-    M[e] = (i < l && j < l) ? W[e] : 0.0;
-    V[e] = (i == j) ? 1.0 : 0.0;
-  }
   __syncthreads();
-  jacobi(M, ldm, V, l_pad, le, sh);
+  for (int i = tid / 64; i < l_pad; i += NT / 64)
+    for (int j = tid % 64; j < l_pad; j += 64) {
+      M[i * ldm + j] = (i < l && j < l) ? W[i * l_pad + j] : 0.0;
+      V[i * l_pad + j] = (i == j) ? 1.0 : 0.0;
+    }
+  __syncthreads();
+  int rounds = 0;
+  jacobi<NT>(M, ldm, V, l_pad, (double2*)nullptr, le, sh, &rounds);
   __syncthreads();
   double smax = -1.0;
-  for (int i = tid; i < l; i += kThreads) smax = fmax(smax, M[i * ldm + i]);
-  smax = block_max(smax, sh.red);
-  __shared__ double scale[kMaxL];
-  __shared__ int dropped;
+  for (int i = tid; i < l; i += NT) smax = fmax(smax, M[i * ldm + i]);
+  smax = block_max<NT>(smax, sh.red);
   if (tid == 0) dropped = 0;
   __syncthreads();
-  if (tid < l) {
-    const double sv = M[tid * ldm + tid];
+  for (int i = tid; i < l; i += NT) {
+    const double sv = M[i * ldm + i];
     const bool keep = smax > 0.0 && sv > 1e-13 * smax;
-    scale[tid] = keep ? 1.0 / sqrt(sv) : 0.0;
+    scale[i] = keep ? 1.0 / sqrt(sv) : 0.0;
     if (!keep) atomicAdd(&dropped, 1);
   }
   __syncthreads();
-  for (int e = tid; e < l_pad * l_pad; e += kThreads) {
-    const int i = e / l_pad, j = e % l_pad;
-    T[e] = (i < l && j < l) ? V[i * l_pad + j] * scale[j] : 0.0;
-  }
+  for (int i = tid / 64; i < l_pad; i += NT / 64)
+    for (int j = tid % 64; j < l_pad; j += 64)
+      T[i * l_pad + j] = (i < l && j < l) ? V[i * l_pad + j] * scale[j] : 0.0;
   if (tid == 0) {
     atomicAdd(&st->orth_fallbacks, 1);
     st->rank_deficient = dropped;
@@ -268,79 +491,130 @@ __global__ __launch_bounds__(kThreads) void k_orth_factor(const double* __restri
 }
 
 // ---- Rayleigh-Ritz eigensolve ---------------------------------------------
+// Diagonalises the symmetrised B, sorts, records the rotations; meta[0] =
+// rounds, meta[1..l] = permutation (sorted position -> original index).
 template <bool IN_LDS>
-__global__ __launch_bounds__(kThreads) void k_small_eig(const double* __restrict__ B, int l, int l_pad, int k,
-                                                        double* __restrict__ theta, double* __restrict__ Vout,
-                                                        double* __restrict__ Tc, double* __restrict__ eigvals,
+__global__ __launch_bounds__(kEigThreads) void k_small_eig(const double* __restrict__ B, int l, int l_pad, int k,
+                                                        double* __restrict__ theta, double* __restrict__ eigvals,
+                                                        double2* __restrict__ rot, int* __restrict__ meta,
                                                         double* __restrict__ scratch, DevStatus* st) {
   __shared__ JacobiShared sh;
   __shared__ double Ml[IN_LDS ? kLdsMaxL * kLdsMaxL : 1];
   __shared__ double th[kMaxL];
   __shared__ int perm[kMaxL];
+  using MT = typename std::conditional<IN_LDS, lds_double*, double*>::type;
+  MT M = IN_LDS ? (MT)(void*)Ml : (MT)(void*)scratch;
   const int tid = threadIdx.x;
   const int ldm = l_pad;
-  double* M = IN_LDS ? Ml : scratch;
-  double* V = scratch + (IN_LDS ? 0 : (int64_t)l_pad * l_pad);
   const int le = l + (l & 1);
 
-  for (int e = tid; e < l_pad * l_pad; e += kThreads) {
+  for (int e = tid; e < l_pad * l_pad; e += kEigThreads) {
     const int i = e / l_pad, j = e % l_pad;
     M[e] = (i < l && j < l) ? 0.5 * (B[i * l_pad + j] + B[j * l_pad + i]) : 0.0;
-    V[e] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  const int sweeps = jacobi(M, ldm, V, l_pad, le, sh);
+  int rounds = 0;
+  const int sweeps = jacobi<kEigThreads>(M, ldm, (double*)nullptr, 0, rot, le, sh, &rounds);
   __syncthreads();
-  if (tid < l) {
-    th[tid] = M[tid * ldm + tid];
-    perm[tid] = tid;
-  }
+  for (int i = tid; i < l; i += kEigThreads) th[i] = M[i * ldm + i];
   __syncthreads();
-  if (tid < l) {
-    const double v = th[tid];
+  for (int i = tid; i < l; i += kEigThreads) {
+    const double v = th[i];
     int rank = 0;
     for (int j = 0; j < l; ++j) {
       const double w = th[j];
-      rank += (w > v || (w == v && j < tid)) ? 1 : 0;
+      rank += (w > v || (w == v && j < i)) ? 1 : 0;
     }
-    perm[rank] = tid;
+    perm[rank] = i;  // ranks are a permutation unless theta holds NaN
   }
   __syncthreads();
-  if (tid < l) theta[tid] = th[perm[tid]];
-  if (tid < k) eigvals[tid] = th[perm[tid]];
-  for (int e = tid; e < l * l; e += kThreads) {
-    const int a = e / l, r = e % l;
-    const double v = V[a * l_pad + perm[r]];
-    Vout[a * l_pad + r] = v;
-    if (r < k) Tc[a * k + r] = v * sqrt(fmax(th[perm[r]], 0.0));
+  for (int r = tid; r < l; r += kEigThreads) {
+    const int src = perm[r];
+    theta[r] = th[src];
+    if (r < k) eigvals[r] = th[src];
+    meta[1 + r] = src;
   }
   if (tid == 0) {
-    st->jacobi_sweeps = sweeps;
+    meta[0] = rounds;
+    st->jacobi_sweeps = sweeps < 0 ? -sweeps : sweeps;
     if (sweeps < 0) atomicAdd(&st->jacobi_unconv, 1);
+  }
+}
+
+// Row i of V = e_i^T J_1 J_2 ... J_N from the recorded rotations (one wave
+// per row), then Vout[i][r] = V[i][perm[r]] and Tc[i][r] = Vout[i][r] *
+// sqrt(max(theta_r, 0)) for r < k.
+constexpr int kRotChunk = 16;  // rounds staged in LDS at a time
+
+__global__ __launch_bounds__(64) void k_rot_apply(const double2* __restrict__ rot, const int* __restrict__ meta,
+                                                  const double* __restrict__ theta, int l, int l_pad, int k,
+                                                  double* __restrict__ Vout, double* __restrict__ Tc) {
+  __shared__ double v[kMaxL];
+  __shared__ double2 cs[kRotChunk * kMaxPairs];
+  const int i = blockIdx.x;  // row of V
+  const int tid = threadIdx.x;
+  const int le = l + (l & 1);
+  const int np = le / 2;
+  for (int j = tid; j < le; j += 64) v[j] = (j == i) ? 1.0 : 0.0;
+  const int rounds = meta[0];
+  for (int r0 = 0; r0 < rounds; r0 += kRotChunk) {
+    const int nrc = (rounds - r0 < kRotChunk) ? rounds - r0 : kRotChunk;
+    __syncthreads();
+    for (int e = tid; e < nrc * np; e += 64) cs[e] = rot[(int64_t)r0 * np + e];
+    __syncthreads();
+    for (int rr = 0; rr < nrc; ++rr) {
+      const int r = (r0 + rr) % (le - 1);
+      for (int t = tid; t < np; t += 64) {
+        const double2 c = cs[rr * np + t];
+        if (c.y != 0.0) {
+          int p, q;
+          round_robin_pair(le, r, t, p, q);
+          const double vp = v[p], vq = v[q];
+          v[p] = c.x * vp - c.y * vq;
+          v[q] = c.y * vp + c.x * vq;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int r = tid; r < l; r += 64) {
+    const double x = v[meta[1 + r]];
+    Vout[i * l_pad + r] = x;
+    if (r < k) Tc[i * k + r] = x * sqrt(fmax(theta[r], 0.0));
   }
 }
 
 }  // namespace
 
+size_t small_eig_rot_bytes(int l) {
+  const int le = l + (l & 1);
+  return (size_t)kMaxSweeps * (le - 1) * (le / 2) * sizeof(double2);
+}
+
 hipError_t launch_orth_factor(const double* W, int l, int l_pad, double* T, double* scratch, DevStatus* st,
-                              hipStream_t s) {
+                              int near_identity, hipStream_t s) {
   if (l > kMaxL || l_pad > kMaxL || l < 1) return hipErrorInvalidValue;
   if (l_pad <= kLdsMaxL)
-    hipLaunchKernelGGL(k_orth_factor<true>, dim3(1), dim3(kThreads), 0, s, W, l, l_pad, T, scratch, st);
+    hipLaunchKernelGGL(k_orth_factor<true>, dim3(1), dim3(kOrthThreads), 0, s, W, l, l_pad, T, scratch, st,
+                       near_identity);
   else
-    hipLaunchKernelGGL(k_orth_factor<false>, dim3(1), dim3(kThreads), 0, s, W, l, l_pad, T, scratch, st);
+    hipLaunchKernelGGL(k_orth_factor<false>, dim3(1), dim3(kOrthThreads), 0, s, W, l, l_pad, T, scratch, st,
+                       near_identity);
   return hipGetLastError();
 }
 
 hipError_t launch_small_eig(const double* B, int l, int l_pad, int k, double* theta, double* V, double* Tc,
-                            double* eigvals_out, double* scratch, DevStatus* st, hipStream_t s) {
+                            double* eigvals_out, double* scratch, void* rot, int* meta, DevStatus* st,
+                            hipStream_t s) {
   if (l > kMaxL || l_pad > kMaxL || k < 1 || k > l) return hipErrorInvalidValue;
   if (l_pad <= kLdsMaxL)
-    hipLaunchKernelGGL(k_small_eig<true>, dim3(1), dim3(kThreads), 0, s, B, l, l_pad, k, theta, V, Tc,
-                       eigvals_out, scratch, st);
+    hipLaunchKernelGGL(k_small_eig<true>, dim3(1), dim3(kEigThreads), 0, s, B, l, l_pad, k, theta, eigvals_out,
+                       (double2*)rot, meta, scratch, st);
   else
-    hipLaunchKernelGGL(k_small_eig<false>, dim3(1), dim3(kThreads), 0, s, B, l, l_pad, k, theta, V, Tc,
-                       eigvals_out, scratch, st);
+    hipLaunchKernelGGL(k_small_eig<false>, dim3(1), dim3(kEigThreads), 0, s, B, l, l_pad, k, theta, eigvals_out,
+                       (double2*)rot, meta, scratch, st);
+  hipLaunchKernelGGL(k_rot_apply, dim3((unsigned)l), dim3(64), 0, s, (const double2*)rot, meta, theta, l, l_pad, k,
+                     V, Tc);
   return hipGetLastError();
 }
 

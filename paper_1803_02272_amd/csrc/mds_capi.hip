@@ -59,8 +59,8 @@ struct mds_plan_s {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   bool ws_owned = false;
-  Region G, Gref, rowpart, colpart, r, c, rsum, mean, fpart, X, Ypart, Y, Q1, Q, Wpart, W, T, B, V, theta, Tc,
-      small, sval, sidx, status;
+  Region G, rowpart, colpart, p4part, r, c, hc, rsum, mean, X, Ypart, Y, Q1, Q, Wpart, W, T, B, V, theta, Tc,
+      small, rot, meta, sval, sidx, status;
   size_t total = 0;
   int last_stage = 0;
   // event timing
@@ -86,8 +86,9 @@ void layout(mds_plan_s* P) {
   const int64_t n = P->n, n_pad = P->n_pad, ldg = P->ldg, lp = P->l_pad;
   const size_t e = (size_t)gk_size(P->gk);
   P->total = 0;
-  add(P, P->G, (size_t)n_pad * ldg * e);
-  add(P, P->Gref, P->form == MDS_FORM_BF16 ? (size_t)n_pad * ldg * 4 : 0);
+  // G is stored only in the bf16 form (range passes stream 2-byte G); the
+  // fp32/fp64 passes and the bf16 form's projection recentre D on the fly.
+  add(P, P->G, P->form == MDS_FORM_BF16 ? (size_t)n_pad * ldg * e : 0);
   const int64_t ncb = (n + kStatsCols - 1) / kStatsCols, nrb = (n + kStatsRows - 1) / kStatsRows;
   add(P, P->rowpart, (size_t)ncb * n * 8);
   add(P, P->colpart, (size_t)nrb * n * 8);
@@ -95,7 +96,8 @@ void layout(mds_plan_s* P) {
   add(P, P->c, (size_t)n * 8);
   add(P, P->rsum, (size_t)n * 8);
   add(P, P->mean, 8);
-  add(P, P->fpart, (size_t)center_write_blocks(n_pad, ldg) * 2 * 8);
+  add(P, P->p4part, (size_t)stats_tiles(n) * 8);
+  add(P, P->hc, (size_t)ldg * 4);
   const size_t xe = (size_t)(gk_size(P->gk) > gk_size(P->ref_gk) ? gk_size(P->gk) : gk_size(P->ref_gk));
   add(P, P->X, (size_t)lp * ldg * xe);
   const size_t acc_main = P->gk == GK_F64 ? 8 : 4, acc_ref = P->ref_gk == GK_F64 ? 8 : 4;
@@ -113,9 +115,11 @@ void layout(mds_plan_s* P) {
   add(P, P->theta, (size_t)lp * 8);
   add(P, P->Tc, (size_t)lp * P->k * 8);
   add(P, P->small, (size_t)2 * lp * lp * 8);
-  const int64_t nblk = (n + 255) / 256;
-  add(P, P->sval, (size_t)(nblk * P->k + P->k) * 8);
-  add(P, P->sidx, (size_t)nblk * P->k * 8);
+  add(P, P->rot, small_eig_rot_bytes(P->l));
+  add(P, P->meta, (size_t)(P->l + 1) * sizeof(int));
+  const int64_t nch = coords_anchor_chunks(n);
+  add(P, P->sval, (size_t)(nch * P->k + P->k) * 8);
+  add(P, P->sidx, (size_t)nch * P->k * 8);
   add(P, P->status, sizeof(DevStatus));
 }
 
@@ -196,21 +200,35 @@ mds_status orthonormalize(mds_plan_s* P, hipStream_t s, int xk) {
   DevStatus* st = P->at<DevStatus>(P->status);
   PhaseTimer tm(P, s, MDS_PH_ORTH);
   MDS_TRY(launch_gram(Y, Y, P->l_pad, P->ldg, Wp, W, s), "gram(Y)");
-  MDS_TRY(launch_orth_factor(W, P->l, P->l_pad, T, sm, st, s), "orth_factor 1");
+  MDS_TRY(launch_orth_factor(W, P->l, P->l_pad, T, sm, st, 0, s), "orth_factor 1");
   MDS_TRY(launch_apply(Y, P->l, P->ldg, T, P->l_pad, P->l, P->l_pad, Q1, -1, nullptr, s), "apply 1");
   MDS_TRY(launch_gram(Q1, Q1, P->l_pad, P->ldg, Wp, W, s), "gram(Q1)");
-  MDS_TRY(launch_orth_factor(W, P->l, P->l_pad, T, sm, st, s), "orth_factor 2");
+  MDS_TRY(launch_orth_factor(W, P->l, P->l_pad, T, sm, st, 1, s), "orth_factor 2");
   MDS_TRY(launch_apply(Q1, P->l, P->ldg, T, P->l_pad, P->l, P->l_pad, Q, xk, P->at<void>(P->X), s), "apply 2");
   return MDS_OK;
 }
 
-mds_status gpass(mds_plan_s* P, hipStream_t s, bool ref) {
+// One G-pass Y = G X.  The bf16 form's range passes read the stored bf16 G;
+// every other pass recentres D on the fly.
+mds_status gpass(mds_plan_s* P, hipStream_t s, bool ref, const void* D) {
   const int gk = ref ? P->ref_gk : P->gk;
   const GPassCfg& cfg = ref ? P->ref_cfg : P->cfg;
-  const void* G = (ref && P->form == MDS_FORM_BF16) ? P->at<void>(P->Gref) : P->at<void>(P->G);
+  const bool from_d = ref || P->form != MDS_FORM_BF16;
+  GPassDSrc src;
+  if (from_d) {
+    src.D = D;
+    src.n = P->n;
+    src.r = P->at<double>(P->r);
+    src.c = P->at<double>(P->c);
+    src.m = P->at<double>(P->mean);
+    src.hc = P->at<float>(P->hc);
+    src.vec = ((uintptr_t)D % 16) == 0;
+    src.d_is_f64 = P->d_dtype == MDS_DTYPE_F64;
+  }
   {
     PhaseTimer tm(P, s, ref ? MDS_PH_GPASS_REF : MDS_PH_GPASS);
-    MDS_TRY(launch_gpass(gk, G, P->ldg, P->n_pad, P->at<void>(P->X), P->l_pad, cfg, P->at<void>(P->Ypart), s),
+    MDS_TRY(launch_gpass(gk, from_d ? nullptr : P->at<void>(P->G), P->ldg, P->n_pad, P->at<void>(P->X), P->l_pad,
+                         cfg, P->at<void>(P->Ypart), src, s),
             "gpass");
   }
   PhaseTimer tm(P, s, MDS_PH_REDUCE);
@@ -233,18 +251,17 @@ mds_status run_impl(mds_plan_s* P, const void* D, double* coords, double* eigval
 
   {
   PhaseTimer tm(P, s, MDS_PH_STATS);
-  MDS_TRY(launch_center_stats(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->at<double>(P->rowpart),
-                              P->at<double>(P->colpart), P->at<double>(P->r), P->at<double>(P->c),
-                              P->at<double>(P->rsum), P->at<double>(P->mean), st, s),
+  MDS_TRY(launch_center_stats(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->ldg, P->at<double>(P->rowpart),
+                              P->at<double>(P->colpart), P->at<double>(P->p4part), P->at<double>(P->r),
+                              P->at<double>(P->c), P->at<double>(P->rsum), P->at<float>(P->hc),
+                              P->at<double>(P->mean), st, s),
           "centring stats");
   }
-  {
-  PhaseTimer tm(P, s, MDS_PH_WRITE);
-  MDS_TRY(launch_center_write(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->n_pad, P->ldg, P->at<double>(P->r),
-                              P->at<double>(P->c), P->at<double>(P->mean), P->gk, P->at<void>(P->G),
-                              P->form == MDS_FORM_BF16 ? P->at<float>(P->Gref) : nullptr,
-                              P->at<double>(P->fpart), st, s),
-          "centring write");
+  if (P->form == MDS_FORM_BF16) {
+    PhaseTimer tm(P, s, MDS_PH_WRITE);
+    MDS_TRY(launch_center_write(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->n_pad, P->ldg, P->at<double>(P->r),
+                                P->at<double>(P->c), P->at<double>(P->mean), P->gk, P->at<void>(P->G), nullptr, s),
+            "centring write");
   }
   P->last_stage = MDS_STAGE_CENTER;
   if (stop_after == MDS_STAGE_CENTER) return MDS_OK;
@@ -259,7 +276,7 @@ mds_status run_impl(mds_plan_s* P, const void* D, double* coords, double* eigval
   const int total_range = 2 * P->q + 1;
   const int passes = stop_after == MDS_STAGE_RANGE ? range_passes : total_range;
   for (int it = 0; it < passes; ++it) {
-    mds_status e = gpass(P, s, false);
+    mds_status e = gpass(P, s, false, D);
     if (e != MDS_OK) return e;
     const int next_xk = (it == total_range - 1) ? P->ref_gk : P->gk;
     e = orthonormalize(P, s, next_xk);
@@ -269,7 +286,7 @@ mds_status run_impl(mds_plan_s* P, const void* D, double* coords, double* eigval
   if (stop_after == MDS_STAGE_RANGE) return MDS_OK;
 
   // projection: Y = G_ref Q, B = Q^T Y
-  mds_status e = gpass(P, s, true);
+  mds_status e = gpass(P, s, true, D);
   if (e != MDS_OK) return e;
   {
     PhaseTimer tm(P, s, MDS_PH_SMALL);
@@ -277,11 +294,13 @@ mds_status run_impl(mds_plan_s* P, const void* D, double* coords, double* eigval
                         P->at<double>(P->B), s),
             "gram(Q, GQ)");
     MDS_TRY(launch_small_eig(P->at<double>(P->B), P->l, P->l_pad, P->k, P->at<double>(P->theta),
-                             P->at<double>(P->V), P->at<double>(P->Tc), eigvals, P->at<double>(P->small), st, s),
+                             P->at<double>(P->V), P->at<double>(P->Tc), eigvals, P->at<double>(P->small),
+                             P->at<void>(P->rot), P->at<int>(P->meta), st, s),
             "small_eig");
   }
   PhaseTimer tm(P, s, MDS_PH_COORDS);
-  MDS_TRY(launch_coords(P->at<double>(P->Q), P->l, P->n, P->ldg, P->at<double>(P->Tc), P->k, coords,
+  MDS_TRY(launch_coords(P->at<double>(P->Q), P->l, P->n, P->ldg, P->at<double>(P->Tc), P->k,
+                        P->at<double>(P->Q1), coords,
                         P->at<double>(P->sval), P->at<int64_t>(P->sidx), s),
           "coords");
   P->last_stage = MDS_STAGE_ALL;
@@ -347,8 +366,8 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
   P->d_dtype = o.d_dtype;
   P->gk = o.form == MDS_FORM_FP64 ? GK_F64 : (o.form == MDS_FORM_FP32 ? GK_F32 : GK_BF16);
   P->ref_gk = o.form == MDS_FORM_BF16 ? GK_F32 : P->gk;
-  P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split);
-  P->ref_cfg = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split);
+  P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, P->form != MDS_FORM_BF16);
+  P->ref_cfg = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, true);
   layout(P);
   *out = P;
   return MDS_OK;
@@ -402,11 +421,11 @@ mds_status mds_get_buffer(mds_plan_t plan, int32_t which, mds_buffer* out) {
   const int64_t lp = plan->l_pad;
   const int xdt = plan->gk == GK_F64 ? 0 : (plan->gk == GK_F32 ? 1 : 2);
   switch (which) {
-    case MDS_BUF_G: b = {plan->at<void>(plan->G), xdt, 0, plan->n_pad, plan->ldg, plan->ldg}; break;
-    case MDS_BUF_GREF:
-      if (plan->form != MDS_FORM_BF16) return fail(MDS_ERR_INVALID_ARG, "no fp32 copy of G in this form");
-      b = {plan->at<void>(plan->Gref), 1, 0, plan->n_pad, plan->ldg, plan->ldg};
+    case MDS_BUF_G:
+      if (plan->form != MDS_FORM_BF16) return fail(MDS_ERR_STATE, "G is not stored in this form");
+      b = {plan->at<void>(plan->G), xdt, 0, plan->n_pad, plan->ldg, plan->ldg};
       break;
+    case MDS_BUF_GREF: return fail(MDS_ERR_STATE, "no fp32 copy of G is stored");
     case MDS_BUF_ROWMEAN: b = {plan->at<void>(plan->r), 0, 0, plan->n, 1, 1}; break;
     case MDS_BUF_COLMEAN: b = {plan->at<void>(plan->c), 0, 0, plan->n, 1, 1}; break;
     case MDS_BUF_MEAN: b = {plan->at<void>(plan->mean), 0, 0, 1, 1, 1}; break;

@@ -45,15 +45,17 @@ struct DevStatus {
 // ---- centring (Sec. 6.2, step 1) ------------------------------------------
 constexpr int kStatsCols = 1024;  // columns per stats tile
 constexpr int kStatsRows = 1024;  // rows per stats tile
-hipError_t launch_center_stats(const void* D, int d_is_f64, int64_t n, double* rowpart, double* colpart,
-                               double* r, double* c, double* rsum, double* mean_all, DevStatus* st,
-                               hipStream_t s);
-// Writes G (kind gk, ld = ldg, n_pad rows) and, if gref != nullptr, an fp32
-// copy used by the refinement pass.  frob/trace partials go to fpart.
+// r, c, m (fp64), hc = fl32(c/2) (ldg floats, zero beyond n), and
+// ||G||_F^2, tr(G) in the status words.  p4part: stats_tiles(n) doubles.
+int64_t stats_tiles(int64_t n);
+hipError_t launch_center_stats(const void* D, int d_is_f64, int64_t n, int64_t ldg, double* rowpart,
+                               double* colpart, double* p4part, double* r, double* c, double* rsum, float* hc,
+                               double* mean_all, DevStatus* st, hipStream_t s);
+// Writes G (kind gk, ld = ldg, n_pad rows) and, if gref != nullptr, an fp32 copy.
 int64_t center_write_blocks(int64_t n_pad, int64_t ldg);
 hipError_t launch_center_write(const void* D, int d_is_f64, int64_t n, int64_t n_pad, int64_t ldg,
                                const double* r, const double* c, const double* mean_all, int gk, void* G,
-                               float* gref, double* fpart, DevStatus* st, hipStream_t s);
+                               float* gref, hipStream_t s);
 
 // ---- Gaussian test matrix ---------------------------------------------------
 hipError_t launch_omega(uint64_t seed, int64_t n, int l, int l_pad, int64_t ldg, int xk, void* Xt,
@@ -66,9 +68,26 @@ struct GPassCfg {
   int split;   // K splits
   int64_t steps_total, steps_per_split;
 };
-GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint);
+GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d);
+// With D != nullptr the A operand is recentred on the fly from D (ld = n)
+// and G is unused.  fp64 passes: gamma_ij = -1/2 (((d_ij^2 - c_j) - r_i) + m)
+// in fp64 (the stored-G value).  fp32 passes: gamma_ij =
+// fma(-1/2, fl32(d_ij^2), hc_j + hr_i) in fp32 with hc_j = fl32(c_j / 2) and
+// hr_i = fl32((r_i - m) / 2), a few fp32 ulps of the terms from the rounded
+// exact value.
+struct GPassDSrc {
+  const void* D = nullptr;
+  int64_t n = 0;
+  const double* r = nullptr;
+  const double* c = nullptr;
+  const float* hc = nullptr;
+  const double* m = nullptr;
+  int vec = 0;
+  int d_is_f64 = 0;
+};
+int64_t gpass_blocks(const GPassCfg& cfg, int64_t n_pad);
 hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const void* Xt, int l_pad,
-                        const GPassCfg& cfg, void* Ypart, hipStream_t s);
+                        const GPassCfg& cfg, void* Ypart, const GPassDSrc& src, hipStream_t s);
 // Y (fp64, l_pad x ldg) = sum_s Ypart[s] in split order.
 hipError_t launch_splitk_reduce(int gk, const void* Ypart, int split, int64_t elems, double* Y,
                                 hipStream_t s);
@@ -82,19 +101,23 @@ hipError_t launch_gram(const double* A, const double* B, int l_pad, int64_t ldg,
 // Out rows >= lt are zeroed.  Optional cast copy of Out into Xc (kind xk).
 hipError_t launch_apply(const double* In, int l, int64_t ldg, const double* T, int ldt, int lt,
                         int l_pad, double* Out, int xk, void* Xc, hipStream_t s);
-// coords (n x k row-major) = Q^T-layout times Tc (l x k)
+int64_t coords_anchor_chunks(int64_t n);
+// coords (n x k row-major) = Q Tc (Tc: l x k), columns sign-normalised.
+// Ct is a transposed scratch of k_pad16 x ldg doubles.
 hipError_t launch_coords(const double* Qt, int l, int64_t n, int64_t ldg, const double* Tc, int k,
-                         double* coords, double* sign_part, int64_t* idx_part, hipStream_t s);
+                         double* Ct, double* coords, double* sign_part, int64_t* idx_part, hipStream_t s);
 
 // ---- small dense kernels (one workgroup) ------------------------------------
 // T such that Y T has orthonormal columns, from W = Y^T Y (Cholesky, or an
 // eigen-based inverse square root when Cholesky breaks down).
+// near_identity: W is the Gram matrix of an almost orthonormal basis (second
+// CholeskyQR step); a first-order factor is used when W is within 1e-9 of I.
 hipError_t launch_orth_factor(const double* W, int l, int l_pad, double* T, double* scratch,
-                              DevStatus* st, hipStream_t s);
+                              DevStatus* st, int near_identity, hipStream_t s);
 // Eigenpairs of the symmetrised B (algebraic descending); Tc = V_k diag(sqrt(max(theta,0))).
+size_t small_eig_rot_bytes(int l);
 hipError_t launch_small_eig(const double* B, int l, int l_pad, int k, double* theta, double* V,
-                            double* Tc, double* eigvals_out, double* scratch, DevStatus* st,
-                            hipStream_t s);
-hipError_t launch_finalize_stats(const double* fpart, int64_t nparts, DevStatus* st, hipStream_t s);
+                            double* Tc, double* eigvals_out, double* scratch, void* rot, int* meta,
+                            DevStatus* st, hipStream_t s);
 
 }  // namespace mds

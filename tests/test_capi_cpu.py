@@ -65,9 +65,9 @@ def test_workspace_size_scales_with_form():
         sizes[form] = b.value
         L.mds_destroy(h)
     npad = 20224
-    assert sizes[0] >= npad * npad * 8
-    assert npad * npad * 4 <= sizes[1] < npad * npad * 8
-    assert sizes[2] >= npad * npad * (2 + 4)  # bf16 G + fp32 refinement copy
+    # only the bf16 form stores G (2 bytes per entry); the others recentre D on the fly
+    assert sizes[0] < npad * npad and sizes[1] < npad * npad
+    assert npad * npad * 2 <= sizes[2] < npad * npad * 3
 
 
 def test_run_without_device_reports_no_device():
