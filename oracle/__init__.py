@@ -7,3 +7,4 @@ function computes and which passage of the paper it follows.
 """
 from .mds_oracle import *  # noqa: F401,F403
 from .mds_oracle import __all__  # noqa: F401
+from . import mds_oracle_large  # noqa: F401  (row-blocked variant for large n)
