@@ -86,6 +86,25 @@ def time_form(mds, torch, D, n, k, p, q, form, steps, warmup):
     return out
 
 
+def copy_probe(torch, mib, reps):
+    """Plain copy of a known size: reads and writes mib MiB per launch."""
+    nb = mib << 20
+    src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    print(json.dumps({"copy_probe_bytes_read": nb, "copy_probe_bytes_written": nb, "launches": reps + 1,
+                      "ms": ms, "gbs_read_plus_write": 2 * nb / (ms * 1e-3) / 1e9}), flush=True)
+
+
 def cpu_baseline(n_full, k, p, q, n_sample, refs):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload;
     time scaled by (n_full / n_sample)^2 (every pass is O(n^2 l))."""
@@ -131,6 +150,9 @@ def main():
     ap.add_argument("--forms", default="bf16,fp32,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20000)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only time a plain device-to-device copy of MIB MiB (stream bandwidth, and the "
+                         "known-size reference for the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -140,6 +162,10 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_probe:
+        copy_probe(torch, args.copy_probe, max(args.steps, 1))
+        return
 
     import paper_1803_02272_amd as mds
     from workloads import gpu as wgpu

@@ -68,11 +68,21 @@ typedef enum mds_form { MDS_FORM_FP64 = 0, MDS_FORM_FP32 = 1, MDS_FORM_BF16 = 2 
 /* Element type of the caller's distance matrix D. */
 typedef enum mds_dtype { MDS_DTYPE_F32 = 0, MDS_DTYPE_F64 = 1 } mds_dtype;
 
+/* Option flags.
+ *   MDS_FLAG_FULL_PROJECTION: stream all of G in the projection pass.  By
+ *   default the projection uses the symmetry of G (D symmetric is the
+ *   contract): B = Q^T G Q is assembled as S + S^T from the upper triangle
+ *   of G only, S = Q^T (W o G) Q with W = 1 above, 1/2 on and 0 below the
+ *   diagonal, which halves that pass's reads and MFMA work.  Both give the
+ *   same B up to rounding for a symmetric D; for a D that breaks the
+ *   contract, the default reads only its upper triangle (j >= i) there. */
+#define MDS_FLAG_FULL_PROJECTION 1
+
 typedef struct mds_opts {
   int32_t form;        /* mds_form (default MDS_FORM_FP32) */
   int32_t d_dtype;     /* mds_dtype (default MDS_DTYPE_F32) */
   int32_t gpass_split; /* K-splits of the G-pass, 0 = automatic */
-  int32_t reserved;    /* must be 0 */
+  int32_t flags;       /* MDS_FLAG_* bits, 0 = defaults; other bits are rejected */
 } mds_opts;
 
 typedef struct mds_plan_s* mds_plan_t;
@@ -133,7 +143,8 @@ typedef enum mds_buffer_id {
   MDS_BUF_MEAN = 4,    /* m, 1 fp64 */
   MDS_BUF_X = 5,       /* current G-pass operand, transposed l_pad x ldg */
   MDS_BUF_Q = 6,       /* orthonormal basis, transposed l_pad x ldg fp64 */
-  MDS_BUF_Y = 7,       /* last G-pass product, transposed l_pad x ldg fp64 */
+  MDS_BUF_Y = 7,       /* last G-pass product, transposed l_pad x ldg fp64 (after the
+                          symmetric projection: 2 (W o G) Q, see MDS_FLAG_FULL_PROJECTION) */
   MDS_BUF_B = 8,       /* projected matrix Q^T G Q, l_pad x l_pad fp64 */
   MDS_BUF_THETA = 9,   /* all l Ritz values, descending, fp64 */
   MDS_BUF_V = 10,      /* Ritz vectors in the Q basis, l x l (ld l_pad) fp64 */

@@ -34,17 +34,18 @@ def _stream_handle(stream):
 class Plan:
     """A plan for one problem shape: n points, k axes, oversample p, q power
     iterations, test-matrix seed, G-pass form ("fp64" | "fp32" | "bf16") and
-    the dtype of D ("f32" | "f64")."""
+    the dtype of D ("f32" | "f64").  full_projection=True streams all of G in
+    the projection pass instead of its upper triangle (MDS_FLAG_FULL_PROJECTION)."""
 
     def __init__(self, n, k, oversample=10, q=2, seed=0, form="fp32", d_dtype="f32", gpass_split=0,
-                 workspace="torch"):
+                 workspace="torch", full_projection=False):
         L = _capi.lib()
         self.n, self.k, self.oversample, self.q, self.seed = int(n), int(k), int(oversample), int(q), int(seed)
         self.form = form
         self.d_dtype = d_dtype
         opts = _capi.MdsOpts(FORMS[form] if isinstance(form, str) else int(form),
                              _capi.DTYPE_F64 if d_dtype in ("f64", "float64") else _capi.DTYPE_F32,
-                             int(gpass_split), 0)
+                             int(gpass_split), _capi.FLAG_FULL_PROJECTION if full_projection else 0)
         h = ctypes.c_void_p()
         check(L.mds_plan_ex(ctypes.byref(h), self.n, self.k, self.oversample, self.q, self.seed,
                             ctypes.byref(opts)), "mds_plan_ex")

@@ -38,10 +38,13 @@ STAGE_CENTER, STAGE_OMEGA, STAGE_RANGE, STAGE_ALL = 1, 2, 3, 100
 
 MAX_L = 256
 
+# option flags (mds_opts.flags)
+FLAG_FULL_PROJECTION = 1
+
 
 class MdsOpts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("d_dtype", ctypes.c_int32),
-                ("gpass_split", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("gpass_split", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class MdsBuffer(ctypes.Structure):

@@ -19,6 +19,18 @@
 //     split index is blockIdx % split: with split a multiple of 8, every
 //     workgroup on an XCD works on the same K range, so that XCD's slice of X
 //     stays in its own L2 while G streams past.
+//   * Symmetric mode (projection pass only, B = Q^T G Q): G is symmetric, so
+//     B = S + S^T with S = Q^T Z and Z = W o G Q, where W weights the strict
+//     upper triangle by 1, the diagonal by 1/2 and the lower triangle by 0.
+//     Only the upper triangle of G is streamed: half the bytes and half the
+//     MFMA work of a full pass.  The kernel writes 2Z (weights 2 / 1 / 0,
+//     exact power-of-two scaling), so that the usual symmetrisation
+//     1/2 (B + B^T) of B = Q^T (2Z) gives S + S^T.  Work item (row block,
+//     K split) covers the split's K range clipped to the columns at or right
+//     of the block's first row; row blocks are dealt to XCDs round-robin
+//     (block mb on XCD mb % 8), which spreads the triangle evenly over the
+//     XCDs, and inside an XCD the split index varies slowest so that
+//     concurrently running workgroups share their slice of X in L2.
 #include <type_traits>
 
 #include "mds_internal.h"
@@ -136,10 +148,11 @@ __device__ __forceinline__ void load_d(const DT* __restrict__ D, int64_t n, int6
   }
 }
 
-template <int GK, int RG, int CG, typename DT>
+template <int GK, int RG, int CG, typename DT, bool SYM>
 __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
     const typename Tr<GK>::T* __restrict__ G, int64_t ldg, const typename Tr<GK>::T* __restrict__ Xt, int split,
-    int64_t steps_total, int64_t steps_per_split, typename Tr<GK>::AccS* __restrict__ Ypart, GPassDSrc src) {
+    int64_t steps_total, int64_t steps_per_split, typename Tr<GK>::AccS* __restrict__ Ypart, GPassDSrc src,
+    int64_t sym_nbx) {
   using TT = Tr<GK>;
   using T = typename TT::T;
   using Acc = typename TT::Acc;
@@ -153,15 +166,31 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
   constexpr int BK = 128 / sizeof(T);  // K elements per step
   __shared__ __attribute__((aligned(16))) unsigned char xs[2][LPAD * kRowB];
 
+  static_assert(!SYM || DLoad<DT>::kFromD, "symmetric mode recentres D on the fly");
+  constexpr int64_t kStepsPerBlock = (64 * RG) / BK;  // K steps spanned by one row block
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int64_t bid = blockIdx.x;
-  const int s = (int)(bid % split);
-  const int64_t mb = bid / split;
+  int s;
+  int64_t mb, st0, st1;
+  if constexpr (SYM) {
+    const int64_t loc = bid >> 3;
+    s = (int)(loc / sym_nbx);
+    mb = (loc % sym_nbx) * 8 + (bid & 7);
+    const int64_t diag0 = mb * kStepsPerBlock;  // first step at or right of the diagonal
+    st0 = (int64_t)s * steps_per_split;
+    st1 = (st0 + steps_per_split < steps_total) ? st0 + steps_per_split : steps_total;
+    if (diag0 > st0) st0 = diag0;
+    if (diag0 >= steps_total || st0 >= st1) return;  // empty item: no partial written (the reduce skips it)
+  } else {
+    s = (int)(bid % split);
+    mb = bid / split;
+    st0 = (int64_t)s * steps_per_split;
+    st1 = (st0 + steps_per_split < steps_total) ? st0 + steps_per_split : steps_total;
+  }
+  const int64_t diag_end = (mb + 1) * kStepsPerBlock;  // steps below this cross the diagonal (SYM)
   const int64_t row0 = mb * (64 * RG) + (int64_t)wave * (RG * 16);
-  const int64_t st0 = (int64_t)s * steps_per_split;
-  const int64_t st1 = (st0 + steps_per_split < steps_total) ? st0 + steps_per_split : steps_total;
 
   Acc acc[RG][CG];
 #pragma unroll
@@ -249,15 +278,19 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
     // A operand of one chunk in MFMA register form.  Recentring mode, fp64:
     // gamma = -1/2 (((d^2 - c_k) - r_i) + m); fp32: gamma = fma(-1/2,
     // fl32(d^2), hc_k + hr_i) (one fma per entry instead of fp64 arithmetic).
+    // Symmetric mode: 2 gamma (the same roundings scaled by 2, exactly),
+    // times 1, 1/2, 0 right of, on and left of the diagonal.
     auto a_operand = [&](int rg, int c, int64_t st) -> u32x4 {
       if constexpr (FD) {
 #pragma clang fp contract(off)
         const int64_t k0 = st * BK + c * (BK / 2) + (lane >> 4) * E;
         const int64_t i = row0 + rg * 16 + (lane & 15);
+        const bool band = SYM && st < diag_end;
         T g[E];
 #pragma unroll
         for (int t = 0; t < E; ++t) {
           const bool valid = (i < n) && (k0 + t < n);
+          T v;
           if constexpr (sizeof(T) == 4) {
             float d2;
             if constexpr (sizeof(DT) == 4) {
@@ -267,11 +300,18 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
               const double d = a[rg][c][t];
               d2 = (float)(d * d);
             }
-            g[t] = valid ? __builtin_fmaf(-0.5f, d2, cv[c][t] + ri[rg]) : 0.0f;
+            const float h = cv[c][t] + ri[rg];
+            v = SYM ? __builtin_fmaf(-1.0f, d2, h + h) : __builtin_fmaf(-0.5f, d2, h);
           } else {
             const double d = (double)a[rg][c][t];
-            g[t] = valid ? -0.5 * (((d * d - cv[c][t]) - ri[rg]) + mval) : 0.0;
+            const double e = ((d * d - cv[c][t]) - ri[rg]) + mval;
+            v = SYM ? -e : -0.5 * e;
           }
+          if (band) {
+            const int64_t j = k0 + t;
+            v = j > i ? v : (j == i ? (T)0.5 * v : (T)0);
+          }
+          g[t] = valid ? v : (T)0;
         }
         u32x4 w;
         __builtin_memcpy(&w, &g, 16);
@@ -350,14 +390,22 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
   }
 }
 
+// Symmetric mode: row block mb has partials only in the splits whose K
+// range reaches its diagonal, k >= first_split(row) = (mb * bm) / cols_per_split.
 template <typename AccS>
 __global__ __launch_bounds__(256) void k_splitk_reduce(const AccS* __restrict__ Yp, int split, int64_t elems,
-                                                       double* __restrict__ Y) {
+                                                       double* __restrict__ Y, int64_t ldg, int64_t sym_bm,
+                                                       int64_t sym_cols_per_split) {
 #pragma clang fp contract(off)
   const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
   if (e >= elems) return;  // elems is a multiple of 4
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  for (int k = 0; k < split; ++k) {
+  int k0 = 0;
+  if (sym_cols_per_split > 0) {
+    const int64_t row = e % ldg;  // e..e+3 share the row block (ldg and bm are multiples of 4)
+    k0 = (int)(((row / sym_bm) * sym_bm) / sym_cols_per_split);
+  }
+  for (int k = k0; k < split; ++k) {
     const AccS* p = Yp + (int64_t)k * elems + e;
     s0 += (double)p[0];
     s1 += (double)p[1];
@@ -368,14 +416,23 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const AccS* __restrict__ 
   reinterpret_cast<double2*>(Y + e)[1] = make_double2(s2, s3);
 }
 
-template <int GK, int RG, int CG, typename DT>
+template <int GK, int RG, int CG, typename DT, bool SYM>
 void launch_one(const void* G, int64_t ldg, const void* Xt, const GPassCfg& cfg, int64_t n_pad, void* Yp,
                 const GPassDSrc& src, hipStream_t s) {
   using T = typename Tr<GK>::T;
   using AccS = typename Tr<GK>::AccS;
-  const int64_t blocks = (n_pad / (64 * RG)) * cfg.split;
-  hipLaunchKernelGGL((k_gpass<GK, RG, CG, DT>), dim3((unsigned)blocks), dim3(256), 0, s, (const T*)G, ldg,
-                     (const T*)Xt, cfg.split, cfg.steps_total, cfg.steps_per_split, (AccS*)Yp, src);
+  const int64_t blocks = gpass_blocks(cfg, n_pad);
+  hipLaunchKernelGGL((k_gpass<GK, RG, CG, DT, SYM>), dim3((unsigned)blocks), dim3(256), 0, s, (const T*)G, ldg,
+                     (const T*)Xt, cfg.split, cfg.steps_total, cfg.steps_per_split, (AccS*)Yp, src, cfg.sym_nbx);
+}
+
+template <int GK, int RG, int CG, typename DT>
+void launch_fd(const void* G, int64_t ldg, const void* Xt, const GPassCfg& cfg, int64_t n_pad, void* Yp,
+               const GPassDSrc& src, hipStream_t s) {
+  if (cfg.sym)
+    launch_one<GK, RG, CG, DT, true>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
+  else
+    launch_one<GK, RG, CG, DT, false>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
 }
 
 template <int GK, int CG>
@@ -383,17 +440,17 @@ hipError_t launch_cg(const void* G, int64_t ldg, const void* Xt, const GPassCfg&
                      const GPassDSrc& src, hipStream_t s) {
   if (!src.D) {
     constexpr int RG = rg_for(GK, CG);
-    if (cfg.rg != RG) return hipErrorInvalidValue;
-    launch_one<GK, RG, CG, void>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
+    if (cfg.rg != RG || cfg.sym) return hipErrorInvalidValue;
+    launch_one<GK, RG, CG, void, false>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
   } else if constexpr (GK == GK_BF16) {
     return hipErrorInvalidValue;  // bf16 passes read the stored bf16 G
   } else {
     constexpr int RG = rg_fd(GK, CG);
     if (cfg.rg != RG) return hipErrorInvalidValue;
     if (src.d_is_f64)
-      launch_one<GK, RG, CG, double>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
+      launch_fd<GK, RG, CG, double>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
     else
-      launch_one<GK, RG, CG, float>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
+      launch_fd<GK, RG, CG, float>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
   }
   return hipGetLastError();
 }
@@ -413,13 +470,25 @@ hipError_t launch_gk(const void* G, int64_t ldg, const void* Xt, int l_pad, cons
 
 }  // namespace
 
-GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d) {
+GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d, bool sym) {
   GPassCfg c{};
   c.rg = from_d ? rg_fd(gk, l_pad / 16) : rg_for(gk, l_pad / 16);
   c.bm = 64 * c.rg;
   const int64_t esize = gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : 2);
   c.steps_total = ldg * esize / 128;
   const int64_t row_blocks = n_pad / c.bm;
+  if (sym && from_d) {
+    // 8 K splits (one slice of X per XCD-resident wave of workgroups); every
+    // split index below `split` holds at least one step
+    int64_t split = split_hint > 0 ? split_hint : 8;
+    if (split > c.steps_total) split = c.steps_total;
+    c.steps_per_split = (c.steps_total + split - 1) / split;
+    c.split = (int)((c.steps_total + c.steps_per_split - 1) / c.steps_per_split);
+    c.sym = 1;
+    c.sym_nbx = (row_blocks + 7) / 8;
+    c.sym_cols_per_split = c.steps_per_split * (128 / esize);
+    return c;
+  }
   int64_t split = split_hint > 0 ? split_hint : (2048 + row_blocks - 1) / row_blocks;
   int64_t max_split = c.steps_total / 16;
   if (max_split < 1) max_split = 1;
@@ -442,16 +511,20 @@ hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const
   }
 }
 
-int64_t gpass_blocks(const GPassCfg& cfg, int64_t n_pad) { return (n_pad / cfg.bm) * cfg.split; }
+int64_t gpass_blocks(const GPassCfg& cfg, int64_t n_pad) {
+  return cfg.sym ? 8 * cfg.sym_nbx * cfg.split : (n_pad / cfg.bm) * cfg.split;
+}
 
-hipError_t launch_splitk_reduce(int gk, const void* Ypart, int split, int64_t elems, double* Y, hipStream_t s) {
+hipError_t launch_splitk_reduce(int gk, const GPassCfg& cfg, const void* Ypart, int64_t ldg, int64_t elems,
+                                double* Y, hipStream_t s) {
   const unsigned blocks = (unsigned)((elems / 4 + 255) / 256);
+  const int64_t cps = cfg.sym ? cfg.sym_cols_per_split : 0;
   if (gk == GK_F64)
-    hipLaunchKernelGGL(k_splitk_reduce<double>, dim3(blocks), dim3(256), 0, s, (const double*)Ypart, split,
-                       elems, Y);
+    hipLaunchKernelGGL(k_splitk_reduce<double>, dim3(blocks), dim3(256), 0, s, (const double*)Ypart, cfg.split,
+                       elems, Y, ldg, (int64_t)cfg.bm, cps);
   else
-    hipLaunchKernelGGL(k_splitk_reduce<float>, dim3(blocks), dim3(256), 0, s, (const float*)Ypart, split,
-                       elems, Y);
+    hipLaunchKernelGGL(k_splitk_reduce<float>, dim3(blocks), dim3(256), 0, s, (const float*)Ypart, cfg.split,
+                       elems, Y, ldg, (int64_t)cfg.bm, cps);
   return hipGetLastError();
 }
 

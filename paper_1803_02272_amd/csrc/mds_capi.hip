@@ -54,6 +54,7 @@ struct mds_plan_s {
   int d_dtype = MDS_DTYPE_F32;
   int gk = GK_F32;      // dtype of G and of the range passes
   int ref_gk = GK_F32;  // dtype of the projection pass
+  int flags = 0;
   GPassCfg cfg{}, ref_cfg{};
   // workspace
   void* ws = nullptr;
@@ -232,7 +233,7 @@ mds_status gpass(mds_plan_s* P, hipStream_t s, bool ref, const void* D) {
             "gpass");
   }
   PhaseTimer tm(P, s, MDS_PH_REDUCE);
-  MDS_TRY(launch_splitk_reduce(gk, P->at<void>(P->Ypart), cfg.split, (int64_t)P->l_pad * P->ldg,
+  MDS_TRY(launch_splitk_reduce(gk, cfg, P->at<void>(P->Ypart), P->ldg, (int64_t)P->l_pad * P->ldg,
                                P->at<double>(P->Y), s),
           "splitk_reduce");
   return MDS_OK;
@@ -285,7 +286,8 @@ mds_status run_impl(mds_plan_s* P, const void* D, double* coords, double* eigval
   P->last_stage = MDS_STAGE_RANGE;
   if (stop_after == MDS_STAGE_RANGE) return MDS_OK;
 
-  // projection: Y = G_ref Q, B = Q^T Y
+  // projection: Y = G_ref Q, B = Q^T Y (symmetric mode: Y = 2 (W o G_ref) Q,
+  // whose symmetrised B is the same Q^T G_ref Q, see k_gpass)
   mds_status e = gpass(P, s, true, D);
   if (e != MDS_OK) return e;
   {
@@ -350,7 +352,8 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
     return fail(MDS_ERR_INVALID_ARG, "unknown form %d", o.form);
   if (o.d_dtype != MDS_DTYPE_F32 && o.d_dtype != MDS_DTYPE_F64)
     return fail(MDS_ERR_INVALID_ARG, "unknown D dtype %d", o.d_dtype);
-  if (o.gpass_split < 0 || o.reserved != 0) return fail(MDS_ERR_INVALID_ARG, "bad options");
+  if (o.gpass_split < 0) return fail(MDS_ERR_INVALID_ARG, "gpass_split = %d < 0", o.gpass_split);
+  if (o.flags & ~MDS_FLAG_FULL_PROJECTION) return fail(MDS_ERR_INVALID_ARG, "unknown flags 0x%x", o.flags);
   mds_plan_s* P = new (std::nothrow) mds_plan_s();
   if (!P) return fail(MDS_ERR_OOM, "host allocation failed");
   P->n = n;
@@ -366,8 +369,10 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
   P->d_dtype = o.d_dtype;
   P->gk = o.form == MDS_FORM_FP64 ? GK_F64 : (o.form == MDS_FORM_FP32 ? GK_F32 : GK_BF16);
   P->ref_gk = o.form == MDS_FORM_BF16 ? GK_F32 : P->gk;
-  P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, P->form != MDS_FORM_BF16);
-  P->ref_cfg = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, true);
+  P->flags = o.flags;
+  P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, P->form != MDS_FORM_BF16, false);
+  P->ref_cfg = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, true,
+                            (o.flags & MDS_FLAG_FULL_PROJECTION) == 0);
   layout(P);
   *out = P;
   return MDS_OK;
@@ -437,7 +442,7 @@ mds_status mds_get_buffer(mds_plan_t plan, int32_t which, mds_buffer* out) {
       break;
     }
     case MDS_BUF_Q: b = {plan->at<void>(plan->Q), 0, 0, lp, plan->ldg, plan->ldg}; break;
-    case MDS_BUF_Y: b = {plan->at<void>(plan->Y), 0, 0, lp, plan->ldg, plan->ldg}; break;
+    case MDS_BUF_Y: b = {plan->at<void>(plan->Y), 0, 0, lp, plan->ldg, plan->ldg}; break;  // see mds.h
     case MDS_BUF_B: b = {plan->at<void>(plan->B), 0, 0, lp, lp, lp}; break;
     case MDS_BUF_THETA: b = {plan->at<void>(plan->theta), 0, 0, plan->l, 1, 1}; break;
     case MDS_BUF_V: b = {plan->at<void>(plan->V), 0, 0, plan->l, plan->l, lp}; break;

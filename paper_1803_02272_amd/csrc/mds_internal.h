@@ -66,9 +66,13 @@ struct GPassCfg {
   int rg;      // 16-row groups per wave
   int bm;      // rows per workgroup
   int split;   // K splits
+  int sym;     // symmetric mode: upper triangle only, Ypart holds 2 (W o G) X
   int64_t steps_total, steps_per_split;
+  int64_t sym_nbx;             // row blocks per XCD (symmetric mode)
+  int64_t sym_cols_per_split;  // K columns per split (symmetric mode)
 };
-GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d);
+// sym (recentring passes only): the projection's symmetric mode, see k_gpass.
+GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d, bool sym);
 // With D != nullptr the A operand is recentred on the fly from D (ld = n)
 // and G is unused.  fp64 passes: gamma_ij = -1/2 (((d_ij^2 - c_j) - r_i) + m)
 // in fp64 (the stored-G value).  fp32 passes: gamma_ij =
@@ -88,9 +92,10 @@ struct GPassDSrc {
 int64_t gpass_blocks(const GPassCfg& cfg, int64_t n_pad);
 hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const void* Xt, int l_pad,
                         const GPassCfg& cfg, void* Ypart, const GPassDSrc& src, hipStream_t s);
-// Y (fp64, l_pad x ldg) = sum_s Ypart[s] in split order.
-hipError_t launch_splitk_reduce(int gk, const void* Ypart, int split, int64_t elems, double* Y,
-                                hipStream_t s);
+// Y (fp64, l_pad x ldg) = sum_s Ypart[s] in split order (symmetric mode:
+// over the splits that hold a partial for the row).
+hipError_t launch_splitk_reduce(int gk, const GPassCfg& cfg, const void* Ypart, int64_t ldg, int64_t elems,
+                                double* Y, hipStream_t s);
 
 // ---- skinny fp64 kernels ----------------------------------------------------
 int64_t gram_chunks(int64_t ldg);

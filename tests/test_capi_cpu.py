@@ -31,10 +31,10 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= set(_capi.SIGNATURES), set(names) - set(_capi.SIGNATURES)
 
 
-def _plan(n, k, p, q, form=1, dt=0, split=0, reserved=0):
+def _plan(n, k, p, q, form=1, dt=0, split=0, flags=0):
     L = _capi.lib()
     h = ctypes.c_void_p()
-    opts = _capi.MdsOpts(form, dt, split, reserved)
+    opts = _capi.MdsOpts(form, dt, split, flags)
     st = L.mds_plan_ex(ctypes.byref(h), n, k, p, q, 0, ctypes.byref(opts))
     return st, h
 
@@ -51,7 +51,11 @@ def test_invalid_arguments_rejected(n, k, p, q):
 def test_invalid_options_rejected():
     assert _plan(100, 4, 4, 1, form=7)[0] == _capi.ERR_INVALID_ARG
     assert _plan(100, 4, 4, 1, dt=5)[0] == _capi.ERR_INVALID_ARG
-    assert _plan(100, 4, 4, 1, reserved=1)[0] == _capi.ERR_INVALID_ARG
+    assert _plan(100, 4, 4, 1, flags=2)[0] == _capi.ERR_INVALID_ARG
+    assert _plan(100, 4, 4, 1, split=-1)[0] == _capi.ERR_INVALID_ARG
+    st, h = _plan(100, 4, 4, 1, flags=_capi.FLAG_FULL_PROJECTION)
+    assert st == _capi.OK
+    _capi.lib().mds_destroy(h)
 
 
 def test_workspace_size_scales_with_form():

@@ -317,3 +317,45 @@ def test_d_f64_with_bf16_form():
     _, X, eig, info = gpu_run(D, k, p, q, 0, "bf16")
     assert info["status"] == 0
     assert rel_eig_err(eig, ref["eigvals"]) < MATCHED_EIG_BAR["bf16"]
+
+
+# ---------------------------------------------------------------------------
+# symmetric projection (default) against the full projection pass
+@pytest.mark.parametrize("name", ["gm2000_f64", "amp3001_f32", "amp5000_r200"])
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("split", [0, 3, 13])
+def test_symmetric_projection_matches_full(name, form, split):
+    """B assembled from the upper triangle of G equals Q^T G Q from the whole
+    of G up to accumulation rounding: same Q (identical range passes), so the
+    symmetrised B, the Ritz values and the coordinates must agree closely."""
+    D, k, p, q = case(name)
+    n = D.shape[0]
+    say(f"[sym] case={name} form={form} split={split}")
+    Dg = torch.from_numpy(np.ascontiguousarray(D)).cuda()
+    out = {}
+    for full in (False, True):
+        plan = mds.Plan(n, k, p, q, 0, form=form, d_dtype=dtype_of(D), gpass_split=split, full_projection=full)
+        coords, eig = plan.run(Dg)
+        info = plan.info()
+        assert info["status"] == 0, info
+        B = plan.buffer(_capi.BUF_B).cpu().numpy()
+        Q = plan.buffer(_capi.BUF_Q).cpu().numpy()
+        out[full] = (coords.cpu().numpy(), eig.cpu().numpy(), 0.5 * (B + B.T), Q)
+        plan.close()
+    (Xs, es, Bs, Qs), (Xf, ef, Bf, Qf) = out[False], out[True]
+    assert np.array_equal(Qs, Qf)  # the range passes do not depend on the projection mode
+    l = k + p
+    Qn = Qs[:l, :n].T
+    G = O.gram_matrix(D)
+    u = 2.0 ** -53 if form == "fp64" else 2.0 ** -24
+    mag = np.abs(Qn).T @ (np.abs(G) @ np.abs(Qn))
+    if form != "fp64":  # recentring terms of the fp32 passes (see the G-pass unit test)
+        r, c, m = O.centring_stats(D)
+        H = 0.5 * (D.astype(np.float64) ** 2 + c[None, :] + np.abs(r - m)[:, None])
+        mag = mag + np.abs(Qn).T @ (H @ np.abs(Qn))
+    diff = np.abs(Bs[:l, :l] - Bf[:l, :l])
+    say(f"    max |B_sym - B_full| / bound {np.max(diff / (4 * n * u * mag)):.3e}")
+    assert np.all(diff <= 4 * n * u * mag)
+    tol = 1e-12 if form == "fp64" else 1e-6
+    assert rel_eig_err(es, ef) < tol
+    assert procrustes_err(Xs, Xf) < (1e-9 if form == "fp64" else 1e-3)
