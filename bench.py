@@ -105,6 +105,71 @@ def copy_probe(torch, mib, reps):
                       "ms": ms, "gbs_read_plus_write": 2 * nb / (ms * 1e-3) / 1e9}), flush=True)
 
 
+def serving_bench(mds, torch, wgpu, seconds, warmup_s, rate, pool_size, budget_gb, slots, seed=0):
+    """Serving mix: Poisson arrivals of MDS jobs with n log-uniform in
+    [500, 30000], half Gaussian-mixture (50 dims, 10 components, means
+    N(0, 25 I)) and half amplicon-Hamming (50 references) distance matrices
+    drawn from a device-resident pool, k=20, oversample 10, q=2, BF16 form,
+    admitted by the server under an HBM budget.  Latency is submit ->
+    completion as observed by the server; requests submitted during the
+    warm-up are excluded."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    ns = np.rint(np.exp(rng.uniform(np.log(500), np.log(30000), pool_size))).astype(int)
+    pool = []
+    t0 = time.perf_counter()
+    for i, n in enumerate(ns):
+        if i % 2 == 0:
+            D = wgpu.mixture_distances(int(n), 50, 10, 25.0, seed=1000 + i)
+        else:
+            D = wgpu.amplicon_distances(int(n), 50, seed=1000 + i)
+        pool.append((mds.Plan(int(n), 20, 10, 2, seed=i, form="bf16"), D))
+    torch.cuda.synchronize()
+    pool_gb = sum(D.numel() * 4 for _, D in pool) / 1e9
+    log(f"[serve] pool of {pool_size} D ({pool_gb:.1f} GB) ready in {time.perf_counter() - t0:.1f} s")
+    budget = int(budget_gb * (1 << 30))
+    out = {"pool": pool_size, "pool_gb": pool_gb, "budget_gib": budget_gb, "slots": slots, "rate_per_s": rate,
+           "seconds": seconds, "warmup_s": warmup_s}
+    with mds.Server(budget, slots=slots) as srv:
+        # saturation: the whole pool submitted at once
+        t0 = time.perf_counter()
+        tickets = [srv.submit(pl, D)[0] for pl, D in pool]
+        for t in tickets:
+            assert srv.wait(t)[0] == 0
+        burst_s = time.perf_counter() - t0
+        out["burst_solves_per_s"] = pool_size / burst_s
+        # open loop: Poisson arrivals
+        gaps = rng.exponential(1.0 / rate, int(rate * (seconds + warmup_s) * 2) + 16)
+        arrivals = np.cumsum(gaps)
+        arrivals = arrivals[arrivals < seconds + warmup_s]
+        picks = rng.integers(0, pool_size, len(arrivals))
+        sub = []
+        start = time.perf_counter()
+        for a, j in zip(arrivals, picks):
+            now = time.perf_counter() - start
+            if a > now:
+                time.sleep(a - now)
+            pl, D = pool[j]
+            sub.append((a, j, srv.submit(pl, D)[0]))
+        lat, done_at = [], []
+        for a, j, t in sub:
+            st, tm = srv.wait(t)
+            assert st == 0, st
+            if a >= warmup_s:
+                lat.append(tm["latency_ms"])
+                done_at.append(a + tm["latency_ms"] * 1e-3)
+        info = srv.stats()
+    n_req = len(lat)
+    window = max(done_at) - warmup_s if done_at else float("nan")
+    out.update({"requests": n_req, "solves_per_s": n_req / window if n_req else None,
+                "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "max_ms": max(lat) if lat else None,
+                "peak_arena_gib": info["peak_bytes"] / (1 << 30)})
+    del pool
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(n_full, k, p, q, n_sample, refs):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload;
     time scaled by (n_full / n_sample)^2 (every pass is O(n^2 l))."""
@@ -150,6 +215,13 @@ def main():
     ap.add_argument("--forms", default="bf16,fp32,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20000)
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="open-loop duration of the serving mix after its warm-up (0 = skip serving)")
+    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-pool", type=int, default=64)
+    ap.add_argument("--serve-budget-gib", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only time a plain device-to-device copy of MIB MiB (stream bandwidth, and the "
                          "known-size reference for the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -288,6 +360,12 @@ def main():
         else None,
         "roofline": roof,
     }
+    if args.serve_seconds > 0:
+        log(f"[bench] serving mix: {args.serve_rate}/s for {args.serve_seconds} s")
+        line["serving"] = serving_bench(mds, torch, wgpu, args.serve_seconds, args.serve_warmup, args.serve_rate,
+                                        args.serve_pool, args.serve_budget_gib, args.serve_slots)
+        log(f"[bench] serving: {line['serving']}")
+        line["p99_ms_serving"] = line["serving"]["p99_ms"]
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle at n={args.cpu_sample}")
         line["cpu_baseline"] = cpu_baseline(n, k, p, q, args.cpu_sample, args.refs)

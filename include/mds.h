@@ -205,6 +205,57 @@ mds_status mds_set_timing(mds_plan_t plan, int32_t enable);
 mds_status mds_get_timings(mds_plan_t plan, mds_phase_time* out, void* stream);
 
 void mds_destroy(mds_plan_t plan);
+
+/* ---- Serving: continuous batching of MDS jobs (spec serving loop) ----
+ * A server owns a device arena of hbm_budget_bytes, allocated once by
+ * mds_server_create (nothing is allocated on the device while serving), and
+ * max_slots HIP streams.  Submitted jobs wait in a FIFO queue; a worker thread
+ * inside the server admits the queue head as soon as a slot is free and the
+ * arena has room for the job's workspace, enqueues the whole run on that
+ * slot's stream, and retires finished jobs, whose slot and memory then admit
+ * the next ones.  Admitted jobs run concurrently on the device.  Each job runs
+ * on the server's own copy of the plan, so its result is bit-identical to
+ * mds_run of the same plan alone, and the caller may reuse or destroy `plan`
+ * right after mds_submit.  Server calls are thread-safe; no call may be in
+ * flight on a server that is being destroyed. */
+typedef struct mds_server_s* mds_server_t;
+typedef uint64_t mds_ticket;
+
+typedef struct mds_job_times {
+  double queue_ms;   /* submit -> admitted (host clock) */
+  double run_ms;     /* admitted -> completion observed by the server */
+  double latency_ms; /* submit -> completion observed */
+} mds_job_times;
+
+typedef struct mds_server_info {
+  int32_t queued, running, slots, pad_;
+  uint64_t completed;
+  size_t budget_bytes, used_bytes, peak_bytes; /* arena size, bytes held by admitted jobs, peak */
+} mds_server_info;
+
+/* Create a server on the current HIP device.  1 <= max_slots <= 256.
+ * Errors: MDS_ERR_INVALID_ARG, MDS_ERR_NO_DEVICE, MDS_ERR_OOM (arena), MDS_ERR_HIP. */
+mds_status mds_server_create(mds_server_t* out, size_t hbm_budget_bytes, int32_t max_slots);
+/* Queue one job.  D, coords, eigvals as for mds_run (device memory of the
+ * server's device); they must stay valid until the job is terminal.
+ * MDS_ERR_BUDGET if the plan's workspace can never fit the arena. */
+mds_status mds_submit(mds_server_t server, mds_plan_t plan, const void* D, double* coords, double* eigvals,
+                      mds_ticket* out);
+/* Non-blocking.  *job_status = MDS_PENDING while queued or running, else the
+ * terminal status: MDS_OK, MDS_ERR_NONFINITE, MDS_ERR_NUMERICAL, MDS_ERR_HIP
+ * or MDS_ERR_CANCELLED.  Returning a terminal status releases the ticket (a
+ * later call reports MDS_ERR_INVALID_ARG).  times may be NULL. */
+mds_status mds_poll(mds_server_t server, mds_ticket ticket, mds_status* job_status, mds_job_times* times);
+/* Like mds_poll, but blocks until the job is terminal. */
+mds_status mds_wait(mds_server_t server, mds_ticket ticket, mds_status* job_status, mds_job_times* times);
+/* Cancel a job that has not been admitted yet (its status becomes
+ * MDS_ERR_CANCELLED); MDS_ERR_STATE once it has started: a running job
+ * completes. */
+mds_status mds_cancel(mds_server_t server, mds_ticket ticket);
+mds_status mds_server_stats(mds_server_t server, mds_server_info* out);
+/* Cancel queued jobs, wait for admitted ones, free the arena and streams. */
+void mds_server_destroy(mds_server_t server);
+
 const char* mds_status_string(mds_status s);
 const char* mds_last_error(void);
 /* Library version as "major.minor.patch". */

@@ -161,3 +161,77 @@ class Plan:
         inf = _capi.MdsInfo()
         check(_capi.lib().mds_get_info(self._h, ctypes.byref(inf), _stream_handle(stream)), "mds_get_info")
         return inf.as_dict()
+
+
+class Server:
+    """Continuous-batching server (mds_server_*): a device arena of
+    ``budget_bytes`` and ``slots`` concurrent streams.  ``submit`` queues a job
+    of a Plan on a device D and returns a ticket; ``poll`` never blocks and
+    returns None while the job is pending, else (status, times)."""
+
+    def __init__(self, budget_bytes, slots=8):
+        h = ctypes.c_void_p()
+        check(_capi.lib().mds_server_create(ctypes.byref(h), int(budget_bytes), int(slots)), "mds_server_create")
+        self._h = h
+        self._keep = {}  # ticket -> tensors that must outlive the job
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _capi.lib().mds_server_destroy(self._h)
+            self._h = None
+        self._keep = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def submit(self, plan, D, coords=None, eigvals=None):
+        """Queue plan on D; returns (ticket, coords, eigvals) with the outputs
+        filled in once the job completes."""
+        import torch
+
+        plan._check_D(D)
+        if coords is None:
+            coords = torch.empty((plan.n, plan.k), dtype=torch.float64, device=D.device)
+        if eigvals is None:
+            eigvals = torch.empty((plan.k,), dtype=torch.float64, device=D.device)
+        t = ctypes.c_uint64()
+        check(_capi.lib().mds_submit(self._h, plan.handle, ctypes.c_void_p(D.data_ptr()),
+                                     ctypes.c_void_p(coords.data_ptr()), ctypes.c_void_p(eigvals.data_ptr()),
+                                     ctypes.byref(t)), "mds_submit")
+        self._keep[t.value] = (D, coords, eigvals)
+        return t.value, coords, eigvals
+
+    def _done(self, ticket, st, tm):
+        self._keep.pop(ticket, None)
+        return st.value, {"queue_ms": tm.queue_ms, "run_ms": tm.run_ms, "latency_ms": tm.latency_ms}
+
+    def poll(self, ticket):
+        st = ctypes.c_int()
+        tm = _capi.MdsJobTimes()
+        check(_capi.lib().mds_poll(self._h, int(ticket), ctypes.byref(st), ctypes.byref(tm)), "mds_poll")
+        if st.value == _capi.PENDING:
+            return None
+        return self._done(ticket, st, tm)
+
+    def wait(self, ticket):
+        st = ctypes.c_int()
+        tm = _capi.MdsJobTimes()
+        check(_capi.lib().mds_wait(self._h, int(ticket), ctypes.byref(st), ctypes.byref(tm)), "mds_wait")
+        return self._done(ticket, st, tm)
+
+    def cancel(self, ticket):
+        check(_capi.lib().mds_cancel(self._h, int(ticket)), "mds_cancel")
+
+    def stats(self):
+        inf = _capi.MdsServerInfo()
+        check(_capi.lib().mds_server_stats(self._h, ctypes.byref(inf)), "mds_server_stats")
+        return inf.as_dict()

@@ -73,6 +73,19 @@ class MdsPhaseTime(ctypes.Structure):
                 ("max_ms", ctypes.c_float)]
 
 
+class MdsJobTimes(ctypes.Structure):
+    _fields_ = [("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
+class MdsServerInfo(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int32), ("running", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("completed", ctypes.c_uint64), ("budget_bytes", ctypes.c_size_t),
+                ("used_bytes", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad_"}
+
+
 # exported symbol -> (restype, argtypes)
 SIGNATURES = {
     "mds_plan": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64, ctypes.c_int32,
@@ -90,6 +103,16 @@ SIGNATURES = {
     "mds_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mds_get_timings": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MdsPhaseTime), ctypes.c_void_p]),
     "mds_destroy": (None, [ctypes.c_void_p]),
+    "mds_server_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, ctypes.c_int32]),
+    "mds_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "mds_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(MdsJobTimes)]),
+    "mds_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(MdsJobTimes)]),
+    "mds_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "mds_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MdsServerInfo)]),
+    "mds_server_destroy": (None, [ctypes.c_void_p]),
     "mds_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mds_last_error": (ctypes.c_char_p, []),
     "mds_version": (ctypes.c_char_p, []),

@@ -18,14 +18,18 @@
 
 #include "../../include/mds.h"
 #include "mds_internal.h"
+#include "plan.h"
 
 using namespace mds;
 
 namespace {
-
 thread_local std::string g_last_error;
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+int gk_size(int gk) { return gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : 2); }
+}  // namespace
 
-mds_status fail(mds_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+namespace mds {
+
 mds_status fail(mds_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -36,44 +40,7 @@ mds_status fail(mds_status s, const char* fmt, ...) {
   return s;
 }
 
-inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
-
-int gk_size(int gk) { return gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : 2); }
-
-struct Region {
-  size_t off = 0, bytes = 0;
-};
-
-}  // namespace
-
-struct mds_plan_s {
-  int64_t n = 0, n_pad = 0, ldg = 0;
-  int k = 0, p = 0, q = 0, l = 0, l_pad = 0;
-  uint64_t seed = 0;
-  int form = MDS_FORM_FP32;
-  int d_dtype = MDS_DTYPE_F32;
-  int gk = GK_F32;      // dtype of G and of the range passes
-  int ref_gk = GK_F32;  // dtype of the projection pass
-  int flags = 0;
-  GPassCfg cfg{}, ref_cfg{};
-  // workspace
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-  bool ws_owned = false;
-  Region G, rowpart, colpart, p4part, r, c, hc, rsum, mean, X, Ypart, Y, Q1, Q, Wpart, W, T, B, V, theta, Tc,
-      small, rot, meta, sval, sidx, status;
-  size_t total = 0;
-  int last_stage = 0;
-  // event timing
-  bool timing = false;
-  std::vector<hipEvent_t> events;  // pool
-  std::vector<int> rec_phase;      // phase of recorded pair i (events 2i, 2i+1)
-
-  template <typename T>
-  T* at(const Region& reg) const {
-    return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + reg.off);
-  }
-};
+}  // namespace mds
 
 namespace {
 
@@ -155,10 +122,14 @@ __global__ void k_status_init(DevStatus* st) {
   *st = z;
 }
 
-mds_status hip_check(hipError_t e, const char* what) {
+}  // namespace
+
+mds_status mds::hip_check(hipError_t e, const char* what) {
   if (e == hipSuccess) return MDS_OK;
   return fail(MDS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+namespace {
 
 #define MDS_TRY(expr, what)                          \
   do {                                               \
@@ -239,8 +210,10 @@ mds_status gpass(mds_plan_s* P, hipStream_t s, bool ref, const void* D) {
   return MDS_OK;
 }
 
-mds_status run_impl(mds_plan_s* P, const void* D, double* coords, double* eigvals, hipStream_t s, int stop_after,
-                    int range_passes) {
+}  // namespace
+
+mds_status mds::run_plan(mds_plan_s* P, const void* D, double* coords, double* eigvals, hipStream_t s,
+                         int stop_after, int range_passes) {
   mds_status st0 = device_present();
   if (st0 != MDS_OK) return st0;
   st0 = ensure_workspace(P);
@@ -309,8 +282,6 @@ mds_status run_impl(mds_plan_s* P, const void* D, double* coords, double* eigval
   return MDS_OK;
 }
 
-}  // namespace
-
 extern "C" {
 
 const char* mds_version(void) { return "0.1.0"; }
@@ -356,6 +327,7 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
   if (o.flags & ~MDS_FLAG_FULL_PROJECTION) return fail(MDS_ERR_INVALID_ARG, "unknown flags 0x%x", o.flags);
   mds_plan_s* P = new (std::nothrow) mds_plan_s();
   if (!P) return fail(MDS_ERR_OOM, "host allocation failed");
+  P->opts = o;
   P->n = n;
   P->n_pad = round_up(n, kPadN);
   P->ldg = P->n_pad;
@@ -412,7 +384,7 @@ mds_status mds_run_stages(mds_plan_t plan, const void* D, double* coords, double
     return fail(MDS_ERR_INVALID_ARG, "range_passes %d outside [1, %d]", range_passes, 2 * plan->q + 1);
   if (stop_after == MDS_STAGE_ALL && (!coords || !eigvals))
     return fail(MDS_ERR_INVALID_ARG, "NULL coords or eigvals");
-  return run_impl(plan, D, coords, eigvals, (hipStream_t)stream, stop_after, range_passes);
+  return run_plan(plan, D, coords, eigvals, (hipStream_t)stream, stop_after, range_passes);
 }
 
 mds_status mds_run(mds_plan_t plan, const void* D, double* coords, double* eigvals, void* stream) {

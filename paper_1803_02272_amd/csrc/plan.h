@@ -1,0 +1,60 @@
+// Host-side plan object shared by the C ABI (mds_capi.hip) and the serving
+// runtime (mds_server.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/mds.h"
+#include "mds_internal.h"
+
+namespace mds {
+
+struct Region {
+  size_t off = 0, bytes = 0;
+};
+
+}  // namespace mds
+
+struct mds_plan_s {
+  int64_t n = 0, n_pad = 0, ldg = 0;
+  int k = 0, p = 0, q = 0, l = 0, l_pad = 0;
+  uint64_t seed = 0;
+  mds_opts opts{};      // options the plan was created with
+  int form = MDS_FORM_FP32;
+  int d_dtype = MDS_DTYPE_F32;
+  int gk = mds::GK_F32;      // dtype of G and of the range passes
+  int ref_gk = mds::GK_F32;  // dtype of the projection pass
+  int flags = 0;
+  mds::GPassCfg cfg{}, ref_cfg{};
+  // workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  mds::Region G, rowpart, colpart, p4part, r, c, hc, rsum, mean, X, Ypart, Y, Q1, Q, Wpart, W, T, B, V, theta, Tc,
+      small, rot, meta, sval, sidx, status;
+  size_t total = 0;
+  int last_stage = 0;
+  // event timing
+  bool timing = false;
+  std::vector<hipEvent_t> events;  // pool
+  std::vector<int> rec_phase;      // phase of recorded pair i (events 2i, 2i+1)
+
+  template <typename T>
+  T* at(const mds::Region& reg) const {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + reg.off);
+  }
+};
+
+namespace mds {
+
+// Record a thread-local error text (mds_last_error) and return s.
+mds_status fail(mds_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+mds_status hip_check(hipError_t e, const char* what);
+// Enqueue one (partial) run of the plan on stream s; the plan's workspace
+// is allocated on first use if none was set.
+mds_status run_plan(mds_plan_s* P, const void* D, double* coords, double* eigvals, hipStream_t s, int stop_after,
+                    int range_passes);
+
+}  // namespace mds

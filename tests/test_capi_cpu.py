@@ -98,3 +98,20 @@ def test_status_strings():
     for code in range(-9, 2):
         assert L.mds_status_string(code).decode()
     assert L.mds_version().decode().count(".") == 2
+
+
+def test_server_without_device_and_bad_arguments():
+    L = _capi.lib()
+    h = ctypes.c_void_p()
+    assert L.mds_server_create(ctypes.byref(h), 1 << 20, 0) == _capi.ERR_INVALID_ARG
+    assert L.mds_server_create(ctypes.byref(h), 1 << 20, 1000) == _capi.ERR_INVALID_ARG
+    assert L.mds_server_create(ctypes.byref(h), 16, 2) == _capi.ERR_INVALID_ARG
+    assert L.mds_server_create(None, 1 << 20, 2) == _capi.ERR_INVALID_ARG
+    st = ctypes.c_int()
+    assert L.mds_poll(None, 1, ctypes.byref(st), None) == _capi.ERR_INVALID_ARG
+    assert L.mds_cancel(None, 1) == _capi.ERR_INVALID_ARG
+    t = ctypes.c_uint64()
+    assert L.mds_submit(None, None, None, None, None, ctypes.byref(t)) == _capi.ERR_INVALID_ARG
+    if not torch.cuda.is_available():
+        assert L.mds_server_create(ctypes.byref(h), 1 << 20, 2) == _capi.ERR_NO_DEVICE
+        assert h.value is None
