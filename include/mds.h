@@ -206,6 +206,34 @@ mds_status mds_get_timings(mds_plan_t plan, mds_phase_time* out, void* stream);
 
 void mds_destroy(mds_plan_t plan);
 
+/* ---- Batched small instances ------------------------------------------------
+ * Many independent MDS instances of uneven n in one persistent launch: one
+ * workgroup runs a whole instance (centring, Omega, range passes with
+ * CholeskyQR2, projection, eigensolve, coordinates), so a launch fills the
+ * GPU with instances rather than with tiles of one instance.  Limits per
+ * instance: 2 <= n <= 16384 and k + oversample rounded up to 16 <= 64.  All
+ * instances of a call share one form.  The values of every dtype follow
+ * mds_run (same G entries, same Omega, same sign convention); sums run in
+ * another order, so results agree with mds_run to rounding, not bit for bit. */
+typedef struct mds_batch_job {
+  const void* D;   /* device, n x n row-major, dtype d_dtype */
+  double* coords;  /* device, n x k row-major fp64 */
+  double* eigvals; /* device, k fp64 */
+  int64_t n;
+  int32_t k, oversample, q, d_dtype;
+  uint64_t seed;
+} mds_batch_job;
+/* Device workspace for the batch (host-only computation). */
+mds_status mds_batch_workspace_size(const mds_batch_job* jobs, int32_t count, int32_t form, size_t* bytes);
+/* Enqueue the batch on `stream` (256-byte aligned workspace of at least the
+ * size above, caller-owned, valid until the stream work completes). */
+mds_status mds_run_batch(const mds_batch_job* jobs, int32_t count, int32_t form, void* workspace, size_t bytes,
+                         void* stream);
+/* Synchronise `stream` and write the numerical status of each instance of
+ * the last batch run in `workspace` (MDS_OK, MDS_ERR_NONFINITE or
+ * MDS_ERR_NUMERICAL) to host statuses[count]. */
+mds_status mds_batch_status(const void* workspace, int32_t count, int32_t* statuses, void* stream);
+
 /* ---- Serving: continuous batching of MDS jobs (spec serving loop) ----
  * A server owns a device arena of hbm_budget_bytes, allocated once by
  * mds_server_create (nothing is allocated on the device while serving), and

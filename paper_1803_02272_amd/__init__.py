@@ -163,6 +163,43 @@ class Plan:
         return inf.as_dict()
 
 
+def run_batch(problems, form="bf16", stream=None):
+    """Batched small instances in one persistent launch (mds_run_batch).
+
+    problems: list of dicts with keys D (contiguous cuda float32/float64 n x n),
+    k, oversample, q, seed.  Returns (results, statuses) with results a list
+    of (coords n x k, eigvals k) fp64 tensors; synchronises the stream."""
+    import torch
+
+    fk = FORMS[form] if isinstance(form, str) else int(form)
+    arr = (_capi.MdsBatchJob * max(len(problems), 1))()
+    outs = []
+    for i, pr in enumerate(problems):
+        D = pr["D"]
+        n = D.shape[0]
+        if not (D.is_cuda and D.dim() == 2 and D.shape[1] == n and D.is_contiguous()
+                and D.dtype in (torch.float32, torch.float64)):
+            raise ValueError("D must be a contiguous square cuda float32/float64 tensor")
+        c = torch.empty((n, int(pr["k"])), dtype=torch.float64, device=D.device)
+        e = torch.empty((int(pr["k"]),), dtype=torch.float64, device=D.device)
+        outs.append((c, e))
+        arr[i] = _capi.MdsBatchJob(D.data_ptr(), c.data_ptr(), e.data_ptr(), n, int(pr["k"]),
+                                   int(pr.get("oversample", 10)), int(pr.get("q", 2)),
+                                   _capi.DTYPE_F64 if D.dtype == torch.float64 else _capi.DTYPE_F32,
+                                   int(pr.get("seed", 0)))
+    L = _capi.lib()
+    nb = ctypes.c_size_t()
+    check(L.mds_batch_workspace_size(arr, len(problems), fk, ctypes.byref(nb)), "mds_batch_workspace_size")
+    ws = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    wp = ctypes.c_void_p(ws.data_ptr() + off)
+    sh = _stream_handle(stream)
+    check(L.mds_run_batch(arr, len(problems), fk, wp, nb.value, sh), "mds_run_batch")
+    st = (ctypes.c_int32 * max(len(problems), 1))()
+    check(L.mds_batch_status(wp, len(problems), st, sh), "mds_batch_status")
+    return outs, [int(st[i]) for i in range(len(problems))]
+
+
 class Server:
     """Continuous-batching server (mds_server_*): a device arena of
     ``budget_bytes`` and ``slots`` concurrent streams.  ``submit`` queues a job

@@ -73,6 +73,12 @@ class MdsPhaseTime(ctypes.Structure):
                 ("max_ms", ctypes.c_float)]
 
 
+class MdsBatchJob(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_void_p), ("coords", ctypes.c_void_p), ("eigvals", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("k", ctypes.c_int32), ("oversample", ctypes.c_int32),
+                ("q", ctypes.c_int32), ("d_dtype", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
 class MdsJobTimes(ctypes.Structure):
     _fields_ = [("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
 
@@ -103,6 +109,12 @@ SIGNATURES = {
     "mds_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mds_get_timings": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MdsPhaseTime), ctypes.c_void_p]),
     "mds_destroy": (None, [ctypes.c_void_p]),
+    "mds_batch_workspace_size": (ctypes.c_int, [ctypes.POINTER(MdsBatchJob), ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_size_t)]),
+    "mds_run_batch": (ctypes.c_int, [ctypes.POINTER(MdsBatchJob), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_size_t, ctypes.c_void_p]),
+    "mds_batch_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.c_void_p]),
     "mds_server_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, ctypes.c_int32]),
     "mds_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),

@@ -1,0 +1,647 @@
+// Batched small MDS: many independent instances of uneven n in one
+// persistent launch, one workgroup (four waves) per instance running the
+// whole method of Sec. 6.2 / 3.2-3.3 on its own:
+//   centring sums (fp64) -> G in the pass dtype -> Omega (the same Philox
+//   stream as the single-instance path) -> (2q+1) x [G-pass on MFMA ->
+//   CholeskyQR2 in fp64] -> projection pass -> B = Q^T G Q -> cyclic Jacobi
+//   -> coordinates with the sign convention of the single-instance path.
+// Workgroups never wait on each other, so any number of instances can be
+// launched; each instance is latency-bound on one CU, and a launch fills the
+// chip with instances instead of with tiles of one instance.  Meant for n up
+// to a few thousand and l_pad <= 64 (the serving mix: k = 20, l = 30).
+//
+// The values of every dtype follow the single-instance path: fp64 G
+// entries from the centring equation in fp64, fp32 entries as
+// fma(-1/2, fl32(d^2), fl32(c_j/2) + fl32((r_i - m)/2)), bf16 entries as the
+// bf16 rounding of the fp32 rounding of the fp64 entry; the bf16 form's
+// projection uses the fp32 entries.  Sums run in a different order, so
+// results agree with a single-instance run to rounding, not bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/mds.h"
+#include "mds_internal.h"
+#include "omega_dev.h"
+#include "plan.h"
+#include "small_dev.h"
+
+namespace mds {
+namespace {
+
+using namespace small;
+
+constexpr int kBT = 256;         // threads per instance
+constexpr int kBMaxL = 64;       // largest l_pad
+constexpr int kBPad = 64;        // n is padded to a multiple of this
+constexpr int kPerLaunch = 32;   // instances per launch (kernel-argument table)
+constexpr int64_t kBMaxN = 16384;
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+struct BJob {
+  const void* D;
+  double* coords;
+  double* eigvals;
+  char* ws;
+  DevStatus* st;
+  int64_t n, n_pad;
+  uint64_t seed;
+  int k, l, l_pad, q, d_is_f64, pad_;
+};
+
+struct BTable {
+  int count, pad_;
+  BJob job[kPerLaunch];
+};
+
+__host__ __device__ inline int64_t rup(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Per-instance workspace (offsets in bytes from the instance base).
+struct BLayout {
+  int64_t r, c, hc, hr, G, X, Y, Q, V, total;
+};
+
+__host__ __device__ inline BLayout blayout(int64_t np, int l_pad, int form) {
+  const int64_t gsz = form == MDS_FORM_FP64 ? 8 : (form == MDS_FORM_FP32 ? 4 : 2);
+  const int64_t xsz = form == MDS_FORM_FP64 ? 8 : 4;  // bf16 form: bf16 range operand, fp32 projection operand
+  BLayout L;
+  int64_t o = 0;
+  L.r = o, o += rup(np * 8, 256);
+  L.c = o, o += rup(np * 8, 256);
+  L.hc = o, o += rup(np * 4, 256);
+  L.hr = o, o += rup(np * 4, 256);
+  L.G = o, o += rup(np * np * gsz, 256);
+  L.X = o, o += rup((int64_t)l_pad * np * xsz, 256);
+  L.Y = o, o += rup((int64_t)l_pad * np * 8, 256);
+  L.Q = o, o += rup((int64_t)l_pad * np * 8, 256);
+  L.V = o, o += rup((int64_t)kBMaxL * kBMaxL * 8, 256);
+  L.total = o;
+  return L;
+}
+
+__device__ __forceinline__ bf16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+
+__device__ __forceinline__ double load_d(const BJob& J, int64_t idx) {
+  return J.d_is_f64 ? ((const double*)J.D)[idx] : (double)((const float*)J.D)[idx];
+}
+
+// ---- MFMA G-pass: Yt (fp64, l_pad x np) = (G X)^T --------------------------
+// GK: operand kind.  FROM_D: A entries recentred from D in fp32 (projection
+// of the bf16 form), else read from the stored G.
+template <int GK, bool FROM_D>
+__device__ void block_gpass(const BJob& J, const void* G, const void* Xt, double* Yt, const float* hc,
+                            const float* hr) {
+#pragma clang fp contract(off)
+  using T = typename std::conditional<GK == GK_F64, double, typename std::conditional<GK == GK_F32, float,
+                                                                                          bf16_t>::type>::type;
+  constexpr int E = 16 / sizeof(T);  // elements per lane per 16-byte chunk
+  constexpr int KS = 4 * E;          // K per chunk (four lane groups)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t np = J.n_pad, n = J.n;
+  const int CG = J.l_pad / 16;
+  const T* Gp = (const T*)G;
+  const T* Xp = (const T*)Xt;
+  for (int64_t tr = wave; tr < np / 16; tr += 4) {
+    const int64_t row = tr * 16 + (lane & 15);
+    using Acc = typename std::conditional<GK == GK_F64, doublex4_t, floatx4_t>::type;
+    Acc acc[kBMaxL / 16];
+#pragma unroll
+    for (int cg = 0; cg < kBMaxL / 16; ++cg)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[cg][e] = 0;
+    for (int64_t k0 = 0; k0 < np; k0 += KS) {
+      const int64_t kk = k0 + (lane >> 4) * E;
+      u32x4 a;
+      if constexpr (FROM_D) {
+        float g[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int64_t col = kk + t;
+          float v = 0.0f;
+          if (row < n && col < n) {
+            float d2;
+            if (J.d_is_f64) {
+              const double d = ((const double*)J.D)[row * n + col];
+              d2 = (float)(d * d);
+            } else {
+              const float d = ((const float*)J.D)[row * n + col];
+              d2 = d * d;
+            }
+            v = __builtin_fmaf(-0.5f, d2, hc[col] + hr[row]);
+          }
+          g[t] = v;
+        }
+        __builtin_memcpy(&a, g, 16);
+      } else {
+        a = *reinterpret_cast<const u32x4*>(Gp + row * np + kk);
+      }
+#pragma unroll
+      for (int cg = 0; cg < kBMaxL / 16; ++cg) {
+        if (cg >= CG) break;
+        const u32x4 b = *reinterpret_cast<const u32x4*>(Xp + (int64_t)(cg * 16 + (lane & 15)) * np + kk);
+        if constexpr (GK == GK_BF16) {
+          acc[cg] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                            __builtin_bit_cast(bf16x8, b), acc[cg], 0, 0, 0);
+        } else if constexpr (GK == GK_F32) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            acc[cg] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[t]), __uint_as_float(b[t]), acc[cg],
+                                                           0, 0, 0);
+        } else {
+          const double a0 = __hiloint2double((int)a.y, (int)a.x), a1 = __hiloint2double((int)a.w, (int)a.z);
+          const double b0 = __hiloint2double((int)b.y, (int)b.x), b1 = __hiloint2double((int)b.w, (int)b.z);
+          acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[cg], 0, 0, 0);
+          acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[cg], 0, 0, 0);
+        }
+      }
+    }
+    // accumulator layout: column lane % 16; rows 4g + r (fp32 accumulate)
+    // or g + 4r (fp64), g = lane / 16
+#pragma unroll
+    for (int cg = 0; cg < kBMaxL / 16; ++cg) {
+      if (cg >= CG) break;
+      double* dst = Yt + (int64_t)(cg * 16 + (lane & 15)) * np + tr * 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = GK == GK_F64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+        dst[rr] = (double)acc[cg][r];
+      }
+    }
+  }
+}
+
+// M (LDS, ld ldm) = A B^T over the l_pad rows of the transposed tall
+// matrices At, Bt (l_pad x np fp64), with fp64 MFMA.
+__device__ void block_gram(const double* At, const double* Bt, int64_t np, int l_pad, lds_double* M, int ldm) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int CG = l_pad / 16;
+  for (int t = wave; t < CG * CG; t += 4) {
+    const int ta = t / CG, tb = t % CG;
+    doublex4_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    const double* pa = At + (int64_t)(ta * 16 + (lane & 15)) * np + (lane >> 4);
+    const double* pb = Bt + (int64_t)(tb * 16 + (lane & 15)) * np + (lane >> 4);
+    for (int64_t k0 = 0; k0 < np; k0 += 8) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[k0], pb[k0], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[k0 + 4], pb[k0 + 4], acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) M[(ta * 16 + (lane >> 4) + 4 * r) * ldm + tb * 16 + (lane & 15)] = acc0[r] + acc1[r];
+  }
+}
+
+// Out^T = (In T)^T: out[b][i] = sum_a T[a][b] in[a][i] (T in LDS, ld ldm),
+// rows b >= l and columns i >= n zero; optional cast copy into X (kind xk).
+__device__ void block_apply(const double* In, double* Out, int64_t np, int64_t n, int l, int l_pad,
+                            const lds_double* Tm, int ldm, void* X, int xk) {
+  for (int64_t i = threadIdx.x; i < np; i += kBT) {
+    double y[kBMaxL];
+#pragma unroll
+    for (int a = 0; a < kBMaxL; ++a) y[a] = (a < l) ? In[(int64_t)a * np + i] : 0.0;
+    for (int b = 0; b < l_pad; ++b) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < kBMaxL; ++a)
+        if (a < l) acc += Tm[a * ldm + b] * y[a];
+      const double v = (b < l && i < n) ? acc : 0.0;
+      Out[(int64_t)b * np + i] = v;
+      if (xk == GK_F64)
+        ((double*)X)[(int64_t)b * np + i] = v;
+      else if (xk == GK_F32)
+        ((float*)X)[(int64_t)b * np + i] = (float)v;
+      else if (xk == GK_BF16)
+        ((bf16_t*)X)[(int64_t)b * np + i] = to_bf16((float)v);
+    }
+  }
+}
+
+struct BShared {
+  JacobiShared sh;
+  double M[kBMaxL * kBMaxL];
+  double P[kBMaxL * kNB];
+  double wdiag[kBMaxL];
+  double scl[kBMaxL];
+  double th[kBMaxL];
+  int perm[kBMaxL];
+  int flag, dropped;
+  double best_v[kBT / 64];
+  int64_t best_i[kBT / 64];
+};
+
+// T with (Yt)^T T orthonormal from M = W = Y^T Y (in LDS): Cholesky and
+// inverse, the first-order factor of an almost orthonormal basis, or the
+// eigen fallback V S^{-1/2} with V in global scratch.  Leaves the full T
+// in M (strictly lower part zero in the triangular cases).
+__device__ void block_factor(BShared& S, int l, int l_pad, bool near_identity, const double* Yt, int64_t np,
+                             double* Vg, DevStatus* st) {
+  lds_double* M = (lds_double*)(void*)S.M;
+  const int tid = threadIdx.x;
+  const int ldm = kBMaxL;
+  for (int i = tid; i < l; i += kBT) S.wdiag[i] = M[i * ldm + i];
+  __syncthreads();
+  if (near_identity) {
+    double emax = 0.0;
+    for (int e = tid; e < l * l; e += kBT) {
+      const int i = e / l, j = e % l;
+      emax = fmax(emax, fabs(M[i * ldm + j] - (i == j ? 1.0 : 0.0)));
+    }
+    emax = block_max<kBT>(emax, S.sh.red);
+    if (emax < 1e-9) {
+      for (int e = tid; e < l_pad * l_pad; e += kBT) {
+        const int i = e / l_pad, j = e % l_pad;
+        double t = 0.0;
+        if (i < l && j < l) {
+          const double x = M[i * ldm + j] - (i == j ? 1.0 : 0.0);
+          t = (i == j) ? 1.0 - 0.5 * x : (j > i ? -x : 0.0);
+        }
+        M[i * ldm + j] = t;  // each entry depends on itself only
+      }
+      __syncthreads();
+      return;
+    }
+  }
+  if (chol_blocked<kBT>(M, ldm, l, S.wdiag, &S.flag)) {
+    trinv_blocked<kBT>(M, ldm, l, S.P);
+    for (int e = tid; e < l_pad * l_pad; e += kBT) {
+      const int i = e / l_pad, j = e % l_pad;
+      if (j < i || i >= l || j >= l) M[i * ldm + j] = 0.0;
+    }
+    __syncthreads();
+    return;
+  }
+  // fallback: eigendecomposition of W (recomputed), T = V diag(s^{-1/2})
+  __syncthreads();
+  block_gram(Yt, Yt, np, l_pad, M, ldm);
+  for (int e = tid; e < kBMaxL * kBMaxL; e += kBT) {
+    const int i = e / kBMaxL, j = e % kBMaxL;
+    Vg[e] = (i == j) ? 1.0 : 0.0;
+    if (i >= l || j >= l) M[e] = 0.0;
+  }
+  __syncthreads();
+  int rounds = 0;
+  jacobi<kBT>(M, ldm, Vg, kBMaxL, (double2*)nullptr, l + (l & 1), S.sh, &rounds);
+  __syncthreads();
+  double smax = -1.0;
+  for (int i = tid; i < l; i += kBT) smax = fmax(smax, M[i * ldm + i]);
+  smax = block_max<kBT>(smax, S.sh.red);
+  if (tid == 0) S.dropped = 0;
+  __syncthreads();
+  for (int i = tid; i < l; i += kBT) {
+    const double sv = M[i * ldm + i];
+    const bool keep = smax > 0.0 && sv > 1e-13 * smax;
+    S.scl[i] = keep ? 1.0 / sqrt(sv) : 0.0;
+    if (!keep) atomicAdd(&S.dropped, 1);
+  }
+  __syncthreads();
+  for (int e = tid; e < kBMaxL * kBMaxL; e += kBT) {
+    const int i = e / kBMaxL, j = e % kBMaxL;
+    M[e] = (i < l && j < l) ? Vg[e] * S.scl[j] : 0.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    atomicAdd(&st->orth_fallbacks, 1);
+    st->rank_deficient = S.dropped;
+  }
+}
+
+// CholeskyQR2 of Yt into Qt (fp64) with a cast copy of Q into X (kind xk).
+__device__ void block_orth(BShared& S, const BJob& J, double* Yt, double* Qt, double* Vg, void* X, int xk) {
+  lds_double* M = (lds_double*)(void*)S.M;
+  const int64_t np = J.n_pad;
+  for (int step = 0; step < 2; ++step) {
+    const double* In = step == 0 ? Yt : Qt;
+    __syncthreads();
+    block_gram(In, In, np, J.l_pad, M, kBMaxL);
+    __syncthreads();
+    block_factor(S, J.l, J.l_pad, step == 1, In, np, Vg, J.st);
+    __syncthreads();
+    // step 0 writes Q1 over Y (In = Yt, Out = Qt would alias in step 1), so:
+    // step 0: Qt = Y T; step 1: Yt = Qt T, then the result is copied back
+    block_apply(In, step == 0 ? Qt : Yt, np, J.n, J.l, J.l_pad, M, kBMaxL, step == 1 ? X : nullptr,
+                step == 1 ? xk : -1);
+    __syncthreads();
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)J.l_pad * np; e += kBT) Qt[e] = Yt[e];
+  __syncthreads();
+}
+
+// Column r of the n x k row-major coords: make the entry of largest
+// magnitude positive (lowest row index on ties).
+__device__ void block_sign(BShared& S, double* C, int64_t n, int k, int r) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double bv = -1.0;
+  int64_t bi = 0;
+  for (int64_t i = tid; i < n; i += kBT) {
+    const double v = fabs(C[i * k + r]);
+    if (v > bv) {
+      bv = v;
+      bi = i;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(bv, off, 64);
+    const int64_t oi = __shfl_xor(bi, off, 64);
+    if (ov > bv || (ov == bv && oi < bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    S.best_v[wave] = bv;
+    S.best_i[wave] = bi;
+  }
+  __syncthreads();
+  bv = S.best_v[0];
+  bi = S.best_i[0];
+  for (int w = 1; w < kBT / 64; ++w)
+    if (S.best_v[w] > bv || (S.best_v[w] == bv && S.best_i[w] < bi)) {
+      bv = S.best_v[w];
+      bi = S.best_i[w];
+    }
+  const bool flip = C[bi * k + r] < 0.0;
+  __syncthreads();
+  if (flip)
+    for (int64_t i = tid; i < n; i += kBT) C[i * k + r] = -C[i * k + r];
+}
+
+template <int FORM>
+__global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
+#pragma clang fp contract(off)
+  if ((int)blockIdx.x >= tab.count) return;
+  const BJob J = tab.job[blockIdx.x];
+  __shared__ BShared S;
+  lds_double* M = (lds_double*)(void*)S.M;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t n = J.n, np = J.n_pad;
+  const int l = J.l, l_pad = J.l_pad, k = J.k;
+  const BLayout Lo = blayout(np, l_pad, FORM);
+  double* r = (double*)(J.ws + Lo.r);
+  double* c = (double*)(J.ws + Lo.c);
+  float* hc = (float*)(J.ws + Lo.hc);
+  float* hr = (float*)(J.ws + Lo.hr);
+  void* G = J.ws + Lo.G;
+  void* X = J.ws + Lo.X;
+  double* Yt = (double*)(J.ws + Lo.Y);
+  double* Qt = (double*)(J.ws + Lo.Q);
+  double* Vg = (double*)(J.ws + Lo.V);
+  constexpr int GK = FORM == MDS_FORM_FP64 ? GK_F64 : (FORM == MDS_FORM_FP32 ? GK_F32 : GK_BF16);
+  constexpr int PK = FORM == MDS_FORM_FP64 ? GK_F64 : GK_F32;  // projection operand
+
+  if (tid == 0) {
+    DevStatus z = {};
+    *J.st = z;
+  }
+  // ---- centring sums (fp64): column means by thread, row means by wave ----
+  for (int64_t j = tid; j < np; j += kBT) {
+    double s0 = 0.0, s1 = 0.0;
+    if (j < n) {
+      int64_t i = 0;
+      for (; i + 1 < n; i += 2) {
+        const double d0 = load_d(J, i * n + j), d1 = load_d(J, (i + 1) * n + j);
+        s0 += d0 * d0;
+        s1 += d1 * d1;
+      }
+      if (i < n) {
+        const double d = load_d(J, i * n + j);
+        s0 += d * d;
+      }
+    }
+    c[j] = j < n ? (s0 + s1) / (double)n : 0.0;
+  }
+  double rsum_part = 0.0;
+  for (int64_t i = wave; i < np; i += kBT / 64) {
+    double s = 0.0;
+    if (i < n)
+      for (int64_t j = lane; j < n; j += 64) {
+        const double d = load_d(J, i * n + j);
+        s += d * d;
+      }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+      r[i] = i < n ? s / (double)n : 0.0;
+      rsum_part += i < n ? s / (double)n : 0.0;
+    }
+  }
+  const double m = block_sum<kBT>(rsum_part, S.sh.red) / (double)n;
+  __syncthreads();
+  if (tid == 0 && !(m == m && fabs(m) <= 1.7976931348623157e308)) J.st->nonfinite = 1;
+  for (int64_t j = tid; j < np; j += kBT) {
+    hc[j] = j < n ? (float)(0.5 * c[j]) : 0.0f;
+    hr[j] = j < n ? (float)(0.5 * (r[j] - m)) : 0.0f;
+  }
+  __syncthreads();
+  // ---- G in the pass dtype ------------------------------------------------
+  for (int64_t i = wave; i < np; i += kBT / 64)
+    for (int64_t j = lane; j < np; j += 64) {
+      const bool in = i < n && j < n;
+      const double d = in ? load_d(J, i * n + j) : 0.0;
+      if constexpr (FORM == MDS_FORM_FP64) {
+        ((double*)G)[i * np + j] = in ? -0.5 * (((d * d - c[j]) - r[i]) + m) : 0.0;
+      } else if constexpr (FORM == MDS_FORM_FP32) {
+        const float d2 = J.d_is_f64 ? (float)(d * d) : (float)d * (float)d;
+        ((float*)G)[i * np + j] = in ? __builtin_fmaf(-0.5f, d2, hc[j] + hr[i]) : 0.0f;
+      } else {
+        ((bf16_t*)G)[i * np + j] = in ? to_bf16((float)(-0.5 * (((d * d - c[j]) - r[i]) + m))) : (bf16_t)0;
+      }
+    }
+  // ---- Omega in the range operand dtype (transposed, l_pad x np) ------------
+  for (int64_t e = tid; e < np * (l_pad / 4); e += kBT) {
+    const int64_t i = e % np, b = e / np;
+    double z[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < n && 4 * b < l) omega::omega_block(J.seed, i, b, z);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t col = 4 * b + t;
+      const double v = col < l ? z[t] : 0.0;
+      if constexpr (GK == GK_F64)
+        ((double*)X)[col * np + i] = v;
+      else if constexpr (GK == GK_F32)
+        ((float*)X)[col * np + i] = (float)v;
+      else
+        ((bf16_t*)X)[col * np + i] = to_bf16((float)v);
+    }
+  }
+  __syncthreads();
+  // ---- range finder ---------------------------------------------------------
+  const int passes = 2 * J.q + 1;
+  for (int it = 0; it < passes; ++it) {
+    block_gpass<GK, false>(J, G, X, Yt, hc, hr);
+    block_orth(S, J, Yt, Qt, Vg, X, it == passes - 1 ? PK : GK);
+  }
+  // ---- projection B = Q^T G Q ------------------------------------------------
+  if constexpr (FORM == MDS_FORM_BF16)
+    block_gpass<GK_F32, true>(J, nullptr, X, Yt, hc, hr);
+  else
+    block_gpass<PK, false>(J, G, X, Yt, hc, hr);
+  __syncthreads();
+  block_gram(Qt, Yt, np, l_pad, M, kBMaxL);
+  __syncthreads();
+  for (int e = tid; e < kBMaxL * kBMaxL; e += kBT) {
+    const int i = e / kBMaxL, j = e % kBMaxL;
+    double v = 0.0;
+    if (i < l && j < l) v = 0.5 * (M[i * kBMaxL + j] + M[j * kBMaxL + i]);
+    Vg[e] = v;        // symmetrised B staged in global scratch
+  }
+  __syncthreads();
+  for (int e = tid; e < kBMaxL * kBMaxL; e += kBT) M[e] = Vg[e];
+  for (int e = tid; e < kBMaxL * kBMaxL; e += kBT) Vg[e] = (e / kBMaxL == e % kBMaxL) ? 1.0 : 0.0;
+  __syncthreads();
+  // ---- eigenpairs of B ------------------------------------------------------
+  int rounds = 0;
+  const int sweeps = jacobi<kBT>(M, kBMaxL, Vg, kBMaxL, (double2*)nullptr, l + (l & 1), S.sh, &rounds);
+  __syncthreads();
+  for (int i = tid; i < l; i += kBT) S.th[i] = M[i * kBMaxL + i];
+  __syncthreads();
+  for (int i = tid; i < l; i += kBT) S.perm[desc_rank(S.th, l, i)] = i;  // a permutation, NaN included
+  __syncthreads();
+  // Tc = V_k diag(sqrt(max(theta, 0))) into M (l x k, ld kBMaxL)
+  for (int e = tid; e < kBMaxL * kBMaxL; e += kBT) {
+    const int a = e / kBMaxL, rr = e % kBMaxL;
+    double v = 0.0;
+    if (a < l && rr < k) {
+      const double thr = S.th[S.perm[rr]];
+      v = Vg[a * kBMaxL + S.perm[rr]] * sqrt(fmax(thr, 0.0));
+    }
+    M[e] = v;
+  }
+  if (tid < k) J.eigvals[tid] = S.th[S.perm[tid]];
+  if (tid == 0) {
+    J.st->jacobi_sweeps = sweeps < 0 ? -sweeps : sweeps;
+    if (sweeps < 0) atomicAdd(&J.st->jacobi_unconv, 1);
+  }
+  __syncthreads();
+  // ---- coordinates X = Q Tc, signs ------------------------------------------
+  for (int64_t i = tid; i < n; i += kBT) {
+    double qv[kBMaxL];
+#pragma unroll
+    for (int a = 0; a < kBMaxL; ++a) qv[a] = (a < l) ? Qt[(int64_t)a * np + i] : 0.0;
+    for (int rr = 0; rr < k; ++rr) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < kBMaxL; ++a)
+        if (a < l) acc += qv[a] * M[a * kBMaxL + rr];
+      J.coords[i * k + rr] = acc;
+    }
+  }
+  __syncthreads();
+  for (int rr = 0; rr < k; ++rr) block_sign(S, J.coords, n, k, rr);
+}
+
+}  // namespace
+}  // namespace mds
+
+using namespace mds;
+
+namespace {
+
+mds_status batch_check(const mds_batch_job* jobs, int32_t count, int32_t form) {
+  if (!jobs || count < 0) return fail(MDS_ERR_INVALID_ARG, "NULL jobs or count < 0");
+  if (form < MDS_FORM_FP64 || form > MDS_FORM_BF16) return fail(MDS_ERR_INVALID_ARG, "unknown form %d", form);
+  for (int32_t i = 0; i < count; ++i) {
+    const mds_batch_job& b = jobs[i];
+    const int64_t l = (int64_t)b.k + b.oversample;
+    if (b.n < 2 || b.n > kBMaxN) return fail(MDS_ERR_INVALID_ARG, "job %d: n = %lld outside [2, %lld]", i,
+                                             (long long)b.n, (long long)kBMaxN);
+    if (b.k < 1 || b.oversample < 0 || b.q < 0 || l > b.n || rup(l, 16) > kBMaxL)
+      return fail(MDS_ERR_INVALID_ARG, "job %d: k = %d, oversample = %d, q = %d (need k + oversample <= "
+                  "min(n, %d))", i, b.k, b.oversample, b.q, kBMaxL);
+    if (b.d_dtype != MDS_DTYPE_F32 && b.d_dtype != MDS_DTYPE_F64)
+      return fail(MDS_ERR_INVALID_ARG, "job %d: unknown D dtype %d", i, b.d_dtype);
+  }
+  return MDS_OK;
+}
+
+size_t job_bytes(const mds_batch_job& b, int form) {
+  const int l_pad = (int)rup((int64_t)b.k + b.oversample, 16);
+  return (size_t)blayout(rup(b.n, kBPad), l_pad, form).total;
+}
+
+}  // namespace
+
+extern "C" {
+
+mds_status mds_batch_workspace_size(const mds_batch_job* jobs, int32_t count, int32_t form, size_t* bytes) {
+  if (!bytes) return fail(MDS_ERR_INVALID_ARG, "bytes is NULL");
+  const mds_status st = batch_check(jobs, count, form);
+  if (st != MDS_OK) return st;
+  size_t total = (size_t)rup((int64_t)count * sizeof(DevStatus), 256);
+  for (int32_t i = 0; i < count; ++i) total += job_bytes(jobs[i], form);
+  *bytes = total;
+  return MDS_OK;
+}
+
+mds_status mds_run_batch(const mds_batch_job* jobs, int32_t count, int32_t form, void* workspace, size_t bytes,
+                         void* stream) {
+  mds_status st = batch_check(jobs, count, form);
+  if (st != MDS_OK) return st;
+  size_t need = 0;
+  mds_batch_workspace_size(jobs, count, form, &need);
+  if (!workspace || bytes < need || ((uintptr_t)workspace % 256) != 0)
+    return fail(MDS_ERR_INVALID_ARG, "workspace NULL, unaligned or smaller than %zu bytes", need);
+  for (int32_t i = 0; i < count; ++i)
+    if (!jobs[i].D || !jobs[i].coords || !jobs[i].eigvals)
+      return fail(MDS_ERR_INVALID_ARG, "job %d: NULL D, coords or eigvals", i);
+  if (count == 0) return MDS_OK;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(MDS_ERR_NO_DEVICE, "no HIP device available");
+  }
+  char* base = static_cast<char*>(workspace);
+  DevStatus* stat = reinterpret_cast<DevStatus*>(base);
+  size_t off = (size_t)rup((int64_t)count * sizeof(DevStatus), 256);
+  for (int32_t i0 = 0; i0 < count; i0 += kPerLaunch) {
+    BTable tab{};
+    tab.count = count - i0 < kPerLaunch ? count - i0 : kPerLaunch;
+    for (int t = 0; t < tab.count; ++t) {
+      const mds_batch_job& b = jobs[i0 + t];
+      BJob& J = tab.job[t];
+      J.D = b.D;
+      J.coords = b.coords;
+      J.eigvals = b.eigvals;
+      J.ws = base + off;
+      J.st = stat + i0 + t;
+      J.n = b.n;
+      J.n_pad = rup(b.n, kBPad);
+      J.seed = b.seed;
+      J.k = b.k;
+      J.l = b.k + b.oversample;
+      J.l_pad = (int)rup(J.l, 16);
+      J.q = b.q;
+      J.d_is_f64 = b.d_dtype == MDS_DTYPE_F64;
+      off += job_bytes(b, form);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (form == MDS_FORM_FP64)
+      hipLaunchKernelGGL(k_batch<MDS_FORM_FP64>, dim3(tab.count), dim3(kBT), 0, s, tab);
+    else if (form == MDS_FORM_FP32)
+      hipLaunchKernelGGL(k_batch<MDS_FORM_FP32>, dim3(tab.count), dim3(kBT), 0, s, tab);
+    else
+      hipLaunchKernelGGL(k_batch<MDS_FORM_BF16>, dim3(tab.count), dim3(kBT), 0, s, tab);
+    st = hip_check(hipGetLastError(), "k_batch launch");
+    if (st != MDS_OK) return st;
+  }
+  return MDS_OK;
+}
+
+mds_status mds_batch_status(const void* workspace, int32_t count, int32_t* statuses, void* stream) {
+  if (!workspace || !statuses || count < 0) return fail(MDS_ERR_INVALID_ARG, "NULL argument");
+  if (count == 0) return MDS_OK;
+  std::vector<DevStatus> h((size_t)count);
+  mds_status st = hip_check(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+  if (st != MDS_OK) return st;
+  st = hip_check(hipMemcpy(h.data(), workspace, (size_t)count * sizeof(DevStatus), hipMemcpyDeviceToHost),
+                 "status copy");
+  if (st != MDS_OK) return st;
+  for (int32_t i = 0; i < count; ++i)
+    statuses[i] = h[i].nonfinite ? MDS_ERR_NONFINITE : (h[i].jacobi_unconv ? MDS_ERR_NUMERICAL : MDS_OK);
+  return MDS_OK;
+}
+
+}  // extern "C"

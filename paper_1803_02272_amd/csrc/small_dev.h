@@ -1,0 +1,398 @@
+// Block-level fp64 helpers shared by the small dense kernels (one workgroup
+// per l x l problem) and the batched small-MDS kernel: reductions, cyclic
+// Jacobi with the round-robin parallel ordering, blocked Cholesky and the
+// blocked inverse of an upper triangular factor.  See k_small.hip for the
+// methods.
+#pragma once
+
+#include "mds_internal.h"
+
+namespace mds {
+namespace small {
+
+constexpr int kEigThreads = 1024;  // small_eig workgroup
+constexpr int kOrthThreads = 256;  // orth_factor workgroup
+constexpr int kNB = 16;            // panel width of the blocked Cholesky / inverse
+constexpr int kMaxPairs = kMaxL / 2;
+constexpr int kMaxSweeps = 40;
+
+typedef __attribute__((address_space(3))) double lds_double;
+
+struct JacobiShared {
+  int2 pq[kMaxPairs];
+  double2 cs[kMaxPairs];
+  double t[kMaxPairs];
+  int nrot;
+  double red[kEigThreads / 64];
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int kThreads>
+__device__ double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+template <int kThreads>
+__device__ double block_max(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = red[0];
+  for (int w = 1; w < kThreads / 64; ++w) s = fmax(s, red[w]);
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ void round_robin_pair(int le, int r, int t, int& p, int& q) {
+  if (t == 0) {
+    p = le - 1;
+    q = r;
+  } else {
+    p = (r + t) % (le - 1);
+    q = (r - t + (le - 1)) % (le - 1);
+  }
+  if (p > q) {
+    const int x = p;
+    p = q;
+    q = x;
+  }
+}
+
+template <int kThreads, typename MT>
+__device__ double frob2(MT M, int ldm, int le) {
+  double f = 0.0;
+  for (int e = threadIdx.x; e < le * le; e += kThreads) {
+    const double v = M[(e / le) * ldm + e % le];
+    f += v * v;
+  }
+  return f;
+}
+
+template <int kThreads, typename MT>
+__device__ double off2(MT M, int ldm, int le) {
+  double f = 0.0;
+  for (int e = threadIdx.x; e < le * le; e += kThreads) {
+    const int i = e / le, j = e % le;
+    if (i != j) {
+      const double v = M[i * ldm + j];
+      f += v * v;
+    }
+  }
+  return f;
+}
+
+// Cyclic Jacobi on the symmetric le x le matrix M (ld ldm; le even, a padding
+// row/column of zeros is never rotated).  Either accumulates V <- V J in
+// place (V != nullptr, ld ldv, identity on entry) or records (c, s) of every
+// pair and round in rot (rot != nullptr).  Returns sweeps used (negative if
+// the cap was hit); *rounds receives the number of rounds recorded.
+template <int kThreads, typename MT>
+__device__ int jacobi(MT M, int ldm, double* V, int ldv, double2* rot, int le, JacobiShared& sh, int* rounds) {
+  constexpr int kMaxBlocksPerThread = (kMaxL / 2) * (kMaxL / 2) / kThreads;
+  const int tid = threadIdx.x;
+  const int np = le / 2;
+  // this thread's fixed (pair a, pair b) blocks; pairs are renamed every round
+  // but the block list of a thread is the same in all rounds
+  int nblk = 0;
+  int blk[kMaxBlocksPerThread];
+  for (int e = tid; e < np * np && nblk < kMaxBlocksPerThread; e += kThreads) blk[nblk++] = ((e / np) << 16) | (e % np);
+  const double fro = sqrt(block_sum<kThreads>(frob2<kThreads>(M, ldm, le), sh.red));
+  const double thr = 1e-17 * fro;
+  int nr = 0;
+  int sweep = 0;
+  bool converged = false;
+  for (; sweep < kMaxSweeps && !converged; ++sweep) {
+    if (tid == 0) sh.nrot = 0;
+    __syncthreads();
+    for (int r = 0; r < le - 1; ++r, ++nr) {
+      if (tid < np) {
+        int p, q;
+        round_robin_pair(le, r, tid, p, q);
+        const double app = M[p * ldm + p], aqq = M[q * ldm + q], apq = M[p * ldm + q];
+        double c = 1.0, s = 0.0, t = 0.0;
+        if (fabs(apq) > thr) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          t = fabs(tau) > 1e150 ? 0.5 / tau : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+          atomicAdd(&sh.nrot, 1);
+        }
+        sh.pq[tid] = make_int2(p, q);
+        sh.cs[tid] = make_double2(c, s);
+        sh.t[tid] = t;
+        if (rot) rot[(int64_t)nr * np + tid] = make_double2(c, s);
+      }
+      __syncthreads();
+      // M <- J^T M J, one 2x2 block (pair a rows, pair b columns) at a time.
+      // All loads of this thread's blocks are issued before any store (the
+      // blocks are disjoint), so their LDS latencies overlap.
+      for (int u0 = 0; u0 < nblk; u0 += 4) {
+        double m[4][4];
+        int idx[4][4];
+        bool act[4];
+#pragma unroll
+        for (int uu = 0; uu < 4; ++uu) {
+          const int u = u0 + uu;
+          act[uu] = false;
+          if (u < nblk) {
+            const int a = blk[u] >> 16, b = blk[u] & 0xffff;
+            act[uu] = sh.cs[a].y != 0.0 || sh.cs[b].y != 0.0;
+            const int2 pqa = sh.pq[a], pqb = sh.pq[b];
+            idx[uu][0] = pqa.x * ldm + pqb.x;
+            idx[uu][1] = pqa.x * ldm + pqb.y;
+            idx[uu][2] = pqa.y * ldm + pqb.x;
+            idx[uu][3] = pqa.y * ldm + pqb.y;
+            if (act[uu]) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) m[uu][e] = M[idx[uu][e]];
+            }
+          }
+        }
+#pragma unroll
+        for (int uu = 0; uu < 4; ++uu) {
+          if (!act[uu]) continue;
+          const int u = u0 + uu;
+          const int a = blk[u] >> 16, b = blk[u] & 0xffff;
+          const double m00 = m[uu][0], m01 = m[uu][1], m10 = m[uu][2], m11 = m[uu][3];
+          if (a == b) {
+            const double t = sh.t[a];
+            M[idx[uu][0]] = m00 - t * m01;
+            M[idx[uu][3]] = m11 + t * m01;
+            M[idx[uu][1]] = 0.0;
+            M[idx[uu][2]] = 0.0;
+          } else {
+            const double2 csa = sh.cs[a], csb = sh.cs[b];
+            const double ca = csa.x, sa = csa.y, cb = csb.x, sb = csb.y;
+            // rows: r_p = c x_p - s x_q, r_q = s x_p + c x_q
+            const double r00 = ca * m00 - sa * m10, r01 = ca * m01 - sa * m11;
+            const double r10 = sa * m00 + ca * m10, r11 = sa * m01 + ca * m11;
+            // columns: y_p = c r_p - s r_q, y_q = s r_p + c r_q
+            M[idx[uu][0]] = cb * r00 - sb * r01;
+            M[idx[uu][1]] = sb * r00 + cb * r01;
+            M[idx[uu][2]] = cb * r10 - sb * r11;
+            M[idx[uu][3]] = sb * r10 + cb * r11;
+          }
+        }
+      }
+      if (V) {
+        for (int i = tid / np; i < le; i += kThreads / np) {
+          const int b = tid % np;
+          if (tid >= (kThreads / np) * np) break;
+          const double2 csb = sh.cs[b];
+          if (csb.y == 0.0) continue;
+          const int2 pqb = sh.pq[b];
+          const double vp = V[i * ldv + pqb.x], vq = V[i * ldv + pqb.y];
+          V[i * ldv + pqb.x] = csb.x * vp - csb.y * vq;
+          V[i * ldv + pqb.y] = csb.y * vp + csb.x * vq;
+        }
+      }
+      __syncthreads();
+    }
+    const int nrot = sh.nrot;
+    const double off = sqrt(block_sum<kThreads>(off2<kThreads>(M, ldm, le), sh.red));
+    converged = (nrot == 0) || (off <= 1e-15 * fro);
+  }
+  *rounds = nr;
+  return converged ? sweep : -sweep;
+}
+
+// ---- orthonormalisation factor ----------------------------------------------
+// Blocked right-looking Cholesky W = R^T R (upper R in M).  Panel rows
+// [k0, k0+16) are factored by wave 0 alone (wave-synchronous, no workgroup
+// barrier); the trailing update M22 -= R12^T R12 is done by all threads with
+// 4x4 register tiles.  Returns false (uniformly) on a collapsed pivot.
+template <int NT, typename MT>
+__device__ bool chol_blocked(MT M, int ldm, int l, const double* wdiag, int* flag) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int k0 = 0; k0 < l; k0 += kNB) {
+    const int nb = (l - k0 < kNB) ? l - k0 : kNB;
+    if (wave == 0) {
+      // left-looking inside the panel: row kk of R from the finished panel
+      // rows above it (loads only, then one store per entry)
+      int ok = 1;
+      for (int kk = k0; kk < k0 + nb; ++kk) {
+        const int nm = kk - k0;  // finished rows in this panel
+        // loads are unconditional from in-bounds addresses (k0 + 15 < l_pad,
+        // columns clamped) and masked by selects, so they issue back to back
+        double col[kNB];  // R[m][kk], m = k0 .. kk-1 (same on every lane)
+#pragma unroll
+        for (int m = 0; m < kNB; ++m) {
+          const double x = M[(k0 + m) * ldm + kk];
+          col[m] = (m < nm) ? x : 0.0;
+        }
+        constexpr int kMaxJ = kMaxL / 64;
+        double row[kMaxJ];
+#pragma unroll
+        for (int c = 0; c < kMaxJ; ++c) {
+          const int j = kk + 1 + lane + 64 * c;
+          const int jc = j < ldm ? j : ldm - 1;
+          double v = M[kk * ldm + jc];
+#pragma unroll
+          for (int m = 0; m < kNB; ++m) v -= col[m] * M[(k0 + m) * ldm + jc];
+          row[c] = v;
+        }
+        double piv = M[kk * ldm + kk];
+#pragma unroll
+        for (int m = 0; m < kNB; ++m) piv -= col[m] * col[m];
+        if (!(piv > 1e-12 * wdiag[kk]) || !(piv > 0.0)) {
+          ok = 0;
+          break;  // uniform within the wave
+        }
+        const double rkk = sqrt(piv), rinv = 1.0 / rkk;
+#pragma unroll
+        for (int c = 0; c < kMaxJ; ++c) {
+          const int j = kk + 1 + lane + 64 * c;
+          if (j < l) M[kk * ldm + j] = row[c] * rinv;
+        }
+        if (lane == 0) M[kk * ldm + kk] = rkk;
+        wave_sync();
+      }
+      if (lane == 0) *flag = ok;
+    }
+    __syncthreads();
+    if (!*flag) return false;
+    const int t0 = k0 + nb;
+    if (t0 < l) {
+      const int ty = tid / 16, tx = tid % 16;  // NT == 256
+      for (int ib = t0; ib < l; ib += 64) {
+        for (int jb = ib; jb < l; jb += 64) {
+          double acc[4][4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+          for (int kk = k0; kk < t0; ++kk) {
+            double ci[4], cj[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const int i = ib + ty + 16 * a;
+              const double x = M[kk * ldm + (i < ldm ? i : ldm - 1)];
+              ci[a] = (i < l) ? x : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const int j = jb + tx + 16 * c;
+              const double x = M[kk * ldm + (j < ldm ? j : ldm - 1)];
+              cj[c] = (j < l) ? x : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+              for (int c = 0; c < 4; ++c) acc[a][c] += ci[a] * cj[c];
+          }
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const int i = ib + ty + 16 * a, j = jb + tx + 16 * c;
+              if (i < l && j < l && j >= i) M[i * ldm + j] -= acc[a][c];
+            }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// In-place blocked inverse of the upper triangular R in M (T = R^{-1}).  For
+// each 16-column block J = [k0, k0+nb):
+//   P = T[0:k0, 0:k0] R[0:k0, J]   (all threads, 4x1 tiles)
+//   T_JJ = R_JJ^{-1}                (wave 0, concurrently)
+//   T[0:k0, J] = -P T_JJ
+template <int NT, typename MT>
+__device__ void trinv_blocked(MT M, int ldm, int l, double* P /* kMaxL x kNB, LDS */) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int k0 = 0; k0 < l; k0 += kNB) {
+    const int nb = (l - k0 < kNB) ? l - k0 : kNB;
+    // P rows i < k0: thread (ty, tx) -> column jj = tx, rows ty + 16a
+    {
+      const int ty = tid / 16, tx = tid % 16;
+      for (int ib = 0; ib < k0; ib += 64) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        const int jcol = k0 + tx;
+        if (tx < nb) {
+          // T upper: row i uses m in [i, k0)
+          const int i_lo = ib + ty;
+          for (int m = i_lo; m < k0; ++m) {
+            const double r = M[m * ldm + jcol];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const int i = i_lo + 16 * a;
+              const double x = M[(i < ldm ? i : ldm - 1) * ldm + m];
+              acc[a] += (i <= m) ? x * r : 0.0;
+            }
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int i = ib + ty + 16 * a;
+          if (i < k0 && tx < nb) P[i * kNB + tx] = acc[a];
+        }
+      }
+    }
+    if (wave == NT / 64 - 1) {
+      // T_JJ = R_JJ^{-1}, column by column, by the last wave
+      for (int j = 0; j < nb; ++j) {
+        const int jj = k0 + j;
+        const double tjj = 1.0 / M[jj * ldm + jj];
+        double acc = 0.0;
+        const int i = lane;  // row within the block
+        if (i < j) {
+#pragma unroll
+          for (int m = 0; m < kNB; ++m) {
+            const double x = M[(k0 + (i < kNB ? i : 0)) * ldm + (k0 + m)] * M[(k0 + m) * ldm + jj];
+            acc += (m >= i && m < j) ? x : 0.0;
+          }
+        }
+        wave_sync();
+        if (i < j) M[(k0 + i) * ldm + jj] = -tjj * acc;
+        if (lane == 0) M[jj * ldm + jj] = tjj;
+        wave_sync();
+      }
+    }
+    __syncthreads();
+    // T[0:k0, J] = -P T_JJ
+    for (int e = tid; e < k0 * kNB; e += NT) {
+      const int i = e / kNB, jj = e % kNB;
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < kNB; ++m) {
+        const double x = P[i * kNB + m] * M[(k0 + m) * ldm + (k0 + jj)];
+        acc += (m <= jj) ? x : 0.0;
+      }
+      if (jj < nb) M[i * ldm + k0 + jj] = -acc;
+    }
+    __syncthreads();
+  }
+}
+
+// Position of th[i] in descending order: a total order on (value, index)
+// with NaN below every number, so the ranks of th[0..l) are always a
+// permutation of 0..l-1 (ties go to the lower index).
+__device__ __forceinline__ int desc_rank(const double* th, int l, int i) {
+  const double v = th[i] != th[i] ? -__builtin_inf() : th[i];
+  int rank = 0;
+  for (int j = 0; j < l; ++j) {
+    const double w = th[j] != th[j] ? -__builtin_inf() : th[j];
+    rank += (w > v || (w == v && j < i)) ? 1 : 0;
+  }
+  return rank;
+}
+
+}  // namespace small
+}  // namespace mds

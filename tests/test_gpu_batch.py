@@ -1,0 +1,80 @@
+"""Batched small instances (mds_run_batch): one persistent launch, one
+workgroup per MDS instance, uneven n.  Each instance against the FP64
+oracle run with the form's roundings, and against the single-instance path."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_util import procrustes_err, rel_eig_err, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1803_02272_amd as mds  # noqa: E402
+from paper_1803_02272_amd import _capi  # noqa: E402
+
+MATCHED_EIG_BAR = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 1e-4}
+COORD_BAR = {"fp64": 1e-8, "fp32": 1e-3, "bf16": 5e-2}
+
+# (kind, n, k, p, q, seed): ragged n (not multiples of 64), l from 2 to 64
+PROBLEMS = [("gm", 517, 20, 10, 2, 1), ("amp", 1000, 20, 10, 2, 2), ("gm", 257, 5, 5, 1, 3),
+            ("amp", 2048, 40, 24, 1, 4), ("gm", 64, 10, 6, 0, 5), ("amp", 1531, 12, 4, 3, 6),
+            ("gm", 3001, 20, 10, 2, 7), ("amp", 333, 1, 1, 2, 8)]
+
+
+def build(kind, n, seed, f64=False):
+    if kind == "gm":
+        X, _ = W.gaussian_mixture(n, 50, 10, 25.0, seed)
+        return W.euclidean_distances(X, dtype=np.float64 if f64 else np.float32)
+    reads, _ = W.amplicon_reads(n, 50, seed=seed)
+    return W.hamming_distances(reads)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16"])
+def test_batch_matches_oracle_and_single_path(form):
+    Ds = [build(kind, n, seed, f64=(form == "fp64" and i % 2 == 0)) for i, (kind, n, _, _, _, seed)
+          in enumerate(PROBLEMS)]
+    probs = [dict(D=torch.from_numpy(D).cuda(), k=k, oversample=p, q=q, seed=seed)
+             for D, (_, n, k, p, q, seed) in zip(Ds, PROBLEMS)]
+    say(f"[batch] form={form} {len(probs)} instances")
+    outs, st = mds.run_batch(probs, form=form)
+    assert st == [_capi.OK] * len(probs)
+    for D, pr, (c, e), (kind, n, k, p, q, seed) in zip(Ds, probs, outs, PROBLEMS):
+        ref = O.rand_mds(D, k, p, q, seed, form=form)
+        X, eig = c.cpu().numpy(), e.cpu().numpy()
+        err = rel_eig_err(eig, ref["eigvals"])
+        cerr = procrustes_err(X, ref["coords"])
+        plan = mds.Plan(n, k, p, q, seed, form=form, d_dtype="f64" if D.dtype == np.float64 else "f32")
+        cs, es = plan.run(pr["D"])
+        serr = rel_eig_err(eig, es.cpu().numpy())
+        say(f"    {kind} n={n} k={k} l={k + p} q={q}: eig vs matched oracle {err:.2e}, coords {cerr:.2e}, "
+            f"vs single path {serr:.2e}")
+        assert err < MATCHED_EIG_BAR[form]
+        assert cerr < COORD_BAR[form]
+        assert serr < MATCHED_EIG_BAR[form]
+        idx = np.argmax(np.abs(X), axis=0)
+        assert np.all(X[idx, np.arange(k)] > 0)
+
+
+def test_batch_edge_cases_and_many_launches():
+    say("[batch] zero D, NaN D, n = 2, 40 instances over two launches")
+    Dz = torch.zeros((300, 300), dtype=torch.float32, device="cuda")
+    Dn = torch.from_numpy(build("amp", 400, 3)).cuda()
+    Dn[5, 9] = float("nan")
+    D2 = torch.tensor([[0.0, 3.0], [3.0, 0.0]], dtype=torch.float32, device="cuda")
+    small = [torch.from_numpy(build("gm", 80 + 7 * i, 100 + i)).cuda() for i in range(37)]
+    probs = [dict(D=Dz, k=4, oversample=4, q=1), dict(D=Dn, k=4, oversample=4, q=1),
+             dict(D=D2, k=1, oversample=1, q=1)] + [dict(D=D, k=6, oversample=4, q=1, seed=i)
+                                                    for i, D in enumerate(small)]
+    outs, st = mds.run_batch(probs, form="fp64")
+    assert st[0] == _capi.OK and st[1] == _capi.ERR_NONFINITE and st[2] == _capi.OK
+    assert torch.all(outs[0][0] == 0) and torch.all(outs[0][1] == 0)
+    assert np.isclose(outs[2][1].item(), 4.5, rtol=1e-12)
+    assert np.allclose(np.abs(outs[2][0].cpu().numpy()), 1.5, rtol=1e-12)
+    for i, D in enumerate(small):
+        ref = O.rand_mds(D.cpu().numpy(), 6, 4, 1, i)
+        assert st[3 + i] == _capi.OK
+        assert rel_eig_err(outs[3 + i][1].cpu().numpy(), ref["eigvals"]) < 1e-10
