@@ -132,6 +132,10 @@ def serving_bench(mds, torch, wgpu, seconds, warmup_s, rate, pool_size, budget_g
     out = {"pool": pool_size, "pool_gb": pool_gb, "budget_gib": budget_gb, "slots": slots, "rate_per_s": rate,
            "seconds": seconds, "warmup_s": warmup_s}
     with mds.Server(budget, slots=slots) as srv:
+        t0 = time.perf_counter()
+        out["batching_small_n_max"] = srv.autotune(form="bf16", k=20, oversample=10, q=2)
+        log(f"[serve] autotuned batching threshold n <= {out['batching_small_n_max']} "
+            f"in {time.perf_counter() - t0:.1f} s")
         # saturation: the whole pool submitted at once
         t0 = time.perf_counter()
         tickets = [srv.submit(pl, D)[0] for pl, D in pool]
@@ -164,7 +168,7 @@ def serving_bench(mds, torch, wgpu, seconds, warmup_s, rate, pool_size, budget_g
     window = max(done_at) - warmup_s if done_at else float("nan")
     out.update({"requests": n_req, "solves_per_s": n_req / window if n_req else None,
                 "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "max_ms": max(lat) if lat else None,
-                "peak_arena_gib": info["peak_bytes"] / (1 << 30)})
+                "peak_arena_gib": info["peak_bytes"] / (1 << 30), "batched_launches": info["batches"]})
     del pool
     torch.cuda.empty_cache()
     return out

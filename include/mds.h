@@ -226,9 +226,27 @@ typedef struct mds_batch_job {
 /* Device workspace for the batch (host-only computation). */
 mds_status mds_batch_workspace_size(const mds_batch_job* jobs, int32_t count, int32_t form, size_t* bytes);
 /* Enqueue the batch on `stream` (256-byte aligned workspace of at least the
- * size above, caller-owned, valid until the stream work completes). */
+ * size above, caller-owned, valid until the stream work completes).  tile:
+ * K depth of the G-pass register tile (1, 2 or 4), 0 = the autotuned choice
+ * for the batch's size class (4 if none was tuned). */
 mds_status mds_run_batch(const mds_batch_job* jobs, int32_t count, int32_t form, void* workspace, size_t bytes,
-                         void* stream);
+                         int32_t tile, void* stream);
+/* Autotuner of the batched kernel.  Times every tile shape of the batched
+ * kernel's G-pass (the K depth of the register tile: 1, 2 or 4 MFMA chunks
+ * of operands loaded ahead) on `batch` instances of size n (a synthetic
+ * full-rank distance matrix), records the fastest in a process-wide table
+ * that mds_run_batch consults for that size class of n, form and l, and
+ * also times the plan path on one instance.  Allocates and frees its own
+ * device memory; synchronises `stream`. */
+typedef struct mds_batch_tune {
+  int32_t tile;                /* chosen K depth */
+  int32_t pad_;
+  float batch_ms_per_job[3];   /* per instance, tile 1, 2, 4 */
+  float batch_ms_best;         /* per instance, chosen tile */
+  float plan_ms;               /* one instance through mds_run */
+} mds_batch_tune;
+mds_status mds_autotune_batch(int32_t form, int64_t n, int32_t k, int32_t oversample, int32_t q, int32_t batch,
+                              void* stream, mds_batch_tune* out);
 /* Synchronise `stream` and write the numerical status of each instance of
  * the last batch run in `workspace` (MDS_OK, MDS_ERR_NONFINITE or
  * MDS_ERR_NUMERICAL) to host statuses[count]. */
@@ -243,8 +261,8 @@ mds_status mds_batch_status(const void* workspace, int32_t count, int32_t* statu
  * slot's stream, and retires finished jobs, whose slot and memory then admit
  * the next ones.  Admitted jobs run concurrently on the device.  Each job runs
  * on the server's own copy of the plan, so its result is bit-identical to
- * mds_run of the same plan alone, and the caller may reuse or destroy `plan`
- * right after mds_submit.  Server calls are thread-safe; no call may be in
+ * mds_run of the same plan alone (small jobs: see mds_server_set_batching),
+ * and the caller may reuse or destroy `plan` right after mds_submit.  Server calls are thread-safe; no call may be in
  * flight on a server that is being destroyed. */
 typedef struct mds_server_s* mds_server_t;
 typedef uint64_t mds_ticket;
@@ -258,6 +276,7 @@ typedef struct mds_job_times {
 typedef struct mds_server_info {
   int32_t queued, running, slots, pad_;
   uint64_t completed;
+  uint64_t batches; /* batched launches of small jobs */
   size_t budget_bytes, used_bytes, peak_bytes; /* arena size, bytes held by admitted jobs, peak */
 } mds_server_info;
 
@@ -281,6 +300,22 @@ mds_status mds_wait(mds_server_t server, mds_ticket ticket, mds_status* job_stat
  * completes. */
 mds_status mds_cancel(mds_server_t server, mds_ticket ticket);
 mds_status mds_server_stats(mds_server_t server, mds_server_info* out);
+/* Batching of small jobs: when the queue head has n <= small_n_max and
+ * k + oversample rounded up to 16 <= 64, and at least one more such job of
+ * the same form waits right behind it, the longest run of them (at most
+ * max_batch, 1..256) is admitted together and runs as one mds_run_batch
+ * launch on one slot (results then agree with mds_run to rounding, not bit
+ * for bit); a lone small job runs through the plan path.  small_n_max = 0 turns batching
+ * off.  Default: small_n_max = 2048, max_batch = 32. */
+mds_status mds_server_set_batching(mds_server_t server, int64_t small_n_max, int32_t max_batch);
+/* Pick small_n_max with the autotuner: for n = 128, 256, ... (while the
+ * batched kernel supports it), run mds_autotune_batch at the server's
+ * max_batch and keep batching a size class while a full batch costs less
+ * than a quarter of the plan path's time per instance.  Also leaves the
+ * chosen tile shapes in the process-wide table.  Call while the server is
+ * idle (it times kernels on the null stream). */
+mds_status mds_server_autotune(mds_server_t server, int32_t form, int32_t k, int32_t oversample, int32_t q,
+                               int64_t* small_n_max);
 /* Cancel queued jobs, wait for admitted ones, free the arena and streams. */
 void mds_server_destroy(mds_server_t server);
 

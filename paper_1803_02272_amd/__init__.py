@@ -163,7 +163,7 @@ class Plan:
         return inf.as_dict()
 
 
-def run_batch(problems, form="bf16", stream=None):
+def run_batch(problems, form="bf16", stream=None, tile=0):
     """Batched small instances in one persistent launch (mds_run_batch).
 
     problems: list of dicts with keys D (contiguous cuda float32/float64 n x n),
@@ -194,10 +194,21 @@ def run_batch(problems, form="bf16", stream=None):
     off = (-ws.data_ptr()) % 256
     wp = ctypes.c_void_p(ws.data_ptr() + off)
     sh = _stream_handle(stream)
-    check(L.mds_run_batch(arr, len(problems), fk, wp, nb.value, sh), "mds_run_batch")
+    check(L.mds_run_batch(arr, len(problems), fk, wp, nb.value, int(tile), sh), "mds_run_batch")
     st = (ctypes.c_int32 * max(len(problems), 1))()
     check(L.mds_batch_status(wp, len(problems), st, sh), "mds_batch_status")
     return outs, [int(st[i]) for i in range(len(problems))]
+
+
+def autotune_batch(n, k=20, oversample=10, q=2, form="bf16", batch=32, stream=None):
+    """Time the batched kernel's tile shapes (and the plan path) at size n;
+    the fastest tile is recorded for mds_run_batch.  Returns a dict."""
+    fk = FORMS[form] if isinstance(form, str) else int(form)
+    t = _capi.MdsBatchTune()
+    check(_capi.lib().mds_autotune_batch(fk, int(n), int(k), int(oversample), int(q), int(batch),
+                                         _stream_handle(stream), ctypes.byref(t)), "mds_autotune_batch")
+    return {"tile": t.tile, "batch_ms_per_job": list(t.batch_ms_per_job), "batch_ms_best": t.batch_ms_best,
+            "plan_ms": t.plan_ms}
 
 
 class Server:
@@ -206,11 +217,13 @@ class Server:
     of a Plan on a device D and returns a ticket; ``poll`` never blocks and
     returns None while the job is pending, else (status, times)."""
 
-    def __init__(self, budget_bytes, slots=8):
+    def __init__(self, budget_bytes, slots=8, small_n_max=None, max_batch=None):
         h = ctypes.c_void_p()
         check(_capi.lib().mds_server_create(ctypes.byref(h), int(budget_bytes), int(slots)), "mds_server_create")
         self._h = h
         self._keep = {}  # ticket -> tensors that must outlive the job
+        if small_n_max is not None or max_batch is not None:
+            self.set_batching(2048 if small_n_max is None else small_n_max, 32 if max_batch is None else max_batch)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -267,6 +280,20 @@ class Server:
 
     def cancel(self, ticket):
         check(_capi.lib().mds_cancel(self._h, int(ticket)), "mds_cancel")
+
+    def set_batching(self, small_n_max=2048, max_batch=32):
+        """Small jobs (n <= small_n_max, l_pad <= 64) at the queue head run
+        together as one batched launch; small_n_max=0 turns batching off."""
+        check(_capi.lib().mds_server_set_batching(self._h, int(small_n_max), int(max_batch)),
+              "mds_server_set_batching")
+
+    def autotune(self, form="bf16", k=20, oversample=10, q=2):
+        """Choose the batching threshold (and batched tile shapes) by timing; returns small_n_max."""
+        fk = FORMS[form] if isinstance(form, str) else int(form)
+        v = ctypes.c_int64()
+        check(_capi.lib().mds_server_autotune(self._h, fk, int(k), int(oversample), int(q), ctypes.byref(v)),
+              "mds_server_autotune")
+        return int(v.value)
 
     def stats(self):
         inf = _capi.MdsServerInfo()

@@ -79,13 +79,19 @@ class MdsBatchJob(ctypes.Structure):
                 ("q", ctypes.c_int32), ("d_dtype", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
+class MdsBatchTune(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("pad_", ctypes.c_int32), ("batch_ms_per_job", ctypes.c_float * 3),
+                ("batch_ms_best", ctypes.c_float), ("plan_ms", ctypes.c_float)]
+
+
 class MdsJobTimes(ctypes.Structure):
     _fields_ = [("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
 
 
 class MdsServerInfo(ctypes.Structure):
     _fields_ = [("queued", ctypes.c_int32), ("running", ctypes.c_int32), ("slots", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("completed", ctypes.c_uint64), ("budget_bytes", ctypes.c_size_t),
+                ("pad_", ctypes.c_int32), ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("budget_bytes", ctypes.c_size_t),
                 ("used_bytes", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t)]
 
     def as_dict(self):
@@ -112,7 +118,12 @@ SIGNATURES = {
     "mds_batch_workspace_size": (ctypes.c_int, [ctypes.POINTER(MdsBatchJob), ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_size_t)]),
     "mds_run_batch": (ctypes.c_int, [ctypes.POINTER(MdsBatchJob), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
-                                     ctypes.c_size_t, ctypes.c_void_p]),
+                                     ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p]),
+    "mds_autotune_batch": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.POINTER(MdsBatchTune)]),
+    "mds_server_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "mds_batch_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.c_void_p]),
     "mds_server_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, ctypes.c_int32]),
@@ -124,6 +135,7 @@ SIGNATURES = {
                                 ctypes.POINTER(MdsJobTimes)]),
     "mds_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "mds_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MdsServerInfo)]),
+    "mds_server_set_batching": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32]),
     "mds_server_destroy": (None, [ctypes.c_void_p]),
     "mds_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mds_last_error": (ctypes.c_char_p, []),

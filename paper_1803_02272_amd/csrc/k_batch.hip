@@ -18,6 +18,8 @@
 // results agree with a single-instance run to rounding, not bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -88,14 +90,96 @@ __device__ __forceinline__ bf16_t to_bf16(float f) {
   return (bf16_t)(u >> 16);
 }
 
-__device__ __forceinline__ double load_d(const BJob& J, int64_t idx) {
-  return J.d_is_f64 ? ((const double*)J.D)[idx] : (double)((const float*)J.D)[idx];
+// ---- centring sums with many loads in flight per thread ---------------------
+constexpr int kUnroll = 16;  // independent loads issued before they are used
+
+// c_j (column means of d^2): thread j walks down its column kUnroll rows at
+// a time (each row access is coalesced over the workgroup).
+template <typename DT>
+__device__ void col_means(const DT* __restrict__ D, int64_t n, int64_t np, double* c) {
+  for (int64_t j = threadIdx.x; j < np; j += kBT) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (j < n) {
+      for (int64_t i0 = 0; i0 < n; i0 += kUnroll) {
+        double d[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) d[u] = (i0 + u < n) ? (double)D[(i0 + u) * n + j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) s[u & 3] += d[u] * d[u];
+      }
+    }
+    c[j] = j < n ? ((s[0] + s[1]) + (s[2] + s[3])) / (double)n : 0.0;
+  }
+}
+
+// r_i (row means of d^2), one wave per row; returns this thread's share of sum_i r_i.
+template <typename DT>
+__device__ double row_means(const DT* __restrict__ D, int64_t n, int64_t np, double* r) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double part = 0.0;
+  for (int64_t i = wave; i < np; i += kBT / 64) {
+    double s = 0.0;
+    if (i < n) {
+      const DT* row = D + i * n;
+      for (int64_t j0 = 0; j0 < n; j0 += 64 * 8) {
+        double d[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t j = j0 + lane + 64 * u;
+          d[u] = j < n ? (double)row[j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += d[u] * d[u];
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+      r[i] = i < n ? s / (double)n : 0.0;
+      part += i < n ? s / (double)n : 0.0;
+    }
+  }
+  return part;
+}
+
+// G in the pass dtype (rows and columns >= n zero), 8 entries per lane in flight.
+template <int FORM, typename DT>
+__device__ void write_g(const DT* __restrict__ D, int64_t n, int64_t np, const double* r, const double* c, double m,
+                        const float* hc, const float* hr, void* G) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t i = wave; i < np; i += kBT / 64) {
+    const double ri = i < n ? r[i] : 0.0;
+    const float hri = hr[i];
+    for (int64_t j0 = 0; j0 < np; j0 += 64 * 8) {
+      DT d[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t j = j0 + lane + 64 * u;
+        d[u] = (i < n && j < n) ? D[i * n + j] : (DT)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t j = j0 + lane + 64 * u;
+        if (j >= np) continue;
+        const bool in = i < n && j < n;
+        const double dd = (double)d[u];
+        if constexpr (FORM == MDS_FORM_FP64) {
+          ((double*)G)[i * np + j] = in ? -0.5 * (((dd * dd - c[j]) - ri) + m) : 0.0;
+        } else if constexpr (FORM == MDS_FORM_FP32) {
+          const float d2 = sizeof(DT) == 8 ? (float)(dd * dd) : (float)d[u] * (float)d[u];
+          ((float*)G)[i * np + j] = in ? __builtin_fmaf(-0.5f, d2, hc[j] + hri) : 0.0f;
+        } else {
+          ((bf16_t*)G)[i * np + j] = in ? to_bf16((float)(-0.5 * (((dd * dd - c[j]) - ri) + m))) : (bf16_t)0;
+        }
+      }
+    }
+  }
 }
 
 // ---- MFMA G-pass: Yt (fp64, l_pad x np) = (G X)^T --------------------------
 // GK: operand kind.  FROM_D: A entries recentred from D in fp32 (projection
 // of the bf16 form), else read from the stored G.
-template <int GK, bool FROM_D>
+template <int GK, bool FROM_D, int KU>
 __device__ void block_gpass(const BJob& J, const void* G, const void* Xt, double* Yt, const float* hc,
                             const float* hr) {
 #pragma clang fp contract(off)
@@ -116,49 +200,63 @@ __device__ void block_gpass(const BJob& J, const void* G, const void* Xt, double
     for (int cg = 0; cg < kBMaxL / 16; ++cg)
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[cg][e] = 0;
-    for (int64_t k0 = 0; k0 < np; k0 += KS) {
-      const int64_t kk = k0 + (lane >> 4) * E;
-      u32x4 a;
-      if constexpr (FROM_D) {
-        float g[4];
+    // KU chunks (the K depth of the register tile) are loaded before the
+    // MFMAs that use them; KU is the tile shape the autotuner picks
+    for (int64_t k0 = 0; k0 < np; k0 += KU * KS) {
+      u32x4 a[KU], b[KU][kBMaxL / 16];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int64_t col = kk + t;
-          float v = 0.0f;
-          if (row < n && col < n) {
-            float d2;
-            if (J.d_is_f64) {
-              const double d = ((const double*)J.D)[row * n + col];
-              d2 = (float)(d * d);
-            } else {
-              const float d = ((const float*)J.D)[row * n + col];
-              d2 = d * d;
+      for (int u = 0; u < KU; ++u) {
+        const int64_t kk = k0 + u * KS + (lane >> 4) * E;
+        const bool live = k0 + u * KS < np;  // np is a multiple of 64, KS divides 64
+        if constexpr (FROM_D) {
+          float g[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int64_t col = kk + t;
+            float v = 0.0f;
+            if (live && row < n && col < n) {
+              float d2;
+              if (J.d_is_f64) {
+                const double d = ((const double*)J.D)[row * n + col];
+                d2 = (float)(d * d);
+              } else {
+                const float d = ((const float*)J.D)[row * n + col];
+                d2 = d * d;
+              }
+              v = __builtin_fmaf(-0.5f, d2, hc[col] + hr[row]);
             }
-            v = __builtin_fmaf(-0.5f, d2, hc[col] + hr[row]);
+            g[t] = v;
           }
-          g[t] = v;
+          __builtin_memcpy(&a[u], g, 16);
+        } else {
+          a[u] = live ? *reinterpret_cast<const u32x4*>(Gp + row * np + kk) : u32x4{0, 0, 0, 0};
         }
-        __builtin_memcpy(&a, g, 16);
-      } else {
-        a = *reinterpret_cast<const u32x4*>(Gp + row * np + kk);
+#pragma unroll
+        for (int cg = 0; cg < kBMaxL / 16; ++cg)
+          b[u][cg] = (live && cg < CG) ? *reinterpret_cast<const u32x4*>(Xp + (int64_t)(cg * 16 + (lane & 15)) * np + kk)
+                                       : u32x4{0, 0, 0, 0};
       }
 #pragma unroll
-      for (int cg = 0; cg < kBMaxL / 16; ++cg) {
-        if (cg >= CG) break;
-        const u32x4 b = *reinterpret_cast<const u32x4*>(Xp + (int64_t)(cg * 16 + (lane & 15)) * np + kk);
-        if constexpr (GK == GK_BF16) {
-          acc[cg] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                            __builtin_bit_cast(bf16x8, b), acc[cg], 0, 0, 0);
-        } else if constexpr (GK == GK_F32) {
+      for (int u = 0; u < KU; ++u) {
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
-            acc[cg] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[t]), __uint_as_float(b[t]), acc[cg],
-                                                           0, 0, 0);
-        } else {
-          const double a0 = __hiloint2double((int)a.y, (int)a.x), a1 = __hiloint2double((int)a.w, (int)a.z);
-          const double b0 = __hiloint2double((int)b.y, (int)b.x), b1 = __hiloint2double((int)b.w, (int)b.z);
-          acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[cg], 0, 0, 0);
-          acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[cg], 0, 0, 0);
+        for (int cg = 0; cg < kBMaxL / 16; ++cg) {
+          if (cg >= CG) break;
+          if constexpr (GK == GK_BF16) {
+            acc[cg] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[u]),
+                                                              __builtin_bit_cast(bf16x8, b[u][cg]), acc[cg], 0, 0, 0);
+          } else if constexpr (GK == GK_F32) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              acc[cg] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[u][t]), __uint_as_float(b[u][cg][t]),
+                                                             acc[cg], 0, 0, 0);
+          } else {
+            const double a0 = __hiloint2double((int)a[u].y, (int)a[u].x);
+            const double a1 = __hiloint2double((int)a[u].w, (int)a[u].z);
+            const double b0 = __hiloint2double((int)b[u][cg].y, (int)b[u][cg].x);
+            const double b1 = __hiloint2double((int)b[u][cg].w, (int)b[u][cg].z);
+            acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[cg], 0, 0, 0);
+            acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[cg], 0, 0, 0);
+          }
         }
       }
     }
@@ -187,9 +285,18 @@ __device__ void block_gram(const double* At, const double* Bt, int64_t np, int l
     doublex4_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
     const double* pa = At + (int64_t)(ta * 16 + (lane & 15)) * np + (lane >> 4);
     const double* pb = Bt + (int64_t)(tb * 16 + (lane & 15)) * np + (lane >> 4);
-    for (int64_t k0 = 0; k0 < np; k0 += 8) {
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[k0], pb[k0], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[k0 + 4], pb[k0 + 4], acc1, 0, 0, 0);
+    for (int64_t k0 = 0; k0 < np; k0 += 32) {  // np is a multiple of 64
+      double xa[8], xb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        xa[u] = pa[k0 + 4 * u];
+        xb[u] = pb[k0 + 4 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; u += 2) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xb[u], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u + 1], xb[u + 1], acc1, 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) M[(ta * 16 + (lane >> 4) + 4 * r) * ldm + tb * 16 + (lane & 15)] = acc0[r] + acc1[r];
@@ -224,6 +331,7 @@ __device__ void block_apply(const double* In, double* Out, int64_t np, int64_t n
 struct BShared {
   JacobiShared sh;
   double M[kBMaxL * kBMaxL];
+  double V[kBMaxL * kBMaxL];  // eigenvectors of B (gfx950: up to 160 KB of LDS per workgroup)
   double P[kBMaxL * kNB];
   double wdiag[kBMaxL];
   double scl[kBMaxL];
@@ -370,7 +478,7 @@ __device__ void block_sign(BShared& S, double* C, int64_t n, int k, int r) {
     for (int64_t i = tid; i < n; i += kBT) C[i * k + r] = -C[i * k + r];
 }
 
-template <int FORM>
+template <int FORM, int KU>
 __global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
 #pragma clang fp contract(off)
   if ((int)blockIdx.x >= tab.count) return;
@@ -398,35 +506,13 @@ __global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
     *J.st = z;
   }
   // ---- centring sums (fp64): column means by thread, row means by wave ----
-  for (int64_t j = tid; j < np; j += kBT) {
-    double s0 = 0.0, s1 = 0.0;
-    if (j < n) {
-      int64_t i = 0;
-      for (; i + 1 < n; i += 2) {
-        const double d0 = load_d(J, i * n + j), d1 = load_d(J, (i + 1) * n + j);
-        s0 += d0 * d0;
-        s1 += d1 * d1;
-      }
-      if (i < n) {
-        const double d = load_d(J, i * n + j);
-        s0 += d * d;
-      }
-    }
-    c[j] = j < n ? (s0 + s1) / (double)n : 0.0;
-  }
-  double rsum_part = 0.0;
-  for (int64_t i = wave; i < np; i += kBT / 64) {
-    double s = 0.0;
-    if (i < n)
-      for (int64_t j = lane; j < n; j += 64) {
-        const double d = load_d(J, i * n + j);
-        s += d * d;
-      }
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) {
-      r[i] = i < n ? s / (double)n : 0.0;
-      rsum_part += i < n ? s / (double)n : 0.0;
-    }
+  double rsum_part;
+  if (J.d_is_f64) {
+    col_means<double>((const double*)J.D, n, np, c);
+    rsum_part = row_means<double>((const double*)J.D, n, np, r);
+  } else {
+    col_means<float>((const float*)J.D, n, np, c);
+    rsum_part = row_means<float>((const float*)J.D, n, np, r);
   }
   const double m = block_sum<kBT>(rsum_part, S.sh.red) / (double)n;
   __syncthreads();
@@ -437,19 +523,10 @@ __global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
   }
   __syncthreads();
   // ---- G in the pass dtype ------------------------------------------------
-  for (int64_t i = wave; i < np; i += kBT / 64)
-    for (int64_t j = lane; j < np; j += 64) {
-      const bool in = i < n && j < n;
-      const double d = in ? load_d(J, i * n + j) : 0.0;
-      if constexpr (FORM == MDS_FORM_FP64) {
-        ((double*)G)[i * np + j] = in ? -0.5 * (((d * d - c[j]) - r[i]) + m) : 0.0;
-      } else if constexpr (FORM == MDS_FORM_FP32) {
-        const float d2 = J.d_is_f64 ? (float)(d * d) : (float)d * (float)d;
-        ((float*)G)[i * np + j] = in ? __builtin_fmaf(-0.5f, d2, hc[j] + hr[i]) : 0.0f;
-      } else {
-        ((bf16_t*)G)[i * np + j] = in ? to_bf16((float)(-0.5 * (((d * d - c[j]) - r[i]) + m))) : (bf16_t)0;
-      }
-    }
+  if (J.d_is_f64)
+    write_g<FORM, double>((const double*)J.D, n, np, r, c, m, hc, hr, G);
+  else
+    write_g<FORM, float>((const float*)J.D, n, np, r, c, m, hc, hr, G);
   // ---- Omega in the range operand dtype (transposed, l_pad x np) ------------
   for (int64_t e = tid; e < np * (l_pad / 4); e += kBT) {
     const int64_t i = e % np, b = e / np;
@@ -471,14 +548,14 @@ __global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
   // ---- range finder ---------------------------------------------------------
   const int passes = 2 * J.q + 1;
   for (int it = 0; it < passes; ++it) {
-    block_gpass<GK, false>(J, G, X, Yt, hc, hr);
+    block_gpass<GK, false, KU>(J, G, X, Yt, hc, hr);
     block_orth(S, J, Yt, Qt, Vg, X, it == passes - 1 ? PK : GK);
   }
   // ---- projection B = Q^T G Q ------------------------------------------------
   if constexpr (FORM == MDS_FORM_BF16)
-    block_gpass<GK_F32, true>(J, nullptr, X, Yt, hc, hr);
+    block_gpass<GK_F32, true, KU>(J, nullptr, X, Yt, hc, hr);
   else
-    block_gpass<PK, false>(J, G, X, Yt, hc, hr);
+    block_gpass<PK, false, KU>(J, G, X, Yt, hc, hr);
   __syncthreads();
   block_gram(Qt, Yt, np, l_pad, M, kBMaxL);
   __syncthreads();
@@ -486,15 +563,17 @@ __global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
     const int i = e / kBMaxL, j = e % kBMaxL;
     double v = 0.0;
     if (i < l && j < l) v = 0.5 * (M[i * kBMaxL + j] + M[j * kBMaxL + i]);
-    Vg[e] = v;        // symmetrised B staged in global scratch
+    S.V[e] = v;  // symmetrised B staged in V
   }
   __syncthreads();
-  for (int e = tid; e < kBMaxL * kBMaxL; e += kBT) M[e] = Vg[e];
-  for (int e = tid; e < kBMaxL * kBMaxL; e += kBT) Vg[e] = (e / kBMaxL == e % kBMaxL) ? 1.0 : 0.0;
+  for (int e = tid; e < kBMaxL * kBMaxL; e += kBT) {
+    M[e] = S.V[e];
+    S.V[e] = (e / kBMaxL == e % kBMaxL) ? 1.0 : 0.0;
+  }
   __syncthreads();
   // ---- eigenpairs of B ------------------------------------------------------
   int rounds = 0;
-  const int sweeps = jacobi<kBT>(M, kBMaxL, Vg, kBMaxL, (double2*)nullptr, l + (l & 1), S.sh, &rounds);
+  const int sweeps = jacobi<kBT>(M, kBMaxL, S.V, kBMaxL, (double2*)nullptr, l + (l & 1), S.sh, &rounds);
   __syncthreads();
   for (int i = tid; i < l; i += kBT) S.th[i] = M[i * kBMaxL + i];
   __syncthreads();
@@ -506,7 +585,7 @@ __global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
     double v = 0.0;
     if (a < l && rr < k) {
       const double thr = S.th[S.perm[rr]];
-      v = Vg[a * kBMaxL + S.perm[rr]] * sqrt(fmax(thr, 0.0));
+      v = S.V[a * kBMaxL + S.perm[rr]] * sqrt(fmax(thr, 0.0));
     }
     M[e] = v;
   }
@@ -538,7 +617,59 @@ __global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
 
 using namespace mds;
 
+int mds::batch_max_l() { return kBMaxL; }
+int64_t mds::batch_max_n() { return kBMaxN; }
+
 namespace {
+
+template <int FORM>
+void launch_form(int ku, const BTable& tab, hipStream_t s) {
+  switch (ku) {
+    case 1: hipLaunchKernelGGL((k_batch<FORM, 1>), dim3(tab.count), dim3(kBT), 0, s, tab); break;
+    case 2: hipLaunchKernelGGL((k_batch<FORM, 2>), dim3(tab.count), dim3(kBT), 0, s, tab); break;
+    default: hipLaunchKernelGGL((k_batch<FORM, 4>), dim3(tab.count), dim3(kBT), 0, s, tab); break;
+  }
+}
+
+void launch_batch(int form, int ku, const BTable& tab, hipStream_t s) {
+  if (form == MDS_FORM_FP64)
+    launch_form<MDS_FORM_FP64>(ku, tab, s);
+  else if (form == MDS_FORM_FP32)
+    launch_form<MDS_FORM_FP32>(ku, tab, s);
+  else
+    launch_form<MDS_FORM_BF16>(ku, tab, s);
+}
+
+// Process-wide autotuning table: (form, size class of n_pad, l_pad) -> KU.
+std::mutex g_tune_mu;
+std::map<uint64_t, int> g_tune;
+constexpr int kDefaultKU = 4;
+constexpr int kKUs[] = {1, 2, 4};
+
+uint64_t tune_key(int form, int64_t np, int l_pad) {
+  int cls = 0;
+  while ((int64_t(64) << cls) < np) ++cls;  // n_pad <= 64 * 2^cls
+  return ((uint64_t)form << 32) | ((uint64_t)cls << 16) | (uint64_t)l_pad;
+}
+
+int tuned_ku(int form, int64_t np, int l_pad) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tune.find(tune_key(form, np, l_pad));
+  return it == g_tune.end() ? kDefaultKU : it->second;
+}
+
+// Symmetric matrix with zero diagonal and entries in [1, 2) from a hash of
+// (min(i, j), max(i, j)): a full-rank G for timing the batched kernel.
+__global__ void k_synth_d(float* D, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t i = e / n, j = e % n;
+  uint64_t h = (uint64_t)(i < j ? i : j) * 0x9E3779B97F4A7C15ull ^ (uint64_t)(i < j ? j : i) * 0xC2B2AE3D27D4EB4Full;
+  h ^= h >> 29;
+  h *= 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 32;
+  D[e] = i == j ? 0.0f : 1.0f + (float)(h >> 40) * 0x1p-24f;
+}
 
 mds_status batch_check(const mds_batch_job* jobs, int32_t count, int32_t form) {
   if (!jobs || count < 0) return fail(MDS_ERR_INVALID_ARG, "NULL jobs or count < 0");
@@ -577,9 +708,10 @@ mds_status mds_batch_workspace_size(const mds_batch_job* jobs, int32_t count, in
 }
 
 mds_status mds_run_batch(const mds_batch_job* jobs, int32_t count, int32_t form, void* workspace, size_t bytes,
-                         void* stream) {
+                         int32_t tile, void* stream) {
   mds_status st = batch_check(jobs, count, form);
   if (st != MDS_OK) return st;
+  if (tile != 0 && tile != 1 && tile != 2 && tile != 4) return fail(MDS_ERR_INVALID_ARG, "tile = %d", tile);
   size_t need = 0;
   mds_batch_workspace_size(jobs, count, form, &need);
   if (!workspace || bytes < need || ((uintptr_t)workspace % 256) != 0)
@@ -617,17 +749,113 @@ mds_status mds_run_batch(const mds_batch_job* jobs, int32_t count, int32_t form,
       J.d_is_f64 = b.d_dtype == MDS_DTYPE_F64;
       off += job_bytes(b, form);
     }
-    hipStream_t s = (hipStream_t)stream;
-    if (form == MDS_FORM_FP64)
-      hipLaunchKernelGGL(k_batch<MDS_FORM_FP64>, dim3(tab.count), dim3(kBT), 0, s, tab);
-    else if (form == MDS_FORM_FP32)
-      hipLaunchKernelGGL(k_batch<MDS_FORM_FP32>, dim3(tab.count), dim3(kBT), 0, s, tab);
-    else
-      hipLaunchKernelGGL(k_batch<MDS_FORM_BF16>, dim3(tab.count), dim3(kBT), 0, s, tab);
+    int64_t np_max = 0;
+    int lp_max = 0;
+    for (int t = 0; t < tab.count; ++t) {
+      np_max = tab.job[t].n_pad > np_max ? tab.job[t].n_pad : np_max;
+      lp_max = tab.job[t].l_pad > lp_max ? tab.job[t].l_pad : lp_max;
+    }
+    const int ku = tile > 0 ? tile : tuned_ku(form, np_max, lp_max);
+    launch_batch(form, ku, tab, (hipStream_t)stream);
     st = hip_check(hipGetLastError(), "k_batch launch");
     if (st != MDS_OK) return st;
   }
   return MDS_OK;
+}
+
+mds_status mds_autotune_batch(int32_t form, int64_t n, int32_t k, int32_t oversample, int32_t q, int32_t batch,
+                              void* stream, mds_batch_tune* out) {
+  if (!out || batch < 1 || batch > 4096) return fail(MDS_ERR_INVALID_ARG, "NULL out or batch outside [1, 4096]");
+  mds_batch_job probe{};
+  probe.D = (void*)256;
+  probe.coords = (double*)256;
+  probe.eigvals = (double*)256;
+  probe.n = n;
+  probe.k = k;
+  probe.oversample = oversample;
+  probe.q = q;
+  mds_status st = batch_check(&probe, 1, form);
+  if (st != MDS_OK) return st;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(MDS_ERR_NO_DEVICE, "no HIP device available");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  float* D = nullptr;
+  double* outs = nullptr;
+  void* ws = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  mds_plan_t plan = nullptr;
+  std::vector<mds_batch_job> jobs((size_t)batch, probe);
+  size_t wsb = 0;
+  const size_t per = (size_t)n * k + k;
+  auto cleanup = [&](mds_status r) {
+    if (plan) mds_destroy(plan);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(D);
+    (void)hipFree(outs);
+    (void)hipFree(ws);
+    return r;
+  };
+  if (hipMalloc((void**)&D, (size_t)n * n * 4) != hipSuccess ||
+      hipMalloc((void**)&outs, per * batch * sizeof(double)) != hipSuccess)
+    return cleanup(fail(MDS_ERR_OOM, "autotune allocation failed"));
+  for (int32_t b = 0; b < batch; ++b) {
+    jobs[b].D = D;
+    jobs[b].coords = outs + per * b;
+    jobs[b].eigvals = outs + per * b + (size_t)n * k;
+    jobs[b].d_dtype = MDS_DTYPE_F32;
+    jobs[b].seed = (uint64_t)b;
+  }
+  mds_batch_workspace_size(jobs.data(), batch, form, &wsb);
+  if (hipMalloc(&ws, wsb) != hipSuccess) return cleanup(fail(MDS_ERR_OOM, "autotune workspace allocation failed"));
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return cleanup(fail(MDS_ERR_HIP, "event creation failed"));
+  hipLaunchKernelGGL(k_synth_d, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, D, n);
+  auto time_ms = [&](auto&& run, float* ms) -> mds_status {
+    mds_status r = run();  // warm-up
+    if (r != MDS_OK) return r;
+    float best = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      (void)hipEventRecord(e0, s);
+      r = run();
+      if (r != MDS_OK) return r;
+      (void)hipEventRecord(e1, s);
+      r = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+      if (r != MDS_OK) return r;
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      best = t < best ? t : best;
+    }
+    *ms = best;
+    return MDS_OK;
+  };
+  out->tile = kDefaultKU;
+  float best = 1e30f;
+  for (int v = 0; v < 3; ++v) {
+    float ms = 0.f;
+    st = time_ms([&] { return mds_run_batch(jobs.data(), batch, form, ws, wsb, kKUs[v], stream); }, &ms);
+    if (st != MDS_OK) return cleanup(st);
+    out->batch_ms_per_job[v] = ms / batch;
+    if (ms < best) {
+      best = ms;
+      out->tile = kKUs[v];
+    }
+  }
+  out->batch_ms_best = best / batch;
+  // the plan path on one instance, for the batching decision
+  mds_opts o = {form, MDS_DTYPE_F32, 0, 0};
+  st = mds_plan_ex(&plan, n, k, oversample, q, 0, &o);
+  if (st != MDS_OK) return cleanup(st);
+  st = time_ms([&] { return mds_run(plan, D, outs, outs + (size_t)n * k, stream); }, &out->plan_ms);
+  if (st != MDS_OK) return cleanup(st);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[tune_key(form, rup(n, kBPad), (int)rup((int64_t)k + oversample, 16))] = out->tile;
+  }
+  return cleanup(MDS_OK);
 }
 
 mds_status mds_batch_status(const void* workspace, int32_t count, int32_t* statuses, void* stream) {

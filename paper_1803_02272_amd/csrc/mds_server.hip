@@ -10,6 +10,13 @@
 // jobs therefore overlap on the device: a small job runs beside a large one
 // instead of behind it.  Each job runs on its own copy of the caller's plan,
 // so its result is bit-identical to mds_run of the same plan alone.
+//
+// Small jobs are batched: when the queue head is small (n <= small_n_max and
+// l_pad <= 64) and at least one more small job of the same form waits right
+// behind it, the longest such run (up to max_batch) is admitted together and
+// runs as one persistent launch of the batched kernel (mds_run_batch), one
+// workgroup per job.  A lone small job takes the plan path, whose latency is
+// lower.  Batched results agree with mds_run to rounding, not bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -95,12 +102,34 @@ struct Job {
   Clock::time_point t_submit, t_start, t_done;
 };
 
+constexpr int kMaxGroup = 256;  // largest batch of small jobs
+
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  DevStatus* host_status = nullptr;  // pinned
-  Job* job = nullptr;
+  DevStatus* host_status = nullptr;  // pinned, kMaxGroup entries
+  std::vector<Job*> group;           // jobs running on this slot (empty: free)
+  bool batched = false;
+  size_t ws_off = 0, ws_bytes = 0;
 };
+
+bool batchable(const Job* j, int64_t small_n_max) {
+  return j->plan->n <= small_n_max && j->plan->l_pad <= batch_max_l() && j->plan->n <= batch_max_n();
+}
+
+mds_batch_job batch_entry(const Job* j) {
+  mds_batch_job b{};
+  b.D = j->D;
+  b.coords = j->coords;
+  b.eigvals = j->eigvals;
+  b.n = j->plan->n;
+  b.k = j->plan->k;
+  b.oversample = j->plan->p;
+  b.q = j->plan->q;
+  b.d_dtype = j->plan->d_dtype;
+  b.seed = j->plan->seed;
+  return b;
+}
 
 }  // namespace
 
@@ -110,6 +139,9 @@ struct mds_server_s {
   void* arena_ptr = nullptr;
   Arena* arena = nullptr;
   std::vector<Slot> slots;
+  int64_t small_n_max = 2048;  // batching threshold (0: never batch)
+  int max_batch = 32;
+  uint64_t batches = 0;        // batched launches so far
   std::deque<Job*> queue;
   std::vector<Job*> running;
   std::unordered_map<mds_ticket, Job*> jobs;
@@ -129,19 +161,41 @@ void free_job(Job* j) {
   delete j;
 }
 
-// Enqueue the whole run of j on its slot; called by the worker without the lock.
-mds_status launch(mds_server_s* S, Job* j) {
-  Slot& sl = S->slots[j->slot];
-  mds_status st = mds_set_workspace(j->plan, static_cast<char*>(S->arena_ptr) + j->ws_off, j->ws_bytes);
-  if (st == MDS_OK) st = run_plan(j->plan, j->D, j->coords, j->eigvals, sl.stream, MDS_STAGE_ALL, 0);
-  if (st == MDS_OK)
-    st = hip_check(hipMemcpyAsync(sl.host_status, j->plan->at<void>(j->plan->status), sizeof(DevStatus),
-                                  hipMemcpyDeviceToHost, sl.stream),
-                   "status copy");
+// Enqueue the slot's group (one job through the plan path, or a batch of
+// small jobs through the batched kernel); called by the worker without the lock.
+mds_status launch(mds_server_s* S, Slot& sl) {
+  char* ws = static_cast<char*>(S->arena_ptr) + sl.ws_off;
+  mds_status st = MDS_OK;
+  if (sl.batched) {
+    std::vector<mds_batch_job> bj;
+    for (Job* j : sl.group) bj.push_back(batch_entry(j));
+    st = mds_run_batch(bj.data(), (int32_t)bj.size(), sl.group[0]->plan->form, ws, sl.ws_bytes, 0, sl.stream);
+    if (st == MDS_OK)
+      st = hip_check(hipMemcpyAsync(sl.host_status, ws, bj.size() * sizeof(DevStatus), hipMemcpyDeviceToHost,
+                                    sl.stream),
+                     "status copy");
+  } else {
+    Job* j = sl.group[0];
+    st = mds_set_workspace(j->plan, ws, sl.ws_bytes);
+    if (st == MDS_OK) st = run_plan(j->plan, j->D, j->coords, j->eigvals, sl.stream, MDS_STAGE_ALL, 0);
+    if (st == MDS_OK)
+      st = hip_check(hipMemcpyAsync(sl.host_status, j->plan->at<void>(j->plan->status), sizeof(DevStatus),
+                                    hipMemcpyDeviceToHost, sl.stream),
+                     "status copy");
+  }
   // the event is recorded whatever happened so that retirement waits for
-  // every kernel this run managed to enqueue
+  // every kernel this group managed to enqueue
   const mds_status ev = hip_check(hipEventRecord(sl.done, sl.stream), "hipEventRecord");
   return st != MDS_OK ? st : ev;
+}
+
+// Workspace bytes of the first `count` jobs of grp as one batch.
+size_t batch_bytes(const std::vector<Job*>& grp, size_t count) {
+  std::vector<mds_batch_job> bj;
+  for (size_t i = 0; i < count; ++i) bj.push_back(batch_entry(grp[i]));
+  size_t bytes = 0;
+  if (mds_batch_workspace_size(bj.data(), (int32_t)count, grp[0]->plan->form, &bytes) != MDS_OK) return 0;
+  return bytes;
 }
 
 void worker_main(mds_server_s* S) {
@@ -150,29 +204,34 @@ void worker_main(mds_server_s* S) {
   for (;;) {
     bool progressed = false;
     // retire finished jobs
-    for (size_t i = 0; i < S->running.size();) {
-      Job* j = S->running[i];
-      Slot& sl = S->slots[j->slot];
+    for (size_t si = 0; si < S->slots.size(); ++si) {
+      Slot& sl = S->slots[si];
+      if (sl.group.empty()) continue;
       const hipError_t q = hipEventQuery(sl.done);
-      if (q == hipErrorNotReady) {
-        ++i;
-        continue;
-      }
-      if (j->result == MDS_PENDING) {
-        if (q != hipSuccess) {
-          j->result = fail(MDS_ERR_HIP, "job %llu: %s", (unsigned long long)j->id, hipGetErrorString(q));
-        } else {
-          const DevStatus& d = *sl.host_status;
-          j->result = d.nonfinite ? MDS_ERR_NONFINITE : (d.jacobi_unconv ? MDS_ERR_NUMERICAL : MDS_OK);
+      if (q == hipErrorNotReady) continue;
+      const Clock::time_point now = Clock::now();
+      for (size_t g = 0; g < sl.group.size(); ++g) {
+        Job* j = sl.group[g];
+        if (j->result == MDS_PENDING) {
+          if (q != hipSuccess) {
+            j->result = fail(MDS_ERR_HIP, "job %llu: %s", (unsigned long long)j->id, hipGetErrorString(q));
+          } else {
+            const DevStatus& d = sl.host_status[sl.batched ? g : 0];
+            j->result = d.nonfinite ? MDS_ERR_NONFINITE : (d.jacobi_unconv ? MDS_ERR_NUMERICAL : MDS_OK);
+          }
         }
+        j->t_done = now;
+        j->state = kDone;
+        ++S->completed;
+        for (size_t r = 0; r < S->running.size(); ++r)
+          if (S->running[r] == j) {
+            S->running[r] = S->running.back();
+            S->running.pop_back();
+            break;
+          }
       }
-      j->t_done = Clock::now();
-      j->state = kDone;
-      S->arena->release(j->ws_off, j->ws_bytes);
-      sl.job = nullptr;
-      S->running[i] = S->running.back();
-      S->running.pop_back();
-      ++S->completed;
+      S->arena->release(sl.ws_off, sl.ws_bytes);
+      sl.group.clear();
       progressed = true;
     }
     if (progressed) S->done_cv.notify_all();
@@ -180,26 +239,63 @@ void worker_main(mds_server_s* S) {
     // admit from the queue head while a slot and arena room are free
     while (!S->queue.empty() && !S->stop) {
       int slot = -1;
-      for (size_t s = 0; s < S->slots.size(); ++s)
-        if (!S->slots[s].job) {
-          slot = (int)s;
+      for (size_t si = 0; si < S->slots.size(); ++si)
+        if (S->slots[si].group.empty()) {
+          slot = (int)si;
           break;
         }
       if (slot < 0) break;
-      Job* j = S->queue.front();
-      size_t off = 0;
-      if (!S->arena->alloc(j->ws_bytes, &off)) break;
-      S->queue.pop_front();
-      j->ws_off = off;
-      j->slot = slot;
-      j->state = kRunning;
-      j->t_start = Clock::now();
-      S->slots[slot].job = j;
-      S->running.push_back(j);
+      Job* head = S->queue.front();
+      std::vector<Job*> grp;
+      size_t bytes = 0, off = 0;
+      bool batched = false;
+      if (S->small_n_max > 0 && batchable(head, S->small_n_max)) {
+        for (Job* j : S->queue) {
+          if ((int)grp.size() >= S->max_batch || !batchable(j, S->small_n_max) || j->plan->form != head->plan->form)
+            break;
+          grp.push_back(j);
+        }
+        // shrink the batch until it fits the free arena
+        size_t count = grp.size();
+        for (; count > 0; --count) {
+          bytes = batch_bytes(grp, count);
+          if (bytes && S->arena->alloc(bytes, &off)) break;
+        }
+        if (count > 1) {
+          grp.resize(count);
+          batched = true;
+        } else {
+          // a lone small job, or no batch that fits: the plan path (lower
+          // latency; its workspace fits the budget, checked at submit)
+          if (count == 1) S->arena->release(off, bytes);
+          grp.assign(1, head);
+          bytes = head->ws_bytes;
+          if (!S->arena->alloc(bytes, &off)) break;
+        }
+      } else {
+        bytes = head->ws_bytes;
+        if (!S->arena->alloc(bytes, &off)) break;
+        grp.push_back(head);
+      }
+      for (size_t g = 0; g < grp.size(); ++g) S->queue.pop_front();
+      Slot& sl = S->slots[slot];
+      sl.group = grp;
+      sl.batched = batched;
+      sl.ws_off = off;
+      sl.ws_bytes = bytes;
+      const Clock::time_point now = Clock::now();
+      for (Job* j : grp) {
+        j->slot = slot;
+        j->state = kRunning;
+        j->t_start = now;
+        S->running.push_back(j);
+      }
+      if (batched) ++S->batches;
       lk.unlock();
-      const mds_status st = launch(S, j);
+      const mds_status st = launch(S, sl);
       lk.lock();
-      if (st != MDS_OK) j->result = st;
+      if (st != MDS_OK)
+        for (Job* j : grp) j->result = st;
       progressed = true;
     }
     if (!progressed) {
@@ -263,7 +359,7 @@ mds_status mds_server_create(mds_server_t* out, size_t hbm_budget_bytes, int32_t
   for (Slot& sl : S->slots) {
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-        hipHostMalloc((void**)&sl.host_status, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc((void**)&sl.host_status, kMaxGroup * sizeof(DevStatus), hipHostMallocDefault) != hipSuccess)
       return cleanup(fail(MDS_ERR_HIP, "stream/event/pinned-buffer creation failed"));
   }
   S->arena = new Arena(hbm_budget_bytes);
@@ -359,9 +455,49 @@ mds_status mds_server_stats(mds_server_t S, mds_server_info* out) {
   out->slots = (int32_t)S->slots.size();
   out->pad_ = 0;
   out->completed = S->completed;
+  out->batches = S->batches;
   out->budget_bytes = S->budget;
   out->used_bytes = S->arena->used();
   out->peak_bytes = S->arena->peak();
+  return MDS_OK;
+}
+
+mds_status mds_server_set_batching(mds_server_t S, int64_t small_n_max, int32_t max_batch) {
+  if (!S) return fail(MDS_ERR_INVALID_ARG, "NULL server");
+  if (small_n_max < 0 || max_batch < 1 || max_batch > kMaxGroup)
+    return fail(MDS_ERR_INVALID_ARG, "small_n_max = %lld, max_batch = %d (need >= 0 and 1..%d)",
+                (long long)small_n_max, max_batch, kMaxGroup);
+  std::lock_guard<std::mutex> g(S->mu);
+  S->small_n_max = small_n_max;
+  S->max_batch = max_batch;
+  return MDS_OK;
+}
+
+mds_status mds_server_autotune(mds_server_t S, int32_t form, int32_t k, int32_t oversample, int32_t q,
+                               int64_t* small_n_max) {
+  if (!S) return fail(MDS_ERR_INVALID_ARG, "NULL server");
+  int max_batch;
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    max_batch = S->max_batch;
+  }
+  // batch a size class only if a full batch costs under a quarter of the
+  // plan path's time per instance (the plan path also overlaps across slots)
+  int64_t chosen = 0;
+  for (int64_t n = 128; n <= 8192; n *= 2) {
+    if ((int64_t)k + oversample > n) continue;
+    mds_batch_tune t{};
+    const mds_status st = mds_autotune_batch(form, n, k, oversample, q, max_batch, nullptr, &t);
+    if (st == MDS_ERR_INVALID_ARG) break;  // past the batched kernel's limits
+    if (st != MDS_OK) return st;
+    if (!(4.0f * t.batch_ms_best < t.plan_ms)) break;
+    chosen = n;
+  }
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    S->small_n_max = chosen;
+  }
+  if (small_n_max) *small_n_max = chosen;
   return MDS_OK;
 }
 

@@ -56,5 +56,8 @@ mds_status hip_check(hipError_t e, const char* what);
 // is allocated on first use if none was set.
 mds_status run_plan(mds_plan_s* P, const void* D, double* coords, double* eigvals, hipStream_t s, int stop_after,
                     int range_passes);
+// Limits of the batched small-instance kernel (l_pad and n).
+int batch_max_l();
+int64_t batch_max_n();
 
 }  // namespace mds

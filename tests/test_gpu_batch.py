@@ -33,14 +33,15 @@ def build(kind, n, seed, f64=False):
     return W.hamming_distances(reads)
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16"])
-def test_batch_matches_oracle_and_single_path(form):
+@pytest.mark.parametrize("form,tile", [("fp64", 0), ("fp32", 0), ("bf16", 0), ("fp64", 1), ("fp32", 2),
+                                       ("bf16", 1), ("bf16", 2), ("bf16", 4)])
+def test_batch_matches_oracle_and_single_path(form, tile):
     Ds = [build(kind, n, seed, f64=(form == "fp64" and i % 2 == 0)) for i, (kind, n, _, _, _, seed)
           in enumerate(PROBLEMS)]
     probs = [dict(D=torch.from_numpy(D).cuda(), k=k, oversample=p, q=q, seed=seed)
              for D, (_, n, k, p, q, seed) in zip(Ds, PROBLEMS)]
-    say(f"[batch] form={form} {len(probs)} instances")
-    outs, st = mds.run_batch(probs, form=form)
+    say(f"[batch] form={form} tile={tile} {len(probs)} instances")
+    outs, st = mds.run_batch(probs, form=form, tile=tile)
     assert st == [_capi.OK] * len(probs)
     for D, pr, (c, e), (kind, n, k, p, q, seed) in zip(Ds, probs, outs, PROBLEMS):
         ref = O.rand_mds(D, k, p, q, seed, form=form)
@@ -78,3 +79,22 @@ def test_batch_edge_cases_and_many_launches():
         ref = O.rand_mds(D.cpu().numpy(), 6, 4, 1, i)
         assert st[3 + i] == _capi.OK
         assert rel_eig_err(outs[3 + i][1].cpu().numpy(), ref["eigvals"]) < 1e-10
+
+
+def test_autotuner_records_a_tile_and_server_threshold():
+    say("[batch] autotune n=300 (batch 8) and the server threshold")
+    t = mds.autotune_batch(300, k=20, oversample=10, q=2, form="bf16", batch=8)
+    assert t["tile"] in (1, 2, 4)
+    assert all(x > 0 for x in t["batch_ms_per_job"]) and t["plan_ms"] > 0
+    assert t["batch_ms_best"] == min(t["batch_ms_per_job"])
+    # runs after tuning use the recorded tile and stay correct
+    D = torch.from_numpy(build("amp", 300, 1)).cuda()
+    outs, st = mds.run_batch([dict(D=D, k=20, oversample=10, q=2, seed=4)] * 3, form="bf16")
+    ref = O.rand_mds(D.cpu().numpy(), 20, 10, 2, 4, form="bf16")
+    assert st == [0, 0, 0]
+    for c, e in outs:
+        assert rel_eig_err(e.cpu().numpy(), ref["eigvals"]) < MATCHED_EIG_BAR["bf16"]
+    with mds.Server(1 << 32, slots=2, max_batch=8) as srv:
+        small_n_max = srv.autotune(form="bf16", k=20, oversample=10, q=2)
+        say(f"    server batching threshold: n <= {small_n_max}")
+        assert small_n_max in (0, 128, 256, 512, 1024, 2048, 4096, 8192)

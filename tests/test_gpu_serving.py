@@ -8,7 +8,7 @@ import time
 
 import pytest
 
-from gpu_util import say
+from gpu_util import procrustes_err, say
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -40,26 +40,40 @@ def alone(plan, D):
     return c.clone(), e.clone()
 
 
-def test_mix_matches_alone_under_budget():
+# batched small jobs agree with the standalone run to the form's rounding
+EIG_TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 1e-4}
+
+
+@pytest.mark.parametrize("batching", [False, True])
+def test_mix_matches_alone_under_budget(batching):
     jobs = []
     for i, (kind, n, k, p, q, form) in enumerate(MIX):
         D = make_D(kind, n, seed=i)
         jobs.append((mds.Plan(n, k, p, q, seed=100 + i, form=form), D))
     sizes = sorted(pl.workspace_size() for pl, _ in jobs)
     budget = sum(sizes[-3:]) + (1 << 20)  # at most ~3 large jobs resident: forces queueing
-    say(f"[serve] {len(jobs)} jobs, budget {budget / 2**20:.0f} MiB, 4 slots")
-    with mds.Server(budget, slots=4) as srv:
+    say(f"[serve] {len(jobs)} jobs, budget {budget / 2**20:.0f} MiB, 4 slots, batching {batching}")
+    with mds.Server(budget, slots=4, small_n_max=2048 if batching else 0) as srv:
         tickets = [srv.submit(pl, D) for pl, D in jobs]
         results = [srv.wait(t) for t, _, _ in tickets]
         st = srv.stats()
     assert all(r[0] == _capi.OK for r in results), results
     assert st["running"] == 0 and st["queued"] == 0 and st["used_bytes"] == 0
     assert 0 < st["peak_bytes"] <= budget and st["completed"] == len(jobs)
+    if not batching:
+        assert st["batches"] == 0
     for (pl, D), (t, c, e), (status, times) in zip(jobs, tickets, results):
         ca, ea = alone(pl, D)
         say(f"    n={pl.n} form={pl.form}: latency {times['latency_ms']:.2f} ms (queue {times['queue_ms']:.2f})")
-        assert torch.equal(c, ca) and torch.equal(e, ea), f"n={pl.n} differs from the standalone run"
         assert times["latency_ms"] >= times["run_ms"] >= 0
+        if batching and pl.n <= 2048:
+            rel = (e - ea).abs().max().item() / max(ea.abs().max().item(), 1e-300)
+            assert rel < EIG_TOL[pl.form], (pl.n, pl.form, rel)
+            assert procrustes_err(c.cpu().numpy(), ca.cpu().numpy()) < 1e-3
+            idx = c.abs().argmax(dim=0)
+            assert torch.all(c[idx, torch.arange(pl.k, device=c.device)] > 0)
+        else:
+            assert torch.equal(c, ca) and torch.equal(e, ea), f"n={pl.n} differs from the standalone run"
 
 
 def test_cancel_nonfinite_budget_and_tickets():
@@ -72,7 +86,7 @@ def test_cancel_nonfinite_budget_and_tickets():
     nan_D = D_small.clone()
     nan_D[3, 7] = float("nan")
     say("[serve] cancel / non-finite / budget / tickets")
-    with mds.Server(big.workspace_size() + 8 * small.workspace_size(), slots=1) as srv:
+    with mds.Server(big.workspace_size() + 8 * small.workspace_size(), slots=1, small_n_max=0) as srv:
         t0 = srv.submit(big, D_big)[0]
         ts = [srv.submit(small, D_small)[0] for _ in range(3)]
         tn = srv.submit(small, nan_D)[0]
@@ -103,3 +117,25 @@ def test_cancel_nonfinite_budget_and_tickets():
         st = _capi.lib().mds_submit(srv._h, huge.handle, ctypes.c_void_p(D_big.data_ptr()), ctypes.c_void_p(256),
                                     ctypes.c_void_p(256), ctypes.byref(t))
         assert st == _capi.ERR_BUDGET
+
+
+def test_small_jobs_batched_in_one_launch():
+    """A burst of small jobs behind one large job: they queue, then run
+    together as batched launches, each within the form's tolerance."""
+    probs = [("gm", 300 + 97 * i, 100 + i) for i in range(20)]
+    big = mds.Plan(12000, 20, 10, 2, seed=9, form="bf16")
+    Dbig = make_D("amp", 12000, seed=9)
+    jobs = [(mds.Plan(n, 20, 10, 2, seed=s, form="bf16"), make_D(kind, n, seed=s)) for kind, n, s in probs]
+    say(f"[serve] 1 large + {len(jobs)} small jobs, 2 slots")
+    with mds.Server(1 << 33, slots=2, small_n_max=4096, max_batch=8) as srv:
+        tb = srv.submit(big, Dbig)[0]
+        tickets = [srv.submit(pl, D) for pl, D in jobs]
+        res = [srv.wait(t) for t, _, _ in tickets]
+        assert srv.wait(tb)[0] == _capi.OK
+        st = srv.stats()
+    assert all(r[0] == _capi.OK for r in res)
+    assert st["batches"] >= len(jobs) // 8
+    for (pl, D), (t, c, e) in zip(jobs, tickets):
+        ca, ea = alone(pl, D)
+        rel = (e - ea).abs().max().item() / ea.abs().max().item()
+        assert rel < EIG_TOL["bf16"], (pl.n, rel)
