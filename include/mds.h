@@ -56,14 +56,20 @@ typedef enum mds_status {
  *   BF16: G stored in bf16 (rounded from fp64 through fp32), bf16 MFMA with
  *         fp32 accumulation for the 2q+1 range passes; the projection pass
  *         ("refinement") uses fp32 G entries and fp32 MFMA.
- * G is stored only in the bf16 form.  Every other pass recomputes each
+ *   FP8:  G stored as OCP FP8 E4M3 codes with one fp32 scale per 256 x 256
+ *         block: g = fl32(gamma), s = fl32(max|g| / 448) over the block (1
+ *         for an all-zero block), code = E4M3(fl32(g / s)), nearest even,
+ *         saturating.  The range passes multiply bf16(fl32(s * code)) with
+ *         bf16 X on bf16 MFMA, fp32 accumulation; the projection is fp32 as
+ *         in the bf16 form.
+ * G is stored only in the bf16 and fp8 forms.  Every other pass recomputes each
  * entry from D: fp64 passes with the centring equation in fp64 (the values a
  * stored fp64 G would hold), fp32 passes as fma(-1/2, fl32(d^2),
  * fl32(c_j/2) + fl32((r_i - m)/2)) in fp32, within a few fp32 ulps of the
  * terms of the rounded exact value.
  * In every form the centring sums, CholeskyQR2, the Gram products of the
  * tall matrices and the small eigensolve run in fp64. */
-typedef enum mds_form { MDS_FORM_FP64 = 0, MDS_FORM_FP32 = 1, MDS_FORM_BF16 = 2 } mds_form;
+typedef enum mds_form { MDS_FORM_FP64 = 0, MDS_FORM_FP32 = 1, MDS_FORM_BF16 = 2, MDS_FORM_FP8 = 3 } mds_form;
 
 /* Element type of the caller's distance matrix D. */
 typedef enum mds_dtype { MDS_DTYPE_F32 = 0, MDS_DTYPE_F64 = 1 } mds_dtype;
@@ -136,7 +142,7 @@ mds_status mds_run_stages(mds_plan_t plan, const void* D, double* coords, double
 
 /* Internal buffers exposed read-only for inspection after a (partial) run. */
 typedef enum mds_buffer_id {
-  MDS_BUF_G = 0,       /* stored Gram matrix, n_pad x ldg bf16 (BF16 form only) */
+  MDS_BUF_G = 0,       /* stored Gram matrix, n_pad x ldg: bf16 (BF16 form) or E4M3 codes (FP8 form) */
   MDS_BUF_GREF = 1,    /* reserved (no fp32 copy of G is stored) */
   MDS_BUF_ROWMEAN = 2, /* r, n fp64 */
   MDS_BUF_COLMEAN = 3, /* c, n fp64 */
@@ -150,12 +156,13 @@ typedef enum mds_buffer_id {
   MDS_BUF_V = 10,      /* Ritz vectors in the Q basis, l x l (ld l_pad) fp64 */
   MDS_BUF_W = 11,      /* last small Gram product (Y^T Y or Q1^T Q1), l_pad x l_pad fp64 */
   MDS_BUF_T = 12,      /* last orthonormalising factor, l_pad x l_pad fp64 */
-  MDS_BUF_Q1 = 13      /* first CholeskyQR iterate, transposed l_pad x ldg fp64 */
+  MDS_BUF_Q1 = 13,     /* first CholeskyQR iterate, transposed l_pad x ldg fp64 */
+  MDS_BUF_GSCALE = 14  /* FP8 form: block scales, (n_pad/256) x (n_pad/256) fp32 */
 } mds_buffer_id;
 
 typedef struct mds_buffer {
   void* ptr;      /* device pointer into the workspace */
-  int32_t dtype;  /* 0 fp64, 1 fp32, 2 bf16 */
+  int32_t dtype;  /* 0 fp64, 1 fp32, 2 bf16, 3 fp8 e4m3 codes */
   int32_t pad_;
   int64_t rows, cols, ld; /* logical shape and leading dimension (elements) */
 } mds_buffer;

@@ -54,6 +54,12 @@ __all__ = [
     "orthonormal_basis",
     "normalise_column_signs",
     "round_to",
+    "round_form",
+    "e4m3_value",
+    "fp8_block_quantize",
+    "fp8_operand",
+    "E4M3_MAX",
+    "FP8_BLOCK",
     "FORMS",
 ]
 
@@ -205,12 +211,66 @@ def round_to(x, dtype: str) -> np.ndarray:
     return (r << np.uint32(16)).view(np.float32).astype(np.float64)
 
 
+E4M3_MAX = 448.0  # largest finite OCP FP8 E4M3 value (1.75 * 2^8)
+FP8_BLOCK = 256   # side of the square blocks that share one scale
+
+
+def e4m3_value(x) -> np.ndarray:
+    """Value of the OCP FP8 E4M3 number nearest to each float (ties to even
+    significand), saturating at +-448.  E4M3: 1 sign bit, 4 exponent bits
+    with bias 7, 3 fraction bits; normal numbers (1 + f/8) 2^(e-7) for
+    e = 1..15 (448 = 1.75 * 2^8 is the largest, the all-ones code is NaN),
+    subnormals (f/8) 2^-6, i.e. multiples of 2^-9 below 2^-6."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x)
+    out = np.zeros_like(a)
+    normal = a >= 2.0 ** -6
+    f, E = np.frexp(a[normal])  # a = f 2^E, f in [0.5, 1)
+    e = E - 1                    # a = (2 f) 2^e, 2 f in [1, 2)
+    out[normal] = np.rint(2.0 * f * 8.0) / 8.0 * np.ldexp(1.0, e)  # np.rint: half to even
+    out[~normal] = np.rint(a[~normal] * 2.0 ** 9) * 2.0 ** -9
+    out = np.minimum(out, E4M3_MAX)
+    return np.copysign(out, x)
+
+
+def fp8_block_quantize(G: np.ndarray, block: int = FP8_BLOCK):
+    """Per-block scaled FP8 storage of G: entries rounded to float32 g; for
+    each block x block tile a float32 scale s = max|g| / 448 (1 for an
+    all-zero tile); stored codes q = e4m3(fl32(g / s)).  Returns (q values,
+    scale per entry), both float64 arrays of G's shape."""
+    g = np.asarray(G, dtype=np.float64).astype(np.float32)
+    n0, n1 = g.shape
+    q = np.zeros(g.shape, dtype=np.float64)
+    sc = np.ones(g.shape, dtype=np.float64)
+    for i0 in range(0, n0, block):
+        for j0 in range(0, n1, block):
+            t = g[i0:i0 + block, j0:j0 + block]
+            mx = np.float32(np.max(np.abs(t))) if t.size else np.float32(0.0)
+            s = np.float32(mx / np.float32(E4M3_MAX)) if mx > 0 else np.float32(1.0)
+            q[i0:i0 + block, j0:j0 + block] = e4m3_value((t / s).astype(np.float32))
+            sc[i0:i0 + block, j0:j0 + block] = s
+    return q, sc
+
+
+def fp8_operand(G: np.ndarray) -> np.ndarray:
+    """The G entries the FP8 form multiplies with: each stored code times its
+    block scale in float32, rounded to bfloat16 (the MFMA operand type)."""
+    q, sc = fp8_block_quantize(G)
+    return round_to((q.astype(np.float32) * sc.astype(np.float32)).astype(np.float64), "bf16")
+
+
 # Dtype of (G, X) in the range passes and in the projection pass of each form.
 FORMS = {
     "fp64": {"range": ("f64", "f64"), "proj": ("f64", "f64")},
     "fp32": {"range": ("f32", "f32"), "proj": ("f32", "f32")},
     "bf16": {"range": ("bf16", "bf16"), "proj": ("f32", "f32")},
+    "fp8": {"range": ("fp8blk", "bf16"), "proj": ("f32", "f32")},
 }
+
+
+def round_form(x, dtype: str) -> np.ndarray:
+    """round_to, plus 'fp8blk': the block-scaled FP8 operand of a matrix."""
+    return fp8_operand(x) if dtype == "fp8blk" else round_to(x, dtype)
 
 
 # ---------------------------------------------------------------------------
@@ -294,8 +354,8 @@ def rand_mds(D, k: int, p: int, q: int, seed: int, G=None, keep_history=False, f
         G = gram_matrix(D)
     gr, xr = FORMS[form]["range"]
     gp, xp = FORMS[form]["proj"]
-    Gr = round_to(G, gr)
-    Gp = round_to(G, gp)
+    Gr = round_form(G, gr)
+    Gp = round_form(G, gp)
     Om = omega(seed, n, l)
     history = []
     Y = Gr @ round_to(Om, xr)

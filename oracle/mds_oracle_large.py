@@ -44,6 +44,10 @@ def centring_stats_blocked(D, block: int = 4096):
 
 def _round_t(x, dtype):
     torch = _torch()
+    if dtype == "fp8blk":  # row block of G: its 256 x 256 tiles are whole
+        from .mds_oracle import fp8_operand
+
+        return torch.from_numpy(fp8_operand(x.numpy()))
     if dtype == "f64":
         return x
     if dtype == "f32":
@@ -64,6 +68,8 @@ def gram_apply_blocked(D, stats, X, gdtype="f64", block: int = 2048):
     Xt = torch.as_tensor(X, dtype=torch.float64)
     n = Dt.shape[0]
     Y = torch.empty((n, Xt.shape[1]), dtype=torch.float64)
+    if gdtype == "fp8blk" and block % 256:
+        raise ValueError("fp8 blocks need row blocks that are multiples of 256")
     for a in range(0, n, block):
         b = min(a + block, n)
         G = -0.5 * (Dt[a:b].to(torch.float64) ** 2 - ct[None, :] - rt[a:b, None] + m)

@@ -138,8 +138,8 @@ class Plan:
             raise RuntimeError("buffer() needs a workspace attached with attach_workspace()")
         b = _capi.MdsBuffer()
         check(_capi.lib().mds_get_buffer(self._h, int(which), ctypes.byref(b)), "mds_get_buffer")
-        dt = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}[b.dtype]
-        esz = {0: 8, 1: 4, 2: 2}[b.dtype]
+        dt = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16, 3: torch.float8_e4m3fn}[b.dtype]
+        esz = {0: 8, 1: 4, 2: 2, 3: 1}[b.dtype]
         rows, cols, ld = b.rows, b.cols, b.ld
         total = (rows - 1) * ld + cols if rows > 0 else 0
         off = b.ptr - self._ws.data_ptr()

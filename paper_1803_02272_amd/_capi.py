@@ -25,8 +25,8 @@ ERR_CANCELLED = -8
 ERR_STATE = -9
 
 # forms and dtypes
-FORM_FP64, FORM_FP32, FORM_BF16 = 0, 1, 2
-FORMS = {"fp64": FORM_FP64, "fp32": FORM_FP32, "bf16": FORM_BF16}
+FORM_FP64, FORM_FP32, FORM_BF16, FORM_FP8 = 0, 1, 2, 3
+FORMS = {"fp64": FORM_FP64, "fp32": FORM_FP32, "bf16": FORM_BF16, "fp8": FORM_FP8}
 DTYPE_F32, DTYPE_F64 = 0, 1
 
 # stages
@@ -34,7 +34,7 @@ STAGE_CENTER, STAGE_OMEGA, STAGE_RANGE, STAGE_ALL = 1, 2, 3, 100
 
 # buffers
 (BUF_G, BUF_GREF, BUF_ROWMEAN, BUF_COLMEAN, BUF_MEAN, BUF_X, BUF_Q, BUF_Y, BUF_B, BUF_THETA, BUF_V, BUF_W, BUF_T,
- BUF_Q1) = range(14)
+ BUF_Q1, BUF_GSCALE) = range(15)
 
 MAX_L = 256
 

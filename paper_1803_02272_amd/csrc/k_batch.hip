@@ -485,7 +485,7 @@ __global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
   const BJob J = tab.job[blockIdx.x];
   __shared__ BShared S;
   lds_double* M = (lds_double*)(void*)S.M;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   const int64_t n = J.n, np = J.n_pad;
   const int l = J.l, l_pad = J.l_pad, k = J.k;
   const BLayout Lo = blayout(np, l_pad, FORM);

@@ -300,7 +300,101 @@ hipError_t write_by_g(const DT* D, int64_t n, int64_t n_pad, int64_t ldg, int ve
   }
 }
 
+// OCP E4M3 code of x (|x| <= 448 up to rounding, finite), nearest even,
+// saturating: 1 sign, 4 exponent (bias 7) and 3 fraction bits; below 2^-6
+// the subnormal multiples of 2^-9.
+__device__ __forceinline__ uint32_t e4m3_code(float x) {
+  const uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
+  const float a = fabsf(x);
+  if (a >= 448.0f) return sign | 0x7Eu;  // largest finite: 1.75 * 2^8
+  if (a >= 0x1p-6f) {
+    uint32_t b = __float_as_uint(a);
+    b += 0x7FFFFu + ((b >> 20) & 1u);  // round the fp32 fraction to 3 bits, ties to even
+    const uint32_t e = ((b >> 23) & 0xFFu) - 120u;  // E4M3 biased exponent (fp32 bias 127, E4M3 bias 7)
+    return sign | (e << 3) | ((b >> 20) & 7u);      // a < 448 cannot round past 448
+  }
+  return sign | (uint32_t)rintf(a * 512.0f);  // 0..8 units of 2^-9 (8 = 2^-6, the smallest normal)
+}
+
+constexpr int kF8CacheRows = 64;  // rows of a block kept in LDS between the two passes
+
+// One workgroup per 256 x 256 block: pass 1 takes the block maximum of
+// |fl32(gamma)|, pass 2 quantizes.  The first kF8CacheRows rows are kept in
+// LDS; the rest are recomputed from D, whose block the infinity cache still
+// holds (the 64 KB of LDS also caps residency at two blocks per CU).
+template <typename DT>
+__global__ __launch_bounds__(256, 2) void k_center_write_fp8(const DT* __restrict__ D, int64_t n, int64_t ldg,
+                                                             const double* __restrict__ r,
+                                                             const double* __restrict__ c,
+                                                             const double* __restrict__ mean_all,
+                                                             uint8_t* __restrict__ G8, float* __restrict__ scales,
+                                                             int64_t nsb) {
+#pragma clang fp contract(off)
+  __shared__ float cache[kF8CacheRows][kF8Block];
+  __shared__ float red[4];
+  const int64_t J = blockIdx.x, I = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int64_t j = J * kF8Block + tid;
+  const int64_t i0 = I * kF8Block;
+  const double m = mean_all[0];
+  const double cj = j < n ? c[j] : 0.0;
+  auto g_at = [&](int64_t i, DT d) -> float {
+    if (i >= n || j >= n) return 0.0f;
+    const double dd = (double)d;
+    return (float)(-0.5 * (((dd * dd - cj) - r[i]) + m));
+  };
+  float mx = 0.0f;
+  for (int ii = 0; ii < kF8Block; ii += 8) {
+    DT d[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = i0 + ii + u;
+      d[u] = (i < n && j < n) ? D[i * n + j] : (DT)0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float g = g_at(i0 + ii + u, d[u]);
+      if (ii + u < kF8CacheRows) cache[ii + u][tid] = g;
+      mx = fmaxf(mx, fabsf(g));
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = mx;
+  __syncthreads();
+  mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  const float s = mx > 0.0f ? mx / 448.0f : 1.0f;
+  if (tid == 0) scales[I * nsb + J] = s;
+  for (int ii = 0; ii < kF8Block; ii += 8) {
+    DT d[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = i0 + ii + u;
+      d[u] = (ii + u >= kF8CacheRows && i < n && j < n) ? D[i * n + j] : (DT)0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float g = ii + u < kF8CacheRows ? cache[ii + u][tid] : g_at(i0 + ii + u, d[u]);
+      G8[(i0 + ii + u) * ldg + j] = (uint8_t)e4m3_code(g / s);
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_center_write_fp8(const void* D, int d_is_f64, int64_t n, int64_t n_pad, int64_t ldg,
+                                   const double* r, const double* c, const double* mean_all, uint8_t* G8,
+                                   float* scales, hipStream_t s) {
+  if (n_pad % kF8Block != 0 || ldg != n_pad) return hipErrorInvalidValue;
+  const int64_t nsb = n_pad / kF8Block;
+  dim3 grid((unsigned)nsb, (unsigned)nsb);
+  if (d_is_f64)
+    hipLaunchKernelGGL(k_center_write_fp8<double>, grid, dim3(256), 0, s, (const double*)D, n, ldg, r, c, mean_all,
+                       G8, scales, nsb);
+  else
+    hipLaunchKernelGGL(k_center_write_fp8<float>, grid, dim3(256), 0, s, (const float*)D, n, ldg, r, c, mean_all,
+                       G8, scales, nsb);
+  return hipGetLastError();
+}
 
 int64_t stats_tiles(int64_t n) {
   return ((n + kStatsCols - 1) / kStatsCols) * ((n + kStatsRows - 1) / kStatsRows);

@@ -45,7 +45,8 @@ struct Tr;
 
 template <>
 struct Tr<GK_BF16> {
-  using T = bf16_t;
+  using T = bf16_t;   // stored G element
+  using XT = bf16_t;  // X operand element
   using Acc = floatx4_t;
   using AccS = float;
   static constexpr int kSub = 1;  // MFMAs per 16-byte operand chunk
@@ -59,6 +60,7 @@ struct Tr<GK_BF16> {
 template <>
 struct Tr<GK_F32> {
   using T = float;
+  using XT = float;
   using Acc = floatx4_t;
   using AccS = float;
   // one 16-byte chunk holds 4 K-values per lane: four K=4 MFMAs, the t-th
@@ -78,6 +80,7 @@ struct Tr<GK_F32> {
 template <>
 struct Tr<GK_F64> {
   using T = double;
+  using XT = double;
   using Acc = doublex4_t;
   using AccS = double;
   static constexpr int kSub = 2;
@@ -94,12 +97,37 @@ struct Tr<GK_F64> {
   }
 };
 
+// FP8: E4M3 codes, decoded and scaled into bf16 A operands (X is bf16).
+template <>
+struct Tr<GK_FP8> {
+  using T = uint8_t;
+  using XT = bf16_t;
+  using Acc = floatx4_t;
+  using AccS = float;
+  static constexpr int kSub = 1;
+  static __device__ __forceinline__ void mma_sub(Acc& c, const u32x4& a, const u32x4& b, int) { mma(c, a, b); }
+  static __device__ __forceinline__ void mma(Acc& c, const u32x4& a, const u32x4& b) {
+    Tr<GK_BF16>::mma(c, a, b);
+  }
+};
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// bf16 bits (round to nearest even) of a finite float.
+__device__ __forceinline__ uint32_t bf16_bits(float v) {
+  uint32_t u = __float_as_uint(v);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
 constexpr int kRowB = 144;  // LDS bytes per X row within a step tile
 
 // 16-row groups per wave, chosen so accumulators + prefetched A operands fit
 // the register file at two workgroups per CU without spilling.
 __host__ __device__ constexpr int rg_for(int gk, int cg) {
-  return gk == GK_F64 ? (cg <= 3 ? 4 : (cg <= 7 ? 2 : 1)) : (cg <= 8 ? 4 : 2);
+  if (gk == GK_F64) return cg <= 3 ? 4 : (cg <= 7 ? 2 : 1);
+  if (gk == GK_FP8) return cg <= 7 ? 4 : 2;  // the E4M3 decode needs a few more registers than bf16
+  return cg <= 8 ? 4 : 2;
 }
 // Recentring passes hold raw D values and recentring terms in registers as
 // well; fewer row groups keep two workgroups per CU.
@@ -150,20 +178,23 @@ __device__ __forceinline__ void load_d(const DT* __restrict__ D, int64_t n, int6
 
 template <int GK, int RG, int CG, typename DT, bool SYM>
 __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
-    const typename Tr<GK>::T* __restrict__ G, int64_t ldg, const typename Tr<GK>::T* __restrict__ Xt, int split,
+    const typename Tr<GK>::T* __restrict__ G, int64_t ldg, const typename Tr<GK>::XT* __restrict__ Xt, int split,
     int64_t steps_total, int64_t steps_per_split, typename Tr<GK>::AccS* __restrict__ Ypart, GPassDSrc src,
     int64_t sym_nbx) {
   using TT = Tr<GK>;
   using T = typename TT::T;
+  using XT = typename TT::XT;
   using Acc = typename TT::Acc;
   using AccS = typename TT::AccS;
   constexpr bool FD = DLoad<DT>::kFromD;
+  constexpr bool F8 = GK == GK_FP8;
   using RawT = typename std::conditional<FD, DT, T>::type;
-  constexpr int E = 16 / sizeof(T);  // A elements per lane per 16-byte chunk
+  constexpr int E = 16 / sizeof(XT);  // A elements per lane per chunk (one 16-byte B operand)
+  constexpr int AB = E * sizeof(T);   // stored-G bytes per lane per chunk
   constexpr int LPAD = CG * 16;
   constexpr int PIECES = LPAD * 8;  // 16-byte pieces per X step tile
   constexpr int PPT = (PIECES + 255) / 256;
-  constexpr int BK = 128 / sizeof(T);  // K elements per step
+  constexpr int BK = 128 / sizeof(XT);  // K elements per step (a 128-byte row of the X tile)
   __shared__ __attribute__((aligned(16))) unsigned char xs[2][LPAD * kRowB];
 
   static_assert(!SYM || DLoad<DT>::kFromD, "symmetric mode recentres D on the fly");
@@ -200,11 +231,13 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[rg][cg][e] = 0;
 
-  const size_t rowbytes = (size_t)ldg * sizeof(T);
+  const size_t rowbytes = (size_t)ldg * sizeof(T);    // stored G
+  const size_t xrowbytes = (size_t)ldg * sizeof(XT);  // X
   const unsigned char* Ab =
-      reinterpret_cast<const unsigned char*>(G) + (size_t)(row0 + (lane & 15)) * rowbytes + (lane >> 4) * 16;
+      reinterpret_cast<const unsigned char*>(G) + (size_t)(row0 + (lane & 15)) * rowbytes + (lane >> 4) * AB;
   const size_t rg_stride = 16 * rowbytes;
   const unsigned char* Xb = reinterpret_cast<const unsigned char*>(Xt);
+  const int64_t f8_row_block = F8 ? (mb * (64 * RG)) / kF8Block : 0;
 
   // recentring state (only used when FD).  CT: precision of the recentring
   // terms (fp32 passes use fl32(c/2) and fl32((r - m)/2), fp64 passes c, r, m).
@@ -253,8 +286,14 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
         for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
-            const u32x4 w = *reinterpret_cast<const u32x4*>(Ab + rg * rg_stride + (size_t)st * 128 + c * 64);
-            __builtin_memcpy(&dst[rg][c], &w, 16);
+            const unsigned char* p = Ab + rg * rg_stride + (size_t)st * (BK * sizeof(T)) + c * (BK / 2 * sizeof(T));
+            if constexpr (AB == 16) {
+              const u32x4 w = *reinterpret_cast<const u32x4*>(p);
+              __builtin_memcpy(&dst[rg][c], &w, 16);
+            } else {
+              const uint2 w = *reinterpret_cast<const uint2*>(p);
+              __builtin_memcpy(&dst[rg][c], &w, 8);
+            }
           }
       }
     };
@@ -263,7 +302,7 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
       for (int u = 0; u < PPT; ++u) {
         const int p = tid + 256 * u;
         if (PIECES % 256 == 0 || p < PIECES)
-          xr[u] = *reinterpret_cast<const u32x4*>(Xb + (size_t)(p >> 3) * rowbytes + (size_t)st * 128 +
+          xr[u] = *reinterpret_cast<const u32x4*>(Xb + (size_t)(p >> 3) * xrowbytes + (size_t)st * 128 +
                                                   (p & 7) * 16);
       }
     };
@@ -315,6 +354,21 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
         }
         u32x4 w;
         __builtin_memcpy(&w, &g, 16);
+        return w;
+      } else if constexpr (F8) {
+        const float sc = src.g8_scales[f8_row_block * src.g8_nsb + (st * BK) / kF8Block];
+        uint32_t cw[2];
+        __builtin_memcpy(cw, &a[rg][c], 8);
+        u32x4 w;
+        // hardware E4M3 decode (OCP, two codes per instruction), scale in
+        // fp32, round to bf16: element t of the chunk is byte t
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)cw[h], false);  // bytes 0, 1
+          const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)cw[h], true);   // bytes 2, 3
+          w[2 * h] = bf16_bits(lo.x * sc) | (bf16_bits(lo.y * sc) << 16);
+          w[2 * h + 1] = bf16_bits(hi.x * sc) | (bf16_bits(hi.y * sc) << 16);
+        }
         return w;
       } else {
         u32x4 w;
@@ -420,10 +474,11 @@ template <int GK, int RG, int CG, typename DT, bool SYM>
 void launch_one(const void* G, int64_t ldg, const void* Xt, const GPassCfg& cfg, int64_t n_pad, void* Yp,
                 const GPassDSrc& src, hipStream_t s) {
   using T = typename Tr<GK>::T;
+  using XT = typename Tr<GK>::XT;
   using AccS = typename Tr<GK>::AccS;
   const int64_t blocks = gpass_blocks(cfg, n_pad);
   hipLaunchKernelGGL((k_gpass<GK, RG, CG, DT, SYM>), dim3((unsigned)blocks), dim3(256), 0, s, (const T*)G, ldg,
-                     (const T*)Xt, cfg.split, cfg.steps_total, cfg.steps_per_split, (AccS*)Yp, src, cfg.sym_nbx);
+                     (const XT*)Xt, cfg.split, cfg.steps_total, cfg.steps_per_split, (AccS*)Yp, src, cfg.sym_nbx);
 }
 
 template <int GK, int RG, int CG, typename DT>
@@ -442,8 +497,8 @@ hipError_t launch_cg(const void* G, int64_t ldg, const void* Xt, const GPassCfg&
     constexpr int RG = rg_for(GK, CG);
     if (cfg.rg != RG || cfg.sym) return hipErrorInvalidValue;
     launch_one<GK, RG, CG, void, false>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
-  } else if constexpr (GK == GK_BF16) {
-    return hipErrorInvalidValue;  // bf16 passes read the stored bf16 G
+  } else if constexpr (GK == GK_BF16 || GK == GK_FP8) {
+    return hipErrorInvalidValue;  // bf16 and fp8 passes read the stored G
   } else {
     constexpr int RG = rg_fd(GK, CG);
     if (cfg.rg != RG) return hipErrorInvalidValue;
@@ -507,6 +562,9 @@ hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const
     case GK_F64: return launch_gk<GK_F64>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
     case GK_F32: return launch_gk<GK_F32>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
     case GK_BF16: return launch_gk<GK_BF16>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
+    case GK_FP8:
+      if (!src.g8_scales || (cfg.bm > kF8Block) || (kF8Block % cfg.bm)) return hipErrorInvalidValue;
+      return launch_gk<GK_FP8>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
     default: return hipErrorInvalidValue;
   }
 }

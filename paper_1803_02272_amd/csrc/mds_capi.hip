@@ -25,7 +25,10 @@ using namespace mds;
 namespace {
 thread_local std::string g_last_error;
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
-int gk_size(int gk) { return gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : 2); }
+int gk_size(int gk) { return gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : (gk == GK_BF16 ? 2 : 1)); }
+// Element kind of the X operand of a pass with G of kind gk (FP8 G meets bf16 X).
+int x_kind(int gk) { return gk == GK_FP8 ? GK_BF16 : gk; }
+bool stores_g(int form) { return form == MDS_FORM_BF16 || form == MDS_FORM_FP8; }
 }  // namespace
 
 namespace mds {
@@ -56,7 +59,9 @@ void layout(mds_plan_s* P) {
   P->total = 0;
   // G is stored only in the bf16 form (range passes stream 2-byte G); the
   // fp32/fp64 passes and the bf16 form's projection recentre D on the fly.
-  add(P, P->G, P->form == MDS_FORM_BF16 ? (size_t)n_pad * ldg * e : 0);
+  add(P, P->G, stores_g(P->form) ? (size_t)n_pad * ldg * e : 0);
+  const int64_t nsb = n_pad / kF8Block;
+  add(P, P->gscale, P->form == MDS_FORM_FP8 ? (size_t)nsb * nsb * 4 : 0);
   const int64_t ncb = (n + kStatsCols - 1) / kStatsCols, nrb = (n + kStatsRows - 1) / kStatsRows;
   add(P, P->rowpart, (size_t)ncb * n * 8);
   add(P, P->colpart, (size_t)nrb * n * 8);
@@ -66,7 +71,8 @@ void layout(mds_plan_s* P) {
   add(P, P->mean, 8);
   add(P, P->p4part, (size_t)stats_tiles(n) * 8);
   add(P, P->hc, (size_t)ldg * 4);
-  const size_t xe = (size_t)(gk_size(P->gk) > gk_size(P->ref_gk) ? gk_size(P->gk) : gk_size(P->ref_gk));
+  const size_t xe = (size_t)(gk_size(x_kind(P->gk)) > gk_size(P->ref_gk) ? gk_size(x_kind(P->gk))
+                                                                         : gk_size(P->ref_gk));
   add(P, P->X, (size_t)lp * ldg * xe);
   const size_t acc_main = P->gk == GK_F64 ? 8 : 4, acc_ref = P->ref_gk == GK_F64 ? 8 : 4;
   const size_t yp_main = (size_t)P->cfg.split * lp * ldg * acc_main;
@@ -185,8 +191,12 @@ mds_status orthonormalize(mds_plan_s* P, hipStream_t s, int xk) {
 mds_status gpass(mds_plan_s* P, hipStream_t s, bool ref, const void* D) {
   const int gk = ref ? P->ref_gk : P->gk;
   const GPassCfg& cfg = ref ? P->ref_cfg : P->cfg;
-  const bool from_d = ref || P->form != MDS_FORM_BF16;
+  const bool from_d = ref || !stores_g(P->form);
   GPassDSrc src;
+  if (gk == GK_FP8) {
+    src.g8_scales = P->at<float>(P->gscale);
+    src.g8_nsb = P->n_pad / kF8Block;
+  }
   if (from_d) {
     src.D = D;
     src.n = P->n;
@@ -231,7 +241,13 @@ mds_status mds::run_plan(mds_plan_s* P, const void* D, double* coords, double* e
                               P->at<double>(P->mean), st, s),
           "centring stats");
   }
-  if (P->form == MDS_FORM_BF16) {
+  if (P->form == MDS_FORM_FP8) {
+    PhaseTimer tm(P, s, MDS_PH_WRITE);
+    MDS_TRY(launch_center_write_fp8(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->n_pad, P->ldg, P->at<double>(P->r),
+                                    P->at<double>(P->c), P->at<double>(P->mean), P->at<uint8_t>(P->G),
+                                    P->at<float>(P->gscale), s),
+            "centring write fp8");
+  } else if (P->form == MDS_FORM_BF16) {
     PhaseTimer tm(P, s, MDS_PH_WRITE);
     MDS_TRY(launch_center_write(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->n_pad, P->ldg, P->at<double>(P->r),
                                 P->at<double>(P->c), P->at<double>(P->mean), P->gk, P->at<void>(P->G), nullptr, s),
@@ -242,7 +258,7 @@ mds_status mds::run_plan(mds_plan_s* P, const void* D, double* coords, double* e
 
   {
     PhaseTimer tm(P, s, MDS_PH_OMEGA);
-    MDS_TRY(launch_omega(P->seed, P->n, P->l, P->l_pad, P->ldg, P->gk, P->at<void>(P->X), s), "omega");
+    MDS_TRY(launch_omega(P->seed, P->n, P->l, P->l_pad, P->ldg, x_kind(P->gk), P->at<void>(P->X), s), "omega");
   }
   P->last_stage = MDS_STAGE_OMEGA;
   if (stop_after == MDS_STAGE_OMEGA) return MDS_OK;
@@ -252,7 +268,7 @@ mds_status mds::run_plan(mds_plan_s* P, const void* D, double* coords, double* e
   for (int it = 0; it < passes; ++it) {
     mds_status e = gpass(P, s, false, D);
     if (e != MDS_OK) return e;
-    const int next_xk = (it == total_range - 1) ? P->ref_gk : P->gk;
+    const int next_xk = (it == total_range - 1) ? P->ref_gk : x_kind(P->gk);
     e = orthonormalize(P, s, next_xk);
     if (e != MDS_OK) return e;
   }
@@ -319,7 +335,7 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
   const int64_t l = (int64_t)k + oversample;
   if (l > n) return fail(MDS_ERR_INVALID_ARG, "k + oversample = %lld > n = %lld", (long long)l, (long long)n);
   if (l > MDS_MAX_L) return fail(MDS_ERR_INVALID_ARG, "k + oversample = %lld > %d", (long long)l, MDS_MAX_L);
-  if (o.form < MDS_FORM_FP64 || o.form > MDS_FORM_BF16)
+  if (o.form < MDS_FORM_FP64 || o.form > MDS_FORM_FP8)
     return fail(MDS_ERR_INVALID_ARG, "unknown form %d", o.form);
   if (o.d_dtype != MDS_DTYPE_F32 && o.d_dtype != MDS_DTYPE_F64)
     return fail(MDS_ERR_INVALID_ARG, "unknown D dtype %d", o.d_dtype);
@@ -339,10 +355,11 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
   P->seed = seed;
   P->form = o.form;
   P->d_dtype = o.d_dtype;
-  P->gk = o.form == MDS_FORM_FP64 ? GK_F64 : (o.form == MDS_FORM_FP32 ? GK_F32 : GK_BF16);
-  P->ref_gk = o.form == MDS_FORM_BF16 ? GK_F32 : P->gk;
+  P->gk = o.form == MDS_FORM_FP64 ? GK_F64
+          : (o.form == MDS_FORM_FP32 ? GK_F32 : (o.form == MDS_FORM_BF16 ? GK_BF16 : GK_FP8));
+  P->ref_gk = stores_g(o.form) ? GK_F32 : P->gk;
   P->flags = o.flags;
-  P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, P->form != MDS_FORM_BF16, false);
+  P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, !stores_g(P->form), false);
   P->ref_cfg = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, true,
                             (o.flags & MDS_FLAG_FULL_PROJECTION) == 0);
   layout(P);
@@ -396,11 +413,16 @@ mds_status mds_get_buffer(mds_plan_t plan, int32_t which, mds_buffer* out) {
   if (!plan->ws) return fail(MDS_ERR_STATE, "plan has no workspace yet");
   mds_buffer b = {};
   const int64_t lp = plan->l_pad;
-  const int xdt = plan->gk == GK_F64 ? 0 : (plan->gk == GK_F32 ? 1 : 2);
+  const int xdt = plan->gk == GK_F64 ? 0 : (plan->gk == GK_F32 ? 1 : 2);  // X dtype (FP8: bf16)
   switch (which) {
     case MDS_BUF_G:
-      if (plan->form != MDS_FORM_BF16) return fail(MDS_ERR_STATE, "G is not stored in this form");
-      b = {plan->at<void>(plan->G), xdt, 0, plan->n_pad, plan->ldg, plan->ldg};
+      if (!stores_g(plan->form)) return fail(MDS_ERR_STATE, "G is not stored in this form");
+      b = {plan->at<void>(plan->G), plan->form == MDS_FORM_FP8 ? 3 : xdt, 0, plan->n_pad, plan->ldg, plan->ldg};
+      break;
+    case MDS_BUF_GSCALE:
+      if (plan->form != MDS_FORM_FP8) return fail(MDS_ERR_STATE, "no block scales in this form");
+      b = {plan->at<void>(plan->gscale), 1, 0, plan->n_pad / kF8Block, plan->n_pad / kF8Block,
+           plan->n_pad / kF8Block};
       break;
     case MDS_BUF_GREF: return fail(MDS_ERR_STATE, "no fp32 copy of G is stored");
     case MDS_BUF_ROWMEAN: b = {plan->at<void>(plan->r), 0, 0, plan->n, 1, 1}; break;

@@ -23,7 +23,10 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4_t;
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double doublex4_t;
 
-enum GKind { GK_F64 = 0, GK_F32 = 1, GK_BF16 = 2 };
+// Kind of the G operand of a pass.  GK_FP8: OCP E4M3 codes with one fp32
+// scale per 256 x 256 block, multiplied on bf16 MFMA (the X operand is bf16).
+enum GKind { GK_F64 = 0, GK_F32 = 1, GK_BF16 = 2, GK_FP8 = 3 };
+constexpr int kF8Block = 256;  // side of the blocks sharing one FP8 scale
 
 constexpr int kPadN = 256;     // padding granule of n (rows and ld of G)
 constexpr int kMaxL = 256;     // largest oversampled rank l = k + p
@@ -51,6 +54,13 @@ int64_t stats_tiles(int64_t n);
 hipError_t launch_center_stats(const void* D, int d_is_f64, int64_t n, int64_t ldg, double* rowpart,
                                double* colpart, double* p4part, double* r, double* c, double* rsum, float* hc,
                                double* mean_all, DevStatus* st, hipStream_t s);
+// FP8 storage of G: per 256 x 256 block, g = fl32(gamma) (gamma in fp64),
+// s = fl32(max|g| / 448) (1 for an all-zero block), code = E4M3(fl32(g / s))
+// rounded to nearest even and saturated at 448.  scales: nsb x nsb fp32,
+// nsb = n_pad / 256.
+hipError_t launch_center_write_fp8(const void* D, int d_is_f64, int64_t n, int64_t n_pad, int64_t ldg,
+                                   const double* r, const double* c, const double* mean_all, uint8_t* G8,
+                                   float* scales, hipStream_t s);
 // Writes G (kind gk, ld = ldg, n_pad rows) and, if gref != nullptr, an fp32 copy.
 int64_t center_write_blocks(int64_t n_pad, int64_t ldg);
 hipError_t launch_center_write(const void* D, int d_is_f64, int64_t n, int64_t n_pad, int64_t ldg,
@@ -80,6 +90,8 @@ GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_h
 // hr_i = fl32((r_i - m) / 2), a few fp32 ulps of the terms from the rounded
 // exact value.
 struct GPassDSrc {
+  const float* g8_scales = nullptr;  // GK_FP8: scale of block (I, J) at [I * g8_nsb + J]
+  int64_t g8_nsb = 0;
   const void* D = nullptr;
   int64_t n = 0;
   const double* r = nullptr;

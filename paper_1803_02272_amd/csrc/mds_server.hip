@@ -114,7 +114,7 @@ struct Slot {
 };
 
 bool batchable(const Job* j, int64_t small_n_max) {
-  return j->plan->n <= small_n_max && j->plan->l_pad <= batch_max_l() && j->plan->n <= batch_max_n();
+  return j->plan->form <= MDS_FORM_BF16 && j->plan->n <= small_n_max && j->plan->l_pad <= batch_max_l() && j->plan->n <= batch_max_n();
 }
 
 mds_batch_job batch_entry(const Job* j) {

@@ -32,7 +32,7 @@ struct mds_plan_s {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   bool ws_owned = false;
-  mds::Region G, rowpart, colpart, p4part, r, c, hc, rsum, mean, X, Ypart, Y, Q1, Q, Wpart, W, T, B, V, theta, Tc,
+  mds::Region G, gscale, rowpart, colpart, p4part, r, c, hc, rsum, mean, X, Ypart, Y, Q1, Q, Wpart, W, T, B, V, theta, Tc,
       small, rot, meta, sval, sidx, status;
   size_t total = 0;
   int last_stage = 0;
