@@ -316,66 +316,56 @@ __device__ __forceinline__ uint32_t e4m3_code(float x) {
   return sign | (uint32_t)rintf(a * 512.0f);  // 0..8 units of 2^-9 (8 = 2^-6, the smallest normal)
 }
 
-constexpr int kF8CacheRows = 64;  // rows of a block kept in LDS between the two passes
+constexpr int kF8Threads = 1024;  // one workgroup per 256 x 256 block, the block held in registers
 
-// One workgroup per 256 x 256 block: pass 1 takes the block maximum of
-// |fl32(gamma)|, pass 2 quantizes.  The first kF8CacheRows rows are kept in
-// LDS; the rest are recomputed from D, whose block the infinity cache still
-// holds (the 64 KB of LDS also caps residency at two blocks per CU).
+// Thread t owns columns 4 (t % 64) .. +3 of its block and the 16 rows
+// 16 (t / 64) .. +15: it loads and recentres its 64 entries once (float4
+// loads, 16 in flight), the block maximum is reduced over the workgroup, and
+// the codes are written from registers, so D is read exactly once.
 template <typename DT>
-__global__ __launch_bounds__(256, 2) void k_center_write_fp8(const DT* __restrict__ D, int64_t n, int64_t ldg,
-                                                             const double* __restrict__ r,
-                                                             const double* __restrict__ c,
-                                                             const double* __restrict__ mean_all,
-                                                             uint8_t* __restrict__ G8, float* __restrict__ scales,
-                                                             int64_t nsb) {
+__global__ __launch_bounds__(kF8Threads) void k_center_write_fp8(const DT* __restrict__ D, int64_t n, int64_t ldg,
+                                                               int base_vec, const double* __restrict__ r,
+                                                               const double* __restrict__ c,
+                                                               const double* __restrict__ mean_all,
+                                                               uint8_t* __restrict__ G8, float* __restrict__ scales,
+                                                               int64_t nsb) {
 #pragma clang fp contract(off)
-  __shared__ float cache[kF8CacheRows][kF8Block];
-  __shared__ float red[4];
-  const int64_t J = blockIdx.x, I = blockIdx.y;
+  __shared__ float red[kF8Threads / 64];
   const int tid = threadIdx.x;
-  const int64_t j = J * kF8Block + tid;
-  const int64_t i0 = I * kF8Block;
+  const int64_t J = blockIdx.x, I = blockIdx.y;
+  const int64_t j0 = J * kF8Block + 4 * (tid & 63);
+  const int64_t ib = I * kF8Block + 16 * (tid >> 6);
   const double m = mean_all[0];
-  const double cj = j < n ? c[j] : 0.0;
-  auto g_at = [&](int64_t i, DT d) -> float {
-    if (i >= n || j >= n) return 0.0f;
-    const double dd = (double)d;
-    return (float)(-0.5 * (((dd * dd - cj) - r[i]) + m));
-  };
+  double cj[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) cj[t] = (j0 + t < n) ? c[j0 + t] : 0.0;
+  float g[16][4];
   float mx = 0.0f;
-  for (int ii = 0; ii < kF8Block; ii += 8) {
-    DT d[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t i = i0 + ii + u;
-      d[u] = (i < n && j < n) ? D[i * n + j] : (DT)0;
-    }
+  for (int u = 0; u < 16; ++u) {
+    const int64_t i = ib + u;
+    double d[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < n) load4<DT>(D + i * n, j0, n, row_vec_ok<DT>(base_vec != 0, i, n), d);
+    const double ri = i < n ? r[i] : 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const float g = g_at(i0 + ii + u, d[u]);
-      if (ii + u < kF8CacheRows) cache[ii + u][tid] = g;
-      mx = fmaxf(mx, fabsf(g));
+    for (int t = 0; t < 4; ++t) {
+      g[u][t] = (i < n && j0 + t < n) ? (float)(-0.5 * (((d[t] * d[t] - cj[t]) - ri) + m)) : 0.0f;
+      mx = fmaxf(mx, fabsf(g[u][t]));
     }
   }
   for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
   if ((tid & 63) == 0) red[tid >> 6] = mx;
   __syncthreads();
-  mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  mx = red[0];
+#pragma unroll
+  for (int w = 1; w < kF8Threads / 64; ++w) mx = fmaxf(mx, red[w]);
   const float s = mx > 0.0f ? mx / 448.0f : 1.0f;
   if (tid == 0) scales[I * nsb + J] = s;
-  for (int ii = 0; ii < kF8Block; ii += 8) {
-    DT d[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t i = i0 + ii + u;
-      d[u] = (ii + u >= kF8CacheRows && i < n && j < n) ? D[i * n + j] : (DT)0;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const float g = ii + u < kF8CacheRows ? cache[ii + u][tid] : g_at(i0 + ii + u, d[u]);
-      G8[(i0 + ii + u) * ldg + j] = (uint8_t)e4m3_code(g / s);
-    }
+  for (int u = 0; u < 16; ++u) {
+    const uint32_t w = e4m3_code(g[u][0] / s) | (e4m3_code(g[u][1] / s) << 8) | (e4m3_code(g[u][2] / s) << 16) |
+                       (e4m3_code(g[u][3] / s) << 24);
+    *reinterpret_cast<uint32_t*>(G8 + (ib + u) * ldg + j0) = w;
   }
 }
 
@@ -386,13 +376,14 @@ hipError_t launch_center_write_fp8(const void* D, int d_is_f64, int64_t n, int64
                                    float* scales, hipStream_t s) {
   if (n_pad % kF8Block != 0 || ldg != n_pad) return hipErrorInvalidValue;
   const int64_t nsb = n_pad / kF8Block;
+  const int vec = ((uintptr_t)D % 16) == 0;
   dim3 grid((unsigned)nsb, (unsigned)nsb);
   if (d_is_f64)
-    hipLaunchKernelGGL(k_center_write_fp8<double>, grid, dim3(256), 0, s, (const double*)D, n, ldg, r, c, mean_all,
-                       G8, scales, nsb);
+    hipLaunchKernelGGL(k_center_write_fp8<double>, grid, dim3(kF8Threads), 0, s, (const double*)D, n, ldg, vec, r, c,
+                       mean_all, G8, scales, nsb);
   else
-    hipLaunchKernelGGL(k_center_write_fp8<float>, grid, dim3(256), 0, s, (const float*)D, n, ldg, r, c, mean_all,
-                       G8, scales, nsb);
+    hipLaunchKernelGGL(k_center_write_fp8<float>, grid, dim3(kF8Threads), 0, s, (const float*)D, n, ldg, vec, r, c,
+                       mean_all, G8, scales, nsb);
   return hipGetLastError();
 }
 

@@ -1,0 +1,71 @@
+"""Low-precision stress at full size: n = 100,000 Gaussian-mixture points
+(50 components, 200 dimensions, means N(0, 9 I), unit covariance), fp32
+Euclidean D (40 GB), k = 200, oversample 20, q = 3.
+
+Pin independent of the oracle's code: G = X_c X_c^T exactly (Sec. 6.3: for
+a Euclidean D the Gram matrix is that of the centred points), so its only
+nonzero eigenvalues are the squared singular values of the centred cloud,
+and rank(G) = 200 < l = 220 makes the randomized method exact (Halko et
+al.: Q Q^T G = G).  The FP64 form must reproduce them up to the fp32
+rounding of D; the BF16 and FP8 forms report their error per dtype.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import say
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1803_02272_amd as mds  # noqa: E402
+from workloads import gpu as WG  # noqa: E402
+
+N, DIM, COMPS, VAR, K, P, Q = 100000, 200, 50, 9.0, 200, 20, 3
+
+
+@pytest.mark.timeout(900)
+def test_c4_full_size_against_point_cloud_spectrum():
+    t0 = time.time()
+    X, _ = W.gaussian_mixture(N, DIM, COMPS, VAR, seed=0)
+    Xc = X - X.mean(axis=0, keepdims=True)
+    sig2 = np.sort(np.linalg.eigvalsh(Xc.T @ Xc))[::-1]  # nonzero spectrum of G = Xc Xc^T
+    say(f"[c4] spectrum of the cloud: {sig2[0]:.4e} .. {sig2[-1]:.4e} ({time.time() - t0:.0f} s)")
+    D = WG.euclidean_from_points(X)
+    errs = {}
+    for form in ("fp64", "fp32", "bf16", "fp8"):
+        plan = mds.Plan(N, K, P, Q, 0, form=form)
+        plan.set_timing(True)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        coords, eig = plan.run(D)
+        torch.cuda.synchronize()
+        ms = (time.time() - t1) * 1e3
+        info = plan.info()
+        ph = plan.timings()
+        e = eig.cpu().numpy()
+        errs[form] = float(np.max(np.abs(e - sig2) / sig2))
+        say(f"[c4] form={form}: {ms:.1f} ms, eig rel err vs cloud spectrum {errs[form]:.3e}, "
+            f"fallbacks {info['orth_fallbacks']}, sweeps {info['jacobi_sweeps']}; phases "
+            + ", ".join(f"{a}={b[1]:.1f}" for a, b in ph.items() if b[0]))
+        assert info["status"] == 0
+        if form == "fp64":
+            # distances rounded to fp32 perturb G by about 2^-24 |d^2| per entry
+            assert errs[form] < 1e-5
+            # the embedding reproduces D on a sample of pairs (k = rank)
+            rng = np.random.default_rng(1)
+            i, j = rng.integers(0, N, 2000), rng.integers(0, N, 2000)
+            C = coords.cpu().numpy()
+            dh = np.linalg.norm(C[i] - C[j], axis=1)
+            dd = np.linalg.norm(X[i] - X[j], axis=1)
+            assert np.max(np.abs(dh - dd)) < 1e-4 * np.max(dd)
+        elif form == "fp32":
+            assert errs[form] < 1e-4
+        plan.close()
+        del coords, eig
+        torch.cuda.empty_cache()
+    say(f"[c4] errors per dtype: {errs}")
