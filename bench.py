@@ -28,9 +28,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "n=1e5 k=100 MDS time & MFMA util, BF16 vs FP32 @1e-3 eig err; p99 latency"
 
+# HBM bytes per launch of the G-pass kernels, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE scaled by a plain copy of known size (profiles/
+# mds_n100000_amplicon_k100_bf16_fp32_profile.md), on the n = 1e5, l_pad = 128
+# workload.  Valid only while the kernel source is the one measured: the
+# sha256 prefix of the file is checked and `traffic` is null otherwise.
+TRAFFIC = {
+    "gpass": {"source": "paper_1803_02272_amd/csrc/k_gpass.hip", "sha256_16": "71007befb074d231",
+              "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 20.861, "write_gb": 0.319},
+    "gpass_ref": {"source": "paper_1803_02272_amd/csrc/k_gpass.hip", "sha256_16": "71007befb074d231",
+                  "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 30.189, "write_gb": 0.231},
+}
+
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
+
+
+def measured_traffic(name, n, l_pad, form):
+    """HBM bytes per launch measured for this kernel, workload and source, or None."""
+    import hashlib
+
+    t = TRAFFIC.get(name)
+    if not t or (t["n"], t["l_pad"], t["form"]) != (n, l_pad, form):
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != t["sha256_16"]:
+            return None
+    return (t["fetch_gb"] + t["write_gb"]) * 1e9
 
 
 def log(*a):
@@ -309,7 +334,8 @@ def main():
         achieved = dom["flops"] / (dom["avg"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[dom["dtype"]], "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom_name, n, (l + 15) // 16 * 16, head_form)
+    roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roof["kernel"] = dom["kernel"]
     roof["avg_launch_ms"] = dom["avg"]
     roof["algorithmic_bytes_per_launch"] = dom["bytes"]
