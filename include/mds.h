@@ -189,7 +189,7 @@ mds_status mds_get_info(mds_plan_t plan, mds_info* out, void* stream);
 /* Per-phase timing with HIP events recorded on the run's stream.  Phases: */
 enum {
   MDS_PH_STATS = 0,    /* centring statistics (read D) */
-  MDS_PH_WRITE = 1,    /* centring write (read D, write G) */
+  MDS_PH_WRITE = 1,    /* centring write (read D, write G); bf16 form on fp32 D: fused with range pass 1 */
   MDS_PH_OMEGA = 2,    /* test matrix */
   MDS_PH_GPASS = 3,    /* one G-pass kernel of the range finder (per launch) */
   MDS_PH_REDUCE = 4,   /* split-K reduction of a G-pass */

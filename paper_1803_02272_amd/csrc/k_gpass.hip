@@ -131,8 +131,10 @@ __host__ __device__ constexpr int rg_for(int gk, int cg) {
 }
 // Recentring passes hold raw D values and recentring terms in registers as
 // well; fewer row groups keep two workgroups per CU.
-__host__ __device__ constexpr int rg_fd(int gk, int cg) {
-  return gk == GK_F64 ? (cg <= 3 ? 2 : 1) : (cg <= 4 ? 4 : (cg <= 8 ? 2 : 1));
+__host__ __device__ constexpr int rg_fd(int gk, int cg, bool d8) {
+  if (gk == GK_F64) return cg <= 3 ? 2 : 1;
+  if (gk == GK_BF16) return cg <= 8 ? 2 : 1;  // fused write-and-pass: 8 raw D values per chunk
+  return cg <= (d8 ? 2 : 4) ? 4 : (cg <= 8 ? 2 : 1);  // fp32; fp64 D doubles the raw values
 }
 __host__ __device__ constexpr int minb_for(int gk, int cg) { return (gk == GK_F64 && cg >= 12) ? 1 : 2; }
 
@@ -148,7 +150,8 @@ struct DLoad<void> {
 
 template <int GK, typename DT>
 __host__ __device__ constexpr int minb_of(int cg) {
-  return DLoad<DT>::kFromD ? 2 : minb_for(GK, cg);
+  // fp64 recentring passes with l_pad > 144 need more than 256 registers
+  return DLoad<DT>::kFromD ? ((GK == GK_F64 && cg >= 10) ? 1 : 2) : minb_for(GK, cg);
 }
 
 // E consecutive elements of row i of D starting at column k0 (k0 % E == 0),
@@ -196,6 +199,8 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
   constexpr int PPT = (PIECES + 255) / 256;
   constexpr int BK = 128 / sizeof(XT);  // K elements per step (a 128-byte row of the X tile)
   __shared__ __attribute__((aligned(16))) unsigned char xs[2][LPAD * kRowB];
+  // fused write-and-pass: the step's c_k (fp64) staged with the X tile
+  __shared__ __attribute__((aligned(16))) double cs[(FD && GK == GK_BF16) ? 2 : 1][(FD && GK == GK_BF16) ? BK : 1];
 
   static_assert(!SYM || DLoad<DT>::kFromD, "symmetric mode recentres D on the fly");
   constexpr int64_t kStepsPerBlock = (64 * RG) / BK;  // K steps spanned by one row block
@@ -240,8 +245,14 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
   const int64_t f8_row_block = F8 ? (mb * (64 * RG)) / kF8Block : 0;
 
   // recentring state (only used when FD).  CT: precision of the recentring
-  // terms (fp32 passes use fl32(c/2) and fl32((r - m)/2), fp64 passes c, r, m).
-  using CT = T;
+  // terms (fp32 passes use fl32(c/2) and fl32((r - m)/2), fp64 passes and the
+  // fused bf16 write-and-pass c, r, m in fp64).
+  using CT = typename std::conditional<sizeof(T) == 4, float, double>::type;
+  // Fused centring write: a bf16 pass from D stores the bf16 A operands it
+  // computes, i.e. writes G (bf16 of fl32 of the fp64 gamma) while taking the
+  // first range pass, so that pass does not read G back.
+  constexpr bool WG = FD && GK == GK_BF16;
+  T* Gw = const_cast<T*>(G);
   const DT* Dp = reinterpret_cast<const DT*>(src.D);
   const int64_t n = src.n;
   CT ri[RG];
@@ -276,7 +287,7 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
             // hc holds ldg zero-padded entries: one aligned 16-byte load
             const u32x4 w = *reinterpret_cast<const u32x4*>(src.hc + k0);
             __builtin_memcpy(&cdst[c], &w, 16);
-          } else {
+          } else if constexpr (!WG) {
 #pragma unroll
             for (int t = 0; t < E; ++t) cdst[c][t] = (k0 + t < n) ? src.c[k0 + t] : 0.0;
           }
@@ -297,7 +308,14 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
           }
       }
     };
+    double2 xc = make_double2(0.0, 0.0);  // WG: this thread's two c_k of the step
     auto load_x = [&](int64_t st) {
+      if constexpr (WG) {
+        if (tid < BK / 2) {
+          const int64_t k = st * BK + 2 * tid;
+          xc = make_double2(k < n ? src.c[k] : 0.0, k + 1 < n ? src.c[k + 1] : 0.0);
+        }
+      }
 #pragma unroll
       for (int u = 0; u < PPT; ++u) {
         const int p = tid + 256 * u;
@@ -307,6 +325,9 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
       }
     };
     auto store_x = [&](unsigned char* buf) {
+      if constexpr (WG) {
+        if (tid < BK / 2) *reinterpret_cast<double2*>(&cs[buf == xs[0] ? 0 : 1][2 * tid]) = xc;
+      }
 #pragma unroll
       for (int u = 0; u < PPT; ++u) {
         const int p = tid + 256 * u;
@@ -319,7 +340,7 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
     // fl32(d^2), hc_k + hr_i) (one fma per entry instead of fp64 arithmetic).
     // Symmetric mode: 2 gamma (the same roundings scaled by 2, exactly),
     // times 1, 1/2, 0 right of, on and left of the diagonal.
-    auto a_operand = [&](int rg, int c, int64_t st) -> u32x4 {
+    auto a_operand = [&](int rg, int c, int64_t st, const double* cl) -> u32x4 {
       if constexpr (FD) {
 #pragma clang fp contract(off)
         const int64_t k0 = st * BK + c * (BK / 2) + (lane >> 4) * E;
@@ -341,6 +362,10 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
             }
             const float h = cv[c][t] + ri[rg];
             v = SYM ? __builtin_fmaf(-1.0f, d2, h + h) : __builtin_fmaf(-0.5f, d2, h);
+          } else if constexpr (GK == GK_BF16) {
+            const double d = (double)a[rg][c][t];
+            const double e = ((d * d - cl[c * (BK / 2) + (lane >> 4) * E + t]) - ri[rg]) + mval;
+            v = (T)bf16_bits((float)(-0.5 * e));
           } else {
             const double d = (double)a[rg][c][t];
             const double e = ((d * d - cv[c][t]) - ri[rg]) + mval;
@@ -389,11 +414,18 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
         load_a(an, cvn, st + 1);
       }
       const unsigned char* xb = xs[buf];
+      const double* cl = cs[WG ? buf : 0];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         u32x4 av[RG];
 #pragma unroll
-        for (int rg = 0; rg < RG; ++rg) av[rg] = a_operand(rg, c, st);
+        for (int rg = 0; rg < RG; ++rg) av[rg] = a_operand(rg, c, st, cl);
+        if constexpr (WG) {
+#pragma unroll
+          for (int rg = 0; rg < RG; ++rg)
+            *reinterpret_cast<u32x4*>(Gw + (row0 + rg * 16 + (lane & 15)) * ldg + st * BK + c * (BK / 2) +
+                                      (lane >> 4) * E) = av[rg];
+        }
 #pragma unroll
         for (int cg = 0; cg < CG; ++cg) {
           const u32x4 b =
@@ -497,15 +529,23 @@ hipError_t launch_cg(const void* G, int64_t ldg, const void* Xt, const GPassCfg&
     constexpr int RG = rg_for(GK, CG);
     if (cfg.rg != RG || cfg.sym) return hipErrorInvalidValue;
     launch_one<GK, RG, CG, void, false>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
-  } else if constexpr (GK == GK_BF16 || GK == GK_FP8) {
-    return hipErrorInvalidValue;  // bf16 and fp8 passes read the stored G
+  } else if constexpr (GK == GK_FP8) {
+    return hipErrorInvalidValue;  // fp8 passes read the stored G
+  } else if constexpr (GK == GK_BF16) {
+    // from D: the fused centring write and first range pass (fp32 D only)
+    constexpr int RG = rg_fd(GK, CG, false);
+    if (cfg.rg != RG || cfg.sym || src.d_is_f64 || !G) return hipErrorInvalidValue;
+    launch_one<GK, RG, CG, float, false>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
   } else {
-    constexpr int RG = rg_fd(GK, CG);
-    if (cfg.rg != RG) return hipErrorInvalidValue;
-    if (src.d_is_f64)
+    if (src.d_is_f64) {
+      constexpr int RG = rg_fd(GK, CG, true);
+      if (cfg.rg != RG) return hipErrorInvalidValue;
       launch_fd<GK, RG, CG, double>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
-    else
+    } else {
+      constexpr int RG = rg_fd(GK, CG, false);
+      if (cfg.rg != RG) return hipErrorInvalidValue;
       launch_fd<GK, RG, CG, float>(G, ldg, Xt, cfg, n_pad, Yp, src, s);
+    }
   }
   return hipGetLastError();
 }
@@ -525,9 +565,10 @@ hipError_t launch_gk(const void* G, int64_t ldg, const void* Xt, int l_pad, cons
 
 }  // namespace
 
-GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d, bool sym) {
+GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d, bool sym,
+                      bool d8) {
   GPassCfg c{};
-  c.rg = from_d ? rg_fd(gk, l_pad / 16) : rg_for(gk, l_pad / 16);
+  c.rg = from_d ? rg_fd(gk, l_pad / 16, d8) : rg_for(gk, l_pad / 16);
   c.bm = 64 * c.rg;
   const int64_t esize = gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : 2);
   c.steps_total = ldg * esize / 128;

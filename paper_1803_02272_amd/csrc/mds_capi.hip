@@ -77,7 +77,9 @@ void layout(mds_plan_s* P) {
   const size_t acc_main = P->gk == GK_F64 ? 8 : 4, acc_ref = P->ref_gk == GK_F64 ? 8 : 4;
   const size_t yp_main = (size_t)P->cfg.split * lp * ldg * acc_main;
   const size_t yp_ref = (size_t)P->ref_cfg.split * lp * ldg * acc_ref;
-  add(P, P->Ypart, yp_main > yp_ref ? yp_main : yp_ref);
+  const size_t yp_w = P->fused ? (size_t)P->wcfg.split * lp * ldg * 4 : 0;
+  const size_t yp = yp_main > yp_ref ? yp_main : yp_ref;
+  add(P, P->Ypart, yp > yp_w ? yp : yp_w);
   add(P, P->Y, (size_t)lp * ldg * 8);
   add(P, P->Q1, (size_t)lp * ldg * 8);
   add(P, P->Q, (size_t)lp * ldg * 8);
@@ -188,10 +190,10 @@ mds_status orthonormalize(mds_plan_s* P, hipStream_t s, int xk) {
 
 // One G-pass Y = G X.  The bf16 form's range passes read the stored bf16 G;
 // every other pass recentres D on the fly.
-mds_status gpass(mds_plan_s* P, hipStream_t s, bool ref, const void* D) {
+mds_status gpass(mds_plan_s* P, hipStream_t s, bool ref, const void* D, bool fused = false) {
   const int gk = ref ? P->ref_gk : P->gk;
-  const GPassCfg& cfg = ref ? P->ref_cfg : P->cfg;
-  const bool from_d = ref || !stores_g(P->form);
+  const GPassCfg& cfg = fused ? P->wcfg : (ref ? P->ref_cfg : P->cfg);
+  const bool from_d = ref || fused || !stores_g(P->form);
   GPassDSrc src;
   if (gk == GK_FP8) {
     src.g8_scales = P->at<float>(P->gscale);
@@ -208,10 +210,10 @@ mds_status gpass(mds_plan_s* P, hipStream_t s, bool ref, const void* D) {
     src.d_is_f64 = P->d_dtype == MDS_DTYPE_F64;
   }
   {
-    PhaseTimer tm(P, s, ref ? MDS_PH_GPASS_REF : MDS_PH_GPASS);
-    MDS_TRY(launch_gpass(gk, from_d ? nullptr : P->at<void>(P->G), P->ldg, P->n_pad, P->at<void>(P->X), P->l_pad,
-                         cfg, P->at<void>(P->Ypart), src, s),
-            "gpass");
+    PhaseTimer tm(P, s, fused ? MDS_PH_WRITE : (ref ? MDS_PH_GPASS_REF : MDS_PH_GPASS));
+    MDS_TRY(launch_gpass(gk, (from_d && !fused) ? nullptr : P->at<void>(P->G), P->ldg, P->n_pad,
+                         P->at<void>(P->X), P->l_pad, cfg, P->at<void>(P->Ypart), src, s),
+            fused ? "centring write + range pass 1" : "gpass");
   }
   PhaseTimer tm(P, s, MDS_PH_REDUCE);
   MDS_TRY(launch_splitk_reduce(gk, cfg, P->at<void>(P->Ypart), P->ldg, (int64_t)P->l_pad * P->ldg,
@@ -241,13 +243,15 @@ mds_status mds::run_plan(mds_plan_s* P, const void* D, double* coords, double* e
                               P->at<double>(P->mean), st, s),
           "centring stats");
   }
+  // fused: the bf16 G is written by the first range pass (needs Omega first)
+  const bool fused = P->fused && stop_after >= MDS_STAGE_RANGE;
   if (P->form == MDS_FORM_FP8) {
     PhaseTimer tm(P, s, MDS_PH_WRITE);
     MDS_TRY(launch_center_write_fp8(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->n_pad, P->ldg, P->at<double>(P->r),
                                     P->at<double>(P->c), P->at<double>(P->mean), P->at<uint8_t>(P->G),
                                     P->at<float>(P->gscale), s),
             "centring write fp8");
-  } else if (P->form == MDS_FORM_BF16) {
+  } else if (P->form == MDS_FORM_BF16 && !fused) {
     PhaseTimer tm(P, s, MDS_PH_WRITE);
     MDS_TRY(launch_center_write(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->n_pad, P->ldg, P->at<double>(P->r),
                                 P->at<double>(P->c), P->at<double>(P->mean), P->gk, P->at<void>(P->G), nullptr, s),
@@ -266,7 +270,7 @@ mds_status mds::run_plan(mds_plan_s* P, const void* D, double* coords, double* e
   const int total_range = 2 * P->q + 1;
   const int passes = stop_after == MDS_STAGE_RANGE ? range_passes : total_range;
   for (int it = 0; it < passes; ++it) {
-    mds_status e = gpass(P, s, false, D);
+    mds_status e = gpass(P, s, false, D, fused && it == 0);
     if (e != MDS_OK) return e;
     const int next_xk = (it == total_range - 1) ? P->ref_gk : x_kind(P->gk);
     e = orthonormalize(P, s, next_xk);
@@ -359,9 +363,13 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
           : (o.form == MDS_FORM_FP32 ? GK_F32 : (o.form == MDS_FORM_BF16 ? GK_BF16 : GK_FP8));
   P->ref_gk = stores_g(o.form) ? GK_F32 : P->gk;
   P->flags = o.flags;
-  P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, !stores_g(P->form), false);
+  const bool d8 = o.d_dtype == MDS_DTYPE_F64;
+  P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, !stores_g(P->form), false, d8);
   P->ref_cfg = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, true,
-                            (o.flags & MDS_FLAG_FULL_PROJECTION) == 0);
+                            (o.flags & MDS_FLAG_FULL_PROJECTION) == 0, d8);
+  // bf16 form on fp32 D: the centring write is fused with the first range pass
+  P->fused = o.form == MDS_FORM_BF16 && !d8;
+  if (P->fused) P->wcfg = gpass_config(GK_BF16, P->l_pad, P->n_pad, P->ldg, o.gpass_split, true, false, false);
   layout(P);
   *out = P;
   return MDS_OK;

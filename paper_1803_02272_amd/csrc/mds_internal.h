@@ -82,7 +82,10 @@ struct GPassCfg {
   int64_t sym_cols_per_split;  // K columns per split (symmetric mode)
 };
 // sym (recentring passes only): the projection's symmetric mode, see k_gpass.
-GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d, bool sym);
+// d8: D holds fp64 (recentring passes keep more raw values in registers).
+// gk == GK_BF16 with from_d: the fused centring write and first range pass.
+GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d, bool sym,
+                      bool d8);
 // With D != nullptr the A operand is recentred on the fly from D (ld = n)
 // and G is unused.  fp64 passes: gamma_ij = -1/2 (((d_ij^2 - c_j) - r_i) + m)
 // in fp64 (the stored-G value).  fp32 passes: gamma_ij =
@@ -90,6 +93,7 @@ GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_h
 // hr_i = fl32((r_i - m) / 2), a few fp32 ulps of the terms from the rounded
 // exact value.
 struct GPassDSrc {
+  // (with gk == GK_BF16 and D set, the pass's G argument is the bf16 G it writes)
   const float* g8_scales = nullptr;  // GK_FP8: scale of block (I, J) at [I * g8_nsb + J]
   int64_t g8_nsb = 0;
   const void* D = nullptr;

@@ -28,6 +28,8 @@ struct mds_plan_s {
   int ref_gk = mds::GK_F32;  // dtype of the projection pass
   int flags = 0;
   mds::GPassCfg cfg{}, ref_cfg{};
+  bool fused = false;   // bf16 centring write fused with the first range pass
+  mds::GPassCfg wcfg{};  // its configuration
   // workspace
   void* ws = nullptr;
   size_t ws_bytes = 0;
