@@ -16,10 +16,124 @@
 namespace mds {
 namespace {
 
-constexpr int kGramChunk = 512;  // columns of the transposed layout per gram workgroup
+__device__ __forceinline__ uint16_t bf16_rne(double v) {
+  uint32_t u = __float_as_uint((float)v);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x0040u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
 
+constexpr int kGramChunk = 512;   // columns of the transposed layout per gram workgroup
+constexpr int kGramStep = 32;     // columns staged in LDS per step
+constexpr int kGramRow = kGramStep + 1;  // LDS row stride (doubles)
+constexpr int kGramThreads = 512;
+
+// Wpart[p] = A_p B_p^T over column chunk p: every workgroup stages 32-column
+// slices of all l_pad rows of A (and B) in LDS (double-buffered, 16-byte
+// loads), and each of its 8 waves accumulates a share of the 16 x 16 output
+// tiles with fp64 MFMA (16x16x4).  sym (A == B): only tiles on or above the
+// diagonal are computed; k_sum_parts mirrors them.
+template <int CG, bool SYM>
+__global__ __launch_bounds__(kGramThreads) void k_gram(const double* __restrict__ A, const double* __restrict__ B,
+                                                       int64_t ldg, int l_pad, double* __restrict__ Wpart) {
+  constexpr int NT = SYM ? CG * (CG + 1) / 2 : CG * CG;  // output tiles
+  constexpr int NW = kGramThreads / 64;
+  constexpr int TPW = (NT + NW - 1) / NW;  // tiles per wave (at most)
+  constexpr int LP = CG * 16;
+  constexpr int NB = SYM ? 1 : 2;  // staged matrices
+  __shared__ double st[2][NB][LP * kGramRow];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * kGramChunk;
+  const int64_t i1 = (i0 + kGramChunk < ldg) ? i0 + kGramChunk : ldg;  // ldg is a multiple of 256
+  // this wave's tiles (ta, tb), ta <= tb when SYM
+  int ta[TPW], tb[TPW];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    int t = wave + NW * u, a = 0;
+    if (t >= NT) t = NT - 1;  // duplicate of a live tile, not stored
+    if constexpr (SYM) {
+      while (t >= CG - a) {
+        t -= CG - a;
+        ++a;
+      }
+      ta[u] = a;
+      tb[u] = a + t;
+    } else {
+      ta[u] = t / CG;
+      tb[u] = t % CG;
+    }
+  }
+  doublex4_t acc[TPW];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) acc[u] = doublex4_t{0.0, 0.0, 0.0, 0.0};
+  // staging: LP rows x 32 doubles per matrix = LP * 16 pieces of 16 bytes
+  constexpr int PIECES = LP * (kGramStep / 2);
+  constexpr int PPT = (PIECES + kGramThreads - 1) / kGramThreads;
+  double2 rg[NB][PPT];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int m = 0; m < NB; ++m)
+#pragma unroll
+      for (int u = 0; u < PPT; ++u) {
+        const int pc = tid + kGramThreads * u;
+        if (PIECES % kGramThreads == 0 || pc < PIECES) {
+          const int row = pc / (kGramStep / 2), c2 = pc % (kGramStep / 2);
+          const double* src = (m == 0 ? A : B) + (int64_t)row * ldg + k0 + 2 * c2;
+          rg[m][u] = k0 < i1 ? *reinterpret_cast<const double2*>(src) : double2{0.0, 0.0};
+        }
+      }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int m = 0; m < NB; ++m)
+#pragma unroll
+      for (int u = 0; u < PPT; ++u) {
+        const int pc = tid + kGramThreads * u;
+        if (PIECES % kGramThreads == 0 || pc < PIECES) {
+          const int row = pc / (kGramStep / 2), c2 = pc % (kGramStep / 2);
+          st[buf][m][row * kGramRow + 2 * c2] = rg[m][u].x;
+          st[buf][m][row * kGramRow + 2 * c2 + 1] = rg[m][u].y;
+        }
+      }
+  };
+  load(i0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = i0; k0 < i1; k0 += kGramStep) {
+    const bool more = k0 + kGramStep < i1;
+    if (more) load(k0 + kGramStep);
+    const double* SA = st[buf][0];
+    const double* SB = st[buf][NB - 1];
+#pragma unroll
+    for (int kg = 0; kg < kGramStep; kg += 4) {
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        // fp64 MFMA operands: lane supplies row l % 16 and K index l / 16
+        const double av = SA[(ta[u] * 16 + (lane & 15)) * kGramRow + kg + (lane >> 4)];
+        const double bv = SB[(tb[u] * 16 + (lane & 15)) * kGramRow + kg + (lane >> 4)];
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+      }
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  double* W = Wpart + blockIdx.x * (int64_t)l_pad * l_pad;
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    if (wave + NW * u >= NT) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      // fp64 MFMA accumulator: register r of lane group g is row g + 4r
+      W[(int64_t)(ta[u] * 16 + (lane >> 4) + 4 * r) * l_pad + tb[u] * 16 + (lane & 15)] = acc[u][r];
+  }
+}
+
+// Register-streamed variant for l_pad > 128 (the LDS tiles of k_gram would
+// not fit): each wave owns a 16-row tile strip over a 512-column chunk.
 template <int CG>
-__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, const double* __restrict__ B,
+__global__ __launch_bounds__(256) void k_gram_wide(const double* __restrict__ A, const double* __restrict__ B,
                                               int64_t ldg, int l_pad, double* __restrict__ Wpart) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tr = blockIdx.y * 4 + wave;  // 16-row tile of W
@@ -65,23 +179,43 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, cons
       W[(int64_t)(tr * 16 + (lane >> 4) + 4 * r) * l_pad + cg * 16 + (lane & 15)] = acc[cg][r];
 }
 
+// out[i][j] = sum_p parts[p][i][j] in partial order; sym: only entries of
+// tiles on or above the diagonal were computed, and each such sum is also
+// written to the mirrored entry.
 __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ parts, int64_t nparts,
-                                                   int64_t elems, double* __restrict__ out) {
+                                                   int64_t elems, double* __restrict__ out, int l_pad, int sym) {
 #pragma clang fp contract(off)
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= elems) return;
+  const int i = (int)(e / l_pad), j = (int)(e % l_pad);
+  if (sym && (j >> 4) < (i >> 4)) return;  // written by its mirror
   double s = 0.0;
 #pragma unroll 8
   for (int64_t p = 0; p < nparts; ++p) s += parts[p * elems + e];
   out[e] = s;
+  if (sym && (j >> 4) > (i >> 4)) out[(int64_t)j * l_pad + i] = s;
 }
 
-__device__ __forceinline__ uint16_t bf16_rne(double v) {
-  uint32_t u = __float_as_uint((float)v);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x0040u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+// Xc = cast(Out) for the next G-pass operand, 4 consecutive entries per thread.
+template <int XK>
+__global__ __launch_bounds__(256) void k_cast(const double* __restrict__ In, int64_t elems, void* __restrict__ Xc) {
+  const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (e >= elems) return;  // elems is a multiple of 4
+  const double2 a = reinterpret_cast<const double2*>(In + e)[0];
+  const double2 b = reinterpret_cast<const double2*>(In + e)[1];
+  if constexpr (XK == GK_F64) {
+    reinterpret_cast<double2*>(reinterpret_cast<double*>(Xc) + e)[0] = a;
+    reinterpret_cast<double2*>(reinterpret_cast<double*>(Xc) + e)[1] = b;
+  } else if constexpr (XK == GK_F32) {
+    *reinterpret_cast<float4*>(reinterpret_cast<float*>(Xc) + e) = make_float4((float)a.x, (float)a.y, (float)b.x,
+                                                                               (float)b.y);
+  } else {
+    const uint32_t lo = bf16_rne(a.x) | ((uint32_t)bf16_rne(a.y) << 16);
+    const uint32_t hi = bf16_rne(b.x) | ((uint32_t)bf16_rne(b.y) << 16);
+    *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(Xc) + e) = make_uint2(lo, hi);
+  }
 }
+
 
 // Out[j][i] = sum_a T[a][j] In[a][i] on fp64 MFMA (16x16x4): A operand = T^T
 // (rows j, K = a) from an LDS block of 64 columns of T, B operand = In (K = a,
@@ -94,7 +228,7 @@ constexpr int kApN = 4;           // 16-column tiles per wave
 
 __global__ __launch_bounds__(256) void k_apply(const double* __restrict__ In, int l, int64_t ldg,
                                                const double* __restrict__ T, int ldt, int lt, int l_out,
-                                               double* __restrict__ Out, int xk, void* __restrict__ Xc) {
+                                               double* __restrict__ Out) {
   extern __shared__ double Ts[];  // la x kApRow
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int la = (l + 3) & ~3;
@@ -112,10 +246,15 @@ __global__ __launch_bounds__(256) void k_apply(const double* __restrict__ In, in
     for (int t = 0; t < 4; ++t) acc[nt][t] = doublex4_t{0.0, 0.0, 0.0, 0.0};
   const double* Ib = In + (int64_t)(lane >> 4) * ldg + i0 + (lane & 15);
   const int ar = lane >> 4, jc = lane & 15;
-  for (int a0 = 0; a0 < la; a0 += 4) {
-    double b[kApN];
+  // software pipeline: the In rows of step a0 + 4 load while step a0 runs
+  double b[kApN];
 #pragma unroll
-    for (int nt = 0; nt < kApN; ++nt) b[nt] = Ib[(int64_t)a0 * ldg + nt * 16];
+  for (int nt = 0; nt < kApN; ++nt) b[nt] = Ib[nt * 16];
+  for (int a0 = 0; a0 < la; a0 += 4) {
+    double bn[kApN];
+    const bool more = a0 + 4 < la;
+#pragma unroll
+    for (int nt = 0; nt < kApN; ++nt) bn[nt] = more ? Ib[(int64_t)(a0 + 4) * ldg + nt * 16] : 0.0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const double av = Ts[(a0 + ar) * kApRow + t * 16 + jc];
@@ -123,27 +262,23 @@ __global__ __launch_bounds__(256) void k_apply(const double* __restrict__ In, in
       for (int nt = 0; nt < kApN; ++nt)
         acc[nt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[nt], acc[nt][t], 0, 0, 0);
     }
+#pragma unroll
+    for (int nt = 0; nt < kApN; ++nt) b[nt] = bn[nt];
   }
   // fp64 accumulator layout: register r of lane group g is row g + 4r
 #pragma unroll
   for (int nt = 0; nt < kApN; ++nt)
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < 4; ++t) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int j = j0 + t * 16 + (lane >> 4) + 4 * r;
         if (j < l_out) {
           const int64_t o = (int64_t)j * ldg + i0 + nt * 16 + (lane & 15);
-          const double v = acc[nt][t][r];
-          Out[o] = v;
-          if (xk == GK_F64)
-            reinterpret_cast<double*>(Xc)[o] = v;
-          else if (xk == GK_F32)
-            reinterpret_cast<float*>(Xc)[o] = (float)v;
-          else if (xk == GK_BF16)
-            reinterpret_cast<uint16_t*>(Xc)[o] = bf16_rne(v);
+          Out[o] = acc[nt][t][r];
         }
       }
+    }
 }
 
 // Better candidate for the column's sign anchor: larger magnitude, then lower row.
@@ -241,8 +376,14 @@ __global__ __launch_bounds__(256) void k_coords_write(const double* __restrict__
 
 template <int CG>
 void gram_one(const double* A, const double* B, int l_pad, int64_t ldg, double* Wpart, hipStream_t s) {
-  dim3 grid((unsigned)((ldg + kGramChunk - 1) / kGramChunk), (unsigned)((CG + 3) / 4));
-  hipLaunchKernelGGL(k_gram<CG>, grid, dim3(256), 0, s, A, B, ldg, l_pad, Wpart);
+  dim3 grid((unsigned)((ldg + kGramChunk - 1) / kGramChunk));
+  if constexpr (CG > 8)
+    hipLaunchKernelGGL(k_gram_wide<CG>, dim3(grid.x, (unsigned)((CG + 3) / 4)), dim3(256), 0, s, A, B, ldg, l_pad,
+                       Wpart);
+  else if (A == B)
+    hipLaunchKernelGGL((k_gram<CG, true>), grid, dim3(kGramThreads), 0, s, A, B, ldg, l_pad, Wpart);
+  else
+    hipLaunchKernelGGL((k_gram<CG, false>), grid, dim3(kGramThreads), 0, s, A, B, ldg, l_pad, Wpart);
 }
 
 }  // namespace
@@ -251,6 +392,7 @@ int64_t gram_chunks(int64_t ldg) { return (ldg + kGramChunk - 1) / kGramChunk; }
 
 hipError_t launch_gram(const double* A, const double* B, int l_pad, int64_t ldg, double* Wpart, double* W,
                        hipStream_t s) {
+  if (ldg % kGramStep != 0) return hipErrorInvalidValue;
   switch (l_pad / 16) {
 #define MDS_G(N) \
   case N: gram_one<N>(A, B, l_pad, ldg, Wpart, s); break;
@@ -261,7 +403,7 @@ hipError_t launch_gram(const double* A, const double* B, int l_pad, int64_t ldg,
   }
   const int64_t elems = (int64_t)l_pad * l_pad;
   hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, Wpart,
-                     gram_chunks(ldg), elems, W);
+                     gram_chunks(ldg), elems, W, l_pad, (A == B && l_pad <= 128) ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -272,12 +414,25 @@ hipError_t launch_apply(const double* In, int l, int64_t ldg, const double* T, i
   const size_t shm = (size_t)la * kApRow * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(kMaxL * kApRow * sizeof(double)));
+    const int mx = (int)(kMaxL * kApRow * sizeof(double));
+    (void)hipFuncSetAttribute((const void*)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     attr_set = true;
   }
   dim3 grid((unsigned)(ldg / (64 * kApN)), (unsigned)((l_pad + kApJ - 1) / kApJ));
-  hipLaunchKernelGGL(k_apply, grid, dim3(256), shm, s, In, l, ldg, T, ldt, lt, l_pad, Out, Xc ? xk : -1, Xc);
+  hipLaunchKernelGGL(k_apply, grid, dim3(256), shm, s, In, l, ldg, T, ldt, lt, l_pad, Out);
+  if (Xc) {
+    // the cast copy in its own elementwise kernel keeps k_apply at two waves per SIMD
+    const int64_t elems = (int64_t)l_pad * ldg;
+    const dim3 cg((unsigned)((elems / 4 + 255) / 256));
+    if (xk == GK_F64)
+      hipLaunchKernelGGL(k_cast<GK_F64>, cg, dim3(256), 0, s, Out, elems, Xc);
+    else if (xk == GK_F32)
+      hipLaunchKernelGGL(k_cast<GK_F32>, cg, dim3(256), 0, s, Out, elems, Xc);
+    else if (xk == GK_BF16)
+      hipLaunchKernelGGL(k_cast<GK_BF16>, cg, dim3(256), 0, s, Out, elems, Xc);
+    else
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
