@@ -70,8 +70,13 @@ def percentile(xs, p):
     return xs[i]
 
 
-def time_form(mds, torch, D, n, k, p, q, form, steps, warmup):
+def time_form(mds, torch, D, n, k, p, q, form, steps, warmup, autotune=True):
     plan = mds.Plan(n, k, p, q, 0, form=form)
+    tuned = None
+    if autotune:
+        t0 = time.perf_counter()
+        tuned = plan.autotune(D)
+        log(f"[bench] form={form}: autotuned splits {tuned} in {time.perf_counter() - t0:.1f} s")
     plan.attach_workspace()
     coords = torch.empty((n, k), dtype=torch.float64, device="cuda")
     eig = torch.empty((k,), dtype=torch.float64, device="cuda")
@@ -104,6 +109,7 @@ def time_form(mds, torch, D, n, k, p, q, form, steps, warmup):
         "eig": eig.double().cpu().numpy(),
         "info": info,
         "gpass_split": info["gpass_split"],
+        "autotune": tuned,
     }
     plan.close()
     del coords
@@ -243,6 +249,7 @@ def main():
     ap.add_argument("--q", type=int, default=2)
     ap.add_argument("--forms", default="bf16,fp32,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default split-K of every pass")
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="open-loop duration of the serving mix after its warm-up (0 = skip serving)")
@@ -284,7 +291,7 @@ def main():
         steps = args.steps if form != "fp64" else 1
         warm = args.warmup if form != "fp64" else 0
         log(f"[bench] form={form} warmup={warm} steps={steps}")
-        res[form] = time_form(mds, torch, D, n, k, p, q, form, steps, warm)
+        res[form] = time_form(mds, torch, D, n, k, p, q, form, steps, warm, autotune=not args.no_autotune)
         log(f"[bench] form={form}: {res[form]['ms']:.2f} ms/step; phases "
             + ", ".join(f"{a}={b['total_ms']:.2f}" for a, b in res[form]["phases"].items() if b["count"]))
     del D
@@ -383,7 +390,8 @@ def main():
         "p99_ms": head["p99_ms"],
         "forms": {f: {"ms": r["ms"], "p99_ms": r["p99_ms"], "eig_rel_err_vs_fp64_form": eig_err(f),
                       "phases_ms": {a: round(b["total_ms"], 4) for a, b in r["phases"].items() if b["count"]},
-                      "gpass_split": r["gpass_split"], "orth_fallbacks": r["info"]["orth_fallbacks"],
+                      "gpass_split": r["gpass_split"], "autotune": r["autotune"],
+                      "orth_fallbacks": r["info"]["orth_fallbacks"],
                       "jacobi_sweeps": r["info"]["jacobi_sweeps"]} for f, r in res.items()},
         "gemm": gemm,
         "speedup_bf16_vs_fp32": (res["fp32"]["ms"] / res["bf16"]["ms"]) if ("bf16" in res and "fp32" in res)

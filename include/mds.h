@@ -87,8 +87,10 @@ typedef enum mds_dtype { MDS_DTYPE_F32 = 0, MDS_DTYPE_F64 = 1 } mds_dtype;
 typedef struct mds_opts {
   int32_t form;        /* mds_form (default MDS_FORM_FP32) */
   int32_t d_dtype;     /* mds_dtype (default MDS_DTYPE_F32) */
-  int32_t gpass_split; /* K-splits of the G-pass, 0 = automatic */
+  int32_t gpass_split; /* K-splits of the range passes, 0 = automatic */
   int32_t flags;       /* MDS_FLAG_* bits, 0 = defaults; other bits are rejected */
+  int32_t proj_split;  /* K-splits of the projection pass, 0 = as gpass_split */
+  int32_t write_split; /* K-splits of the fused centring write + first range pass, 0 = as gpass_split */
 } mds_opts;
 
 typedef struct mds_plan_s* mds_plan_t;
@@ -210,6 +212,19 @@ mds_status mds_set_timing(mds_plan_t plan, int32_t enable);
 /* Synchronise `stream`, then fill out[MDS_NUM_PHASES] with the phases timed
  * since the previous call, and reset the accumulators. */
 mds_status mds_get_timings(mds_plan_t plan, mds_phase_time* out, void* stream);
+
+/* Autotuner of a plan: times every split-K candidate (the K extent of a
+ * workgroup's tile) of the range pass, the projection pass and, in the bf16
+ * form on fp32 D, the fused centring write, on this plan's shape and the
+ * given D; stores the fastest in the plan's options (copies made by the
+ * server inherit them) and reports them.  Must be called before a workspace
+ * is attached; allocates and frees a temporary one; synchronises `stream`. */
+typedef struct mds_tune_result {
+  int32_t range_split, proj_split, write_split, pad_;
+  float range_ms, proj_ms, write_ms; /* best per-launch times (pass + split-K reduction) */
+  int32_t candidates;                /* configurations timed */
+} mds_tune_result;
+mds_status mds_autotune(mds_plan_t plan, const void* D, void* stream, mds_tune_result* out);
 
 void mds_destroy(mds_plan_t plan);
 

@@ -38,14 +38,15 @@ class Plan:
     the projection pass instead of its upper triangle (MDS_FLAG_FULL_PROJECTION)."""
 
     def __init__(self, n, k, oversample=10, q=2, seed=0, form="fp32", d_dtype="f32", gpass_split=0,
-                 workspace="torch", full_projection=False):
+                 workspace="torch", full_projection=False, proj_split=0, write_split=0):
         L = _capi.lib()
         self.n, self.k, self.oversample, self.q, self.seed = int(n), int(k), int(oversample), int(q), int(seed)
         self.form = form
         self.d_dtype = d_dtype
         opts = _capi.MdsOpts(FORMS[form] if isinstance(form, str) else int(form),
                              _capi.DTYPE_F64 if d_dtype in ("f64", "float64") else _capi.DTYPE_F32,
-                             int(gpass_split), _capi.FLAG_FULL_PROJECTION if full_projection else 0)
+                             int(gpass_split), _capi.FLAG_FULL_PROJECTION if full_projection else 0,
+                             int(proj_split), int(write_split))
         h = ctypes.c_void_p()
         check(L.mds_plan_ex(ctypes.byref(h), self.n, self.k, self.oversample, self.q, self.seed,
                             ctypes.byref(opts)), "mds_plan_ex")
@@ -75,6 +76,15 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def autotune(self, D, stream=None):
+        """Time the split-K candidates of each pass kind on D and keep the
+        fastest (call before the first run); returns the chosen splits."""
+        self._check_D(D)
+        r = _capi.MdsTuneResult()
+        check(_capi.lib().mds_autotune(self._h, ctypes.c_void_p(D.data_ptr()), _stream_handle(stream),
+                                       ctypes.byref(r)), "mds_autotune")
+        return r.as_dict()
 
     # -- workspace -----------------------------------------------------------
     def workspace_size(self) -> int:

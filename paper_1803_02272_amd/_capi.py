@@ -44,7 +44,8 @@ FLAG_FULL_PROJECTION = 1
 
 class MdsOpts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("d_dtype", ctypes.c_int32),
-                ("gpass_split", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("gpass_split", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("proj_split", ctypes.c_int32), ("write_split", ctypes.c_int32)]
 
 
 class MdsBuffer(ctypes.Structure):
@@ -77,6 +78,15 @@ class MdsBatchJob(ctypes.Structure):
     _fields_ = [("D", ctypes.c_void_p), ("coords", ctypes.c_void_p), ("eigvals", ctypes.c_void_p),
                 ("n", ctypes.c_int64), ("k", ctypes.c_int32), ("oversample", ctypes.c_int32),
                 ("q", ctypes.c_int32), ("d_dtype", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class MdsTuneResult(ctypes.Structure):
+    _fields_ = [("range_split", ctypes.c_int32), ("proj_split", ctypes.c_int32), ("write_split", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("range_ms", ctypes.c_float), ("proj_ms", ctypes.c_float),
+                ("write_ms", ctypes.c_float), ("candidates", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad_"}
 
 
 class MdsBatchTune(ctypes.Structure):
@@ -114,6 +124,8 @@ SIGNATURES = {
     "mds_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MdsInfo), ctypes.c_void_p]),
     "mds_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mds_get_timings": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MdsPhaseTime), ctypes.c_void_p]),
+    "mds_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.POINTER(MdsTuneResult)]),
     "mds_destroy": (None, [ctypes.c_void_p]),
     "mds_batch_workspace_size": (ctypes.c_int, [ctypes.POINTER(MdsBatchJob), ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_size_t)]),

@@ -78,8 +78,9 @@ void layout(mds_plan_s* P) {
   const size_t yp_main = (size_t)P->cfg.split * lp * ldg * acc_main;
   const size_t yp_ref = (size_t)P->ref_cfg.split * lp * ldg * acc_ref;
   const size_t yp_w = P->fused ? (size_t)P->wcfg.split * lp * ldg * 4 : 0;
-  const size_t yp = yp_main > yp_ref ? yp_main : yp_ref;
-  add(P, P->Ypart, yp > yp_w ? yp : yp_w);
+  size_t yp = yp_main > yp_ref ? yp_main : yp_ref;
+  yp = yp > yp_w ? yp : yp_w;
+  add(P, P->Ypart, yp > P->ypart_min ? yp : P->ypart_min);
   add(P, P->Y, (size_t)lp * ldg * 8);
   add(P, P->Q1, (size_t)lp * ldg * 8);
   add(P, P->Q, (size_t)lp * ldg * 8);
@@ -97,6 +98,22 @@ void layout(mds_plan_s* P) {
   add(P, P->sval, (size_t)(nch * P->k + P->k) * 8);
   add(P, P->sidx, (size_t)nch * P->k * 8);
   add(P, P->status, sizeof(DevStatus));
+}
+
+// Pass configurations from the plan's options (split-K per pass kind), then
+// the workspace layout.
+void configure(mds_plan_s* P) {
+  const mds_opts& o = P->opts;
+  const bool d8 = o.d_dtype == MDS_DTYPE_F64;
+  P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, !stores_g(P->form), false, d8);
+  P->ref_cfg = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, o.proj_split ? o.proj_split : o.gpass_split,
+                            true, (o.flags & MDS_FLAG_FULL_PROJECTION) == 0, d8);
+  // bf16 form on fp32 D: the centring write is fused with the first range pass
+  P->fused = o.form == MDS_FORM_BF16 && !d8;
+  if (P->fused)
+    P->wcfg = gpass_config(GK_BF16, P->l_pad, P->n_pad, P->ldg, o.write_split ? o.write_split : o.gpass_split,
+                           true, false, false);
+  layout(P);
 }
 
 // Bracket a phase with events on the stream when timing is enabled.
@@ -190,10 +207,29 @@ mds_status orthonormalize(mds_plan_s* P, hipStream_t s, int xk) {
 
 // One G-pass Y = G X.  The bf16 form's range passes read the stored bf16 G;
 // every other pass recentres D on the fly.
+GPassDSrc make_src(mds_plan_s* P, int gk, bool from_d, const void* D);
+
 mds_status gpass(mds_plan_s* P, hipStream_t s, bool ref, const void* D, bool fused = false) {
   const int gk = ref ? P->ref_gk : P->gk;
   const GPassCfg& cfg = fused ? P->wcfg : (ref ? P->ref_cfg : P->cfg);
   const bool from_d = ref || fused || !stores_g(P->form);
+  const GPassDSrc src = make_src(P, gk, from_d, D);
+  {
+    PhaseTimer tm(P, s, fused ? MDS_PH_WRITE : (ref ? MDS_PH_GPASS_REF : MDS_PH_GPASS));
+    MDS_TRY(launch_gpass(gk, (from_d && !fused) ? nullptr : P->at<void>(P->G), P->ldg, P->n_pad,
+                         P->at<void>(P->X), P->l_pad, cfg, P->at<void>(P->Ypart), src, s),
+            fused ? "centring write + range pass 1" : "gpass");
+  }
+  PhaseTimer tm(P, s, MDS_PH_REDUCE);
+  MDS_TRY(launch_splitk_reduce(gk, cfg, P->at<void>(P->Ypart), P->ldg, (int64_t)P->l_pad * P->ldg,
+                               P->at<double>(P->Y), s),
+          "splitk_reduce");
+  return MDS_OK;
+}
+
+// Source of a G-pass: block scales of a stored fp8 G, or D and the centring
+// terms when the pass recentres D.
+GPassDSrc make_src(mds_plan_s* P, int gk, bool from_d, const void* D) {
   GPassDSrc src;
   if (gk == GK_FP8) {
     src.g8_scales = P->at<float>(P->gscale);
@@ -209,17 +245,7 @@ mds_status gpass(mds_plan_s* P, hipStream_t s, bool ref, const void* D, bool fus
     src.vec = ((uintptr_t)D % 16) == 0;
     src.d_is_f64 = P->d_dtype == MDS_DTYPE_F64;
   }
-  {
-    PhaseTimer tm(P, s, fused ? MDS_PH_WRITE : (ref ? MDS_PH_GPASS_REF : MDS_PH_GPASS));
-    MDS_TRY(launch_gpass(gk, (from_d && !fused) ? nullptr : P->at<void>(P->G), P->ldg, P->n_pad,
-                         P->at<void>(P->X), P->l_pad, cfg, P->at<void>(P->Ypart), src, s),
-            fused ? "centring write + range pass 1" : "gpass");
-  }
-  PhaseTimer tm(P, s, MDS_PH_REDUCE);
-  MDS_TRY(launch_splitk_reduce(gk, cfg, P->at<void>(P->Ypart), P->ldg, (int64_t)P->l_pad * P->ldg,
-                               P->at<double>(P->Y), s),
-          "splitk_reduce");
-  return MDS_OK;
+  return src;
 }
 
 }  // namespace
@@ -329,7 +355,7 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
                        const mds_opts* opts) {
   if (!out) return fail(MDS_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  mds_opts o = {MDS_FORM_FP32, MDS_DTYPE_F32, 0, 0};
+  mds_opts o = {MDS_FORM_FP32, MDS_DTYPE_F32, 0, 0, 0, 0};
   if (opts) o = *opts;
   if (n < 2) return fail(MDS_ERR_INVALID_ARG, "n = %lld < 2", (long long)n);
   if (n > 1000000) return fail(MDS_ERR_INVALID_ARG, "n = %lld > 1000000", (long long)n);
@@ -343,7 +369,8 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
     return fail(MDS_ERR_INVALID_ARG, "unknown form %d", o.form);
   if (o.d_dtype != MDS_DTYPE_F32 && o.d_dtype != MDS_DTYPE_F64)
     return fail(MDS_ERR_INVALID_ARG, "unknown D dtype %d", o.d_dtype);
-  if (o.gpass_split < 0) return fail(MDS_ERR_INVALID_ARG, "gpass_split = %d < 0", o.gpass_split);
+  if (o.gpass_split < 0 || o.proj_split < 0 || o.write_split < 0)
+    return fail(MDS_ERR_INVALID_ARG, "negative split (%d, %d, %d)", o.gpass_split, o.proj_split, o.write_split);
   if (o.flags & ~MDS_FLAG_FULL_PROJECTION) return fail(MDS_ERR_INVALID_ARG, "unknown flags 0x%x", o.flags);
   mds_plan_s* P = new (std::nothrow) mds_plan_s();
   if (!P) return fail(MDS_ERR_OOM, "host allocation failed");
@@ -363,14 +390,7 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
           : (o.form == MDS_FORM_FP32 ? GK_F32 : (o.form == MDS_FORM_BF16 ? GK_BF16 : GK_FP8));
   P->ref_gk = stores_g(o.form) ? GK_F32 : P->gk;
   P->flags = o.flags;
-  const bool d8 = o.d_dtype == MDS_DTYPE_F64;
-  P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, !stores_g(P->form), false, d8);
-  P->ref_cfg = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, true,
-                            (o.flags & MDS_FLAG_FULL_PROJECTION) == 0, d8);
-  // bf16 form on fp32 D: the centring write is fused with the first range pass
-  P->fused = o.form == MDS_FORM_BF16 && !d8;
-  if (P->fused) P->wcfg = gpass_config(GK_BF16, P->l_pad, P->n_pad, P->ldg, o.gpass_split, true, false, false);
-  layout(P);
+  configure(P);
   *out = P;
   return MDS_OK;
 }
@@ -512,6 +532,108 @@ mds_status mds_get_timings(mds_plan_t plan, mds_phase_time* out, void* stream) {
   }
   plan->rec_phase.clear();
   return MDS_OK;
+}
+
+mds_status mds_autotune(mds_plan_t P, const void* D, void* stream, mds_tune_result* out) {
+  if (!P || !D || !out) return fail(MDS_ERR_INVALID_ARG, "NULL argument");
+  if (P->ws) return fail(MDS_ERR_STATE, "autotune before a workspace is attached or allocated");
+  mds_status st = device_present();
+  if (st != MDS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  static const int kCands[] = {0, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48};
+  const bool d8 = P->d_dtype == MDS_DTYPE_F64;
+  const bool sym = (P->opts.flags & MDS_FLAG_FULL_PROJECTION) == 0;
+  auto cfg_of = [&](int kind, int split) {
+    if (kind == 0) return gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, split, !stores_g(P->form), false, d8);
+    if (kind == 1) return gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, split, true, sym, d8);
+    return gpass_config(GK_BF16, P->l_pad, P->n_pad, P->ldg, split, true, false, false);
+  };
+  const int kinds = P->fused ? 3 : 2;
+  // workspace sized for the largest candidate's partials
+  size_t ymax = 0;
+  for (int kind = 0; kind < kinds; ++kind)
+    for (int c : kCands) {
+      const GPassCfg g = cfg_of(kind, c);
+      const int gk = kind == 0 ? P->gk : (kind == 1 ? P->ref_gk : GK_BF16);
+      const size_t b = (size_t)g.split * P->l_pad * P->ldg * (gk == GK_F64 ? 8 : 4);
+      ymax = b > ymax ? b : ymax;
+    }
+  P->ypart_min = ymax;
+  layout(P);
+  st = ensure_workspace(P);
+  if (st != MDS_OK) {
+    P->ypart_min = 0;
+    layout(P);
+    return st;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto finish = [&](mds_status r) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(P->ws);
+    P->ws = nullptr;
+    P->ws_owned = false;
+    P->ws_bytes = 0;
+    P->ypart_min = 0;
+    configure(P);
+    return r;
+  };
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return finish(fail(MDS_ERR_HIP, "event creation failed"));
+  // centring, stored G and Omega in the workspace
+  st = run_plan(P, D, nullptr, nullptr, s, MDS_STAGE_OMEGA, 0);
+  if (st != MDS_OK) return finish(st);
+  int best[3] = {0, 0, 0};
+  float best_ms[3] = {0.f, 0.f, 0.f};
+  int timed = 0;
+  for (int kind = 0; kind < kinds; ++kind) {
+    const int gk = kind == 0 ? P->gk : (kind == 1 ? P->ref_gk : GK_BF16);
+    const bool from_d = kind != 0 || !stores_g(P->form);
+    const GPassDSrc src = make_src(P, gk, from_d, D);
+    void* G = (kind == 2 || !from_d) ? P->at<void>(P->G) : nullptr;
+    float kbest = 1e30f;
+    int last_split = -1;
+    for (int c : kCands) {
+      const GPassCfg g = cfg_of(kind, c);
+      if (g.split == last_split && c != 0) continue;  // same configuration as a candidate already timed
+      last_split = g.split;
+      float ms_best = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {  // first launch warms up
+        float ms = 0.f;
+        hipError_t e = hipEventRecord(e0, s);
+        if (e == hipSuccess)
+          e = launch_gpass(gk, G, P->ldg, P->n_pad, P->at<void>(P->X), P->l_pad, g, P->at<void>(P->Ypart), src, s);
+        // the split-K reduction grows with the split: it is part of the cost
+        if (e == hipSuccess)
+          e = launch_splitk_reduce(gk == GK_F64 ? GK_F64 : GK_F32, g, P->at<void>(P->Ypart), P->ldg,
+                                   (int64_t)P->l_pad * P->ldg, P->at<double>(P->Y), s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) return finish(hip_check(e, "autotune gpass"));
+        if (rep > 0 && ms < ms_best) ms_best = ms;
+      }
+      ++timed;
+      if (ms_best < kbest) {
+        kbest = ms_best;
+        best[kind] = g.split;
+      }
+    }
+    best_ms[kind] = kbest;
+  }
+  P->opts.gpass_split = best[0];
+  P->opts.proj_split = best[1];
+  P->opts.write_split = P->fused ? best[2] : 0;
+  out->range_split = best[0];
+  out->proj_split = best[1];
+  out->write_split = P->opts.write_split;
+  out->pad_ = 0;
+  out->range_ms = best_ms[0];
+  out->proj_ms = best_ms[1];
+  out->write_ms = P->fused ? best_ms[2] : 0.f;
+  out->candidates = timed;
+  return finish(MDS_OK);
 }
 
 void mds_destroy(mds_plan_t plan) {

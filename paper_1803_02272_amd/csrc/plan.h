@@ -30,6 +30,7 @@ struct mds_plan_s {
   mds::GPassCfg cfg{}, ref_cfg{};
   bool fused = false;   // bf16 centring write fused with the first range pass
   mds::GPassCfg wcfg{};  // its configuration
+  size_t ypart_min = 0;   // lower bound on the split-K partials region (autotuning)
   // workspace
   void* ws = nullptr;
   size_t ws_bytes = 0;

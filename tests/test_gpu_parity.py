@@ -375,3 +375,27 @@ def test_symmetric_projection_matches_full(name, form, split):
     tol = 1e-12 if form == "fp64" else 1e-6
     assert rel_eig_err(es, ef) < tol
     assert procrustes_err(Xs, Xf) < (1e-9 if form == "fp64" else 1e-3)
+
+
+# ---------------------------------------------------------------------------
+# plan autotuner: the chosen split-K configuration runs and keeps parity
+@pytest.mark.parametrize("form", ["fp32", "bf16"])
+def test_autotuned_plan_parity(form):
+    name = "amp5000_r200"
+    D, k, p, q = case(name)
+    say(f"[autotune] case={name} form={form}")
+    plan = mds.Plan(D.shape[0], k, p, q, 0, form=form)
+    Dg = torch.from_numpy(D).cuda()
+    r = plan.autotune(Dg)
+    say(f"    chosen {r}")
+    assert r["candidates"] >= 3 and r["range_ms"] > 0 and r["proj_ms"] > 0
+    assert (r["write_ms"] > 0) == (form == "bf16")
+    coords, eig = plan.run(Dg)
+    info = plan.info()
+    assert info["status"] == 0
+    if r["range_split"]:
+        assert info["gpass_split"] == r["range_split"]
+    ref = oracle_rand(name, form=form)
+    assert rel_eig_err(eig.cpu().numpy(), ref["eigvals"]) < MATCHED_EIG_BAR[form]
+    with pytest.raises(mds.MdsError):
+        plan.autotune(Dg)  # the workspace is attached now
