@@ -6,8 +6,9 @@
 //   stats: one read of D; per 1024 x 1024 tile, each wave owns 256 rows and
 //          every lane 16 columns; row partials come from a 64-lane butterfly,
 //          column partials from registers and a fixed-order LDS merge of the
-//          four waves.  Partials are combined in a fixed order afterwards, so
-//          results are bitwise reproducible (no floating-point atomics).
+//          four waves; the tiles on the diagonal also sum d_ii^2.  Partials
+//          are combined in a fixed order afterwards, so results are bitwise
+//          reproducible (no floating-point atomics).
 //   write: one read of D and one write of G in the pass dtype (plus an fp32
 //          copy for the refinement pass when requested), with ||G||_F^2 and
 //          tr(G) partials.  Squares are formed in fp64 (exact for fp32 input)
@@ -63,9 +64,12 @@ __device__ __forceinline__ bool row_vec_ok(bool base_ok, int64_t i, int64_t n) {
 
 constexpr int kWaves = 4;
 constexpr int kRowsPerWave = kStatsRows / kWaves;  // 256
+static_assert(kStatsRows == kStatsCols, "the diagonal of D lies in the tiles with cb == rb");
 
 // One read of D per 1024 x 1024 tile.  Loads of the next batch of rows are
 // issued before the current batch is reduced (raw values held in registers).
+// p4part[rb * ncb + cb] = sum of d^4 over the tile; a diagonal tile (cb == rb)
+// also writes p4part[ncb * nrb + rb] = sum of its d_ii^2.
 template <typename DT>
 __global__ __launch_bounds__(256, 2) void k_stats(const DT* __restrict__ D, int64_t n, int base_vec,
                                                   double* __restrict__ rowpart, double* __restrict__ colpart,
@@ -81,7 +85,8 @@ __global__ __launch_bounds__(256, 2) void k_stats(const DT* __restrict__ D, int6
   double cacc[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) cacc[t] = 0.0;
-  double acc4 = 0.0;
+  double acc4 = 0.0, accd = 0.0;
+  const bool diag_tile = cb == rb;
 
   DT raw[RB][16], rawn[RB][16];
   auto load_batch = [&](DT (&dst)[RB][16], int64_t i) {
@@ -118,6 +123,9 @@ __global__ __launch_bounds__(256, 2) void k_stats(const DT* __restrict__ D, int6
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) {
       double rs = 0.0;
+      const int64_t ii = i + rr;
+      // column offset of d_ii from this lane's first column (diagonal tiles only)
+      const int dcol = diag_tile ? (int)(ii - c0) - lane * 4 : -1;
 #pragma unroll
       for (int t = 0; t < 16; ++t) {
         const double d = (double)raw[rr][t];
@@ -125,9 +133,9 @@ __global__ __launch_bounds__(256, 2) void k_stats(const DT* __restrict__ D, int6
         cacc[t] += sq;
         rs += sq;
         acc4 += sq * sq;
+        accd += ((t >> 2) * 256 + (t & 3) == dcol) ? sq : 0.0;
       }
       rs = wave_sum(rs);
-      const int64_t ii = i + rr;
       if (lane == 0 && ii < r1) rowpart[cb * n + ii] = rs;
     }
     if (more) {
@@ -138,19 +146,26 @@ __global__ __launch_bounds__(256, 2) void k_stats(const DT* __restrict__ D, int6
     }
   }
   __shared__ double sh[kWaves][kStatsCols];
-  __shared__ double sh4[kWaves];
+  __shared__ double sh4[kWaves], shd[kWaves];
 #pragma unroll
   for (int g = 0; g < 4; ++g)
 #pragma unroll
     for (int t = 0; t < 4; ++t) sh[wave][g * 256 + lane * 4 + t] = cacc[g * 4 + t];
   acc4 = wave_sum(acc4);
-  if (lane == 0) sh4[wave] = acc4;
+  accd = wave_sum(accd);
+  if (lane == 0) {
+    sh4[wave] = acc4;
+    shd[wave] = accd;
+  }
   __syncthreads();
   for (int cc = threadIdx.x; cc < kStatsCols; cc += 256) {
     const int64_t c = c0 + cc;
     if (c < n) colpart[rb * n + c] = ((sh[0][cc] + sh[1][cc]) + sh[2][cc]) + sh[3][cc];
   }
-  if (threadIdx.x == 0) p4part[rb * gridDim.x + cb] = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
+  if (threadIdx.x == 0) {
+    p4part[rb * gridDim.x + cb] = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
+    if (diag_tile) p4part[(int64_t)gridDim.x * gridDim.y + rb] = ((shd[0] + shd[1]) + shd[2]) + shd[3];
+  }
 }
 
 // r_i, c_j (means of d^2), and hc_j = fl32(c_j / 2) for the fp32 recentring
@@ -184,11 +199,10 @@ __global__ __launch_bounds__(256) void k_stats_reduce(const double* __restrict__
 // A = B + r 1^T + 1 c^T - m 1 1^T splits into Frobenius-orthogonal parts, so
 // ||B||^2 = ||A||^2 - n ||r||^2 - n ||c||^2 + n^2 m^2 and ||G||^2 = ||B||^2 / 4;
 // tr G = -1/2 (sum_i d_ii^2 - n m).
-template <typename DT>
 __global__ __launch_bounds__(1024) void k_grand(const double* __restrict__ rsum, const double* __restrict__ r,
                                                 const double* __restrict__ c, const double* __restrict__ p4part,
-                                                int64_t np4, const DT* __restrict__ D, int64_t n,
-                                                double* __restrict__ mean_all, DevStatus* st) {
+                                                int64_t np4, int64_t ndiag, int64_t n, double* __restrict__ mean_all,
+                                                DevStatus* st) {
 #pragma clang fp contract(off)
   __shared__ double sh[5][1024];
   double s = 0.0, rr = 0.0, cc = 0.0, q = 0.0, dg = 0.0;
@@ -196,10 +210,9 @@ __global__ __launch_bounds__(1024) void k_grand(const double* __restrict__ rsum,
     s += rsum[i];
     rr += r[i] * r[i];
     cc += c[i] * c[i];
-    const double d = (double)D[i * n + i];
-    dg += d * d;
   }
   for (int64_t i = threadIdx.x; i < np4; i += 1024) q += p4part[i];
+  for (int64_t i = threadIdx.x; i < ndiag; i += 1024) dg += p4part[np4 + i];
   sh[0][threadIdx.x] = s;
   sh[1][threadIdx.x] = rr;
   sh[2][threadIdx.x] = cc;
@@ -400,8 +413,9 @@ hipError_t launch_center_write_fp8(const void* D, int d_is_f64, int64_t n, int64
   return hipGetLastError();
 }
 
-int64_t stats_tiles(int64_t n) {
-  return ((n + kStatsCols - 1) / kStatsCols) * ((n + kStatsRows - 1) / kStatsRows);
+int64_t stats_parts(int64_t n) {
+  const int64_t nrb = (n + kStatsRows - 1) / kStatsRows;
+  return ((n + kStatsCols - 1) / kStatsCols) * nrb + nrb;
 }
 
 hipError_t launch_center_stats(const void* D, int d_is_f64, int64_t n, int64_t ldg, double* rowpart,
@@ -417,12 +431,7 @@ hipError_t launch_center_stats(const void* D, int d_is_f64, int64_t n, int64_t l
     hipLaunchKernelGGL(k_stats<float>, grid, dim3(256), 0, s, (const float*)D, n, vec, rowpart, colpart, p4part);
   hipLaunchKernelGGL(k_stats_reduce, dim3((unsigned)((ldg + 255) / 256)), dim3(256), 0, s, rowpart, colpart, ncb,
                      nrb, n, ldg, r, c, rsum, hc);
-  if (d_is_f64)
-    hipLaunchKernelGGL(k_grand<double>, dim3(1), dim3(1024), 0, s, rsum, r, c, p4part, ncb * nrb,
-                       (const double*)D, n, mean_all, st);
-  else
-    hipLaunchKernelGGL(k_grand<float>, dim3(1), dim3(1024), 0, s, rsum, r, c, p4part, ncb * nrb,
-                       (const float*)D, n, mean_all, st);
+  hipLaunchKernelGGL(k_grand, dim3(1), dim3(1024), 0, s, rsum, r, c, p4part, ncb * nrb, nrb, n, mean_all, st);
   return hipGetLastError();
 }
 

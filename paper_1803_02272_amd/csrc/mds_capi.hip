@@ -69,7 +69,7 @@ void layout(mds_plan_s* P) {
   add(P, P->c, (size_t)n * 8);
   add(P, P->rsum, (size_t)n * 8);
   add(P, P->mean, 8);
-  add(P, P->p4part, (size_t)stats_tiles(n) * 8);
+  add(P, P->p4part, (size_t)stats_parts(n) * 8);
   add(P, P->hc, (size_t)ldg * 4);
   const size_t xe = (size_t)(gk_size(x_kind(P->gk)) > gk_size(P->ref_gk) ? gk_size(x_kind(P->gk))
                                                                          : gk_size(P->ref_gk));

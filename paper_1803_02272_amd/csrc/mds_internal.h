@@ -49,8 +49,8 @@ struct DevStatus {
 constexpr int kStatsCols = 1024;  // columns per stats tile
 constexpr int kStatsRows = 1024;  // rows per stats tile
 // r, c, m (fp64), hc = fl32(c/2) (ldg floats, zero beyond n), and
-// ||G||_F^2, tr(G) in the status words.  p4part: stats_tiles(n) doubles.
-int64_t stats_tiles(int64_t n);
+// ||G||_F^2, tr(G) in the status words.  p4part: stats_parts(n) doubles.
+int64_t stats_parts(int64_t n);
 hipError_t launch_center_stats(const void* D, int d_is_f64, int64_t n, int64_t ldg, double* rowpart,
                                double* colpart, double* p4part, double* r, double* c, double* rsum, float* hc,
                                double* mean_all, DevStatus* st, hipStream_t s);

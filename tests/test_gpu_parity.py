@@ -136,6 +136,28 @@ def test_centring_stage(name, form):
     assert info["status"] == 0
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_centring_trace_nonzero_diagonal(dtype):
+    # A distance matrix has a zero diagonal, but the centring is defined for any
+    # square D: tr G = -1/2 (sum_i d_ii^2 - n m) picks up the diagonal, which lies
+    # in several 1024 x 1024 statistics tiles here (n = 2600, ragged last tile).
+    n = 2600
+    D, _, _, _ = case("gm2000_f64")
+    rng = np.random.default_rng(7)
+    Dn = np.abs(rng.standard_normal((n, n))) + 1.0
+    Dn[:2000, :2000] = D
+    Dn[np.arange(n), np.arange(n)] = rng.uniform(0.5, 3.0, n)
+    Dn = np.ascontiguousarray(Dn.astype(dtype))
+    say(f"[centring trace] n={n} dtype={np.dtype(dtype).name}")
+    plan = mds.Plan(n, 5, 5, 0, 0, form="fp64", d_dtype=dtype_of(Dn))
+    plan.run_stages(torch.from_numpy(Dn).cuda(), _capi.STAGE_RANGE, 1)
+    torch.cuda.synchronize()
+    G = O.gram_matrix(Dn)
+    info = plan.info()
+    assert np.isclose(info["trace"], np.trace(G), rtol=1e-12)
+    assert np.isclose(info["frob2"], np.sum(G * G), rtol=1e-11)
+
+
 @pytest.mark.parametrize("form", ["fp64", "fp32", "bf16"])
 def test_omega_stage(form):
     D, k, p, q = case("amp1237_f32")
