@@ -169,6 +169,12 @@ __device__ __forceinline__ void load_d(const DT* __restrict__ D, int64_t n, int6
       const u32x4 w1 = *reinterpret_cast<const u32x4*>(p + E / 2);
       __builtin_memcpy(&v, &w0, 16);
       __builtin_memcpy(reinterpret_cast<char*>(&v) + 16, &w1, 16);
+    } else if constexpr (sizeof(DT) * E == 64) {
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const u32x4 w = *reinterpret_cast<const u32x4*>(p + h * (E / 4));
+        __builtin_memcpy(reinterpret_cast<char*>(&v) + 16 * h, &w, 16);
+      }
     } else {  // 8 bytes
       const uint2 w = *reinterpret_cast<const uint2*>(p);
       __builtin_memcpy(&v, &w, 8);
@@ -476,6 +482,486 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
   }
 }
 
+// ---- fp32 passes on bf16 MFMA: three-term split ----------------------------
+// An fp32 value a is the exact sum a0 + a1 + a2 of three bf16 values:
+// a0 = bf16(a), a1 = bf16(a - a0), a2 = (a - a0) - a1, rounding to nearest
+// even; both differences are exact in fp32 and a2 has at most 8 significant
+// bits.  With |a1| <= 2^-8 |a| and |a2| <= 2^-16 |a| (normal range), the six
+// products a_p b_q with p + q <= 2 leave out terms below 2^-22 |a b|, about
+// one fp32 rounding of the product, so this pass computes the fp32 pass's
+// Y = G X (fp32 operands fl32(gamma) and fl32(x), fp32 accumulation) to fp32
+// accuracy.  Per 32 K-values and 16 x 16 tile: six bf16 MFMAs (16x16x32,
+// 16 cycles) instead of eight fp32 ones (16x16x4, 32 cycles).
+//
+// X is stored split (written by the cast after the orthonormalisation): row
+// j of the transposed operand holds, per 32 consecutive K-values, the 32
+// bf16 a0 terms, then the a1 terms, then the a2 terms (192 bytes).  A step
+// covers 32 K-values: each lane recentres 8 consecutive entries of D per row
+// group (one 128-byte line per row and step), splits them in registers, and
+// meets the three 16-byte B pieces of its K-group from the LDS step tile.
+constexpr int kX3Step = 32;           // K-values per step
+constexpr int kX3RowB = 3 * 64 + 16;  // LDS bytes per X row of a step tile: 3 planes + pad (conflict-free reads)
+
+__host__ __device__ constexpr int rg_x3(int cg, bool d8) { return cg <= (d8 ? 6 : 8) ? 2 : 1; }
+
+typedef __bf16 bf16x2v_t __attribute__((ext_vector_type(2)));
+
+// Three-term split of 8 floats into the bf16 planes w[0..2] (element t at
+// halfword t of each plane).
+__device__ __forceinline__ void split3(const float (&g)[8], u32x4 (&w)[3]) {
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const f32x2 v = {g[2 * h], g[2 * h + 1]};
+    const bf16x2v_t v0 = __builtin_convertvector(v, bf16x2v_t);
+    const f32x2 r1 = v - __builtin_convertvector(v0, f32x2);
+    const bf16x2v_t v1 = __builtin_convertvector(r1, bf16x2v_t);
+    const f32x2 r2 = r1 - __builtin_convertvector(v1, f32x2);
+    const bf16x2v_t v2 = __builtin_convertvector(r2, bf16x2v_t);
+    w[0][h] = __builtin_bit_cast(uint32_t, v0);
+    w[1][h] = __builtin_bit_cast(uint32_t, v1);
+    w[2][h] = __builtin_bit_cast(uint32_t, v2);
+  }
+}
+
+template <int RG, int CG, typename DT, bool SYM>
+__global__ __launch_bounds__(256, 2) void k_gpass_x3(const uint16_t* __restrict__ X3, int64_t ldg, int split,
+                                                     int64_t steps_total, int64_t steps_per_split,
+                                                     float* __restrict__ Ypart, GPassDSrc src, int64_t sym_nbx) {
+  constexpr int LPAD = CG * 16;
+  constexpr int BK = kX3Step;
+  constexpr int PIECES = LPAD * 12;  // 16-byte pieces of a step's X tile (3 planes x 4 K-groups per row)
+  constexpr int PPT = (PIECES + 255) / 256;
+  constexpr int64_t kStepsPerBlock = (64 * RG) / BK;
+  constexpr int DV = 16 / (int)sizeof(DT);  // row alignment (elements) for 16-byte loads of D
+  __shared__ __attribute__((aligned(16))) unsigned char xs[2][LPAD * kX3RowB];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t bid = blockIdx.x;
+  int s;
+  int64_t mb, st0, st1;
+  if constexpr (SYM) {  // same work items as the symmetric k_gpass
+    const int64_t loc = bid >> 3;
+    s = (int)(loc / sym_nbx);
+    mb = (loc % sym_nbx) * 8 + (bid & 7);
+    const int64_t diag0 = mb * kStepsPerBlock;
+    st0 = (int64_t)s * steps_per_split;
+    st1 = (st0 + steps_per_split < steps_total) ? st0 + steps_per_split : steps_total;
+    if (diag0 > st0) st0 = diag0;
+    if (diag0 >= steps_total || st0 >= st1) return;
+  } else {
+    s = (int)(bid % split);
+    mb = bid / split;
+    st0 = (int64_t)s * steps_per_split;
+    st1 = (st0 + steps_per_split < steps_total) ? st0 + steps_per_split : steps_total;
+  }
+  const int64_t diag_end = (mb + 1) * kStepsPerBlock;
+  const int64_t row0 = mb * (64 * RG) + (int64_t)wave * (RG * 16);
+
+  floatx4_t acc[RG][CG];
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[rg][cg][e] = 0.0f;
+
+  const DT* Dp = reinterpret_cast<const DT*>(src.D);
+  const int64_t n = src.n;
+  const double mval = src.m[0];
+  float ri[RG];  // hr_i (symmetric mode: 2 hr_i, exact)
+  bool rowvec[RG];
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg) {
+    const int64_t i = row0 + rg * 16 + (lane & 15);
+    const float h = (i < n) ? (float)(0.5 * (src.r[i] - mval)) : 0.0f;
+    ri[rg] = SYM ? h + h : h;
+    rowvec[rg] = src.vec && (((i * n) % DV) == 0);
+  }
+  const size_t xrowbytes = (size_t)ldg * 6;
+  const unsigned char* Xb = reinterpret_cast<const unsigned char*>(X3);
+
+  if (st0 < st1) {
+    DT a[RG][8], an[RG][8];
+    float cv[8], cvn[8];
+    u32x4 xr[PPT];
+    auto load_a = [&](DT (&dst)[RG][8], float (&cdst)[8], int64_t st) {
+      const int64_t k0 = st * BK + (lane >> 4) * 8;
+#pragma unroll
+      for (int rg = 0; rg < RG; ++rg) load_d<DT, 8>(Dp, n, row0 + rg * 16 + (lane & 15), k0, rowvec[rg], dst[rg]);
+      // hc holds ldg zero-padded entries (ldg is a multiple of 32)
+      const u32x4 w0 = *reinterpret_cast<const u32x4*>(src.hc + k0);
+      const u32x4 w1 = *reinterpret_cast<const u32x4*>(src.hc + k0 + 4);
+      __builtin_memcpy(&cdst[0], &w0, 16);
+      __builtin_memcpy(&cdst[4], &w1, 16);
+    };
+    auto load_x = [&](int64_t st) {
+#pragma unroll
+      for (int u = 0; u < PPT; ++u) {
+        const int p = tid + 256 * u;
+        if (PIECES % 256 == 0 || p < PIECES)
+          xr[u] = *reinterpret_cast<const u32x4*>(Xb + (size_t)(p / 12) * xrowbytes + (size_t)st * 192 +
+                                                  (p % 12) * 16);
+      }
+    };
+    auto store_x = [&](unsigned char* buf) {
+#pragma unroll
+      for (int u = 0; u < PPT; ++u) {
+        const int p = tid + 256 * u;
+        if (PIECES % 256 == 0 || p < PIECES) *reinterpret_cast<u32x4*>(buf + (p / 12) * kX3RowB + (p % 12) * 16) = xr[u];
+      }
+    };
+    // gamma = fma(-1/2, fl32(d^2), hc_k + hr_i) as in the fp32 pass
+    // (symmetric mode: 2 gamma = fma(-1, fl32(d^2), 2 hc_k + 2 hr_i), the same
+    // roundings scaled by 2, times 1, 1/2, 0 right of, on and left of the
+    // diagonal), then split into three bf16 planes.  Entries outside n x n
+    // need no mask: columns k >= n meet zero rows of X (the padding of Q),
+    // and rows i >= n are zeroed in the output.
+    auto a_split = [&](int rg, const float (&ch)[8], auto band_tag, int64_t st, u32x4 (&w)[3]) {
+#pragma clang fp contract(off)
+      constexpr bool BAND = decltype(band_tag)::value;
+      float g[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        float d2;
+        if constexpr (sizeof(DT) == 4) {
+          const float d = a[rg][t];
+          d2 = d * d;
+        } else {
+          const double d = a[rg][t];
+          d2 = (float)(d * d);
+        }
+        float v = __builtin_fmaf(SYM ? -1.0f : -0.5f, d2, ch[t] + ri[rg]);
+        if constexpr (BAND) {
+          const int64_t j = st * BK + (lane >> 4) * 8 + t;
+          const int64_t i = row0 + rg * 16 + (lane & 15);
+          v = j > i ? v : (j == i ? 0.5f * v : 0.0f);
+        }
+        g[t] = v;
+      }
+      split3(g, w);
+    };
+
+    load_a(a, cv, st0);
+    load_x(st0);
+    store_x(xs[0]);
+    __syncthreads();
+    for (int64_t st = st0; st < st1; ++st) {
+      const int buf = (int)((st - st0) & 1);
+      const bool more = st + 1 < st1;
+      if (more) {
+        load_x(st + 1);
+        load_a(an, cvn, st + 1);
+      }
+      u32x4 w[RG][3];
+      float ch[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) ch[t] = SYM ? cv[t] + cv[t] : cv[t];
+      if (SYM && st < diag_end) {
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) a_split(rg, ch, std::true_type{}, st, w[rg]);
+      } else {
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) a_split(rg, ch, std::false_type{}, st, w[rg]);
+      }
+      const unsigned char* xb = xs[buf];
+#pragma unroll
+      for (int cg0 = 0; cg0 < CG; cg0 += 2) {
+        constexpr int NP = 2;
+        u32x4 bb[NP][3];
+#pragma unroll
+        for (int h = 0; h < NP; ++h)
+          if (cg0 + h < CG) {
+            const unsigned char* bp = xb + ((cg0 + h) * 16 + (lane & 15)) * kX3RowB + (lane >> 4) * 16;
+            bb[h][0] = *reinterpret_cast<const u32x4*>(bp);
+            bb[h][1] = *reinterpret_cast<const u32x4*>(bp + 64);
+            bb[h][2] = *reinterpret_cast<const u32x4*>(bp + 128);
+          }
+        constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+        for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+          for (int h = 0; h < NP; ++h)
+            if (cg0 + h < CG)
+#pragma unroll
+              for (int rg = 0; rg < RG; ++rg) Tr<GK_BF16>::mma(acc[rg][cg0 + h], w[rg][PA[pr]], bb[h][PB[pr]]);
+      }
+      if (more) store_x(xs[buf ^ 1]);
+      __syncthreads();
+      if (more) {
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+          for (int t = 0; t < 8; ++t) a[rg][t] = an[rg][t];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) cv[t] = cvn[t];
+      }
+    }
+  }
+
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg) {
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg) {
+      const int col = cg * 16 + (lane & 15);
+      float* dst = Ypart + ((int64_t)s * LPAD + col) * ldg + row0 + rg * 16;
+      const int64_t i4 = row0 + rg * 16 + 4 * (lane >> 4);  // rows i4 .. i4+3 of this lane
+      float4 o = make_float4(acc[rg][cg][0], acc[rg][cg][1], acc[rg][cg][2], acc[rg][cg][3]);
+      if (i4 + 3 >= n) {
+        o.x = i4 < n ? o.x : 0.0f;
+        o.y = i4 + 1 < n ? o.y : 0.0f;
+        o.z = i4 + 2 < n ? o.z : 0.0f;
+        o.w = i4 + 3 < n ? o.w : 0.0f;
+      }
+      *reinterpret_cast<float4*>(dst + 4 * (lane >> 4)) = o;
+    }
+  }
+}
+
+// ---- the symmetric split pass with D streamed through LDS ------------------
+// Same arithmetic, work items and output as k_gpass_x3 in symmetric mode
+// (fp32 D, n % 4 == 0, 16-byte aligned D, l_pad <= 128), organised around
+// gfx950's global-to-LDS loads (global_load_lds_dwordx4: lane l's 16 bytes
+// land at the wave's LDS address + 16 l, no registers involved):
+//   * 512 threads (8 waves x 2 row groups, 256 rows) per workgroup and one
+//     workgroup per CU: the X step tile (three planes, 192 bytes per row) is
+//     shared by eight waves instead of four;
+//   * each wave streams its own rows of D into a three-stage LDS ring, two
+//     steps ahead, and reads them back in its own lane order;
+//   * the X tile is double-buffered, its 16-byte slots swizzled
+//     (slot = plane * 4 l_pad + 4 row + (kgroup ^ ((row >> 2) & 3))) so that
+//     the B-operand reads of 16 consecutive rows hit distinct banks.
+// Every buffer is its own __shared__ array and the step loop is unrolled six
+// ways (2 X buffers x 3 ring stages), so each LDS access names a fixed array
+// and the compiler's waits for the DMA stay as precise as the explicit
+// vmcnt waits below; the workgroup barrier is taken without a memory fence,
+// which would wait for the DMA two steps ahead as well.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gbl_void_t;
+
+__device__ __forceinline__ void dma16(const void* g, void* l) {
+  __builtin_amdgcn_global_load_lds((gbl_void_t*)g, (lds_void_t*)l, 16, 0, 0);
+}
+
+constexpr int kDmaWaves = 8;
+constexpr int kDmaMaxL = 128;  // LDS: 2 X tiles (2 x 24 KB at l_pad 128) + ring (3 x 32 KB)
+
+template <int CG>
+__global__ __launch_bounds__(512, 1) void k_gpass_x3d(const uint16_t* __restrict__ X3, int64_t ldg,
+                                                      int64_t steps_total, int64_t steps_per_split,
+                                                      float* __restrict__ Ypart, GPassDSrc src, int64_t sym_nbx) {
+  constexpr bool SYM = true;
+  constexpr int RG = 2;
+  constexpr int NW = kDmaWaves;
+  constexpr int LPAD = CG * 16;
+  constexpr int BK = kX3Step;
+  constexpr int XINS = CG * 3;                       // 1 KB DMA instructions per X step tile
+  constexpr int64_t BM = NW * RG * 16;               // 256 rows per workgroup
+  constexpr int64_t kStepsPerBlock = BM / BK;
+  constexpr int DSTAGE = RG * 2 * 1024;              // bytes of one wave's D stage
+  __shared__ __attribute__((aligned(16))) unsigned char xs0[XINS * 1024];
+  __shared__ __attribute__((aligned(16))) unsigned char xs1[XINS * 1024];
+  __shared__ __attribute__((aligned(16))) unsigned char ds0[NW * DSTAGE];
+  __shared__ __attribute__((aligned(16))) unsigned char ds1[NW * DSTAGE];
+  __shared__ __attribute__((aligned(16))) unsigned char ds2[NW * DSTAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t bid = blockIdx.x;
+  int s;
+  int64_t mb, st0, st1;
+  {  // work item (row block, K split), as in k_gpass_x3
+    const int64_t loc = bid >> 3;
+    s = (int)(loc / sym_nbx);
+    mb = (loc % sym_nbx) * 8 + (bid & 7);
+    const int64_t diag0 = mb * kStepsPerBlock;
+    st0 = (int64_t)s * steps_per_split;
+    st1 = (st0 + steps_per_split < steps_total) ? st0 + steps_per_split : steps_total;
+    if (diag0 > st0) st0 = diag0;
+    if (diag0 >= steps_total || st0 >= st1) return;
+  }
+  const int64_t diag_end = (mb + 1) * kStepsPerBlock;
+  const int64_t row0 = mb * BM + (int64_t)wave * (RG * 16);
+
+  floatx4_t acc[RG][CG];
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[rg][cg][e] = 0.0f;
+
+  const float* Dp = reinterpret_cast<const float*>(src.D);
+  const int64_t n = src.n;
+  const int64_t nn = n * n;
+  const double mval = src.m[0];
+  float ri[RG];
+  const float* drow[RG];
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg) {
+    const int64_t i = row0 + rg * 16 + (lane & 15);
+    const float h = (i < n) ? (float)(0.5 * (src.r[i] - mval)) : 0.0f;
+    ri[rg] = SYM ? h + h : h;
+    drow[rg] = Dp + (i < n ? i : n - 1) * n;  // rows beyond n read row n-1 (zeroed in the output)
+  }
+  const size_t xrowbytes = (size_t)ldg * 6;
+  const unsigned char* Xb = reinterpret_cast<const unsigned char*>(X3);
+
+  // D of step st into stage sd: this wave's rows, 16 bytes per lane per
+  // (row group, half); reads past the end of D are clamped to its last 16
+  // bytes (their columns meet zero rows of X).
+  auto dma_d = [&](int64_t st, unsigned char (&dd)[NW * DSTAGE]) {
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t k = st * BK + (lane >> 4) * 8 + h * 4;
+        const float* g = drow[rg] + k;
+        if (g + 4 > Dp + nn) g = Dp + nn - 4;
+        dma16(g, &dd[wave * DSTAGE + (rg * 2 + h) * 1024]);
+      }
+  };
+  // X tile of step st into buffer b: slot S = q * 64 + lane holds plane p,
+  // row, K-group kg at S = p * 4 LPAD + 4 row + (kg ^ ((row >> 2) & 3))
+  auto dma_x = [&](int64_t st, unsigned char (&xd)[XINS * 1024]) {
+#pragma unroll
+    for (int u = 0; u < (XINS + NW - 1) / NW; ++u) {
+      const int q = wave + u * NW;
+      if (XINS % NW != 0 && q >= XINS) break;
+      const int S = q * 64 + lane;
+      const int p = S / (LPAD * 4), rem = S % (LPAD * 4);
+      const int row = rem >> 2, kg = (rem & 3) ^ ((row >> 2) & 3);
+      dma16(Xb + (size_t)row * xrowbytes + (size_t)st * 192 + p * 64 + kg * 16, &xd[q * 1024]);
+    }
+  };
+  auto load_c = [&](int64_t st, float (&cdst)[8]) {
+    const int64_t k0 = st * BK + (lane >> 4) * 8;
+    const u32x4 w0 = *reinterpret_cast<const u32x4*>(src.hc + k0);
+    const u32x4 w1 = *reinterpret_cast<const u32x4*>(src.hc + k0 + 4);
+    __builtin_memcpy(&cdst[0], &w0, 16);
+    __builtin_memcpy(&cdst[4], &w1, 16);
+  };
+
+  float cv[8], cvn[8];
+  dma_x(st0, xs0);
+  dma_d(st0, ds0);
+  dma_d(st0 + 1 < st1 ? st0 + 1 : st0, ds1);
+  load_c(st0, cv);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  // one step: X(st) in xr, X(st + 1) goes to xw (separate LDS arrays, so the
+  // compiler sees that the reads of xr do not wait for that DMA)
+  using XBuf = unsigned char[XINS * 1024];
+  using DBuf = unsigned char[NW * DSTAGE];
+  auto step = [&](int64_t st, XBuf& xr, XBuf& xw, DBuf& dr, DBuf& dw) {
+    // the prefetches are issued on every step (the last steps re-load step
+    // st1 - 1 into buffers that are not read again), so that the wait counts
+    // below and the compiler's own are the same on every path
+    const int64_t stx = st + 1 < st1 ? st + 1 : st1 - 1;
+    const int64_t std2 = st + 2 < st1 ? st + 2 : st1 - 1;
+    dma_x(stx, xw);
+    load_c(stx, cvn);
+    dma_d(std2, dw);
+    u32x4 w[RG][3];
+    float ch[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) ch[t] = SYM ? cv[t] + cv[t] : cv[t];
+    const bool band = SYM && st < diag_end;
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) {
+#pragma clang fp contract(off)
+      const u32x4 lo = *reinterpret_cast<const u32x4*>(&dr[wave * DSTAGE + (rg * 2) * 1024 + lane * 16]);
+      const u32x4 hi = *reinterpret_cast<const u32x4*>(&dr[wave * DSTAGE + (rg * 2 + 1) * 1024 + lane * 16]);
+      float dv[8];
+      __builtin_memcpy(&dv[0], &lo, 16);
+      __builtin_memcpy(&dv[4], &hi, 16);
+      float g[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float d2 = dv[t] * dv[t];
+        g[t] = __builtin_fmaf(SYM ? -1.0f : -0.5f, d2, ch[t] + ri[rg]);
+      }
+      if (band) {
+        const int64_t i = row0 + rg * 16 + (lane & 15);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int64_t j = st * BK + (lane >> 4) * 8 + t;
+          g[t] = j > i ? g[t] : (j == i ? 0.5f * g[t] : 0.0f);
+        }
+      }
+      split3(g, w[rg]);
+    }
+#pragma unroll
+    for (int cg0 = 0; cg0 < CG; cg0 += 2) {
+      constexpr int NP = 2;
+      u32x4 bb[NP][3];
+#pragma unroll
+      for (int h = 0; h < NP; ++h)
+        if (cg0 + h < CG) {
+          const int row = (cg0 + h) * 16 + (lane & 15);
+          const int kgs = (lane >> 4) ^ ((row >> 2) & 3);
+#pragma unroll
+          for (int p = 0; p < 3; ++p)
+            bb[h][p] = *reinterpret_cast<const u32x4*>(&xr[(p * LPAD * 4 + row * 4 + kgs) * 16]);
+        }
+      constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+      for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+        for (int h = 0; h < NP; ++h)
+          if (cg0 + h < CG)
+#pragma unroll
+            for (int rg = 0; rg < RG; ++rg) Tr<GK_BF16>::mma(acc[rg][cg0 + h], w[rg][PA[pr]], bb[h][PB[pr]]);
+    }
+    // X(st + 1) and D(st + 1) complete (D(st + 2), issued last, may still run)
+    __builtin_amdgcn_s_waitcnt(0x0F70 | RG * 2);  // vmcnt(RG*2)
+    // workgroup barrier without a memory fence (a fence would also wait for
+    // the DMA of D(st + 2)); the waits above make X(st + 1) visible
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int t = 0; t < 8; ++t) cv[t] = cvn[t];
+    __builtin_amdgcn_sched_barrier(0);  // steps are scheduled one at a time (register pressure)
+  };
+  // D(st) sits in stage (st - st0) % 3 and X(st) in buffer (st - st0) % 2:
+  // six steps per trip keep every LDS array static
+  for (int64_t st = st0; st < st1; st += 6) {
+    step(st, xs0, xs1, ds0, ds2);
+    if (st + 1 >= st1) break;
+    step(st + 1, xs1, xs0, ds1, ds0);
+    if (st + 2 >= st1) break;
+    step(st + 2, xs0, xs1, ds2, ds1);
+    if (st + 3 >= st1) break;
+    step(st + 3, xs1, xs0, ds0, ds2);
+    if (st + 4 >= st1) break;
+    step(st + 4, xs0, xs1, ds1, ds0);
+    if (st + 5 >= st1) break;
+    step(st + 5, xs1, xs0, ds2, ds1);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // no DMA outstanding at exit
+
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg) {
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg) {
+      const int col = cg * 16 + (lane & 15);
+      float* dst = Ypart + ((int64_t)s * LPAD + col) * ldg + row0 + rg * 16;
+      const int64_t i4 = row0 + rg * 16 + 4 * (lane >> 4);
+      float4 o = make_float4(acc[rg][cg][0], acc[rg][cg][1], acc[rg][cg][2], acc[rg][cg][3]);
+      if (i4 + 3 >= n) {
+        o.x = i4 < n ? o.x : 0.0f;
+        o.y = i4 + 1 < n ? o.y : 0.0f;
+        o.z = i4 + 2 < n ? o.z : 0.0f;
+        o.w = i4 + 3 < n ? o.w : 0.0f;
+      }
+      *reinterpret_cast<float4*>(dst + 4 * (lane >> 4)) = o;
+    }
+  }
+}
+
 // Symmetric mode: row block mb has partials only in the splits whose K
 // range reaches its diagonal, k >= first_split(row) = (mb * bm) / cols_per_split.
 template <typename AccS>
@@ -550,6 +1036,57 @@ hipError_t launch_cg(const void* G, int64_t ldg, const void* Xt, const GPassCfg&
   return hipGetLastError();
 }
 
+template <int CG, typename DT, bool SYM>
+void launch_x3_one(const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t n_pad, void* Yp, const GPassDSrc& src,
+                   hipStream_t s) {
+  constexpr int RG = rg_x3(CG, sizeof(DT) == 8);
+  hipLaunchKernelGGL((k_gpass_x3<RG, CG, DT, SYM>), dim3((unsigned)gpass_blocks(cfg, n_pad)), dim3(256), 0, s,
+                     (const uint16_t*)Xt, ldg, cfg.split, cfg.steps_total, cfg.steps_per_split, (float*)Yp, src,
+                     cfg.sym_nbx);
+}
+
+template <int CG>
+hipError_t launch_x3_cg(const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t n_pad, void* Yp,
+                        const GPassDSrc& src, hipStream_t s) {
+  if (!src.D) return hipErrorInvalidValue;
+  if (cfg.dma) {
+    if constexpr (CG * 16 <= kDmaMaxL) {
+      if (!cfg.sym || cfg.bm != kDmaWaves * 32 || src.d_is_f64 || !src.vec || src.n % 4 != 0)
+        return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_gpass_x3d<CG>), dim3((unsigned)gpass_blocks(cfg, n_pad)), dim3(64 * kDmaWaves), 0, s,
+                         (const uint16_t*)Xt, ldg, cfg.steps_total, cfg.steps_per_split, (float*)Yp, src,
+                         cfg.sym_nbx);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
+  if (cfg.rg != rg_x3(CG, src.d_is_f64 != 0)) return hipErrorInvalidValue;
+  if (src.d_is_f64) {
+    if (cfg.sym)
+      launch_x3_one<CG, double, true>(Xt, ldg, cfg, n_pad, Yp, src, s);
+    else
+      launch_x3_one<CG, double, false>(Xt, ldg, cfg, n_pad, Yp, src, s);
+  } else {
+    if (cfg.sym)
+      launch_x3_one<CG, float, true>(Xt, ldg, cfg, n_pad, Yp, src, s);
+    else
+      launch_x3_one<CG, float, false>(Xt, ldg, cfg, n_pad, Yp, src, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_x3(const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t n_pad, void* Yp,
+                     const GPassDSrc& src, hipStream_t s) {
+  switch (l_pad / 16) {
+#define MDS_CG(N) \
+  case N: return launch_x3_cg<N>(Xt, ldg, cfg, n_pad, Yp, src, s);
+    MDS_CG(1) MDS_CG(2) MDS_CG(3) MDS_CG(4) MDS_CG(5) MDS_CG(6) MDS_CG(7) MDS_CG(8)
+    MDS_CG(9) MDS_CG(10) MDS_CG(11) MDS_CG(12) MDS_CG(13) MDS_CG(14) MDS_CG(15) MDS_CG(16)
+#undef MDS_CG
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int GK>
 hipError_t launch_gk(const void* G, int64_t ldg, const void* Xt, int l_pad, const GPassCfg& cfg, int64_t n_pad,
                      void* Yp, const GPassDSrc& src, hipStream_t s) {
@@ -566,11 +1103,17 @@ hipError_t launch_gk(const void* G, int64_t ldg, const void* Xt, int l_pad, cons
 }  // namespace
 
 GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d, bool sym,
-                      bool d8) {
+                      bool d8, bool dma_ok) {
   GPassCfg c{};
-  c.rg = from_d ? rg_fd(gk, l_pad / 16, d8) : rg_for(gk, l_pad / 16);
+  c.rg = gk == GK_F32S ? rg_x3(l_pad / 16, d8) : (from_d ? rg_fd(gk, l_pad / 16, d8) : rg_for(gk, l_pad / 16));
   c.bm = 64 * c.rg;
-  const int64_t esize = gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : 2);
+  if (gk == GK_F32S && dma_ok && sym && from_d && !d8 && l_pad <= kDmaMaxL && n_pad % (kDmaWaves * 32) == 0) {
+    c.dma = 1;  // k_gpass_x3d: 8 waves of 2 row groups
+    c.rg = 2;
+    c.bm = kDmaWaves * 32;
+  }
+  // bytes per K-value of a step's 128-byte row (the split pass steps 32 K-values, like fp32)
+  const int64_t esize = gk == GK_F64 ? 8 : ((gk == GK_F32 || gk == GK_F32S) ? 4 : 2);
   c.steps_total = ldg * esize / 128;
   const int64_t row_blocks = n_pad / c.bm;
   if (sym && from_d) {
@@ -606,6 +1149,7 @@ hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const
     case GK_FP8:
       if (!src.g8_scales || (cfg.bm > kF8Block) || (kF8Block % cfg.bm)) return hipErrorInvalidValue;
       return launch_gk<GK_FP8>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
+    case GK_F32S: return launch_x3(Xt, ldg, l_pad, cfg, n_pad, Ypart, src, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -197,13 +197,37 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ pa
 }
 
 // Xc = cast(Out) for the next G-pass operand, 4 consecutive entries per thread.
+// GK_F32S: x = fl32(Out) split exactly into x0 + x1 + x2 (bf16, each step
+// rounding to nearest even); per row and 32 consecutive columns, the 32 x0,
+// then the 32 x1, then the 32 x2 (the layout the split G-pass reads).
 template <int XK>
-__global__ __launch_bounds__(256) void k_cast(const double* __restrict__ In, int64_t elems, void* __restrict__ Xc) {
+__global__ __launch_bounds__(256) void k_cast(const double* __restrict__ In, int64_t elems, int64_t ldg,
+                                              void* __restrict__ Xc) {
   const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
   if (e >= elems) return;  // elems is a multiple of 4
   const double2 a = reinterpret_cast<const double2*>(In + e)[0];
   const double2 b = reinterpret_cast<const double2*>(In + e)[1];
-  if constexpr (XK == GK_F64) {
+  if constexpr (XK == GK_F32S) {
+    const float x[4] = {(float)a.x, (float)a.y, (float)b.x, (float)b.y};
+    uint16_t h[3][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const __bf16 v0 = (__bf16)x[t];
+      const float r1 = x[t] - (float)v0;
+      const __bf16 v1 = (__bf16)r1;
+      const float r2 = r1 - (float)v1;
+      const __bf16 v2 = (__bf16)r2;
+      h[0][t] = __builtin_bit_cast(uint16_t, v0);
+      h[1][t] = __builtin_bit_cast(uint16_t, v1);
+      h[2][t] = __builtin_bit_cast(uint16_t, v2);
+    }
+    const int64_t j = e / ldg, k = e % ldg;  // 4 | ldg: the four entries share a row and a 32-column group
+    uint16_t* dst = reinterpret_cast<uint16_t*>(Xc) + j * (3 * ldg) + (k / 32) * 96 + (k % 32);
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      *reinterpret_cast<uint2*>(dst + 32 * p) =
+          make_uint2(h[p][0] | ((uint32_t)h[p][1] << 16), h[p][2] | ((uint32_t)h[p][3] << 16));
+  } else if constexpr (XK == GK_F64) {
     reinterpret_cast<double2*>(reinterpret_cast<double*>(Xc) + e)[0] = a;
     reinterpret_cast<double2*>(reinterpret_cast<double*>(Xc) + e)[1] = b;
   } else if constexpr (XK == GK_F32) {
@@ -425,11 +449,13 @@ hipError_t launch_apply(const double* In, int l, int64_t ldg, const double* T, i
     const int64_t elems = (int64_t)l_pad * ldg;
     const dim3 cg((unsigned)((elems / 4 + 255) / 256));
     if (xk == GK_F64)
-      hipLaunchKernelGGL(k_cast<GK_F64>, cg, dim3(256), 0, s, Out, elems, Xc);
+      hipLaunchKernelGGL(k_cast<GK_F64>, cg, dim3(256), 0, s, Out, elems, ldg, Xc);
     else if (xk == GK_F32)
-      hipLaunchKernelGGL(k_cast<GK_F32>, cg, dim3(256), 0, s, Out, elems, Xc);
+      hipLaunchKernelGGL(k_cast<GK_F32>, cg, dim3(256), 0, s, Out, elems, ldg, Xc);
     else if (xk == GK_BF16)
-      hipLaunchKernelGGL(k_cast<GK_BF16>, cg, dim3(256), 0, s, Out, elems, Xc);
+      hipLaunchKernelGGL(k_cast<GK_BF16>, cg, dim3(256), 0, s, Out, elems, ldg, Xc);
+    else if (xk == GK_F32S && ldg % 32 == 0)
+      hipLaunchKernelGGL(k_cast<GK_F32S>, cg, dim3(256), 0, s, Out, elems, ldg, Xc);
     else
       return hipErrorInvalidValue;
   }

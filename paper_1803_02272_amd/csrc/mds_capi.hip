@@ -25,7 +25,10 @@ using namespace mds;
 namespace {
 thread_local std::string g_last_error;
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
-int gk_size(int gk) { return gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : (gk == GK_BF16 ? 2 : 1)); }
+// bytes per element of G or X of a pass kind (GK_F32S: three bf16 terms of X)
+int gk_size(int gk) {
+  return gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : (gk == GK_BF16 ? 2 : (gk == GK_F32S ? 6 : 1)));
+}
 // Element kind of the X operand of a pass with G of kind gk (FP8 G meets bf16 X).
 int x_kind(int gk) { return gk == GK_FP8 ? GK_BF16 : gk; }
 bool stores_g(int form) { return form == MDS_FORM_BF16 || form == MDS_FORM_FP8; }
@@ -76,7 +79,8 @@ void layout(mds_plan_s* P) {
   add(P, P->X, (size_t)lp * ldg * xe);
   const size_t acc_main = P->gk == GK_F64 ? 8 : 4, acc_ref = P->ref_gk == GK_F64 ? 8 : 4;
   const size_t yp_main = (size_t)P->cfg.split * lp * ldg * acc_main;
-  const size_t yp_ref = (size_t)P->ref_cfg.split * lp * ldg * acc_ref;
+  const int ref_split = P->ref_cfg.split > P->ref_cfg_alt.split ? P->ref_cfg.split : P->ref_cfg_alt.split;
+  const size_t yp_ref = (size_t)ref_split * lp * ldg * acc_ref;
   const size_t yp_w = P->fused ? (size_t)P->wcfg.split * lp * ldg * 4 : 0;
   size_t yp = yp_main > yp_ref ? yp_main : yp_ref;
   yp = yp > yp_w ? yp : yp_w;
@@ -106,8 +110,10 @@ void configure(mds_plan_s* P) {
   const mds_opts& o = P->opts;
   const bool d8 = o.d_dtype == MDS_DTYPE_F64;
   P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, o.gpass_split, !stores_g(P->form), false, d8);
-  P->ref_cfg = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, o.proj_split ? o.proj_split : o.gpass_split,
-                            true, (o.flags & MDS_FLAG_FULL_PROJECTION) == 0, d8);
+  const int ps = o.proj_split ? o.proj_split : o.gpass_split;
+  const bool psym = (o.flags & MDS_FLAG_FULL_PROJECTION) == 0;
+  P->ref_cfg = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, ps, true, psym, d8, P->n % 4 == 0);
+  P->ref_cfg_alt = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, ps, true, psym, d8, false);
   // bf16 form on fp32 D: the centring write is fused with the first range pass
   P->fused = o.form == MDS_FORM_BF16 && !d8;
   if (P->fused)
@@ -211,9 +217,10 @@ GPassDSrc make_src(mds_plan_s* P, int gk, bool from_d, const void* D);
 
 mds_status gpass(mds_plan_s* P, hipStream_t s, bool ref, const void* D, bool fused = false) {
   const int gk = ref ? P->ref_gk : P->gk;
-  const GPassCfg& cfg = fused ? P->wcfg : (ref ? P->ref_cfg : P->cfg);
   const bool from_d = ref || fused || !stores_g(P->form);
   const GPassDSrc src = make_src(P, gk, from_d, D);
+  const GPassCfg& cfg =
+      fused ? P->wcfg : (ref ? ((P->ref_cfg.dma && !src.vec) ? P->ref_cfg_alt : P->ref_cfg) : P->cfg);
   {
     PhaseTimer tm(P, s, fused ? MDS_PH_WRITE : (ref ? MDS_PH_GPASS_REF : MDS_PH_GPASS));
     MDS_TRY(launch_gpass(gk, (from_d && !fused) ? nullptr : P->at<void>(P->G), P->ldg, P->n_pad,
@@ -371,7 +378,8 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
     return fail(MDS_ERR_INVALID_ARG, "unknown D dtype %d", o.d_dtype);
   if (o.gpass_split < 0 || o.proj_split < 0 || o.write_split < 0)
     return fail(MDS_ERR_INVALID_ARG, "negative split (%d, %d, %d)", o.gpass_split, o.proj_split, o.write_split);
-  if (o.flags & ~MDS_FLAG_FULL_PROJECTION) return fail(MDS_ERR_INVALID_ARG, "unknown flags 0x%x", o.flags);
+  if (o.flags & ~(MDS_FLAG_FULL_PROJECTION | MDS_FLAG_FP32_MFMA_PROJECTION))
+    return fail(MDS_ERR_INVALID_ARG, "unknown flags 0x%x", o.flags);
   mds_plan_s* P = new (std::nothrow) mds_plan_s();
   if (!P) return fail(MDS_ERR_OOM, "host allocation failed");
   P->opts = o;
@@ -388,7 +396,9 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
   P->d_dtype = o.d_dtype;
   P->gk = o.form == MDS_FORM_FP64 ? GK_F64
           : (o.form == MDS_FORM_FP32 ? GK_F32 : (o.form == MDS_FORM_BF16 ? GK_BF16 : GK_FP8));
-  P->ref_gk = stores_g(o.form) ? GK_F32 : P->gk;
+  // projection ("refinement") of the stored-G forms: fp32, by default as the
+  // three-term bf16 split on bf16 MFMA
+  P->ref_gk = stores_g(o.form) ? ((o.flags & MDS_FLAG_FP32_MFMA_PROJECTION) ? GK_F32 : GK_F32S) : P->gk;
   P->flags = o.flags;
   configure(P);
   *out = P;
@@ -459,8 +469,12 @@ mds_status mds_get_buffer(mds_plan_t plan, int32_t which, mds_buffer* out) {
     case MDS_BUF_X: {
       // dtype of the operand depends on which pass wrote it last
       int dt = xdt;
-      if (plan->last_stage >= MDS_STAGE_ALL && plan->ref_gk != plan->gk) dt = 1;
-      b = {plan->at<void>(plan->X), dt, 0, lp, plan->ldg, plan->ldg};
+      int64_t cols = plan->ldg;
+      if (plan->last_stage >= MDS_STAGE_ALL && plan->ref_gk != plan->gk) {
+        dt = plan->ref_gk == GK_F32 ? 1 : 2;
+        if (plan->ref_gk == GK_F32S) cols = 3 * plan->ldg;
+      }
+      b = {plan->at<void>(plan->X), dt, 0, lp, cols, cols};
       break;
     }
     case MDS_BUF_Q: b = {plan->at<void>(plan->Q), 0, 0, lp, plan->ldg, plan->ldg}; break;
@@ -545,7 +559,9 @@ mds_status mds_autotune(mds_plan_t P, const void* D, void* stream, mds_tune_resu
   const bool sym = (P->opts.flags & MDS_FLAG_FULL_PROJECTION) == 0;
   auto cfg_of = [&](int kind, int split) {
     if (kind == 0) return gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, split, !stores_g(P->form), false, d8);
-    if (kind == 1) return gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, split, true, sym, d8);
+    if (kind == 1)
+      return gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, split, true, sym, d8,
+                          P->n % 4 == 0 && (uintptr_t)D % 16 == 0);
     return gpass_config(GK_BF16, P->l_pad, P->n_pad, P->ldg, split, true, false, false);
   };
   const int kinds = P->fused ? 3 : 2;

@@ -25,7 +25,9 @@ typedef __attribute__((__vector_size__(4 * sizeof(double)))) double doublex4_t;
 
 // Kind of the G operand of a pass.  GK_FP8: OCP E4M3 codes with one fp32
 // scale per 256 x 256 block, multiplied on bf16 MFMA (the X operand is bf16).
-enum GKind { GK_F64 = 0, GK_F32 = 1, GK_BF16 = 2, GK_FP8 = 3 };
+// GK_F32S: the fp32 pass (recentring D) computed on bf16 MFMA from exact
+// three-term bf16 splits of both operands; X is stored split (see k_gpass).
+enum GKind { GK_F64 = 0, GK_F32 = 1, GK_BF16 = 2, GK_FP8 = 3, GK_F32S = 4 };
 constexpr int kF8Block = 256;  // side of the blocks sharing one FP8 scale
 
 constexpr int kPadN = 256;     // padding granule of n (rows and ld of G)
@@ -80,12 +82,15 @@ struct GPassCfg {
   int64_t steps_total, steps_per_split;
   int64_t sym_nbx;             // row blocks per XCD (symmetric mode)
   int64_t sym_cols_per_split;  // K columns per split (symmetric mode)
+  int dma;                     // split pass through the LDS ring (k_gpass_x3d): fp32 D, n % 4 == 0, aligned D
 };
 // sym (recentring passes only): the projection's symmetric mode, see k_gpass.
 // d8: D holds fp64 (recentring passes keep more raw values in registers).
 // gk == GK_BF16 with from_d: the fused centring write and first range pass.
+// dma_ok (GK_F32S, symmetric): n % 4 == 0 and D 16-byte aligned, so the pass
+// may stream D through LDS (needs the same alignment at launch).
 GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d, bool sym,
-                      bool d8);
+                      bool d8, bool dma_ok = false);
 // With D != nullptr the A operand is recentred on the fly from D (ld = n)
 // and G is unused.  fp64 passes: gamma_ij = -1/2 (((d_ij^2 - c_j) - r_i) + m)
 // in fp64 (the stored-G value).  fp32 passes: gamma_ij =

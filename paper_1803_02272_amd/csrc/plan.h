@@ -27,7 +27,9 @@ struct mds_plan_s {
   int gk = mds::GK_F32;      // dtype of G and of the range passes
   int ref_gk = mds::GK_F32;  // dtype of the projection pass
   int flags = 0;
-  mds::GPassCfg cfg{}, ref_cfg{};
+  // ref_cfg_alt: the projection's configuration for a D that is not 16-byte
+  // aligned (equal to ref_cfg unless ref_cfg streams D through LDS)
+  mds::GPassCfg cfg{}, ref_cfg{}, ref_cfg_alt{};
   bool fused = false;   // bf16 centring write fused with the first range pass
   mds::GPassCfg wcfg{};  // its configuration
   size_t ypart_min = 0;   // lower bound on the split-K partials region (autotuning)

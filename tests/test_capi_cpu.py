@@ -51,11 +51,13 @@ def test_invalid_arguments_rejected(n, k, p, q):
 def test_invalid_options_rejected():
     assert _plan(100, 4, 4, 1, form=7)[0] == _capi.ERR_INVALID_ARG
     assert _plan(100, 4, 4, 1, dt=5)[0] == _capi.ERR_INVALID_ARG
-    assert _plan(100, 4, 4, 1, flags=2)[0] == _capi.ERR_INVALID_ARG
+    assert _plan(100, 4, 4, 1, flags=4)[0] == _capi.ERR_INVALID_ARG
     assert _plan(100, 4, 4, 1, split=-1)[0] == _capi.ERR_INVALID_ARG
-    st, h = _plan(100, 4, 4, 1, flags=_capi.FLAG_FULL_PROJECTION)
-    assert st == _capi.OK
-    _capi.lib().mds_destroy(h)
+    for flags in (_capi.FLAG_FULL_PROJECTION, _capi.FLAG_FP32_MFMA_PROJECTION,
+                  _capi.FLAG_FULL_PROJECTION | _capi.FLAG_FP32_MFMA_PROJECTION):
+        st, h = _plan(100, 4, 4, 1, form=2, flags=flags)
+        assert st == _capi.OK
+        _capi.lib().mds_destroy(h)
 
 
 def test_workspace_size_scales_with_form():

@@ -400,6 +400,101 @@ def test_symmetric_projection_matches_full(name, form, split):
 
 
 # ---------------------------------------------------------------------------
+# fp32 projection on bf16 MFMA (three-term split) against fp32 MFMA
+@pytest.mark.parametrize("name", ["gm2000_f64", "amp1237_f32"])
+def test_split_projection_unit(name):
+    """The bf16 form's full projection Y = G Q with both operands split into
+    three bf16 terms: against an fp64 product of the fp32 operands, within the
+    fp32 pass's bound plus 2^-22 per product for the three dropped terms."""
+    D, k, p, q = case(name)
+    n = D.shape[0]
+    l = k + p
+    say(f"[split proj] case={name}")
+    plan = mds.Plan(n, k, p, q, 3, form="bf16", d_dtype=dtype_of(D), full_projection=True)
+    plan.run(torch.from_numpy(np.ascontiguousarray(D)).cuda())
+    assert plan.info()["status"] == 0
+    Qt = plan.buffer(_capi.BUF_Q).cpu().numpy()
+    Q32 = Qt[:l, :n].T.astype(np.float32).astype(np.float64)
+    # the split operand holds fl32(Q) exactly: x0 + x1 + x2 per entry
+    X3 = plan.buffer(_capi.BUF_X).float().cpu().numpy().astype(np.float64)
+    ldg = X3.shape[1] // 3
+    planes = X3.reshape(X3.shape[0], ldg // 32, 3, 32)
+    recon = (planes[:, :, 0, :] + planes[:, :, 1, :] + planes[:, :, 2, :]).reshape(X3.shape[0], ldg)
+    assert np.array_equal(recon[:l, :n], Q32.T)
+    assert np.all(recon[l:] == 0) and np.all(recon[:, n:] == 0)
+    G = O.gram_matrix(D).astype(np.float32).astype(np.float64)
+    want = G @ Q32
+    u = 2.0 ** -24
+    r, c, m = O.centring_stats(D)
+    H = 0.5 * (D.astype(np.float64) ** 2 + c[None, :] + np.abs(r - m)[:, None])
+    bound = (2 * n * u + 2.0 ** -22) * (np.abs(G) @ np.abs(Q32)) + 4 * u * (H @ np.abs(Q32))
+    Y = plan.buffer(_capi.BUF_Y).cpu().numpy()[:l, :n].T
+    say(f"    max |Y - want| / bound {np.max(np.abs(Y - want) / bound):.3e}")
+    assert np.all(np.abs(Y - want) <= bound)
+
+
+@pytest.mark.parametrize("name", ["gm2000_f64", "amp3001_f32", "amp5000_r200"])
+@pytest.mark.parametrize("form", ["bf16", "fp8"])
+@pytest.mark.parametrize("full", [False, True])
+def test_split_projection_matches_fp32_mfma(name, form, full):
+    """Same Q, projection by the three-term split or on fp32 MFMA: B agrees
+    within fp32 accumulation bounds, and so do the Ritz values and coordinates."""
+    D, k, p, q = case(name)
+    n = D.shape[0]
+    l = k + p
+    say(f"[split vs f32] case={name} form={form} full={full}")
+    Dg = torch.from_numpy(np.ascontiguousarray(D)).cuda()
+    out = {}
+    for f32 in (False, True):
+        plan = mds.Plan(n, k, p, q, 0, form=form, d_dtype=dtype_of(D), full_projection=full,
+                        fp32_mfma_projection=f32)
+        coords, eig = plan.run(Dg)
+        assert plan.info()["status"] == 0
+        B = plan.buffer(_capi.BUF_B).cpu().numpy()
+        out[f32] = (coords.cpu().numpy(), eig.cpu().numpy(), 0.5 * (B + B.T), plan.buffer(_capi.BUF_Q).cpu().numpy())
+        plan.close()
+    (Xs, es, Bs, Qs), (Xf, ef, Bf, Qf) = out[False], out[True]
+    assert np.array_equal(Qs, Qf)
+    Qn = Qs[:l, :n].T
+    G = O.gram_matrix(D)
+    r, c, m = O.centring_stats(D)
+    H = 0.5 * (D.astype(np.float64) ** 2 + c[None, :] + np.abs(r - m)[:, None])
+    mag = np.abs(Qn).T @ ((np.abs(G) + H) @ np.abs(Qn))
+    diff = np.abs(Bs[:l, :l] - Bf[:l, :l])
+    bound = (4 * n * 2.0 ** -24 + 2.0 ** -21) * mag
+    say(f"    max |B_split - B_f32| / bound {np.max(diff / bound):.3e}, eig rel {rel_eig_err(es, ef):.2e}")
+    assert np.all(diff <= bound)
+    assert rel_eig_err(es, ef) < 1e-6
+    assert procrustes_err(Xs, Xf) < 1e-3
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16", "fp8"])
+def test_misaligned_d_matches_aligned(form):
+    """D at an address that is not 16-byte aligned takes the per-element load
+    paths (and, for the split projection, the register kernel instead of the
+    LDS ring): the same sums in the same order, so the results are identical."""
+    name = "amp5000_r200"
+    D, k, p, q = case(name)
+    n = D.shape[0]
+    say(f"[misaligned] case={name} form={form}")
+    flat = torch.empty(n * n + 1, dtype=torch.float32, device="cuda")
+    Dm = flat[1:].view(n, n)
+    Dm.copy_(torch.from_numpy(D))
+    assert Dm.data_ptr() % 16 != 0
+    Da = torch.from_numpy(D).cuda()
+    assert Da.data_ptr() % 16 == 0
+    res = []
+    for Dg in (Da, Dm):
+        plan = mds.Plan(n, k, p, q, 0, form=form)
+        coords, eig = plan.run(Dg)
+        assert plan.info()["status"] == 0
+        res.append((coords.cpu().numpy(), eig.cpu().numpy()))
+        plan.close()
+    assert np.array_equal(res[0][1], res[1][1])
+    assert np.array_equal(res[0][0], res[1][0])
+
+
+# ---------------------------------------------------------------------------
 # plan autotuner: the chosen split-K configuration runs and keeps parity
 @pytest.mark.parametrize("form", ["fp32", "bf16"])
 def test_autotuned_plan_parity(form):
