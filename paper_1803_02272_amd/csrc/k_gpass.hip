@@ -346,7 +346,8 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
     // fl32(d^2), hc_k + hr_i) (one fma per entry instead of fp64 arithmetic).
     // Symmetric mode: 2 gamma (the same roundings scaled by 2, exactly),
     // times 1, 1/2, 0 right of, on and left of the diagonal.
-    auto a_operand = [&](int rg, int c, int64_t st, const double* cl) -> u32x4 {
+    auto a_operand = [&](int rg, int c, int64_t st, const double* cl, const RawT (&a)[RG][2][E],
+                         const CT (&cv)[2][E]) -> u32x4 {
       if constexpr (FD) {
 #pragma clang fp contract(off)
         const int64_t k0 = st * BK + c * (BK / 2) + (lane >> 4) * E;
@@ -408,24 +409,28 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
       }
     };
 
-    load_a(a, cv, st0);
-    load_x(st0);
-    store_x(xs[0]);
-    __syncthreads();
-    for (int64_t st = st0; st < st1; ++st) {
-      const int buf = (int)((st - st0) & 1);
-      const bool more = st + 1 < st1;
-      if (more) {
-        load_x(st + 1);
-        load_a(an, cvn, st + 1);
-      }
+    // One step: the operands of step st are in (ac, cc) and xs[buf]; the
+    // loads of step st + 1 go to (an_, cn_) and the other LDS buffer.  The
+    // prefetch is issued on every step (the last step re-loads step st1 - 1
+    // into buffers that are not read again) and the two register sets swap
+    // roles from one step to the next, so that the loads of step st + 1 stay
+    // in flight during all of step st: no conditional loads or register
+    // copies for the compiler's wait counts to merge.
+    auto step = [&](int64_t st, int buf, RawT (&ac)[RG][2][E], CT (&cc)[2][E], RawT (&an_)[RG][2][E],
+                    CT (&cn_)[2][E]) {
+      const int64_t stn = st + 1 < st1 ? st + 1 : st1 - 1;
+      load_x(stn);
+      load_a(an_, cn_, stn);
+      // keep the prefetch at the top of the step (the scheduler would sink it
+      // towards its uses at the end of the step, leaving nothing in flight)
+      __builtin_amdgcn_sched_barrier(0);
       const unsigned char* xb = xs[buf];
       const double* cl = cs[WG ? buf : 0];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         u32x4 av[RG];
 #pragma unroll
-        for (int rg = 0; rg < RG; ++rg) av[rg] = a_operand(rg, c, st, cl);
+        for (int rg = 0; rg < RG; ++rg) av[rg] = a_operand(rg, c, st, cl, ac, cc);
         if constexpr (WG) {
 #pragma unroll
           for (int rg = 0; rg < RG; ++rg)
@@ -443,22 +448,17 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
             for (int rg = 0; rg < RG; ++rg) TT::mma_sub(acc[rg][cg], av[rg], b, t);
         }
       }
-      if (more) store_x(xs[buf ^ 1]);
+      store_x(xs[buf ^ 1]);
       __syncthreads();
-      if (more) {
-#pragma unroll
-        for (int rg = 0; rg < RG; ++rg)
-#pragma unroll
-          for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int t = 0; t < E; ++t) a[rg][c][t] = an[rg][c][t];
-        if constexpr (FD) {
-#pragma unroll
-          for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int t = 0; t < E; ++t) cv[c][t] = cvn[c][t];
-        }
-      }
+    };
+
+    load_a(a, cv, st0);
+    load_x(st0);
+    store_x(xs[0]);
+    __syncthreads();
+    for (int64_t st = st0; st < st1; st += 2) {
+      step(st, 0, a, cv, an, cvn);
+      if (st + 1 < st1) step(st + 1, 1, an, cvn, a, cv);
     }
   }
 
