@@ -34,10 +34,12 @@ METRIC = "n=1e5 k=100 MDS time & MFMA util, BF16 vs FP32 @1e-3 eig err; p99 late
 # workload.  Valid only while the kernel source is the one measured: the
 # sha256 prefix of the file is checked and `traffic` is null otherwise.
 TRAFFIC = {
-    "gpass": {"source": "paper_1803_02272_amd/csrc/k_gpass.hip", "sha256_16": "71007befb074d231",
-              "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 20.861, "write_gb": 0.319},
-    "gpass_ref": {"source": "paper_1803_02272_amd/csrc/k_gpass.hip", "sha256_16": "71007befb074d231",
-                  "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 30.189, "write_gb": 0.231},
+    # range pass, stored bf16 G, split-K 3 (the split the autotuner chose in that run)
+    "gpass": {"source": "paper_1803_02272_amd/csrc/k_gpass.hip", "sha256_16": "4d19ca55bc01d85a",
+              "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 23.098, "write_gb": 0.164},
+    # symmetric fp32 projection as three-term bf16 split (k_gpass_x3d), split-K 24
+    "gpass_ref": {"source": "paper_1803_02272_amd/csrc/k_gpass.hip", "sha256_16": "4d19ca55bc01d85a",
+                  "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 23.648, "write_gb": 0.651},
 }
 
 # MI355X published peaks
@@ -307,26 +309,50 @@ def main():
         e = res[form]["eig"]
         return float(np.max(np.abs(e - ref_eig) / np.abs(ref_eig)))
 
-    # dominant kernel of the headline form and its roofline
+    # dominant kernel of the headline form and its roofline.  Algorithmic work:
+    # a range pass reads G once (stored bf16 / fp8 G, else the fp32 D it
+    # recentres) and does 2 n^2 l flops; the symmetric projection reads the
+    # upper triangle of D (n^2 / 2 fp32) and does n^2 l useful flops, which the
+    # bf16 and fp8 forms execute as six bf16 products per entry (three-term
+    # split of the fp32 operands) on bf16 MFMA.
     flops_pass = 2.0 * n * n * l
+    d_bytes = 4  # D is fp32 in this workload
+    g_bytes = {"bf16": 2, "fp8": 1}
+    x_bytes = {"bf16": 2, "fp8": 2, "fp32": 4, "fp64": 8}
     gb = {"bf16": 2, "fp32": 4, "fp64": 8}
+
+    def range_bytes(form):
+        return n * n * g_bytes.get(form, d_bytes) + n * l * (x_bytes[form] + 4)
+
+    def mfma_dtype(form):
+        return "bf16" if form == "fp8" else form  # fp8 codes are decoded into bf16 MFMA operands
+
+    def split_proj(form):
+        return form in ("bf16", "fp8")
+
+    proj_flops = 1.0 * n * n * l
+    proj_bytes = n * n // 2 * d_bytes + n * l * (6 + 4)
+
+    def proj_mfma(form):
+        """(executed MFMA flops of one projection, dtype whose peak bounds it)"""
+        return (6.0 * proj_flops, "bf16") if split_proj(form) else (proj_flops, form)
+
     ph = head["phases"]
     cands = {}
     if ph["gpass"]["count"]:
-        bG = gb[head_form]
         cands["gpass"] = dict(
             kernel=f"k_gpass<{head_form}> (range pass Y = G X)", total=ph["gpass"]["total_ms"],
-            avg=ph["gpass"]["avg_ms"], bytes=n * n * bG + n * l * (bG + 4), flops=flops_pass,
-            bound="hbm" if 2.0 * l / bG < PEAK_TFLOPS[head_form] * 1e12 / (PEAK_HBM_GBS * 1e9) else "mfma",
-            dtype=head_form)
+            avg=ph["gpass"]["avg_ms"], bytes=range_bytes(head_form), flops=flops_pass,
+            bound="hbm" if flops_pass / range_bytes(head_form) < PEAK_TFLOPS[mfma_dtype(head_form)] * 1e12 / (PEAK_HBM_GBS * 1e9)
+            else "mfma",
+            dtype=mfma_dtype(head_form))
     if ph["gpass_ref"]["count"]:
-        ref_form = "fp32" if head_form == "bf16" else head_form
-        bG = gb[ref_form]
+        pf, pdt = proj_mfma(head_form)
         cands["gpass_ref"] = dict(
-            kernel=f"k_gpass<{ref_form}> (projection Y = G Q)", total=ph["gpass_ref"]["total_ms"],
-            avg=ph["gpass_ref"]["avg_ms"], bytes=n * n * bG + n * l * (bG + 4), flops=flops_pass,
-            bound="hbm" if 2.0 * l / bG < PEAK_TFLOPS[ref_form] * 1e12 / (PEAK_HBM_GBS * 1e9) else "mfma",
-            dtype=ref_form)
+            kernel=("k_gpass_x3d (projection, fp32 as 3-term bf16 split, symmetric)" if split_proj(head_form)
+                    else f"k_gpass<{head_form}> (projection, symmetric)"),
+            total=ph["gpass_ref"]["total_ms"], avg=ph["gpass_ref"]["avg_ms"], bytes=proj_bytes, flops=pf,
+            bound="mfma", dtype=pdt)
     for name, unit_bytes in (("write", n * n * (4 + gb[head_form] + (4 if head_form == "bf16" else 0))),
                              ("stats", n * n * 4)):
         if ph[name]["count"]:
@@ -348,26 +374,29 @@ def main():
     roof["algorithmic_bytes_per_launch"] = dom["bytes"]
     roof["algorithmic_flops_per_launch"] = dom["flops"]
 
-    # MFMA utilisation of the G-passes of each form (algorithmic flops / time / dtype peak)
+    # MFMA utilisation of the G-passes of each form: algorithmic TFLOP/s, and
+    # the executed MFMA work over the peak of the dtype it runs on
     gemm = {}
     for form, r in res.items():
         g = r["phases"]["gpass"]
         gr = r["phases"]["gpass_ref"]
-        rf = "fp32" if form == "bf16" else form
         entry = {}
         if g["count"]:
             tf = flops_pass / (g["avg_ms"] * 1e-3) / 1e12
             entry["range_pass_ms"] = g["avg_ms"]
             entry["range_pass_tflops"] = tf
-            entry["range_pass_mfma_frac"] = tf / PEAK_TFLOPS[form]
-            entry["range_pass_hbm_gbs"] = n * n * gb[form] / (g["avg_ms"] * 1e-3) / 1e9
+            entry["range_pass_mfma_frac"] = tf / PEAK_TFLOPS[mfma_dtype(form)]
+            entry["range_pass_hbm_gbs"] = range_bytes(form) / (g["avg_ms"] * 1e-3) / 1e9
         if gr["count"]:
-            tf = flops_pass / (gr["avg_ms"] * 1e-3) / 1e12
+            pf, pdt = proj_mfma(form)
             entry["proj_pass_ms"] = gr["avg_ms"]
-            entry["proj_pass_tflops"] = tf
-            entry["proj_pass_mfma_frac"] = tf / PEAK_TFLOPS[rf]
+            entry["proj_pass_tflops"] = proj_flops / (gr["avg_ms"] * 1e-3) / 1e12
+            entry["proj_pass_mfma"] = "bf16 (six products of three-term splits)" if split_proj(form) else form
+            entry["proj_pass_mfma_frac"] = pf / (gr["avg_ms"] * 1e-3) / 1e12 / PEAK_TFLOPS[pdt]
+            entry["proj_pass_hbm_gbs"] = proj_bytes / (gr["avg_ms"] * 1e-3) / 1e9
         tot = (g["total_ms"] + gr["total_ms"])
-        entry["all_passes_tflops"] = (2 * q + 2) * flops_pass / (tot * 1e-3) / 1e12 if tot else None
+        alg = (2 * q + 1) * flops_pass + proj_flops
+        entry["all_passes_tflops"] = alg / (tot * 1e-3) / 1e12 if tot else None
         gemm[form] = entry
 
     line = {
