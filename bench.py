@@ -73,7 +73,8 @@ def percentile(xs, p):
 
 
 def time_form(mds, torch, D, n, k, p, q, form, steps, warmup, autotune=True):
-    plan = mds.Plan(n, k, p, q, 0, form=form)
+    # "fp32s": the fp32 form with every pass as the three-term bf16 split
+    plan = mds.Plan(n, k, p, q, 0, form="fp32" if form == "fp32s" else form, split_fp32=form == "fp32s")
     tuned = None
     if autotune:
         t0 = time.perf_counter()
@@ -249,7 +250,8 @@ def main():
     ap.add_argument("--k", type=int, default=100)
     ap.add_argument("--oversample", type=int, default=20)
     ap.add_argument("--q", type=int, default=2)
-    ap.add_argument("--forms", default="bf16,fp32,fp64")
+    ap.add_argument("--forms", default="bf16,fp32,fp32s,fp64",
+                    help="fp32s = the fp32 form with every pass as the three-term bf16 split")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default split-K of every pass")
     ap.add_argument("--cpu-sample", type=int, default=20000)
@@ -318,17 +320,22 @@ def main():
     flops_pass = 2.0 * n * n * l
     d_bytes = 4  # D is fp32 in this workload
     g_bytes = {"bf16": 2, "fp8": 1}
-    x_bytes = {"bf16": 2, "fp8": 2, "fp32": 4, "fp64": 8}
-    gb = {"bf16": 2, "fp32": 4, "fp64": 8}
+    x_bytes = {"bf16": 2, "fp8": 2, "fp32": 4, "fp32s": 6, "fp64": 8}
+    gb = {"bf16": 2, "fp8": 1, "fp32": 4, "fp32s": 4, "fp64": 8}
 
     def range_bytes(form):
         return n * n * g_bytes.get(form, d_bytes) + n * l * (x_bytes[form] + 4)
 
     def mfma_dtype(form):
-        return "bf16" if form == "fp8" else form  # fp8 codes are decoded into bf16 MFMA operands
+        # fp8 codes are decoded into bf16 MFMA operands; split passes run on bf16 MFMA
+        return "bf16" if form in ("fp8", "fp32s") else form
 
     def split_proj(form):
-        return form in ("bf16", "fp8")
+        return form in ("bf16", "fp8", "fp32s")
+
+    def range_executed(form):
+        """executed MFMA flops of one range pass (six products per entry when split)"""
+        return 6.0 * flops_pass if form == "fp32s" else flops_pass
 
     proj_flops = 1.0 * n * n * l
     proj_bytes = n * n // 2 * d_bytes + n * l * (6 + 4)
@@ -385,7 +392,8 @@ def main():
             tf = flops_pass / (g["avg_ms"] * 1e-3) / 1e12
             entry["range_pass_ms"] = g["avg_ms"]
             entry["range_pass_tflops"] = tf
-            entry["range_pass_mfma_frac"] = tf / PEAK_TFLOPS[mfma_dtype(form)]
+            entry["range_pass_mfma_frac"] = (range_executed(form) / (g["avg_ms"] * 1e-3) / 1e12
+                                             / PEAK_TFLOPS[mfma_dtype(form)])
             entry["range_pass_hbm_gbs"] = range_bytes(form) / (g["avg_ms"] * 1e-3) / 1e9
         if gr["count"]:
             pf, pdt = proj_mfma(form)

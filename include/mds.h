@@ -93,6 +93,12 @@ typedef enum mds_dtype { MDS_DTYPE_F32 = 0, MDS_DTYPE_F64 = 1 } mds_dtype;
  *   results differ by fp32 rounding only, the split is about 2.5x faster).
  *   No effect in the other forms. */
 #define MDS_FLAG_FP32_MFMA_PROJECTION 2
+/*   MDS_FLAG_SPLIT_FP32: FP32 form, run every G-pass (range passes and
+ *   projection) as the three-term bf16 split on bf16 MFMA described under
+ *   MDS_FORM_BF16: the same fp32 operands and fp32 accumulation as the plain
+ *   FP32 form, to fp32 accuracy, in less time.  No effect in the other
+ *   forms (the BF16 and FP8 forms' projection already uses it). */
+#define MDS_FLAG_SPLIT_FP32 4
 
 typedef struct mds_opts {
   int32_t form;        /* mds_form (default MDS_FORM_FP32) */
@@ -159,9 +165,10 @@ typedef enum mds_buffer_id {
   MDS_BUF_ROWMEAN = 2, /* r, n fp64 */
   MDS_BUF_COLMEAN = 3, /* c, n fp64 */
   MDS_BUF_MEAN = 4,    /* m, 1 fp64 */
-  MDS_BUF_X = 5,       /* current G-pass operand, transposed l_pad x ldg; after the
-                          split projection of the BF16/FP8 forms, l_pad rows of 3 ldg
-                          bf16: per 32 columns the 32 x0, 32 x1 and 32 x2 terms */
+  MDS_BUF_X = 5,       /* current G-pass operand, transposed l_pad x ldg; in the split
+                          passes (the BF16/FP8 forms' projection, MDS_FLAG_SPLIT_FP32),
+                          l_pad rows of 3 ldg bf16: per 32 columns the 32 x0, 32 x1 and
+                          32 x2 terms */
   MDS_BUF_Q = 6,       /* orthonormal basis, transposed l_pad x ldg fp64 */
   MDS_BUF_Y = 7,       /* last G-pass product, transposed l_pad x ldg fp64 (after the
                           symmetric projection: 2 (W o G) Q, see MDS_FLAG_FULL_PROJECTION) */

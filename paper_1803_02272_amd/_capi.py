@@ -41,6 +41,7 @@ MAX_L = 256
 # option flags (mds_opts.flags)
 FLAG_FULL_PROJECTION = 1
 FLAG_FP32_MFMA_PROJECTION = 2
+FLAG_SPLIT_FP32 = 4
 
 
 class MdsOpts(ctypes.Structure):

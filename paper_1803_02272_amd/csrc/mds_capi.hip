@@ -378,7 +378,7 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
     return fail(MDS_ERR_INVALID_ARG, "unknown D dtype %d", o.d_dtype);
   if (o.gpass_split < 0 || o.proj_split < 0 || o.write_split < 0)
     return fail(MDS_ERR_INVALID_ARG, "negative split (%d, %d, %d)", o.gpass_split, o.proj_split, o.write_split);
-  if (o.flags & ~(MDS_FLAG_FULL_PROJECTION | MDS_FLAG_FP32_MFMA_PROJECTION))
+  if (o.flags & ~(MDS_FLAG_FULL_PROJECTION | MDS_FLAG_FP32_MFMA_PROJECTION | MDS_FLAG_SPLIT_FP32))
     return fail(MDS_ERR_INVALID_ARG, "unknown flags 0x%x", o.flags);
   mds_plan_s* P = new (std::nothrow) mds_plan_s();
   if (!P) return fail(MDS_ERR_OOM, "host allocation failed");
@@ -399,6 +399,8 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
   // projection ("refinement") of the stored-G forms: fp32, by default as the
   // three-term bf16 split on bf16 MFMA
   P->ref_gk = stores_g(o.form) ? ((o.flags & MDS_FLAG_FP32_MFMA_PROJECTION) ? GK_F32 : GK_F32S) : P->gk;
+  // FP32 form with every pass as the three-term bf16 split
+  if (o.form == MDS_FORM_FP32 && (o.flags & MDS_FLAG_SPLIT_FP32)) P->gk = P->ref_gk = GK_F32S;
   P->flags = o.flags;
   configure(P);
   *out = P;
@@ -451,7 +453,8 @@ mds_status mds_get_buffer(mds_plan_t plan, int32_t which, mds_buffer* out) {
   if (!plan->ws) return fail(MDS_ERR_STATE, "plan has no workspace yet");
   mds_buffer b = {};
   const int64_t lp = plan->l_pad;
-  const int xdt = plan->gk == GK_F64 ? 0 : (plan->gk == GK_F32 ? 1 : 2);  // X dtype (FP8: bf16)
+  // X dtype (FP8: bf16; split passes: bf16 planes)
+  const int xdt = plan->gk == GK_F64 ? 0 : (plan->gk == GK_F32 ? 1 : 2);
   switch (which) {
     case MDS_BUF_G:
       if (!stores_g(plan->form)) return fail(MDS_ERR_STATE, "G is not stored in this form");
@@ -469,7 +472,7 @@ mds_status mds_get_buffer(mds_plan_t plan, int32_t which, mds_buffer* out) {
     case MDS_BUF_X: {
       // dtype of the operand depends on which pass wrote it last
       int dt = xdt;
-      int64_t cols = plan->ldg;
+      int64_t cols = plan->gk == GK_F32S ? 3 * plan->ldg : plan->ldg;
       if (plan->last_stage >= MDS_STAGE_ALL && plan->ref_gk != plan->gk) {
         dt = plan->ref_gk == GK_F32 ? 1 : 2;
         if (plan->ref_gk == GK_F32S) cols = 3 * plan->ldg;

@@ -468,6 +468,56 @@ def test_split_projection_matches_fp32_mfma(name, form, full):
     assert procrustes_err(Xs, Xf) < 1e-3
 
 
+def test_split_fp32_omega():
+    """With every fp32 pass split, Omega is written as three bf16 planes whose
+    sum is exactly fl32(Omega)."""
+    D, k, p, q = case("amp1237_f32")
+    n, l, seed = D.shape[0], k + p, 99
+    say(f"[split fp32 omega] n={n} l={l}")
+    plan = mds.Plan(n, k, p, q, seed, form="fp32", split_fp32=True)
+    plan.run_stages(torch.from_numpy(D).cuda(), _capi.STAGE_OMEGA)
+    torch.cuda.synchronize()
+    X3 = plan.buffer(_capi.BUF_X).float().cpu().numpy().astype(np.float64)
+    ldg = X3.shape[1] // 3
+    planes = X3.reshape(X3.shape[0], ldg // 32, 3, 32)
+    recon = (planes[:, :, 0, :] + planes[:, :, 1, :] + planes[:, :, 2, :]).reshape(X3.shape[0], ldg)
+    Om = O.omega(seed, n, l).astype(np.float32).astype(np.float64)
+    assert np.array_equal(recon[:l, :n], Om.T)
+    assert np.all(recon[l:] == 0) and np.all(recon[:, n:] == 0)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("full", [False, True])
+def test_split_fp32_form_parity(name, full):
+    """The fp32 form with every pass as the three-term bf16 split: same bars as
+    the plain fp32 form against the oracle, and agreement with the plain form
+    to fp32 rounding."""
+    D, k, p, q = case(name)
+    say(f"[split fp32] case={name} full={full}")
+    ref = oracle_rand(name)
+    matched = oracle_rand(name, form="fp32")
+    Dg = torch.from_numpy(np.ascontiguousarray(D)).cuda()
+    res = {}
+    for split in (False, True):
+        plan = mds.Plan(D.shape[0], k, p, q, 0, form="fp32", d_dtype=dtype_of(D), split_fp32=split,
+                        full_projection=full)
+        coords, eig = plan.run(Dg)
+        info = plan.info()
+        assert info["status"] == 0, info
+        res[split] = (coords.cpu().numpy(), eig.cpu().numpy())
+        plan.close()
+    X, eig = res[True]
+    err, merr = rel_eig_err(eig, ref["eigvals"]), rel_eig_err(eig, matched["eigvals"])
+    cerr = procrustes_err(X, ref["coords"])
+    dplain = rel_eig_err(eig, res[False][1])
+    say(f"    eig rel err vs fp64 {err:.3e}  vs matched {merr:.3e}  vs plain fp32 form {dplain:.3e}"
+        f"  coords procrustes {cerr:.3e}")
+    assert merr < MATCHED_EIG_BAR["fp32"]
+    assert err < EIG_BAR["fp32"]
+    assert cerr < COORD_BAR["fp32"]
+    assert dplain < 1e-6
+
+
 @pytest.mark.parametrize("form", ["fp32", "bf16", "fp8"])
 def test_misaligned_d_matches_aligned(form):
     """D at an address that is not 16-byte aligned takes the per-element load
