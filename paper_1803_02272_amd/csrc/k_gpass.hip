@@ -112,12 +112,11 @@ struct Tr<GK_FP8> {
 };
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v_t __attribute__((ext_vector_type(2)));
 
-// bf16 bits (round to nearest even) of a finite float.
-__device__ __forceinline__ uint32_t bf16_bits(float v) {
-  uint32_t u = __float_as_uint(v);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
+// Two floats rounded to nearest even into packed bf16 (one v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint32_t bf16x2_bits(f32x2 v) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2v_t));
 }
 
 constexpr int kRowB = 144;  // LDS bytes per X row within a step tile
@@ -126,7 +125,7 @@ constexpr int kRowB = 144;  // LDS bytes per X row within a step tile
 // the register file at two workgroups per CU without spilling.
 __host__ __device__ constexpr int rg_for(int gk, int cg) {
   if (gk == GK_F64) return cg <= 3 ? 4 : (cg <= 7 ? 2 : 1);
-  if (gk == GK_FP8) return cg <= 7 ? 4 : 2;  // the E4M3 decode needs a few more registers than bf16
+  if (gk == GK_FP8) return cg <= 8 ? 4 : 2;  // the E4M3 decode needs a few more registers than bf16
   return cg <= 8 ? 4 : 2;
 }
 // Recentring passes hold raw D values and recentring terms in registers as
@@ -348,7 +347,24 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
     // times 1, 1/2, 0 right of, on and left of the diagonal.
     auto a_operand = [&](int rg, int c, int64_t st, const double* cl, const RawT (&a)[RG][2][E],
                          const CT (&cv)[2][E]) -> u32x4 {
-      if constexpr (FD) {
+      if constexpr (FD && GK == GK_BF16) {
+        // fused centring write: bf16(fl32(gamma)) with gamma in fp64 (no
+        // symmetric mode here), rounded two at a time
+#pragma clang fp contract(off)
+        const int64_t k0 = st * BK + c * (BK / 2) + (lane >> 4) * E;
+        const int64_t i = row0 + rg * 16 + (lane & 15);
+        float f[E];
+#pragma unroll
+        for (int t = 0; t < E; ++t) {
+          const double d = (double)a[rg][c][t];
+          const double e = ((d * d - cl[c * (BK / 2) + (lane >> 4) * E + t]) - ri[rg]) + mval;
+          f[t] = (i < n && k0 + t < n) ? (float)(-0.5 * e) : 0.0f;
+        }
+        u32x4 w;
+#pragma unroll
+        for (int h = 0; h < E / 2; ++h) w[h] = bf16x2_bits(f32x2{f[2 * h], f[2 * h + 1]});
+        return w;
+      } else if constexpr (FD) {
 #pragma clang fp contract(off)
         const int64_t k0 = st * BK + c * (BK / 2) + (lane >> 4) * E;
         const int64_t i = row0 + rg * 16 + (lane & 15);
@@ -369,10 +385,6 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
             }
             const float h = cv[c][t] + ri[rg];
             v = SYM ? __builtin_fmaf(-1.0f, d2, h + h) : __builtin_fmaf(-0.5f, d2, h);
-          } else if constexpr (GK == GK_BF16) {
-            const double d = (double)a[rg][c][t];
-            const double e = ((d * d - cl[c * (BK / 2) + (lane >> 4) * E + t]) - ri[rg]) + mval;
-            v = (T)bf16_bits((float)(-0.5 * e));
           } else {
             const double d = (double)a[rg][c][t];
             const double e = ((d * d - cv[c][t]) - ri[rg]) + mval;
@@ -398,8 +410,8 @@ __global__ __launch_bounds__(256, (minb_of<GK, DT>(CG))) void k_gpass(
         for (int h = 0; h < 2; ++h) {
           const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)cw[h], false);  // bytes 0, 1
           const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)cw[h], true);   // bytes 2, 3
-          w[2 * h] = bf16_bits(lo.x * sc) | (bf16_bits(lo.y * sc) << 16);
-          w[2 * h + 1] = bf16_bits(hi.x * sc) | (bf16_bits(hi.y * sc) << 16);
+          w[2 * h] = bf16x2_bits(lo * sc);
+          w[2 * h + 1] = bf16x2_bits(hi * sc);
         }
         return w;
       } else {
@@ -503,8 +515,6 @@ constexpr int kX3Step = 32;           // K-values per step
 constexpr int kX3RowB = 3 * 64 + 16;  // LDS bytes per X row of a step tile: 3 planes + pad (conflict-free reads)
 
 __host__ __device__ constexpr int rg_x3(int cg, bool d8) { return cg <= (d8 ? 6 : 8) ? 2 : 1; }
-
-typedef __bf16 bf16x2v_t __attribute__((ext_vector_type(2)));
 
 // Three-term split of 8 floats into the bf16 planes w[0..2] (element t at
 // halfword t of each plane).
