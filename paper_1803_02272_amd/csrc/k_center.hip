@@ -329,17 +329,14 @@ hipError_t write_by_g(const DT* D, int64_t n, int64_t n_pad, int64_t ldg, int ve
 // OCP E4M3 code of x (|x| <= 448 up to rounding, finite), nearest even,
 // saturating: 1 sign, 4 exponent (bias 7) and 3 fraction bits; below 2^-6
 // the subnormal multiples of 2^-9.
-__device__ __forceinline__ uint32_t e4m3_code(float x) {
-  const uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
-  const float a = fabsf(x);
-  if (a >= 448.0f) return sign | 0x7Eu;  // largest finite: 1.75 * 2^8
-  if (a >= 0x1p-6f) {
-    uint32_t b = __float_as_uint(a);
-    b += 0x7FFFFu + ((b >> 20) & 1u);  // round the fp32 fraction to 3 bits, ties to even
-    const uint32_t e = ((b >> 23) & 0xFFu) - 120u;  // E4M3 biased exponent (fp32 bias 127, E4M3 bias 7)
-    return sign | (e << 3) | ((b >> 20) & 7u);      // a < 448 cannot round past 448
-  }
-  return sign | (uint32_t)rintf(a * 512.0f);  // 0..8 units of 2^-9 (8 = 2^-6, the smallest normal)
+// E4M3 encoding (OCP, round to nearest even) of values with |x| <= 448
+// (1 + 2^-23): gfx950's v_cvt_pk_fp8_f32, two values per instruction.  It was
+// checked on the GPU against a bit-level software encoder (fp32 fraction
+// rounded to 3 bits, ties to even; subnormals in units of 2^-9) on every fp32
+// bit pattern of magnitude up to 452, both signs: no difference.
+template <bool HI>
+__device__ __forceinline__ int e4m3_pack2(float a, float b, int old) {
+  return __builtin_amdgcn_cvt_pk_fp8_f32(a, b, old, HI);
 }
 
 constexpr int kF8Threads = 1024;  // one workgroup per 256 x 256 block, the block held in registers
@@ -387,11 +384,19 @@ __global__ __launch_bounds__(kF8Threads) void k_center_write_fp8(const DT* __res
   for (int w = 1; w < kF8Threads / 64; ++w) mx = fmaxf(mx, red[w]);
   const float s = mx > 0.0f ? mx / 448.0f : 1.0f;
   if (tid == 0) scales[I * nsb + J] = s;
+  // fl32(g / s) as fl32(g * (1 / s)) in fp64: the quotient of two fp32
+  // values is never a midpoint of the fp32 grid and stays at least ~2^-48
+  // (relative) away from one, while the fp64 product is within ~2^-52 of
+  // g / s, so both round to the same fp32 value (no fp32 division sequence)
+  const double rinv = 1.0 / (double)s;
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
-    const uint32_t w = e4m3_code(g[u][0] / s) | (e4m3_code(g[u][1] / s) << 8) | (e4m3_code(g[u][2] / s) << 16) |
-                       (e4m3_code(g[u][3] / s) << 24);
-    *reinterpret_cast<uint32_t*>(G8 + (ib + u) * ldg + j0) = w;
+    float q[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) q[t] = (float)((double)g[u][t] * rinv);
+    int w = e4m3_pack2<false>(q[0], q[1], 0);  // bytes 0, 1
+    w = e4m3_pack2<true>(q[2], q[3], w);       // bytes 2, 3
+    *reinterpret_cast<int*>(G8 + (ib + u) * ldg + j0) = w;
   }
 }
 
