@@ -34,12 +34,13 @@ METRIC = "n=1e5 k=100 MDS time & MFMA util, BF16 vs FP32 @1e-3 eig err; p99 late
 # workload.  Valid only while the kernel source is the one measured: the
 # sha256 prefix of the file is checked and `traffic` is null otherwise.
 TRAFFIC = {
-    # range pass, stored bf16 G, split-K 3 (the split the autotuner chose in that run)
-    "gpass": {"source": "paper_1803_02272_amd/csrc/k_gpass.hip", "sha256_16": "4d19ca55bc01d85a",
-              "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 23.098, "write_gb": 0.164},
-    # symmetric fp32 projection as three-term bf16 split (k_gpass_x3d), split-K 24
-    "gpass_ref": {"source": "paper_1803_02272_amd/csrc/k_gpass.hip", "sha256_16": "4d19ca55bc01d85a",
-                  "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 23.648, "write_gb": 0.651},
+    # range pass over the stored bf16 G; FETCH_SIZE at split-K 3, WRITE_SIZE
+    # (split-K partials) at split-K 8: the autotuner chose those in the two runs
+    "gpass": {"source": "paper_1803_02272_amd/csrc/k_gpass.hip", "sha256_16": "27b651db8e41ac0e",
+              "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 23.064, "write_gb": 0.446},
+    # symmetric fp32 projection as three-term bf16 split (k_gpass_x3d), split-K 16 / 12
+    "gpass_ref": {"source": "paper_1803_02272_amd/csrc/k_gpass.hip", "sha256_16": "27b651db8e41ac0e",
+                  "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 23.765, "write_gb": 0.337},
 }
 
 # MI355X published peaks
