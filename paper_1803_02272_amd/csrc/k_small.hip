@@ -181,13 +181,13 @@ __global__ __launch_bounds__(64) void k_rot_apply(const double2* __restrict__ ro
   const int np = le / 2;
   for (int j = tid; j < le; j += 64) v[j] = (j == i) ? 1.0 : 0.0;
   const int rounds = meta[0];
+  int r = 0;  // round within the sweep: (r0 + rr) mod (le - 1)
   for (int r0 = 0; r0 < rounds; r0 += kRotChunk) {
     const int nrc = (rounds - r0 < kRotChunk) ? rounds - r0 : kRotChunk;
     __syncthreads();
     for (int e = tid; e < nrc * np; e += 64) cs[e] = rot[(int64_t)r0 * np + e];
     __syncthreads();
-    for (int rr = 0; rr < nrc; ++rr) {
-      const int r = (r0 + rr) % (le - 1);
+    for (int rr = 0; rr < nrc; ++rr, r = (r + 1 == le - 1) ? 0 : r + 1) {
       for (int t = tid; t < np; t += 64) {
         const double2 c = cs[rr * np + t];
         if (c.y != 0.0) {

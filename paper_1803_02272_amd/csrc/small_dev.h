@@ -57,13 +57,21 @@ __device__ double block_max(double v, double* red) {
   return s;
 }
 
+// Round-robin (chess tournament) pairing of le indices: in round r of a
+// sweep, position t pairs index le - 1 with r (t = 0) or (r + t) with
+// (r - t), modulo le - 1; returned with p < q.  Callers keep 0 <= r < le - 1
+// and 0 <= t < le / 2, so one conditional subtraction or addition replaces
+// each reduction modulo le - 1.
 __device__ __forceinline__ void round_robin_pair(int le, int r, int t, int& p, int& q) {
+  const int m = le - 1;
   if (t == 0) {
-    p = le - 1;
+    p = m;
     q = r;
   } else {
-    p = (r + t) % (le - 1);
-    q = (r - t + (le - 1)) % (le - 1);
+    p = r + t;
+    p -= p >= m ? m : 0;
+    q = r - t;
+    q += q < 0 ? m : 0;
   }
   if (p > q) {
     const int x = p;
