@@ -330,7 +330,7 @@ __device__ void block_apply(const double* In, double* Out, int64_t np, int64_t n
 
 struct BShared {
   JacobiShared sh;
-  double M[kBMaxL * kBMaxL];
+  double M[kBMaxL * kBMaxL + kBMaxL];  // ld kBMaxL, or kBMaxL + 1 (odd) for the Jacobi
   double V[kBMaxL * kBMaxL];  // eigenvectors of B (gfx950: up to 160 KB of LDS per workgroup)
   double P[kBMaxL * kNB];
   double wdiag[kBMaxL];
@@ -385,23 +385,24 @@ __device__ void block_factor(BShared& S, int l, int l_pad, bool near_identity, c
   }
   // fallback: eigendecomposition of W (recomputed), T = V diag(s^{-1/2})
   __syncthreads();
-  block_gram(Yt, Yt, np, l_pad, M, ldm);
+  constexpr int ldj = kBMaxL + 1;  // odd: the Jacobi's (min, max) accesses spread over LDS banks
+  block_gram(Yt, Yt, np, l_pad, M, ldj);
   for (int e = tid; e < kBMaxL * kBMaxL; e += kBT) {
     const int i = e / kBMaxL, j = e % kBMaxL;
     Vg[e] = (i == j) ? 1.0 : 0.0;
-    if (i >= l || j >= l) M[e] = 0.0;
+    if (i >= l || j >= l) M[i * ldj + j] = 0.0;
   }
   __syncthreads();
   int rounds = 0;
-  jacobi<kBT>(M, ldm, Vg, kBMaxL, (double2*)nullptr, l + (l & 1), S.sh, &rounds);
+  jacobi<kBT>(M, ldj, Vg, kBMaxL, (double2*)nullptr, l + (l & 1), S.sh, &rounds);
   __syncthreads();
   double smax = -1.0;
-  for (int i = tid; i < l; i += kBT) smax = fmax(smax, M[i * ldm + i]);
+  for (int i = tid; i < l; i += kBT) smax = fmax(smax, M[i * ldj + i]);
   smax = block_max<kBT>(smax, S.sh.red);
   if (tid == 0) S.dropped = 0;
   __syncthreads();
   for (int i = tid; i < l; i += kBT) {
-    const double sv = M[i * ldm + i];
+    const double sv = M[i * ldj + i];
     const bool keep = smax > 0.0 && sv > 1e-13 * smax;
     S.scl[i] = keep ? 1.0 / sqrt(sv) : 0.0;
     if (!keep) atomicAdd(&S.dropped, 1);
@@ -566,16 +567,17 @@ __global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
     S.V[e] = v;  // symmetrised B staged in V
   }
   __syncthreads();
+  constexpr int ldj = kBMaxL + 1;  // odd: the Jacobi's (min, max) accesses spread over LDS banks
   for (int e = tid; e < kBMaxL * kBMaxL; e += kBT) {
-    M[e] = S.V[e];
+    M[(e / kBMaxL) * ldj + e % kBMaxL] = S.V[e];
     S.V[e] = (e / kBMaxL == e % kBMaxL) ? 1.0 : 0.0;
   }
   __syncthreads();
   // ---- eigenpairs of B ------------------------------------------------------
   int rounds = 0;
-  const int sweeps = jacobi<kBT>(M, kBMaxL, S.V, kBMaxL, (double2*)nullptr, l + (l & 1), S.sh, &rounds);
+  const int sweeps = jacobi<kBT>(M, ldj, S.V, kBMaxL, (double2*)nullptr, l + (l & 1), S.sh, &rounds);
   __syncthreads();
-  for (int i = tid; i < l; i += kBT) S.th[i] = M[i * kBMaxL + i];
+  for (int i = tid; i < l; i += kBT) S.th[i] = M[i * ldj + i];
   __syncthreads();
   for (int i = tid; i < l; i += kBT) S.perm[desc_rank(S.th, l, i)] = i;  // a permutation, NaN included
   __syncthreads();

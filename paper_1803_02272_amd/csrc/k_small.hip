@@ -17,7 +17,9 @@
 //
 // The symmetric eigensolver is cyclic Jacobi with the round-robin parallel
 // ordering: every round rotates l/2 disjoint pairs at once, each thread
-// updating whole 2x2 blocks J_p^T M_pq J_q, so a round needs two barriers.
+// updating whole 2x2 blocks J_p^T M_pq J_q of the upper triangle (pairs
+// p <= q only, half the LDS traffic of the full matrix), so a round needs
+// two barriers.
 // A rotation is skipped when |m_pq| <= 1e-17 ||M||_F; the iteration stops
 // after the first sweep that ends with off(M) <= 1e-15 ||M||_F or that
 // rotated nothing (cap 40 sweeps).  In small_eig the rotations are recorded
@@ -41,7 +43,7 @@ __global__ __launch_bounds__(kOrthThreads) void k_orth_factor(const double* __re
                                                               DevStatus* st, int near_identity) {
   constexpr int NT = kOrthThreads;
   __shared__ JacobiShared sh;
-  __shared__ double Ml[IN_LDS ? kLdsMaxL * kLdsMaxL : 1];
+  __shared__ double Ml[IN_LDS ? kLdsMaxL * (kLdsMaxL + 1) : 1];  // ld l_pad, or l_pad + 1 for the Jacobi
   __shared__ double wdiag[kMaxL];
   __shared__ double P[IN_LDS ? kLdsMaxL * kNB : kMaxL * kNB];
   __shared__ double scale[kMaxL];
@@ -91,23 +93,24 @@ __global__ __launch_bounds__(kOrthThreads) void k_orth_factor(const double* __re
   }
 
   // Fallback: T = V diag(s^{-1/2}) over the retained eigen-directions of W.
+  const int ldj = IN_LDS ? l_pad + 1 : l_pad;  // odd in LDS: the Jacobi's (min, max) accesses spread over banks
   __syncthreads();
   for (int i = tid / 64; i < l_pad; i += NT / 64)
     for (int j = tid % 64; j < l_pad; j += 64) {
-      M[i * ldm + j] = (i < l && j < l) ? W[i * l_pad + j] : 0.0;
+      M[i * ldj + j] = (i < l && j < l) ? W[i * l_pad + j] : 0.0;
       V[i * l_pad + j] = (i == j) ? 1.0 : 0.0;
     }
   __syncthreads();
   int rounds = 0;
-  jacobi<NT>(M, ldm, V, l_pad, (double2*)nullptr, le, sh, &rounds);
+  jacobi<NT>(M, ldj, V, l_pad, (double2*)nullptr, le, sh, &rounds);
   __syncthreads();
   double smax = -1.0;
-  for (int i = tid; i < l; i += NT) smax = fmax(smax, M[i * ldm + i]);
+  for (int i = tid; i < l; i += NT) smax = fmax(smax, M[i * ldj + i]);
   smax = block_max<NT>(smax, sh.red);
   if (tid == 0) dropped = 0;
   __syncthreads();
   for (int i = tid; i < l; i += NT) {
-    const double sv = M[i * ldm + i];
+    const double sv = M[i * ldj + i];
     const bool keep = smax > 0.0 && sv > 1e-13 * smax;
     scale[i] = keep ? 1.0 / sqrt(sv) : 0.0;
     if (!keep) atomicAdd(&dropped, 1);
@@ -131,18 +134,18 @@ __global__ __launch_bounds__(kEigThreads) void k_small_eig(const double* __restr
                                                         double2* __restrict__ rot, int* __restrict__ meta,
                                                         double* __restrict__ scratch, DevStatus* st) {
   __shared__ JacobiShared sh;
-  __shared__ double Ml[IN_LDS ? kLdsMaxL * kLdsMaxL : 1];
+  __shared__ double Ml[IN_LDS ? kLdsMaxL * (kLdsMaxL + 1) : 1];
   __shared__ double th[kMaxL];
   __shared__ int perm[kMaxL];
   using MT = typename std::conditional<IN_LDS, lds_double*, double*>::type;
   MT M = IN_LDS ? (MT)(void*)Ml : (MT)(void*)scratch;
   const int tid = threadIdx.x;
-  const int ldm = l_pad;
+  const int ldm = IN_LDS ? l_pad + 1 : l_pad;  // odd in LDS: the Jacobi's (min, max) accesses spread over banks
   const int le = l + (l & 1);
 
   for (int e = tid; e < l_pad * l_pad; e += kEigThreads) {
     const int i = e / l_pad, j = e % l_pad;
-    M[e] = (i < l && j < l) ? 0.5 * (B[i * l_pad + j] + B[j * l_pad + i]) : 0.0;
+    M[i * ldm + j] = (i < l && j < l) ? 0.5 * (B[i * l_pad + j] + B[j * l_pad + i]) : 0.0;
   }
   __syncthreads();
   int rounds = 0;

@@ -80,45 +80,70 @@ __device__ __forceinline__ void round_robin_pair(int le, int r, int t, int& p, i
   }
 }
 
+// Squared Frobenius norm and squared off-diagonal norm of the symmetric
+// le x le matrix held in the upper triangle of M (diagonal included).
 template <int kThreads, typename MT>
-__device__ double frob2(MT M, int ldm, int le) {
-  double f = 0.0;
-  for (int e = threadIdx.x; e < le * le; e += kThreads) {
-    const double v = M[(e / le) * ldm + e % le];
-    f += v * v;
-  }
-  return f;
-}
-
-template <int kThreads, typename MT>
-__device__ double off2(MT M, int ldm, int le) {
-  double f = 0.0;
+__device__ void upper_norms2(MT M, int ldm, int le, double& fro2, double& off2) {
+  double d = 0.0, o = 0.0;
   for (int e = threadIdx.x; e < le * le; e += kThreads) {
     const int i = e / le, j = e % le;
-    if (i != j) {
-      const double v = M[i * ldm + j];
-      f += v * v;
-    }
+    if (j < i) continue;
+    const double v = M[i * ldm + j];
+    if (i == j)
+      d += v * v;
+    else
+      o += 2.0 * v * v;
   }
-  return f;
+  fro2 = d + o;
+  off2 = o;
+}
+
+// Offset of entry (i, j) of a symmetric matrix kept in the upper triangle.
+__device__ __forceinline__ int upper_at(int i, int j, int ldm) { return i < j ? i * ldm + j : j * ldm + i; }
+
+// 1/x and 1/sqrt(y) for normal fp64 arguments: the hardware estimate refined
+// by two Newton steps (each at least doubles the correct bits), giving a
+// result within about one ulp without the IEEE division and square-root
+// sequences.
+__device__ __forceinline__ double rcp_newton(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsqrt_newton(double y) {
+  double r = __builtin_amdgcn_rsq(y);
+  r = r * fma(-0.5 * y, r * r, 1.5);
+  return r * fma(-0.5 * y, r * r, 1.5);
 }
 
 // Cyclic Jacobi on the symmetric le x le matrix M (ld ldm; le even, a padding
-// row/column of zeros is never rotated).  Either accumulates V <- V J in
+// row/column of zeros is never rotated).  Only the upper triangle of M
+// (diagonal included) is read and updated: each round rotates the 2x2 blocks
+// of pairs a <= b, whose entries are addressed by (min, max) index, so an
+// odd ldm keeps the LDS accesses of a wave on distinct banks.  On return the
+// upper triangle holds the rotated matrix (eigenvalues on the diagonal); the
+// strict lower triangle is left as it was.  Either accumulates V <- V J in
 // place (V != nullptr, ld ldv, identity on entry) or records (c, s) of every
 // pair and round in rot (rot != nullptr).  Returns sweeps used (negative if
 // the cap was hit); *rounds receives the number of rounds recorded.
 template <int kThreads, typename MT>
 __device__ int jacobi(MT M, int ldm, double* V, int ldv, double2* rot, int le, JacobiShared& sh, int* rounds) {
-  constexpr int kMaxBlocksPerThread = (kMaxL / 2) * (kMaxL / 2) / kThreads;
+  constexpr int kMaxBlocksPerThread = ((kMaxL / 2) * (kMaxL / 2 + 1) / 2 + kThreads - 1) / kThreads;
   const int tid = threadIdx.x;
   const int np = le / 2;
-  // this thread's fixed (pair a, pair b) blocks; pairs are renamed every round
-  // but the block list of a thread is the same in all rounds
+  // this thread's fixed (pair a, pair b) blocks, a <= b, in row-major order
+  // of the upper triangle; pairs are renamed every round but the block list
+  // of a thread is the same in all rounds
   int nblk = 0;
   int blk[kMaxBlocksPerThread];
-  for (int e = tid; e < np * np && nblk < kMaxBlocksPerThread; e += kThreads) blk[nblk++] = ((e / np) << 16) | (e % np);
-  const double fro = sqrt(block_sum<kThreads>(frob2<kThreads>(M, ldm, le), sh.red));
+  for (int e = tid; e < np * (np + 1) / 2 && nblk < kMaxBlocksPerThread; e += kThreads) {
+    int a = 0, rem = e;
+    while (rem >= np - a) rem -= np - a++;
+    blk[nblk++] = (a << 16) | (a + rem);
+  }
+  double fro2, off2;
+  upper_norms2<kThreads>(M, ldm, le, fro2, off2);
+  const double fro = sqrt(block_sum<kThreads>(fro2, sh.red));
   const double thr = 1e-17 * fro;
   int nr = 0;
   int sweep = 0;
@@ -133,11 +158,21 @@ __device__ int jacobi(MT M, int ldm, double* V, int ldv, double2* rot, int le, J
         const double app = M[p * ldm + p], aqq = M[q * ldm + q], apq = M[p * ldm + q];
         double c = 1.0, s = 0.0, t = 0.0;
         if (fabs(apq) > thr) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          t = fabs(tau) > 1e150 ? 0.5 / tau : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
+          // tan of the rotation angle, the root of t^2 + 2 tau t - 1 = 0 of
+          // smaller magnitude; cos = 1/sqrt(1 + t^2), sin = t cos
+          if (fabs(apq) > 1e-200) {
+            const double tau = (aqq - app) * rcp_newton(2.0 * apq);
+            const double y = fma(tau, tau, 1.0);  // finite up to |tau| ~ 1e154
+            t = fabs(tau) > 1e150 ? 0.5 * rcp_newton(tau)
+                                  : (tau >= 0.0 ? 1.0 : -1.0) * rcp_newton(fma(y, rsqrt_newton(y), fabs(tau)));
+            c = rsqrt_newton(fma(t, t, 1.0));
+          } else {  // off-diagonal near the fp64 underflow range: IEEE operations
+            const double tau = (aqq - app) / (2.0 * apq);
+            t = fabs(tau) > 1e150 ? 0.5 / tau : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+          }
           s = t * c;
-          atomicAdd(&sh.nrot, 1);
+          sh.nrot = 1;  // any rotation this sweep (all writers store the same value)
         }
         sh.pq[tid] = make_int2(p, q);
         sh.cs[tid] = make_double2(c, s);
@@ -145,9 +180,9 @@ __device__ int jacobi(MT M, int ldm, double* V, int ldv, double2* rot, int le, J
         if (rot) rot[(int64_t)nr * np + tid] = make_double2(c, s);
       }
       __syncthreads();
-      // M <- J^T M J, one 2x2 block (pair a rows, pair b columns) at a time.
-      // All loads of this thread's blocks are issued before any store (the
-      // blocks are disjoint), so their LDS latencies overlap.
+      // M <- J^T M J, one 2x2 block (pair a rows, pair b columns, a <= b) at a
+      // time.  All loads of this thread's blocks are issued before any store
+      // (the blocks are disjoint), so their LDS latencies overlap.
       for (int u0 = 0; u0 < nblk; u0 += 4) {
         double m[4][4];
         int idx[4][4];
@@ -160,10 +195,10 @@ __device__ int jacobi(MT M, int ldm, double* V, int ldv, double2* rot, int le, J
             const int a = blk[u] >> 16, b = blk[u] & 0xffff;
             act[uu] = sh.cs[a].y != 0.0 || sh.cs[b].y != 0.0;
             const int2 pqa = sh.pq[a], pqb = sh.pq[b];
-            idx[uu][0] = pqa.x * ldm + pqb.x;
-            idx[uu][1] = pqa.x * ldm + pqb.y;
-            idx[uu][2] = pqa.y * ldm + pqb.x;
-            idx[uu][3] = pqa.y * ldm + pqb.y;
+            idx[uu][0] = upper_at(pqa.x, pqb.x, ldm);
+            idx[uu][1] = upper_at(pqa.x, pqb.y, ldm);
+            idx[uu][2] = upper_at(pqa.y, pqb.x, ldm);  // == idx[uu][1] when a == b
+            idx[uu][3] = upper_at(pqa.y, pqb.y, ldm);
             if (act[uu]) {
 #pragma unroll
               for (int e = 0; e < 4; ++e) m[uu][e] = M[idx[uu][e]];
@@ -181,7 +216,6 @@ __device__ int jacobi(MT M, int ldm, double* V, int ldv, double2* rot, int le, J
             M[idx[uu][0]] = m00 - t * m01;
             M[idx[uu][3]] = m11 + t * m01;
             M[idx[uu][1]] = 0.0;
-            M[idx[uu][2]] = 0.0;
           } else {
             const double2 csa = sh.cs[a], csb = sh.cs[b];
             const double ca = csa.x, sa = csa.y, cb = csb.x, sb = csb.y;
@@ -211,7 +245,8 @@ __device__ int jacobi(MT M, int ldm, double* V, int ldv, double2* rot, int le, J
       __syncthreads();
     }
     const int nrot = sh.nrot;
-    const double off = sqrt(block_sum<kThreads>(off2<kThreads>(M, ldm, le), sh.red));
+    upper_norms2<kThreads>(M, ldm, le, fro2, off2);
+    const double off = sqrt(block_sum<kThreads>(off2, sh.red));
     converged = (nrot == 0) || (off <= 1e-15 * fro);
   }
   *rounds = nr;
