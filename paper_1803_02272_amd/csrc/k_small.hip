@@ -8,7 +8,11 @@
 //                a pivot collapses (rank-deficient or too ill-conditioned Y)
 //                it falls back to the eigendecomposition W = V S V^T and
 //                T = V S^{-1/2}, dropping directions with s <= 1e-13 s_max, so
-//                those columns of Q become exactly zero.
+//                those columns of Q become exactly zero.  For l_pad <= 128 the
+//                Cholesky and the inverse keep the matrix in registers of a
+//                1024-thread workgroup (right-looking, one barrier per column;
+//                then barrier-free back substitution per column of R^{-1});
+//                larger l use the blocked LDS/global versions.
 //   small_eig    Rayleigh-Ritz on B = Q^T G Q (symmetrised): eigenpairs in
 //                algebraic descending order (Sec. 6.2, step 2 on the projected
 //                matrix), eigenvalues keep their sign (G need not be PSD,
@@ -37,63 +41,17 @@ namespace {
 
 using namespace small;
 
-template <bool IN_LDS>
-__global__ __launch_bounds__(kOrthThreads) void k_orth_factor(const double* __restrict__ W, int l, int l_pad,
-                                                              double* __restrict__ T, double* __restrict__ scratch,
-                                                              DevStatus* st, int near_identity) {
-  constexpr int NT = kOrthThreads;
-  __shared__ JacobiShared sh;
-  __shared__ double Ml[IN_LDS ? kLdsMaxL * (kLdsMaxL + 1) : 1];  // ld l_pad, or l_pad + 1 for the Jacobi
-  __shared__ double wdiag[kMaxL];
-  __shared__ double P[IN_LDS ? kLdsMaxL * kNB : kMaxL * kNB];
-  __shared__ double scale[kMaxL];
-  __shared__ int flag, dropped;
-  using MT = typename std::conditional<IN_LDS, lds_double*, double*>::type;
-  MT M = IN_LDS ? (MT)(void*)Ml : (MT)(void*)scratch;
-  double* V = scratch + (IN_LDS ? 0 : (int64_t)l_pad * l_pad);
+// Eigen fallback of orth_factor: T = V diag(s^{-1/2}) over the retained
+// eigen-directions of W (V accumulated in global scratch, M with an odd ld
+// ldj in LDS).  Out of line, so the register needs of the Jacobi with V do
+// not weigh on the Cholesky path of the same kernel.
+template <int NT, typename MT>
+__device__ __attribute__((noinline)) void orth_fallback(const double* __restrict__ W, int l, int l_pad,
+                                                        double* __restrict__ T, MT M, int ldj, double* V,
+                                                        JacobiShared& sh, double* scale, int* dropped,
+                                                        DevStatus* st) {
   const int tid = threadIdx.x;
-  const int ldm = l_pad;
   const int le = l + (l & 1);
-
-  for (int i = tid / 64; i < l_pad; i += NT / 64)
-    for (int j = tid % 64; j < l_pad; j += 64) M[i * ldm + j] = (i < l && j < l) ? W[i * l_pad + j] : 0.0;
-  for (int i = tid; i < l; i += NT) wdiag[i] = W[i * l_pad + i];
-  __syncthreads();
-
-  if (near_identity) {
-    // Second CholeskyQR step: W = Q1^T Q1 = I + E.  If max|E| < 1e-9, then
-    // chol(I + E) = I + U + O(|E|^2) with U = triu(E), diag(E)/2 on the
-    // diagonal, and R^{-1} = I - U + O(|E|^2): no factorization needed.
-    double emax = 0.0;
-    for (int i = tid / 64; i < l; i += NT / 64)
-      for (int j = tid % 64; j < l; j += 64) emax = fmax(emax, fabs(M[i * ldm + j] - (i == j ? 1.0 : 0.0)));
-    emax = block_max<NT>(emax, sh.red);
-    if (emax < 1e-9) {
-      for (int i = tid / 64; i < l_pad; i += NT / 64)
-        for (int j = tid % 64; j < l_pad; j += 64) {
-          double t = 0.0;
-          if (i < l && j < l) {
-            const double e = M[i * ldm + j] - (i == j ? 1.0 : 0.0);
-            t = (i == j) ? 1.0 - 0.5 * e : (j > i ? -e : 0.0);
-          }
-          T[i * l_pad + j] = t;
-        }
-      if (tid == 0) st->rank_deficient = 0;
-      return;
-    }
-  }
-
-  if (chol_blocked<NT>(M, ldm, l, wdiag, &flag)) {
-    trinv_blocked<NT>(M, ldm, l, P);
-    for (int i = tid / 64; i < l_pad; i += NT / 64)
-      for (int j = tid % 64; j < l_pad; j += 64)
-        T[i * l_pad + j] = (i < l && j < l && j >= i) ? M[i * ldm + j] : 0.0;
-    if (tid == 0) st->rank_deficient = 0;
-    return;
-  }
-
-  // Fallback: T = V diag(s^{-1/2}) over the retained eigen-directions of W.
-  const int ldj = IN_LDS ? l_pad + 1 : l_pad;  // odd in LDS: the Jacobi's (min, max) accesses spread over banks
   __syncthreads();
   for (int i = tid / 64; i < l_pad; i += NT / 64)
     for (int j = tid % 64; j < l_pad; j += 64) {
@@ -107,13 +65,13 @@ __global__ __launch_bounds__(kOrthThreads) void k_orth_factor(const double* __re
   double smax = -1.0;
   for (int i = tid; i < l; i += NT) smax = fmax(smax, M[i * ldj + i]);
   smax = block_max<NT>(smax, sh.red);
-  if (tid == 0) dropped = 0;
+  if (tid == 0) *dropped = 0;
   __syncthreads();
   for (int i = tid; i < l; i += NT) {
     const double sv = M[i * ldj + i];
     const bool keep = smax > 0.0 && sv > 1e-13 * smax;
     scale[i] = keep ? 1.0 / sqrt(sv) : 0.0;
-    if (!keep) atomicAdd(&dropped, 1);
+    if (!keep) atomicAdd(dropped, 1);
   }
   __syncthreads();
   for (int i = tid / 64; i < l_pad; i += NT / 64)
@@ -121,8 +79,76 @@ __global__ __launch_bounds__(kOrthThreads) void k_orth_factor(const double* __re
       T[i * l_pad + j] = (i < l && j < l) ? V[i * l_pad + j] * scale[j] : 0.0;
   if (tid == 0) {
     atomicAdd(&st->orth_fallbacks, 1);
-    st->rank_deficient = dropped;
+    st->rank_deficient = *dropped;
   }
+}
+
+template <bool IN_LDS>
+__global__ __launch_bounds__(IN_LDS ? kOrthRegThreads : kOrthThreads) void k_orth_factor(
+    const double* __restrict__ W, int l, int l_pad, double* __restrict__ T, double* __restrict__ scratch,
+    DevStatus* st, int near_identity) {
+  constexpr int NT = IN_LDS ? kOrthRegThreads : kOrthThreads;
+  __shared__ JacobiShared sh;
+  __shared__ double Ml[IN_LDS ? kLdsMaxL * (kLdsMaxL + 1) : 1];  // ld l_pad + 1 (R, then the Jacobi)
+  __shared__ double wdiag[kMaxL];
+  __shared__ double P[IN_LDS ? 1 : kMaxL * kNB];
+  __shared__ double scale[kMaxL];
+  __shared__ __attribute__((aligned(16))) double colbuf[IN_LDS ? 2 * kLdsMaxL : 1];
+  __shared__ double rdinv[IN_LDS ? kMaxL : 1];
+  __shared__ int flag, dropped;
+  using MT = typename std::conditional<IN_LDS, lds_double*, double*>::type;
+  MT M = IN_LDS ? (MT)(void*)Ml : (MT)(void*)scratch;
+  double* V = scratch + (IN_LDS ? 0 : (int64_t)l_pad * l_pad);
+  const int tid = threadIdx.x;
+  const int ldm = IN_LDS ? l_pad + 1 : l_pad;  // odd in LDS: column reads of R spread over banks
+
+  if (!IN_LDS)
+    for (int i = tid / 64; i < l_pad; i += NT / 64)
+      for (int j = tid % 64; j < l_pad; j += 64) M[i * ldm + j] = (i < l && j < l) ? W[i * l_pad + j] : 0.0;
+  for (int i = tid; i < l; i += NT) wdiag[i] = W[i * l_pad + i];
+  __syncthreads();
+
+  if (near_identity) {
+    // Second CholeskyQR step: W = Q1^T Q1 = I + E.  If max|E| < 1e-9, then
+    // chol(I + E) = I + U + O(|E|^2) with U = triu(E), diag(E)/2 on the
+    // diagonal, and R^{-1} = I - U + O(|E|^2): no factorization needed.
+    double emax = 0.0;
+    for (int i = tid / 64; i < l; i += NT / 64)
+      for (int j = tid % 64; j < l; j += 64) emax = fmax(emax, fabs(W[i * l_pad + j] - (i == j ? 1.0 : 0.0)));
+    emax = block_max<NT>(emax, sh.red);
+    if (emax < 1e-9) {
+      for (int i = tid / 64; i < l_pad; i += NT / 64)
+        for (int j = tid % 64; j < l_pad; j += 64) {
+          double t = 0.0;
+          if (i < l && j < l) {
+            const double e = W[i * l_pad + j] - (i == j ? 1.0 : 0.0);
+            t = (i == j) ? 1.0 - 0.5 * e : (j > i ? -e : 0.0);
+          }
+          T[i * l_pad + j] = t;
+        }
+      if (tid == 0) st->rank_deficient = 0;
+      return;
+    }
+  }
+
+  if constexpr (IN_LDS) {
+    if (chol_reg<NT>(W, l_pad, M, ldm, l, wdiag, colbuf, rdinv)) {
+      trinv_reg<NT>(M, ldm, l, rdinv, T, l_pad);
+      if (tid == 0) st->rank_deficient = 0;
+      return;
+    }
+  } else {
+    if (chol_blocked<NT>(M, ldm, l, wdiag, &flag)) {
+      trinv_blocked<NT>(M, ldm, l, P);
+      for (int i = tid / 64; i < l_pad; i += NT / 64)
+        for (int j = tid % 64; j < l_pad; j += 64)
+          T[i * l_pad + j] = (i < l && j < l && j >= i) ? M[i * ldm + j] : 0.0;
+      if (tid == 0) st->rank_deficient = 0;
+      return;
+    }
+  }
+
+  orth_fallback<NT>(W, l, l_pad, T, M, IN_LDS ? l_pad + 1 : l_pad, V, sh, scale, &dropped, st);
 }
 
 // ---- Rayleigh-Ritz eigensolve ---------------------------------------------
@@ -222,7 +248,7 @@ hipError_t launch_orth_factor(const double* W, int l, int l_pad, double* T, doub
                               int near_identity, hipStream_t s) {
   if (l > kMaxL || l_pad > kMaxL || l < 1) return hipErrorInvalidValue;
   if (l_pad <= kLdsMaxL)
-    hipLaunchKernelGGL(k_orth_factor<true>, dim3(1), dim3(kOrthThreads), 0, s, W, l, l_pad, T, scratch, st,
+    hipLaunchKernelGGL(k_orth_factor<true>, dim3(1), dim3(kOrthRegThreads), 0, s, W, l, l_pad, T, scratch, st,
                        near_identity);
   else
     hipLaunchKernelGGL(k_orth_factor<false>, dim3(1), dim3(kOrthThreads), 0, s, W, l, l_pad, T, scratch, st,

@@ -11,7 +11,9 @@ namespace mds {
 namespace small {
 
 constexpr int kEigThreads = 1024;  // small_eig workgroup
-constexpr int kOrthThreads = 256;  // orth_factor workgroup
+constexpr int kOrthThreads = 256;  // orth_factor workgroup, l_pad > 128 (global scratch)
+constexpr int kOrthRegThreads = 1024;  // orth_factor workgroup, l_pad <= 128 (register-resident factor)
+constexpr int kRegSlots = 16;  // rows per thread of the register-resident factor
 constexpr int kNB = 16;            // panel width of the blocked Cholesky / inverse
 constexpr int kMaxPairs = kMaxL / 2;
 constexpr int kMaxSweeps = 40;
@@ -421,6 +423,136 @@ __device__ void trinv_blocked(MT M, int ldm, int l, double* P /* kMaxL x kNB, LD
       if (jj < nb) M[i * ldm + k0 + jj] = -acc;
     }
     __syncthreads();
+  }
+}
+
+// ---- register-resident factor for l <= 128 --------------------------------
+// Right-looking Cholesky W = L L^T (R = L^T) with NT threads.  With cw = l
+// rounded up to 64 and rpc = NT / cw threads per column (cw^2 <= kRegSlots
+// NT), thread (j, h) keeps A[i][j] of column j for the rows
+// i = 2h + 2 rpc p + e (e = 0, 1) in static register slots 2p + e.  Step k
+// reads column k from a double-buffered LDS copy (colbuf, 2 x 128) that the
+// owners of column k publish at the end of step k - 1, so a step needs one
+// barrier; the update A[i][j] -= A[i][k] A[j][k] / A[k][k] uses the unscaled
+// column (1/A[k][k] by Newton), and each column is scaled by 1/sqrt(pivot)
+// once at the end (its pivot is the value its own row held when it became
+// the pivot column; later steps do not touch it).  Rows i < j of a column
+// are never read back.  Writes R (upper triangle, ld ldm) into M and
+// 1/R[j][j] into rdinv.  Returns false (uniformly) on a pivot below
+// 1e-12 wdiag[k] (or not positive), the same test as chol_blocked.
+template <int NT, typename MT>
+__device__ bool chol_reg(const double* __restrict__ W, int ldw, MT M, int ldm, int l, const double* wdiag,
+                         double* colbuf, double* rdinv) {
+  const int tid = threadIdx.x;
+  const int cw = (l + 63) & ~63;
+  const int rpc = NT / cw;
+  const int j = tid / rpc, h = tid % rpc;
+  auto row = [&](int s) { return 2 * h + 2 * rpc * (s >> 1) + (s & 1); };
+  double a[kRegSlots];
+#pragma unroll
+  for (int s = 0; s < kRegSlots; ++s) {
+    const int i = row(s);
+    a[s] = (j < l && i < l && i >= j) ? W[j * ldw + i] : 0.0;  // A[i][j] = W[j][i]
+  }
+  if (j == 0) {
+#pragma unroll
+    for (int s = 0; s < kRegSlots; ++s) {
+      const int i = row(s);
+      if (i < l) colbuf[i] = a[s];
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < l; ++k) {
+    const double* cb = colbuf + (k & 1) * kLdsMaxL;
+    const double piv = cb[k], wk = wdiag[k], cj = cb[j < l ? j : 0];
+    if (!(piv > 1e-12 * wk) || !(piv > 0.0)) return false;
+    if (j > k && j < l) {
+      double rp = rcp_newton(piv);
+      if (!(piv > 1e-290)) rp = 1.0 / piv;  // uniform; the estimate is for normal arguments
+      const double ajk = cj * rp;
+#pragma unroll
+      for (int p = 0; p < kRegSlots / 2; ++p) {  // rows of this thread in 16-byte pairs
+        const int i0 = 2 * h + 2 * rpc * p;
+        const double2 v = *(const double2*)(cb + (i0 < kLdsMaxL - 2 ? i0 : kLdsMaxL - 2));
+        if (i0 >= j && i0 < l) a[2 * p] -= v.x * ajk;
+        if (i0 + 1 >= j && i0 + 1 < l) a[2 * p + 1] -= v.y * ajk;
+      }
+      if (j == k + 1) {  // publish the finished column k + 1
+        double* nb = colbuf + ((k + 1) & 1) * kLdsMaxL;
+#pragma unroll
+        for (int s = 0; s < kRegSlots; ++s) {
+          const int i = row(s);
+          if (i >= j && i < l) nb[i] = a[s];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double pj = 0.0;  // the pivot of column j, held by one lane of the column
+#pragma unroll
+  for (int s = 0; s < kRegSlots; ++s) pj = (row(s) == j) ? a[s] : pj;
+  for (int o = 1; o < rpc; o <<= 1) pj += __shfl_xor(pj, o, 64);
+  const double rs = (j < l) ? 1.0 / sqrt(pj) : 0.0;
+#pragma unroll
+  for (int s = 0; s < kRegSlots; ++s) {
+    const int i = row(s);
+    if (j < l && i < l && i >= j) M[j * ldm + i] = (i == j) ? pj * rs : a[s] * rs;
+  }
+  if (j < l && h == 0) rdinv[j] = rs;
+  __syncthreads();
+  return true;
+}
+
+// T = R^{-1} for the upper R in M (ld ldm) with 1/R[m][m] in rdinv, written
+// to T (row-major, ld ldt; zero below the diagonal and in rows/columns
+// l..ldt-1).  Column j of T solves R t = e_j upwards; thread (j, h) keeps
+// the entries of rows i = h + rpc s in static slots.  The steps m run
+// downwards in slot order, so the owner of t_m holds it in a static slot and
+// hands it to the other lanes of its column (same wave) with a shuffle; R
+// is only read, so the columns need no barrier.  A wave stops once every one
+// of its columns is finished.
+template <int NT, typename MT>
+__device__ void trinv_reg(MT M, int ldm, int l, const double* rdinv, double* __restrict__ T, int ldt) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int cw = (l + 63) & ~63;
+  const int rpc = NT / cw;
+  const int j = tid / rpc, h = tid % rpc;
+  double b[kRegSlots], rdv[kRegSlots];
+#pragma unroll
+  for (int s = 0; s < kRegSlots; ++s) {
+    const int i = h + rpc * s;
+    b[s] = (i == j) ? 1.0 : 0.0;
+    rdv[s] = rdinv[i < l ? i : 0];
+  }
+  const int jmax = __builtin_amdgcn_readfirstlane((tid | 63) / rpc);  // last column of this wave
+#pragma unroll
+  for (int sp = kRegSlots - 1; sp >= 0; --sp) {
+    for (int hp = rpc - 1; hp >= 0; --hp) {
+      const int m = hp + rpc * sp;
+      if (m >= l || m > jmax) continue;  // uniform
+      double r[kRegSlots];
+#pragma unroll
+      for (int s = 0; s <= sp; ++s) {
+        const int i = h + rpc * s;
+        r[s] = M[(i < m ? i : 0) * ldm + m];
+      }
+      const double own = b[sp] * rdv[sp];  // t_m in the lane that owns row m
+      const double tsh = __shfl(own, (lane & ~(rpc - 1)) | hp, 64);
+      const double t = (m <= j) ? tsh : 0.0;
+      if (h == hp) b[sp] = t;
+#pragma unroll
+      for (int s = 0; s <= sp; ++s) {
+        const int i = h + rpc * s;
+        if (i < m) b[s] -= r[s] * t;
+      }
+    }
+  }
+  if (j < ldt) {
+#pragma unroll
+    for (int s = 0; s < kRegSlots; ++s) {
+      const int i = h + rpc * s;
+      if (i < ldt) T[i * ldt + j] = (j < l && i <= j) ? b[s] : 0.0;
+    }
   }
 }
 
