@@ -244,21 +244,24 @@ __global__ __launch_bounds__(256) void k_cast(const double* __restrict__ In, int
 // Out[j][i] = sum_a T[a][j] In[a][i] on fp64 MFMA (16x16x4): A operand = T^T
 // (rows j, K = a) from an LDS block of 64 columns of T, B operand = In (K = a,
 // columns i, 16 consecutive i per lane group: 128-byte loads).  A workgroup
-// covers 256 columns i (64 per wave, four 16-column tiles) and 64 rows j; the
-// l rows of In are padded to a multiple of 4 (In is zero beyond l).
+// of 8 waves covers 256 columns i (32 per wave, two 16-column tiles) and 64
+// rows j; the l rows of In are padded to a multiple of 4 (In is zero beyond
+// l).  Two tiles per wave at 8 waves keep more loads of In in flight than
+// four tiles at 4 waves (fewer accumulators per wave, twice the waves).
 constexpr int kApJ = 64;
 constexpr int kApRow = kApJ + 2;  // LDS row stride (doubles)
-constexpr int kApN = 4;           // 16-column tiles per wave
+constexpr int kApN = 2;           // 16-column tiles per wave
+constexpr int kApThreads = 512;
 
-__global__ __launch_bounds__(256) void k_apply(const double* __restrict__ In, int l, int64_t ldg,
+__global__ __launch_bounds__(kApThreads) void k_apply(const double* __restrict__ In, int l, int64_t ldg,
                                                const double* __restrict__ T, int ldt, int lt, int l_out,
                                                double* __restrict__ Out) {
   extern __shared__ double Ts[];  // la x kApRow
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int la = (l + 3) & ~3;
   const int j0 = blockIdx.y * kApJ;
-  const int64_t i0 = (int64_t)blockIdx.x * (64 * kApN) + wave * (16 * kApN);
-  for (int e = tid; e < la * kApJ; e += 256) {
+  const int64_t i0 = (int64_t)blockIdx.x * ((kApThreads / 64) * 16 * kApN) + wave * (16 * kApN);
+  for (int e = tid; e < la * kApJ; e += kApThreads) {
     const int a = e / kApJ, jj = e % kApJ, j = j0 + jj;
     Ts[a * kApRow + jj] = (a < l && j < lt) ? T[(int64_t)a * ldt + j] : 0.0;
   }
@@ -433,7 +436,8 @@ hipError_t launch_gram(const double* A, const double* B, int l_pad, int64_t ldg,
 
 hipError_t launch_apply(const double* In, int l, int64_t ldg, const double* T, int ldt, int lt, int l_pad,
                         double* Out, int xk, void* Xc, hipStream_t s) {
-  if (l > kMaxL || l_pad > kMaxL || ldg % (64 * kApN) != 0) return hipErrorInvalidValue;
+  constexpr int64_t cols = (kApThreads / 64) * 16 * kApN;  // columns i per workgroup
+  if (l > kMaxL || l_pad > kMaxL || ldg % cols != 0) return hipErrorInvalidValue;
   const int la = (l + 3) & ~3;
   const size_t shm = (size_t)la * kApRow * sizeof(double);
   static bool attr_set = false;
@@ -442,10 +446,10 @@ hipError_t launch_apply(const double* In, int l, int64_t ldg, const double* T, i
     (void)hipFuncSetAttribute((const void*)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     attr_set = true;
   }
-  dim3 grid((unsigned)(ldg / (64 * kApN)), (unsigned)((l_pad + kApJ - 1) / kApJ));
-  hipLaunchKernelGGL(k_apply, grid, dim3(256), shm, s, In, l, ldg, T, ldt, lt, l_pad, Out);
+  dim3 grid((unsigned)(ldg / cols), (unsigned)((l_pad + kApJ - 1) / kApJ));
+  hipLaunchKernelGGL(k_apply, grid, dim3(kApThreads), shm, s, In, l, ldg, T, ldt, lt, l_pad, Out);
   if (Xc) {
-    // the cast copy in its own elementwise kernel keeps k_apply at two waves per SIMD
+    // the cast copy in its own elementwise kernel (fewer registers in k_apply)
     const int64_t elems = (int64_t)l_pad * ldg;
     const dim3 cg((unsigned)((elems / 4 + 255) / 256));
     if (xk == GK_F64)
