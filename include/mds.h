@@ -99,6 +99,15 @@ typedef enum mds_dtype { MDS_DTYPE_F32 = 0, MDS_DTYPE_F64 = 1 } mds_dtype;
  *   FP32 form, to fp32 accuracy, in less time.  No effect in the other
  *   forms (the BF16 and FP8 forms' projection already uses it). */
 #define MDS_FLAG_SPLIT_FP32 4
+/*   MDS_FLAG_FULL_STATS: read all of D in the centring statistics.  By
+ *   default that pass uses the symmetry of D (the contract) and reads only
+ *   its 1024 x 1024 tiles on and above the diagonal, half of D: the row
+ *   means r_i = (1/n) sum_j d_ij^2 are assembled from the row sums of the
+ *   tiles right of the diagonal and the column sums of the tiles above it,
+ *   and c = r.  With the flag, r and c are the row and column means of all
+ *   of D as written in the double-centring formula; both agree up to
+ *   rounding for a symmetric D. */
+#define MDS_FLAG_FULL_STATS 8
 
 typedef struct mds_opts {
   int32_t form;        /* mds_form (default MDS_FORM_FP32) */

@@ -39,11 +39,12 @@ class Plan:
     fp32_mfma_projection=True runs the bf16/fp8 forms' fp32 projection on fp32
     MFMA instead of the three-term bf16 split (MDS_FLAG_FP32_MFMA_PROJECTION);
     split_fp32=True runs every pass of the fp32 form as that split
-    (MDS_FLAG_SPLIT_FP32)."""
+    (MDS_FLAG_SPLIT_FP32); full_stats=True reads all of D in the centring
+    statistics instead of its upper-triangle tiles (MDS_FLAG_FULL_STATS)."""
 
     def __init__(self, n, k, oversample=10, q=2, seed=0, form="fp32", d_dtype="f32", gpass_split=0,
                  workspace="torch", full_projection=False, proj_split=0, write_split=0,
-                 fp32_mfma_projection=False, split_fp32=False):
+                 fp32_mfma_projection=False, split_fp32=False, full_stats=False):
         L = _capi.lib()
         self.n, self.k, self.oversample, self.q, self.seed = int(n), int(k), int(oversample), int(q), int(seed)
         self.form = form
@@ -53,7 +54,8 @@ class Plan:
                              int(gpass_split),
                              (_capi.FLAG_FULL_PROJECTION if full_projection else 0)
                              | (_capi.FLAG_FP32_MFMA_PROJECTION if fp32_mfma_projection else 0)
-                             | (_capi.FLAG_SPLIT_FP32 if split_fp32 else 0),
+                             | (_capi.FLAG_SPLIT_FP32 if split_fp32 else 0)
+                             | (_capi.FLAG_FULL_STATS if full_stats else 0),
                              int(proj_split), int(write_split))
         h = ctypes.c_void_p()
         check(L.mds_plan_ex(ctypes.byref(h), self.n, self.k, self.oversample, self.q, self.seed,

@@ -42,6 +42,7 @@ MAX_L = 256
 FLAG_FULL_PROJECTION = 1
 FLAG_FP32_MFMA_PROJECTION = 2
 FLAG_SPLIT_FP32 = 4
+FLAG_FULL_STATS = 8
 
 
 class MdsOpts(ctypes.Structure):

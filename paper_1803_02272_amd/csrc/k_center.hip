@@ -3,10 +3,17 @@
 //   r_i = (1/n) sum_j d_ij^2,  c_j = (1/n) sum_i d_ij^2,  m = (1/n^2) sum_ij d_ij^2.
 //
 // Two HBM-streaming passes over D:
-//   stats: one read of D; per 1024 x 1024 tile, each wave owns 256 rows and
-//          every lane 16 columns; row partials come from a 64-lane butterfly,
-//          column partials from registers and a fixed-order LDS merge of the
-//          four waves; the tiles on the diagonal also sum d_ii^2.  Partials
+//   stats: per 1024 x 1024 tile, each wave owns 256 rows and every lane 16
+//          columns; row partials come from a 64-lane butterfly, column
+//          partials from registers and a fixed-order LDS merge of the four
+//          waves; the tiles on the diagonal also sum d_ii^2.  With a
+//          symmetric D (the default) only the tiles on and above the
+//          diagonal are read, half of D: an off-diagonal tile's row sums go
+//          to its rows and its column sums to the mirrored rows, so
+//          r_i = c_i = (1/n) (sum over tiles right of and on the diagonal
+//          of row i's partials + sum over tiles above it of column i's
+//          partials), and its sum of d^4 counts twice.  The full mode reads
+//          all of D and keeps row and column means as written.  Partials
 //          are combined in a fixed order afterwards, so results are bitwise
 //          reproducible (no floating-point atomics).
 //   write: one read of D and one write of G in the pass dtype (plus an fp32
@@ -69,17 +76,26 @@ static_assert(kStatsRows == kStatsCols, "the diagonal of D lies in the tiles wit
 // One read of D per 1024 x 1024 tile.  Loads of the next batch of rows are
 // issued before the current batch is reduced (raw values held in registers).
 // p4part[rb * ncb + cb] = sum of d^4 over the tile; a diagonal tile (cb == rb)
-// also writes p4part[ncb * nrb + rb] = sum of its d_ii^2.
+// also writes p4part[ncb * nrb + rb] = sum of its d_ii^2.  sym: tiles below
+// the diagonal (cb < rb) write zero partials and read nothing, the diagonal
+// tile writes zero column partials, and an off-diagonal tile's d^4 sum is
+// doubled.
 template <typename DT>
 __global__ __launch_bounds__(256, 2) void k_stats(const DT* __restrict__ D, int64_t n, int base_vec,
                                                   double* __restrict__ rowpart, double* __restrict__ colpart,
-                                                  double* __restrict__ p4part) {
+                                                  double* __restrict__ p4part, int sym) {
 #pragma clang fp contract(off)
   constexpr int RB = 2;  // rows per batch
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t cb = blockIdx.x, rb = blockIdx.y;
   const int64_t c0 = cb * kStatsCols;
+  if (sym && cb < rb) {  // the mirror of tile (rb, cb) above the diagonal holds these sums
+    for (int64_t i = rb * kStatsRows + threadIdx.x; i < n && i < (rb + 1) * kStatsRows; i += 256) rowpart[cb * n + i] = 0.0;
+    for (int64_t c = c0 + threadIdx.x; c < n && c < c0 + kStatsCols; c += 256) colpart[rb * n + c] = 0.0;
+    if (threadIdx.x == 0) p4part[rb * gridDim.x + cb] = 0.0;
+    return;
+  }
   const int64_t r0 = rb * kStatsRows + (int64_t)wave * kRowsPerWave;
   const int64_t r1 = (r0 + kRowsPerWave < n) ? r0 + kRowsPerWave : n;
   double cacc[16];
@@ -158,23 +174,26 @@ __global__ __launch_bounds__(256, 2) void k_stats(const DT* __restrict__ D, int6
     shd[wave] = accd;
   }
   __syncthreads();
+  const bool mirror_cols = !sym || cb != rb;  // sym: the diagonal tile's column sums repeat its row sums
   for (int cc = threadIdx.x; cc < kStatsCols; cc += 256) {
     const int64_t c = c0 + cc;
-    if (c < n) colpart[rb * n + c] = ((sh[0][cc] + sh[1][cc]) + sh[2][cc]) + sh[3][cc];
+    if (c < n) colpart[rb * n + c] = mirror_cols ? ((sh[0][cc] + sh[1][cc]) + sh[2][cc]) + sh[3][cc] : 0.0;
   }
   if (threadIdx.x == 0) {
-    p4part[rb * gridDim.x + cb] = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
+    const double q4 = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
+    p4part[rb * gridDim.x + cb] = (sym && cb != rb) ? 2.0 * q4 : q4;
     if (diag_tile) p4part[(int64_t)gridDim.x * gridDim.y + rb] = ((shd[0] + shd[1]) + shd[2]) + shd[3];
   }
 }
 
 // r_i, c_j (means of d^2), and hc_j = fl32(c_j / 2) for the fp32 recentring
-// of the G-passes (zero beyond n up to ldg).
+// of the G-passes (zero beyond n up to ldg).  sym: r_i = c_i from the row
+// and column partials together.
 __global__ __launch_bounds__(256) void k_stats_reduce(const double* __restrict__ rowpart,
                                                       const double* __restrict__ colpart, int64_t ncb,
                                                       int64_t nrb, int64_t n, int64_t ldg, double* __restrict__ r,
                                                       double* __restrict__ c, double* __restrict__ rsum,
-                                                      float* __restrict__ hc) {
+                                                      float* __restrict__ hc, int sym) {
 #pragma clang fp contract(off)
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= ldg) return;
@@ -188,10 +207,18 @@ __global__ __launch_bounds__(256) void k_stats_reduce(const double* __restrict__
   double t = 0.0;
 #pragma unroll 8
   for (int64_t b = 0; b < nrb; ++b) t += colpart[b * n + i];
-  rsum[i] = s;
-  r[i] = s / (double)n;
-  c[i] = t / (double)n;
-  hc[i] = (float)(0.5 * (t / (double)n));
+  if (sym) {
+    const double u = s + t;
+    rsum[i] = u;
+    r[i] = u / (double)n;
+    c[i] = u / (double)n;
+    hc[i] = (float)(0.5 * (u / (double)n));
+  } else {
+    rsum[i] = s;
+    r[i] = s / (double)n;
+    c[i] = t / (double)n;
+    hc[i] = (float)(0.5 * (t / (double)n));
+  }
 }
 
 // Grand mean m, and the by-products ||G||_F^2 and tr(G) from their closed
@@ -425,17 +452,19 @@ int64_t stats_parts(int64_t n) {
 
 hipError_t launch_center_stats(const void* D, int d_is_f64, int64_t n, int64_t ldg, double* rowpart,
                                double* colpart, double* p4part, double* r, double* c, double* rsum, float* hc,
-                               double* mean_all, DevStatus* st, hipStream_t s) {
+                               double* mean_all, DevStatus* st, int sym, hipStream_t s) {
   const int64_t ncb = (n + kStatsCols - 1) / kStatsCols;
   const int64_t nrb = (n + kStatsRows - 1) / kStatsRows;
   const int vec = ((uintptr_t)D % 16) == 0;
   dim3 grid((unsigned)ncb, (unsigned)nrb);
   if (d_is_f64)
-    hipLaunchKernelGGL(k_stats<double>, grid, dim3(256), 0, s, (const double*)D, n, vec, rowpart, colpart, p4part);
+    hipLaunchKernelGGL(k_stats<double>, grid, dim3(256), 0, s, (const double*)D, n, vec, rowpart, colpart, p4part,
+                       sym);
   else
-    hipLaunchKernelGGL(k_stats<float>, grid, dim3(256), 0, s, (const float*)D, n, vec, rowpart, colpart, p4part);
+    hipLaunchKernelGGL(k_stats<float>, grid, dim3(256), 0, s, (const float*)D, n, vec, rowpart, colpart, p4part,
+                       sym);
   hipLaunchKernelGGL(k_stats_reduce, dim3((unsigned)((ldg + 255) / 256)), dim3(256), 0, s, rowpart, colpart, ncb,
-                     nrb, n, ldg, r, c, rsum, hc);
+                     nrb, n, ldg, r, c, rsum, hc, sym);
   hipLaunchKernelGGL(k_grand, dim3(1), dim3(1024), 0, s, rsum, r, c, p4part, ncb * nrb, nrb, n, mean_all, st);
   return hipGetLastError();
 }

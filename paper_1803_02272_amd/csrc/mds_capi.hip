@@ -273,7 +273,7 @@ mds_status mds::run_plan(mds_plan_s* P, const void* D, double* coords, double* e
   MDS_TRY(launch_center_stats(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->ldg, P->at<double>(P->rowpart),
                               P->at<double>(P->colpart), P->at<double>(P->p4part), P->at<double>(P->r),
                               P->at<double>(P->c), P->at<double>(P->rsum), P->at<float>(P->hc),
-                              P->at<double>(P->mean), st, s),
+                              P->at<double>(P->mean), st, (P->opts.flags & MDS_FLAG_FULL_STATS) == 0 ? 1 : 0, s),
           "centring stats");
   }
   // fused: the bf16 G is written by the first range pass (needs Omega first)
@@ -378,7 +378,7 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
     return fail(MDS_ERR_INVALID_ARG, "unknown D dtype %d", o.d_dtype);
   if (o.gpass_split < 0 || o.proj_split < 0 || o.write_split < 0)
     return fail(MDS_ERR_INVALID_ARG, "negative split (%d, %d, %d)", o.gpass_split, o.proj_split, o.write_split);
-  if (o.flags & ~(MDS_FLAG_FULL_PROJECTION | MDS_FLAG_FP32_MFMA_PROJECTION | MDS_FLAG_SPLIT_FP32))
+  if (o.flags & ~(MDS_FLAG_FULL_PROJECTION | MDS_FLAG_FP32_MFMA_PROJECTION | MDS_FLAG_SPLIT_FP32 | MDS_FLAG_FULL_STATS))
     return fail(MDS_ERR_INVALID_ARG, "unknown flags 0x%x", o.flags);
   mds_plan_s* P = new (std::nothrow) mds_plan_s();
   if (!P) return fail(MDS_ERR_OOM, "host allocation failed");

@@ -52,10 +52,11 @@ constexpr int kStatsCols = 1024;  // columns per stats tile
 constexpr int kStatsRows = 1024;  // rows per stats tile
 // r, c, m (fp64), hc = fl32(c/2) (ldg floats, zero beyond n), and
 // ||G||_F^2, tr(G) in the status words.  p4part: stats_parts(n) doubles.
+// sym: read the tiles on and above the diagonal only (D symmetric), r = c.
 int64_t stats_parts(int64_t n);
 hipError_t launch_center_stats(const void* D, int d_is_f64, int64_t n, int64_t ldg, double* rowpart,
                                double* colpart, double* p4part, double* r, double* c, double* rsum, float* hc,
-                               double* mean_all, DevStatus* st, hipStream_t s);
+                               double* mean_all, DevStatus* st, int sym, hipStream_t s);
 // FP8 storage of G: per 256 x 256 block, g = fl32(gamma) (gamma in fp64),
 // s = fl32(max|g| / 448) (1 for an all-zero block), code = E4M3(fl32(g / s))
 // rounded to nearest even and saturated at 448.  scales: nsb x nsb fp32,

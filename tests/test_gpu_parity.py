@@ -137,25 +137,60 @@ def test_centring_stage(name, form):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_centring_trace_nonzero_diagonal(dtype):
+@pytest.mark.parametrize("full_stats", [False, True])
+def test_centring_trace_nonzero_diagonal(dtype, full_stats):
     # A distance matrix has a zero diagonal, but the centring is defined for any
     # square D: tr G = -1/2 (sum_i d_ii^2 - n m) picks up the diagonal, which lies
     # in several 1024 x 1024 statistics tiles here (n = 2600, ragged last tile).
+    # The default statistics read the tiles on and above the diagonal of a
+    # symmetric D; full_stats reads all of an asymmetric one (row and column
+    # means as written).
     n = 2600
     D, _, _, _ = case("gm2000_f64")
     rng = np.random.default_rng(7)
     Dn = np.abs(rng.standard_normal((n, n))) + 1.0
     Dn[:2000, :2000] = D
+    if not full_stats:
+        Dn = 0.5 * (Dn + Dn.T)
     Dn[np.arange(n), np.arange(n)] = rng.uniform(0.5, 3.0, n)
     Dn = np.ascontiguousarray(Dn.astype(dtype))
-    say(f"[centring trace] n={n} dtype={np.dtype(dtype).name}")
-    plan = mds.Plan(n, 5, 5, 0, 0, form="fp64", d_dtype=dtype_of(Dn))
+    say(f"[centring trace] n={n} dtype={np.dtype(dtype).name} full_stats={full_stats}")
+    plan = mds.Plan(n, 5, 5, 0, 0, form="fp64", d_dtype=dtype_of(Dn), full_stats=full_stats)
     plan.run_stages(torch.from_numpy(Dn).cuda(), _capi.STAGE_RANGE, 1)
     torch.cuda.synchronize()
     G = O.gram_matrix(Dn)
     info = plan.info()
     assert np.isclose(info["trace"], np.trace(G), rtol=1e-12)
     assert np.isclose(info["frob2"], np.sum(G * G), rtol=1e-11)
+    D2 = Dn.astype(np.float64) ** 2
+    r_g = plan.buffer(_capi.BUF_ROWMEAN).double().cpu().numpy()[:n, 0]
+    c_g = plan.buffer(_capi.BUF_COLMEAN).double().cpu().numpy()[:n, 0]
+    assert np.allclose(r_g, D2.mean(axis=1), rtol=1e-13, atol=0)
+    assert np.allclose(c_g, D2.mean(axis=0), rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("form", ["fp64", "bf16"])
+def test_symmetric_stats_match_full(form):
+    # Default statistics (tiles on and above the diagonal, r = c) against the
+    # full read on a symmetric D spanning 3 x 3 tiles (n = 3001, ragged last one):
+    # the same centring up to the order of the fp64 sums.
+    D, k, p, q = case("amp3001_f32")
+    n = D.shape[0]
+    say(f"[symmetric stats] n={n} form={form}")
+    outs = []
+    for full in (False, True):
+        plan = mds.Plan(n, k, p, q, 0, form=form, d_dtype=dtype_of(D), full_stats=full)
+        coords, eig = plan.run(torch.from_numpy(D).cuda())
+        torch.cuda.synchronize()
+        info = plan.info()
+        assert info["status"] == 0, info
+        outs.append((eig.cpu().numpy(), info))
+        plan.close()
+    (e0, i0), (e1, i1) = outs
+    for key in ("frob2", "trace", "sum_sq"):
+        if key in i0:
+            assert np.isclose(i0[key], i1[key], rtol=1e-13), key
+    assert np.max(np.abs(e0 - e1)) <= (1e-12 if form == "fp64" else 1e-6) * np.max(np.abs(e1))
 
 
 @pytest.mark.parametrize("form", ["fp64", "fp32", "bf16"])
