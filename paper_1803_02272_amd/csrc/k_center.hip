@@ -76,26 +76,29 @@ static_assert(kStatsRows == kStatsCols, "the diagonal of D lies in the tiles wit
 // One read of D per 1024 x 1024 tile.  Loads of the next batch of rows are
 // issued before the current batch is reduced (raw values held in registers).
 // p4part[rb * ncb + cb] = sum of d^4 over the tile; a diagonal tile (cb == rb)
-// also writes p4part[ncb * nrb + rb] = sum of its d_ii^2.  sym: tiles below
-// the diagonal (cb < rb) write zero partials and read nothing, the diagonal
-// tile writes zero column partials, and an off-diagonal tile's d^4 sum is
-// doubled.
+// also writes p4part[np4 + rb] = sum of its d_ii^2 (np4 = ncb * nrb).  sym:
+// the grid is one workgroup per tile on or above the diagonal, taken in
+// row-major order of the upper triangle (np4 = nb (nb + 1) / 2, p4part
+// indexed by that order); the diagonal tile writes no column partials and an
+// off-diagonal tile's d^4 sum is doubled.
 template <typename DT>
 __global__ __launch_bounds__(256, 2) void k_stats(const DT* __restrict__ D, int64_t n, int base_vec,
                                                   double* __restrict__ rowpart, double* __restrict__ colpart,
-                                                  double* __restrict__ p4part, int sym) {
+                                                  double* __restrict__ p4part, int sym, int64_t nb) {
 #pragma clang fp contract(off)
   constexpr int RB = 2;  // rows per batch
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t cb = blockIdx.x, rb = blockIdx.y;
-  const int64_t c0 = cb * kStatsCols;
-  if (sym && cb < rb) {  // the mirror of tile (rb, cb) above the diagonal holds these sums
-    for (int64_t i = rb * kStatsRows + threadIdx.x; i < n && i < (rb + 1) * kStatsRows; i += 256) rowpart[cb * n + i] = 0.0;
-    for (int64_t c = c0 + threadIdx.x; c < n && c < c0 + kStatsCols; c += 256) colpart[rb * n + c] = 0.0;
-    if (threadIdx.x == 0) p4part[rb * gridDim.x + cb] = 0.0;
-    return;
+  int64_t cb = blockIdx.x, rb = blockIdx.y, p4i = rb * nb + cb, np4 = nb * nb;
+  if (sym) {  // tile t of the upper triangle: row rb holds nb - rb tiles
+    int64_t t = blockIdx.x;
+    rb = 0;
+    while (t >= nb - rb) t -= nb - rb++;
+    cb = rb + t;
+    p4i = blockIdx.x;
+    np4 = nb * (nb + 1) / 2;
   }
+  const int64_t c0 = cb * kStatsCols;
   const int64_t r0 = rb * kStatsRows + (int64_t)wave * kRowsPerWave;
   const int64_t r1 = (r0 + kRowsPerWave < n) ? r0 + kRowsPerWave : n;
   double cacc[16];
@@ -181,8 +184,8 @@ __global__ __launch_bounds__(256, 2) void k_stats(const DT* __restrict__ D, int6
   }
   if (threadIdx.x == 0) {
     const double q4 = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
-    p4part[rb * gridDim.x + cb] = (sym && cb != rb) ? 2.0 * q4 : q4;
-    if (diag_tile) p4part[(int64_t)gridDim.x * gridDim.y + rb] = ((shd[0] + shd[1]) + shd[2]) + shd[3];
+    p4part[p4i] = (sym && cb != rb) ? 2.0 * q4 : q4;
+    if (diag_tile) p4part[np4 + rb] = ((shd[0] + shd[1]) + shd[2]) + shd[3];
   }
 }
 
@@ -201,12 +204,14 @@ __global__ __launch_bounds__(256) void k_stats_reduce(const double* __restrict__
     hc[i] = 0.0f;
     return;
   }
+  // sym: row i's tiles right of and on the diagonal, column i's tiles above it
+  const int64_t bi = i / kStatsRows;
   double s = 0.0;
 #pragma unroll 8
-  for (int64_t b = 0; b < ncb; ++b) s += rowpart[b * n + i];
+  for (int64_t b = sym ? bi : 0; b < ncb; ++b) s += rowpart[b * n + i];
   double t = 0.0;
 #pragma unroll 8
-  for (int64_t b = 0; b < nrb; ++b) t += colpart[b * n + i];
+  for (int64_t b = 0; b < (sym ? bi : nrb); ++b) t += colpart[b * n + i];
   if (sym) {
     const double u = s + t;
     rsum[i] = u;
@@ -456,16 +461,17 @@ hipError_t launch_center_stats(const void* D, int d_is_f64, int64_t n, int64_t l
   const int64_t ncb = (n + kStatsCols - 1) / kStatsCols;
   const int64_t nrb = (n + kStatsRows - 1) / kStatsRows;
   const int vec = ((uintptr_t)D % 16) == 0;
-  dim3 grid((unsigned)ncb, (unsigned)nrb);
+  dim3 grid = sym ? dim3((unsigned)(ncb * (ncb + 1) / 2)) : dim3((unsigned)ncb, (unsigned)nrb);
   if (d_is_f64)
     hipLaunchKernelGGL(k_stats<double>, grid, dim3(256), 0, s, (const double*)D, n, vec, rowpart, colpart, p4part,
-                       sym);
+                       sym, ncb);
   else
     hipLaunchKernelGGL(k_stats<float>, grid, dim3(256), 0, s, (const float*)D, n, vec, rowpart, colpart, p4part,
-                       sym);
+                       sym, ncb);
   hipLaunchKernelGGL(k_stats_reduce, dim3((unsigned)((ldg + 255) / 256)), dim3(256), 0, s, rowpart, colpart, ncb,
                      nrb, n, ldg, r, c, rsum, hc, sym);
-  hipLaunchKernelGGL(k_grand, dim3(1), dim3(1024), 0, s, rsum, r, c, p4part, ncb * nrb, nrb, n, mean_all, st);
+  hipLaunchKernelGGL(k_grand, dim3(1), dim3(1024), 0, s, rsum, r, c, p4part, sym ? ncb * (ncb + 1) / 2 : ncb * nrb,
+                     nrb, n, mean_all, st);
   return hipGetLastError();
 }
 
