@@ -41,6 +41,12 @@ namespace {
 
 using namespace small;
 
+// the register-resident factor holds cw^2 / NT rows per thread (cw = l rounded
+// up to 64) in kRegSlots registers: every l_pad <= kLdsMaxL must fit
+static_assert(kLdsMaxL * kLdsMaxL <= kRegSlots * kOrthRegThreads, "register slots of chol_reg / trinv_reg");
+static_assert(kOrthRegThreads / kLdsMaxL <= 64 && (kOrthRegThreads / kLdsMaxL) * kLdsMaxL == kOrthRegThreads,
+              "the lanes of one column share a wave");
+
 // Eigen fallback of orth_factor: T = V diag(s^{-1/2}) over the retained
 // eigen-directions of W (V accumulated in global scratch, M with an odd ld
 // ldj in LDS).  Out of line, so the register needs of the Jacobi with V do
