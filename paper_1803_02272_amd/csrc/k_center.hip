@@ -15,7 +15,9 @@
 //          partials), and its sum of d^4 counts twice.  The full mode reads
 //          all of D and keeps row and column means as written.  Partials
 //          are combined in a fixed order afterwards, so results are bitwise
-//          reproducible (no floating-point atomics).
+//          reproducible (no floating-point atomics).  A symmetric D with
+//          n <= 16384 is read row by row instead (one wave per row): at those
+//          sizes the tile grid would leave most of the GPU idle.
 //   write: one read of D and one write of G in the pass dtype (plus an fp32
 //          copy for the refinement pass when requested), with ||G||_F^2 and
 //          tr(G) partials.  Squares are formed in fp64 (exact for fp32 input)
@@ -224,6 +226,76 @@ __global__ __launch_bounds__(256) void k_stats_reduce(const double* __restrict__
     c[i] = t / (double)n;
     hc[i] = (float)(0.5 * (t / (double)n));
   }
+}
+
+// Statistics of a symmetric D up to kStatsRowModeMax points: one wave per row
+// sums d_ij^2 over the whole row (twice the bytes of the tile mode, but one
+// workgroup per 4 rows instead of one per 1024 x 1024 tile, which leaves
+// most of the GPU idle at these sizes).  Writes r = c, rsum and hc directly;
+// p4part[b] = sum of d^4 over the rows of workgroup b and p4part[nwg + b] =
+// sum of their d_ii^2 (fixed-order merge of the four waves).
+constexpr int64_t kStatsRowModeMax = 16384;
+constexpr int kStatsRowModeRows = 4;  // rows per workgroup, one per wave
+template <typename DT>
+__global__ __launch_bounds__(256) void k_stats_rows(const DT* __restrict__ D, int64_t n, int base_vec, int64_t ldg,
+                                                    double* __restrict__ r, double* __restrict__ c,
+                                                    double* __restrict__ rsum, float* __restrict__ hc,
+                                                    double* __restrict__ p4part) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * kStatsRowModeRows + wave;
+  double sr = 0.0, s4 = 0.0, sd = 0.0;
+  if (i < n) {
+    const DT* row = D + i * n;
+    const bool vec = row_vec_ok<DT>(base_vec != 0, i, n);
+    int64_t c0 = lane * 4;
+    for (; c0 + 768 < n; c0 += 1024) {  // four 16-byte loads in flight per lane
+      double v[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) load4<DT>(row, c0 + 256 * u, n, vec, v[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const double sq = v[u][t] * v[u][t];
+          sr += sq;
+          s4 += sq * sq;
+          sd += (c0 + 256 * u + t == i) ? sq : 0.0;
+        }
+    }
+    for (; c0 < n; c0 += 256) {
+      double v[4];
+      load4<DT>(row, c0, n, vec, v);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double sq = v[t] * v[t];
+        sr += sq;
+        s4 += sq * sq;
+        sd += (c0 + t == i) ? sq : 0.0;
+      }
+    }
+  }
+  sr = wave_sum(sr);
+  s4 = wave_sum(s4);
+  sd = wave_sum(sd);
+  if (lane == 0 && i < n) {
+    rsum[i] = sr;
+    r[i] = sr / (double)n;
+    c[i] = sr / (double)n;
+    hc[i] = (float)(0.5 * (sr / (double)n));
+  }
+  __shared__ double w4[kStatsRowModeRows], wd[kStatsRowModeRows];
+  if (lane == 0) {
+    w4[wave] = s4;
+    wd[wave] = sd;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    p4part[blockIdx.x] = ((w4[0] + w4[1]) + w4[2]) + w4[3];
+    p4part[gridDim.x + blockIdx.x] = ((wd[0] + wd[1]) + wd[2]) + wd[3];
+  }
+  if (blockIdx.x == 0)
+    for (int64_t j = n + threadIdx.x; j < ldg; j += 256) hc[j] = 0.0f;
 }
 
 // Grand mean m, and the by-products ||G||_F^2 and tr(G) from their closed
@@ -452,7 +524,9 @@ hipError_t launch_center_write_fp8(const void* D, int d_is_f64, int64_t n, int64
 
 int64_t stats_parts(int64_t n) {
   const int64_t nrb = (n + kStatsRows - 1) / kStatsRows;
-  return ((n + kStatsCols - 1) / kStatsCols) * nrb + nrb;
+  const int64_t tiles = ((n + kStatsCols - 1) / kStatsCols) * nrb + nrb;
+  const int64_t rows = 2 * ((n + kStatsRowModeRows - 1) / kStatsRowModeRows);  // row mode
+  return n <= kStatsRowModeMax && rows > tiles ? rows : tiles;
 }
 
 hipError_t launch_center_stats(const void* D, int d_is_f64, int64_t n, int64_t ldg, double* rowpart,
@@ -461,6 +535,17 @@ hipError_t launch_center_stats(const void* D, int d_is_f64, int64_t n, int64_t l
   const int64_t ncb = (n + kStatsCols - 1) / kStatsCols;
   const int64_t nrb = (n + kStatsRows - 1) / kStatsRows;
   const int vec = ((uintptr_t)D % 16) == 0;
+  if (sym && n <= kStatsRowModeMax) {
+    const int64_t nwg = (n + kStatsRowModeRows - 1) / kStatsRowModeRows;
+    if (d_is_f64)
+      hipLaunchKernelGGL(k_stats_rows<double>, dim3((unsigned)nwg), dim3(256), 0, s, (const double*)D, n, vec, ldg, r,
+                         c, rsum, hc, p4part);
+    else
+      hipLaunchKernelGGL(k_stats_rows<float>, dim3((unsigned)nwg), dim3(256), 0, s, (const float*)D, n, vec, ldg, r, c,
+                         rsum, hc, p4part);
+    hipLaunchKernelGGL(k_grand, dim3(1), dim3(1024), 0, s, rsum, r, c, p4part, nwg, nwg, n, mean_all, st);
+    return hipGetLastError();
+  }
   dim3 grid = sym ? dim3((unsigned)(ncb * (ncb + 1) / 2)) : dim3((unsigned)ncb, (unsigned)nrb);
   if (d_is_f64)
     hipLaunchKernelGGL(k_stats<double>, grid, dim3(256), 0, s, (const double*)D, n, vec, rowpart, colpart, p4part,
