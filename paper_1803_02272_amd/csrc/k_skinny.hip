@@ -23,19 +23,21 @@ __device__ __forceinline__ uint16_t bf16_rne(double v) {
   return (uint16_t)(u >> 16);
 }
 
-constexpr int kGramChunk = 512;   // columns of the transposed layout per gram workgroup
+constexpr int kGramChunk = 512;   // most columns of the transposed layout per gram workgroup
 constexpr int kGramStep = 32;     // columns staged in LDS per step
 constexpr int kGramRow = kGramStep + 1;  // LDS row stride (doubles)
 constexpr int kGramThreads = 512;
 
-// Wpart[p] = A_p B_p^T over column chunk p: every workgroup stages 32-column
-// slices of all l_pad rows of A (and B) in LDS (double-buffered, 16-byte
-// loads), and each of its 8 waves accumulates a share of the 16 x 16 output
+// Wpart[p] = A_p B_p^T over column chunk p (chunk columns, a multiple of 64):
+// every workgroup stages 32-column slices of all l_pad rows of A (and B) in
+// LDS (double-buffered, 16-byte loads), and each of its 8 waves accumulates
+// a share of the 16 x 16 output
 // tiles with fp64 MFMA (16x16x4).  sym (A == B): only tiles on or above the
 // diagonal are computed; k_sum_parts mirrors them.
 template <int CG, bool SYM>
 __global__ __launch_bounds__(kGramThreads) void k_gram(const double* __restrict__ A, const double* __restrict__ B,
-                                                       int64_t ldg, int l_pad, double* __restrict__ Wpart) {
+                                                       int64_t ldg, int l_pad, double* __restrict__ Wpart,
+                                                       int64_t chunk) {
   constexpr int NT = SYM ? CG * (CG + 1) / 2 : CG * CG;  // output tiles
   constexpr int NW = kGramThreads / 64;
   constexpr int TPW = (NT + NW - 1) / NW;  // tiles per wave (at most)
@@ -43,8 +45,8 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const double* __restrict_
   constexpr int NB = SYM ? 1 : 2;  // staged matrices
   __shared__ double st[2][NB][LP * kGramRow];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t i0 = (int64_t)blockIdx.x * kGramChunk;
-  const int64_t i1 = (i0 + kGramChunk < ldg) ? i0 + kGramChunk : ldg;  // ldg is a multiple of 256
+  const int64_t i0 = (int64_t)blockIdx.x * chunk;
+  const int64_t i1 = (i0 + chunk < ldg) ? i0 + chunk : ldg;  // ldg and chunk are multiples of 64
   // this wave's tiles (ta, tb), ta <= tb when SYM
   int ta[TPW], tb[TPW];
 #pragma unroll
@@ -131,16 +133,16 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const double* __restrict_
 }
 
 // Register-streamed variant for l_pad > 128 (the LDS tiles of k_gram would
-// not fit): each wave owns a 16-row tile strip over a 512-column chunk.
+// not fit): each wave owns a 16-row tile strip over one column chunk.
 template <int CG>
 __global__ __launch_bounds__(256) void k_gram_wide(const double* __restrict__ A, const double* __restrict__ B,
-                                              int64_t ldg, int l_pad, double* __restrict__ Wpart) {
+                                              int64_t ldg, int l_pad, double* __restrict__ Wpart, int64_t chunk) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tr = blockIdx.y * 4 + wave;  // 16-row tile of W
   if (tr * 16 >= l_pad) return;          // no barriers below
   const int64_t p = blockIdx.x;
-  const int64_t i0 = p * kGramChunk;
-  const int64_t i1 = (i0 + kGramChunk < ldg) ? i0 + kGramChunk : ldg;
+  const int64_t i0 = p * chunk;
+  const int64_t i1 = (i0 + chunk < ldg) ? i0 + chunk : ldg;
   doublex4_t acc[CG];
 #pragma unroll
   for (int cg = 0; cg < CG; ++cg) acc[cg] = doublex4_t{0.0, 0.0, 0.0, 0.0};
@@ -401,21 +403,36 @@ __global__ __launch_bounds__(256) void k_coords_write(const double* __restrict__
   }
 }
 
+// Columns per gram workgroup: 512 once that gives at least 128 workgroups
+// (more, smaller chunks only add partial sums to reduce at n = 1e5), else
+// the power of two (at least 64) that gives about 256 workgroups, so that
+// small and mid-size problems still spread over the GPU.
+int64_t gram_chunk_cols(int64_t ldg) {
+  if (ldg >= 128 * (int64_t)kGramChunk) return kGramChunk;
+  int64_t c = 64;
+  while (c * 2 <= ldg / 256 && c * 2 <= kGramChunk) c *= 2;
+  return c;
+}
+
 template <int CG>
 void gram_one(const double* A, const double* B, int l_pad, int64_t ldg, double* Wpart, hipStream_t s) {
-  dim3 grid((unsigned)((ldg + kGramChunk - 1) / kGramChunk));
+  const int64_t chunk = gram_chunk_cols(ldg);
+  dim3 grid((unsigned)((ldg + chunk - 1) / chunk));
   if constexpr (CG > 8)
     hipLaunchKernelGGL(k_gram_wide<CG>, dim3(grid.x, (unsigned)((CG + 3) / 4)), dim3(256), 0, s, A, B, ldg, l_pad,
-                       Wpart);
+                       Wpart, chunk);
   else if (A == B)
-    hipLaunchKernelGGL((k_gram<CG, true>), grid, dim3(kGramThreads), 0, s, A, B, ldg, l_pad, Wpart);
+    hipLaunchKernelGGL((k_gram<CG, true>), grid, dim3(kGramThreads), 0, s, A, B, ldg, l_pad, Wpart, chunk);
   else
-    hipLaunchKernelGGL((k_gram<CG, false>), grid, dim3(kGramThreads), 0, s, A, B, ldg, l_pad, Wpart);
+    hipLaunchKernelGGL((k_gram<CG, false>), grid, dim3(kGramThreads), 0, s, A, B, ldg, l_pad, Wpart, chunk);
 }
 
 }  // namespace
 
-int64_t gram_chunks(int64_t ldg) { return (ldg + kGramChunk - 1) / kGramChunk; }
+int64_t gram_chunks(int64_t ldg) {
+  const int64_t chunk = gram_chunk_cols(ldg);
+  return (ldg + chunk - 1) / chunk;
+}
 
 hipError_t launch_gram(const double* A, const double* B, int l_pad, int64_t ldg, double* Wpart, double* W,
                        hipStream_t s) {
