@@ -44,6 +44,9 @@ using namespace small;
 // the register-resident factor holds cw^2 / NT rows per thread (cw = l rounded
 // up to 64) in kRegSlots registers: every l_pad <= kLdsMaxL must fit
 static_assert(kLdsMaxL * kLdsMaxL <= kRegSlots * kOrthRegThreads, "register slots of chol_reg / trinv_reg");
+static_assert(kSmallLMax * kSmallLMax <= kRegSlots * kOrthRegThreadsSmall, "register slots at l_pad <= kSmallLMax");
+static_assert(kSmallLMax % 64 == 0 && (kOrthRegThreadsSmall / kSmallLMax) * kSmallLMax == kOrthRegThreadsSmall,
+              "the lanes of one column share a wave (small l)");
 static_assert(kOrthRegThreads / kLdsMaxL <= 64 && (kOrthRegThreads / kLdsMaxL) * kLdsMaxL == kOrthRegThreads,
               "the lanes of one column share a wave");
 
@@ -89,11 +92,10 @@ __device__ __attribute__((noinline)) void orth_fallback(const double* __restrict
   }
 }
 
-template <bool IN_LDS>
-__global__ __launch_bounds__(IN_LDS ? kOrthRegThreads : kOrthThreads) void k_orth_factor(
-    const double* __restrict__ W, int l, int l_pad, double* __restrict__ T, double* __restrict__ scratch,
-    DevStatus* st, int near_identity) {
-  constexpr int NT = IN_LDS ? kOrthRegThreads : kOrthThreads;
+template <bool IN_LDS, int NT>
+__global__ __launch_bounds__(NT) void k_orth_factor(const double* __restrict__ W, int l, int l_pad,
+                                                     double* __restrict__ T, double* __restrict__ scratch,
+                                                     DevStatus* st, int near_identity) {
   __shared__ JacobiShared sh;
   __shared__ double Ml[IN_LDS ? kLdsMaxL * (kLdsMaxL + 1) : 1];  // ld l_pad + 1 (R, then the Jacobi)
   __shared__ double wdiag[kMaxL];
@@ -160,8 +162,8 @@ __global__ __launch_bounds__(IN_LDS ? kOrthRegThreads : kOrthThreads) void k_ort
 // ---- Rayleigh-Ritz eigensolve ---------------------------------------------
 // Diagonalises the symmetrised B, sorts, records the rotations; meta[0] =
 // rounds, meta[1..l] = permutation (sorted position -> original index).
-template <bool IN_LDS>
-__global__ __launch_bounds__(kEigThreads) void k_small_eig(const double* __restrict__ B, int l, int l_pad, int k,
+template <bool IN_LDS, int NT>
+__global__ __launch_bounds__(NT) void k_small_eig(const double* __restrict__ B, int l, int l_pad, int k,
                                                         double* __restrict__ theta, double* __restrict__ eigvals,
                                                         double2* __restrict__ rot, int* __restrict__ meta,
                                                         double* __restrict__ scratch, DevStatus* st) {
@@ -175,19 +177,19 @@ __global__ __launch_bounds__(kEigThreads) void k_small_eig(const double* __restr
   const int ldm = IN_LDS ? l_pad + 1 : l_pad;  // odd in LDS: the Jacobi's (min, max) accesses spread over banks
   const int le = l + (l & 1);
 
-  for (int e = tid; e < l_pad * l_pad; e += kEigThreads) {
+  for (int e = tid; e < l_pad * l_pad; e += NT) {
     const int i = e / l_pad, j = e % l_pad;
     M[i * ldm + j] = (i < l && j < l) ? 0.5 * (B[i * l_pad + j] + B[j * l_pad + i]) : 0.0;
   }
   __syncthreads();
   int rounds = 0;
-  const int sweeps = jacobi<kEigThreads>(M, ldm, (double*)nullptr, 0, rot, le, sh, &rounds);
+  const int sweeps = jacobi<NT>(M, ldm, (double*)nullptr, 0, rot, le, sh, &rounds);
   __syncthreads();
-  for (int i = tid; i < l; i += kEigThreads) th[i] = M[i * ldm + i];
+  for (int i = tid; i < l; i += NT) th[i] = M[i * ldm + i];
   __syncthreads();
-  for (int i = tid; i < l; i += kEigThreads) perm[desc_rank(th, l, i)] = i;  // a permutation, NaN included
+  for (int i = tid; i < l; i += NT) perm[desc_rank(th, l, i)] = i;  // a permutation, NaN included
   __syncthreads();
-  for (int r = tid; r < l; r += kEigThreads) {
+  for (int r = tid; r < l; r += NT) {
     const int src = perm[r];
     theta[r] = th[src];
     if (r < k) eigvals[r] = th[src];
@@ -253,12 +255,17 @@ size_t small_eig_rot_bytes(int l) {
 hipError_t launch_orth_factor(const double* W, int l, int l_pad, double* T, double* scratch, DevStatus* st,
                               int near_identity, hipStream_t s) {
   if (l > kMaxL || l_pad > kMaxL || l < 1) return hipErrorInvalidValue;
-  if (l_pad <= kLdsMaxL)
-    hipLaunchKernelGGL(k_orth_factor<true>, dim3(1), dim3(kOrthRegThreads), 0, s, W, l, l_pad, T, scratch, st,
-                       near_identity);
+  // l_pad <= 64: a quarter of the threads (the register factor still holds
+  // 16 rows per thread), so each column step synchronises 4 waves, not 16
+  if (l_pad <= kSmallLMax)
+    hipLaunchKernelGGL((k_orth_factor<true, kOrthRegThreadsSmall>), dim3(1), dim3(kOrthRegThreadsSmall), 0, s, W, l,
+                       l_pad, T, scratch, st, near_identity);
+  else if (l_pad <= kLdsMaxL)
+    hipLaunchKernelGGL((k_orth_factor<true, kOrthRegThreads>), dim3(1), dim3(kOrthRegThreads), 0, s, W, l, l_pad, T,
+                       scratch, st, near_identity);
   else
-    hipLaunchKernelGGL(k_orth_factor<false>, dim3(1), dim3(kOrthThreads), 0, s, W, l, l_pad, T, scratch, st,
-                       near_identity);
+    hipLaunchKernelGGL((k_orth_factor<false, kOrthThreads>), dim3(1), dim3(kOrthThreads), 0, s, W, l, l_pad, T,
+                       scratch, st, near_identity);
   return hipGetLastError();
 }
 
@@ -266,12 +273,15 @@ hipError_t launch_small_eig(const double* B, int l, int l_pad, int k, double* th
                             double* eigvals_out, double* scratch, void* rot, int* meta, DevStatus* st,
                             hipStream_t s) {
   if (l > kMaxL || l_pad > kMaxL || k < 1 || k > l) return hipErrorInvalidValue;
-  if (l_pad <= kLdsMaxL)
-    hipLaunchKernelGGL(k_small_eig<true>, dim3(1), dim3(kEigThreads), 0, s, B, l, l_pad, k, theta, eigvals_out,
-                       (double2*)rot, meta, scratch, st);
+  if (l_pad <= kSmallLMax)  // fewer waves to synchronise per Jacobi round
+    hipLaunchKernelGGL((k_small_eig<true, kEigThreadsSmall>), dim3(1), dim3(kEigThreadsSmall), 0, s, B, l, l_pad, k,
+                       theta, eigvals_out, (double2*)rot, meta, scratch, st);
+  else if (l_pad <= kLdsMaxL)
+    hipLaunchKernelGGL((k_small_eig<true, kEigThreads>), dim3(1), dim3(kEigThreads), 0, s, B, l, l_pad, k, theta,
+                       eigvals_out, (double2*)rot, meta, scratch, st);
   else
-    hipLaunchKernelGGL(k_small_eig<false>, dim3(1), dim3(kEigThreads), 0, s, B, l, l_pad, k, theta, eigvals_out,
-                       (double2*)rot, meta, scratch, st);
+    hipLaunchKernelGGL((k_small_eig<false, kEigThreads>), dim3(1), dim3(kEigThreads), 0, s, B, l, l_pad, k, theta,
+                       eigvals_out, (double2*)rot, meta, scratch, st);
   hipLaunchKernelGGL(k_rot_apply, dim3((unsigned)l), dim3(64), 0, s, (const double2*)rot, meta, theta, l, l_pad, k,
                      V, Tc);
   return hipGetLastError();
