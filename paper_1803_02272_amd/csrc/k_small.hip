@@ -273,10 +273,7 @@ hipError_t launch_small_eig(const double* B, int l, int l_pad, int k, double* th
                             double* eigvals_out, double* scratch, void* rot, int* meta, DevStatus* st,
                             hipStream_t s) {
   if (l > kMaxL || l_pad > kMaxL || k < 1 || k > l) return hipErrorInvalidValue;
-  if (l_pad <= kSmallLMax)  // fewer waves to synchronise per Jacobi round
-    hipLaunchKernelGGL((k_small_eig<true, kEigThreadsSmall>), dim3(1), dim3(kEigThreadsSmall), 0, s, B, l, l_pad, k,
-                       theta, eigvals_out, (double2*)rot, meta, scratch, st);
-  else if (l_pad <= kLdsMaxL)
+  if (l_pad <= kLdsMaxL)
     hipLaunchKernelGGL((k_small_eig<true, kEigThreads>), dim3(1), dim3(kEigThreads), 0, s, B, l, l_pad, k, theta,
                        eigvals_out, (double2*)rot, meta, scratch, st);
   else

@@ -13,9 +13,8 @@ namespace small {
 constexpr int kEigThreads = 1024;  // small_eig workgroup
 constexpr int kOrthThreads = 256;  // orth_factor workgroup, l_pad > 128 (global scratch)
 constexpr int kOrthRegThreads = 1024;  // orth_factor workgroup, l_pad <= 128 (register-resident factor)
-constexpr int kSmallLMax = 64;              // l_pad up to which the small kernels run a quarter of the threads
+constexpr int kSmallLMax = 64;              // l_pad up to which orth_factor runs a quarter of the threads
 constexpr int kOrthRegThreadsSmall = 256;   // orth_factor workgroup, l_pad <= kSmallLMax
-constexpr int kEigThreadsSmall = 256;       // small_eig workgroup, l_pad <= kSmallLMax
 constexpr int kRegSlots = 16;  // rows per thread of the register-resident factor
 constexpr int kNB = 16;            // panel width of the blocked Cholesky / inverse
 constexpr int kMaxPairs = kMaxL / 2;
