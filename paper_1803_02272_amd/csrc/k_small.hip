@@ -10,9 +10,10 @@
 //                T = V S^{-1/2}, dropping directions with s <= 1e-13 s_max, so
 //                those columns of Q become exactly zero.  For l_pad <= 128 the
 //                Cholesky and the inverse keep the matrix in registers of a
-//                1024-thread workgroup (right-looking, one barrier per column;
-//                then barrier-free back substitution per column of R^{-1});
-//                larger l use the blocked LDS/global versions.
+//                1024-thread workgroup, 256 threads for l_pad <= 64
+//                (right-looking, one barrier per column; then barrier-free
+//                back substitution per column of R^{-1}); larger l use the
+//                blocked versions on a global-memory copy.
 //   small_eig    Rayleigh-Ritz on B = Q^T G Q (symmetrised): eigenpairs in
 //                algebraic descending order (Sec. 6.2, step 2 on the projected
 //                matrix), eigenvalues keep their sign (G need not be PSD,
