@@ -246,57 +246,57 @@ __global__ __launch_bounds__(256) void k_cast(const double* __restrict__ In, int
 // Out[j][i] = sum_a T[a][j] In[a][i] on fp64 MFMA (16x16x4): A operand = T^T
 // (rows j, K = a) from an LDS block of 64 columns of T, B operand = In (K = a,
 // columns i, 16 consecutive i per lane group: 128-byte loads).  A workgroup
-// of 8 waves covers 256 columns i (32 per wave, two 16-column tiles) and 64
-// rows j; the l rows of In are padded to a multiple of 4 (In is zero beyond
-// l).  Two tiles per wave at 8 waves keep more loads of In in flight than
-// four tiles at 4 waves (fewer accumulators per wave, twice the waves).
+// of NTH / 64 waves covers NN 16-column tiles per wave and 64 rows j; the l
+// rows of In are padded to a multiple of 4 (In is zero beyond l).  Large n:
+// 8 waves of two tiles (256 columns) keep more loads of In in flight than 4
+// waves of four; when that gives fewer than 128 workgroups, 4 waves of one
+// tile (64 columns) spread the work over more CUs.
 constexpr int kApJ = 64;
 constexpr int kApRow = kApJ + 2;  // LDS row stride (doubles)
-constexpr int kApN = 2;           // 16-column tiles per wave
-constexpr int kApThreads = 512;
 
-__global__ __launch_bounds__(kApThreads) void k_apply(const double* __restrict__ In, int l, int64_t ldg,
+template <int NN, int NTH>
+__global__ __launch_bounds__(NTH) void k_apply(const double* __restrict__ In, int l, int64_t ldg,
                                                const double* __restrict__ T, int ldt, int lt, int l_out,
                                                double* __restrict__ Out) {
   extern __shared__ double Ts[];  // la x kApRow
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int la = (l + 3) & ~3;
   const int j0 = blockIdx.y * kApJ;
-  const int64_t i0 = (int64_t)blockIdx.x * ((kApThreads / 64) * 16 * kApN) + wave * (16 * kApN);
-  for (int e = tid; e < la * kApJ; e += kApThreads) {
+  const int64_t i0 = (int64_t)blockIdx.x * ((NTH / 64) * 16 * NN) + wave * (16 * NN);
+  for (int e = tid; e < la * kApJ; e += NTH) {
     const int a = e / kApJ, jj = e % kApJ, j = j0 + jj;
     Ts[a * kApRow + jj] = (a < l && j < lt) ? T[(int64_t)a * ldt + j] : 0.0;
   }
   __syncthreads();
-  doublex4_t acc[kApN][4];
+  doublex4_t acc[NN][4];
 #pragma unroll
-  for (int nt = 0; nt < kApN; ++nt)
+  for (int nt = 0; nt < NN; ++nt)
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[nt][t] = doublex4_t{0.0, 0.0, 0.0, 0.0};
   const double* Ib = In + (int64_t)(lane >> 4) * ldg + i0 + (lane & 15);
   const int ar = lane >> 4, jc = lane & 15;
   // software pipeline: the In rows of step a0 + 4 load while step a0 runs
-  double b[kApN];
+  double b[NN];
 #pragma unroll
-  for (int nt = 0; nt < kApN; ++nt) b[nt] = Ib[nt * 16];
+  for (int nt = 0; nt < NN; ++nt) b[nt] = Ib[nt * 16];
   for (int a0 = 0; a0 < la; a0 += 4) {
-    double bn[kApN];
+    double bn[NN];
     const bool more = a0 + 4 < la;
 #pragma unroll
-    for (int nt = 0; nt < kApN; ++nt) bn[nt] = more ? Ib[(int64_t)(a0 + 4) * ldg + nt * 16] : 0.0;
+    for (int nt = 0; nt < NN; ++nt) bn[nt] = more ? Ib[(int64_t)(a0 + 4) * ldg + nt * 16] : 0.0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const double av = Ts[(a0 + ar) * kApRow + t * 16 + jc];
 #pragma unroll
-      for (int nt = 0; nt < kApN; ++nt)
+      for (int nt = 0; nt < NN; ++nt)
         acc[nt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[nt], acc[nt][t], 0, 0, 0);
     }
 #pragma unroll
-    for (int nt = 0; nt < kApN; ++nt) b[nt] = bn[nt];
+    for (int nt = 0; nt < NN; ++nt) b[nt] = bn[nt];
   }
   // fp64 accumulator layout: register r of lane group g is row g + 4r
 #pragma unroll
-  for (int nt = 0; nt < kApN; ++nt)
+  for (int nt = 0; nt < NN; ++nt)
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
 #pragma unroll
@@ -453,18 +453,24 @@ hipError_t launch_gram(const double* A, const double* B, int l_pad, int64_t ldg,
 
 hipError_t launch_apply(const double* In, int l, int64_t ldg, const double* T, int ldt, int lt, int l_pad,
                         double* Out, int xk, void* Xc, hipStream_t s) {
-  constexpr int64_t cols = (kApThreads / 64) * 16 * kApN;  // columns i per workgroup
-  if (l > kMaxL || l_pad > kMaxL || ldg % cols != 0) return hipErrorInvalidValue;
+  constexpr int64_t kWide = 8 * 16 * 2, kNarrow = 4 * 16 * 1;  // columns i per workgroup
+  if (l > kMaxL || l_pad > kMaxL || ldg % kWide != 0) return hipErrorInvalidValue;
   const int la = (l + 3) & ~3;
   const size_t shm = (size_t)la * kApRow * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {
     const int mx = (int)(kMaxL * kApRow * sizeof(double));
-    (void)hipFuncSetAttribute((const void*)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    (void)hipFuncSetAttribute((const void*)k_apply<2, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    (void)hipFuncSetAttribute((const void*)k_apply<1, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     attr_set = true;
   }
-  dim3 grid((unsigned)(ldg / cols), (unsigned)((l_pad + kApJ - 1) / kApJ));
-  hipLaunchKernelGGL(k_apply, grid, dim3(kApThreads), shm, s, In, l, ldg, T, ldt, lt, l_pad, Out);
+  const unsigned jb = (unsigned)((l_pad + kApJ - 1) / kApJ);
+  if (ldg / kWide >= 128)
+    hipLaunchKernelGGL((k_apply<2, 512>), dim3((unsigned)(ldg / kWide), jb), dim3(512), shm, s, In, l, ldg, T, ldt,
+                       lt, l_pad, Out);
+  else
+    hipLaunchKernelGGL((k_apply<1, 256>), dim3((unsigned)(ldg / kNarrow), jb), dim3(256), shm, s, In, l, ldg, T, ldt,
+                       lt, l_pad, Out);
   if (Xc) {
     // the cast copy in its own elementwise kernel (fewer registers in k_apply)
     const int64_t elems = (int64_t)l_pad * ldg;
