@@ -181,21 +181,34 @@ __global__ __launch_bounds__(256) void k_gram_wide(const double* __restrict__ A,
       W[(int64_t)(tr * 16 + (lane >> 4) + 4 * r) * l_pad + cg * 16 + (lane & 15)] = acc[cg][r];
 }
 
-// out[i][j] = sum_p parts[p][i][j] in partial order; sym: only entries of
-// tiles on or above the diagonal were computed, and each such sum is also
-// written to the mirrored entry.
+// out[i][j] = sum_p parts[p][i][j]; sym: only entries of tiles on or above the
+// diagonal were computed, and each such sum is also written to the mirrored
+// entry.  A workgroup takes 16 entries with 16 threads each: thread slice q
+// sums parts q, q + 16, ... in order, and the 16 slice sums are added in
+// slice order, so the result is the same on every run (many partials, as
+// with small gram chunks, no longer form one serial chain per entry).
+constexpr int kSumEntries = 16, kSumSlices = 16;
 __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ parts, int64_t nparts,
                                                    int64_t elems, double* __restrict__ out, int l_pad, int sym) {
 #pragma clang fp contract(off)
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= elems) return;
+  __shared__ double sh[kSumSlices][kSumEntries];
+  const int el = threadIdx.x % kSumEntries, q = threadIdx.x / kSumEntries;
+  const int64_t e = (int64_t)blockIdx.x * kSumEntries + el;
+  double s = 0.0;
+  if (e < elems) {
+#pragma unroll 4
+    for (int64_t p = q; p < nparts; p += kSumSlices) s += parts[p * elems + e];
+  }
+  sh[q][el] = s;
+  __syncthreads();
+  if (q != 0 || e >= elems) return;
   const int i = (int)(e / l_pad), j = (int)(e % l_pad);
   if (sym && (j >> 4) < (i >> 4)) return;  // written by its mirror
-  double s = 0.0;
-#pragma unroll 8
-  for (int64_t p = 0; p < nparts; ++p) s += parts[p * elems + e];
-  out[e] = s;
-  if (sym && (j >> 4) > (i >> 4)) out[(int64_t)j * l_pad + i] = s;
+  double t = 0.0;
+#pragma unroll
+  for (int k = 0; k < kSumSlices; ++k) t += sh[k][el];
+  out[e] = t;
+  if (sym && (j >> 4) > (i >> 4)) out[(int64_t)j * l_pad + i] = t;
 }
 
 // Xc = cast(Out) for the next G-pass operand, 4 consecutive entries per thread.
@@ -446,7 +459,7 @@ hipError_t launch_gram(const double* A, const double* B, int l_pad, int64_t ldg,
     default: return hipErrorInvalidValue;
   }
   const int64_t elems = (int64_t)l_pad * l_pad;
-  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, Wpart,
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((elems + kSumEntries - 1) / kSumEntries)), dim3(256), 0, s, Wpart,
                      gram_chunks(ldg), elems, W, l_pad, (A == B && l_pad <= 128) ? 1 : 0);
   return hipGetLastError();
 }
