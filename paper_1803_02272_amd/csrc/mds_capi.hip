@@ -109,14 +109,16 @@ void layout(mds_plan_s* P) {
 void configure(mds_plan_s* P) {
   const mds_opts& o = P->opts;
   const bool d8 = o.d_dtype == MDS_DTYPE_F64;
-  // default split-K of the range passes: about three workgroups per CU (the
-  // pass library's own default aims at eight, which at mid-size n only adds
-  // partials: a bf16 solve at n = 30,000 takes 4.35 ms instead of 4.49)
+  // default split-K of the range passes at mid-size n (fewer than 256 row
+  // blocks): about three workgroups per CU.  The pass library's own default
+  // aims at eight, which there only adds partials (a bf16 solve at n = 30,000
+  // takes 4.35 ms instead of 4.49); with more row blocks (n = 1e5) its larger
+  // split is the faster one (at l_pad = 224, three splits against one).
   int64_t range_split = o.gpass_split;
   if (range_split == 0) {
     const GPassCfg c0 = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, 0, !stores_g(P->form), false, d8);
     const int64_t rows = P->n_pad / c0.bm;
-    range_split = (768 + rows - 1) / rows;
+    if (rows < 256) range_split = (768 + rows - 1) / rows;
   }
   P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, (int)range_split, !stores_g(P->form), false, d8);
   const int ps = o.proj_split ? o.proj_split : o.gpass_split;
