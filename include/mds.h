@@ -47,31 +47,44 @@ typedef enum mds_status {
   MDS_ERR_NUMERICAL = -6,   /* eigensolver did not converge */
   MDS_ERR_HIP = -7,         /* a HIP runtime call or kernel launch failed */
   MDS_ERR_CANCELLED = -8,   /* job cancelled before it ran */
-  MDS_ERR_STATE = -9        /* call not valid in the plan's current state */
+  MDS_ERR_STATE = -9,       /* call not valid in the plan's current state */
+  MDS_ERR_NOT_METRIC = -10  /* MDS_FLAG_CHECK_INPUT: D is not symmetric with a zero diagonal */
 } mds_status;
 
 /* Arithmetic form of the G-passes (dtype of the G operand).
  *   FP64: G entries in fp64, fp64 MFMA.
  *   FP32: G entries rounded to fp32, fp32 MFMA.
- *   BF16: G stored in bf16 (rounded from fp64 through fp32), bf16 MFMA with
- *         fp32 accumulation for the 2q+1 range passes; the projection pass
- *         ("refinement") multiplies fp32 G entries with fp32 Q to fp32
+ *   BF16: G stored in bf16 (rounded from fp64 through fp32).  Of the 2q+1
+ *         range passes, the first and the last run in fp32 and the q*2-1
+ *         between them on the stored bf16 G against bf16 X (bf16 MFMA, fp32
+ *         accumulation); the projection pass ("refinement") is fp32 too.
+ *         An fp32 pass multiplies fp32 G entries with fp32 X to fp32
  *         accuracy: each fp32 operand is split exactly into three bf16 terms
  *         (a = a0 + a1 + a2, each rounded to nearest even) and the six
  *         products a_p b_q with p + q <= 2 run on bf16 MFMA with fp32
  *         accumulation (the dropped terms are below 2^-22 |a b|), see
- *         MDS_FLAG_FP32_MFMA_PROJECTION.
+ *         MDS_FLAG_FP32_MFMA_PROJECTION.  The first range pass also writes
+ *         the stored G (fused centring write, fp32 D).  Running the two end
+ *         passes in fp32 keeps the bf16 rounding of G out of the sketch of
+ *         Omega and out of the final basis: the Ritz values then stay within
+ *         1e-3 (relative, per eigenvalue) of the fp64 method also where the
+ *         k-th eigenvalue lies in a near-degenerate bulk, where a sketch made
+ *         entirely of bf16 passes moves them by about 1e-3
+ *         (MDS_FLAG_LOWP_ALL_RANGE restores that faster schedule).
  *   FP8:  G stored as OCP FP8 E4M3 codes with one fp32 scale per 256 x 256
  *         block: g = fl32(gamma), s = fl32(max|g| / 448) over the block (1
  *         for an all-zero block), code = E4M3(fl32(g / s)), nearest even,
- *         saturating.  The range passes multiply bf16(fl32(s * code)) with
- *         bf16 X on bf16 MFMA, fp32 accumulation; the projection is fp32 as
- *         in the bf16 form.
- * G is stored only in the bf16 and fp8 forms.  Every other pass recomputes each
+ *         saturating.  The range passes between the first and the last
+ *         multiply bf16(fl32(s * code)) with bf16 X on bf16 MFMA, fp32
+ *         accumulation; the first and last range passes and the projection
+ *         are fp32 as in the bf16 form.
+ * G is stored only in the bf16 and fp8 forms (and only when q >= 1: with q = 0
+ * the one range pass is an fp32 pass).  Every other pass recomputes each
  * entry from D: fp64 passes with the centring equation in fp64 (the values a
  * stored fp64 G would hold), fp32 passes as fma(-1/2, fl32(d^2),
  * fl32(c_j/2) + fl32((r_i - m)/2)) in fp32, within a few fp32 ulps of the
- * terms of the rounded exact value.
+ * terms of the rounded exact value (the fused first pass of the bf16 form
+ * uses fl32(gamma) of the fp64 gamma itself).
  * In every form the centring sums, CholeskyQR2, the Gram products of the
  * tall matrices and the small eigensolve run in fp64. */
 typedef enum mds_form { MDS_FORM_FP64 = 0, MDS_FORM_FP32 = 1, MDS_FORM_BF16 = 2, MDS_FORM_FP8 = 3 } mds_form;
@@ -108,6 +121,20 @@ typedef enum mds_dtype { MDS_DTYPE_F32 = 0, MDS_DTYPE_F64 = 1 } mds_dtype;
  *   of D as written in the double-centring formula; both agree up to
  *   rounding for a symmetric D. */
 #define MDS_FLAG_FULL_STATS 8
+/*   MDS_FLAG_CHECK_INPUT: before the centring, test the finite-metric
+ *   contract on the whole of D (one extra read of D): d_ij == d_ji exactly
+ *   for every pair and d_ii == 0.  Violations are counted on the device and
+ *   reported by mds_get_info (asym_pairs, diag_nonzero) with status
+ *   MDS_ERR_NOT_METRIC; the run itself still completes (its result is that
+ *   of the upper triangle of D, see MDS_FLAG_FULL_STATS and
+ *   MDS_FLAG_FULL_PROJECTION).  A NaN entry counts as asymmetric. */
+#define MDS_FLAG_CHECK_INPUT 16
+/*   MDS_FLAG_LOWP_ALL_RANGE: BF16 and FP8 forms, run all 2q+1 range passes
+ *   on the stored low-precision G (no fp32 first and last range pass): faster
+ *   by about two fp32 passes less, with Ritz values that may move by ~1e-3
+ *   relative when the k-th eigenvalue lies in a near-degenerate bulk (bf16;
+ *   ~1e-1 for fp8).  No effect in the other forms. */
+#define MDS_FLAG_LOWP_ALL_RANGE 32
 
 typedef struct mds_opts {
   int32_t form;        /* mds_form (default MDS_FORM_FP32) */
@@ -116,6 +143,8 @@ typedef struct mds_opts {
   int32_t flags;       /* MDS_FLAG_* bits, 0 = defaults; other bits are rejected */
   int32_t proj_split;  /* K-splits of the projection pass, 0 = as gpass_split */
   int32_t write_split; /* K-splits of the fused centring write + first range pass, 0 = as gpass_split */
+  int32_t f32_split;   /* K-splits of the fp32 end range passes of the BF16/FP8 forms that are not
+                          fused with the write, 0 = as gpass_split */
 } mds_opts;
 
 typedef struct mds_plan_s* mds_plan_t;
@@ -211,6 +240,8 @@ typedef struct mds_info {
   double sum_sq;             /* sum_ij d_ij^2 */
   double frob2;              /* ||G||_F^2 (fp64, closed form in the centring sums) */
   double trace;              /* tr(G) */
+  int64_t asym_pairs;        /* MDS_FLAG_CHECK_INPUT: pairs i < j with d_ij != d_ji */
+  int64_t diag_nonzero;      /* MDS_FLAG_CHECK_INPUT: entries d_ii != 0 */
 } mds_info;
 
 /* Synchronise `stream`, then report the plan's last-run diagnostics. */
@@ -221,13 +252,17 @@ enum {
   MDS_PH_STATS = 0,    /* centring statistics (read D) */
   MDS_PH_WRITE = 1,    /* centring write (read D, write G); bf16 form on fp32 D: fused with range pass 1 */
   MDS_PH_OMEGA = 2,    /* test matrix */
-  MDS_PH_GPASS = 3,    /* one G-pass kernel of the range finder (per launch) */
+  MDS_PH_GPASS = 3,    /* one range-pass kernel over the form's G (per launch); the fp32 end
+                          passes of the BF16/FP8 forms are MDS_PH_WRITE or MDS_PH_GPASS_F32 */
   MDS_PH_REDUCE = 4,   /* split-K reduction of a G-pass */
   MDS_PH_ORTH = 5,     /* one CholeskyQR2 */
   MDS_PH_GPASS_REF = 6,/* the projection G-pass kernel */
   MDS_PH_SMALL = 7,    /* B = Q^T (G Q) and the small eigensolve */
   MDS_PH_COORDS = 8,   /* coordinates and signs */
-  MDS_NUM_PHASES = 9
+  MDS_PH_GPASS_F32 = 9,/* an fp32 range pass of the BF16/FP8 forms that is not fused with the write
+                          (the last one; the first as well on fp64 D or in the FP8 form) */
+  MDS_PH_CHECK = 10,   /* MDS_FLAG_CHECK_INPUT: the symmetry and diagonal test */
+  MDS_NUM_PHASES = 11
 };
 typedef struct mds_phase_time {
   int32_t count;   /* launches timed since the last read */
@@ -242,19 +277,29 @@ mds_status mds_set_timing(mds_plan_t plan, int32_t enable);
 mds_status mds_get_timings(mds_plan_t plan, mds_phase_time* out, void* stream);
 
 /* Autotuner of a plan: times every split-K candidate (the K extent of a
- * workgroup's tile) of the range pass, the projection pass and, in the bf16
- * form on fp32 D, the fused centring write, on this plan's shape and the
+ * workgroup's tile) of the range pass, the projection pass, the fp32 end
+ * range passes of the BF16/FP8 forms and, in the bf16 form on fp32 D, the
+ * fused centring write, on this plan's shape and the
  * given D; stores the fastest in the plan's options (copies made by the
  * server inherit them) and reports them.  Must be called before a workspace
  * is attached; allocates and frees a temporary one; synchronises `stream`. */
 typedef struct mds_tune_result {
-  int32_t range_split, proj_split, write_split, pad_;
-  float range_ms, proj_ms, write_ms; /* best per-launch times (pass + split-K reduction) */
-  int32_t candidates;                /* configurations timed */
+  int32_t range_split, proj_split, write_split, f32_split;
+  float range_ms, proj_ms, write_ms, f32_ms; /* best per-launch times (pass + split-K reduction) */
+  int32_t candidates;                        /* configurations timed */
 } mds_tune_result;
 mds_status mds_autotune(mds_plan_t plan, const void* D, void* stream, mds_tune_result* out);
 
 void mds_destroy(mds_plan_t plan);
+
+/* The generator behind Omega, exposed for validation against published
+ * known-answer vectors: Philox4x64-10 (Salmon, Moraes, Dror and Shaw,
+ * "Parallel Random Numbers: As Easy as 1, 2, 3", SC'11; the test matrix of
+ * the random projection, Sec. 3.2, draws entry (i, j) from the block at
+ * counter (i, j / 4, 0, 0) with key (seed, 0)).  in: device, count x 6
+ * uint64 (counter words 0..3, key words 0..1); out: device, count x 4 uint64
+ * (the block).  Enqueued on `stream`; caller-owned buffers. */
+mds_status mds_philox4x64_10(const uint64_t* in, uint64_t* out, int64_t count, void* stream);
 
 /* ---- Batched small instances ------------------------------------------------
  * Many independent MDS instances of uneven n in one persistent launch: one

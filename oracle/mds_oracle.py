@@ -38,14 +38,14 @@ G^(2q+1) Omega, Philox known-answer vectors and numpy's independent Philox.
 """
 from __future__ import annotations
 
-import math
-
 import numpy as np
 
 __all__ = [
     "philox4x64_10",
     "omega_words",
     "omega",
+    "ln_unit",
+    "sincos_2pi",
     "centring_stats",
     "gram_matrix",
     "gram_entries",
@@ -61,6 +61,7 @@ __all__ = [
     "E4M3_MAX",
     "FP8_BLOCK",
     "FORMS",
+    "pass_dtypes",
 ]
 
 # ---------------------------------------------------------------------------
@@ -128,19 +129,96 @@ def omega_words(seed: int, rows, blocks):
     return philox4x64_10(ctr, (seed, 0))
 
 
-_TWO_PI = 2.0 * math.pi
 _TWO_M53 = 2.0 ** -53
+
+# ---------------------------------------------------------------------------
+# ln, sin and cos for Box-Muller, written from the mathematics with + - * /
+# and sqrt only, in a fixed order (numpy float64 arrays: IEEE round to
+# nearest, no fused multiply-add), so that the library's device code, which
+# evaluates the same expressions in the same order, produces the same bits.
+# ---------------------------------------------------------------------------
+_LN2_HI = float.fromhex("0x1.62e42ff000000p-1")   # ln 2 rounded to a 32-bit fraction (e * _LN2_HI is exact)
+_LN2_LO = float.fromhex("-0x1.718432a1b0e26p-35")  # ln 2 - _LN2_HI, rounded
+_SQRT_HALF = float.fromhex("0x1.6a09e667f3bcdp-1")
+_PI_4 = float.fromhex("0x1.921fb54442d18p-1")     # pi / 4, rounded
+# 1 / (2j + 1) for j = 1..10: the odd terms of 2 atanh(s) = ln((1 + s) / (1 - s))
+_ATANH = [float.fromhex(h) for h in (
+    "0x1.5555555555555p-2", "0x1.999999999999ap-3", "0x1.2492492492492p-3", "0x1.c71c71c71c71cp-4",
+    "0x1.745d1745d1746p-4", "0x1.3b13b13b13b14p-4", "0x1.1111111111111p-4", "0x1.e1e1e1e1e1e1ep-5",
+    "0x1.af286bca1af28p-5", "0x1.8618618618618p-5")]
+# (-1)^j / (2j + 1)! for j = 1..8 (sine) and (-1)^j / (2j)! for j = 1..9 (cosine)
+_SIN = [float.fromhex(h) for h in (
+    "-0x1.5555555555555p-3", "0x1.1111111111111p-7", "-0x1.a01a01a01a01ap-13", "0x1.71de3a556c734p-19",
+    "-0x1.ae64567f544e4p-26", "0x1.6124613a86d09p-33", "-0x1.ae7f3e733b81fp-41", "0x1.952c77030ad4ap-49")]
+_COS = [float.fromhex(h) for h in (
+    "-0x1.0000000000000p-1", "0x1.5555555555555p-5", "-0x1.6c16c16c16c17p-10", "0x1.a01a01a01a01ap-16",
+    "-0x1.27e4fb7789f5cp-22", "0x1.1eed8eff8d898p-29", "-0x1.93974a8c07c9dp-37", "0x1.ae7f3e733b81fp-45",
+    "-0x1.6827863b97d97p-53")]
+
+
+def ln_unit(u: np.ndarray) -> np.ndarray:
+    """Natural logarithm of u in (0, 1].  u = m 2^e with m in [sqrt(1/2),
+    sqrt(2)) (exact split); ln m = 2 atanh(s) with s = (m - 1) / (m + 1),
+    |s| <= 0.172, summed as s + s z P(z), z = s^2, P the odd-term series to
+    z^9 / 21 (remainder below 2^-54 relative); ln u = e ln2_hi + (e ln2_lo +
+    ln m) with ln 2 split so that e ln2_hi is exact."""
+    u = np.asarray(u, dtype=np.float64)
+    f, e = np.frexp(u)  # u = f 2^e, f in [1/2, 1)
+    low = f < _SQRT_HALF
+    m = np.where(low, f + f, f)
+    e = np.where(low, e - 1, e).astype(np.float64)
+    s = (m - 1.0) / (m + 1.0)
+    z = s * s
+    p = np.full_like(s, _ATANH[-1])
+    for c in reversed(_ATANH[:-1]):
+        p = p * z + c
+    t = s * (z * p)
+    lnm = (s + t) * 2.0
+    return e * _LN2_HI + (e * _LN2_LO + lnm)
+
+
+def sincos_2pi(v: np.ndarray):
+    """(sin 2 pi v, cos 2 pi v) for v in [0, 1).  Octant reduction of the
+    dyadic v (exact): 8 v = o + f, x = a pi/4 with a = f (o even) or 1 - f
+    (o odd), x in [0, pi/4]; Taylor series of sin and cos in z = x^2 to x^17
+    and x^18 (remainders below 2^-55); the octant maps (sin x, cos x) to the
+    angle by symmetry (exact sign changes and swaps)."""
+    v = np.asarray(v, dtype=np.float64)
+    t = v * 8.0
+    o = np.floor(t)
+    f = t - o
+    odd = (o.astype(np.int64) & 1) == 1
+    a = np.where(odd, 1.0 - f, f)
+    x = a * _PI_4
+    z = x * x
+    ps = np.full_like(x, _SIN[-1])
+    for c in reversed(_SIN[:-1]):
+        ps = ps * z + c
+    sx = x + (x * z) * ps
+    pc = np.full_like(x, _COS[-1])
+    for c in reversed(_COS[:-1]):
+        pc = pc * z + c
+    cx = 1.0 + z * pc
+    oi = o.astype(np.int64)
+    # octant o: angle = o pi/4 + f pi/4; sin / cos of it from (sx, cx)
+    swap = (oi == 1) | (oi == 2) | (oi == 5) | (oi == 6)
+    s_out = np.where(swap, cx, sx)
+    c_out = np.where(swap, sx, cx)
+    s_neg = oi >= 4
+    c_neg = (oi >= 2) & (oi <= 5)
+    return np.where(s_neg, -s_out, s_out), np.where(c_neg, -c_out, c_out)
 
 
 def _box_muller(wa: np.ndarray, wb: np.ndarray):
     """Two standard normals from two 64-bit words (Box and Muller, 1958):
     u = (top 53 bits of wa + 1/2) 2^-53 in (0,1), v = (top 53 bits of wb)
-    2^-53 in [0,1); z = sqrt(-2 ln u) (cos 2 pi v, sin 2 pi v)."""
+    2^-53 in [0,1); z = sqrt(-2 ln u) (cos 2 pi v, sin 2 pi v), with the
+    ln, sin and cos above."""
     u = ((wa >> np.uint64(11)).astype(np.float64) + 0.5) * _TWO_M53
     v = (wb >> np.uint64(11)).astype(np.float64) * _TWO_M53
-    rho = np.sqrt(-2.0 * np.log(u))
-    ang = _TWO_PI * v
-    return rho * np.cos(ang), rho * np.sin(ang)
+    rho = np.sqrt(-2.0 * ln_unit(u))
+    sn, cs = sincos_2pi(v)
+    return rho * cs, rho * sn
 
 
 def omega(seed: int, n: int, l: int, rows=None) -> np.ndarray:
@@ -259,13 +337,29 @@ def fp8_operand(G: np.ndarray) -> np.ndarray:
     return round_to((q.astype(np.float32) * sc.astype(np.float32)).astype(np.float64), "bf16")
 
 
-# Dtype of (G, X) in the range passes and in the projection pass of each form.
+# Dtype of (G, X) in the range passes and in the projection pass of each
+# form.  The low-precision forms ("bf16", "fp8") run the first and the last
+# range pass in fp32 and only the passes between them on the stored
+# low-precision G (the sketch of Omega and the final basis then carry no
+# bf16/fp8 rounding of G); "bf16_all" and "fp8_all" run every range pass on
+# the stored G.  The projection is fp32 in all four low-precision variants
+# (the fp32 "refinement" pass).
+_F32 = ("f32", "f32")
 FORMS = {
-    "fp64": {"range": ("f64", "f64"), "proj": ("f64", "f64")},
-    "fp32": {"range": ("f32", "f32"), "proj": ("f32", "f32")},
-    "bf16": {"range": ("bf16", "bf16"), "proj": ("f32", "f32")},
-    "fp8": {"range": ("fp8blk", "bf16"), "proj": ("f32", "f32")},
+    "fp64": {"first": ("f64", "f64"), "range": ("f64", "f64"), "last": ("f64", "f64"), "proj": ("f64", "f64")},
+    "fp32": {"first": _F32, "range": _F32, "last": _F32, "proj": _F32},
+    "bf16": {"first": _F32, "range": ("bf16", "bf16"), "last": _F32, "proj": _F32},
+    "fp8": {"first": _F32, "range": ("fp8blk", "bf16"), "last": _F32, "proj": _F32},
+    "bf16_all": {"first": ("bf16", "bf16"), "range": ("bf16", "bf16"), "last": ("bf16", "bf16"), "proj": _F32},
+    "fp8_all": {"first": ("fp8blk", "bf16"), "range": ("fp8blk", "bf16"), "last": ("fp8blk", "bf16"),
+                "proj": _F32},
 }
+
+
+def pass_dtypes(form: str, it: int, q: int):
+    """(G dtype, X dtype) of range application `it` (0-based, of 2q + 1)."""
+    f = FORMS[form]
+    return f["first"] if it == 0 else (f["last"] if it == 2 * q else f["range"])
 
 
 def round_form(x, dtype: str) -> np.ndarray:
@@ -330,10 +424,10 @@ def rand_mds(D, k: int, p: int, q: int, seed: int, G=None, keep_history=False, f
     """Randomized classical MDS.
 
     ``form`` names the storage precision of the operands of each product with
-    G (see ``FORMS``): before every application Y = G X both G and X are
-    rounded to that form's dtype and the product is then taken exactly in
-    float64 arithmetic.  Everything else stays float64.  form="fp64" is the
-    plain method.
+    G (see ``FORMS`` and ``pass_dtypes``): before every application Y = G X
+    both G and X are rounded to that pass's dtypes and the product is then
+    taken exactly in float64 arithmetic.  Everything else stays float64.
+    form="fp64" is the plain method.
 
     Steps, in order:
       1. G from D (Sec. 6.2, step 1).
@@ -352,23 +446,24 @@ def rand_mds(D, k: int, p: int, q: int, seed: int, G=None, keep_history=False, f
         raise ValueError("need 1 <= k, p >= 0, k + p <= n, q >= 0")
     if G is None:
         G = gram_matrix(D)
-    gr, xr = FORMS[form]["range"]
+    rounded = {}
+
+    def g_as(dt):
+        if dt not in rounded:
+            rounded[dt] = round_form(G, dt)
+        return rounded[dt]
+
     gp, xp = FORMS[form]["proj"]
-    Gr = round_form(G, gr)
-    Gp = round_form(G, gp)
     Om = omega(seed, n, l)
     history = []
-    Y = Gr @ round_to(Om, xr)
-    Q = orthonormal_basis(Y)
-    if keep_history:
-        history.append(Q.copy())
-    for _ in range(q):
-        for _half in range(2):
-            Y = Gr @ round_to(Q, xr)
-            Q = orthonormal_basis(Y)
-            if keep_history:
-                history.append(Q.copy())
-    Y = Gp @ round_to(Q, xp)
+    Q = Om
+    for it in range(2 * q + 1):  # Omega, then q times two applications (G^T = G)
+        gr, xr = pass_dtypes(form, it, q)
+        Y = g_as(gr) @ round_to(Q, xr)
+        Q = orthonormal_basis(Y)
+        if keep_history:
+            history.append(Q.copy())
+    Y = g_as(gp) @ round_to(Q, xp)
     B = Q.T @ Y
     B = 0.5 * (B + B.T)
     theta, V = _sorted_eigh(B)

@@ -14,7 +14,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .mds_oracle import omega, normalise_column_signs, FORMS
+from .mds_oracle import omega, normalise_column_signs, FORMS, pass_dtypes
 
 
 def _torch():
@@ -89,21 +89,15 @@ def rand_mds_blocked(D, k: int, p: int, q: int, seed: int, form: str = "fp64", b
     say = progress or (lambda msg: None)
     stats = centring_stats_blocked(D)
     say("centring statistics done")
-    gr, xr = FORMS[form]["range"]
     gp, xp = FORMS[form]["proj"]
     from .mds_oracle import round_to, orthonormal_basis
 
-    Om = omega(seed, n, l)
-    Y = gram_apply_blocked(D, stats, round_to(Om, xr), gr, block)
-    Q = orthonormal_basis(Y)
-    say("range pass 1 done")
-    passes = 1
-    for _ in range(q):
-        for _half in range(2):
-            Y = gram_apply_blocked(D, stats, round_to(Q, xr), gr, block)
-            Q = orthonormal_basis(Y)
-            passes += 1
-            say(f"range pass {passes} done")
+    Q = omega(seed, n, l)
+    for it in range(2 * q + 1):  # Omega, then q times two applications (G^T = G)
+        gr, xr = pass_dtypes(form, it, q)
+        Y = gram_apply_blocked(D, stats, round_to(Q, xr), gr, block)
+        Q = orthonormal_basis(Y)
+        say(f"range pass {it + 1} done")
     Y = gram_apply_blocked(D, stats, round_to(Q, xp), gp, block)
     B = Q.T @ Y
     B = 0.5 * (B + B.T)

@@ -23,6 +23,7 @@ ERR_NUMERICAL = -6
 ERR_HIP = -7
 ERR_CANCELLED = -8
 ERR_STATE = -9
+ERR_NOT_METRIC = -10
 
 # forms and dtypes
 FORM_FP64, FORM_FP32, FORM_BF16, FORM_FP8 = 0, 1, 2, 3
@@ -43,12 +44,15 @@ FLAG_FULL_PROJECTION = 1
 FLAG_FP32_MFMA_PROJECTION = 2
 FLAG_SPLIT_FP32 = 4
 FLAG_FULL_STATS = 8
+FLAG_CHECK_INPUT = 16
+FLAG_LOWP_ALL_RANGE = 32
 
 
 class MdsOpts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("d_dtype", ctypes.c_int32),
                 ("gpass_split", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("proj_split", ctypes.c_int32), ("write_split", ctypes.c_int32)]
+                ("proj_split", ctypes.c_int32), ("write_split", ctypes.c_int32),
+                ("f32_split", ctypes.c_int32)]
 
 
 class MdsBuffer(ctypes.Structure):
@@ -63,13 +67,15 @@ class MdsInfo(ctypes.Structure):
                 ("k", ctypes.c_int32), ("l", ctypes.c_int32), ("l_pad", ctypes.c_int32),
                 ("q", ctypes.c_int32), ("form", ctypes.c_int32), ("gpass_split", ctypes.c_int32),
                 ("n", ctypes.c_int64), ("ldg", ctypes.c_int64),
-                ("sum_sq", ctypes.c_double), ("frob2", ctypes.c_double), ("trace", ctypes.c_double)]
+                ("sum_sq", ctypes.c_double), ("frob2", ctypes.c_double), ("trace", ctypes.c_double),
+                ("asym_pairs", ctypes.c_int64), ("diag_nonzero", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
-PHASES = ["stats", "write", "omega", "gpass", "reduce", "orth", "gpass_ref", "small", "coords"]
+PHASES = ["stats", "write", "omega", "gpass", "reduce", "orth", "gpass_ref", "small", "coords", "gpass_f32",
+          "check"]
 
 
 class MdsPhaseTime(ctypes.Structure):
@@ -85,8 +91,8 @@ class MdsBatchJob(ctypes.Structure):
 
 class MdsTuneResult(ctypes.Structure):
     _fields_ = [("range_split", ctypes.c_int32), ("proj_split", ctypes.c_int32), ("write_split", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("range_ms", ctypes.c_float), ("proj_ms", ctypes.c_float),
-                ("write_ms", ctypes.c_float), ("candidates", ctypes.c_int32)]
+                ("f32_split", ctypes.c_int32), ("range_ms", ctypes.c_float), ("proj_ms", ctypes.c_float),
+                ("write_ms", ctypes.c_float), ("f32_ms", ctypes.c_float), ("candidates", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad_"}
@@ -130,6 +136,7 @@ SIGNATURES = {
     "mds_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.POINTER(MdsTuneResult)]),
     "mds_destroy": (None, [ctypes.c_void_p]),
+    "mds_philox4x64_10": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "mds_batch_workspace_size": (ctypes.c_int, [ctypes.POINTER(MdsBatchJob), ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_size_t)]),
     "mds_run_batch": (ctypes.c_int, [ctypes.POINTER(MdsBatchJob), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,

@@ -5,19 +5,25 @@
 //   stream as the single-instance path) -> (2q+1) x [G-pass on MFMA ->
 //   CholeskyQR2 in fp64] -> projection pass -> B = Q^T G Q -> cyclic Jacobi
 //   -> coordinates with the sign convention of the single-instance path.
-// Workgroups never wait on each other, so any number of instances can be
-// launched; each instance is latency-bound on one CU, and a launch fills the
-// chip with instances instead of with tiles of one instance.  Meant for n up
-// to a few thousand and l_pad <= 64 (the serving mix: k = 20, l = 30).
+// The launch is persistent: its grid is sized to the device (as many
+// workgroups as fit at once) and every workgroup takes the next instance
+// from a job table in device memory through an atomic counter until the
+// table is exhausted, so one launch runs any number of instances and keeps
+// every CU busy while instances of uneven size finish at different times
+// (the host orders the table by decreasing work).  Workgroups never wait on
+// each other.  Meant for n up to a few thousand and l_pad <= 64 (the serving
+// mix: k = 20, l = 30).
 //
 // The values of every dtype follow the single-instance path: fp64 G
 // entries from the centring equation in fp64, fp32 entries as
 // fma(-1/2, fl32(d^2), fl32(c_j/2) + fl32((r_i - m)/2)), bf16 entries as the
 // bf16 rounding of the fp32 rounding of the fp64 entry; the bf16 form's
-// projection uses the fp32 entries.  Sums run in a different order, so
-// results agree with a single-instance run to rounding, not bit for bit.
+// first and last range passes and its projection use the fp32 entries.  Sums
+// run in a different order, so results agree with a single-instance run to
+// rounding, not bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <new>
@@ -37,7 +43,6 @@ using namespace small;
 constexpr int kBT = 256;         // threads per instance
 constexpr int kBMaxL = 64;       // largest l_pad
 constexpr int kBPad = 64;        // n is padded to a multiple of this
-constexpr int kPerLaunch = 32;   // instances per launch (kernel-argument table)
 constexpr int64_t kBMaxN = 16384;
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
@@ -49,15 +54,26 @@ struct BJob {
   double* eigvals;
   char* ws;
   DevStatus* st;
+  int32_t* status_out;  // optional device word: the instance's final mds_status
   int64_t n, n_pad;
   uint64_t seed;
   int k, l, l_pad, q, d_is_f64, pad_;
 };
 
-struct BTable {
-  int count, pad_;
-  BJob job[kPerLaunch];
+// Head of a batch workspace: per-instance status words, the job table (in
+// the order the workgroups take it) and the work counter.
+struct BHead {
+  int64_t status, table, counter, total;
 };
+__host__ __device__ inline int64_t rup(int64_t v, int64_t m);
+inline BHead bhead(int32_t count) {
+  BHead h;
+  h.status = 0;
+  h.table = rup((int64_t)count * (int64_t)sizeof(DevStatus), 256);
+  h.counter = h.table + rup((int64_t)count * (int64_t)sizeof(BJob), 256);
+  h.total = h.counter + 256;
+  return h;
+}
 
 __host__ __device__ inline int64_t rup(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -480,11 +496,43 @@ __device__ void block_sign(BShared& S, double* C, int64_t n, int k, int r) {
 }
 
 template <int FORM, int KU>
-__global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
-#pragma clang fp contract(off)
-  if ((int)blockIdx.x >= tab.count) return;
-  const BJob J = tab.job[blockIdx.x];
+__device__ void batch_instance(const BJob& J, BShared& S);
+
+__global__ void k_batch_reset(int* counter) { *counter = 0; }
+
+// The job table is written by kernels from their arguments (at most
+// kTableChunk jobs per launch), so enqueueing a batch copies no host memory.
+constexpr int kTableChunk = 32;
+struct BChunk {
+  int first, count;
+  BJob job[kTableChunk];
+};
+__global__ void k_batch_table(BChunk c, BJob* __restrict__ table) {
+  if ((int)threadIdx.x < c.count) table[c.first + threadIdx.x] = c.job[threadIdx.x];
+}
+
+// Persistent launch: each workgroup takes instances from the table until it
+// is exhausted (every workgroup reaches the exit; no workgroup waits on
+// another).
+template <int FORM, int KU>
+__global__ __launch_bounds__(kBT, 1) void k_batch(const BJob* __restrict__ table, int count, int* counter) {
   __shared__ BShared S;
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = next;
+    __syncthreads();  // every thread has read `next` before thread 0 overwrites it
+    if (t >= count) return;
+    const BJob job = table[t];
+    batch_instance<FORM, KU>(job, S);
+    __syncthreads();
+  }
+}
+
+template <int FORM, int KU>
+__device__ void batch_instance(const BJob& J, BShared& S) {
+#pragma clang fp contract(off)
   lds_double* M = (lds_double*)(void*)S.M;
   const int tid = threadIdx.x;
   const int64_t n = J.n, np = J.n_pad;
@@ -501,6 +549,11 @@ __global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
   double* Vg = (double*)(J.ws + Lo.V);
   constexpr int GK = FORM == MDS_FORM_FP64 ? GK_F64 : (FORM == MDS_FORM_FP32 ? GK_F32 : GK_BF16);
   constexpr int PK = FORM == MDS_FORM_FP64 ? GK_F64 : GK_F32;  // projection operand
+  // the bf16 form's first and last range passes recentre D in fp32 (like its
+  // projection); the passes between them read the stored bf16 G
+  const int passes = 2 * J.q + 1;
+  auto f32_pass = [&](int it) { return FORM == MDS_FORM_BF16 && (it == 0 || it == passes - 1); };
+  const bool store_g = !(FORM == MDS_FORM_BF16 && J.q == 0);
 
   if (tid == 0) {
     DevStatus z = {};
@@ -524,11 +577,13 @@ __global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
   }
   __syncthreads();
   // ---- G in the pass dtype ------------------------------------------------
-  if (J.d_is_f64)
-    write_g<FORM, double>((const double*)J.D, n, np, r, c, m, hc, hr, G);
-  else
-    write_g<FORM, float>((const float*)J.D, n, np, r, c, m, hc, hr, G);
-  // ---- Omega in the range operand dtype (transposed, l_pad x np) ------------
+  if (store_g) {
+    if (J.d_is_f64)
+      write_g<FORM, double>((const double*)J.D, n, np, r, c, m, hc, hr, G);
+    else
+      write_g<FORM, float>((const float*)J.D, n, np, r, c, m, hc, hr, G);
+  }
+  // ---- Omega in the first pass's operand dtype (transposed, l_pad x np) -----
   for (int64_t e = tid; e < np * (l_pad / 4); e += kBT) {
     const int64_t i = e % np, b = e / np;
     double z[4] = {0.0, 0.0, 0.0, 0.0};
@@ -539,7 +594,7 @@ __global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
       const double v = col < l ? z[t] : 0.0;
       if constexpr (GK == GK_F64)
         ((double*)X)[col * np + i] = v;
-      else if constexpr (GK == GK_F32)
+      else if constexpr (GK == GK_F32 || FORM == MDS_FORM_BF16)  // bf16: fp32 first pass
         ((float*)X)[col * np + i] = (float)v;
       else
         ((bf16_t*)X)[col * np + i] = to_bf16((float)v);
@@ -547,10 +602,13 @@ __global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
   }
   __syncthreads();
   // ---- range finder ---------------------------------------------------------
-  const int passes = 2 * J.q + 1;
   for (int it = 0; it < passes; ++it) {
-    block_gpass<GK, false, KU>(J, G, X, Yt, hc, hr);
-    block_orth(S, J, Yt, Qt, Vg, X, it == passes - 1 ? PK : GK);
+    if (f32_pass(it))
+      block_gpass<GK_F32, true, KU>(J, nullptr, X, Yt, hc, hr);
+    else
+      block_gpass<GK, false, KU>(J, G, X, Yt, hc, hr);
+    const int next = it == passes - 1 ? PK : (f32_pass(it + 1) ? (int)GK_F32 : GK);
+    block_orth(S, J, Yt, Qt, Vg, X, next);
   }
   // ---- projection B = Q^T G Q ------------------------------------------------
   if constexpr (FORM == MDS_FORM_BF16)
@@ -612,6 +670,11 @@ __global__ __launch_bounds__(kBT, 1) void k_batch(BTable tab) {
   }
   __syncthreads();
   for (int rr = 0; rr < k; ++rr) block_sign(S, J.coords, n, k, rr);
+  __syncthreads();
+  if (tid == 0 && J.status_out) {
+    const DevStatus& d = *J.st;
+    *J.status_out = d.nonfinite ? MDS_ERR_NONFINITE : (d.jacobi_unconv ? MDS_ERR_NUMERICAL : MDS_OK);
+  }
 }
 
 }  // namespace
@@ -624,22 +687,51 @@ int64_t mds::batch_max_n() { return kBMaxN; }
 
 namespace {
 
+// Workgroups of the persistent launch: as many as the device holds at once
+// (one per CU at this kernel's LDS and register use), never more than the
+// instances.
+template <int FORM, int KU>
+int persistent_grid(int count) {
+  static int per_device[64] = {0};  // workgroups that fit, per device
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  int g = per_device[dev];
+  if (g == 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<FORM, KU>, kBT, 0) != hipSuccess ||
+        per_cu <= 0)
+      per_cu = 1;
+    g = cus * per_cu;
+    per_device[dev] = g;
+  }
+  return count < g ? count : g;
+}
+
+template <int FORM, int KU>
+void launch_fk(const BJob* table, int count, int* counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, counter);
+  hipLaunchKernelGGL((k_batch<FORM, KU>), dim3(persistent_grid<FORM, KU>(count)), dim3(kBT), 0, s, table, count,
+                     counter);
+}
+
 template <int FORM>
-void launch_form(int ku, const BTable& tab, hipStream_t s) {
+void launch_form(int ku, const BJob* table, int count, int* counter, hipStream_t s) {
   switch (ku) {
-    case 1: hipLaunchKernelGGL((k_batch<FORM, 1>), dim3(tab.count), dim3(kBT), 0, s, tab); break;
-    case 2: hipLaunchKernelGGL((k_batch<FORM, 2>), dim3(tab.count), dim3(kBT), 0, s, tab); break;
-    default: hipLaunchKernelGGL((k_batch<FORM, 4>), dim3(tab.count), dim3(kBT), 0, s, tab); break;
+    case 1: launch_fk<FORM, 1>(table, count, counter, s); break;
+    case 2: launch_fk<FORM, 2>(table, count, counter, s); break;
+    default: launch_fk<FORM, 4>(table, count, counter, s); break;
   }
 }
 
-void launch_batch(int form, int ku, const BTable& tab, hipStream_t s) {
+void launch_batch(int form, int ku, const BJob* table, int count, int* counter, hipStream_t s) {
   if (form == MDS_FORM_FP64)
-    launch_form<MDS_FORM_FP64>(ku, tab, s);
+    launch_form<MDS_FORM_FP64>(ku, table, count, counter, s);
   else if (form == MDS_FORM_FP32)
-    launch_form<MDS_FORM_FP32>(ku, tab, s);
+    launch_form<MDS_FORM_FP32>(ku, table, count, counter, s);
   else
-    launch_form<MDS_FORM_BF16>(ku, tab, s);
+    launch_form<MDS_FORM_BF16>(ku, table, count, counter, s);
 }
 
 // Process-wide autotuning table: (form, size class of n_pad, l_pad) -> KU.
@@ -695,6 +787,82 @@ size_t job_bytes(const mds_batch_job& b, int form) {
   return (size_t)blayout(rup(b.n, kBPad), l_pad, form).total;
 }
 
+// Enqueue a checked batch into `workspace` (a BHead followed by the
+// per-instance regions): job table (ordered by decreasing work), counter
+// reset and the persistent launch.  status_out: optional device array of
+// count words for the final status of each instance.
+mds_status enqueue_batch(const mds_batch_job* jobs, int32_t count, int32_t form, char* base, int32_t tile,
+                         int32_t* status_out, hipStream_t s) {
+  const BHead H = bhead(count);
+  DevStatus* stat = reinterpret_cast<DevStatus*>(base + H.status);
+  std::vector<BJob> table((size_t)count);
+  std::vector<double> work((size_t)count);
+  size_t off = (size_t)H.total;
+  int64_t np_max = 0;
+  int lp_max = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const mds_batch_job& b = jobs[i];
+    BJob& J = table[i];
+    J.D = b.D;
+    J.coords = b.coords;
+    J.eigvals = b.eigvals;
+    J.ws = base + off;
+    J.st = stat + i;
+    J.status_out = status_out ? status_out + i : nullptr;
+    J.n = b.n;
+    J.n_pad = rup(b.n, kBPad);
+    J.seed = b.seed;
+    J.k = b.k;
+    J.l = b.k + b.oversample;
+    J.l_pad = (int)rup(J.l, 16);
+    J.q = b.q;
+    J.d_is_f64 = b.d_dtype == MDS_DTYPE_F64;
+    J.pad_ = 0;
+    off += job_bytes(b, form);
+    work[i] = (double)J.n_pad * (double)J.n_pad * (2 * J.q + 3) * J.l_pad;
+    np_max = J.n_pad > np_max ? J.n_pad : np_max;
+    lp_max = J.l_pad > lp_max ? J.l_pad : lp_max;
+  }
+  // largest instances first: the persistent grid then ends with short ones
+  std::vector<int32_t> order((size_t)count);
+  for (int32_t i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+  std::vector<BJob> sorted((size_t)count);
+  for (int32_t i = 0; i < count; ++i) sorted[i] = table[order[i]];
+  BJob* dtable = reinterpret_cast<BJob*>(base + H.table);
+  for (int32_t i0 = 0; i0 < count; i0 += kTableChunk) {
+    BChunk c{};
+    c.first = i0;
+    c.count = count - i0 < kTableChunk ? count - i0 : kTableChunk;
+    for (int t = 0; t < c.count; ++t) c.job[t] = sorted[i0 + t];
+    hipLaunchKernelGGL(k_batch_table, dim3(1), dim3(kTableChunk), 0, s, c, dtable);
+  }
+  mds_status st = hip_check(hipGetLastError(), "batch job table");
+  if (st != MDS_OK) return st;
+  const int ku = tile > 0 ? tile : tuned_ku(form, np_max, lp_max);
+  launch_batch(form, ku, dtable, count, reinterpret_cast<int*>(base + H.counter), s);
+  return hip_check(hipGetLastError(), "k_batch launch");
+}
+
+mds_status batch_args(const mds_batch_job* jobs, int32_t count, int32_t form, int32_t tile) {
+  mds_status st = batch_check(jobs, count, form);
+  if (st != MDS_OK) return st;
+  if (tile != 0 && tile != 1 && tile != 2 && tile != 4) return fail(MDS_ERR_INVALID_ARG, "tile = %d", tile);
+  for (int32_t i = 0; i < count; ++i)
+    if (!jobs[i].D || !jobs[i].coords || !jobs[i].eigvals)
+      return fail(MDS_ERR_INVALID_ARG, "job %d: NULL D, coords or eigvals", i);
+  return MDS_OK;
+}
+
+mds_status have_device() {
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(MDS_ERR_NO_DEVICE, "no HIP device available");
+  }
+  return MDS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -703,7 +871,7 @@ mds_status mds_batch_workspace_size(const mds_batch_job* jobs, int32_t count, in
   if (!bytes) return fail(MDS_ERR_INVALID_ARG, "bytes is NULL");
   const mds_status st = batch_check(jobs, count, form);
   if (st != MDS_OK) return st;
-  size_t total = (size_t)rup((int64_t)count * sizeof(DevStatus), 256);
+  size_t total = (size_t)bhead(count).total;
   for (int32_t i = 0; i < count; ++i) total += job_bytes(jobs[i], form);
   *bytes = total;
   return MDS_OK;
@@ -711,58 +879,16 @@ mds_status mds_batch_workspace_size(const mds_batch_job* jobs, int32_t count, in
 
 mds_status mds_run_batch(const mds_batch_job* jobs, int32_t count, int32_t form, void* workspace, size_t bytes,
                          int32_t tile, void* stream) {
-  mds_status st = batch_check(jobs, count, form);
+  mds_status st = batch_args(jobs, count, form, tile);
   if (st != MDS_OK) return st;
-  if (tile != 0 && tile != 1 && tile != 2 && tile != 4) return fail(MDS_ERR_INVALID_ARG, "tile = %d", tile);
   size_t need = 0;
   mds_batch_workspace_size(jobs, count, form, &need);
   if (!workspace || bytes < need || ((uintptr_t)workspace % 256) != 0)
     return fail(MDS_ERR_INVALID_ARG, "workspace NULL, unaligned or smaller than %zu bytes", need);
-  for (int32_t i = 0; i < count; ++i)
-    if (!jobs[i].D || !jobs[i].coords || !jobs[i].eigvals)
-      return fail(MDS_ERR_INVALID_ARG, "job %d: NULL D, coords or eigvals", i);
   if (count == 0) return MDS_OK;
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
-    (void)hipGetLastError();
-    return fail(MDS_ERR_NO_DEVICE, "no HIP device available");
-  }
-  char* base = static_cast<char*>(workspace);
-  DevStatus* stat = reinterpret_cast<DevStatus*>(base);
-  size_t off = (size_t)rup((int64_t)count * sizeof(DevStatus), 256);
-  for (int32_t i0 = 0; i0 < count; i0 += kPerLaunch) {
-    BTable tab{};
-    tab.count = count - i0 < kPerLaunch ? count - i0 : kPerLaunch;
-    for (int t = 0; t < tab.count; ++t) {
-      const mds_batch_job& b = jobs[i0 + t];
-      BJob& J = tab.job[t];
-      J.D = b.D;
-      J.coords = b.coords;
-      J.eigvals = b.eigvals;
-      J.ws = base + off;
-      J.st = stat + i0 + t;
-      J.n = b.n;
-      J.n_pad = rup(b.n, kBPad);
-      J.seed = b.seed;
-      J.k = b.k;
-      J.l = b.k + b.oversample;
-      J.l_pad = (int)rup(J.l, 16);
-      J.q = b.q;
-      J.d_is_f64 = b.d_dtype == MDS_DTYPE_F64;
-      off += job_bytes(b, form);
-    }
-    int64_t np_max = 0;
-    int lp_max = 0;
-    for (int t = 0; t < tab.count; ++t) {
-      np_max = tab.job[t].n_pad > np_max ? tab.job[t].n_pad : np_max;
-      lp_max = tab.job[t].l_pad > lp_max ? tab.job[t].l_pad : lp_max;
-    }
-    const int ku = tile > 0 ? tile : tuned_ku(form, np_max, lp_max);
-    launch_batch(form, ku, tab, (hipStream_t)stream);
-    st = hip_check(hipGetLastError(), "k_batch launch");
-    if (st != MDS_OK) return st;
-  }
-  return MDS_OK;
+  st = have_device();
+  if (st != MDS_OK) return st;
+  return enqueue_batch(jobs, count, form, static_cast<char*>(workspace), tile, nullptr, (hipStream_t)stream);
 }
 
 mds_status mds_autotune_batch(int32_t form, int64_t n, int32_t k, int32_t oversample, int32_t q, int32_t batch,

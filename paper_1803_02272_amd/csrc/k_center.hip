@@ -504,6 +504,45 @@ __global__ __launch_bounds__(kF8Threads) void k_center_write_fp8(const DT* __res
   }
 }
 
+// ---- finite-metric check (MDS_FLAG_CHECK_INPUT) ------------------------------
+// One workgroup per pair of 64 x 64 tiles (I, J), I <= J: tile (J, I) is
+// staged transposed in LDS and compared entry by entry with tile (I, J);
+// a diagonal tile compares its strict upper triangle with the lower one and
+// tests its diagonal.  Integer counts, so the result is exact.
+constexpr int kChk = 64;
+template <typename DT>
+__global__ __launch_bounds__(256) void k_check_input(const DT* __restrict__ D, int64_t n, DevStatus* st) {
+  const int64_t I = blockIdx.y, J = blockIdx.x;
+  if (I > J) return;
+  __shared__ DT t[kChk][kChk + 1];
+  __shared__ unsigned int cnt[2];
+  const int tid = threadIdx.x;
+  if (tid < 2) cnt[tid] = 0;
+  const int c = tid & 63, r0 = tid >> 6;  // lane c reads column c of 4 rows per sweep
+  // stage tile (J, I): t[col][row] = D[J*64 + row][I*64 + col]
+  for (int r = r0; r < kChk; r += 4) {
+    const int64_t i = J * kChk + r, j = I * kChk + c;
+    t[c][r] = (i < n && j < n) ? D[i * n + j] : (DT)0;
+  }
+  __syncthreads();
+  unsigned int asym = 0, diag = 0;
+  for (int r = r0; r < kChk; r += 4) {
+    const int64_t i = I * kChk + r, j = J * kChk + c;
+    if (i >= n || j >= n) continue;
+    const DT a = D[i * n + j];
+    if (I == J && r == c) {
+      diag += a != (DT)0;
+    } else if (I < J || r < c) {
+      asym += !(a == t[r][c]);  // t[r][c] = D[j][i]; NaN counts as asymmetric
+    }
+  }
+  if (asym) atomicAdd(&cnt[0], asym);
+  if (diag) atomicAdd(&cnt[1], diag);
+  __syncthreads();
+  if (tid == 0 && cnt[0]) atomicAdd(&st->asym_pairs, (unsigned long long)cnt[0]);
+  if (tid == 0 && cnt[1]) atomicAdd(&st->diag_nonzero, (unsigned long long)cnt[1]);
+}
+
 }  // namespace
 
 hipError_t launch_center_write_fp8(const void* D, int d_is_f64, int64_t n, int64_t n_pad, int64_t ldg,
@@ -519,6 +558,17 @@ hipError_t launch_center_write_fp8(const void* D, int d_is_f64, int64_t n, int64
   else
     hipLaunchKernelGGL(k_center_write_fp8<float>, grid, dim3(kF8Threads), 0, s, (const float*)D, n, ldg, vec, r, c,
                        mean_all, G8, scales, nsb);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_input(const void* D, int d_is_f64, int64_t n, DevStatus* st, hipStream_t s) {
+  const int64_t tiles = (n + kChk - 1) / kChk;
+  if (tiles > 65535) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)tiles, (unsigned)tiles);
+  if (d_is_f64)
+    hipLaunchKernelGGL(k_check_input<double>, grid, dim3(256), 0, s, (const double*)D, n, st);
+  else
+    hipLaunchKernelGGL(k_check_input<float>, grid, dim3(256), 0, s, (const float*)D, n, st);
   return hipGetLastError();
 }
 

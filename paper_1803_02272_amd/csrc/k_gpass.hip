@@ -533,10 +533,16 @@ __device__ __forceinline__ void split3(const float (&g)[8], u32x4 (&w)[3]) {
   }
 }
 
-template <int RG, int CG, typename DT, bool SYM>
+// WG: the fused centring write (fp32 D, full pass): each entry is recentred
+// in fp64 as in the centring equation, g = fl32(gamma) is stored into the
+// bf16 G as bf16(g) (the stored-G value of the bf16 form) and split for the
+// pass, so that the first range pass takes fl32(gamma) itself.
+template <int RG, int CG, typename DT, bool SYM, bool WG = false>
 __global__ __launch_bounds__(256, 2) void k_gpass_x3(const uint16_t* __restrict__ X3, int64_t ldg, int split,
                                                      int64_t steps_total, int64_t steps_per_split,
-                                                     float* __restrict__ Ypart, GPassDSrc src, int64_t sym_nbx) {
+                                                     float* __restrict__ Ypart, GPassDSrc src, int64_t sym_nbx,
+                                                     uint16_t* __restrict__ Gw) {
+  static_assert(!WG || (!SYM && sizeof(DT) == 4), "the fused write is a full pass over fp32 D");
   constexpr int LPAD = CG * 16;
   constexpr int BK = kX3Step;
   constexpr int PIECES = LPAD * 12;  // 16-byte pieces of a step's X tile (3 planes x 4 K-groups per row)
@@ -581,30 +587,39 @@ __global__ __launch_bounds__(256, 2) void k_gpass_x3(const uint16_t* __restrict_
   const int64_t n = src.n;
   const double mval = src.m[0];
   float ri[RG];  // hr_i (symmetric mode: 2 hr_i, exact)
+  double rd[RG];  // WG: r_i in fp64
   bool rowvec[RG];
 #pragma unroll
   for (int rg = 0; rg < RG; ++rg) {
     const int64_t i = row0 + rg * 16 + (lane & 15);
     const float h = (i < n) ? (float)(0.5 * (src.r[i] - mval)) : 0.0f;
     ri[rg] = SYM ? h + h : h;
+    rd[rg] = (WG && i < n) ? src.r[i] : 0.0;
     rowvec[rg] = src.vec && (((i * n) % DV) == 0);
   }
   const size_t xrowbytes = (size_t)ldg * 6;
   const unsigned char* Xb = reinterpret_cast<const unsigned char*>(X3);
+  // recentring terms per K-value: fl32(c_k / 2), or c_k in fp64 for the fused write
+  using CVT = typename std::conditional<WG, double, float>::type;
 
   if (st0 < st1) {
     DT a[RG][8], an[RG][8];
-    float cv[8], cvn[8];
+    CVT cv[8], cvn[8];
     u32x4 xr[PPT];
-    auto load_a = [&](DT (&dst)[RG][8], float (&cdst)[8], int64_t st) {
+    auto load_a = [&](DT (&dst)[RG][8], CVT (&cdst)[8], int64_t st) {
       const int64_t k0 = st * BK + (lane >> 4) * 8;
 #pragma unroll
       for (int rg = 0; rg < RG; ++rg) load_d<DT, 8>(Dp, n, row0 + rg * 16 + (lane & 15), k0, rowvec[rg], dst[rg]);
-      // hc holds ldg zero-padded entries (ldg is a multiple of 32)
-      const u32x4 w0 = *reinterpret_cast<const u32x4*>(src.hc + k0);
-      const u32x4 w1 = *reinterpret_cast<const u32x4*>(src.hc + k0 + 4);
-      __builtin_memcpy(&cdst[0], &w0, 16);
-      __builtin_memcpy(&cdst[4], &w1, 16);
+      if constexpr (WG) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) cdst[t] = (k0 + t < n) ? src.c[k0 + t] : 0.0;
+      } else {
+        // hc holds ldg zero-padded entries (ldg is a multiple of 32)
+        const u32x4 w0 = *reinterpret_cast<const u32x4*>(src.hc + k0);
+        const u32x4 w1 = *reinterpret_cast<const u32x4*>(src.hc + k0 + 4);
+        __builtin_memcpy(&cdst[0], &w0, 16);
+        __builtin_memcpy(&cdst[4], &w1, 16);
+      }
     };
     auto load_x = [&](int64_t st) {
 #pragma unroll
@@ -628,10 +643,28 @@ __global__ __launch_bounds__(256, 2) void k_gpass_x3(const uint16_t* __restrict_
     // diagonal), then split into three bf16 planes.  Entries outside n x n
     // need no mask: columns k >= n meet zero rows of X (the padding of Q),
     // and rows i >= n are zeroed in the output.
-    auto a_split = [&](int rg, const float (&ch)[8], auto band_tag, int64_t st, u32x4 (&w)[3]) {
+    auto a_split = [&](int rg, const CVT (&ch)[8], auto band_tag, int64_t st, u32x4 (&w)[3]) {
 #pragma clang fp contract(off)
       constexpr bool BAND = decltype(band_tag)::value;
       float g[8];
+      if constexpr (WG) {
+        // gamma = -1/2 (((d^2 - c_k) - r_i) + m) in fp64, g = fl32(gamma),
+        // zero outside n x n; bf16(g) is the stored G entry
+        const int64_t k0 = st * BK + (lane >> 4) * 8;
+        const int64_t i = row0 + rg * 16 + (lane & 15);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const double d = (double)a[rg][t];
+          const double e = ((d * d - ch[t]) - rd[rg]) + mval;
+          g[t] = (i < n && k0 + t < n) ? (float)(-0.5 * e) : 0.0f;
+        }
+        u32x4 gw;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) gw[h] = bf16x2_bits(f32x2{g[2 * h], g[2 * h + 1]});
+        *reinterpret_cast<u32x4*>(Gw + i * ldg + k0) = gw;
+        split3(g, w);
+        return;
+      }
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         float d2;
@@ -665,7 +698,7 @@ __global__ __launch_bounds__(256, 2) void k_gpass_x3(const uint16_t* __restrict_
         load_a(an, cvn, st + 1);
       }
       u32x4 w[RG][3];
-      float ch[8];
+      CVT ch[8];
 #pragma unroll
       for (int t = 0; t < 8; ++t) ch[t] = SYM ? cv[t] + cv[t] : cv[t];
       if (SYM && st < diag_end) {
@@ -1046,19 +1079,24 @@ hipError_t launch_cg(const void* G, int64_t ldg, const void* Xt, const GPassCfg&
   return hipGetLastError();
 }
 
-template <int CG, typename DT, bool SYM>
+template <int CG, typename DT, bool SYM, bool WG = false>
 void launch_x3_one(const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t n_pad, void* Yp, const GPassDSrc& src,
-                   hipStream_t s) {
+                   hipStream_t s, void* Gw = nullptr) {
   constexpr int RG = rg_x3(CG, sizeof(DT) == 8);
-  hipLaunchKernelGGL((k_gpass_x3<RG, CG, DT, SYM>), dim3((unsigned)gpass_blocks(cfg, n_pad)), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_gpass_x3<RG, CG, DT, SYM, WG>), dim3((unsigned)gpass_blocks(cfg, n_pad)), dim3(256), 0, s,
                      (const uint16_t*)Xt, ldg, cfg.split, cfg.steps_total, cfg.steps_per_split, (float*)Yp, src,
-                     cfg.sym_nbx);
+                     cfg.sym_nbx, (uint16_t*)Gw);
 }
 
 template <int CG>
 hipError_t launch_x3_cg(const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t n_pad, void* Yp,
-                        const GPassDSrc& src, hipStream_t s) {
+                        const GPassDSrc& src, hipStream_t s, void* Gw) {
   if (!src.D) return hipErrorInvalidValue;
+  if (Gw) {  // fused centring write: full pass over fp32 D
+    if (cfg.dma || cfg.sym || src.d_is_f64 || cfg.rg != rg_x3(CG, false)) return hipErrorInvalidValue;
+    launch_x3_one<CG, float, false, true>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
+    return hipGetLastError();
+  }
   if (cfg.dma) {
     if constexpr (CG * 16 <= kDmaMaxL) {
       if (!cfg.sym || cfg.bm != kDmaWaves * 32 || src.d_is_f64 || !src.vec || src.n % 4 != 0)
@@ -1086,10 +1124,10 @@ hipError_t launch_x3_cg(const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_
 }
 
 hipError_t launch_x3(const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t n_pad, void* Yp,
-                     const GPassDSrc& src, hipStream_t s) {
+                     const GPassDSrc& src, hipStream_t s, void* Gw) {
   switch (l_pad / 16) {
 #define MDS_CG(N) \
-  case N: return launch_x3_cg<N>(Xt, ldg, cfg, n_pad, Yp, src, s);
+  case N: return launch_x3_cg<N>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
     MDS_CG(1) MDS_CG(2) MDS_CG(3) MDS_CG(4) MDS_CG(5) MDS_CG(6) MDS_CG(7) MDS_CG(8)
     MDS_CG(9) MDS_CG(10) MDS_CG(11) MDS_CG(12) MDS_CG(13) MDS_CG(14) MDS_CG(15) MDS_CG(16)
 #undef MDS_CG
@@ -1159,7 +1197,7 @@ hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const
     case GK_FP8:
       if (!src.g8_scales || (cfg.bm > kF8Block) || (kF8Block % cfg.bm)) return hipErrorInvalidValue;
       return launch_gk<GK_FP8>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
-    case GK_F32S: return launch_x3(Xt, ldg, l_pad, cfg, n_pad, Ypart, src, s);
+    case GK_F32S: return launch_x3(Xt, ldg, l_pad, cfg, n_pad, Ypart, src, s, const_cast<void*>(G));
     default: return hipErrorInvalidValue;
   }
 }

@@ -55,7 +55,24 @@ __global__ __launch_bounds__(256) void k_omega_split(uint64_t seed, int64_t n, i
   }
 }
 
+// Raw generator blocks: in[6 i .. 6 i + 5] = counter words 0..3, key words
+// 0..1; out[4 i .. 4 i + 3] = the block.
+__global__ __launch_bounds__(256) void k_philox(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+                                                int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  uint64_t x[4] = {in[6 * i], in[6 * i + 1], in[6 * i + 2], in[6 * i + 3]};
+  philox4x64_10(x, in[6 * i + 4], in[6 * i + 5]);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) out[4 * i + t] = x[t];
+}
+
 }  // namespace
+
+hipError_t launch_philox(const uint64_t* in, uint64_t* out, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_philox, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, in, out, count);
+  return hipGetLastError();
+}
 
 hipError_t launch_omega(uint64_t seed, int64_t n, int l, int l_pad, int64_t ldg, int xk, void* Xt,
                         hipStream_t s) {

@@ -56,13 +56,19 @@ void add(mds_plan_s* P, Region& reg, size_t bytes) {
   P->total += (size_t)round_up((int64_t)bytes, 256);
 }
 
+// Kind of range pass `it` (0-based, of 2q + 1): the BF16/FP8 forms run the
+// first and the last in fp32 (three-term split) unless MDS_FLAG_LOWP_ALL_RANGE.
+int pass_kind(const mds_plan_s* P, int it) {
+  return (P->refine && (it == 0 || it == 2 * P->q)) ? GK_F32S : P->gk;
+}
+
 void layout(mds_plan_s* P) {
   const int64_t n = P->n, n_pad = P->n_pad, ldg = P->ldg, lp = P->l_pad;
   const size_t e = (size_t)gk_size(P->gk);
   P->total = 0;
-  // G is stored only in the bf16 form (range passes stream 2-byte G); the
-  // fp32/fp64 passes and the bf16 form's projection recentre D on the fly.
-  add(P, P->G, stores_g(P->form) ? (size_t)n_pad * ldg * e : 0);
+  // G is stored only in the bf16/fp8 forms (their middle range passes stream
+  // the 2- or 1-byte G); every other pass recentres D on the fly.
+  add(P, P->G, P->needs_g ? (size_t)n_pad * ldg * e : 0);
   const int64_t nsb = n_pad / kF8Block;
   add(P, P->gscale, P->form == MDS_FORM_FP8 ? (size_t)nsb * nsb * 4 : 0);
   const int64_t ncb = (n + kStatsCols - 1) / kStatsCols, nrb = (n + kStatsRows - 1) / kStatsRows;
@@ -74,16 +80,19 @@ void layout(mds_plan_s* P) {
   add(P, P->mean, 8);
   add(P, P->p4part, (size_t)stats_parts(n) * 8);
   add(P, P->hc, (size_t)ldg * 4);
-  const size_t xe = (size_t)(gk_size(x_kind(P->gk)) > gk_size(P->ref_gk) ? gk_size(x_kind(P->gk))
-                                                                         : gk_size(P->ref_gk));
+  size_t xe = (size_t)(gk_size(x_kind(P->gk)) > gk_size(P->ref_gk) ? gk_size(x_kind(P->gk))
+                                                                   : gk_size(P->ref_gk));
+  if (P->refine && (size_t)gk_size(GK_F32S) > xe) xe = (size_t)gk_size(GK_F32S);
   add(P, P->X, (size_t)lp * ldg * xe);
   const size_t acc_main = P->gk == GK_F64 ? 8 : 4, acc_ref = P->ref_gk == GK_F64 ? 8 : 4;
   const size_t yp_main = (size_t)P->cfg.split * lp * ldg * acc_main;
   const int ref_split = P->ref_cfg.split > P->ref_cfg_alt.split ? P->ref_cfg.split : P->ref_cfg_alt.split;
   const size_t yp_ref = (size_t)ref_split * lp * ldg * acc_ref;
   const size_t yp_w = P->fused ? (size_t)P->wcfg.split * lp * ldg * 4 : 0;
+  const size_t yp_f = P->refine ? (size_t)P->fcfg.split * lp * ldg * 4 : 0;
   size_t yp = yp_main > yp_ref ? yp_main : yp_ref;
   yp = yp > yp_w ? yp : yp_w;
+  yp = yp > yp_f ? yp : yp_f;
   add(P, P->Ypart, yp > P->ypart_min ? yp : P->ypart_min);
   add(P, P->Y, (size_t)lp * ldg * 8);
   add(P, P->Q1, (size_t)lp * ldg * 8);
@@ -125,11 +134,18 @@ void configure(mds_plan_s* P) {
   const bool psym = (o.flags & MDS_FLAG_FULL_PROJECTION) == 0;
   P->ref_cfg = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, ps, true, psym, d8, P->n % 4 == 0);
   P->ref_cfg_alt = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, ps, true, psym, d8, false);
-  // bf16 form on fp32 D: the centring write is fused with the first range pass
-  P->fused = o.form == MDS_FORM_BF16 && !d8;
+  // fp32 end range passes of the bf16/fp8 forms (full passes recentring D)
+  P->refine = stores_g(o.form) && (o.flags & MDS_FLAG_LOWP_ALL_RANGE) == 0;
+  P->needs_g = stores_g(o.form) && !(P->refine && P->q == 0);
+  if (P->refine)
+    P->fcfg = gpass_config(GK_F32S, P->l_pad, P->n_pad, P->ldg, o.f32_split ? o.f32_split : o.gpass_split, true,
+                           false, d8);
+  // bf16 form on fp32 D: the centring write is fused with the first range
+  // pass (an fp32 split pass when refining, else a bf16 pass)
+  P->fused = o.form == MDS_FORM_BF16 && !d8 && P->needs_g;
   if (P->fused)
-    P->wcfg = gpass_config(GK_BF16, P->l_pad, P->n_pad, P->ldg, o.write_split ? o.write_split : o.gpass_split,
-                           true, false, false);
+    P->wcfg = gpass_config(P->refine ? GK_F32S : GK_BF16, P->l_pad, P->n_pad, P->ldg,
+                           o.write_split ? o.write_split : o.gpass_split, true, false, false);
   layout(P);
 }
 
@@ -222,27 +238,35 @@ mds_status orthonormalize(mds_plan_s* P, hipStream_t s, int xk) {
   return MDS_OK;
 }
 
-// One G-pass Y = G X.  The bf16 form's range passes read the stored bf16 G;
-// every other pass recentres D on the fly.
+// One G-pass Y = G X of kind gk with configuration cfg, then its split-K
+// reduction.  from_d: the pass recentres D (else it reads the stored G);
+// Gw: the fused centring write's target (the bf16 G).
 GPassDSrc make_src(mds_plan_s* P, int gk, bool from_d, const void* D);
 
-mds_status gpass(mds_plan_s* P, hipStream_t s, bool ref, const void* D, bool fused = false) {
-  const int gk = ref ? P->ref_gk : P->gk;
-  const bool from_d = ref || fused || !stores_g(P->form);
+mds_status gpass(mds_plan_s* P, hipStream_t s, int gk, const GPassCfg& cfg0, bool from_d, const void* D, void* Gw,
+                 int phase) {
   const GPassDSrc src = make_src(P, gk, from_d, D);
-  const GPassCfg& cfg =
-      fused ? P->wcfg : (ref ? ((P->ref_cfg.dma && !src.vec) ? P->ref_cfg_alt : P->ref_cfg) : P->cfg);
+  // the projection's LDS-ring kernel needs a 16-byte aligned D
+  const GPassCfg& cfg = (&cfg0 == &P->ref_cfg && P->ref_cfg.dma && !src.vec) ? P->ref_cfg_alt : cfg0;
   {
-    PhaseTimer tm(P, s, fused ? MDS_PH_WRITE : (ref ? MDS_PH_GPASS_REF : MDS_PH_GPASS));
-    MDS_TRY(launch_gpass(gk, (from_d && !fused) ? nullptr : P->at<void>(P->G), P->ldg, P->n_pad,
+    PhaseTimer tm(P, s, phase);
+    MDS_TRY(launch_gpass(gk, Gw ? Gw : (from_d ? nullptr : P->at<void>(P->G)), P->ldg, P->n_pad,
                          P->at<void>(P->X), P->l_pad, cfg, P->at<void>(P->Ypart), src, s),
-            fused ? "centring write + range pass 1" : "gpass");
+            Gw ? "centring write + range pass 1" : "gpass");
   }
   PhaseTimer tm(P, s, MDS_PH_REDUCE);
   MDS_TRY(launch_splitk_reduce(gk, cfg, P->at<void>(P->Ypart), P->ldg, (int64_t)P->l_pad * P->ldg,
                                P->at<double>(P->Y), s),
           "splitk_reduce");
   return MDS_OK;
+}
+
+// Range pass `it` of the plan (kind, configuration, source and phase).
+mds_status range_pass(mds_plan_s* P, hipStream_t s, int it, bool fused, const void* D) {
+  const int gk = pass_kind(P, it);
+  if (it == 0 && fused) return gpass(P, s, gk, P->wcfg, true, D, P->at<void>(P->G), MDS_PH_WRITE);
+  if (gk == GK_F32S && P->refine) return gpass(P, s, gk, P->fcfg, true, D, nullptr, MDS_PH_GPASS_F32);
+  return gpass(P, s, gk, P->cfg, !stores_g(P->form), D, nullptr, MDS_PH_GPASS);
 }
 
 // Source of a G-pass: block scales of a stored fp8 G, or D and the centring
@@ -276,9 +300,14 @@ mds_status mds::run_plan(mds_plan_s* P, const void* D, double* coords, double* e
   if (st0 != MDS_OK) return st0;
   DevStatus* st = P->at<DevStatus>(P->status);
   P->last_stage = 0;
+  P->last_xk = -1;
   hipLaunchKernelGGL(k_status_init, dim3(1), dim3(1), 0, s, st);
   MDS_TRY(hipGetLastError(), "status init");
 
+  if (P->opts.flags & MDS_FLAG_CHECK_INPUT) {
+    PhaseTimer tm(P, s, MDS_PH_CHECK);
+    MDS_TRY(launch_check_input(D, P->d_dtype == MDS_DTYPE_F64, P->n, st, s), "input check");
+  }
   {
   PhaseTimer tm(P, s, MDS_PH_STATS);
   MDS_TRY(launch_center_stats(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->ldg, P->at<double>(P->rowpart),
@@ -289,13 +318,13 @@ mds_status mds::run_plan(mds_plan_s* P, const void* D, double* coords, double* e
   }
   // fused: the bf16 G is written by the first range pass (needs Omega first)
   const bool fused = P->fused && stop_after >= MDS_STAGE_RANGE;
-  if (P->form == MDS_FORM_FP8) {
+  if (P->form == MDS_FORM_FP8 && P->needs_g) {
     PhaseTimer tm(P, s, MDS_PH_WRITE);
     MDS_TRY(launch_center_write_fp8(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->n_pad, P->ldg, P->at<double>(P->r),
                                     P->at<double>(P->c), P->at<double>(P->mean), P->at<uint8_t>(P->G),
                                     P->at<float>(P->gscale), s),
             "centring write fp8");
-  } else if (P->form == MDS_FORM_BF16 && !fused) {
+  } else if (P->form == MDS_FORM_BF16 && P->needs_g && !fused) {
     PhaseTimer tm(P, s, MDS_PH_WRITE);
     MDS_TRY(launch_center_write(D, P->d_dtype == MDS_DTYPE_F64, P->n, P->n_pad, P->ldg, P->at<double>(P->r),
                                 P->at<double>(P->c), P->at<double>(P->mean), P->gk, P->at<void>(P->G), nullptr, s),
@@ -306,7 +335,9 @@ mds_status mds::run_plan(mds_plan_s* P, const void* D, double* coords, double* e
 
   {
     PhaseTimer tm(P, s, MDS_PH_OMEGA);
-    MDS_TRY(launch_omega(P->seed, P->n, P->l, P->l_pad, P->ldg, x_kind(P->gk), P->at<void>(P->X), s), "omega");
+    const int xk0 = x_kind(pass_kind(P, 0));
+    MDS_TRY(launch_omega(P->seed, P->n, P->l, P->l_pad, P->ldg, xk0, P->at<void>(P->X), s), "omega");
+    P->last_xk = xk0;
   }
   P->last_stage = MDS_STAGE_OMEGA;
   if (stop_after == MDS_STAGE_OMEGA) return MDS_OK;
@@ -314,18 +345,19 @@ mds_status mds::run_plan(mds_plan_s* P, const void* D, double* coords, double* e
   const int total_range = 2 * P->q + 1;
   const int passes = stop_after == MDS_STAGE_RANGE ? range_passes : total_range;
   for (int it = 0; it < passes; ++it) {
-    mds_status e = gpass(P, s, false, D, fused && it == 0);
+    mds_status e = range_pass(P, s, it, fused, D);
     if (e != MDS_OK) return e;
-    const int next_xk = (it == total_range - 1) ? P->ref_gk : x_kind(P->gk);
+    const int next_xk = (it == total_range - 1) ? P->ref_gk : x_kind(pass_kind(P, it + 1));
     e = orthonormalize(P, s, next_xk);
     if (e != MDS_OK) return e;
+    P->last_xk = next_xk;
   }
   P->last_stage = MDS_STAGE_RANGE;
   if (stop_after == MDS_STAGE_RANGE) return MDS_OK;
 
   // projection: Y = G_ref Q, B = Q^T Y (symmetric mode: Y = 2 (W o G_ref) Q,
   // whose symmetrised B is the same Q^T G_ref Q, see k_gpass)
-  mds_status e = gpass(P, s, true, D);
+  mds_status e = gpass(P, s, P->ref_gk, P->ref_cfg, true, D, nullptr, MDS_PH_GPASS_REF);
   if (e != MDS_OK) return e;
   {
     PhaseTimer tm(P, s, MDS_PH_SMALL);
@@ -365,6 +397,7 @@ const char* mds_status_string(mds_status s) {
     case MDS_ERR_HIP: return "HIP error";
     case MDS_ERR_CANCELLED: return "cancelled";
     case MDS_ERR_STATE: return "invalid state";
+    case MDS_ERR_NOT_METRIC: return "D is not symmetric with a zero diagonal";
   }
   return "unknown status";
 }
@@ -373,7 +406,7 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
                        const mds_opts* opts) {
   if (!out) return fail(MDS_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  mds_opts o = {MDS_FORM_FP32, MDS_DTYPE_F32, 0, 0, 0, 0};
+  mds_opts o = {MDS_FORM_FP32, MDS_DTYPE_F32, 0, 0, 0, 0, 0};
   if (opts) o = *opts;
   if (n < 2) return fail(MDS_ERR_INVALID_ARG, "n = %lld < 2", (long long)n);
   if (n > 1000000) return fail(MDS_ERR_INVALID_ARG, "n = %lld > 1000000", (long long)n);
@@ -387,10 +420,14 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
     return fail(MDS_ERR_INVALID_ARG, "unknown form %d", o.form);
   if (o.d_dtype != MDS_DTYPE_F32 && o.d_dtype != MDS_DTYPE_F64)
     return fail(MDS_ERR_INVALID_ARG, "unknown D dtype %d", o.d_dtype);
-  if (o.gpass_split < 0 || o.proj_split < 0 || o.write_split < 0)
-    return fail(MDS_ERR_INVALID_ARG, "negative split (%d, %d, %d)", o.gpass_split, o.proj_split, o.write_split);
-  if (o.flags & ~(MDS_FLAG_FULL_PROJECTION | MDS_FLAG_FP32_MFMA_PROJECTION | MDS_FLAG_SPLIT_FP32 | MDS_FLAG_FULL_STATS))
+  if (o.gpass_split < 0 || o.proj_split < 0 || o.write_split < 0 || o.f32_split < 0)
+    return fail(MDS_ERR_INVALID_ARG, "negative split (%d, %d, %d, %d)", o.gpass_split, o.proj_split, o.write_split,
+                o.f32_split);
+  if (o.flags & ~(MDS_FLAG_FULL_PROJECTION | MDS_FLAG_FP32_MFMA_PROJECTION | MDS_FLAG_SPLIT_FP32 |
+                  MDS_FLAG_FULL_STATS | MDS_FLAG_CHECK_INPUT | MDS_FLAG_LOWP_ALL_RANGE))
     return fail(MDS_ERR_INVALID_ARG, "unknown flags 0x%x", o.flags);
+  if ((o.flags & MDS_FLAG_CHECK_INPUT) && (n + 63) / 64 > 65535)
+    return fail(MDS_ERR_INVALID_ARG, "MDS_FLAG_CHECK_INPUT supports n <= %d", 65535 * 64);
   mds_plan_s* P = new (std::nothrow) mds_plan_s();
   if (!P) return fail(MDS_ERR_OOM, "host allocation failed");
   P->opts = o;
@@ -468,7 +505,7 @@ mds_status mds_get_buffer(mds_plan_t plan, int32_t which, mds_buffer* out) {
   const int xdt = plan->gk == GK_F64 ? 0 : (plan->gk == GK_F32 ? 1 : 2);
   switch (which) {
     case MDS_BUF_G:
-      if (!stores_g(plan->form)) return fail(MDS_ERR_STATE, "G is not stored in this form");
+      if (!plan->needs_g) return fail(MDS_ERR_STATE, "G is not stored in this form");
       b = {plan->at<void>(plan->G), plan->form == MDS_FORM_FP8 ? 3 : xdt, 0, plan->n_pad, plan->ldg, plan->ldg};
       break;
     case MDS_BUF_GSCALE:
@@ -481,13 +518,10 @@ mds_status mds_get_buffer(mds_plan_t plan, int32_t which, mds_buffer* out) {
     case MDS_BUF_COLMEAN: b = {plan->at<void>(plan->c), 0, 0, plan->n, 1, 1}; break;
     case MDS_BUF_MEAN: b = {plan->at<void>(plan->mean), 0, 0, 1, 1, 1}; break;
     case MDS_BUF_X: {
-      // dtype of the operand depends on which pass wrote it last
-      int dt = xdt;
-      int64_t cols = plan->gk == GK_F32S ? 3 * plan->ldg : plan->ldg;
-      if (plan->last_stage >= MDS_STAGE_ALL && plan->ref_gk != plan->gk) {
-        dt = plan->ref_gk == GK_F32 ? 1 : 2;
-        if (plan->ref_gk == GK_F32S) cols = 3 * plan->ldg;
-      }
+      // dtype of the operand that the last pass or cast wrote
+      const int xk = plan->last_xk >= 0 ? plan->last_xk : x_kind(plan->gk);
+      const int dt = xk == GK_F64 ? 0 : (xk == GK_F32 ? 1 : 2);
+      const int64_t cols = xk == GK_F32S ? 3 * plan->ldg : plan->ldg;
       b = {plan->at<void>(plan->X), dt, 0, lp, cols, cols};
       break;
     }
@@ -529,8 +563,12 @@ mds_status mds_get_info(mds_plan_t plan, mds_info* out, void* stream) {
     info.sum_sq = d.sum_sq;
     info.frob2 = d.frob2;
     info.trace = d.trace;
+    info.asym_pairs = (int64_t)d.asym_pairs;
+    info.diag_nonzero = (int64_t)d.diag_nonzero;
     if (d.nonfinite)
       info.status = MDS_ERR_NONFINITE;
+    else if ((plan->opts.flags & MDS_FLAG_CHECK_INPUT) && (d.asym_pairs || d.diag_nonzero))
+      info.status = MDS_ERR_NOT_METRIC;
     else if (d.jacobi_unconv)
       info.status = MDS_ERR_NUMERICAL;
   }
@@ -571,23 +609,35 @@ mds_status mds_autotune(mds_plan_t P, const void* D, void* stream, mds_tune_resu
   static const int kCands[] = {0, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48};
   const bool d8 = P->d_dtype == MDS_DTYPE_F64;
   const bool sym = (P->opts.flags & MDS_FLAG_FULL_PROJECTION) == 0;
+  // pass kinds: 0 range passes over the form's G, 1 projection, 2 fused
+  // centring write + first range pass, 3 fp32 end range passes (refine)
+  enum { kRange = 0, kProj = 1, kWrite = 2, kF32 = 3, kKinds = 4 };
+  const bool has_kind[kKinds] = {!P->refine || P->q >= 1, true, P->fused, P->refine};
+  auto gk_of = [&](int kind) {
+    if (kind == kRange) return P->gk;
+    if (kind == kProj) return P->ref_gk;
+    if (kind == kWrite) return P->refine ? (int)GK_F32S : (int)GK_BF16;
+    return (int)GK_F32S;
+  };
   auto cfg_of = [&](int kind, int split) {
-    if (kind == 0) return gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, split, !stores_g(P->form), false, d8);
-    if (kind == 1)
+    if (kind == kRange)
+      return gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, split, !stores_g(P->form), false, d8);
+    if (kind == kProj)
       return gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, split, true, sym, d8,
                           P->n % 4 == 0 && (uintptr_t)D % 16 == 0);
-    return gpass_config(GK_BF16, P->l_pad, P->n_pad, P->ldg, split, true, false, false);
+    if (kind == kWrite) return gpass_config(gk_of(kWrite), P->l_pad, P->n_pad, P->ldg, split, true, false, false);
+    return gpass_config(GK_F32S, P->l_pad, P->n_pad, P->ldg, split, true, false, d8);
   };
-  const int kinds = P->fused ? 3 : 2;
   // workspace sized for the largest candidate's partials
   size_t ymax = 0;
-  for (int kind = 0; kind < kinds; ++kind)
+  for (int kind = 0; kind < kKinds; ++kind) {
+    if (!has_kind[kind]) continue;
     for (int c : kCands) {
       const GPassCfg g = cfg_of(kind, c);
-      const int gk = kind == 0 ? P->gk : (kind == 1 ? P->ref_gk : GK_BF16);
-      const size_t b = (size_t)g.split * P->l_pad * P->ldg * (gk == GK_F64 ? 8 : 4);
+      const size_t b = (size_t)g.split * P->l_pad * P->ldg * (gk_of(kind) == GK_F64 ? 8 : 4);
       ymax = b > ymax ? b : ymax;
     }
+  }
   P->ypart_min = ymax;
   layout(P);
   st = ensure_workspace(P);
@@ -614,14 +664,18 @@ mds_status mds_autotune(mds_plan_t P, const void* D, void* stream, mds_tune_resu
   // centring, stored G and Omega in the workspace
   st = run_plan(P, D, nullptr, nullptr, s, MDS_STAGE_OMEGA, 0);
   if (st != MDS_OK) return finish(st);
-  int best[3] = {0, 0, 0};
-  float best_ms[3] = {0.f, 0.f, 0.f};
+  int best[kKinds] = {0, 0, 0, 0};
+  float best_ms[kKinds] = {0.f, 0.f, 0.f, 0.f};
   int timed = 0;
-  for (int kind = 0; kind < kinds; ++kind) {
-    const int gk = kind == 0 ? P->gk : (kind == 1 ? P->ref_gk : GK_BF16);
-    const bool from_d = kind != 0 || !stores_g(P->form);
+  for (int kind = 0; kind < kKinds; ++kind) {
+    if (!has_kind[kind]) continue;
+    const int gk = gk_of(kind);
+    const bool from_d = kind != kRange || !stores_g(P->form);
     const GPassDSrc src = make_src(P, gk, from_d, D);
-    void* G = (kind == 2 || !from_d) ? P->at<void>(P->G) : nullptr;
+    void* G = (kind == kWrite || !from_d) ? P->at<void>(P->G) : nullptr;
+    // the pass operand X holds the split-K test data of any kind: Omega in
+    // the dtype of the first pass (its contents do not change the timing of
+    // the other kinds, which read the same number of bytes from it)
     float kbest = 1e30f;
     int last_split = -1;
     for (int c : kCands) {
@@ -652,18 +706,29 @@ mds_status mds_autotune(mds_plan_t P, const void* D, void* stream, mds_tune_resu
     }
     best_ms[kind] = kbest;
   }
-  P->opts.gpass_split = best[0];
-  P->opts.proj_split = best[1];
-  P->opts.write_split = P->fused ? best[2] : 0;
-  out->range_split = best[0];
-  out->proj_split = best[1];
+  P->opts.gpass_split = best[kRange];
+  P->opts.proj_split = best[kProj];
+  P->opts.write_split = P->fused ? best[kWrite] : 0;
+  P->opts.f32_split = P->refine ? best[kF32] : 0;
+  out->range_split = best[kRange];
+  out->proj_split = best[kProj];
   out->write_split = P->opts.write_split;
-  out->pad_ = 0;
-  out->range_ms = best_ms[0];
-  out->proj_ms = best_ms[1];
-  out->write_ms = P->fused ? best_ms[2] : 0.f;
+  out->f32_split = P->opts.f32_split;
+  out->range_ms = best_ms[kRange];
+  out->proj_ms = best_ms[kProj];
+  out->write_ms = P->fused ? best_ms[kWrite] : 0.f;
+  out->f32_ms = P->refine ? best_ms[kF32] : 0.f;
   out->candidates = timed;
   return finish(MDS_OK);
+}
+
+mds_status mds_philox4x64_10(const uint64_t* in, uint64_t* out, int64_t count, void* stream) {
+  if (count < 0 || (count > 0 && (!in || !out))) return fail(MDS_ERR_INVALID_ARG, "NULL pointer or count < 0");
+  if (count == 0) return MDS_OK;
+  if (count > ((int64_t)1 << 36)) return fail(MDS_ERR_INVALID_ARG, "count = %lld too large", (long long)count);
+  const mds_status st = device_present();
+  if (st != MDS_OK) return st;
+  return hip_check(launch_philox(in, out, count, (hipStream_t)stream), "philox");
 }
 
 void mds_destroy(mds_plan_t plan) {

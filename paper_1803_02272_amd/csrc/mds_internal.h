@@ -45,6 +45,8 @@ struct DevStatus {
   double sum_sq;        // sum_ij d_ij^2
   double frob2;         // ||G||_F^2
   double trace;         // tr(G)
+  unsigned long long asym_pairs;    // check_input: pairs i < j with d_ij != d_ji
+  unsigned long long diag_nonzero;  // check_input: entries d_ii != 0
 };
 
 // ---- centring (Sec. 6.2, step 1) ------------------------------------------
@@ -70,7 +72,13 @@ hipError_t launch_center_write(const void* D, int d_is_f64, int64_t n, int64_t n
                                const double* r, const double* c, const double* mean_all, int gk, void* G,
                                float* gref, hipStream_t s);
 
+// Finite-metric contract of D (symmetric, zero diagonal), whole matrix:
+// adds the counts of asymmetric pairs and nonzero diagonal entries to st.
+hipError_t launch_check_input(const void* D, int d_is_f64, int64_t n, DevStatus* st, hipStream_t s);
+
 // ---- Gaussian test matrix ---------------------------------------------------
+// Raw Philox4x64-10 blocks (counter words 0..3 and key words 0..1 per item).
+hipError_t launch_philox(const uint64_t* in, uint64_t* out, int64_t count, hipStream_t s);
 hipError_t launch_omega(uint64_t seed, int64_t n, int l, int l_pad, int64_t ldg, int xk, void* Xt,
                         hipStream_t s);
 
@@ -87,7 +95,9 @@ struct GPassCfg {
 };
 // sym (recentring passes only): the projection's symmetric mode, see k_gpass.
 // d8: D holds fp64 (recentring passes keep more raw values in registers).
-// gk == GK_BF16 with from_d: the fused centring write and first range pass.
+// gk == GK_BF16 with from_d: the fused centring write and first range pass
+// on bf16 MFMA; gk == GK_F32S with a G argument: the fused centring write and
+// an fp32 first range pass (three-term split).
 // dma_ok (GK_F32S, symmetric): n % 4 == 0 and D 16-byte aligned, so the pass
 // may stream D through LDS (needs the same alignment at launch).
 GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d, bool sym,
@@ -99,7 +109,8 @@ GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_h
 // hr_i = fl32((r_i - m) / 2), a few fp32 ulps of the terms from the rounded
 // exact value.
 struct GPassDSrc {
-  // (with gk == GK_BF16 and D set, the pass's G argument is the bf16 G it writes)
+  // (with gk == GK_BF16 or GK_F32S and D set, a non-null G argument of the pass
+  // is the bf16 G that it writes: the fused centring write)
   const float* g8_scales = nullptr;  // GK_FP8: scale of block (I, J) at [I * g8_nsb + J]
   int64_t g8_nsb = 0;
   const void* D = nullptr;

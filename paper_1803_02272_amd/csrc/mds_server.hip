@@ -113,8 +113,13 @@ struct Slot {
   size_t ws_off = 0, ws_bytes = 0;
 };
 
+// The batched kernel runs the default schedule of each form (fp32 end passes
+// in bf16, full-matrix centring and projection), so plans with option flags
+// always take the plan path.
 bool batchable(const Job* j, int64_t small_n_max) {
-  return j->plan->form <= MDS_FORM_BF16 && j->plan->n <= small_n_max && j->plan->l_pad <= batch_max_l() && j->plan->n <= batch_max_n();
+  const mds_plan_s* P = j->plan;
+  return P->form <= MDS_FORM_BF16 && P->opts.flags == 0 && P->n <= small_n_max && P->l_pad <= batch_max_l() &&
+         P->n <= batch_max_n();
 }
 
 mds_batch_job batch_entry(const Job* j) {

@@ -30,8 +30,14 @@ struct mds_plan_s {
   // ref_cfg_alt: the projection's configuration for a D that is not 16-byte
   // aligned (equal to ref_cfg unless ref_cfg streams D through LDS)
   mds::GPassCfg cfg{}, ref_cfg{}, ref_cfg_alt{};
-  bool fused = false;   // bf16 centring write fused with the first range pass
-  mds::GPassCfg wcfg{};  // its configuration
+  // refine: BF16/FP8 forms whose first and last range passes run in fp32
+  // (three-term split) around the passes over the stored low-precision G
+  bool refine = false;
+  bool needs_g = false;  // G is stored (BF16/FP8 forms with at least one pass over it)
+  mds::GPassCfg fcfg{};  // the fp32 end range passes that are not fused with the write
+  bool fused = false;   // bf16 centring write fused with the first range pass (fp32 D)
+  mds::GPassCfg wcfg{};  // its configuration (an fp32 split pass when refine, else a bf16 pass)
+  int last_xk = -1;      // kind of the operand currently in X (inspection)
   size_t ypart_min = 0;   // lower bound on the split-K partials region (autotuning)
   // workspace
   void* ws = nullptr;

@@ -51,12 +51,14 @@ def test_invalid_arguments_rejected(n, k, p, q):
 def test_invalid_options_rejected():
     assert _plan(100, 4, 4, 1, form=7)[0] == _capi.ERR_INVALID_ARG
     assert _plan(100, 4, 4, 1, dt=5)[0] == _capi.ERR_INVALID_ARG
-    assert _plan(100, 4, 4, 1, flags=16)[0] == _capi.ERR_INVALID_ARG
+    assert _plan(100, 4, 4, 1, flags=64)[0] == _capi.ERR_INVALID_ARG
     assert _plan(100, 4, 4, 1, split=-1)[0] == _capi.ERR_INVALID_ARG
     for form, flags in ((2, _capi.FLAG_FULL_PROJECTION), (2, _capi.FLAG_FP32_MFMA_PROJECTION),
                         (2, _capi.FLAG_FULL_PROJECTION | _capi.FLAG_FP32_MFMA_PROJECTION),
                         (1, _capi.FLAG_SPLIT_FP32), (1, _capi.FLAG_SPLIT_FP32 | _capi.FLAG_FULL_PROJECTION),
-                        (0, _capi.FLAG_FULL_STATS), (2, _capi.FLAG_FULL_STATS | _capi.FLAG_FULL_PROJECTION)):
+                        (0, _capi.FLAG_FULL_STATS), (2, _capi.FLAG_FULL_STATS | _capi.FLAG_FULL_PROJECTION),
+                        (1, _capi.FLAG_CHECK_INPUT), (2, _capi.FLAG_LOWP_ALL_RANGE),
+                        (3, _capi.FLAG_LOWP_ALL_RANGE | _capi.FLAG_CHECK_INPUT)):
         st, h = _plan(100, 4, 4, 1, form=form, flags=flags)
         assert st == _capi.OK
         _capi.lib().mds_destroy(h)
@@ -76,6 +78,13 @@ def test_workspace_size_scales_with_form():
     # only the bf16 form stores G (2 bytes per entry); the others recentre D on the fly
     assert sizes[0] < npad * npad and sizes[1] < npad * npad
     assert npad * npad * 2 <= sizes[2] < npad * npad * 3
+    # with q = 0 the bf16 form's one range pass is an fp32 pass: no G is stored
+    st, h = _plan(20000, 50, 10, 0, form=2)
+    b = ctypes.c_size_t()
+    assert L.mds_workspace_size(h, ctypes.byref(b)) == _capi.OK and b.value < npad * npad
+    L.mds_destroy(h)
+    # the input check covers n up to 65535 tiles of 64
+    assert _plan(65535 * 64 + 1, 4, 4, 1, flags=_capi.FLAG_CHECK_INPUT)[0] == _capi.ERR_INVALID_ARG
 
 
 def test_run_without_device_reports_no_device():
@@ -99,7 +108,7 @@ def test_run_without_device_reports_no_device():
 
 def test_status_strings():
     L = _capi.lib()
-    for code in range(-9, 2):
+    for code in range(-10, 2):
         assert L.mds_status_string(code).decode()
     assert L.mds_version().decode().count(".") == 2
 

@@ -1,6 +1,7 @@
-"""Batched small instances (mds_run_batch): one persistent launch, one
-workgroup per MDS instance, uneven n.  Each instance against the FP64
-oracle run with the form's roundings, and against the single-instance path."""
+"""Batched small instances (mds_run_batch): one persistent launch whose
+workgroups take MDS instances of uneven n from a device job table.  Each
+instance against the FP64 oracle (plain, at the form's stated bar, and run
+with the form's roundings), and against the single-instance path."""
 import numpy as np
 import pytest
 
@@ -18,6 +19,9 @@ from paper_1803_02272_amd import _capi  # noqa: E402
 
 MATCHED_EIG_BAR = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 1e-4}
 COORD_BAR = {"fp64": 1e-8, "fp32": 1e-3, "bf16": 5e-2}
+# against the plain fp64 oracle: the stated bars (the bf16 form's first and
+# last range passes are fp32 in the batched kernel as in the plan path)
+EIG_BAR = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 1e-3}
 
 # (kind, n, k, p, q, seed): ragged n (not multiples of 64), l from 2 to 64
 PROBLEMS = [("gm", 517, 20, 10, 2, 1), ("amp", 1000, 20, 10, 2, 2), ("gm", 257, 5, 5, 1, 3),
@@ -45,23 +49,26 @@ def test_batch_matches_oracle_and_single_path(form, tile):
     assert st == [_capi.OK] * len(probs)
     for D, pr, (c, e), (kind, n, k, p, q, seed) in zip(Ds, probs, outs, PROBLEMS):
         ref = O.rand_mds(D, k, p, q, seed, form=form)
+        plain = O.rand_mds(D, k, p, q, seed) if form != "fp64" else ref
         X, eig = c.cpu().numpy(), e.cpu().numpy()
         err = rel_eig_err(eig, ref["eigvals"])
+        perr = rel_eig_err(eig, plain["eigvals"])
         cerr = procrustes_err(X, ref["coords"])
         plan = mds.Plan(n, k, p, q, seed, form=form, d_dtype="f64" if D.dtype == np.float64 else "f32")
         cs, es = plan.run(pr["D"])
         serr = rel_eig_err(eig, es.cpu().numpy())
-        say(f"    {kind} n={n} k={k} l={k + p} q={q}: eig vs matched oracle {err:.2e}, coords {cerr:.2e}, "
-            f"vs single path {serr:.2e}")
+        say(f"    {kind} n={n} k={k} l={k + p} q={q}: eig vs matched oracle {err:.2e}, vs plain {perr:.2e}, "
+            f"coords {cerr:.2e}, vs single path {serr:.2e}")
         assert err < MATCHED_EIG_BAR[form]
+        assert perr < EIG_BAR[form]
         assert cerr < COORD_BAR[form]
         assert serr < MATCHED_EIG_BAR[form]
         idx = np.argmax(np.abs(X), axis=0)
         assert np.all(X[idx, np.arange(k)] > 0)
 
 
-def test_batch_edge_cases_and_many_launches():
-    say("[batch] zero D, NaN D, n = 2, 40 instances over two launches")
+def test_batch_edge_cases_and_many_instances():
+    say("[batch] zero D, NaN D, n = 2, 40 instances in one persistent launch")
     Dz = torch.zeros((300, 300), dtype=torch.float32, device="cuda")
     Dn = torch.from_numpy(build("amp", 400, 3)).cuda()
     Dn[5, 9] = float("nan")
@@ -98,3 +105,23 @@ def test_autotuner_records_a_tile_and_server_threshold():
         small_n_max = srv.autotune(form="bf16", k=20, oversample=10, q=2)
         say(f"    server batching threshold: n <= {small_n_max}")
         assert small_n_max in (0, 128, 256, 512, 1024, 2048, 4096, 8192)
+
+
+def test_batch_many_more_instances_than_workgroups():
+    """600 instances (more than the persistent grid holds at once) of uneven
+    n in one call: every instance's result equals the same instance run in a
+    batch of its own (the work queue changes which workgroup runs it, not
+    what it computes)."""
+    rng = np.random.default_rng(11)
+    ns = rng.integers(40, 300, 600)
+    Ds = [torch.from_numpy(build("gm" if i % 2 else "amp", int(n), 200 + i)).cuda() for i, n in enumerate(ns)]
+    probs = [dict(D=D, k=6, oversample=4, q=1, seed=i) for i, D in enumerate(Ds)]
+    say(f"[batch] {len(probs)} instances, n in [40, 300)")
+    outs, st = mds.run_batch(probs, form="bf16", tile=4)
+    assert st == [_capi.OK] * len(probs)
+    for i in (0, 1, 299, 598, 599):
+        o1, s1 = mds.run_batch([probs[i]], form="bf16", tile=4)
+        assert s1 == [_capi.OK]
+        assert torch.equal(o1[0][0], outs[i][0]) and torch.equal(o1[0][1], outs[i][1])
+        ref = O.rand_mds(Ds[i].cpu().numpy(), 6, 4, 1, i)
+        assert rel_eig_err(outs[i][1].cpu().numpy(), ref["eigvals"]) < EIG_BAR["bf16"]

@@ -4,7 +4,8 @@ substitutions at a per-read rate uniform in 1-5%), D = Hamming / 400 in fp32,
 k = 50, oversample 10, q = 2.  The reference is the FP64 oracle (same method,
 same test matrix) on the same D, and the oracle run with each form's operand
 roundings.  The fp32 form is this workload's form; the bf16 form and the fp32
-form with split passes are checked as well.
+form with split passes are checked as well, the bf16 form against the plain
+oracle at its 1e-3 bar.
 """
 import numpy as np
 import pytest
@@ -48,4 +49,7 @@ def test_c2_amplicon_n20000():
         if form == "fp32":
             assert err < 1e-5
             assert cerr < 1e-3
+        else:  # bf16 form (fp32 end passes) against the plain fp64 oracle
+            assert err < 1e-3
+            assert cerr < 5e-3
         plan.close()

@@ -7,7 +7,8 @@ a Euclidean D the Gram matrix is that of the centred points), so its only
 nonzero eigenvalues are the squared singular values of the centred cloud,
 and rank(G) = 200 < l = 220 makes the randomized method exact (Halko et
 al.: Q Q^T G = G).  The FP64 form must reproduce them up to the fp32
-rounding of D; the BF16 and FP8 forms report their error per dtype.
+rounding of D, the FP32 form within 1e-5 and the BF16 and FP8 forms within
+1e-3 (relative, per eigenvalue).
 """
 import time
 
@@ -64,7 +65,13 @@ def test_c4_full_size_against_point_cloud_spectrum():
             dd = np.linalg.norm(X[i] - X[j], axis=1)
             assert np.max(np.abs(dh - dd)) < 1e-4 * np.max(dd)
         elif form == "fp32":
-            assert errs[form] < 1e-4
+            # fp32 entries of G add ~2^-24 relative per entry to the fp32
+            # rounding of D; the stated fp32 bar applies
+            assert errs[form] < 1e-5
+        else:
+            # bf16 and fp8 storage of G (fp32 first and last range passes and
+            # projection): the stated 1e-3 bar of the low-precision forms
+            assert errs[form] < 1e-3
         plan.close()
         del coords, eig
         torch.cuda.empty_cache()

@@ -22,15 +22,26 @@ if not torch.cuda.is_available():  # pragma: no cover - collected on CPU only
 import paper_1803_02272_amd as mds  # noqa: E402
 from paper_1803_02272_amd import _capi  # noqa: E402
 
-# bars against the plain fp64 oracle (the stated targets)
+# bars against the plain fp64 oracle (the stated targets): relative error
+# per eigenvalue over the top k, coordinates after sign + Procrustes.  The
+# bf16 form's first and last range passes are fp32, which keeps it within the
+# 1e-3 bar also where the k-th eigenvalue lies in a near-degenerate bulk
+# (gm2000, amp3001; the oracle model of the form measures <= 9e-5 on these
+# cases and <= 2e-4 on the coordinates).
 EIG_BAR = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 1e-3}
-COORD_BAR = {"fp64": 1e-8, "fp32": 1e-3, "bf16": 5e-2}
-# the FP8 form has no stated bar against the plain oracle (3 fraction bits);
-# its error is reported, and it must match the oracle run with its roundings
+COORD_BAR = {"fp64": 1e-8, "fp32": 1e-3, "bf16": 5e-3, "fp8": 5e-2}
+# FP8 (3 fraction bits): Weyl's inequality bounds the move of every
+# eigenvalue by the spectral norm of the storage error, |dtheta_i| <=
+# ||G_fp8 - G||_2, asserted on every case (the fp8 roundings of G come from
+# the oracle's E4M3 model, which is pinned to PyTorch's float8_e4m3fn); the
+# 1e-3 relative bar is asserted where the storage error is small against the
+# k-th eigenvalue, and amp3001 (k-th eigenvalue in the bulk, 3.5e-3 in the
+# oracle model of the form) is reported against it only.
+FP8_REL_CASES = {"gm2000_f64", "amp1237_f32", "amp5000_r200"}
 # bars against the oracle run with the same storage roundings as the form
 # (isolates kernel errors from the precision of the form: what remains is
 # fp32 accumulation order and occasional flips of a bf16 rounding)
-MATCHED_EIG_BAR = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 1e-4, "fp8": 1e-4}
+MATCHED_EIG_BAR = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 1e-4, "fp8": 1e-4, "bf16_all": 1e-4, "fp8_all": 1e-4}
 
 
 def gm_case(n, dim, comps, var, seed, dtype):
@@ -51,12 +62,6 @@ CASES = {
     # the paper-scale amplicon recipe (200 references, k=100, p=20, q=2) at n=5000
     "amp5000_r200": (lambda: amp_case(5000, 200, 0), 100, 20, 2),
 }
-# Cases where the k-th eigenvalue is separated from the noise bulk, as in the
-# paper-scale amplicon workload; there bf16 storage of G meets the 1e-3 bar.
-# In gm2000 and amp3001 the k-th eigenvalue lies inside a near-degenerate
-# bulk and bf16 storage alone moves it by about 1.1e-3 (the oracle run with
-# the bf16 roundings shows the same), so only the matched bar applies there.
-BF16_TARGET_LIKE = {"amp1237_f32", "amp5000_r200"}
 _cache = {}
 
 
@@ -74,6 +79,29 @@ def oracle_rand(name, seed=0, keep_history=False, form="fp64"):
         D, k, p, q = case(name)
         _cache[key] = O.rand_mds(D, k, p, q, seed, keep_history=keep_history, form=form)
     return _cache[key]
+
+
+def fp8_weyl_bound(name):
+    """||G_fp8 - G||_2 with G_fp8 the oracle's block-scaled E4M3 operand."""
+    key = (name, "weyl")
+    if key not in _cache:
+        import scipy.sparse.linalg
+
+        D = case(name)[0]
+        G = O.gram_matrix(D)
+        E = O.fp8_operand(G) - G
+        _cache[key] = float(abs(scipy.sparse.linalg.eigsh(0.5 * (E + E.T), k=1, which="LM",
+                                                           return_eigenvectors=False)[0]))
+    return _cache[key]
+
+
+def split_sum(X3):
+    """x0 + x1 + x2 of a split operand (l_pad x 3 ldg bf16 planes, per 32
+    columns the 32 x0, then the x1, then the x2 terms) as l_pad x ldg fp64."""
+    X3 = np.asarray(X3, dtype=np.float64)
+    ldg = X3.shape[1] // 3
+    planes = X3.reshape(X3.shape[0], ldg // 32, 3, 32)
+    return (planes[:, :, 0, :] + planes[:, :, 1, :] + planes[:, :, 2, :]).reshape(X3.shape[0], ldg)
 
 
 def dtype_of(D):
@@ -193,26 +221,52 @@ def test_symmetric_stats_match_full(form):
     assert np.max(np.abs(e0 - e1)) <= (1e-12 if form == "fp64" else 1e-6) * np.max(np.abs(e1))
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16", "bf16_all"])
 def test_omega_stage(form):
     D, k, p, q = case("amp1237_f32")
     n = D.shape[0]
     seed = 1234567
     l = k + p
     say(f"[omega] n={n} l={l} form={form}")
-    plan = mds.Plan(n, k, p, q, seed, form=form)
+    plan = mds.Plan(n, k, p, q, seed, form=form.replace("_all", ""), lowp_all_range=form.endswith("_all"))
     plan.run_stages(torch.from_numpy(D).cuda(), _capi.STAGE_OMEGA)
     torch.cuda.synchronize()
     Xt = plan.buffer(_capi.BUF_X).double().cpu().numpy()
+    if form == "bf16":  # the first range pass is fp32: Omega as its exact three-term split
+        Xt = split_sum(Xt)
     Om = O.omega(seed, n, l)
     got = Xt[:l, :n].T
     if form == "fp64":
-        assert np.max(np.abs(got - Om) / np.maximum(1.0, np.abs(Om))) < 1e-14
-    elif form == "fp32":
+        # the same IEEE operations in the same order on both sides: bit-identical
+        assert np.array_equal(got, Om)
+    elif form in ("fp32", "bf16"):
         assert np.max(np.abs(got - Om.astype(np.float32))) <= 2e-7 * np.max(np.abs(Om))
     else:
         assert np.mean(got != bf16_round(Om)) < 1e-3
     assert np.all(Xt[l:, :] == 0) and np.all(Xt[:, n:] == 0)
+
+
+def test_philox_known_answers_on_device():
+    """The device generator's raw blocks against the published known-answer
+    vectors of Philox4x64-10, and against the oracle's blocks on the counters
+    Omega uses (row i, column block b, key (seed, 0))."""
+    from conftest import load_kat
+
+    rows = load_kat("philox4x64_10_kat.txt")
+    rng = np.random.default_rng(8)
+    extra = [[int(i), int(b), 0, 0, 12345, 0] for i, b in zip(rng.integers(0, 10 ** 6, 500), rng.integers(0, 64, 500))]
+    inp = np.array([r[0:6] for r in rows] + extra, dtype=np.uint64)
+    say(f"[philox] {len(inp)} blocks on the device")
+    din = torch.from_numpy(inp.view(np.int64)).cuda()
+    dout = torch.empty((len(inp), 4), dtype=torch.int64, device="cuda")
+    st = _capi.lib().mds_philox4x64_10(din.data_ptr(), dout.data_ptr(), len(inp), None)
+    assert st == _capi.OK
+    torch.cuda.synchronize()
+    got = dout.cpu().numpy().view(np.uint64)
+    for r, g in zip(rows, got[: len(rows)]):
+        assert [int(x) for x in g] == r[6:10]
+    want = O.philox4x64_10(inp[len(rows):, :4], (12345, 0))
+    assert np.array_equal(got[len(rows):], want)
 
 
 @pytest.mark.parametrize("name", ["gm2000_f64", "amp1237_f32"])
@@ -230,21 +284,22 @@ def test_gpass_and_cholqr2_unit(name, form):
     torch.cuda.synchronize()
     G = O.gram_matrix(D)
     Om = O.omega(5, n, l)
-    if form == "fp32":
+    # fp32 first pass in every form but fp64 (the bf16 and fp8 forms take
+    # their first range pass in fp32 as a three-term bf16 split)
+    if form != "fp64":
         G, Om = G.astype(np.float32).astype(np.float64), Om.astype(np.float32).astype(np.float64)
-    elif form == "bf16":
-        G, Om = bf16_round(G).astype(np.float64), bf16_round(Om).astype(np.float64)
-    elif form == "fp8":
-        G, Om = O.fp8_operand(G), bf16_round(Om).astype(np.float64)
     want = G @ Om
     mag = np.abs(G) @ np.abs(Om)
     Yt = plan.buffer(_capi.BUF_Y).cpu().numpy()
     Y = Yt[:l, :n].T
     u = 2.0 ** -53 if form == "fp64" else 2.0 ** -24
     bound = 2 * n * u * mag
-    if form == "fp32":
-        # fp32 passes recentre D on the fly with one fma per entry from
-        # fl32(d^2), fl32(c/2), fl32((r-m)/2): a few ulps of those terms
+    if form in ("bf16", "fp8"):
+        bound = bound + 2.0 ** -22 * mag  # the three dropped products of the split
+    # fp32 passes recentre D on the fly with one fma per entry from fl32(d^2),
+    # fl32(c/2), fl32((r-m)/2): a few ulps of those terms (the fused bf16
+    # first pass over fp32 D takes fl32 of the fp64 entry itself)
+    if form == "fp32" or (form in ("bf16", "fp8") and not (form == "bf16" and D.dtype == np.float32)):
         r, c, m = O.centring_stats(D)
         H = 0.5 * (D.astype(np.float64) ** 2 + c[None, :] + np.abs(r - m)[:, None])
         bound = bound + 4 * u * (H @ np.abs(Om))
@@ -289,11 +344,16 @@ def test_full_run_parity(name, form):
     say(f"    eig rel err vs fp64 {err:.3e}  vs matched {merr:.3e}  coords procrustes {cerr:.3e}"
         f"  fallbacks {info['orth_fallbacks']}  sweeps {info['jacobi_sweeps']}")
     assert merr < MATCHED_EIG_BAR[form]
+    assert cerr < COORD_BAR[form]
     if form == "fp8":
-        pass  # error against the plain oracle is reported above; no stated bar
-    elif form != "bf16" or name in BF16_TARGET_LIKE:
+        wb = fp8_weyl_bound(name)
+        dmax = float(np.max(np.abs(eig - ref["eigvals"])))
+        say(f"    fp8: max |dtheta| {dmax:.3e} <= ||G_fp8 - G||_2 = {wb:.3e} (ratio {dmax / wb:.2e})")
+        assert dmax <= wb
+        if name in FP8_REL_CASES:
+            assert err < 1e-3
+    else:
         assert err < EIG_BAR[form]
-        assert cerr < COORD_BAR[form]
     # theta and V are a Rayleigh-Ritz pair of the projected matrix
     th = plan.buffer(_capi.BUF_THETA).cpu().numpy()[:, 0]
     assert np.all(np.diff(th) <= 0)
@@ -303,6 +363,27 @@ def test_full_run_parity(name, form):
     assert np.all(X[idx, np.arange(k)] > 0)
     if form == "fp64":
         assert sign_aligned_err(X, ref["coords"]) < 1e-7
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("form", ["bf16", "fp8"])
+def test_lowp_all_range_schedule(name, form):
+    """MDS_FLAG_LOWP_ALL_RANGE: every range pass on the stored low-precision G
+    (no fp32 end passes).  Checked against the oracle run with that schedule's
+    roundings; its error against the plain oracle is reported (it may exceed
+    1e-3 where the k-th eigenvalue lies in a near-degenerate bulk)."""
+    D, k, p, q = case(name)
+    say(f"[lowp all] case={name} form={form}")
+    ref = oracle_rand(name)
+    matched = oracle_rand(name, form=form + "_all")
+    plan = mds.Plan(D.shape[0], k, p, q, 0, form=form, d_dtype=dtype_of(D), lowp_all_range=True)
+    coords, eig = plan.run(torch.from_numpy(np.ascontiguousarray(D)).cuda())
+    info = plan.info()
+    assert info["status"] == 0, info
+    eig = eig.cpu().numpy()
+    err, merr = rel_eig_err(eig, ref["eigvals"]), rel_eig_err(eig, matched["eigvals"])
+    say(f"    eig rel err vs fp64 {err:.3e}  vs matched {merr:.3e}")
+    assert merr < MATCHED_EIG_BAR[form + "_all"]
 
 
 def test_bitwise_repeatable():
@@ -387,9 +468,11 @@ def test_d_f64_with_bf16_form():
     D, k, p, q = case(name)
     say("[dtype] fp64 D, bf16 form")
     ref = oracle_rand(name, form="bf16")
+    plain = oracle_rand(name)
     _, X, eig, info = gpu_run(D, k, p, q, 0, "bf16")
     assert info["status"] == 0
     assert rel_eig_err(eig, ref["eigvals"]) < MATCHED_EIG_BAR["bf16"]
+    assert rel_eig_err(eig, plain["eigvals"]) < EIG_BAR["bf16"]
 
 
 # ---------------------------------------------------------------------------
@@ -451,10 +534,7 @@ def test_split_projection_unit(name):
     Qt = plan.buffer(_capi.BUF_Q).cpu().numpy()
     Q32 = Qt[:l, :n].T.astype(np.float32).astype(np.float64)
     # the split operand holds fl32(Q) exactly: x0 + x1 + x2 per entry
-    X3 = plan.buffer(_capi.BUF_X).float().cpu().numpy().astype(np.float64)
-    ldg = X3.shape[1] // 3
-    planes = X3.reshape(X3.shape[0], ldg // 32, 3, 32)
-    recon = (planes[:, :, 0, :] + planes[:, :, 1, :] + planes[:, :, 2, :]).reshape(X3.shape[0], ldg)
+    recon = split_sum(plan.buffer(_capi.BUF_X).float().cpu().numpy())
     assert np.array_equal(recon[:l, :n], Q32.T)
     assert np.all(recon[l:] == 0) and np.all(recon[:, n:] == 0)
     G = O.gram_matrix(D).astype(np.float32).astype(np.float64)
@@ -512,10 +592,7 @@ def test_split_fp32_omega():
     plan = mds.Plan(n, k, p, q, seed, form="fp32", split_fp32=True)
     plan.run_stages(torch.from_numpy(D).cuda(), _capi.STAGE_OMEGA)
     torch.cuda.synchronize()
-    X3 = plan.buffer(_capi.BUF_X).float().cpu().numpy().astype(np.float64)
-    ldg = X3.shape[1] // 3
-    planes = X3.reshape(X3.shape[0], ldg // 32, 3, 32)
-    recon = (planes[:, :, 0, :] + planes[:, :, 1, :] + planes[:, :, 2, :]).reshape(X3.shape[0], ldg)
+    recon = split_sum(plan.buffer(_capi.BUF_X).float().cpu().numpy())
     Om = O.omega(seed, n, l).astype(np.float32).astype(np.float64)
     assert np.array_equal(recon[:l, :n], Om.T)
     assert np.all(recon[l:] == 0) and np.all(recon[:, n:] == 0)
@@ -592,6 +669,7 @@ def test_autotuned_plan_parity(form):
     say(f"    chosen {r}")
     assert r["candidates"] >= 3 and r["range_ms"] > 0 and r["proj_ms"] > 0
     assert (r["write_ms"] > 0) == (form == "bf16")
+    assert (r["f32_ms"] > 0) == (form == "bf16")  # the last range pass of the bf16 form is fp32
     coords, eig = plan.run(Dg)
     info = plan.info()
     assert info["status"] == 0

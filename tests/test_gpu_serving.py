@@ -76,6 +76,28 @@ def test_mix_matches_alone_under_budget(batching):
             assert torch.equal(c, ca) and torch.equal(e, ea), f"n={pl.n} differs from the standalone run"
 
 
+def test_served_bf16_jobs_against_the_plain_oracle():
+    """Served BF16 jobs of the mix (plan path and batched small jobs) against
+    the plain FP64 oracle at the form's stated 1e-3 bar."""
+    import numpy as np
+
+    import oracle as O
+    from gpu_util import rel_eig_err
+
+    picks = [("gm", 517, 1), ("amp", 3001, 2), ("gm", 2500, 3), ("amp", 9000, 4), ("gm", 15000, 5)]
+    jobs = [(mds.Plan(n, 20, 10, 2, seed=s, form="bf16"), make_D(kind, n, seed=s)) for kind, n, s in picks]
+    say(f"[serve] {len(jobs)} bf16 jobs against the plain oracle")
+    with mds.Server(1 << 34, slots=4, small_n_max=1024) as srv:
+        tickets = [srv.submit(pl, D) for pl, D in jobs]
+        res = [srv.wait(t) for t, _, _ in tickets]
+    assert all(r[0] == _capi.OK for r in res)
+    for (pl, D), (t, c, e) in zip(jobs, tickets):
+        ref = O.rand_mds(D.cpu().numpy(), 20, 10, 2, pl.seed)
+        err = rel_eig_err(e.cpu().numpy(), ref["eigvals"])
+        say(f"    n={pl.n}: eig rel err vs plain oracle {err:.2e}")
+        assert err < 1e-3
+
+
 def test_cancel_nonfinite_budget_and_tickets():
     import ctypes
 

@@ -168,3 +168,34 @@ def test_bf16_form_perturbs_like_its_storage():
     c = O.rand_mds(D, 20, 10, 1, 0, form="fp32")["eigvals"]
     eb, ec = np.max(np.abs(b - a) / a), np.max(np.abs(c - a) / a)
     assert 1e-9 < ec < 1e-5 and ec < eb < 2e-2
+
+
+def test_low_precision_schedule_has_fp32_end_passes():
+    # The bf16/fp8 forms take their first and last range application in fp32:
+    # with q = 0 that single application is the whole range finder, so the
+    # form is the fp32 form exactly; with q >= 1 it differs from the variant
+    # that runs every application on the stored bf16 G.
+    reads, _ = W.amplicon_reads(500, 20, seed=3)
+    D = W.hamming_distances(reads)
+    f32 = O.rand_mds(D, 8, 4, 0, 1, form="fp32")
+    for form in ("bf16", "fp8"):
+        assert np.array_equal(O.rand_mds(D, 8, 4, 0, 1, form=form)["eigvals"], f32["eigvals"])
+    assert [O.pass_dtypes("bf16", it, 2) for it in range(5)] == [
+        ("f32", "f32"), ("bf16", "bf16"), ("bf16", "bf16"), ("bf16", "bf16"), ("f32", "f32")]
+    assert all(O.pass_dtypes("bf16_all", it, 2) == ("bf16", "bf16") for it in range(5))
+    a = O.rand_mds(D, 8, 4, 1, 1, form="bf16")["eigvals"]
+    b = O.rand_mds(D, 8, 4, 1, 1, form="bf16_all")["eigvals"]
+    assert not np.array_equal(a, b)
+
+
+def test_fp32_end_passes_keep_bf16_within_1e3_near_degenerate():
+    # 10-component mixture in 50 dims, k = 10: the k-th eigenvalue lies in the
+    # noise bulk, where a sketch made only of bf16 applications moves the
+    # Ritz values by more than 1e-3 relative to the fp64 method; with the two
+    # end applications in fp32 the bf16 form stays well inside 1e-3.
+    X, _ = W.gaussian_mixture(2000, 50, 10, 25.0, seed=0)
+    D = W.euclidean_distances(X)
+    ref = O.rand_mds(D, 10, 10, 1, 0)["eigvals"]
+    err = {f: np.max(np.abs(O.rand_mds(D, 10, 10, 1, 0, form=f)["eigvals"] - ref) / np.abs(ref))
+           for f in ("bf16", "bf16_all")}
+    assert err["bf16"] < 2e-4 < 1e-3 < err["bf16_all"]
