@@ -679,3 +679,39 @@ def test_autotuned_plan_parity(form):
     assert rel_eig_err(eig.cpu().numpy(), ref["eigvals"]) < MATCHED_EIG_BAR[form]
     with pytest.raises(mds.MdsError):
         plan.autotune(Dg)  # the workspace is attached now
+
+
+# ---------------------------------------------------------------------------
+# finite-metric input check (MDS_FLAG_CHECK_INPUT)
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_check_input_flags_asymmetry_and_diagonal(dtype):
+    """Symmetric D with a zero diagonal passes; flipped pairs and nonzero
+    diagonal entries are counted exactly (several 64 x 64 tiles, ragged
+    edge) and the run reports MDS_ERR_NOT_METRIC."""
+    n = 1000
+    D = amp_case(n, 12, 4).astype(dtype)
+    say(f"[check input] n={n} dtype={np.dtype(dtype).name}")
+    plan = mds.Plan(n, 5, 5, 1, 0, form="fp64", d_dtype=dtype_of(D), check_input=True)
+    plan.run(torch.from_numpy(np.ascontiguousarray(D)).cuda())
+    info = plan.info()
+    assert info["status"] == 0 and info["asym_pairs"] == 0 and info["diag_nonzero"] == 0
+    Db = D.copy()
+    pairs = [(3, 900), (64, 65), (999, 0), (500, 501), (10, 11)]
+    for i, j in pairs:
+        Db[i, j] = Db[i, j] + 0.25  # d_ij != d_ji, one entry per pair
+    Db[7, 7] = 0.5
+    Db[998, 998] = 1.0
+    Db[200, 300] = np.nan  # NaN compares unequal: counted as asymmetric
+    plan.run(torch.from_numpy(np.ascontiguousarray(Db)).cuda())
+    info = plan.info()
+    assert info["asym_pairs"] == len(pairs) + 1 and info["diag_nonzero"] == 2
+    assert info["status"] == _capi.ERR_NONFINITE  # non-finite input takes precedence
+    Db[200, 300] = Db[300, 200]
+    plan.run(torch.from_numpy(np.ascontiguousarray(Db)).cuda())
+    info = plan.info()
+    assert info["asym_pairs"] == len(pairs) and info["diag_nonzero"] == 2
+    assert info["status"] == _capi.ERR_NOT_METRIC
+    # without the flag the same D runs through (the contract is not checked)
+    plan2 = mds.Plan(n, 5, 5, 1, 0, form="fp64", d_dtype=dtype_of(D))
+    plan2.run(torch.from_numpy(np.ascontiguousarray(Db)).cuda())
+    assert plan2.info()["status"] == 0
