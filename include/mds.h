@@ -347,6 +347,27 @@ mds_status mds_autotune_batch(int32_t form, int64_t n, int32_t k, int32_t oversa
  * MDS_ERR_NUMERICAL) to host statuses[count]. */
 mds_status mds_batch_status(const void* workspace, int32_t count, int32_t* statuses, void* stream);
 
+/* mds_run_batch without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The batch workspace is a static device
+ * array of MDS_BATCH_STATIC_BYTES (128 MiB) that the library holds on every
+ * device it runs on until the process ends; no hipMalloc,
+ * hipFree or allocating library routine is called.  The same kernels as
+ * mds_run_batch, so each instance's result equals mds_run_batch's.
+ *   jobs, count, form, tile: as for mds_run_batch.
+ *   statuses: optional device array of count int32 (NULL: none), written
+ *             with each instance's final status (MDS_OK, MDS_ERR_NONFINITE,
+ *             MDS_ERR_NUMERICAL) by the batched kernel itself.
+ * Errors (host-side, before any device work): MDS_ERR_INVALID_ARG for bad
+ * jobs or a batch whose workspace (mds_batch_workspace_size) exceeds the
+ * capacity, MDS_ERR_NO_DEVICE.  All calls on one device share its array and
+ * each call overwrites what the last one left: calls that overlap on one
+ * device (different streams, or threads) race and must be serialised by the
+ * caller. */
+#define MDS_BATCH_STATIC_BYTES ((size_t)128 << 20)
+mds_status mds_run_batch_static(const mds_batch_job* jobs, int32_t count, int32_t form, int32_t tile,
+                                int32_t* statuses, void* stream);
+
 /* ---- Serving: continuous batching of MDS jobs (spec serving loop) ----
  * A server owns a device arena of hbm_budget_bytes, allocated once by
  * mds_server_create (nothing is allocated on the device while serving), and

@@ -38,6 +38,7 @@ STAGE_CENTER, STAGE_OMEGA, STAGE_RANGE, STAGE_ALL = 1, 2, 3, 100
  BUF_Q1, BUF_GSCALE) = range(15)
 
 MAX_L = 256
+BATCH_STATIC_BYTES = 128 << 20  # MDS_BATCH_STATIC_BYTES
 
 # option flags (mds_opts.flags)
 FLAG_FULL_PROJECTION = 1
@@ -148,6 +149,8 @@ SIGNATURES = {
                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "mds_batch_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.c_void_p]),
+    "mds_run_batch_static": (ctypes.c_int, [ctypes.POINTER(MdsBatchJob), ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "mds_server_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t, ctypes.c_int32]),
     "mds_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),

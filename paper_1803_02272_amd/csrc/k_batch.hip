@@ -891,6 +891,62 @@ mds_status mds_run_batch(const mds_batch_job* jobs, int32_t count, int32_t form,
   return enqueue_batch(jobs, count, form, static_cast<char*>(workspace), tile, nullptr, (hipStream_t)stream);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device memory of mds_run_batch_static: a file-scope array, one copy per
+// device, held until the process ends.  Host code never passes the array's
+// name to a kernel: its device address is looked up once per device with
+// hipGetSymbolAddress and only that address is used.
+constexpr size_t kStaticScratchBytes = MDS_BATCH_STATIC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Address of this device's scratch (the current device), looked up on the
+// first call on the device.
+mds_status static_scratch(char** out) {
+  int dev = 0;
+  mds_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (st != MDS_OK) return st;
+  if (dev < 0 || dev >= kMaxDevices) return fail(MDS_ERR_NO_DEVICE, "device %d outside the supported range", dev);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    st = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (st != MDS_OK) return st;
+    if (!p || ((uintptr_t)p % 256) != 0) return fail(MDS_ERR_HIP, "scratch address %p not 256-byte aligned", p);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<char*>(g_scratch_ptr[dev]);
+  return MDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mds_status mds_run_batch_static(const mds_batch_job* jobs, int32_t count, int32_t form, int32_t tile,
+                                int32_t* statuses, void* stream) {
+  mds_status st = batch_args(jobs, count, form, tile);
+  if (st != MDS_OK) return st;
+  size_t need = 0;
+  mds_batch_workspace_size(jobs, count, form, &need);
+  if (need > kStaticScratchBytes)
+    return fail(MDS_ERR_INVALID_ARG, "batch needs %zu bytes of workspace; the static scratch holds %zu", need,
+                kStaticScratchBytes);
+  if (count == 0) return MDS_OK;
+  st = have_device();
+  if (st != MDS_OK) return st;
+  char* base = nullptr;
+  st = static_scratch(&base);
+  if (st != MDS_OK) return st;
+  return enqueue_batch(jobs, count, form, base, tile, statuses, (hipStream_t)stream);
+}
+
 mds_status mds_autotune_batch(int32_t form, int64_t n, int32_t k, int32_t oversample, int32_t q, int32_t batch,
                               void* stream, mds_batch_tune* out) {
   if (!out || batch < 1 || batch > 4096) return fail(MDS_ERR_INVALID_ARG, "NULL out or batch outside [1, 4096]");
