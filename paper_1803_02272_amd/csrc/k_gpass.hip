@@ -762,248 +762,9 @@ __global__ __launch_bounds__(256, 2) void k_gpass_x3(const uint16_t* __restrict_
   }
 }
 
-// ---- the symmetric split pass with D streamed through LDS ------------------
-// Same arithmetic, work items and output as k_gpass_x3 in symmetric mode
-// (fp32 D, n % 4 == 0, 16-byte aligned D, l_pad <= 128), organised around
-// gfx950's global-to-LDS loads (global_load_lds_dwordx4: lane l's 16 bytes
-// land at the wave's LDS address + 16 l, no registers involved):
-//   * 512 threads (8 waves x 2 row groups, 256 rows) per workgroup and one
-//     workgroup per CU: the X step tile (three planes, 192 bytes per row) is
-//     shared by eight waves instead of four;
-//   * each wave streams its own rows of D into a three-stage LDS ring, two
-//     steps ahead, and reads them back in its own lane order;
-//   * the X tile is double-buffered, its 16-byte slots swizzled
-//     (slot = plane * 4 l_pad + 4 row + (kgroup ^ ((row >> 2) & 3))) so that
-//     the B-operand reads of 16 consecutive rows hit distinct banks.
-// Every buffer is its own __shared__ array and the step loop is unrolled six
-// ways (2 X buffers x 3 ring stages), so each LDS access names a fixed array
-// and the compiler's waits for the DMA stay as precise as the explicit
-// vmcnt waits below; the workgroup barrier is taken without a memory fence,
-// which would wait for the DMA two steps ahead as well.
-typedef __attribute__((address_space(3))) void lds_void_t;
-typedef __attribute__((address_space(1))) const void gbl_void_t;
-
-__device__ __forceinline__ void dma16(const void* g, void* l) {
-  __builtin_amdgcn_global_load_lds((gbl_void_t*)g, (lds_void_t*)l, 16, 0, 0);
-}
-
-constexpr int kDmaWaves = 8;
-constexpr int kDmaMaxL = 128;  // LDS: 2 X tiles (2 x 24 KB at l_pad 128) + ring (3 x 32 KB)
-
-template <int CG>
-__global__ __launch_bounds__(512, 1) void k_gpass_x3d(const uint16_t* __restrict__ X3, int64_t ldg,
-                                                      int64_t steps_total, int64_t steps_per_split,
-                                                      float* __restrict__ Ypart, GPassDSrc src, int64_t sym_nbx) {
-  constexpr bool SYM = true;
-  constexpr int RG = 2;
-  constexpr int NW = kDmaWaves;
-  constexpr int LPAD = CG * 16;
-  constexpr int BK = kX3Step;
-  constexpr int XINS = CG * 3;                       // 1 KB DMA instructions per X step tile
-  constexpr int64_t BM = NW * RG * 16;               // 256 rows per workgroup
-  constexpr int64_t kStepsPerBlock = BM / BK;
-  constexpr int DSTAGE = RG * 2 * 1024;              // bytes of one wave's D stage
-  __shared__ __attribute__((aligned(16))) unsigned char xs0[XINS * 1024];
-  __shared__ __attribute__((aligned(16))) unsigned char xs1[XINS * 1024];
-  __shared__ __attribute__((aligned(16))) unsigned char ds0[NW * DSTAGE];
-  __shared__ __attribute__((aligned(16))) unsigned char ds1[NW * DSTAGE];
-  __shared__ __attribute__((aligned(16))) unsigned char ds2[NW * DSTAGE];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int64_t bid = blockIdx.x;
-  int s;
-  int64_t mb, st0, st1;
-  {  // work item (row block, K split), as in k_gpass_x3
-    const int64_t loc = bid >> 3;
-    s = (int)(loc / sym_nbx);
-    mb = (loc % sym_nbx) * 8 + (bid & 7);
-    const int64_t diag0 = mb * kStepsPerBlock;
-    st0 = (int64_t)s * steps_per_split;
-    st1 = (st0 + steps_per_split < steps_total) ? st0 + steps_per_split : steps_total;
-    if (diag0 > st0) st0 = diag0;
-    if (diag0 >= steps_total || st0 >= st1) return;
-  }
-  const int64_t diag_end = (mb + 1) * kStepsPerBlock;
-  const int64_t row0 = mb * BM + (int64_t)wave * (RG * 16);
-
-  floatx4_t acc[RG][CG];
-#pragma unroll
-  for (int rg = 0; rg < RG; ++rg)
-#pragma unroll
-    for (int cg = 0; cg < CG; ++cg)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc[rg][cg][e] = 0.0f;
-
-  const float* Dp = reinterpret_cast<const float*>(src.D);
-  const int64_t n = src.n;
-  const int64_t nn = n * n;
-  const double mval = src.m[0];
-  float ri[RG];
-  const float* drow[RG];
-#pragma unroll
-  for (int rg = 0; rg < RG; ++rg) {
-    const int64_t i = row0 + rg * 16 + (lane & 15);
-    const float h = (i < n) ? (float)(0.5 * (src.r[i] - mval)) : 0.0f;
-    ri[rg] = SYM ? h + h : h;
-    drow[rg] = Dp + (i < n ? i : n - 1) * n;  // rows beyond n read row n-1 (zeroed in the output)
-  }
-  const size_t xrowbytes = (size_t)ldg * 6;
-  const unsigned char* Xb = reinterpret_cast<const unsigned char*>(X3);
-
-  // D of step st into stage sd: this wave's rows, 16 bytes per lane per
-  // (row group, half); reads past the end of D are clamped to its last 16
-  // bytes (their columns meet zero rows of X).
-  auto dma_d = [&](int64_t st, unsigned char (&dd)[NW * DSTAGE]) {
-#pragma unroll
-    for (int rg = 0; rg < RG; ++rg)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int64_t k = st * BK + (lane >> 4) * 8 + h * 4;
-        const float* g = drow[rg] + k;
-        if (g + 4 > Dp + nn) g = Dp + nn - 4;
-        dma16(g, &dd[wave * DSTAGE + (rg * 2 + h) * 1024]);
-      }
-  };
-  // X tile of step st into buffer b: slot S = q * 64 + lane holds plane p,
-  // row, K-group kg at S = p * 4 LPAD + 4 row + (kg ^ ((row >> 2) & 3))
-  auto dma_x = [&](int64_t st, unsigned char (&xd)[XINS * 1024]) {
-#pragma unroll
-    for (int u = 0; u < (XINS + NW - 1) / NW; ++u) {
-      const int q = wave + u * NW;
-      if (XINS % NW != 0 && q >= XINS) break;
-      const int S = q * 64 + lane;
-      const int p = S / (LPAD * 4), rem = S % (LPAD * 4);
-      const int row = rem >> 2, kg = (rem & 3) ^ ((row >> 2) & 3);
-      dma16(Xb + (size_t)row * xrowbytes + (size_t)st * 192 + p * 64 + kg * 16, &xd[q * 1024]);
-    }
-  };
-  auto load_c = [&](int64_t st, float (&cdst)[8]) {
-    const int64_t k0 = st * BK + (lane >> 4) * 8;
-    const u32x4 w0 = *reinterpret_cast<const u32x4*>(src.hc + k0);
-    const u32x4 w1 = *reinterpret_cast<const u32x4*>(src.hc + k0 + 4);
-    __builtin_memcpy(&cdst[0], &w0, 16);
-    __builtin_memcpy(&cdst[4], &w1, 16);
-  };
-
-  float cv[8], cvn[8];
-  dma_x(st0, xs0);
-  dma_d(st0, ds0);
-  dma_d(st0 + 1 < st1 ? st0 + 1 : st0, ds1);
-  load_c(st0, cv);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  // one step: X(st) in xr, X(st + 1) goes to xw (separate LDS arrays, so the
-  // compiler sees that the reads of xr do not wait for that DMA)
-  using XBuf = unsigned char[XINS * 1024];
-  using DBuf = unsigned char[NW * DSTAGE];
-  auto step = [&](int64_t st, XBuf& xr, XBuf& xw, DBuf& dr, DBuf& dw) {
-    // the prefetches are issued on every step (the last steps re-load step
-    // st1 - 1 into buffers that are not read again), so that the wait counts
-    // below and the compiler's own are the same on every path
-    const int64_t stx = st + 1 < st1 ? st + 1 : st1 - 1;
-    const int64_t std2 = st + 2 < st1 ? st + 2 : st1 - 1;
-    dma_x(stx, xw);
-    load_c(stx, cvn);
-    dma_d(std2, dw);
-    u32x4 w[RG][3];
-    float ch[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) ch[t] = SYM ? cv[t] + cv[t] : cv[t];
-    const bool band = SYM && st < diag_end;
-#pragma unroll
-    for (int rg = 0; rg < RG; ++rg) {
-#pragma clang fp contract(off)
-      const u32x4 lo = *reinterpret_cast<const u32x4*>(&dr[wave * DSTAGE + (rg * 2) * 1024 + lane * 16]);
-      const u32x4 hi = *reinterpret_cast<const u32x4*>(&dr[wave * DSTAGE + (rg * 2 + 1) * 1024 + lane * 16]);
-      float dv[8];
-      __builtin_memcpy(&dv[0], &lo, 16);
-      __builtin_memcpy(&dv[4], &hi, 16);
-      float g[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const float d2 = dv[t] * dv[t];
-        g[t] = __builtin_fmaf(SYM ? -1.0f : -0.5f, d2, ch[t] + ri[rg]);
-      }
-      if (band) {
-        const int64_t i = row0 + rg * 16 + (lane & 15);
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int64_t j = st * BK + (lane >> 4) * 8 + t;
-          g[t] = j > i ? g[t] : (j == i ? 0.5f * g[t] : 0.0f);
-        }
-      }
-      split3(g, w[rg]);
-    }
-#pragma unroll
-    for (int cg0 = 0; cg0 < CG; cg0 += 2) {
-      constexpr int NP = 2;
-      u32x4 bb[NP][3];
-#pragma unroll
-      for (int h = 0; h < NP; ++h)
-        if (cg0 + h < CG) {
-          const int row = (cg0 + h) * 16 + (lane & 15);
-          const int kgs = (lane >> 4) ^ ((row >> 2) & 3);
-#pragma unroll
-          for (int p = 0; p < 3; ++p)
-            bb[h][p] = *reinterpret_cast<const u32x4*>(&xr[(p * LPAD * 4 + row * 4 + kgs) * 16]);
-        }
-      constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
-#pragma unroll
-      for (int pr = 0; pr < 6; ++pr)
-#pragma unroll
-        for (int h = 0; h < NP; ++h)
-          if (cg0 + h < CG)
-#pragma unroll
-            for (int rg = 0; rg < RG; ++rg) Tr<GK_BF16>::mma(acc[rg][cg0 + h], w[rg][PA[pr]], bb[h][PB[pr]]);
-    }
-    // X(st + 1) and D(st + 1) complete (D(st + 2), issued last, may still run)
-    __builtin_amdgcn_s_waitcnt(0x0F70 | RG * 2);  // vmcnt(RG*2)
-    // workgroup barrier without a memory fence (a fence would also wait for
-    // the DMA of D(st + 2)); the waits above make X(st + 1) visible
-    __asm__ volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    __asm__ volatile("" ::: "memory");
-#pragma unroll
-    for (int t = 0; t < 8; ++t) cv[t] = cvn[t];
-    __builtin_amdgcn_sched_barrier(0);  // steps are scheduled one at a time (register pressure)
-  };
-  // D(st) sits in stage (st - st0) % 3 and X(st) in buffer (st - st0) % 2:
-  // six steps per trip keep every LDS array static
-  for (int64_t st = st0; st < st1; st += 6) {
-    step(st, xs0, xs1, ds0, ds2);
-    if (st + 1 >= st1) break;
-    step(st + 1, xs1, xs0, ds1, ds0);
-    if (st + 2 >= st1) break;
-    step(st + 2, xs0, xs1, ds2, ds1);
-    if (st + 3 >= st1) break;
-    step(st + 3, xs1, xs0, ds0, ds2);
-    if (st + 4 >= st1) break;
-    step(st + 4, xs0, xs1, ds1, ds0);
-    if (st + 5 >= st1) break;
-    step(st + 5, xs1, xs0, ds2, ds1);
-  }
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // no DMA outstanding at exit
-
-#pragma unroll
-  for (int rg = 0; rg < RG; ++rg) {
-#pragma unroll
-    for (int cg = 0; cg < CG; ++cg) {
-      const int col = cg * 16 + (lane & 15);
-      float* dst = Ypart + ((int64_t)s * LPAD + col) * ldg + row0 + rg * 16;
-      const int64_t i4 = row0 + rg * 16 + 4 * (lane >> 4);
-      float4 o = make_float4(acc[rg][cg][0], acc[rg][cg][1], acc[rg][cg][2], acc[rg][cg][3]);
-      if (i4 + 3 >= n) {
-        o.x = i4 < n ? o.x : 0.0f;
-        o.y = i4 + 1 < n ? o.y : 0.0f;
-        o.z = i4 + 2 < n ? o.z : 0.0f;
-        o.w = i4 + 3 < n ? o.w : 0.0f;
-      }
-      *reinterpret_cast<float4*>(dst + 4 * (lane >> 4)) = o;
-    }
-  }
-}
+// The split passes that stream D through LDS (fp32 D, n % 4 == 0, aligned D,
+// l_pad <= 128) run in k_split.hip: 8 waves of 2 row groups per workgroup.
+constexpr int kDmaMaxL = 128;
 
 // Symmetric mode: row block mb has partials only in the splits whose K
 // range reaches its diagonal, k >= first_split(row) = (mb * bm) / cols_per_split.
@@ -1092,21 +853,11 @@ template <int CG>
 hipError_t launch_x3_cg(const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t n_pad, void* Yp,
                         const GPassDSrc& src, hipStream_t s, void* Gw) {
   if (!src.D) return hipErrorInvalidValue;
+  if (cfg.dma) return launch_split_pass(Xt, ldg, CG * 16, cfg, gpass_blocks(cfg, n_pad), Yp, src, Gw, s);
   if (Gw) {  // fused centring write: full pass over fp32 D
-    if (cfg.dma || cfg.sym || src.d_is_f64 || cfg.rg != rg_x3(CG, false)) return hipErrorInvalidValue;
+    if (cfg.sym || src.d_is_f64 || cfg.rg != rg_x3(CG, false)) return hipErrorInvalidValue;
     launch_x3_one<CG, float, false, true>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
     return hipGetLastError();
-  }
-  if (cfg.dma) {
-    if constexpr (CG * 16 <= kDmaMaxL) {
-      if (!cfg.sym || cfg.bm != kDmaWaves * 32 || src.d_is_f64 || !src.vec || src.n % 4 != 0)
-        return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_gpass_x3d<CG>), dim3((unsigned)gpass_blocks(cfg, n_pad)), dim3(64 * kDmaWaves), 0, s,
-                         (const uint16_t*)Xt, ldg, cfg.steps_total, cfg.steps_per_split, (float*)Yp, src,
-                         cfg.sym_nbx);
-      return hipGetLastError();
-    }
-    return hipErrorInvalidValue;
   }
   if (cfg.rg != rg_x3(CG, src.d_is_f64 != 0)) return hipErrorInvalidValue;
   if (src.d_is_f64) {
@@ -1155,10 +906,10 @@ GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_h
   GPassCfg c{};
   c.rg = gk == GK_F32S ? rg_x3(l_pad / 16, d8) : (from_d ? rg_fd(gk, l_pad / 16, d8) : rg_for(gk, l_pad / 16));
   c.bm = 64 * c.rg;
-  if (gk == GK_F32S && dma_ok && sym && from_d && !d8 && l_pad <= kDmaMaxL && n_pad % (kDmaWaves * 32) == 0) {
-    c.dma = 1;  // k_gpass_x3d: 8 waves of 2 row groups
+  if (gk == GK_F32S && dma_ok && from_d && !d8 && l_pad <= kDmaMaxL && n_pad % split_pass_rows() == 0) {
+    c.dma = 1;  // k_split: 8 waves of 2 row groups
     c.rg = 2;
-    c.bm = kDmaWaves * 32;
+    c.bm = split_pass_rows();
   }
   // bytes per K-value of a step's 128-byte row (the split pass steps 32 K-values, like fp32)
   const int64_t esize = gk == GK_F64 ? 8 : ((gk == GK_F32 || gk == GK_F32S) ? 4 : 2);
@@ -1185,6 +936,16 @@ GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_h
   c.split = (int)split;
   c.steps_per_split = (c.steps_total + split - 1) / split;
   return c;
+}
+
+GPassCfg gpass_config_nodma(const GPassCfg& c, int l_pad, int64_t n_pad, bool d8) {
+  GPassCfg f = c;
+  if (!c.dma) return f;
+  f.dma = 0;
+  f.rg = rg_x3(l_pad / 16, d8);
+  f.bm = 64 * f.rg;
+  if (f.sym) f.sym_nbx = (n_pad / f.bm + 7) / 8;
+  return f;
 }
 
 hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const void* Xt, int l_pad,

@@ -1,0 +1,412 @@
+// fp32 G-passes on bf16 MFMA with both operands as exact three-term bf16
+// splits (Sec. 3.2-3.3: the products Y = G X of the range finder and of the
+// projection), streamed from the fp32 distance matrix D and recentred on the
+// fly (Sec. 6.2, step 1), software-pipelined for gfx950.
+//
+// Arithmetic (the same as k_gpass_x3): an fp32 value a is the exact sum
+// a0 + a1 + a2 of three bf16 terms (each rounded to nearest even); the six
+// products a_p b_q with p + q <= 2 are accumulated in fp32, the three
+// dropped ones are below 2^-22 |a b|.  Three modes:
+//   kFull  Y = G X over all of D, gamma = fma(-1/2, fl32(d^2), hc_k + hr_i)
+//          with hc_k = fl32(c_k / 2), hr_i = fl32((r_i - m) / 2);
+//   kSym   the projection's symmetric pass, 2 (W o G) X over the upper
+//          triangle of D (W = 1 above, 1/2 on, 0 below the diagonal);
+//   kWrite the fused centring write: gamma in fp64 as in the centring
+//          equation, g = fl32(gamma) stored as bf16(g) into G (zero outside
+//          n x n) and split for the first range pass.
+//
+// Organisation (512 threads = 8 waves x 32 rows, 256 rows per workgroup,
+// one workgroup per CU, steps of 32 K-values):
+//   * every wave streams its own 32 rows of D into a three-stage LDS ring
+//     with global-to-LDS loads (global_load_lds_dwordx4: lane l's 16 bytes
+//     land at the instruction's LDS address + 16 l), issued three steps
+//     before the step they feed, and reads them back in its own lane order;
+//   * the X tile of a step (three bf16 planes, 192 bytes per row), and with
+//     it the recentring terms of the following step (c_k / 2, or c_k in
+//     fp64), are loaded the same way into one of two LDS buffers shared by
+//     the eight waves; the tile is swizzled so that 16 consecutive rows read
+//     distinct banks;
+//   * the split A operands of step st + 1 are computed during step st, in
+//     slices placed between the MFMAs of step st, so that the recentring
+//     and splitting VALU work runs in the MFMA shadow rather than between
+//     the steps;
+//   * one workgroup barrier per step, without a memory fence (which would
+//     also wait for the D loads in flight): after it the next X tile is
+//     complete and the current one is no longer read.
+// Every LDS buffer is its own __shared__ array and the step loop is unrolled
+// six ways (2 X buffers x 3 ring stages), so each LDS access names a fixed
+// array and the compiler's wait counts stay as precise as the explicit ones.
+// Requires fp32 D, n % 4 == 0, a 16-byte aligned D and l_pad <= 128.
+#include <type_traits>
+
+#include "mds_internal.h"
+
+namespace mds {
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v_t __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gbl_void_t;
+
+enum SplitMode { kFull = 0, kSym = 1, kWrite = 2 };
+
+constexpr int kWaves = 8;
+constexpr int kRG = 2;                  // 16-row groups per wave
+constexpr int kBK = 32;                 // K-values per step
+constexpr int kBM = kWaves * kRG * 16;  // 256 rows per workgroup
+constexpr int kAux = 256;               // recentring terms carried with an X tile (32 doubles)
+
+// 16 bytes per lane from a buffer resource at byte offset voff into LDS at
+// l + 16 lane (buffer_load_dwordx4 ... lds).  Offsets at or past the
+// resource's size read zeros, which bounds every read by the buffer.
+__device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t r, uint32_t voff, void* l) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)l, 16, voff, 0, 0, 0);
+}
+
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit elements (gfx9 family)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRsrcWord3);
+}
+
+__device__ __forceinline__ uint32_t bf16x2_bits(f32x2 v) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2v_t));
+}
+
+// Three-term split of 4 floats into dwords 2 half, 2 half + 1 of the planes.
+__device__ __forceinline__ void split3_4(const float (&g)[4], u32x4 (&w)[3], int half) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const f32x2 v = {g[2 * h], g[2 * h + 1]};
+    const bf16x2v_t v0 = __builtin_convertvector(v, bf16x2v_t);
+    const f32x2 r1 = v - __builtin_convertvector(v0, f32x2);
+    const bf16x2v_t v1 = __builtin_convertvector(r1, bf16x2v_t);
+    const f32x2 r2 = r1 - __builtin_convertvector(v1, f32x2);
+    const bf16x2v_t v2 = __builtin_convertvector(r2, bf16x2v_t);
+    w[0][2 * half + h] = __builtin_bit_cast(uint32_t, v0);
+    w[1][2 * half + h] = __builtin_bit_cast(uint32_t, v1);
+    w[2][2 * half + h] = __builtin_bit_cast(uint32_t, v2);
+  }
+}
+
+__device__ __forceinline__ void mma(floatx4_t& c, const u32x4& a, const u32x4& b) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
+                                              0, 0, 0);
+}
+
+template <int CG, int MODE>
+__global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X3, int64_t ldg, int split,
+                                                  int64_t steps_total, int64_t steps_per_split,
+                                                  float* __restrict__ Ypart, GPassDSrc src, int64_t sym_nbx,
+                                                  uint16_t* __restrict__ Gw) {
+  constexpr bool SYM = MODE == kSym;
+  constexpr bool WG = MODE == kWrite;
+  constexpr int LPAD = CG * 16;
+  constexpr int XINS = CG * 3;                          // 1 KB loads per X step tile
+  constexpr int XBYTES = XINS * 1024 + kAux;
+  constexpr int DSTAGE = kRG * 2 * 1024;               // one wave's D stage (32 rows x 32 fp32)
+  constexpr int64_t kStepsPerBlock = kBM / kBK;
+  using CT = typename std::conditional<WG, double, float>::type;  // recentring term per K-value
+  constexpr int kPieces = kBK * (int)sizeof(CT) / 16;              // 16-byte pieces of a step's terms
+  constexpr int NCP = (CG + 1) / 2;                                // column-group pairs per step
+  __shared__ __attribute__((aligned(16))) unsigned char xs0[XBYTES];
+  __shared__ __attribute__((aligned(16))) unsigned char xs1[XBYTES];
+  __shared__ __attribute__((aligned(16))) unsigned char ds0[kWaves * DSTAGE];
+  __shared__ __attribute__((aligned(16))) unsigned char ds1[kWaves * DSTAGE];
+  __shared__ __attribute__((aligned(16))) unsigned char ds2[kWaves * DSTAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t bid = blockIdx.x;
+  int s;
+  int64_t mb, st0, st1;
+  if constexpr (SYM) {  // work item (row block, K split) clipped to the triangle
+    const int64_t loc = bid >> 3;
+    s = (int)(loc / sym_nbx);
+    mb = (loc % sym_nbx) * 8 + (bid & 7);
+    const int64_t diag0 = mb * kStepsPerBlock;
+    st0 = (int64_t)s * steps_per_split;
+    st1 = (st0 + steps_per_split < steps_total) ? st0 + steps_per_split : steps_total;
+    if (diag0 > st0) st0 = diag0;
+    if (diag0 >= steps_total || st0 >= st1) return;  // empty item: no partial written
+  } else {
+    const uint32_t b32 = (uint32_t)blockIdx.x;
+    s = (int)(b32 % (uint32_t)split);
+    mb = (int64_t)(b32 / (uint32_t)split);
+    st0 = (int64_t)s * steps_per_split;
+    st1 = (st0 + steps_per_split < steps_total) ? st0 + steps_per_split : steps_total;
+    // (never taken: every split holds a step.  Stating it lets the compiler
+    // see a loop that runs at least once, which keeps the accumulators in
+    // place instead of spilling them.)
+    if (st0 >= st1) return;
+  }
+  const int64_t diag_end = (mb + 1) * kStepsPerBlock;
+  const int64_t row0 = mb * kBM + (int64_t)wave * (kRG * 16);
+
+  floatx4_t acc[kRG][CG];
+#pragma unroll
+  for (int rg = 0; rg < kRG; ++rg)
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[rg][cg][e] = 0.0f;
+
+  const float* Dp = reinterpret_cast<const float*>(src.D);
+  const int64_t n = src.n;
+  const double mval = src.m[0];
+  float ri[kRG];   // hr_i = fl32((r_i - m) / 2) (symmetric mode: 2 hr_i, exact)
+  double rd[kRG];  // fused write: r_i
+#pragma unroll
+  for (int rg = 0; rg < kRG; ++rg) {
+    const int64_t i = row0 + rg * 16 + (lane & 15);
+    const float h = (i < n) ? (float)(0.5 * (src.r[i] - mval)) : 0.0f;
+    ri[rg] = SYM ? h + h : h;
+    rd[rg] = (WG && i < n) ? src.r[i] : 0.0;
+  }
+  // Buffer resources (32-bit offsets, reads past the end return zeros):
+  //   this workgroup's rows of D (rows >= n read zeros; a row's columns >= n
+  //   run into the next row, finite values that meet zero rows of X or are
+  //   masked in the fused write), the split operand X, and the recentring
+  //   terms (fl32(c_k / 2), ldg zero-padded entries, or c_k, n entries)
+  const int64_t blk_rows = n - mb * kBM < kBM ? (n - mb * kBM > 0 ? n - mb * kBM : 0) : kBM;
+  const __amdgpu_buffer_rsrc_t rD = make_rsrc(Dp + mb * kBM * n, blk_rows * n * 4);
+  const __amdgpu_buffer_rsrc_t rX = make_rsrc(X3, (int64_t)LPAD * ldg * 6);
+  const __amdgpu_buffer_rsrc_t rC =
+      WG ? make_rsrc(src.c, n * 8) : make_rsrc(src.hc, ldg * 4);
+  // per-lane offsets of step 0: D pieces (row group, half), X tile pieces
+  uint32_t d_off[kRG][2];
+#pragma unroll
+  for (int rg = 0; rg < kRG; ++rg)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      d_off[rg][h] = (uint32_t)((((int64_t)wave * (kRG * 16) + rg * 16 + (lane & 15)) * n + (lane >> 4) * 8 + h * 4) * 4);
+  constexpr int XPW = (XINS + kWaves - 1) / kWaves;  // X tile loads per wave
+  uint32_t x_off[XPW];
+#pragma unroll
+  for (int u = 0; u < XPW; ++u) {
+    const int q = wave + u * kWaves;
+    const int S = q * 64 + lane;
+    const int p = S / (LPAD * 4), rem = S % (LPAD * 4);
+    const int row = rem >> 2, kg = (rem & 3) ^ ((row >> 2) & 3);
+    x_off[u] = (uint32_t)((int64_t)row * ldg * 6 + p * 64 + kg * 16);
+  }
+
+  // D of step st into stage dd: this wave's rows, 16 bytes per lane per (row
+  // group, half)
+  auto dma_d = [&](int64_t st, unsigned char (&dd)[kWaves * DSTAGE]) {
+#pragma unroll
+    for (int rg = 0; rg < kRG; ++rg)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        dma16(rD, d_off[rg][h] + (uint32_t)st * (kBK * 4), &dd[wave * DSTAGE + (rg * 2 + h) * 1024]);
+  };
+  // recentring terms of step stc into the aux area of xd (last wave, one
+  // 16-byte piece per lane)
+  auto dma_aux = [&](int64_t stc, unsigned char (&xd)[XBYTES]) {
+    if (wave == kWaves - 1 && lane < kPieces)
+      dma16(rC, (uint32_t)(stc * kBK * (int)sizeof(CT)) + lane * 16, &xd[XINS * 1024]);
+  };
+  // X tile of step st: slot S = q * 64 + lane holds plane p, row, K-group kg
+  // at S = p * 4 LPAD + 4 row + (kg ^ ((row >> 2) & 3)); then the terms of stc
+  auto dma_x = [&](int64_t st, int64_t stc, unsigned char (&xd)[XBYTES]) {
+#pragma unroll
+    for (int u = 0; u < XPW; ++u) {
+      const int q = wave + u * kWaves;
+      if (XINS % kWaves != 0 && q >= XINS) break;
+      dma16(rX, x_off[u] + (uint32_t)st * 192, &xd[q * 1024]);
+    }
+    dma_aux(stc, xd);
+  };
+
+  using DBuf = unsigned char[kWaves * DSTAGE];
+  using XBuf = unsigned char[XBYTES];
+  // Slice `part` (row group part / 2, K-values 4 (part % 2) .. + 3 of the
+  // lane's 8) of the split A operands of step st, from D in stage dd and the
+  // terms in the aux area of xa.
+  auto split_slice = [&](int part, int64_t st, const DBuf& dd, const XBuf& xa, u32x4 (&w)[kRG][3]) {
+#pragma clang fp contract(off)
+    const int rg = part >> 1, half = part & 1;
+    const u32x4 dw = *reinterpret_cast<const u32x4*>(&dd[wave * DSTAGE + (rg * 2 + half) * 1024 + lane * 16]);
+    float dv[4];
+    __builtin_memcpy(dv, &dw, 16);
+    const int kk = (lane >> 4) * 8 + half * 4;  // K-value of dv[0] within the step
+    CT cv[4];
+    __builtin_memcpy(cv, &xa[XINS * 1024 + kk * sizeof(CT)], 4 * sizeof(CT));
+    const int64_t i = row0 + rg * 16 + (lane & 15);
+    float g[4];
+    if constexpr (WG) {
+      const int64_t k0 = st * kBK + kk;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double d = (double)dv[t];
+        const double e = ((d * d - cv[t]) - rd[rg]) + mval;
+        g[t] = (i < n && k0 + t < n) ? (float)(-0.5 * e) : 0.0f;
+      }
+      uint2 gw;
+      gw.x = bf16x2_bits(f32x2{g[0], g[1]});
+      gw.y = bf16x2_bits(f32x2{g[2], g[3]});
+      *reinterpret_cast<uint2*>(Gw + i * ldg + k0) = gw;
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float d2 = dv[t] * dv[t];
+        const float c = SYM ? cv[t] + cv[t] : cv[t];
+        g[t] = __builtin_fmaf(SYM ? -1.0f : -0.5f, d2, c + ri[rg]);
+      }
+      if (SYM && st < diag_end) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int64_t j = st * kBK + kk + t;
+          g[t] = j > i ? g[t] : (j == i ? 0.5f * g[t] : 0.0f);
+        }
+      }
+    }
+    split3_4(g, w[rg], half);
+  };
+
+  u32x4 wA[kRG][3], wB[kRG][3];
+  // prologue: X(st0) with the terms of st0 + 1, D of the first three steps,
+  // the terms of st0 (into the other buffer's aux area) and the split of st0
+  const int64_t last = st1 - 1;
+  dma_x(st0, st0 + 1 < st1 ? st0 + 1 : last, xs0);
+  dma_aux(st0, xs1);
+  dma_d(st0, ds0);
+  dma_d(st0 + 1 < st1 ? st0 + 1 : last, ds1);
+  dma_d(st0 + 2 < st1 ? st0 + 2 : last, ds2);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  __syncthreads();
+#pragma unroll
+  for (int part = 0; part < 4; ++part) split_slice(part, st0, ds0, xs1, wA);
+  __syncthreads();  // every wave has read the terms in xs1 before it is reloaded
+
+  // One step: X(st) in xr (with the terms of st + 1), D(st + 1) in dn; the
+  // loads of X(st + 1) (+ terms of st + 2) go to xw and D(st + 3) to dw;
+  // wc holds the split of st, wn receives the split of st + 1.  The loads are
+  // issued on every step (clamped to the last step at the end), so that the
+  // wait counts below are the same on every path.
+  auto step = [&](int64_t st, XBuf& xr, XBuf& xw, DBuf& dn, DBuf& dw, u32x4 (&wc)[kRG][3],
+                  u32x4 (&wn)[kRG][3]) {
+    const int64_t s1 = st + 1 < st1 ? st + 1 : last;
+    const int64_t s2 = st + 2 < st1 ? st + 2 : last;
+    const int64_t s3 = st + 3 < st1 ? st + 3 : last;
+    dma_x(s1, s2, xw);
+    dma_d(s3, dw);
+    constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+    for (int cp = 0; cp < NCP; ++cp) {
+      // one column-group pair at a time: its B operands, its share of the next
+      // split and its MFMAs are scheduled together (hoisting the loads of all
+      // pairs to the top of the step would need four times the B registers)
+      __builtin_amdgcn_sched_barrier(0);
+      const int cg0 = 2 * cp;
+      u32x4 bb[2][3];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (cg0 + h < CG) {
+          const int row = (cg0 + h) * 16 + (lane & 15);
+          const int kgs = (lane >> 4) ^ ((row >> 2) & 3);
+#pragma unroll
+          for (int p = 0; p < 3; ++p)
+            bb[h][p] = *reinterpret_cast<const u32x4*>(&xr[(p * LPAD * 4 + row * 4 + kgs) * 16]);
+        }
+      // this pair's share of the next step's split (slices spread over the
+      // pairs).  On the last step s1 is clamped to that step: the slice is
+      // recomputed from the same data (the loads are clamped alike), which
+      // rewrites the fused write's G entries with the same values.
+      // (a scheduling region of its own: the other wave on the SIMD keeps the
+      // MFMA pipe busy meanwhile, and the registers of the slice are not
+      // mixed into the MFMA sequence)
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int part = (cp * 4) / NCP; part < ((cp + 1) * 4) / NCP; ++part) split_slice(part, s1, dn, xr, wn);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          if (cg0 + h < CG)
+#pragma unroll
+            for (int rg = 0; rg < kRG; ++rg) mma(acc[rg][cg0 + h], wc[rg][PA[pr]], bb[h][PB[pr]]);
+    }
+    // X(st + 1) and its terms complete (D(st + 3), issued last, may still run)
+    __builtin_amdgcn_s_waitcnt(0x0F70 | kRG * 2);  // vmcnt(4)
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);  // steps are scheduled one at a time (register pressure)
+  };
+  // X(st) in buffer (st - st0) % 2, D(st) in stage (st - st0) % 3, the split of
+  // st in wA or wB by (st - st0) % 2: six steps per trip keep every array static
+  for (int64_t st = st0; st < st1; st += 6) {
+    step(st, xs0, xs1, ds1, ds0, wA, wB);
+    if (st + 1 >= st1) break;
+    step(st + 1, xs1, xs0, ds2, ds1, wB, wA);
+    if (st + 2 >= st1) break;
+    step(st + 2, xs0, xs1, ds0, ds2, wA, wB);
+    if (st + 3 >= st1) break;
+    step(st + 3, xs1, xs0, ds1, ds0, wB, wA);
+    if (st + 4 >= st1) break;
+    step(st + 4, xs0, xs1, ds2, ds1, wA, wB);
+    if (st + 5 >= st1) break;
+    step(st + 5, xs1, xs0, ds0, ds2, wB, wA);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // no load outstanding at exit
+
+#pragma unroll
+  for (int rg = 0; rg < kRG; ++rg) {
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg) {
+      const int col = cg * 16 + (lane & 15);
+      float* dst = Ypart + ((int64_t)s * LPAD + col) * ldg + row0 + rg * 16;
+      const int64_t i4 = row0 + rg * 16 + 4 * (lane >> 4);
+      float4 o = make_float4(acc[rg][cg][0], acc[rg][cg][1], acc[rg][cg][2], acc[rg][cg][3]);
+      if (i4 + 3 >= n) {
+        o.x = i4 < n ? o.x : 0.0f;
+        o.y = i4 + 1 < n ? o.y : 0.0f;
+        o.z = i4 + 2 < n ? o.z : 0.0f;
+        o.w = i4 + 3 < n ? o.w : 0.0f;
+      }
+      *reinterpret_cast<float4*>(dst + 4 * (lane >> 4)) = o;
+    }
+  }
+}
+
+template <int CG>
+hipError_t launch_cg(int mode, const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t blocks, void* Yp,
+                     const GPassDSrc& src, void* Gw, hipStream_t s) {
+  const dim3 grid((unsigned)blocks), block(64 * kWaves);
+  if (mode == kSym)
+    hipLaunchKernelGGL((k_split<CG, kSym>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split, cfg.steps_total,
+                       cfg.steps_per_split, (float*)Yp, src, cfg.sym_nbx, (uint16_t*)nullptr);
+  else if (mode == kWrite)
+    hipLaunchKernelGGL((k_split<CG, kWrite>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split,
+                       cfg.steps_total, cfg.steps_per_split, (float*)Yp, src, cfg.sym_nbx, (uint16_t*)Gw);
+  else
+    hipLaunchKernelGGL((k_split<CG, kFull>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split,
+                       cfg.steps_total, cfg.steps_per_split, (float*)Yp, src, cfg.sym_nbx, (uint16_t*)nullptr);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int split_pass_rows() { return kBM; }
+
+hipError_t launch_split_pass(const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t blocks, void* Yp,
+                             const GPassDSrc& src, void* Gw, hipStream_t s) {
+  if (!src.D || src.d_is_f64 || !src.vec || src.n % 4 != 0 || cfg.bm != kBM || l_pad % 16 != 0 || l_pad > 128)
+    return hipErrorInvalidValue;
+  if (Gw && cfg.sym) return hipErrorInvalidValue;
+  const int mode = cfg.sym ? kSym : (Gw ? kWrite : kFull);
+  switch (l_pad / 16) {
+#define MDS_CG(N) \
+  case N: return launch_cg<N>(mode, Xt, ldg, cfg, blocks, Yp, src, Gw, s);
+    MDS_CG(1) MDS_CG(2) MDS_CG(3) MDS_CG(4) MDS_CG(5) MDS_CG(6) MDS_CG(7) MDS_CG(8)
+#undef MDS_CG
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace mds

@@ -129,7 +129,8 @@ void configure(mds_plan_s* P) {
     const int64_t rows = P->n_pad / c0.bm;
     if (rows < 256) range_split = (768 + rows - 1) / rows;
   }
-  P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, (int)range_split, !stores_g(P->form), false, d8);
+  P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, (int)range_split, !stores_g(P->form), false, d8,
+                        P->gk == GK_F32S && P->n % 4 == 0);
   const int ps = o.proj_split ? o.proj_split : o.gpass_split;
   const bool psym = (o.flags & MDS_FLAG_FULL_PROJECTION) == 0;
   P->ref_cfg = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, ps, true, psym, d8, P->n % 4 == 0);
@@ -139,13 +140,13 @@ void configure(mds_plan_s* P) {
   P->needs_g = stores_g(o.form) && !(P->refine && P->q == 0);
   if (P->refine)
     P->fcfg = gpass_config(GK_F32S, P->l_pad, P->n_pad, P->ldg, o.f32_split ? o.f32_split : o.gpass_split, true,
-                           false, d8);
+                           false, d8, P->n % 4 == 0);
   // bf16 form on fp32 D: the centring write is fused with the first range
   // pass (an fp32 split pass when refining, else a bf16 pass)
   P->fused = o.form == MDS_FORM_BF16 && !d8 && P->needs_g;
   if (P->fused)
     P->wcfg = gpass_config(P->refine ? GK_F32S : GK_BF16, P->l_pad, P->n_pad, P->ldg,
-                           o.write_split ? o.write_split : o.gpass_split, true, false, false);
+                           o.write_split ? o.write_split : o.gpass_split, true, false, false, P->n % 4 == 0);
   layout(P);
 }
 
@@ -246,8 +247,9 @@ GPassDSrc make_src(mds_plan_s* P, int gk, bool from_d, const void* D);
 mds_status gpass(mds_plan_s* P, hipStream_t s, int gk, const GPassCfg& cfg0, bool from_d, const void* D, void* Gw,
                  int phase) {
   const GPassDSrc src = make_src(P, gk, from_d, D);
-  // the projection's LDS-ring kernel needs a 16-byte aligned D
-  const GPassCfg& cfg = (&cfg0 == &P->ref_cfg && P->ref_cfg.dma && !src.vec) ? P->ref_cfg_alt : cfg0;
+  // the LDS-ring split kernel needs a 16-byte aligned D: else the same split
+  // with the register-prefetch kernel
+  const GPassCfg cfg = src.vec ? cfg0 : gpass_config_nodma(cfg0, P->l_pad, P->n_pad, P->d_dtype == MDS_DTYPE_F64);
   {
     PhaseTimer tm(P, s, phase);
     MDS_TRY(launch_gpass(gk, Gw ? Gw : (from_d ? nullptr : P->at<void>(P->G)), P->ldg, P->n_pad,
@@ -621,12 +623,15 @@ mds_status mds_autotune(mds_plan_t P, const void* D, void* stream, mds_tune_resu
   };
   auto cfg_of = [&](int kind, int split) {
     if (kind == kRange)
-      return gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, split, !stores_g(P->form), false, d8);
+      return gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, split, !stores_g(P->form), false, d8,
+                          P->gk == GK_F32S && P->n % 4 == 0 && (uintptr_t)D % 16 == 0);
     if (kind == kProj)
       return gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, split, true, sym, d8,
                           P->n % 4 == 0 && (uintptr_t)D % 16 == 0);
-    if (kind == kWrite) return gpass_config(gk_of(kWrite), P->l_pad, P->n_pad, P->ldg, split, true, false, false);
-    return gpass_config(GK_F32S, P->l_pad, P->n_pad, P->ldg, split, true, false, d8);
+    const bool dma_ok = P->n % 4 == 0 && (uintptr_t)D % 16 == 0;
+    if (kind == kWrite)
+      return gpass_config(gk_of(kWrite), P->l_pad, P->n_pad, P->ldg, split, true, false, false, dma_ok);
+    return gpass_config(GK_F32S, P->l_pad, P->n_pad, P->ldg, split, true, false, d8, dma_ok);
   };
   // workspace sized for the largest candidate's partials
   size_t ymax = 0;

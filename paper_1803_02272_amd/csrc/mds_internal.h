@@ -91,15 +91,15 @@ struct GPassCfg {
   int64_t steps_total, steps_per_split;
   int64_t sym_nbx;             // row blocks per XCD (symmetric mode)
   int64_t sym_cols_per_split;  // K columns per split (symmetric mode)
-  int dma;                     // split pass through the LDS ring (k_gpass_x3d): fp32 D, n % 4 == 0, aligned D
+  int dma;                     // split pass through the LDS ring (k_split): fp32 D, n % 4 == 0, aligned D
 };
 // sym (recentring passes only): the projection's symmetric mode, see k_gpass.
 // d8: D holds fp64 (recentring passes keep more raw values in registers).
 // gk == GK_BF16 with from_d: the fused centring write and first range pass
 // on bf16 MFMA; gk == GK_F32S with a G argument: the fused centring write and
 // an fp32 first range pass (three-term split).
-// dma_ok (GK_F32S, symmetric): n % 4 == 0 and D 16-byte aligned, so the pass
-// may stream D through LDS (needs the same alignment at launch).
+// dma_ok (GK_F32S): n % 4 == 0 and D 16-byte aligned, so the pass may stream
+// D through LDS (needs the same alignment at launch).
 GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d, bool sym,
                       bool d8, bool dma_ok = false);
 // With D != nullptr the A operand is recentred on the fly from D (ld = n)
@@ -122,7 +122,17 @@ struct GPassDSrc {
   int vec = 0;
   int d_is_f64 = 0;
 };
+// The same pass (split, K ranges, summation order) with the register-prefetch
+// kernel instead of the LDS-ring split kernel, for a D that is not 16-byte
+// aligned.
+GPassCfg gpass_config_nodma(const GPassCfg& c, int l_pad, int64_t n_pad, bool d8);
 int64_t gpass_blocks(const GPassCfg& cfg, int64_t n_pad);
+// The pipelined split pass (fp32 D, n % 4 == 0, 16-byte aligned D, l_pad <=
+// 128; cfg.dma configurations): full pass, symmetric projection, or with Gw
+// the fused centring write.  split_pass_rows(): rows per workgroup.
+int split_pass_rows();
+hipError_t launch_split_pass(const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t blocks, void* Yp,
+                             const GPassDSrc& src, void* Gw, hipStream_t s);
 hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const void* Xt, int l_pad,
                         const GPassCfg& cfg, void* Ypart, const GPassDSrc& src, hipStream_t s);
 // Y (fp64, l_pad x ldg) = sum_s Ypart[s] in split order (symmetric mode:
