@@ -272,21 +272,33 @@ def gram_entries(d_vals, r_i, c_j, m):
 # Storage roundings of the arithmetic forms
 # ---------------------------------------------------------------------------
 
+def _bf16_of_f32(f: np.ndarray) -> np.ndarray:
+    """float32 array -> nearest-even bfloat16 values, as float32."""
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + np.uint64(0x7FFF) + ((u >> np.uint64(16)) & np.uint64(1))) >> np.uint64(16)).astype(np.uint32)
+    return (r << np.uint32(16)).view(np.float32)
+
+
 def round_to(x, dtype: str) -> np.ndarray:
     """Round float64 values to the storage type of a form and return them as
     float64: 'f64' keeps them, 'f32' rounds to nearest even, 'bf16' rounds to
-    float32 and then to bfloat16 (8 significant bits), both nearest even."""
+    float32 and then to bfloat16 (8 significant bits), both nearest even;
+    'bf16x2' is the sum of the first two terms of the bfloat16 expansion of
+    the float32 value f: b0 = bf16(f), b1 = bf16(f - b0) (f - b0 is exact in
+    float32), about 16 significant bits."""
     x = np.asarray(x, dtype=np.float64)
     if dtype == "f64":
         return x.copy()
     f = x.astype(np.float32)
     if dtype == "f32":
         return f.astype(np.float64)
-    if dtype != "bf16":
-        raise ValueError(dtype)
-    u = f.view(np.uint32).astype(np.uint64)
-    r = ((u + np.uint64(0x7FFF) + ((u >> np.uint64(16)) & np.uint64(1))) >> np.uint64(16)).astype(np.uint32)
-    return (r << np.uint32(16)).view(np.float32).astype(np.float64)
+    if dtype == "bf16":
+        return _bf16_of_f32(f).astype(np.float64)
+    if dtype == "bf16x2":
+        b0 = _bf16_of_f32(f)
+        b1 = _bf16_of_f32((f - b0).astype(np.float32))
+        return b0.astype(np.float64) + b1.astype(np.float64)
+    raise ValueError(dtype)
 
 
 E4M3_MAX = 448.0  # largest finite OCP FP8 E4M3 value (1.75 * 2^8)
@@ -339,17 +351,19 @@ def fp8_operand(G: np.ndarray) -> np.ndarray:
 
 # Dtype of (G, X) in the range passes and in the projection pass of each
 # form.  The low-precision forms ("bf16", "fp8") run the first and the last
-# range pass in fp32 and only the passes between them on the stored
-# low-precision G (the sketch of Omega and the final basis then carry no
-# bf16/fp8 rounding of G); "bf16_all" and "fp8_all" run every range pass on
-# the stored G.  The projection is fp32 in all four low-precision variants
-# (the fp32 "refinement" pass).
+# range pass with both operands to about 16 significant bits (two-term
+# bfloat16 expansions of their float32 values) and only the passes between
+# them on the stored low-precision G (the sketch of Omega and the final basis
+# then carry no bf16/fp8 rounding of G); "bf16_all" and "fp8_all" run every
+# range pass on the stored G.  The projection is fp32 in all four
+# low-precision variants (the fp32 "refinement" pass).
 _F32 = ("f32", "f32")
+_X2 = ("bf16x2", "bf16x2")
 FORMS = {
     "fp64": {"first": ("f64", "f64"), "range": ("f64", "f64"), "last": ("f64", "f64"), "proj": ("f64", "f64")},
     "fp32": {"first": _F32, "range": _F32, "last": _F32, "proj": _F32},
-    "bf16": {"first": _F32, "range": ("bf16", "bf16"), "last": _F32, "proj": _F32},
-    "fp8": {"first": _F32, "range": ("fp8blk", "bf16"), "last": _F32, "proj": _F32},
+    "bf16": {"first": _X2, "range": ("bf16", "bf16"), "last": _X2, "proj": _F32},
+    "fp8": {"first": _X2, "range": ("fp8blk", "bf16"), "last": _X2, "proj": _F32},
     "bf16_all": {"first": ("bf16", "bf16"), "range": ("bf16", "bf16"), "last": ("bf16", "bf16"), "proj": _F32},
     "fp8_all": {"first": ("fp8blk", "bf16"), "range": ("fp8blk", "bf16"), "last": ("fp8blk", "bf16"),
                 "proj": _F32},

@@ -54,6 +54,11 @@ def _round_t(x, dtype):
         return x.to(torch.float32).to(torch.float64)
     if dtype == "bf16":
         return x.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+    if dtype == "bf16x2":  # first two terms of the bfloat16 expansion of the float32 value
+        f = x.to(torch.float32)
+        b0 = f.to(torch.bfloat16).to(torch.float32)
+        b1 = (f - b0).to(torch.bfloat16).to(torch.float32)
+        return b0.to(torch.float64) + b1.to(torch.float64)
     raise ValueError(dtype)
 
 

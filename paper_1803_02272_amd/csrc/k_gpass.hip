@@ -537,7 +537,9 @@ __device__ __forceinline__ void split3(const float (&g)[8], u32x4 (&w)[3]) {
 // in fp64 as in the centring equation, g = fl32(gamma) is stored into the
 // bf16 G as bf16(g) (the stored-G value of the bf16 form) and split for the
 // pass, so that the first range pass takes fl32(gamma) itself.
-template <int RG, int CG, typename DT, bool SYM, bool WG = false>
+// NT: terms of the split (3: six products, fp32 accuracy; 2: the first two
+// terms of each operand and three products, a0 b0 + a0 b1 + a1 b0).
+template <int RG, int CG, typename DT, bool SYM, bool WG = false, int NT = 3>
 __global__ __launch_bounds__(256, 2) void k_gpass_x3(const uint16_t* __restrict__ X3, int64_t ldg, int split,
                                                      int64_t steps_total, int64_t steps_per_split,
                                                      float* __restrict__ Ypart, GPassDSrc src, int64_t sym_nbx,
@@ -721,9 +723,12 @@ __global__ __launch_bounds__(256, 2) void k_gpass_x3(const uint16_t* __restrict_
             bb[h][1] = *reinterpret_cast<const u32x4*>(bp + 64);
             bb[h][2] = *reinterpret_cast<const u32x4*>(bp + 128);
           }
-        constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
+        // products smallest first: six for three terms, three for two
+        constexpr int NPR = NT == 3 ? 6 : 3;
+        constexpr int PA[6] = {NT == 3 ? 2 : 1, NT == 3 ? 1 : 0, 0, 1, 0, 0};
+        constexpr int PB[6] = {0, 1, NT == 3 ? 2 : 0, 0, 1, 0};
 #pragma unroll
-        for (int pr = 0; pr < 6; ++pr)
+        for (int pr = 0; pr < NPR; ++pr)
 #pragma unroll
           for (int h = 0; h < NP; ++h)
             if (cg0 + h < CG)
@@ -840,45 +845,53 @@ hipError_t launch_cg(const void* G, int64_t ldg, const void* Xt, const GPassCfg&
   return hipGetLastError();
 }
 
-template <int CG, typename DT, bool SYM, bool WG = false>
+template <int CG, typename DT, bool SYM, bool WG = false, int NT = 3>
 void launch_x3_one(const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t n_pad, void* Yp, const GPassDSrc& src,
                    hipStream_t s, void* Gw = nullptr) {
   constexpr int RG = rg_x3(CG, sizeof(DT) == 8);
-  hipLaunchKernelGGL((k_gpass_x3<RG, CG, DT, SYM, WG>), dim3((unsigned)gpass_blocks(cfg, n_pad)), dim3(256), 0, s,
-                     (const uint16_t*)Xt, ldg, cfg.split, cfg.steps_total, cfg.steps_per_split, (float*)Yp, src,
+  hipLaunchKernelGGL((k_gpass_x3<RG, CG, DT, SYM, WG, NT>), dim3((unsigned)gpass_blocks(cfg, n_pad)), dim3(256), 0,
+                     s, (const uint16_t*)Xt, ldg, cfg.split, cfg.steps_total, cfg.steps_per_split, (float*)Yp, src,
                      cfg.sym_nbx, (uint16_t*)Gw);
 }
 
-template <int CG>
-hipError_t launch_x3_cg(const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t n_pad, void* Yp,
+template <int CG, int NT>
+hipError_t launch_x3_nt(const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t n_pad, void* Yp,
                         const GPassDSrc& src, hipStream_t s, void* Gw) {
-  if (!src.D) return hipErrorInvalidValue;
-  if (cfg.dma) return launch_split_pass(Xt, ldg, CG * 16, cfg, gpass_blocks(cfg, n_pad), Yp, src, Gw, s);
   if (Gw) {  // fused centring write: full pass over fp32 D
     if (cfg.sym || src.d_is_f64 || cfg.rg != rg_x3(CG, false)) return hipErrorInvalidValue;
-    launch_x3_one<CG, float, false, true>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
+    launch_x3_one<CG, float, false, true, NT>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
     return hipGetLastError();
   }
   if (cfg.rg != rg_x3(CG, src.d_is_f64 != 0)) return hipErrorInvalidValue;
+  if (NT == 2 && cfg.sym) return hipErrorInvalidValue;  // the two-term split serves range passes only
   if (src.d_is_f64) {
     if (cfg.sym)
       launch_x3_one<CG, double, true>(Xt, ldg, cfg, n_pad, Yp, src, s);
     else
-      launch_x3_one<CG, double, false>(Xt, ldg, cfg, n_pad, Yp, src, s);
+      launch_x3_one<CG, double, false, false, NT>(Xt, ldg, cfg, n_pad, Yp, src, s);
   } else {
     if (cfg.sym)
       launch_x3_one<CG, float, true>(Xt, ldg, cfg, n_pad, Yp, src, s);
     else
-      launch_x3_one<CG, float, false>(Xt, ldg, cfg, n_pad, Yp, src, s);
+      launch_x3_one<CG, float, false, false, NT>(Xt, ldg, cfg, n_pad, Yp, src, s);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_x3(const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t n_pad, void* Yp,
+template <int CG>
+hipError_t launch_x3_cg(int nt, const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t n_pad, void* Yp,
+                        const GPassDSrc& src, hipStream_t s, void* Gw) {
+  if (!src.D) return hipErrorInvalidValue;
+  if (cfg.dma) return launch_split_pass(nt, Xt, ldg, CG * 16, cfg, gpass_blocks(cfg, n_pad), Yp, src, Gw, s);
+  return nt == 2 ? launch_x3_nt<CG, 2>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw)
+                 : launch_x3_nt<CG, 3>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
+}
+
+hipError_t launch_x3(int nt, const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t n_pad, void* Yp,
                      const GPassDSrc& src, hipStream_t s, void* Gw) {
   switch (l_pad / 16) {
 #define MDS_CG(N) \
-  case N: return launch_x3_cg<N>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
+  case N: return launch_x3_cg<N>(nt, Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
     MDS_CG(1) MDS_CG(2) MDS_CG(3) MDS_CG(4) MDS_CG(5) MDS_CG(6) MDS_CG(7) MDS_CG(8)
     MDS_CG(9) MDS_CG(10) MDS_CG(11) MDS_CG(12) MDS_CG(13) MDS_CG(14) MDS_CG(15) MDS_CG(16)
 #undef MDS_CG
@@ -904,15 +917,15 @@ hipError_t launch_gk(const void* G, int64_t ldg, const void* Xt, int l_pad, cons
 GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d, bool sym,
                       bool d8, bool dma_ok) {
   GPassCfg c{};
-  c.rg = gk == GK_F32S ? rg_x3(l_pad / 16, d8) : (from_d ? rg_fd(gk, l_pad / 16, d8) : rg_for(gk, l_pad / 16));
+  c.rg = gk_split(gk) ? rg_x3(l_pad / 16, d8) : (from_d ? rg_fd(gk, l_pad / 16, d8) : rg_for(gk, l_pad / 16));
   c.bm = 64 * c.rg;
-  if (gk == GK_F32S && dma_ok && from_d && !d8 && l_pad <= kDmaMaxL && n_pad % split_pass_rows() == 0) {
-    c.dma = 1;  // k_split: 8 waves of 2 row groups
+  if (gk_split(gk) && dma_ok && from_d && !d8 && l_pad <= kDmaMaxL && n_pad % split_pass_rows() == 0) {
+    c.dma = 1;  // k_split: 8 waves of 2 row groups, row blocks dealt to XCDs (see sym_nbx)
     c.rg = 2;
     c.bm = split_pass_rows();
   }
   // bytes per K-value of a step's 128-byte row (the split pass steps 32 K-values, like fp32)
-  const int64_t esize = gk == GK_F64 ? 8 : ((gk == GK_F32 || gk == GK_F32S) ? 4 : 2);
+  const int64_t esize = gk == GK_F64 ? 8 : ((gk == GK_F32 || gk_split(gk)) ? 4 : 2);
   c.steps_total = ldg * esize / 128;
   const int64_t row_blocks = n_pad / c.bm;
   if (sym && from_d) {
@@ -935,6 +948,7 @@ GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_h
   if (split < 1) split = 1;
   c.split = (int)split;
   c.steps_per_split = (c.steps_total + split - 1) / split;
+  if (c.dma) c.sym_nbx = (row_blocks + 7) / 8;  // row blocks per XCD
   return c;
 }
 
@@ -958,13 +972,14 @@ hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const
     case GK_FP8:
       if (!src.g8_scales || (cfg.bm > kF8Block) || (kF8Block % cfg.bm)) return hipErrorInvalidValue;
       return launch_gk<GK_FP8>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
-    case GK_F32S: return launch_x3(Xt, ldg, l_pad, cfg, n_pad, Ypart, src, s, const_cast<void*>(G));
+    case GK_F32S: return launch_x3(3, Xt, ldg, l_pad, cfg, n_pad, Ypart, src, s, const_cast<void*>(G));
+    case GK_S2: return launch_x3(2, Xt, ldg, l_pad, cfg, n_pad, Ypart, src, s, const_cast<void*>(G));
     default: return hipErrorInvalidValue;
   }
 }
 
 int64_t gpass_blocks(const GPassCfg& cfg, int64_t n_pad) {
-  return cfg.sym ? 8 * cfg.sym_nbx * cfg.split : (n_pad / cfg.bm) * cfg.split;
+  return (cfg.sym || cfg.dma) ? 8 * cfg.sym_nbx * cfg.split : (n_pad / cfg.bm) * cfg.split;
 }
 
 hipError_t launch_splitk_reduce(int gk, const GPassCfg& cfg, const void* Ypart, int64_t ldg, int64_t elems,

@@ -6,21 +6,27 @@
 // Arithmetic (the same as k_gpass_x3): an fp32 value a is the exact sum
 // a0 + a1 + a2 of three bf16 terms (each rounded to nearest even); the six
 // products a_p b_q with p + q <= 2 are accumulated in fp32, the three
-// dropped ones are below 2^-22 |a b|.  Three modes:
+// dropped ones are below 2^-22 |a b|.  With two terms (NT = 2, range passes)
+// the products are a0 b0 + a0 b1 + a1 b0: both operands to about 16
+// significant bits, the result within about 3 2^-18 |a b| per product, in
+// half the MFMA and much less of the splitting work.  Three modes:
 //   kFull  Y = G X over all of D, gamma = fma(-1/2, fl32(d^2), hc_k + hr_i)
 //          with hc_k = fl32(c_k / 2), hr_i = fl32((r_i - m) / 2);
 //   kSym   the projection's symmetric pass, 2 (W o G) X over the upper
 //          triangle of D (W = 1 above, 1/2 on, 0 below the diagonal);
-//   kWrite the fused centring write: gamma in fp64 as in the centring
-//          equation, g = fl32(gamma) stored as bf16(g) into G (zero outside
-//          n x n) and split for the first range pass.
+//   kWrite the fused centring write: gamma in fp64 from the centring
+//          equation, g = fl32(gamma) stored as bf16(g) into G (the padding
+//          outside n x n is zeroed by a separate small kernel) and split for
+//          the first range pass.
 //
 // Organisation (512 threads = 8 waves x 32 rows, 256 rows per workgroup,
 // one workgroup per CU, steps of 32 K-values):
 //   * every wave streams its own 32 rows of D into a three-stage LDS ring
-//     with global-to-LDS loads (global_load_lds_dwordx4: lane l's 16 bytes
-//     land at the instruction's LDS address + 16 l), issued three steps
-//     before the step they feed, and reads them back in its own lane order;
+//     with buffer-to-LDS loads (lane l's 16 bytes land at the instruction's
+//     LDS address + 16 l), whole 128-byte lines per 8 lanes with the
+//     nontemporal hint, issued three steps before the step they feed; the
+//     pieces of a row are placed in XOR-swizzled slots so that the reads in
+//     the MFMA operand layout are free of bank conflicts;
 //   * the X tile of a step (three bf16 planes, 192 bytes per row), and with
 //     it the recentring terms of the following step (c_k / 2, or c_k in
 //     fp64), are loaded the same way into one of two LDS buffers shared by
@@ -64,6 +70,13 @@ constexpr int kAux = 256;               // recentring terms carried with an X ti
 __device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t r, uint32_t voff, void* l) {
   __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)l, 16, voff, 0, 0, 0);
 }
+// The same with the nontemporal hint, for D: every byte is read once per pass
+// (measured on MI355X for whole 128-byte lines per 8 lanes: 6.5 TB/s with the
+// hint against 5.9 without; lanes that cover half lines reach 5.4 and lose
+// more with it)
+__device__ __forceinline__ void dma16_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff, void* l) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)l, 16, voff, 0, 0, 2);
+}
 
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit elements (gfx9 family)
 
@@ -96,15 +109,16 @@ __device__ __forceinline__ void mma(floatx4_t& c, const u32x4& a, const u32x4& b
                                               0, 0, 0);
 }
 
-template <int CG, int MODE>
+template <int CG, int MODE, int NT>
 __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X3, int64_t ldg, int split,
                                                   int64_t steps_total, int64_t steps_per_split,
                                                   float* __restrict__ Ypart, GPassDSrc src, int64_t sym_nbx,
                                                   uint16_t* __restrict__ Gw) {
   constexpr bool SYM = MODE == kSym;
   constexpr bool WG = MODE == kWrite;
+  static_assert(NT == 3 || (NT == 2 && !SYM), "two-term splits serve the range passes");
   constexpr int LPAD = CG * 16;
-  constexpr int XINS = CG * 3;                          // 1 KB loads per X step tile
+  constexpr int XINS = CG * NT;                         // 1 KB loads per X step tile (NT planes)
   constexpr int XBYTES = XINS * 1024 + kAux;
   constexpr int DSTAGE = kRG * 2 * 1024;               // one wave's D stage (32 rows x 32 fp32)
   constexpr int64_t kStepsPerBlock = kBM / kBK;
@@ -133,15 +147,19 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
     if (diag0 > st0) st0 = diag0;
     if (diag0 >= steps_total || st0 >= st1) return;  // empty item: no partial written
   } else {
-    const uint32_t b32 = (uint32_t)blockIdx.x;
-    s = (int)(b32 % (uint32_t)split);
-    mb = (int64_t)(b32 / (uint32_t)split);
+    // row blocks dealt to XCDs round-robin (block mb on XCD mb % 8), the split
+    // index varying slowest inside an XCD: the workgroups that run together
+    // on an XCD stream the same K range in step, so each X tile is fetched
+    // into that XCD's L2 once and read there by all of them
+    const int64_t loc = bid >> 3;
+    s = (int)(loc / sym_nbx);
+    mb = (loc % sym_nbx) * 8 + (bid & 7);
     st0 = (int64_t)s * steps_per_split;
     st1 = (st0 + steps_per_split < steps_total) ? st0 + steps_per_split : steps_total;
-    // (never taken: every split holds a step.  Stating it lets the compiler
-    // see a loop that runs at least once, which keeps the accumulators in
-    // place instead of spilling them.)
-    if (st0 >= st1) return;
+    // (the second test never holds: every split has a step.  Stating it lets
+    // the compiler see a loop that runs at least once, which keeps the
+    // accumulators in place instead of spilling them.)
+    if (mb * kBM >= ldg || st0 >= st1) return;
   }
   const int64_t diag_end = (mb + 1) * kStepsPerBlock;
   const int64_t row0 = mb * kBM + (int64_t)wave * (kRG * 16);
@@ -158,13 +176,13 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
   const int64_t n = src.n;
   const double mval = src.m[0];
   float ri[kRG];   // hr_i = fl32((r_i - m) / 2) (symmetric mode: 2 hr_i, exact)
-  double rd[kRG];  // fused write: r_i
+  double rd[kRG];  // fused write: (r_i - m) / 2 in fp64
 #pragma unroll
   for (int rg = 0; rg < kRG; ++rg) {
     const int64_t i = row0 + rg * 16 + (lane & 15);
     const float h = (i < n) ? (float)(0.5 * (src.r[i] - mval)) : 0.0f;
     ri[rg] = SYM ? h + h : h;
-    rd[rg] = (WG && i < n) ? src.r[i] : 0.0;
+    rd[rg] = (WG && i < n) ? 0.5 * (src.r[i] - mval) : 0.0;
   }
   // Buffer resources (32-bit offsets, reads past the end return zeros):
   //   this workgroup's rows of D (rows >= n read zeros; a row's columns >= n
@@ -176,13 +194,17 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
   const __amdgpu_buffer_rsrc_t rX = make_rsrc(X3, (int64_t)LPAD * ldg * 6);
   const __amdgpu_buffer_rsrc_t rC =
       WG ? make_rsrc(src.c, n * 8) : make_rsrc(src.hc, ldg * 4);
-  // per-lane offsets of step 0: D pieces (row group, half), X tile pieces
-  uint32_t d_off[kRG][2];
+  // per-lane offsets of step 0.  D: load q (0..3) of a wave covers its rows
+  // 8q .. 8q + 7 as whole 128-byte lines (8 lanes per row); lane l lands at
+  // LDS slot l = 8 (row % 8) + slot and brings piece (16 bytes, 4 K-values)
+  // slot ^ (row % 8) of its row, so that the A-operand reads below, 16 rows
+  // at one K-piece, fall on distinct banks.
+  uint32_t d_off[4];
 #pragma unroll
-  for (int rg = 0; rg < kRG; ++rg)
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-      d_off[rg][h] = (uint32_t)((((int64_t)wave * (kRG * 16) + rg * 16 + (lane & 15)) * n + (lane >> 4) * 8 + h * 4) * 4);
+  for (int q = 0; q < 4; ++q) {
+    const int rr = lane >> 3, piece = (lane & 7) ^ rr;
+    d_off[q] = (uint32_t)((((int64_t)wave * (kRG * 16) + q * 8 + rr) * n + piece * 4) * 4);
+  }
   constexpr int XPW = (XINS + kWaves - 1) / kWaves;  // X tile loads per wave
   uint32_t x_off[XPW];
 #pragma unroll
@@ -194,14 +216,10 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
     x_off[u] = (uint32_t)((int64_t)row * ldg * 6 + p * 64 + kg * 16);
   }
 
-  // D of step st into stage dd: this wave's rows, 16 bytes per lane per (row
-  // group, half)
+  // D of step st into stage dd: this wave's 32 rows x 128 bytes
   auto dma_d = [&](int64_t st, unsigned char (&dd)[kWaves * DSTAGE]) {
 #pragma unroll
-    for (int rg = 0; rg < kRG; ++rg)
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-        dma16(rD, d_off[rg][h] + (uint32_t)st * (kBK * 4), &dd[wave * DSTAGE + (rg * 2 + h) * 1024]);
+    for (int q = 0; q < 4; ++q) dma16_nt(rD, d_off[q] + (uint32_t)st * (kBK * 4), &dd[wave * DSTAGE + q * 1024]);
   };
   // recentring terms of step stc into the aux area of xd (last wave, one
   // 16-byte piece per lane)
@@ -223,51 +241,97 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
 
   using DBuf = unsigned char[kWaves * DSTAGE];
   using XBuf = unsigned char[XBYTES];
-  // Slice `part` (row group part / 2, K-values 4 (part % 2) .. + 3 of the
-  // lane's 8) of the split A operands of step st, from D in stage dd and the
-  // terms in the aux area of xa.
-  auto split_slice = [&](int part, int64_t st, const DBuf& dd, const XBuf& xa, u32x4 (&w)[kRG][3]) {
-#pragma clang fp contract(off)
-    const int rg = part >> 1, half = part & 1;
-    const u32x4 dw = *reinterpret_cast<const u32x4*>(&dd[wave * DSTAGE + (rg * 2 + half) * 1024 + lane * 16]);
+  // A slice of the split A operands of step st: row group part / 2, K-values
+  // 4 (part % 2) .. + 3 of the lane's 8, from D in stage dd and the terms in
+  // the aux area of xa.  It is computed in kSliceOps small operations so that
+  // the step can place them between its MFMAs.
+  struct Slice {
     float dv[4];
-    __builtin_memcpy(dv, &dw, 16);
-    const int kk = (lane >> 4) * 8 + half * 4;  // K-value of dv[0] within the step
     CT cv[4];
-    __builtin_memcpy(cv, &xa[XINS * 1024 + kk * sizeof(CT)], 4 * sizeof(CT));
-    const int64_t i = row0 + rg * 16 + (lane & 15);
     float g[4];
-    if constexpr (WG) {
-      const int64_t k0 = st * kBK + kk;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const double d = (double)dv[t];
-        const double e = ((d * d - cv[t]) - rd[rg]) + mval;
-        g[t] = (i < n && k0 + t < n) ? (float)(-0.5 * e) : 0.0f;
-      }
-      uint2 gw;
-      gw.x = bf16x2_bits(f32x2{g[0], g[1]});
-      gw.y = bf16x2_bits(f32x2{g[2], g[3]});
-      *reinterpret_cast<uint2*>(Gw + i * ldg + k0) = gw;
-    } else {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const float d2 = dv[t] * dv[t];
-        const float c = SYM ? cv[t] + cv[t] : cv[t];
-        g[t] = __builtin_fmaf(SYM ? -1.0f : -0.5f, d2, c + ri[rg]);
-      }
-      if (SYM && st < diag_end) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int64_t j = st * kBK + kk + t;
-          g[t] = j > i ? g[t] : (j == i ? 0.5f * g[t] : 0.0f);
+    bf16x2v_t v[2][NT];  // planes of the two value pairs
+    f32x2 r[2];
+    int64_t i, k0;
+    int rg, half;
+  };
+  constexpr int kSliceOps = 4 + 2 * NT - 2;  // 4 recentring + (NT - 1) split phases per value pair
+  auto slice_load = [&](Slice& S, int part, int64_t st, const DBuf& dd, const XBuf& xa) {
+    S.rg = part >> 1;
+    S.half = part & 1;
+    // this lane's row r of the wave's 32 and K-piece pc (see d_off)
+    const int r = S.rg * 16 + (lane & 15), pc = 2 * (lane >> 4) + S.half;
+    const u32x4 dw = *reinterpret_cast<const u32x4*>(
+        &dd[wave * DSTAGE + (r >> 3) * 1024 + (r & 7) * 128 + ((pc ^ (r & 7)) * 16)]);
+    __builtin_memcpy(S.dv, &dw, 16);
+    const int kk = (lane >> 4) * 8 + S.half * 4;  // K-value of dv[0] within the step
+    __builtin_memcpy(S.cv, &xa[XINS * 1024 + kk * sizeof(CT)], 4 * sizeof(CT));
+    S.i = row0 + S.rg * 16 + (lane & 15);
+    S.k0 = st * kBK + kk;
+  };
+  uint32_t gkeep[kRG][2];  // fused write: bf16 G of the first half of each row group
+  // operation j: 0..3 recentre value j (the fused write stores the four bf16
+  // entries after the last), 4..9 split the two value pairs into the planes
+  auto slice_op = [&](Slice& S, int j, u32x4 (&w)[kRG][NT]) {
+#pragma clang fp contract(off)
+    if (j < 4) {
+      const int t = j;
+      if constexpr (WG) {
+        // gamma = 1/2 (c_k - d^2) + (r_i - m) / 2, the centring equation
+        // rearranged into two fused operations in fp64 (d^2 is exact in
+        // fp64 for an fp32 d); entries outside n x n are zeroed afterwards
+        // (launch_split_zero_pad), their values here are finite and meet
+        // zero rows of Omega
+        const double d = (double)S.dv[t];
+        const double e = __builtin_fma(-d, d, S.cv[t]);
+        S.g[t] = (float)__builtin_fma(0.5, e, rd[S.rg]);
+        if (t == 3) {
+          // the two halves of a row group hold K-values 8j .. 8j + 3 and
+          // 8j + 4 .. 8j + 7 of the lane's row: the first is kept, the
+          // second completes one 16-byte store (4 lanes cover 64 bytes of a row)
+          const uint32_t lo = bf16x2_bits(f32x2{S.g[0], S.g[1]});
+          const uint32_t hi = bf16x2_bits(f32x2{S.g[2], S.g[3]});
+          if (S.half == 0) {
+            gkeep[S.rg][0] = lo;
+            gkeep[S.rg][1] = hi;
+          } else {
+            *reinterpret_cast<uint4*>(Gw + S.i * ldg + S.k0 - 4) = make_uint4(gkeep[S.rg][0], gkeep[S.rg][1], lo, hi);
+          }
         }
+      } else {
+        const float d2 = S.dv[t] * S.dv[t];
+        const float c = SYM ? S.cv[t] + S.cv[t] : S.cv[t];
+        float g = __builtin_fmaf(SYM ? -1.0f : -0.5f, d2, c + ri[S.rg]);
+        if (SYM) {  // weights 1, 1/2, 0 right of, on and left of the diagonal
+          const int64_t jj = S.k0 + t;
+          g = jj > S.i ? g : (jj == S.i ? 0.5f * g : 0.0f);
+        }
+        S.g[t] = g;
+      }
+    } else {
+      const int q = (j - 4) / (NT - 1), ph = (j - 4) % (NT - 1);  // value pair, phase
+      if (ph == 0) {
+        const f32x2 x = {S.g[2 * q], S.g[2 * q + 1]};
+        S.v[q][0] = __builtin_convertvector(x, bf16x2v_t);
+        S.r[q] = x - __builtin_convertvector(S.v[q][0], f32x2);
+      } else if (NT == 3 && ph == 1) {
+        S.v[q][1] = __builtin_convertvector(S.r[q], bf16x2v_t);
+        S.r[q] = S.r[q] - __builtin_convertvector(S.v[q][1], f32x2);
+      }
+      if (ph == NT - 2) {  // last phase: the final term, then the planes
+        S.v[q][NT - 1] = __builtin_convertvector(S.r[q], bf16x2v_t);
+#pragma unroll
+        for (int p = 0; p < NT; ++p) w[S.rg][p][2 * S.half + q] = __builtin_bit_cast(uint32_t, S.v[q][p]);
       }
     }
-    split3_4(g, w[rg], half);
+  };
+  auto split_slice = [&](int part, int64_t st, const DBuf& dd, const XBuf& xa, u32x4 (&w)[kRG][NT]) {
+    Slice S;
+    slice_load(S, part, st, dd, xa);
+#pragma unroll
+    for (int j = 0; j < kSliceOps; ++j) slice_op(S, j, w);
   };
 
-  u32x4 wA[kRG][3], wB[kRG][3];
+  u32x4 wA[kRG][NT], wB[kRG][NT];
   // prologue: X(st0) with the terms of st0 + 1, D of the first three steps,
   // the terms of st0 (into the other buffer's aux area) and the split of st0
   const int64_t last = st1 - 1;
@@ -287,52 +351,75 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
   // wc holds the split of st, wn receives the split of st + 1.  The loads are
   // issued on every step (clamped to the last step at the end), so that the
   // wait counts below are the same on every path.
-  auto step = [&](int64_t st, XBuf& xr, XBuf& xw, DBuf& dn, DBuf& dw, u32x4 (&wc)[kRG][3],
-                  u32x4 (&wn)[kRG][3]) {
+  auto step = [&](int64_t st, XBuf& xr, XBuf& xw, DBuf& dn, DBuf& dw, u32x4 (&wc)[kRG][NT],
+                  u32x4 (&wn)[kRG][NT]) {
     const int64_t s1 = st + 1 < st1 ? st + 1 : last;
     const int64_t s2 = st + 2 < st1 ? st + 2 : last;
     const int64_t s3 = st + 3 < st1 ? st + 3 : last;
     dma_x(s1, s2, xw);
     dma_d(s3, dw);
-    constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
+    // products smallest first: a2 b0, a1 b1, a0 b2, a1 b0, a0 b1, a0 b0 (three
+    // terms) or a1 b0, a0 b1, a0 b0 (two terms)
+    constexpr int NPR = NT == 3 ? 6 : 3;
+    constexpr int PA[6] = {NT == 3 ? 2 : 1, NT == 3 ? 1 : 0, 0, 1, 0, 0};
+    constexpr int PB[6] = {0, 1, NT == 3 ? 2 : 0, 0, 1, 0};
 #pragma unroll
     for (int cp = 0; cp < NCP; ++cp) {
-      // one column-group pair at a time: its B operands, its share of the next
-      // split and its MFMAs are scheduled together (hoisting the loads of all
-      // pairs to the top of the step would need four times the B registers)
-      __builtin_amdgcn_sched_barrier(0);
+      // One column-group pair: its B operands and the inputs of its share of
+      // the next step's split are read first; then its MFMAs are issued in a
+      // fixed order, each followed by one small operation of that share, so
+      // that the SIMD runs the VALU work while the MFMA executes (the two
+      // are independent).  The schedule barriers keep this order.
       const int cg0 = 2 * cp;
-      u32x4 bb[2][3];
+      constexpr int kMaxSl = 4;
+      const int sl0 = (cp * 4) / NCP, sl1 = ((cp + 1) * 4) / NCP;  // slices of this pair
+      __builtin_amdgcn_sched_barrier(0);
+      u32x4 bb[2][NT];
 #pragma unroll
       for (int h = 0; h < 2; ++h)
         if (cg0 + h < CG) {
           const int row = (cg0 + h) * 16 + (lane & 15);
           const int kgs = (lane >> 4) ^ ((row >> 2) & 3);
 #pragma unroll
-          for (int p = 0; p < 3; ++p)
+          for (int p = 0; p < NT; ++p)
             bb[h][p] = *reinterpret_cast<const u32x4*>(&xr[(p * LPAD * 4 + row * 4 + kgs) * 16]);
         }
-      // this pair's share of the next step's split (slices spread over the
-      // pairs).  On the last step s1 is clamped to that step: the slice is
-      // recomputed from the same data (the loads are clamped alike), which
-      // rewrites the fused write's G entries with the same values.
-      // (a scheduling region of its own: the other wave on the SIMD keeps the
-      // MFMA pipe busy meanwhile, and the registers of the slice are not
-      // mixed into the MFMA sequence)
+      Slice S[kMaxSl];
+#pragma unroll
+      for (int sl = 0; sl < kMaxSl; ++sl)
+        if (sl0 + sl < sl1) slice_load(S[sl], sl0 + sl, s1, dn, xr);
       __builtin_amdgcn_sched_barrier(0);
+      const int nops = (sl1 - sl0) * kSliceOps;
+      auto mfmas = [&]() {
 #pragma unroll
-      for (int part = (cp * 4) / NCP; part < ((cp + 1) * 4) / NCP; ++part) split_slice(part, s1, dn, xr, wn);
-      __builtin_amdgcn_sched_barrier(0);
+        for (int pr = 0; pr < NPR; ++pr)
 #pragma unroll
-      for (int pr = 0; pr < 6; ++pr)
+          for (int h = 0; h < 2; ++h)
+            if (cg0 + h < CG)
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-          if (cg0 + h < CG)
+              for (int rg = 0; rg < kRG; ++rg) mma(acc[rg][cg0 + h], wc[rg][PA[pr]], bb[h][PB[pr]]);
+      };
+      auto slices = [&]() {
 #pragma unroll
-            for (int rg = 0; rg < kRG; ++rg) mma(acc[rg][cg0 + h], wc[rg][PA[pr]], bb[h][PB[pr]]);
+        for (int op = 0; op < nops; ++op) slice_op(S[op / kSliceOps], op % kSliceOps, wn);
+      };
+      // The two waves of a SIMD (waves w and w + 4) take the pair's VALU and
+      // MFMA work in opposite orders, so that one wave's splitting runs while
+      // the other's MFMAs execute.
+      if (wave & 4) {
+        slices();
+        __builtin_amdgcn_sched_barrier(0);
+        mfmas();
+      } else {
+        mfmas();
+        __builtin_amdgcn_sched_barrier(0);
+        slices();
+      }
     }
-    // X(st + 1) and its terms complete (D(st + 3), issued last, may still run)
-    __builtin_amdgcn_s_waitcnt(0x0F70 | kRG * 2);  // vmcnt(4)
+    // X(st + 1) and its terms complete; D(st + 3) and, in the fused write,
+    // the kRG stores of G issued after it may still run (stores count in
+    // vmcnt, in issue order with the loads)
+    __builtin_amdgcn_s_waitcnt(0x0F70 | (4 + (WG ? kRG : 0)));  // vmcnt(4) or vmcnt(6)
     __asm__ volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     __asm__ volatile("" ::: "memory");
@@ -374,35 +461,65 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
   }
 }
 
-template <int CG>
+template <int CG, int NT>
 hipError_t launch_cg(int mode, const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t blocks, void* Yp,
                      const GPassDSrc& src, void* Gw, hipStream_t s) {
   const dim3 grid((unsigned)blocks), block(64 * kWaves);
-  if (mode == kSym)
-    hipLaunchKernelGGL((k_split<CG, kSym>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split, cfg.steps_total,
-                       cfg.steps_per_split, (float*)Yp, src, cfg.sym_nbx, (uint16_t*)nullptr);
-  else if (mode == kWrite)
-    hipLaunchKernelGGL((k_split<CG, kWrite>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split,
+  if constexpr (NT == 3) {
+    if (mode == kSym) {
+      hipLaunchKernelGGL((k_split<CG, kSym, 3>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split,
+                         cfg.steps_total, cfg.steps_per_split, (float*)Yp, src, cfg.sym_nbx, (uint16_t*)nullptr);
+      return hipGetLastError();
+    }
+  } else {
+    if (mode == kSym) return hipErrorInvalidValue;
+  }
+  if (mode == kWrite)
+    hipLaunchKernelGGL((k_split<CG, kWrite, NT>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split,
                        cfg.steps_total, cfg.steps_per_split, (float*)Yp, src, cfg.sym_nbx, (uint16_t*)Gw);
   else
-    hipLaunchKernelGGL((k_split<CG, kFull>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split,
+    hipLaunchKernelGGL((k_split<CG, kFull, NT>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split,
                        cfg.steps_total, cfg.steps_per_split, (float*)Yp, src, cfg.sym_nbx, (uint16_t*)nullptr);
   return hipGetLastError();
 }
 
+// Zero the entries of the bf16 G outside n x n (rows >= n, and columns >= n
+// of the rows below n) after the fused centring write.
+__global__ __launch_bounds__(256) void k_zero_pad(uint16_t* __restrict__ G, int64_t n, int64_t n_pad, int64_t ldg) {
+  const int64_t tail = n_pad - n;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t cols_part = n * tail;  // (i < n, k >= n)
+  if (e < cols_part) {
+    G[(e / tail) * ldg + n + e % tail] = 0;
+  } else {
+    const int64_t f = e - cols_part;  // rows >= n, all ldg columns
+    if (f < tail * ldg) G[(n + f / ldg) * ldg + f % ldg] = 0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_split_zero_pad(void* G, int64_t n, int64_t n_pad, int64_t ldg, hipStream_t s) {
+  const int64_t total = n * (n_pad - n) + (n_pad - n) * ldg;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_pad, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (uint16_t*)G, n, n_pad, ldg);
+  return hipGetLastError();
+}
 
 int split_pass_rows() { return kBM; }
 
-hipError_t launch_split_pass(const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t blocks, void* Yp,
-                             const GPassDSrc& src, void* Gw, hipStream_t s) {
-  if (!src.D || src.d_is_f64 || !src.vec || src.n % 4 != 0 || cfg.bm != kBM || l_pad % 16 != 0 || l_pad > 128)
+hipError_t launch_split_pass(int nterms, const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t blocks,
+                             void* Yp, const GPassDSrc& src, void* Gw, hipStream_t s) {
+  if (!src.D || src.d_is_f64 || !src.vec || src.n % 4 != 0 || cfg.bm != kBM || l_pad % 16 != 0 || l_pad > 128 ||
+      (nterms != 2 && nterms != 3))
     return hipErrorInvalidValue;
   if (Gw && cfg.sym) return hipErrorInvalidValue;
   const int mode = cfg.sym ? kSym : (Gw ? kWrite : kFull);
   switch (l_pad / 16) {
-#define MDS_CG(N) \
-  case N: return launch_cg<N>(mode, Xt, ldg, cfg, blocks, Yp, src, Gw, s);
+#define MDS_CG(N)                                                                              \
+  case N:                                                                                      \
+    return nterms == 2 ? launch_cg<N, 2>(mode, Xt, ldg, cfg, blocks, Yp, src, Gw, s)           \
+                       : launch_cg<N, 3>(mode, Xt, ldg, cfg, blocks, Yp, src, Gw, s);
     MDS_CG(1) MDS_CG(2) MDS_CG(3) MDS_CG(4) MDS_CG(5) MDS_CG(6) MDS_CG(7) MDS_CG(8)
 #undef MDS_CG
     default: return hipErrorInvalidValue;

@@ -27,10 +27,11 @@ thread_local std::string g_last_error;
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 // bytes per element of G or X of a pass kind (GK_F32S: three bf16 terms of X)
 int gk_size(int gk) {
-  return gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : (gk == GK_BF16 ? 2 : (gk == GK_F32S ? 6 : 1)));
+  return gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : (gk == GK_BF16 ? 2 : (gk_split(gk) ? 6 : 1)));
 }
 // Element kind of the X operand of a pass with G of kind gk (FP8 G meets bf16 X).
-int x_kind(int gk) { return gk == GK_FP8 ? GK_BF16 : gk; }
+// (the two-term split pass reads the first two planes of the split layout)
+int x_kind(int gk) { return gk == GK_FP8 ? GK_BF16 : (gk == GK_S2 ? GK_F32S : gk); }
 bool stores_g(int form) { return form == MDS_FORM_BF16 || form == MDS_FORM_FP8; }
 }  // namespace
 
@@ -57,9 +58,10 @@ void add(mds_plan_s* P, Region& reg, size_t bytes) {
 }
 
 // Kind of range pass `it` (0-based, of 2q + 1): the BF16/FP8 forms run the
-// first and the last in fp32 (three-term split) unless MDS_FLAG_LOWP_ALL_RANGE.
+// first and the last from D with two-term bf16 splits of both operands
+// (about 16 significant bits) unless MDS_FLAG_LOWP_ALL_RANGE.
 int pass_kind(const mds_plan_s* P, int it) {
-  return (P->refine && (it == 0 || it == 2 * P->q)) ? GK_F32S : P->gk;
+  return (P->refine && (it == 0 || it == 2 * P->q)) ? GK_S2 : P->gk;
 }
 
 void layout(mds_plan_s* P) {
@@ -82,7 +84,7 @@ void layout(mds_plan_s* P) {
   add(P, P->hc, (size_t)ldg * 4);
   size_t xe = (size_t)(gk_size(x_kind(P->gk)) > gk_size(P->ref_gk) ? gk_size(x_kind(P->gk))
                                                                    : gk_size(P->ref_gk));
-  if (P->refine && (size_t)gk_size(GK_F32S) > xe) xe = (size_t)gk_size(GK_F32S);
+  if (P->refine && (size_t)gk_size(GK_S2) > xe) xe = (size_t)gk_size(GK_S2);
   add(P, P->X, (size_t)lp * ldg * xe);
   const size_t acc_main = P->gk == GK_F64 ? 8 : 4, acc_ref = P->ref_gk == GK_F64 ? 8 : 4;
   const size_t yp_main = (size_t)P->cfg.split * lp * ldg * acc_main;
@@ -139,13 +141,13 @@ void configure(mds_plan_s* P) {
   P->refine = stores_g(o.form) && (o.flags & MDS_FLAG_LOWP_ALL_RANGE) == 0;
   P->needs_g = stores_g(o.form) && !(P->refine && P->q == 0);
   if (P->refine)
-    P->fcfg = gpass_config(GK_F32S, P->l_pad, P->n_pad, P->ldg, o.f32_split ? o.f32_split : o.gpass_split, true,
+    P->fcfg = gpass_config(GK_S2, P->l_pad, P->n_pad, P->ldg, o.f32_split ? o.f32_split : o.gpass_split, true,
                            false, d8, P->n % 4 == 0);
   // bf16 form on fp32 D: the centring write is fused with the first range
   // pass (an fp32 split pass when refining, else a bf16 pass)
   P->fused = o.form == MDS_FORM_BF16 && !d8 && P->needs_g;
   if (P->fused)
-    P->wcfg = gpass_config(P->refine ? GK_F32S : GK_BF16, P->l_pad, P->n_pad, P->ldg,
+    P->wcfg = gpass_config(P->refine ? GK_S2 : GK_BF16, P->l_pad, P->n_pad, P->ldg,
                            o.write_split ? o.write_split : o.gpass_split, true, false, false, P->n % 4 == 0);
   layout(P);
 }
@@ -266,8 +268,13 @@ mds_status gpass(mds_plan_s* P, hipStream_t s, int gk, const GPassCfg& cfg0, boo
 // Range pass `it` of the plan (kind, configuration, source and phase).
 mds_status range_pass(mds_plan_s* P, hipStream_t s, int it, bool fused, const void* D) {
   const int gk = pass_kind(P, it);
-  if (it == 0 && fused) return gpass(P, s, gk, P->wcfg, true, D, P->at<void>(P->G), MDS_PH_WRITE);
-  if (gk == GK_F32S && P->refine) return gpass(P, s, gk, P->fcfg, true, D, nullptr, MDS_PH_GPASS_F32);
+  if (it == 0 && fused) {
+    mds_status e = gpass(P, s, gk, P->wcfg, true, D, P->at<void>(P->G), MDS_PH_WRITE);
+    if (e == MDS_OK && P->wcfg.dma)  // the LDS-ring kernel leaves the padding of G to this
+      e = hip_check(launch_split_zero_pad(P->at<void>(P->G), P->n, P->n_pad, P->ldg, s), "zero padding of G");
+    return e;
+  }
+  if (gk == GK_S2) return gpass(P, s, gk, P->fcfg, true, D, nullptr, MDS_PH_GPASS_F32);
   return gpass(P, s, gk, P->cfg, !stores_g(P->form), D, nullptr, MDS_PH_GPASS);
 }
 
@@ -618,8 +625,8 @@ mds_status mds_autotune(mds_plan_t P, const void* D, void* stream, mds_tune_resu
   auto gk_of = [&](int kind) {
     if (kind == kRange) return P->gk;
     if (kind == kProj) return P->ref_gk;
-    if (kind == kWrite) return P->refine ? (int)GK_F32S : (int)GK_BF16;
-    return (int)GK_F32S;
+    if (kind == kWrite) return P->refine ? (int)GK_S2 : (int)GK_BF16;
+    return (int)GK_S2;
   };
   auto cfg_of = [&](int kind, int split) {
     if (kind == kRange)
@@ -631,7 +638,7 @@ mds_status mds_autotune(mds_plan_t P, const void* D, void* stream, mds_tune_resu
     const bool dma_ok = P->n % 4 == 0 && (uintptr_t)D % 16 == 0;
     if (kind == kWrite)
       return gpass_config(gk_of(kWrite), P->l_pad, P->n_pad, P->ldg, split, true, false, false, dma_ok);
-    return gpass_config(GK_F32S, P->l_pad, P->n_pad, P->ldg, split, true, false, d8, dma_ok);
+    return gpass_config(GK_S2, P->l_pad, P->n_pad, P->ldg, split, true, false, d8, dma_ok);
   };
   // workspace sized for the largest candidate's partials
   size_t ymax = 0;

@@ -27,7 +27,11 @@ typedef __attribute__((__vector_size__(4 * sizeof(double)))) double doublex4_t;
 // scale per 256 x 256 block, multiplied on bf16 MFMA (the X operand is bf16).
 // GK_F32S: the fp32 pass (recentring D) computed on bf16 MFMA from exact
 // three-term bf16 splits of both operands; X is stored split (see k_gpass).
-enum GKind { GK_F64 = 0, GK_F32 = 1, GK_BF16 = 2, GK_FP8 = 3, GK_F32S = 4 };
+// GK_S2: the same pass with the two-term splits (the first two terms: about
+// 16 significant bits per operand) and three products instead of six; it
+// reads the first two planes of the same split X layout.
+enum GKind { GK_F64 = 0, GK_F32 = 1, GK_BF16 = 2, GK_FP8 = 3, GK_F32S = 4, GK_S2 = 5 };
+inline bool gk_split(int gk) { return gk == GK_F32S || gk == GK_S2; }
 constexpr int kF8Block = 256;  // side of the blocks sharing one FP8 scale
 
 constexpr int kPadN = 256;     // padding granule of n (rows and ld of G)
@@ -89,7 +93,7 @@ struct GPassCfg {
   int split;   // K splits
   int sym;     // symmetric mode: upper triangle only, Ypart holds 2 (W o G) X
   int64_t steps_total, steps_per_split;
-  int64_t sym_nbx;             // row blocks per XCD (symmetric mode)
+  int64_t sym_nbx;             // row blocks per XCD (symmetric mode and the LDS-ring split kernel)
   int64_t sym_cols_per_split;  // K columns per split (symmetric mode)
   int dma;                     // split pass through the LDS ring (k_split): fp32 D, n % 4 == 0, aligned D
 };
@@ -109,7 +113,7 @@ GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_h
 // hr_i = fl32((r_i - m) / 2), a few fp32 ulps of the terms from the rounded
 // exact value.
 struct GPassDSrc {
-  // (with gk == GK_BF16 or GK_F32S and D set, a non-null G argument of the pass
+  // (with gk == GK_BF16, GK_F32S or GK_S2 and D set, a non-null G argument of the pass
   // is the bf16 G that it writes: the fused centring write)
   const float* g8_scales = nullptr;  // GK_FP8: scale of block (I, J) at [I * g8_nsb + J]
   int64_t g8_nsb = 0;
@@ -131,8 +135,10 @@ int64_t gpass_blocks(const GPassCfg& cfg, int64_t n_pad);
 // 128; cfg.dma configurations): full pass, symmetric projection, or with Gw
 // the fused centring write.  split_pass_rows(): rows per workgroup.
 int split_pass_rows();
-hipError_t launch_split_pass(const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t blocks, void* Yp,
-                             const GPassDSrc& src, void* Gw, hipStream_t s);
+// Zero the padding of the bf16 G (rows >= n, columns >= n) left by the fused write.
+hipError_t launch_split_zero_pad(void* G, int64_t n, int64_t n_pad, int64_t ldg, hipStream_t s);
+hipError_t launch_split_pass(int nterms, const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t blocks,
+                             void* Yp, const GPassDSrc& src, void* Gw, hipStream_t s);
 hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const void* Xt, int l_pad,
                         const GPassCfg& cfg, void* Ypart, const GPassDSrc& src, hipStream_t s);
 // Y (fp64, l_pad x ldg) = sum_s Ypart[s] in split order (symmetric mode:

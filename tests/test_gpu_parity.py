@@ -232,7 +232,7 @@ def test_omega_stage(form):
     plan.run_stages(torch.from_numpy(D).cuda(), _capi.STAGE_OMEGA)
     torch.cuda.synchronize()
     Xt = plan.buffer(_capi.BUF_X).double().cpu().numpy()
-    if form == "bf16":  # the first range pass is fp32: Omega as its exact three-term split
+    if form == "bf16":  # Omega as the exact three-term split of fl32(Omega); the first range pass reads two terms
         Xt = split_sum(Xt)
     Om = O.omega(seed, n, l)
     got = Xt[:l, :n].T
@@ -284,10 +284,15 @@ def test_gpass_and_cholqr2_unit(name, form):
     torch.cuda.synchronize()
     G = O.gram_matrix(D)
     Om = O.omega(5, n, l)
-    # fp32 first pass in every form but fp64 (the bf16 and fp8 forms take
-    # their first range pass in fp32 as a three-term bf16 split)
-    if form != "fp64":
+    # fp32 first pass (fp32 form); the bf16 and fp8 forms take their first
+    # range pass with both operands as two-term bfloat16 expansions of their
+    # fp32 values (16 significant bits) and three products a0 b0 + a0 b1 +
+    # a1 b0: against the exact product of the expansions, the kernel leaves
+    # out a1 b1 (below 2^-17 |a b|)
+    if form == "fp32":
         G, Om = G.astype(np.float32).astype(np.float64), Om.astype(np.float32).astype(np.float64)
+    elif form in ("bf16", "fp8"):
+        G, Om = O.round_to(G, "bf16x2"), O.round_to(Om, "bf16x2")
     want = G @ Om
     mag = np.abs(G) @ np.abs(Om)
     Yt = plan.buffer(_capi.BUF_Y).cpu().numpy()
@@ -295,7 +300,7 @@ def test_gpass_and_cholqr2_unit(name, form):
     u = 2.0 ** -53 if form == "fp64" else 2.0 ** -24
     bound = 2 * n * u * mag
     if form in ("bf16", "fp8"):
-        bound = bound + 2.0 ** -22 * mag  # the three dropped products of the split
+        bound = bound + 2.0 ** -16 * mag  # the dropped product a1 b1, and the expansions of nearby fp32 values
     # fp32 passes recentre D on the fly with one fma per entry from fl32(d^2),
     # fl32(c/2), fl32((r-m)/2): a few ulps of those terms (the fused bf16
     # first pass over fp32 D takes fl32 of the fp64 entry itself)

@@ -164,28 +164,51 @@ def test_bf16_form_perturbs_like_its_storage():
     reads, _ = W.amplicon_reads(600, 30, seed=7)
     D = W.hamming_distances(reads)
     a = O.rand_mds(D, 20, 10, 1, 0)["eigvals"]
-    b = O.rand_mds(D, 20, 10, 1, 0, form="bf16")["eigvals"]
+    b = O.rand_mds(D, 20, 10, 1, 0, form="bf16_all")["eigvals"]
     c = O.rand_mds(D, 20, 10, 1, 0, form="fp32")["eigvals"]
-    eb, ec = np.max(np.abs(b - a) / a), np.max(np.abs(c - a) / a)
-    assert 1e-9 < ec < 1e-5 and ec < eb < 2e-2
+    d = O.rand_mds(D, 20, 10, 1, 0, form="bf16")["eigvals"]
+    eb, ec, ed = (np.max(np.abs(v - a) / a) for v in (b, c, d))
+    # every pass on bf16 G: well above fp32; with 16-bit end passes: far below
+    assert 1e-9 < ec < 1e-5 and ec < eb < 2e-2 and ed < eb / 10
 
 
-def test_low_precision_schedule_has_fp32_end_passes():
-    # The bf16/fp8 forms take their first and last range application in fp32:
-    # with q = 0 that single application is the whole range finder, so the
-    # form is the fp32 form exactly; with q >= 1 it differs from the variant
-    # that runs every application on the stored bf16 G.
+def test_low_precision_schedule_has_16_bit_end_passes():
+    # The bf16/fp8 forms take their first and last range application with
+    # 16-bit operands (two-term bfloat16 expansions): with q = 0 that single
+    # application is the whole range finder, so both forms are the same
+    # method and stay within the 16-bit operand precision of the fp32 form;
+    # with q >= 1 the bf16 form differs from the variant that runs every
+    # application on the stored bf16 G.
     reads, _ = W.amplicon_reads(500, 20, seed=3)
     D = W.hamming_distances(reads)
-    f32 = O.rand_mds(D, 8, 4, 0, 1, form="fp32")
-    for form in ("bf16", "fp8"):
-        assert np.array_equal(O.rand_mds(D, 8, 4, 0, 1, form=form)["eigvals"], f32["eigvals"])
+    f32 = O.rand_mds(D, 8, 4, 0, 1, form="fp32")["eigvals"]
+    b16 = O.rand_mds(D, 8, 4, 0, 1, form="bf16")["eigvals"]
+    assert np.array_equal(O.rand_mds(D, 8, 4, 0, 1, form="fp8")["eigvals"], b16)
+    assert 0 < np.max(np.abs(b16 - f32) / f32) < 1e-5
     assert [O.pass_dtypes("bf16", it, 2) for it in range(5)] == [
-        ("f32", "f32"), ("bf16", "bf16"), ("bf16", "bf16"), ("bf16", "bf16"), ("f32", "f32")]
+        ("bf16x2", "bf16x2"), ("bf16", "bf16"), ("bf16", "bf16"), ("bf16", "bf16"), ("bf16x2", "bf16x2")]
     assert all(O.pass_dtypes("bf16_all", it, 2) == ("bf16", "bf16") for it in range(5))
     a = O.rand_mds(D, 8, 4, 1, 1, form="bf16")["eigvals"]
     b = O.rand_mds(D, 8, 4, 1, 1, form="bf16_all")["eigvals"]
     assert not np.array_equal(a, b)
+
+
+def test_two_term_bfloat16_rounding():
+    # b0 + b1 with b0 = bf16(f), b1 = bf16(f - b0): against torch's own
+    # float32 -> bfloat16 conversion (independent), the 2^-17 relative bound
+    # of two nearest-even 8-bit roundings, and exact cases
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(200000) * 10.0 ** rng.integers(-6, 6, 200000)
+    got = O.round_to(x, "bf16x2")
+    f = torch.from_numpy(x.astype(np.float32))
+    b0 = f.to(torch.bfloat16).to(torch.float32)
+    b1 = (f - b0).to(torch.bfloat16).to(torch.float32)
+    assert np.array_equal(got, b0.double().numpy() + b1.double().numpy())
+    f64 = x.astype(np.float32).astype(np.float64)
+    assert np.all(np.abs(got - f64) <= 2.0 ** -17 * np.abs(f64))
+    exact = np.array([1.0, 1.0 + 2.0 ** -12, -3.5, 0.0])  # at most 16 significant bits
+    assert np.array_equal(O.round_to(exact, "bf16x2"), exact)
 
 
 def test_fp32_end_passes_keep_bf16_within_1e3_near_degenerate():
