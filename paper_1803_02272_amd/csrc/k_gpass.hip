@@ -948,7 +948,13 @@ GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_h
   if (split < 1) split = 1;
   c.split = (int)split;
   c.steps_per_split = (c.steps_total + split - 1) / split;
-  if (c.dma) c.sym_nbx = (row_blocks + 7) / 8;  // row blocks per XCD
+  if (c.dma) {
+    c.sym_nbx = (row_blocks + 7) / 8;  // row blocks per XCD
+    // K ranges of an even number of steps (the fused write stores step
+    // pairs); every split index below `split` keeps at least one step
+    c.steps_per_split += c.steps_per_split % 2;
+    c.split = (int)((c.steps_total + c.steps_per_split - 1) / c.steps_per_split);
+  }
   return c;
 }
 

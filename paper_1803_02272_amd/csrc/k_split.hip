@@ -268,7 +268,9 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
     S.i = row0 + S.rg * 16 + (lane & 15);
     S.k0 = st * kBK + kk;
   };
-  uint32_t gkeep[kRG][2];  // fused write: bf16 G of the first half of each row group
+  // fused write: bf16 G of the lane's row and K-values 8j .. 8j + 7 (j = lane / 16)
+  // of the step being split (gcur) and of the step before it (gprev)
+  u32x4 gcur[kRG], gprev[kRG];
   // operation j: 0..3 recentre value j (the fused write stores the four bf16
   // entries after the last), 4..9 split the two value pairs into the planes
   auto slice_op = [&](Slice& S, int j, u32x4 (&w)[kRG][NT]) {
@@ -284,18 +286,9 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
         const double d = (double)S.dv[t];
         const double e = __builtin_fma(-d, d, S.cv[t]);
         S.g[t] = (float)__builtin_fma(0.5, e, rd[S.rg]);
-        if (t == 3) {
-          // the two halves of a row group hold K-values 8j .. 8j + 3 and
-          // 8j + 4 .. 8j + 7 of the lane's row: the first is kept, the
-          // second completes one 16-byte store (4 lanes cover 64 bytes of a row)
-          const uint32_t lo = bf16x2_bits(f32x2{S.g[0], S.g[1]});
-          const uint32_t hi = bf16x2_bits(f32x2{S.g[2], S.g[3]});
-          if (S.half == 0) {
-            gkeep[S.rg][0] = lo;
-            gkeep[S.rg][1] = hi;
-          } else {
-            *reinterpret_cast<uint4*>(Gw + S.i * ldg + S.k0 - 4) = make_uint4(gkeep[S.rg][0], gkeep[S.rg][1], lo, hi);
-          }
+        if (t == 3) {  // half h holds K-values 8j + 4h .. 8j + 4h + 3
+          gcur[S.rg][2 * S.half] = bf16x2_bits(f32x2{S.g[0], S.g[1]});
+          gcur[S.rg][2 * S.half + 1] = bf16x2_bits(f32x2{S.g[2], S.g[3]});
         }
       } else {
         const float d2 = S.dv[t] * S.dv[t];
@@ -331,6 +324,28 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
     for (int j = 0; j < kSliceOps; ++j) slice_op(S, j, w);
   };
 
+  // Fused write, K-steps sp - 1 and sp (an aligned pair: 128 bytes of each
+  // row): both are staged in this wave's area of the D stage dd, whose D the
+  // wave has finished reading, and read back as whole lines, so that each of
+  // the four 16-byte stores covers 8 rows x 128 bytes.  Staging slot of row r,
+  // 16-byte piece p: r * 128 + (p ^ (r % 8)) * 16.
+  auto store_pair = [&](int64_t sp, DBuf& dd) {
+    unsigned char* area = &dd[wave * DSTAGE];
+#pragma unroll
+    for (int rg = 0; rg < kRG; ++rg) {
+      const int r = rg * 16 + (lane & 15), j = lane >> 4;
+      *reinterpret_cast<u32x4*>(&area[r * 128 + ((j ^ (r & 7)) * 16)]) = gprev[rg];
+      *reinterpret_cast<u32x4*>(&area[r * 128 + (((4 + j) ^ (r & 7)) * 16)]) = gcur[rg];
+    }
+    const int64_t col = (sp - 1) * kBK + (lane & 7) * 8;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = q * 8 + (lane >> 3);
+      const u32x4 v = *reinterpret_cast<const u32x4*>(&area[r * 128 + (((lane & 7) ^ (r & 7)) * 16)]);
+      __builtin_nontemporal_store(v, reinterpret_cast<u32x4*>(Gw + (row0 + r) * ldg + col));  // streamed out
+    }
+  };
+
   u32x4 wA[kRG][NT], wB[kRG][NT];
   // prologue: X(st0) with the terms of st0 + 1, D of the first three steps,
   // the terms of st0 (into the other buffer's aux area) and the split of st0
@@ -344,6 +359,10 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
   __syncthreads();
 #pragma unroll
   for (int part = 0; part < 4; ++part) split_slice(part, st0, ds0, xs1, wA);
+  if constexpr (WG) {
+#pragma unroll
+    for (int rg = 0; rg < kRG; ++rg) gprev[rg] = gcur[rg];
+  }
   __syncthreads();  // every wave has read the terms in xs1 before it is reloaded
 
   // One step: X(st) in xr (with the terms of st + 1), D(st + 1) in dn; the
@@ -352,7 +371,7 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
   // issued on every step (clamped to the last step at the end), so that the
   // wait counts below are the same on every path.
   auto step = [&](int64_t st, XBuf& xr, XBuf& xw, DBuf& dn, DBuf& dw, u32x4 (&wc)[kRG][NT],
-                  u32x4 (&wn)[kRG][NT]) {
+                  u32x4 (&wn)[kRG][NT], bool pair_end) {
     const int64_t s1 = st + 1 < st1 ? st + 1 : last;
     const int64_t s2 = st + 2 < st1 ? st + 2 : last;
     const int64_t s3 = st + 3 < st1 ? st + 3 : last;
@@ -416,10 +435,25 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
         slices();
       }
     }
-    // X(st + 1) and its terms complete; D(st + 3) and, in the fused write,
-    // the kRG stores of G issued after it may still run (stores count in
+    // The fused write: the split of s1 is the second step of an aligned pair
+    // when the step offset st - st0 is even (st0 and the range length are
+    // even); the pair is stored, else the step is kept for the next one.  The
+    // last step splits s1 = st1 - 1 again, at an odd offset: kept, not stored.
+    if constexpr (WG) {
+      if (pair_end) {
+        store_pair(s1, dn);
+      } else {
+#pragma unroll
+        for (int rg = 0; rg < kRG; ++rg) gprev[rg] = gcur[rg];
+      }
+    }
+    // X(st + 1) and its terms complete; D(st + 3) and, after a stored pair,
+    // the four G stores issued after it may still run (stores count in
     // vmcnt, in issue order with the loads)
-    __builtin_amdgcn_s_waitcnt(0x0F70 | (4 + (WG ? kRG : 0)));  // vmcnt(4) or vmcnt(6)
+    if (WG && pair_end)
+      __builtin_amdgcn_s_waitcnt(0x0F70 | 8);  // vmcnt(8)
+    else
+      __builtin_amdgcn_s_waitcnt(0x0F70 | 4);  // vmcnt(4)
     __asm__ volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     __asm__ volatile("" ::: "memory");
@@ -428,17 +462,17 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
   // X(st) in buffer (st - st0) % 2, D(st) in stage (st - st0) % 3, the split of
   // st in wA or wB by (st - st0) % 2: six steps per trip keep every array static
   for (int64_t st = st0; st < st1; st += 6) {
-    step(st, xs0, xs1, ds1, ds0, wA, wB);
+    step(st, xs0, xs1, ds1, ds0, wA, wB, true);
     if (st + 1 >= st1) break;
-    step(st + 1, xs1, xs0, ds2, ds1, wB, wA);
+    step(st + 1, xs1, xs0, ds2, ds1, wB, wA, false);
     if (st + 2 >= st1) break;
-    step(st + 2, xs0, xs1, ds0, ds2, wA, wB);
+    step(st + 2, xs0, xs1, ds0, ds2, wA, wB, true);
     if (st + 3 >= st1) break;
-    step(st + 3, xs1, xs0, ds1, ds0, wB, wA);
+    step(st + 3, xs1, xs0, ds1, ds0, wB, wA, false);
     if (st + 4 >= st1) break;
-    step(st + 4, xs0, xs1, ds2, ds1, wA, wB);
+    step(st + 4, xs0, xs1, ds2, ds1, wA, wB, true);
     if (st + 5 >= st1) break;
-    step(st + 5, xs1, xs0, ds0, ds2, wB, wA);
+    step(st + 5, xs1, xs0, ds0, ds2, wB, wA, false);
   }
   __builtin_amdgcn_s_waitcnt(0x0F70);  // no load outstanding at exit
 
@@ -514,6 +548,9 @@ hipError_t launch_split_pass(int nterms, const void* Xt, int64_t ldg, int l_pad,
       (nterms != 2 && nterms != 3))
     return hipErrorInvalidValue;
   if (Gw && cfg.sym) return hipErrorInvalidValue;
+  // the fused write stores aligned pairs of steps: every K range starts on an
+  // even step and has an even length
+  if (Gw && (cfg.steps_per_split % 2 != 0 || cfg.steps_total % 2 != 0)) return hipErrorInvalidValue;
   const int mode = cfg.sym ? kSym : (Gw ? kWrite : kFull);
   switch (l_pad / 16) {
 #define MDS_CG(N)                                                                              \
