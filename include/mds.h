@@ -55,29 +55,37 @@ typedef enum mds_status {
  *   FP64: G entries in fp64, fp64 MFMA.
  *   FP32: G entries rounded to fp32, fp32 MFMA.
  *   BF16: G stored in bf16 (rounded from fp64 through fp32).  Of the 2q+1
- *         range passes, the first and the last run in fp32 and the q*2-1
- *         between them on the stored bf16 G against bf16 X (bf16 MFMA, fp32
- *         accumulation); the projection pass ("refinement") is fp32 too.
- *         An fp32 pass multiplies fp32 G entries with fp32 X to fp32
- *         accuracy: each fp32 operand is split exactly into three bf16 terms
- *         (a = a0 + a1 + a2, each rounded to nearest even) and the six
- *         products a_p b_q with p + q <= 2 run on bf16 MFMA with fp32
- *         accumulation (the dropped terms are below 2^-22 |a b|), see
- *         MDS_FLAG_FP32_MFMA_PROJECTION.  The first range pass also writes
- *         the stored G (fused centring write, fp32 D).  Running the two end
- *         passes in fp32 keeps the bf16 rounding of G out of the sketch of
- *         Omega and out of the final basis: the Ritz values then stay within
- *         1e-3 (relative, per eigenvalue) of the fp64 method also where the
- *         k-th eigenvalue lies in a near-degenerate bulk, where a sketch made
+ *         range passes, the first and the last are 16-bit passes over D and
+ *         the q*2-1 between them run on the stored bf16 G against bf16 X
+ *         (bf16 MFMA, fp32 accumulation); the projection pass
+ *         ("refinement") is a 16-bit pass too.  A 16-bit pass takes each
+ *         operand's fp32 value a as the two-term bf16 expansion a0 + a1
+ *         (a0 = bf16(a), a1 = bf16(a - a0), nearest even: about 16
+ *         significant bits) and accumulates a0 b0 + a0 b1 + a1 b0 on bf16
+ *         MFMA in fp32.  The first range pass also writes the stored G
+ *         (fused centring write, fp32 D).  Running the two end passes at 16
+ *         bits keeps the bf16 rounding of G out of the sketch of Omega and
+ *         out of the final basis: the Ritz values then stay within 1e-3
+ *         (relative, per eigenvalue) of the fp64 method also where the k-th
+ *         eigenvalue lies in a near-degenerate bulk, where a sketch made
  *         entirely of bf16 passes moves them by about 1e-3
- *         (MDS_FLAG_LOWP_ALL_RANGE restores that faster schedule).
+ *         (MDS_FLAG_LOWP_ALL_RANGE restores that faster schedule).  The
+ *         16-bit projection adds a few 1e-6 at most to the Ritz values
+ *         (MDS_FLAG_FP32_PROJECTION makes it an fp32 pass).
+ *         An fp32 pass (the FP32 form with MDS_FLAG_SPLIT_FP32, the
+ *         projection with MDS_FLAG_FP32_PROJECTION) multiplies fp32 G
+ *         entries with fp32 X to fp32 accuracy: each fp32 operand is split
+ *         exactly into three bf16 terms (a = a0 + a1 + a2, each rounded to
+ *         nearest even) and the six products a_p b_q with p + q <= 2 run on
+ *         bf16 MFMA with fp32 accumulation (the dropped terms are below
+ *         2^-22 |a b|).
  *   FP8:  G stored as OCP FP8 E4M3 codes with one fp32 scale per 256 x 256
  *         block: g = fl32(gamma), s = fl32(max|g| / 448) over the block (1
  *         for an all-zero block), code = E4M3(fl32(g / s)), nearest even,
  *         saturating.  The range passes between the first and the last
  *         multiply bf16(fl32(s * code)) with bf16 X on bf16 MFMA, fp32
  *         accumulation; the first and last range passes and the projection
- *         are fp32 as in the bf16 form.
+ *         are 16-bit passes as in the bf16 form.
  * G is stored only in the bf16 and fp8 forms (and only when q >= 1: with q = 0
  * the one range pass is an fp32 pass).  Every other pass recomputes each
  * entry from D: fp64 passes with the centring equation in fp64 (the values a
@@ -101,10 +109,10 @@ typedef enum mds_dtype { MDS_DTYPE_F32 = 0, MDS_DTYPE_F64 = 1 } mds_dtype;
  *   same B up to rounding for a symmetric D; for a D that breaks the
  *   contract, the default reads only its upper triangle (j >= i) there. */
 #define MDS_FLAG_FULL_PROJECTION 1
-/*   MDS_FLAG_FP32_MFMA_PROJECTION: BF16 and FP8 forms, run the projection on
- *   fp32 MFMA instead of the three-term bf16 split (same fp32 operands; the
- *   results differ by fp32 rounding only, the split is about 2.5x faster).
- *   No effect in the other forms. */
+/*   MDS_FLAG_FP32_MFMA_PROJECTION: BF16 and FP8 forms, run the projection as
+ *   an fp32 pass on fp32 MFMA (same fp32 operands as MDS_FLAG_FP32_PROJECTION;
+ *   the results differ by fp32 rounding only, the split is about 2.5x
+ *   faster).  No effect in the other forms. */
 #define MDS_FLAG_FP32_MFMA_PROJECTION 2
 /*   MDS_FLAG_SPLIT_FP32: FP32 form, run every G-pass (range passes and
  *   projection) as the three-term bf16 split on bf16 MFMA described under
@@ -135,6 +143,10 @@ typedef enum mds_dtype { MDS_DTYPE_F32 = 0, MDS_DTYPE_F64 = 1 } mds_dtype;
  *   relative when the k-th eigenvalue lies in a near-degenerate bulk (bf16;
  *   ~1e-1 for fp8).  No effect in the other forms. */
 #define MDS_FLAG_LOWP_ALL_RANGE 32
+/*   MDS_FLAG_FP32_PROJECTION: BF16 and FP8 forms, run the projection as an
+ *   fp32 pass (three-term bf16 split, six products) instead of the 16-bit
+ *   pass (two terms, three products).  No effect in the other forms. */
+#define MDS_FLAG_FP32_PROJECTION 64
 
 typedef struct mds_opts {
   int32_t form;        /* mds_form (default MDS_FORM_FP32) */

@@ -355,18 +355,20 @@ def fp8_operand(G: np.ndarray) -> np.ndarray:
 # bfloat16 expansions of their float32 values) and only the passes between
 # them on the stored low-precision G (the sketch of Omega and the final basis
 # then carry no bf16/fp8 rounding of G); "bf16_all" and "fp8_all" run every
-# range pass on the stored G.  The projection is fp32 in all four
-# low-precision variants (the fp32 "refinement" pass).
+# range pass on the stored G.  Their projection (the "refinement" pass) is a
+# 16-bit pass as well; "bf16_p32" and "fp8_p32" make it an fp32 pass.
 _F32 = ("f32", "f32")
 _X2 = ("bf16x2", "bf16x2")
 FORMS = {
     "fp64": {"first": ("f64", "f64"), "range": ("f64", "f64"), "last": ("f64", "f64"), "proj": ("f64", "f64")},
     "fp32": {"first": _F32, "range": _F32, "last": _F32, "proj": _F32},
-    "bf16": {"first": _X2, "range": ("bf16", "bf16"), "last": _X2, "proj": _F32},
-    "fp8": {"first": _X2, "range": ("fp8blk", "bf16"), "last": _X2, "proj": _F32},
-    "bf16_all": {"first": ("bf16", "bf16"), "range": ("bf16", "bf16"), "last": ("bf16", "bf16"), "proj": _F32},
+    "bf16": {"first": _X2, "range": ("bf16", "bf16"), "last": _X2, "proj": _X2},
+    "fp8": {"first": _X2, "range": ("fp8blk", "bf16"), "last": _X2, "proj": _X2},
+    "bf16_p32": {"first": _X2, "range": ("bf16", "bf16"), "last": _X2, "proj": _F32},
+    "fp8_p32": {"first": _X2, "range": ("fp8blk", "bf16"), "last": _X2, "proj": _F32},
+    "bf16_all": {"first": ("bf16", "bf16"), "range": ("bf16", "bf16"), "last": ("bf16", "bf16"), "proj": _X2},
     "fp8_all": {"first": ("fp8blk", "bf16"), "range": ("fp8blk", "bf16"), "last": ("fp8blk", "bf16"),
-                "proj": _F32},
+                "proj": _X2},
 }
 
 

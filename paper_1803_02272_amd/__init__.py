@@ -36,8 +36,8 @@ class Plan:
     iterations, test-matrix seed, G-pass form ("fp64" | "fp32" | "bf16") and
     the dtype of D ("f32" | "f64").  full_projection=True streams all of G in
     the projection pass instead of its upper triangle (MDS_FLAG_FULL_PROJECTION);
-    fp32_mfma_projection=True runs the bf16/fp8 forms' fp32 projection on fp32
-    MFMA instead of the three-term bf16 split (MDS_FLAG_FP32_MFMA_PROJECTION);
+    fp32_mfma_projection=True runs the bf16/fp8 forms' projection as an fp32
+    pass on fp32 MFMA (MDS_FLAG_FP32_MFMA_PROJECTION);
     split_fp32=True runs every pass of the fp32 form as that split
     (MDS_FLAG_SPLIT_FP32); full_stats=True reads all of D in the centring
     statistics instead of its upper-triangle tiles (MDS_FLAG_FULL_STATS);
@@ -45,12 +45,14 @@ class Plan:
     (MDS_FLAG_CHECK_INPUT; info() then reports asym_pairs and diag_nonzero
     and status ERR_NOT_METRIC on a violation); lowp_all_range=True runs every
     range pass of the bf16/fp8 forms on the stored low-precision G, without
-    the fp32 first and last range passes (MDS_FLAG_LOWP_ALL_RANGE)."""
+    the 16-bit first and last range passes (MDS_FLAG_LOWP_ALL_RANGE);
+    fp32_projection=True makes the bf16/fp8 forms' projection an fp32 pass
+    (three-term split) instead of a 16-bit one (MDS_FLAG_FP32_PROJECTION)."""
 
     def __init__(self, n, k, oversample=10, q=2, seed=0, form="fp32", d_dtype="f32", gpass_split=0,
                  workspace="torch", full_projection=False, proj_split=0, write_split=0,
                  fp32_mfma_projection=False, split_fp32=False, full_stats=False, check_input=False,
-                 lowp_all_range=False, f32_split=0):
+                 lowp_all_range=False, f32_split=0, fp32_projection=False):
         L = _capi.lib()
         self.n, self.k, self.oversample, self.q, self.seed = int(n), int(k), int(oversample), int(q), int(seed)
         self.form = form
@@ -63,7 +65,8 @@ class Plan:
                              | (_capi.FLAG_SPLIT_FP32 if split_fp32 else 0)
                              | (_capi.FLAG_FULL_STATS if full_stats else 0)
                              | (_capi.FLAG_CHECK_INPUT if check_input else 0)
-                             | (_capi.FLAG_LOWP_ALL_RANGE if lowp_all_range else 0),
+                             | (_capi.FLAG_LOWP_ALL_RANGE if lowp_all_range else 0)
+                             | (_capi.FLAG_FP32_PROJECTION if fp32_projection else 0),
                              int(proj_split), int(write_split), int(f32_split))
         h = ctypes.c_void_p()
         check(L.mds_plan_ex(ctypes.byref(h), self.n, self.k, self.oversample, self.q, self.seed,

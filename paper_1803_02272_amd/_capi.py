@@ -47,6 +47,7 @@ FLAG_SPLIT_FP32 = 4
 FLAG_FULL_STATS = 8
 FLAG_CHECK_INPUT = 16
 FLAG_LOWP_ALL_RANGE = 32
+FLAG_FP32_PROJECTION = 64
 
 
 class MdsOpts(ctypes.Structure):

@@ -589,14 +589,14 @@ __global__ __launch_bounds__(256, 2) void k_gpass_x3(const uint16_t* __restrict_
   const int64_t n = src.n;
   const double mval = src.m[0];
   float ri[RG];  // hr_i (symmetric mode: 2 hr_i, exact)
-  double rd[RG];  // WG: r_i in fp64
+  double rd[RG];  // WG: (r_i - m) / 2 in fp64
   bool rowvec[RG];
 #pragma unroll
   for (int rg = 0; rg < RG; ++rg) {
     const int64_t i = row0 + rg * 16 + (lane & 15);
     const float h = (i < n) ? (float)(0.5 * (src.r[i] - mval)) : 0.0f;
     ri[rg] = SYM ? h + h : h;
-    rd[rg] = (WG && i < n) ? src.r[i] : 0.0;
+    rd[rg] = (WG && i < n) ? 0.5 * (src.r[i] - mval) : 0.0;
     rowvec[rg] = src.vec && (((i * n) % DV) == 0);
   }
   const size_t xrowbytes = (size_t)ldg * 6;
@@ -650,15 +650,16 @@ __global__ __launch_bounds__(256, 2) void k_gpass_x3(const uint16_t* __restrict_
       constexpr bool BAND = decltype(band_tag)::value;
       float g[8];
       if constexpr (WG) {
-        // gamma = -1/2 (((d^2 - c_k) - r_i) + m) in fp64, g = fl32(gamma),
+        // gamma = 1/2 (c_k - d^2) + (r_i - m) / 2 in fp64 as two fused
+        // operations (the LDS-ring kernel's expression), g = fl32(gamma),
         // zero outside n x n; bf16(g) is the stored G entry
         const int64_t k0 = st * BK + (lane >> 4) * 8;
         const int64_t i = row0 + rg * 16 + (lane & 15);
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
           const double d = (double)a[rg][t];
-          const double e = ((d * d - ch[t]) - rd[rg]) + mval;
-          g[t] = (i < n && k0 + t < n) ? (float)(-0.5 * e) : 0.0f;
+          const double e = __builtin_fma(-d, d, ch[t]);
+          g[t] = (i < n && k0 + t < n) ? (float)__builtin_fma(0.5, e, rd[rg]) : 0.0f;
         }
         u32x4 gw;
 #pragma unroll
@@ -863,15 +864,14 @@ hipError_t launch_x3_nt(const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_
     return hipGetLastError();
   }
   if (cfg.rg != rg_x3(CG, src.d_is_f64 != 0)) return hipErrorInvalidValue;
-  if (NT == 2 && cfg.sym) return hipErrorInvalidValue;  // the two-term split serves range passes only
   if (src.d_is_f64) {
     if (cfg.sym)
-      launch_x3_one<CG, double, true>(Xt, ldg, cfg, n_pad, Yp, src, s);
+      launch_x3_one<CG, double, true, false, NT>(Xt, ldg, cfg, n_pad, Yp, src, s);
     else
       launch_x3_one<CG, double, false, false, NT>(Xt, ldg, cfg, n_pad, Yp, src, s);
   } else {
     if (cfg.sym)
-      launch_x3_one<CG, float, true>(Xt, ldg, cfg, n_pad, Yp, src, s);
+      launch_x3_one<CG, float, true, false, NT>(Xt, ldg, cfg, n_pad, Yp, src, s);
     else
       launch_x3_one<CG, float, false, false, NT>(Xt, ldg, cfg, n_pad, Yp, src, s);
   }
@@ -924,6 +924,11 @@ GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_h
     c.rg = 2;
     c.bm = split_pass_rows();
   }
+  if (gk == GK_BF16 && !from_d && dma_ok && l_pad <= kDmaMaxL && n_pad % gstream_rows() == 0 && ldg == n_pad) {
+    c.dma = 1;  // k_gstream: the stored bf16 G through an LDS ring, same work mapping
+    c.rg = 2;
+    c.bm = gstream_rows();
+  }
   // bytes per K-value of a step's 128-byte row (the split pass steps 32 K-values, like fp32)
   const int64_t esize = gk == GK_F64 ? 8 : ((gk == GK_F32 || gk_split(gk)) ? 4 : 2);
   c.steps_total = ldg * esize / 128;
@@ -974,7 +979,9 @@ hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const
   switch (gk) {
     case GK_F64: return launch_gk<GK_F64>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
     case GK_F32: return launch_gk<GK_F32>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
-    case GK_BF16: return launch_gk<GK_BF16>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
+    case GK_BF16:
+      if (cfg.dma && !src.D) return launch_gstream(G, ldg, Xt, l_pad, cfg, src.n, gpass_blocks(cfg, n_pad), Ypart, s);
+      return launch_gk<GK_BF16>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
     case GK_FP8:
       if (!src.g8_scales || (cfg.bm > kF8Block) || (kF8Block % cfg.bm)) return hipErrorInvalidValue;
       return launch_gk<GK_FP8>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);

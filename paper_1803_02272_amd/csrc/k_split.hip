@@ -6,10 +6,10 @@
 // Arithmetic (the same as k_gpass_x3): an fp32 value a is the exact sum
 // a0 + a1 + a2 of three bf16 terms (each rounded to nearest even); the six
 // products a_p b_q with p + q <= 2 are accumulated in fp32, the three
-// dropped ones are below 2^-22 |a b|.  With two terms (NT = 2, range passes)
-// the products are a0 b0 + a0 b1 + a1 b0: both operands to about 16
-// significant bits, the result within about 3 2^-18 |a b| per product, in
-// half the MFMA and much less of the splitting work.  Three modes:
+// dropped ones are below 2^-22 |a b|.  With two terms (NT = 2: the 16-bit
+// range passes and projection) the products are a0 b0 + a0 b1 + a1 b0: each
+// operand within 2^-17 of its fp32 value, the result within 2^-15 |a b| per
+// product, in half the MFMA and much less of the splitting work.  Three modes:
 //   kFull  Y = G X over all of D, gamma = fma(-1/2, fl32(d^2), hc_k + hr_i)
 //          with hc_k = fl32(c_k / 2), hr_i = fl32((r_i - m) / 2);
 //   kSym   the projection's symmetric pass, 2 (W o G) X over the upper
@@ -116,7 +116,6 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
                                                   uint16_t* __restrict__ Gw) {
   constexpr bool SYM = MODE == kSym;
   constexpr bool WG = MODE == kWrite;
-  static_assert(NT == 3 || (NT == 2 && !SYM), "two-term splits serve the range passes");
   constexpr int LPAD = CG * 16;
   constexpr int XINS = CG * NT;                         // 1 KB loads per X step tile (NT planes)
   constexpr int XBYTES = XINS * 1024 + kAux;
@@ -499,16 +498,10 @@ template <int CG, int NT>
 hipError_t launch_cg(int mode, const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t blocks, void* Yp,
                      const GPassDSrc& src, void* Gw, hipStream_t s) {
   const dim3 grid((unsigned)blocks), block(64 * kWaves);
-  if constexpr (NT == 3) {
-    if (mode == kSym) {
-      hipLaunchKernelGGL((k_split<CG, kSym, 3>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split,
-                         cfg.steps_total, cfg.steps_per_split, (float*)Yp, src, cfg.sym_nbx, (uint16_t*)nullptr);
-      return hipGetLastError();
-    }
-  } else {
-    if (mode == kSym) return hipErrorInvalidValue;
-  }
-  if (mode == kWrite)
+  if (mode == kSym)
+    hipLaunchKernelGGL((k_split<CG, kSym, NT>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split,
+                       cfg.steps_total, cfg.steps_per_split, (float*)Yp, src, cfg.sym_nbx, (uint16_t*)nullptr);
+  else if (mode == kWrite)
     hipLaunchKernelGGL((k_split<CG, kWrite, NT>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split,
                        cfg.steps_total, cfg.steps_per_split, (float*)Yp, src, cfg.sym_nbx, (uint16_t*)Gw);
   else

@@ -132,7 +132,7 @@ void configure(mds_plan_s* P) {
     if (rows < 256) range_split = (768 + rows - 1) / rows;
   }
   P->cfg = gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, (int)range_split, !stores_g(P->form), false, d8,
-                        P->gk == GK_F32S && P->n % 4 == 0);
+                        P->gk == GK_BF16 || (P->gk == GK_F32S && P->n % 4 == 0));
   const int ps = o.proj_split ? o.proj_split : o.gpass_split;
   const bool psym = (o.flags & MDS_FLAG_FULL_PROJECTION) == 0;
   P->ref_cfg = gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, ps, true, psym, d8, P->n % 4 == 0);
@@ -251,7 +251,8 @@ mds_status gpass(mds_plan_s* P, hipStream_t s, int gk, const GPassCfg& cfg0, boo
   const GPassDSrc src = make_src(P, gk, from_d, D);
   // the LDS-ring split kernel needs a 16-byte aligned D: else the same split
   // with the register-prefetch kernel
-  const GPassCfg cfg = src.vec ? cfg0 : gpass_config_nodma(cfg0, P->l_pad, P->n_pad, P->d_dtype == MDS_DTYPE_F64);
+  const GPassCfg cfg =
+      (!src.D || src.vec) ? cfg0 : gpass_config_nodma(cfg0, P->l_pad, P->n_pad, P->d_dtype == MDS_DTYPE_F64);
   {
     PhaseTimer tm(P, s, phase);
     MDS_TRY(launch_gpass(gk, Gw ? Gw : (from_d ? nullptr : P->at<void>(P->G)), P->ldg, P->n_pad,
@@ -282,6 +283,7 @@ mds_status range_pass(mds_plan_s* P, hipStream_t s, int it, bool fused, const vo
 // terms when the pass recentres D.
 GPassDSrc make_src(mds_plan_s* P, int gk, bool from_d, const void* D) {
   GPassDSrc src;
+  src.n = P->n;
   if (gk == GK_FP8) {
     src.g8_scales = P->at<float>(P->gscale);
     src.g8_nsb = P->n_pad / kF8Block;
@@ -356,7 +358,7 @@ mds_status mds::run_plan(mds_plan_s* P, const void* D, double* coords, double* e
   for (int it = 0; it < passes; ++it) {
     mds_status e = range_pass(P, s, it, fused, D);
     if (e != MDS_OK) return e;
-    const int next_xk = (it == total_range - 1) ? P->ref_gk : x_kind(pass_kind(P, it + 1));
+    const int next_xk = x_kind((it == total_range - 1) ? P->ref_gk : pass_kind(P, it + 1));
     e = orthonormalize(P, s, next_xk);
     if (e != MDS_OK) return e;
     P->last_xk = next_xk;
@@ -433,7 +435,7 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
     return fail(MDS_ERR_INVALID_ARG, "negative split (%d, %d, %d, %d)", o.gpass_split, o.proj_split, o.write_split,
                 o.f32_split);
   if (o.flags & ~(MDS_FLAG_FULL_PROJECTION | MDS_FLAG_FP32_MFMA_PROJECTION | MDS_FLAG_SPLIT_FP32 |
-                  MDS_FLAG_FULL_STATS | MDS_FLAG_CHECK_INPUT | MDS_FLAG_LOWP_ALL_RANGE))
+                  MDS_FLAG_FULL_STATS | MDS_FLAG_CHECK_INPUT | MDS_FLAG_LOWP_ALL_RANGE | MDS_FLAG_FP32_PROJECTION))
     return fail(MDS_ERR_INVALID_ARG, "unknown flags 0x%x", o.flags);
   if ((o.flags & MDS_FLAG_CHECK_INPUT) && (n + 63) / 64 > 65535)
     return fail(MDS_ERR_INVALID_ARG, "MDS_FLAG_CHECK_INPUT supports n <= %d", 65535 * 64);
@@ -453,9 +455,12 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
   P->d_dtype = o.d_dtype;
   P->gk = o.form == MDS_FORM_FP64 ? GK_F64
           : (o.form == MDS_FORM_FP32 ? GK_F32 : (o.form == MDS_FORM_BF16 ? GK_BF16 : GK_FP8));
-  // projection ("refinement") of the stored-G forms: fp32, by default as the
-  // three-term bf16 split on bf16 MFMA
-  P->ref_gk = stores_g(o.form) ? ((o.flags & MDS_FLAG_FP32_MFMA_PROJECTION) ? GK_F32 : GK_F32S) : P->gk;
+  // projection ("refinement") of the stored-G forms: a 16-bit pass (two-term
+  // bf16 split) by default, else fp32 as the three-term split or on fp32 MFMA
+  P->ref_gk = !stores_g(o.form)                             ? P->gk
+              : (o.flags & MDS_FLAG_FP32_MFMA_PROJECTION) ? GK_F32
+              : (o.flags & MDS_FLAG_FP32_PROJECTION)      ? GK_F32S
+                                                          : GK_S2;
   // FP32 form with every pass as the three-term bf16 split
   if (o.form == MDS_FORM_FP32 && (o.flags & MDS_FLAG_SPLIT_FP32)) P->gk = P->ref_gk = GK_F32S;
   P->flags = o.flags;
@@ -631,7 +636,7 @@ mds_status mds_autotune(mds_plan_t P, const void* D, void* stream, mds_tune_resu
   auto cfg_of = [&](int kind, int split) {
     if (kind == kRange)
       return gpass_config(P->gk, P->l_pad, P->n_pad, P->ldg, split, !stores_g(P->form), false, d8,
-                          P->gk == GK_F32S && P->n % 4 == 0 && (uintptr_t)D % 16 == 0);
+                          P->gk == GK_BF16 || (P->gk == GK_F32S && P->n % 4 == 0 && (uintptr_t)D % 16 == 0));
     if (kind == kProj)
       return gpass_config(P->ref_gk, P->l_pad, P->n_pad, P->ldg, split, true, sym, d8,
                           P->n % 4 == 0 && (uintptr_t)D % 16 == 0);

@@ -95,15 +95,16 @@ struct GPassCfg {
   int64_t steps_total, steps_per_split;
   int64_t sym_nbx;             // row blocks per XCD (symmetric mode and the LDS-ring split kernel)
   int64_t sym_cols_per_split;  // K columns per split (symmetric mode)
-  int dma;                     // split pass through the LDS ring (k_split): fp32 D, n % 4 == 0, aligned D
+  int dma;                     // pass through an LDS ring: k_split (fp32 D, n % 4 == 0, aligned D) or k_gstream (bf16 G)
 };
 // sym (recentring passes only): the projection's symmetric mode, see k_gpass.
 // d8: D holds fp64 (recentring passes keep more raw values in registers).
 // gk == GK_BF16 with from_d: the fused centring write and first range pass
 // on bf16 MFMA; gk == GK_F32S with a G argument: the fused centring write and
 // an fp32 first range pass (three-term split).
-// dma_ok (GK_F32S): n % 4 == 0 and D 16-byte aligned, so the pass may stream
-// D through LDS (needs the same alignment at launch).
+// dma_ok (split kinds from D): n % 4 == 0 and D 16-byte aligned, so the pass
+// may stream D through LDS (needs the same alignment at launch); (GK_BF16
+// over the stored G): stream G through LDS (k_gstream).
 GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_hint, bool from_d, bool sym,
                       bool d8, bool dma_ok = false);
 // With D != nullptr the A operand is recentred on the fly from D (ld = n)
@@ -135,6 +136,11 @@ int64_t gpass_blocks(const GPassCfg& cfg, int64_t n_pad);
 // 128; cfg.dma configurations): full pass, symmetric projection, or with Gw
 // the fused centring write.  split_pass_rows(): rows per workgroup.
 int split_pass_rows();
+// The range pass over a stored bf16 G through an LDS ring (k_gstream):
+// 256-row blocks, l_pad <= 128, a configuration from gpass_config with dma set.
+int gstream_rows();
+hipError_t launch_gstream(const void* G, int64_t ldg, const void* Xt, int l_pad, const GPassCfg& cfg, int64_t n,
+                          int64_t blocks, void* Yp, hipStream_t s);
 // Zero the padding of the bf16 G (rows >= n, columns >= n) left by the fused write.
 hipError_t launch_split_zero_pad(void* G, int64_t n, int64_t n_pad, int64_t ldg, hipStream_t s);
 hipError_t launch_split_pass(int nterms, const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t blocks,

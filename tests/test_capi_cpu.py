@@ -51,14 +51,15 @@ def test_invalid_arguments_rejected(n, k, p, q):
 def test_invalid_options_rejected():
     assert _plan(100, 4, 4, 1, form=7)[0] == _capi.ERR_INVALID_ARG
     assert _plan(100, 4, 4, 1, dt=5)[0] == _capi.ERR_INVALID_ARG
-    assert _plan(100, 4, 4, 1, flags=64)[0] == _capi.ERR_INVALID_ARG
+    assert _plan(100, 4, 4, 1, flags=128)[0] == _capi.ERR_INVALID_ARG
     assert _plan(100, 4, 4, 1, split=-1)[0] == _capi.ERR_INVALID_ARG
     for form, flags in ((2, _capi.FLAG_FULL_PROJECTION), (2, _capi.FLAG_FP32_MFMA_PROJECTION),
                         (2, _capi.FLAG_FULL_PROJECTION | _capi.FLAG_FP32_MFMA_PROJECTION),
                         (1, _capi.FLAG_SPLIT_FP32), (1, _capi.FLAG_SPLIT_FP32 | _capi.FLAG_FULL_PROJECTION),
                         (0, _capi.FLAG_FULL_STATS), (2, _capi.FLAG_FULL_STATS | _capi.FLAG_FULL_PROJECTION),
                         (1, _capi.FLAG_CHECK_INPUT), (2, _capi.FLAG_LOWP_ALL_RANGE),
-                        (3, _capi.FLAG_LOWP_ALL_RANGE | _capi.FLAG_CHECK_INPUT)):
+                        (3, _capi.FLAG_LOWP_ALL_RANGE | _capi.FLAG_CHECK_INPUT), (2, _capi.FLAG_FP32_PROJECTION),
+                        (3, _capi.FLAG_FP32_PROJECTION | _capi.FLAG_FULL_PROJECTION)):
         st, h = _plan(100, 4, 4, 1, form=form, flags=flags)
         assert st == _capi.OK
         _capi.lib().mds_destroy(h)
