@@ -1,0 +1,77 @@
+"""Implicit centring at a size where G could not be stored: n = 240,000
+Gaussian-mixture points (20 components, 100 dimensions, means N(0, 9 I),
+unit covariance), fp32 Euclidean D (230 GB of HBM), k = 100, oversample 20,
+q = 1, FP32 form.
+
+The FP32 form never writes G: every pass recentres D on the fly (Sec. 6.2,
+step 1: the centring equation evaluated inside the product), so the plan's
+workspace stays O(n l) and D is the only n x n array.  A stored fp32 G would
+need another 230 GB (a bf16 one 115 GB), which does not fit beside D.
+
+Pin independent of the oracle's code (no n x n host array is needed): for a
+Euclidean D the Gram matrix is X_c X_c^T (Sec. 6.3), whose only nonzero
+eigenvalues are the squared singular values of the centred cloud; rank 100
+< l = 120 makes the randomized method exact (Halko et al.: Q Q^T G = G).  The
+Ritz values must match that spectrum within the fp32 bar 1e-5 (relative, per
+eigenvalue), and the embedding must reproduce D on sampled pairs.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import say
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1803_02272_amd as mds  # noqa: E402
+from workloads import gpu as WG  # noqa: E402
+
+N, DIM, COMPS, VAR, K, P, Q = 240000, 100, 20, 9.0, 100, 20, 1
+
+
+@pytest.mark.timeout(900)
+def test_fp32_form_beyond_stored_g_capacity():
+    free, total = torch.cuda.mem_get_info()
+    need = N * N * 4
+    say(f"[scale] n={N}: D takes {need / 1e9:.1f} GB of {free / 1e9:.1f} GB free ({total / 1e9:.1f} GB total)")
+    if free < need + (8 << 30):
+        pytest.skip("the device has too little free memory for a 230 GB D")
+    t0 = time.time()
+    X, _ = W.gaussian_mixture(N, DIM, COMPS, VAR, seed=5)
+    Xc = X - X.mean(axis=0, keepdims=True)
+    sig2 = np.sort(np.linalg.eigvalsh(Xc.T @ Xc))[::-1]  # nonzero spectrum of G = Xc Xc^T
+    D = WG.euclidean_from_points(X)
+    say(f"[scale] cloud spectrum {sig2[0]:.4e} .. {sig2[-1]:.4e}; D generated ({time.time() - t0:.0f} s)")
+    for split in (False, True):
+        plan = mds.Plan(N, K, P, Q, 0, form="fp32", split_fp32=split)
+        ws = plan.workspace_size()
+        assert ws < 4 << 30  # O(n l): no n x n buffer besides D
+        plan.set_timing(True)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        coords, eig = plan.run(D)
+        torch.cuda.synchronize()
+        ms = (time.time() - t1) * 1e3
+        info = plan.info()
+        assert info["status"] == 0, info
+        e = eig.cpu().numpy()
+        err = float(np.max(np.abs(e - sig2) / sig2))
+        ph = plan.timings()
+        say(f"[scale] fp32 split={split}: {ms:.0f} ms, workspace {ws / 1e9:.2f} GB, eig rel err vs cloud "
+            f"spectrum {err:.3e}; phases " + ", ".join(f"{a}={b[1]:.1f}" for a, b in ph.items() if b[0]))
+        assert err < 1e-5
+        # k = rank: the embedding reproduces D on sampled pairs
+        rng = np.random.default_rng(2)
+        i, j = rng.integers(0, N, 4000), rng.integers(0, N, 4000)
+        C = coords.cpu().numpy()
+        dh = np.linalg.norm(C[i] - C[j], axis=1)
+        dd = np.linalg.norm(X[i] - X[j], axis=1)
+        say(f"[scale] max |d_hat - d| / max d over 4000 pairs {np.max(np.abs(dh - dd)) / np.max(dd):.2e}")
+        assert np.max(np.abs(dh - dd)) < 1e-4 * np.max(dd)
+        plan.close()
+        del coords, eig
