@@ -313,6 +313,53 @@ void mds_destroy(mds_plan_t plan);
  * (the block).  Enqueued on `stream`; caller-owned buffers. */
 mds_status mds_philox4x64_10(const uint64_t* in, uint64_t* out, int64_t count, void* stream);
 
+/* Pairwise distances on the device: the dissimilarity matrix between reads
+ * that the method takes as input (Sec. 2.2; in Table 1 its computation is
+ * the dominant cost of the pipeline), written as the D that mds_run reads:
+ * row-major n x n, ld = n, element type d_dtype (MDS_DTYPE_F32 or _F64).
+ * Caller-owned device buffers, enqueued on `stream` (no allocation, no
+ * synchronisation).  Argument errors (NULL pointer, sizes out of range, bad
+ * dtype) return MDS_ERR_INVALID_ARG before any device call; no device:
+ * MDS_ERR_NO_DEVICE.  Exact in the sense that each entry is the stated
+ * formula with its stated roundings: the same bits as a CPU evaluation.
+ *
+ * mds_hamming_distances: codes is n x length bytes (row-major, ld = length),
+ * one base per byte as 0..3 (A, C, G, T); d_ij = (number of positions p at
+ * which codes differ) / length, the fp64 quotient rounded to nearest even
+ * in d_dtype.  A byte outside 0..3 matches nothing, itself included (an
+ * unknown base is a mismatch).  The Hamming distance stands in for the
+ * alignment-based dissimilarity of Sec. 2.2 (reads that differ by
+ * substitutions only).  1 <= n <= 4e6, 1 <= length <= 2048.
+ *
+ * mds_euclidean_distances: X is n x dim fp64 points (row-major, ld = dim);
+ * d_ij = sqrt(sum_k (x_ik - x_jk)^2) with the square and each partial sum
+ * rounded to fp64 (no fused multiply-add), k increasing, then the square
+ * root rounded to d_dtype.  D is exactly symmetric with a zero diagonal.
+ * 1 <= n <= 4e6, 1 <= dim <= 2^20. */
+mds_status mds_hamming_distances(const uint8_t* codes, int64_t n, int32_t length, int32_t d_dtype, void* D,
+                                 void* stream);
+mds_status mds_euclidean_distances(const double* X, int64_t n, int32_t dim, int32_t d_dtype, void* D, void* stream);
+
+/* Connected components of the threshold graph on D (Sec. 7, Conclusions and
+ * perspectives: the n items are the vertices and (i, j), i != j, is an edge
+ * iff d_ij <= threshold; the components are candidate clusters of reads).
+ * D: device n x n, row-major, ld = n, element type d_dtype; each entry is
+ * compared as an fp64 value (exact for fp32 D); a NaN entry is no edge.  By
+ * default only the upper triangle j > i is read (D symmetric by contract,
+ * half the reads); with MDS_CC_FULL_MATRIX every off-diagonal entry is read
+ * and (i, j) is an edge iff d_ij <= threshold or d_ji <= threshold.
+ * labels: device int32[n], written with labels[i] = the smallest index of
+ * the component of i (canonical: the same labels whatever the evaluation
+ * order).  n_components: device int64, the number of components, or NULL.
+ * Caller-owned buffers; enqueued on `stream`, no allocation and no
+ * synchronisation; labels and n_components are valid once the stream
+ * reaches that point.  Argument errors (NULL D or labels, n outside
+ * 1..4e6, bad dtype or flags, NaN threshold) return MDS_ERR_INVALID_ARG
+ * before any device call; no device: MDS_ERR_NO_DEVICE. */
+#define MDS_CC_FULL_MATRIX 1
+mds_status mds_threshold_components(const void* D, int32_t d_dtype, int64_t n, double threshold, int32_t flags,
+                                    int32_t* labels, int64_t* n_components, void* stream);
+
 /* ---- Batched small instances ------------------------------------------------
  * Many independent MDS instances of uneven n in one persistent launch: one
  * workgroup runs a whole instance (centring, Omega, range passes with

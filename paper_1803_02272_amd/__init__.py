@@ -15,7 +15,8 @@ import ctypes
 from . import _capi
 from ._capi import MdsError, check
 
-__all__ = ["Plan", "MdsError", "library_version", "FORMS"]
+__all__ = ["Plan", "MdsError", "library_version", "FORMS", "hamming_distances", "euclidean_distances",
+           "threshold_components"]
 
 FORMS = _capi.FORMS
 
@@ -29,6 +30,73 @@ def _stream_handle(stream):
 
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _distance_out(n, dtype, out):
+    import torch
+
+    tdt = {"f32": torch.float32, "f64": torch.float64}[dtype]
+    if out is None:
+        out = torch.empty((n, n), dtype=tdt, device="cuda")
+    if out.dtype != tdt or tuple(out.shape) != (n, n) or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError("out must be a contiguous CUDA tensor of shape (n, n) and the requested dtype")
+    return out, (_capi.DTYPE_F64 if dtype == "f64" else _capi.DTYPE_F32)
+
+
+def hamming_distances(codes, dtype="f32", out=None, stream=None):
+    """D[i, j] = (positions where reads i and j differ) / length
+    (mds_hamming_distances).  codes: CUDA uint8 tensor n x length of base
+    codes 0..3; returns (or fills) the n x n D in fp32 or fp64."""
+    import torch
+
+    if codes.dtype != torch.uint8 or codes.dim() != 2 or not codes.is_cuda:
+        raise ValueError("codes must be a CUDA uint8 tensor of shape (n, length)")
+    codes = codes.contiguous()
+    n, length = codes.shape
+    out, dt = _distance_out(n, dtype, out)
+    check(_capi.lib().mds_hamming_distances(ctypes.c_void_p(codes.data_ptr()), n, length, dt,
+                                            ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+          "mds_hamming_distances")
+    return out
+
+
+def threshold_components(D, threshold, full_matrix=False, stream=None):
+    """Connected components of the graph with an edge (i, j) wherever
+    D[i, j] <= threshold (mds_threshold_components).  D: CUDA float32 or
+    float64 n x n (upper triangle read unless full_matrix).  Returns
+    (labels, count): CUDA int32 labels (the smallest index of each item's
+    component) and a CUDA int64 scalar tensor, both filled on the stream."""
+    import torch
+
+    if D.dim() != 2 or D.shape[0] != D.shape[1] or not D.is_cuda or D.dtype not in (torch.float32, torch.float64):
+        raise ValueError("D must be a square CUDA float32/float64 tensor")
+    D = D.contiguous()
+    n = D.shape[0]
+    labels = torch.empty(n, dtype=torch.int32, device=D.device)
+    count = torch.empty((), dtype=torch.int64, device=D.device)
+    dt = _capi.DTYPE_F64 if D.dtype == torch.float64 else _capi.DTYPE_F32
+    check(_capi.lib().mds_threshold_components(ctypes.c_void_p(D.data_ptr()), dt, n, float(threshold),
+                                               _capi.CC_FULL_MATRIX if full_matrix else 0,
+                                               ctypes.c_void_p(labels.data_ptr()), ctypes.c_void_p(count.data_ptr()),
+                                               _stream_handle(stream)),
+          "mds_threshold_components")
+    return labels, count
+
+
+def euclidean_distances(X, dtype="f32", out=None, stream=None):
+    """D[i, j] = sqrt(sum_k (x_ik - x_jk)^2) in fp64, rounded to the output
+    type (mds_euclidean_distances).  X: CUDA float64 tensor n x dim."""
+    import torch
+
+    if X.dtype != torch.float64 or X.dim() != 2 or not X.is_cuda:
+        raise ValueError("X must be a CUDA float64 tensor of shape (n, dim)")
+    X = X.contiguous()
+    n, dim = X.shape
+    out, dt = _distance_out(n, dtype, out)
+    check(_capi.lib().mds_euclidean_distances(ctypes.c_void_p(X.data_ptr()), n, dim, dt,
+                                              ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+          "mds_euclidean_distances")
+    return out
 
 
 class Plan:

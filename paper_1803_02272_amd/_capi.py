@@ -48,6 +48,7 @@ FLAG_FULL_STATS = 8
 FLAG_CHECK_INPUT = 16
 FLAG_LOWP_ALL_RANGE = 32
 FLAG_FP32_PROJECTION = 64
+CC_FULL_MATRIX = 1
 
 
 class MdsOpts(ctypes.Structure):
@@ -139,6 +140,12 @@ SIGNATURES = {
                                     ctypes.POINTER(MdsTuneResult)]),
     "mds_destroy": (None, [ctypes.c_void_p]),
     "mds_philox4x64_10": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "mds_hamming_distances": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "mds_euclidean_distances": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.c_void_p, ctypes.c_void_p]),
+    "mds_threshold_components": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                                ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mds_batch_workspace_size": (ctypes.c_int, [ctypes.POINTER(MdsBatchJob), ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_size_t)]),
     "mds_run_batch": (ctypes.c_int, [ctypes.POINTER(MdsBatchJob), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,

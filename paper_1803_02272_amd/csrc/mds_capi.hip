@@ -748,6 +748,43 @@ mds_status mds_philox4x64_10(const uint64_t* in, uint64_t* out, int64_t count, v
   return hip_check(launch_philox(in, out, count, (hipStream_t)stream), "philox");
 }
 
+mds_status mds_hamming_distances(const uint8_t* codes, int64_t n, int32_t length, int32_t d_dtype, void* D,
+                                 void* stream) {
+  if (!codes || !D) return fail(MDS_ERR_INVALID_ARG, "NULL codes or D");
+  if (n < 1 || n > kMaxDistanceN) return fail(MDS_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (length < 1 || length > kMaxHammingLength)
+    return fail(MDS_ERR_INVALID_ARG, "length = %d out of range 1..%d", length, kMaxHammingLength);
+  if (d_dtype != MDS_DTYPE_F32 && d_dtype != MDS_DTYPE_F64) return fail(MDS_ERR_INVALID_ARG, "bad d_dtype");
+  const mds_status st = device_present();
+  if (st != MDS_OK) return st;
+  return hip_check(launch_hamming(codes, n, length, d_dtype == MDS_DTYPE_F64, D, (hipStream_t)stream),
+                   "hamming distances");
+}
+
+mds_status mds_euclidean_distances(const double* X, int64_t n, int32_t dim, int32_t d_dtype, void* D, void* stream) {
+  if (!X || !D) return fail(MDS_ERR_INVALID_ARG, "NULL X or D");
+  if (n < 1 || n > kMaxDistanceN) return fail(MDS_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (dim < 1 || dim > (1 << 20)) return fail(MDS_ERR_INVALID_ARG, "dim = %d out of range", dim);
+  if (d_dtype != MDS_DTYPE_F32 && d_dtype != MDS_DTYPE_F64) return fail(MDS_ERR_INVALID_ARG, "bad d_dtype");
+  const mds_status st = device_present();
+  if (st != MDS_OK) return st;
+  return hip_check(launch_euclid(X, n, dim, d_dtype == MDS_DTYPE_F64, D, (hipStream_t)stream), "euclidean distances");
+}
+
+mds_status mds_threshold_components(const void* D, int32_t d_dtype, int64_t n, double threshold, int32_t flags,
+                                    int32_t* labels, int64_t* n_components, void* stream) {
+  if (!D || !labels) return fail(MDS_ERR_INVALID_ARG, "NULL D or labels");
+  if (n < 1 || n > kMaxDistanceN) return fail(MDS_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (d_dtype != MDS_DTYPE_F32 && d_dtype != MDS_DTYPE_F64) return fail(MDS_ERR_INVALID_ARG, "bad d_dtype");
+  if (flags & ~MDS_CC_FULL_MATRIX) return fail(MDS_ERR_INVALID_ARG, "unknown flags 0x%x", (unsigned)flags);
+  if (threshold != threshold) return fail(MDS_ERR_INVALID_ARG, "NaN threshold");
+  const mds_status st = device_present();
+  if (st != MDS_OK) return st;
+  return hip_check(launch_components(D, d_dtype == MDS_DTYPE_F64, n, threshold, (flags & MDS_CC_FULL_MATRIX) != 0,
+                                     labels, n_components, (hipStream_t)stream),
+                   "threshold components");
+}
+
 void mds_destroy(mds_plan_t plan) {
   if (!plan) return;
   for (hipEvent_t e : plan->events) (void)hipEventDestroy(e);

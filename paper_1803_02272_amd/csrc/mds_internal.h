@@ -141,6 +141,28 @@ int split_pass_rows();
 int gstream_rows();
 hipError_t launch_gstream(const void* G, int64_t ldg, const void* Xt, int l_pad, const GPassCfg& cfg, int64_t n,
                           int64_t blocks, void* Yp, hipStream_t s);
+// Pairwise distances (k_dist.hip): D row-major n x n in fp32 or fp64.
+constexpr int kMaxHammingLength = 2048;
+constexpr int64_t kMaxDistanceN = 4000000;
+hipError_t launch_hamming(const uint8_t* codes, int64_t n, int L, bool f64, void* D, hipStream_t s);
+hipError_t launch_euclid(const double* X, int64_t n, int dim, bool f64, void* D, hipStream_t s);
+// Connected components of the threshold graph (k_cc.hip); n_components may be null.
+hipError_t launch_components(const void* D, bool f64, int64_t n, double theta, bool full, int32_t* labels,
+                             int64_t* n_components, hipStream_t s);
+// Tile (I, J), I <= J, of linear index t in the row-ordered upper triangle of
+// nt x nt tiles: row I starts at S(I) = I nt - I (I - 1) / 2; the largest I
+// with S(I) <= t from the root of the quadratic, corrected by whole steps.
+__device__ inline void upper_tile(int64_t t, int64_t nt, int64_t& I, int64_t& J) {
+  auto row_start = [&](int64_t r) { return r * nt - r * (r - 1) / 2; };
+  const double b2 = 2.0 * (double)nt + 1.0;
+  int64_t r = (int64_t)((b2 - __builtin_sqrt(b2 * b2 - 8.0 * (double)t)) * 0.5);
+  if (r < 0) r = 0;
+  if (r > nt - 1) r = nt - 1;
+  while (r > 0 && row_start(r) > t) --r;
+  while (r + 1 < nt && row_start(r + 1) <= t) ++r;
+  I = r;
+  J = r + (t - row_start(r));
+}
 // Zero the padding of the bf16 G (rows >= n, columns >= n) left by the fused write.
 hipError_t launch_split_zero_pad(void* G, int64_t n, int64_t n_pad, int64_t ldg, hipStream_t s);
 hipError_t launch_split_pass(int nterms, const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t blocks,

@@ -1,0 +1,115 @@
+"""The library's pairwise distances (mds_hamming_distances,
+mds_euclidean_distances; Sec. 2.2) against the CPU oracle, bit for bit:
+small and ragged sizes (several tiles and a partial one), unknown bases,
+every load and store path (aligned and unaligned codes and D, lengths that
+are and are not multiples of 16, fp32 and fp64 output), and at full size
+(n = 100,000 reads of length 400) the whole matrix against the input
+generator's own kernel plus sampled rows against the oracle."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import say
+from workloads import gpu as WG
+from oracle import distances as OD
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1803_02272_amd as mds  # noqa: E402
+from paper_1803_02272_amd import _capi  # noqa: E402
+
+NPDT = {"f32": np.float32, "f64": np.float64}
+
+
+def _codes(n, L, seed, unknown=0):
+    reads, _ = W.amplicon_reads(n, max(1, n // 50), length=L, seed=seed)
+    if unknown:
+        rng = np.random.default_rng(seed + 100)
+        i, p = rng.integers(0, n, unknown), rng.integers(0, L, unknown)
+        reads[i, p] = rng.choice(np.array([4, 7, 255], dtype=np.uint8), unknown)
+    return reads
+
+
+@pytest.mark.parametrize("n,L,unknown", [(1, 400, 0), (2, 16, 0), (7, 1, 0), (300, 400, 5), (1001, 37, 9),
+                                         (513, 400, 0), (260, 2048, 3)])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_hamming_matches_oracle(n, L, unknown, dtype):
+    say(f"[hamming] n={n} L={L} unknown={unknown} dtype={dtype}")
+    codes = _codes(n, L, seed=n + L, unknown=unknown)
+    want = OD.hamming(codes, NPDT[dtype])
+    got = mds.hamming_distances(torch.from_numpy(codes).cuda(), dtype=dtype).cpu().numpy()
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_hamming_unaligned_codes_and_output(dtype):
+    """Codes at an odd address and D at an address that is not 16-byte
+    aligned take the byte loads and the element stores: same bits."""
+    n, L = 301, 400
+    codes = _codes(n, L, seed=3)
+    want = OD.hamming(codes, NPDT[dtype])
+    flat = torch.zeros(n * L + 1, dtype=torch.uint8, device="cuda")
+    cview = flat[1:].view(n, L)
+    cview.copy_(torch.from_numpy(codes))
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    dflat = torch.zeros(n * n + 1, dtype=tdt, device="cuda")
+    dview = dflat[1:].view(n, n)
+    st = _capi.lib().mds_hamming_distances(cview.data_ptr(), n, L, 0 if dtype == "f32" else 1, dview.data_ptr(),
+                                           None)
+    assert st == _capi.OK
+    torch.cuda.synchronize()
+    assert np.array_equal(dview.cpu().numpy(), want)
+    assert dflat[0].item() == 0  # nothing written before D
+
+
+@pytest.mark.parametrize("n,dim", [(1, 3), (3, 1), (65, 50), (130, 2), (1001, 33), (300, 200)])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_euclidean_matches_oracle(n, dim, dtype):
+    say(f"[euclid] n={n} dim={dim} dtype={dtype}")
+    X, _ = W.gaussian_mixture(n, dim, 5, 9.0, seed=n + dim)
+    want = OD.euclidean(X, NPDT[dtype])
+    got = mds.euclidean_distances(torch.from_numpy(X).cuda(), dtype=dtype).cpu().numpy()
+    assert np.array_equal(got, want)
+
+
+def test_distance_argument_errors():
+    L = _capi.lib()
+    d = torch.zeros(4, dtype=torch.float32, device="cuda")
+    assert L.mds_hamming_distances(None, 2, 4, 0, d.data_ptr(), None) == _capi.ERR_INVALID_ARG
+    assert L.mds_hamming_distances(d.data_ptr(), 2, 0, 0, d.data_ptr(), None) == _capi.ERR_INVALID_ARG
+    assert L.mds_hamming_distances(d.data_ptr(), 2, 2049, 0, d.data_ptr(), None) == _capi.ERR_INVALID_ARG
+    assert L.mds_hamming_distances(d.data_ptr(), 0, 4, 0, d.data_ptr(), None) == _capi.ERR_INVALID_ARG
+    assert L.mds_euclidean_distances(d.data_ptr(), 2, 0, 0, d.data_ptr(), None) == _capi.ERR_INVALID_ARG
+    assert L.mds_euclidean_distances(d.data_ptr(), 2, 2, 3, d.data_ptr(), None) == _capi.ERR_INVALID_ARG
+
+
+@pytest.mark.slow
+def test_hamming_full_size_against_generator_and_oracle_rows():
+    n, L = 100000, 400
+    reads, _ = W.amplicon_reads(n, 200, seed=0)
+    t0 = time.time()
+    ref = WG.hamming_from_reads(reads)  # the input generator's popcount kernel
+    say(f"[hamming full] generator done ({time.time() - t0:.0f} s)")
+    codes = torch.from_numpy(reads).cuda()
+    D = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    mds.hamming_distances(codes, out=D)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    mds.hamming_distances(codes, out=D)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    say(f"[hamming full] {ms:.2f} ms: {n * n * 4 / ms / 1e6:.0f} GB/s written, "
+        f"{2.0 * n * n * 4 * L / ms / 1e9:.0f} TOPS (one-hot int8)")
+    assert torch.equal(D, ref)
+    del ref
+    rng = np.random.default_rng(5)
+    rows = rng.integers(0, n, 24)
+    got = D[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert np.array_equal(got, OD.hamming(reads, np.float32, rows=rows))
