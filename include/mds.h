@@ -243,7 +243,7 @@ mds_status mds_get_buffer(mds_plan_t plan, int32_t which, mds_buffer* out);
 typedef struct mds_info {
   int32_t status;            /* numerical outcome of the last run */
   int32_t nonfinite;         /* 1 if D contained NaN/Inf */
-  int32_t orth_fallbacks;    /* orthonormalisations that used the eigen fallback */
+  int32_t orth_fallbacks;    /* orthonormalisations that deflated (dropped) directions */
   int32_t jacobi_sweeps;     /* sweeps of the last small eigensolve */
   int32_t jacobi_unconverged;
   int32_t rank_deficient;    /* directions dropped by the last orthonormalisation */

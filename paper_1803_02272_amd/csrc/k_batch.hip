@@ -79,7 +79,7 @@ __host__ __device__ inline int64_t rup(int64_t v, int64_t m) { return (v + m - 1
 
 // Per-instance workspace (offsets in bytes from the instance base).
 struct BLayout {
-  int64_t r, c, hc, hr, G, X, Y, Q, V, total;
+  int64_t r, c, hc, hr, G, X, Y, Q, total;
 };
 
 __host__ __device__ inline BLayout blayout(int64_t np, int l_pad, int form) {
@@ -95,7 +95,6 @@ __host__ __device__ inline BLayout blayout(int64_t np, int l_pad, int form) {
   L.X = o, o += rup((int64_t)l_pad * np * xsz, 256);
   L.Y = o, o += rup((int64_t)l_pad * np * 8, 256);
   L.Q = o, o += rup((int64_t)l_pad * np * 8, 256);
-  L.V = o, o += rup((int64_t)kBMaxL * kBMaxL * 8, 256);
   L.total = o;
   return L;
 }
@@ -350,20 +349,19 @@ struct BShared {
   double V[kBMaxL * kBMaxL];  // eigenvectors of B (gfx950: up to 160 KB of LDS per workgroup)
   double P[kBMaxL * kNB];
   double wdiag[kBMaxL];
-  double scl[kBMaxL];
   double th[kBMaxL];
   int perm[kBMaxL];
-  int flag, dropped;
+  int defl[kBMaxL];
+  int dropped;
   double best_v[kBT / 64];
   int64_t best_i[kBT / 64];
 };
 
 // T with (Yt)^T T orthonormal from M = W = Y^T Y (in LDS): Cholesky and
-// inverse, the first-order factor of an almost orthonormal basis, or the
-// eigen fallback V S^{-1/2} with V in global scratch.  Leaves the full T
-// in M (strictly lower part zero in the triangular cases).
-__device__ void block_factor(BShared& S, int l, int l_pad, bool near_identity, const double* Yt, int64_t np,
-                             double* Vg, DevStatus* st) {
+// inverse (deflating collapsed pivots: those columns of Q are zero), or the
+// first-order factor of an almost orthonormal basis.  Leaves the full T in M
+// (strictly lower part zero).
+__device__ void block_factor(BShared& S, int l, int l_pad, bool near_identity, DevStatus* st) {
   lds_double* M = (lds_double*)(void*)S.M;
   const int tid = threadIdx.x;
   const int ldm = kBMaxL;
@@ -390,53 +388,23 @@ __device__ void block_factor(BShared& S, int l, int l_pad, bool near_identity, c
       return;
     }
   }
-  if (chol_blocked<kBT>(M, ldm, l, S.wdiag, &S.flag)) {
-    trinv_blocked<kBT>(M, ldm, l, S.P);
-    for (int e = tid; e < l_pad * l_pad; e += kBT) {
-      const int i = e / l_pad, j = e % l_pad;
-      if (j < i || i >= l || j >= l) M[i * ldm + j] = 0.0;
-    }
-    __syncthreads();
-    return;
-  }
-  // fallback: eigendecomposition of W (recomputed), T = V diag(s^{-1/2})
-  __syncthreads();
-  constexpr int ldj = kBMaxL + 1;  // odd: the Jacobi's (min, max) accesses spread over LDS banks
-  block_gram(Yt, Yt, np, l_pad, M, ldj);
-  for (int e = tid; e < kBMaxL * kBMaxL; e += kBT) {
-    const int i = e / kBMaxL, j = e % kBMaxL;
-    Vg[e] = (i == j) ? 1.0 : 0.0;
-    if (i >= l || j >= l) M[i * ldj + j] = 0.0;
-  }
-  __syncthreads();
-  int rounds = 0;
-  jacobi<kBT>(M, ldj, Vg, kBMaxL, (double2*)nullptr, l + (l & 1), S.sh, &rounds);
-  __syncthreads();
-  double smax = -1.0;
-  for (int i = tid; i < l; i += kBT) smax = fmax(smax, M[i * ldj + i]);
-  smax = block_max<kBT>(smax, S.sh.red);
   if (tid == 0) S.dropped = 0;
   __syncthreads();
-  for (int i = tid; i < l; i += kBT) {
-    const double sv = M[i * ldj + i];
-    const bool keep = smax > 0.0 && sv > 1e-13 * smax;
-    S.scl[i] = keep ? 1.0 / sqrt(sv) : 0.0;
-    if (!keep) atomicAdd(&S.dropped, 1);
-  }
-  __syncthreads();
-  for (int e = tid; e < kBMaxL * kBMaxL; e += kBT) {
-    const int i = e / kBMaxL, j = e % kBMaxL;
-    M[e] = (i < l && j < l) ? Vg[e] * S.scl[j] : 0.0;
+  chol_blocked<kBT>(M, ldm, l, S.wdiag, S.defl, &S.dropped);
+  trinv_blocked<kBT>(M, ldm, l, S.P);
+  for (int e = tid; e < l_pad * l_pad; e += kBT) {
+    const int i = e / l_pad, j = e % l_pad;
+    if (j < i || i >= l || j >= l || S.defl[j]) M[i * ldm + j] = 0.0;  // dropped columns: zero in Q
   }
   __syncthreads();
   if (tid == 0) {
-    atomicAdd(&st->orth_fallbacks, 1);
     st->rank_deficient = S.dropped;
+    if (S.dropped) atomicAdd(&st->orth_fallbacks, 1);
   }
 }
 
 // CholeskyQR2 of Yt into Qt (fp64) with a cast copy of Q into X (kind xk).
-__device__ void block_orth(BShared& S, const BJob& J, double* Yt, double* Qt, double* Vg, void* X, int xk) {
+__device__ void block_orth(BShared& S, const BJob& J, double* Yt, double* Qt, void* X, int xk) {
   lds_double* M = (lds_double*)(void*)S.M;
   const int64_t np = J.n_pad;
   for (int step = 0; step < 2; ++step) {
@@ -444,7 +412,7 @@ __device__ void block_orth(BShared& S, const BJob& J, double* Yt, double* Qt, do
     __syncthreads();
     block_gram(In, In, np, J.l_pad, M, kBMaxL);
     __syncthreads();
-    block_factor(S, J.l, J.l_pad, step == 1, In, np, Vg, J.st);
+    block_factor(S, J.l, J.l_pad, step == 1, J.st);
     __syncthreads();
     // step 0 writes Q1 over Y (In = Yt, Out = Qt would alias in step 1), so:
     // step 0: Qt = Y T; step 1: Yt = Qt T, then the result is copied back
@@ -546,7 +514,6 @@ __device__ void batch_instance(const BJob& J, BShared& S) {
   void* X = J.ws + Lo.X;
   double* Yt = (double*)(J.ws + Lo.Y);
   double* Qt = (double*)(J.ws + Lo.Q);
-  double* Vg = (double*)(J.ws + Lo.V);
   constexpr int GK = FORM == MDS_FORM_FP64 ? GK_F64 : (FORM == MDS_FORM_FP32 ? GK_F32 : GK_BF16);
   constexpr int PK = FORM == MDS_FORM_FP64 ? GK_F64 : GK_F32;  // projection operand
   // the bf16 form's first and last range passes recentre D in fp32 (like its
@@ -608,7 +575,7 @@ __device__ void batch_instance(const BJob& J, BShared& S) {
     else
       block_gpass<GK, false, KU>(J, G, X, Yt, hc, hr);
     const int next = it == passes - 1 ? PK : (f32_pass(it + 1) ? (int)GK_F32 : GK);
-    block_orth(S, J, Yt, Qt, Vg, X, next);
+    block_orth(S, J, Yt, Qt, X, next);
   }
   // ---- projection B = Q^T G Q ------------------------------------------------
   if constexpr (FORM == MDS_FORM_BF16)

@@ -4,11 +4,12 @@
 //                Cholesky W = R^T R and T = R^{-1} (one CholeskyQR step;
 //                applied twice this is CholeskyQR2, Fukaya et al. 2014).  In
 //                the second step W is I + E with tiny E; when max|E| < 1e-9
-//                the factor is I - triu(E) (diagonal E/2), exact to O(E^2).  When
-//                a pivot collapses (rank-deficient or too ill-conditioned Y)
-//                it falls back to the eigendecomposition W = V S V^T and
-//                T = V S^{-1/2}, dropping directions with s <= 1e-13 s_max, so
-//                those columns of Q become exactly zero.  For l_pad <= 128 the
+//                the factor is I - triu(E) (diagonal E/2), exact to O(E^2).  A
+//                pivot that collapses (a column of Y within 1e-7 of the span
+//                of the earlier ones: rank-deficient or too ill-conditioned
+//                Y) deflates its column, which becomes exactly zero in Q, and
+//                the factorization goes on (no eigen fallback: a rank-
+//                deficient Y costs no more than a full-rank one).  For l_pad <= 128 the
 //                Cholesky and the inverse keep the matrix in registers of a
 //                1024-thread workgroup, 256 threads for l_pad <= 64
 //                (right-looking, one barrier per column; then barrier-free
@@ -51,48 +52,6 @@ static_assert(kSmallLMax % 64 == 0 && (kOrthRegThreadsSmall / kSmallLMax) * kSma
 static_assert(kOrthRegThreads / kLdsMaxL <= 64 && (kOrthRegThreads / kLdsMaxL) * kLdsMaxL == kOrthRegThreads,
               "the lanes of one column share a wave");
 
-// Eigen fallback of orth_factor: T = V diag(s^{-1/2}) over the retained
-// eigen-directions of W (V accumulated in global scratch, M with an odd ld
-// ldj in LDS).  Out of line, so the register needs of the Jacobi with V do
-// not weigh on the Cholesky path of the same kernel.
-template <int NT, typename MT>
-__device__ __attribute__((noinline)) void orth_fallback(const double* __restrict__ W, int l, int l_pad,
-                                                        double* __restrict__ T, MT M, int ldj, double* V,
-                                                        JacobiShared& sh, double* scale, int* dropped,
-                                                        DevStatus* st) {
-  const int tid = threadIdx.x;
-  const int le = l + (l & 1);
-  __syncthreads();
-  for (int i = tid / 64; i < l_pad; i += NT / 64)
-    for (int j = tid % 64; j < l_pad; j += 64) {
-      M[i * ldj + j] = (i < l && j < l) ? W[i * l_pad + j] : 0.0;
-      V[i * l_pad + j] = (i == j) ? 1.0 : 0.0;
-    }
-  __syncthreads();
-  int rounds = 0;
-  jacobi<NT>(M, ldj, V, l_pad, (double2*)nullptr, le, sh, &rounds);
-  __syncthreads();
-  double smax = -1.0;
-  for (int i = tid; i < l; i += NT) smax = fmax(smax, M[i * ldj + i]);
-  smax = block_max<NT>(smax, sh.red);
-  if (tid == 0) *dropped = 0;
-  __syncthreads();
-  for (int i = tid; i < l; i += NT) {
-    const double sv = M[i * ldj + i];
-    const bool keep = smax > 0.0 && sv > 1e-13 * smax;
-    scale[i] = keep ? 1.0 / sqrt(sv) : 0.0;
-    if (!keep) atomicAdd(dropped, 1);
-  }
-  __syncthreads();
-  for (int i = tid / 64; i < l_pad; i += NT / 64)
-    for (int j = tid % 64; j < l_pad; j += 64)
-      T[i * l_pad + j] = (i < l && j < l) ? V[i * l_pad + j] * scale[j] : 0.0;
-  if (tid == 0) {
-    atomicAdd(&st->orth_fallbacks, 1);
-    st->rank_deficient = *dropped;
-  }
-}
-
 template <bool IN_LDS, int NT>
 __global__ __launch_bounds__(NT) void k_orth_factor(const double* __restrict__ W, int l, int l_pad,
                                                      double* __restrict__ T, double* __restrict__ scratch,
@@ -101,13 +60,12 @@ __global__ __launch_bounds__(NT) void k_orth_factor(const double* __restrict__ W
   __shared__ double Ml[IN_LDS ? kLdsMaxL * (kLdsMaxL + 1) : 1];  // ld l_pad + 1 (R, then the Jacobi)
   __shared__ double wdiag[kMaxL];
   __shared__ double P[IN_LDS ? 1 : kMaxL * kNB];
-  __shared__ double scale[kMaxL];
   __shared__ __attribute__((aligned(16))) double colbuf[IN_LDS ? 2 * kLdsMaxL : 1];
   __shared__ double rdinv[IN_LDS ? kMaxL : 1];
-  __shared__ int flag, dropped;
+  __shared__ int defl[IN_LDS ? 1 : kMaxL];
+  __shared__ int ndefl;
   using MT = typename std::conditional<IN_LDS, lds_double*, double*>::type;
   MT M = IN_LDS ? (MT)(void*)Ml : (MT)(void*)scratch;
-  double* V = scratch + (IN_LDS ? 0 : (int64_t)l_pad * l_pad);
   const int tid = threadIdx.x;
   const int ldm = IN_LDS ? l_pad + 1 : l_pad;  // odd in LDS: column reads of R spread over banks
 
@@ -115,6 +73,7 @@ __global__ __launch_bounds__(NT) void k_orth_factor(const double* __restrict__ W
     for (int i = tid / 64; i < l_pad; i += NT / 64)
       for (int j = tid % 64; j < l_pad; j += 64) M[i * ldm + j] = (i < l && j < l) ? W[i * l_pad + j] : 0.0;
   for (int i = tid; i < l; i += NT) wdiag[i] = W[i * l_pad + i];
+  if (tid == 0) ndefl = 0;
   __syncthreads();
 
   if (near_identity) {
@@ -141,23 +100,20 @@ __global__ __launch_bounds__(NT) void k_orth_factor(const double* __restrict__ W
   }
 
   if constexpr (IN_LDS) {
-    if (chol_reg<NT>(W, l_pad, M, ldm, l, wdiag, colbuf, rdinv)) {
-      trinv_reg<NT>(M, ldm, l, rdinv, T, l_pad);
-      if (tid == 0) st->rank_deficient = 0;
-      return;
-    }
+    chol_reg<NT>(W, l_pad, M, ldm, l, wdiag, colbuf, rdinv, &ndefl);
+    trinv_reg<NT>(M, ldm, l, rdinv, T, l_pad);  // zero rows and columns of the dropped
   } else {
-    if (chol_blocked<NT>(M, ldm, l, wdiag, &flag)) {
-      trinv_blocked<NT>(M, ldm, l, P);
-      for (int i = tid / 64; i < l_pad; i += NT / 64)
-        for (int j = tid % 64; j < l_pad; j += 64)
-          T[i * l_pad + j] = (i < l && j < l && j >= i) ? M[i * ldm + j] : 0.0;
-      if (tid == 0) st->rank_deficient = 0;
-      return;
-    }
+    chol_blocked<NT>(M, ldm, l, wdiag, defl, &ndefl);
+    trinv_blocked<NT>(M, ldm, l, P);
+    for (int i = tid / 64; i < l_pad; i += NT / 64)
+      for (int j = tid % 64; j < l_pad; j += 64)
+        T[i * l_pad + j] = (i < l && j < l && j >= i && !defl[j]) ? M[i * ldm + j] : 0.0;
   }
-
-  orth_fallback<NT>(W, l, l_pad, T, M, IN_LDS ? l_pad + 1 : l_pad, V, sh, scale, &dropped, st);
+  __syncthreads();
+  if (tid == 0) {
+    st->rank_deficient = ndefl;
+    if (ndefl) atomicAdd(&st->orth_fallbacks, 1);
+  }
 }
 
 // ---- Rayleigh-Ritz eigensolve ---------------------------------------------

@@ -41,7 +41,7 @@ constexpr int kLdsMaxL = 128;  // small kernels keep an l x l fp64 matrix in LDS
 // Device-side status words (written by kernels, read back by the host).
 struct DevStatus {
   int nonfinite;        // D produced a non-finite sum of squares
-  int orth_fallbacks;   // orthonormalisations that left the Cholesky path
+  int orth_fallbacks;   // orthonormalisations that deflated directions
   int jacobi_sweeps;    // sweeps used by the last eigensolve
   int jacobi_unconv;    // eigensolves that hit the sweep cap
   int rank_deficient;   // last orthonormalisation dropped directions

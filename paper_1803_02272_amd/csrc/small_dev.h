@@ -17,6 +17,14 @@ constexpr int kSmallLMax = 64;              // l_pad up to which orth_factor run
 constexpr int kOrthRegThreadsSmall = 256;   // orth_factor workgroup, l_pad <= kSmallLMax
 constexpr int kRegSlots = 16;  // rows per thread of the register-resident factor
 constexpr int kNB = 16;            // panel width of the blocked Cholesky / inverse
+// Deflation of the orthonormalisation factor: a Cholesky pivot of W = Y^T Y
+// at or below kDeflate times its column's diagonal entry of W (column j of Y
+// keeps a relative residual of at most 1e-7 after the earlier columns are
+// projected out), or not positive, drops column j: its row of R is e_j, no
+// later column is updated with it, and T = R^{-1} gets a zero row and column
+// j (column j of Q is exactly zero).  The kept columns have a condition
+// number below about 1e7, inside CholeskyQR2's range (u^{-1/2}).
+constexpr double kDeflate = 1e-14;
 constexpr int kMaxPairs = kMaxL / 2;
 constexpr int kMaxSweeps = 40;
 
@@ -261,16 +269,16 @@ __device__ int jacobi(MT M, int ldm, double* V, int ldv, double2* rot, int le, J
 // Blocked right-looking Cholesky W = R^T R (upper R in M).  Panel rows
 // [k0, k0+16) are factored by wave 0 alone (wave-synchronous, no workgroup
 // barrier); the trailing update M22 -= R12^T R12 is done by all threads with
-// 4x4 register tiles.  Returns false (uniformly) on a collapsed pivot.
+// 4x4 register tiles.  Deflates collapsed pivots (kDeflate): defl[j] = 1 for
+// a dropped column (its row of R is e_j), *ndefl counts them.
 template <int NT, typename MT>
-__device__ bool chol_blocked(MT M, int ldm, int l, const double* wdiag, int* flag) {
+__device__ void chol_blocked(MT M, int ldm, int l, const double* wdiag, int* defl, int* ndefl) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int k0 = 0; k0 < l; k0 += kNB) {
     const int nb = (l - k0 < kNB) ? l - k0 : kNB;
     if (wave == 0) {
       // left-looking inside the panel: row kk of R from the finished panel
       // rows above it (loads only, then one store per entry)
-      int ok = 1;
       for (int kk = k0; kk < k0 + nb; ++kk) {
         const int nm = kk - k0;  // finished rows in this panel
         // loads are unconditional from in-bounds addresses (k0 + 15 < l_pad,
@@ -295,23 +303,22 @@ __device__ bool chol_blocked(MT M, int ldm, int l, const double* wdiag, int* fla
         double piv = M[kk * ldm + kk];
 #pragma unroll
         for (int m = 0; m < kNB; ++m) piv -= col[m] * col[m];
-        if (!(piv > 1e-12 * wdiag[kk]) || !(piv > 0.0)) {
-          ok = 0;
-          break;  // uniform within the wave
-        }
-        const double rkk = sqrt(piv), rinv = 1.0 / rkk;
+        const bool drop = !(piv > kDeflate * wdiag[kk]) || !(piv > 0.0);  // uniform within the wave
+        const double rkk = drop ? 1.0 : sqrt(piv), rinv = 1.0 / rkk;
 #pragma unroll
         for (int c = 0; c < kMaxJ; ++c) {
           const int j = kk + 1 + lane + 64 * c;
-          if (j < l) M[kk * ldm + j] = row[c] * rinv;
+          if (j < l) M[kk * ldm + j] = drop ? 0.0 : row[c] * rinv;
         }
-        if (lane == 0) M[kk * ldm + kk] = rkk;
+        if (lane == 0) {
+          M[kk * ldm + kk] = rkk;
+          defl[kk] = drop ? 1 : 0;
+          if (drop) ++*ndefl;
+        }
         wave_sync();
       }
-      if (lane == 0) *flag = ok;
     }
     __syncthreads();
-    if (!*flag) return false;
     const int t0 = k0 + nb;
     if (t0 < l) {
       const int ty = tid / 16, tx = tid % 16;  // NT == 256
@@ -353,7 +360,6 @@ __device__ bool chol_blocked(MT M, int ldm, int l, const double* wdiag, int* fla
     }
     __syncthreads();
   }
-  return true;
 }
 
 // In-place blocked inverse of the upper triangular R in M (T = R^{-1}).  For
@@ -440,11 +446,13 @@ __device__ void trinv_blocked(MT M, int ldm, int l, double* P /* kMaxL x kNB, LD
 // once at the end (its pivot is the value its own row held when it became
 // the pivot column; later steps do not touch it).  Rows i < j of a column
 // are never read back.  Writes R (upper triangle, ld ldm) into M and
-// 1/R[j][j] into rdinv.  Returns false (uniformly) on a pivot below
-// 1e-12 wdiag[k] (or not positive), the same test as chol_blocked.
+// 1/R[j][j] into rdinv.  Deflates collapsed pivots as chol_blocked (the same
+// test): a dropped column updates no other column, its row of R is e_j and
+// rdinv[j] = 0, so that trinv_reg returns T with row and column j zero;
+// *ndefl counts the dropped columns.
 template <int NT, typename MT>
-__device__ bool chol_reg(const double* __restrict__ W, int ldw, MT M, int ldm, int l, const double* wdiag,
-                         double* colbuf, double* rdinv) {
+__device__ void chol_reg(const double* __restrict__ W, int ldw, MT M, int ldm, int l, const double* wdiag,
+                         double* colbuf, double* rdinv, int* ndefl) {
   const int tid = threadIdx.x;
   const int cw = (l + 63) & ~63;
   const int rpc = NT / cw;
@@ -467,17 +475,19 @@ __device__ bool chol_reg(const double* __restrict__ W, int ldw, MT M, int ldm, i
   for (int k = 0; k < l; ++k) {
     const double* cb = colbuf + (k & 1) * kLdsMaxL;
     const double piv = cb[k], wk = wdiag[k], cj = cb[j < l ? j : 0];
-    if (!(piv > 1e-12 * wk) || !(piv > 0.0)) return false;
+    const bool drop = !(piv > kDeflate * wk) || !(piv > 0.0);  // uniform
     if (j > k && j < l) {
-      double rp = rcp_newton(piv);
-      if (!(piv > 1e-290)) rp = 1.0 / piv;  // uniform; the estimate is for normal arguments
-      const double ajk = cj * rp;
+      if (!drop) {
+        double rp = rcp_newton(piv);
+        if (!(piv > 1e-290)) rp = 1.0 / piv;  // uniform; the estimate is for normal arguments
+        const double ajk = cj * rp;
 #pragma unroll
-      for (int p = 0; p < kRegSlots / 2; ++p) {  // rows of this thread in 16-byte pairs
-        const int i0 = 2 * h + 2 * rpc * p;
-        const double2 v = *(const double2*)(cb + (i0 < kLdsMaxL - 2 ? i0 : kLdsMaxL - 2));
-        if (i0 >= j && i0 < l) a[2 * p] -= v.x * ajk;
-        if (i0 + 1 >= j && i0 + 1 < l) a[2 * p + 1] -= v.y * ajk;
+        for (int p = 0; p < kRegSlots / 2; ++p) {  // rows of this thread in 16-byte pairs
+          const int i0 = 2 * h + 2 * rpc * p;
+          const double2 v = *(const double2*)(cb + (i0 < kLdsMaxL - 2 ? i0 : kLdsMaxL - 2));
+          if (i0 >= j && i0 < l) a[2 * p] -= v.x * ajk;
+          if (i0 + 1 >= j && i0 + 1 < l) a[2 * p + 1] -= v.y * ajk;
+        }
       }
       if (j == k + 1) {  // publish the finished column k + 1
         double* nb = colbuf + ((k + 1) & 1) * kLdsMaxL;
@@ -494,15 +504,19 @@ __device__ bool chol_reg(const double* __restrict__ W, int ldw, MT M, int ldm, i
 #pragma unroll
   for (int s = 0; s < kRegSlots; ++s) pj = (row(s) == j) ? a[s] : pj;
   for (int o = 1; o < rpc; o <<= 1) pj += __shfl_xor(pj, o, 64);
-  const double rs = (j < l) ? 1.0 / sqrt(pj) : 0.0;
+  // the same pivot and test as at step j
+  const bool dropj = j < l && (!(pj > kDeflate * wdiag[j]) || !(pj > 0.0));
+  const double rs = (j < l && !dropj) ? 1.0 / sqrt(pj) : 0.0;
 #pragma unroll
   for (int s = 0; s < kRegSlots; ++s) {
     const int i = row(s);
-    if (j < l && i < l && i >= j) M[j * ldm + i] = (i == j) ? pj * rs : a[s] * rs;
+    if (j < l && i < l && i >= j) M[j * ldm + i] = dropj ? (i == j ? 1.0 : 0.0) : ((i == j) ? pj * rs : a[s] * rs);
   }
-  if (j < l && h == 0) rdinv[j] = rs;
+  if (j < l && h == 0) {
+    rdinv[j] = rs;
+    if (dropj) atomicAdd(ndefl, 1);
+  }
   __syncthreads();
-  return true;
 }
 
 // T = R^{-1} for the upper R in M (ld ldm) with 1/R[m][m] in rdinv, written
