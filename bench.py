@@ -4,14 +4,16 @@
 Workload: synthetic amplicon reads standing in for the Lake Geneva rbcL
 sample of the paper (200 random references of length 400, n = 100,000
 reads with 1-5 % substitutions; D = Hamming / 400 in fp32, 40 GB, generated
-on the GPU), k = 100 axes, oversample 20, q = 2 power iterations.
+by the library's own distance kernel), k = 100 axes, oversample 20, q = 2
+power iterations.
 
 A step is one complete run of the method through the C ABI with D resident
 in HBM: centring, test matrix, 2q+1 orthonormalised range passes, the
 projection pass, the small eigensolve and the coordinates.  The headline
 value is the BF16 form's time per MDS; the FP32 form is timed beside it, an
 FP64-form run is the accuracy reference, and the FP64 CPU oracle is timed on
-a bounded sample.
+a bounded sample.  The distance kernel that writes D and the threshold-graph
+components on the same D are timed once each beside the MDS step.
 
 Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
 """
@@ -28,24 +30,30 @@ sys.path.insert(0, ROOT)
 
 METRIC = "n=1e5 k=100 MDS time & MFMA util, BF16 vs FP32 @1e-3 eig err; p99 latency"
 
-# HBM bytes per launch of the G-pass kernels, from rocprofv3 FETCH_SIZE and
+# HBM bytes per launch of the pass kernels, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE scaled by a plain copy of known size (profiles/
-# mds_n100000_amplicon_k100_bf16_fp32_profile.md), on the n = 1e5, l_pad = 128
-# workload.  Valid only while the kernel source is the one measured: the
-# sha256 prefix of the file is checked and `traffic` is null otherwise.
+# mds_n100000_amplicon_k100_bf16_fp32s_profile.md), on the n = 1e5, l_pad = 128
+# workload, bf16 form.  Valid only while the kernel source is the one
+# measured: the sha256 prefix of the file is checked and `traffic` is null
+# otherwise.
+_KS = {"source": "paper_1803_02272_amd/csrc/k_split.hip", "sha256_16": "6e44ddec6afe3c5b",
+       "n": 100000, "l_pad": 128, "form": "bf16"}
 TRAFFIC = {
-    # range pass over the stored bf16 G; FETCH_SIZE at split-K 3, WRITE_SIZE
-    # (split-K partials) at split-K 8: the autotuner chose those in the two runs
-    "gpass": {"source": "paper_1803_02272_amd/csrc/k_gpass.hip", "sha256_16": "27b651db8e41ac0e",
-              "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 23.064, "write_gb": 0.446},
-    # symmetric fp32 projection as three-term bf16 split (k_gpass_x3d), split-K 16 / 12
-    "gpass_ref": {"source": "paper_1803_02272_amd/csrc/k_gpass.hip", "sha256_16": "27b651db8e41ac0e",
-                  "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 23.765, "write_gb": 0.337},
+    # fused centring write + 16-bit range pass 1 (k_split<kWrite, 2 terms>)
+    "write": dict(_KS, fetch_gb=42.487, write_gb=20.952),
+    # 16-bit last range pass from D (k_split<kFull, 2 terms>)
+    "gpass_f32": dict(_KS, fetch_gb=41.853, write_gb=0.684),
+    # 16-bit symmetric projection (k_split<kSym, 2 terms>)
+    "gpass_ref": dict(_KS, fetch_gb=22.141, write_gb=0.443),
+    # range pass over the stored bf16 G (k_gstream)
+    "gpass": {"source": "paper_1803_02272_amd/csrc/k_gstream.hip", "sha256_16": "52fc14276cfd36ee",
+              "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 20.588, "write_gb": 0.155},
 }
 
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
+PEAK_INT8_TOPS = 5000.0
 
 
 def measured_traffic(name, n, l_pad, form):
@@ -74,9 +82,10 @@ def percentile(xs, p):
 
 
 # Benchmark variants: name -> Plan keyword arguments.  "bf16" and "fp8" are
-# the library's default schedules (fp32 first and last range pass); "bf16a"
-# and "fp8a" run every range pass on the stored G (MDS_FLAG_LOWP_ALL_RANGE);
-# "fp32s" is the fp32 form with every pass as the three-term bf16 split.
+# the library's default schedules (16-bit first and last range pass and
+# projection, two-term bf16 splits); "bf16a" and "fp8a" run every range pass
+# on the stored G (MDS_FLAG_LOWP_ALL_RANGE); "fp32s" is the fp32 form with
+# every pass as the three-term bf16 split.
 VARIANTS = {
     "bf16": dict(form="bf16"), "bf16a": dict(form="bf16", lowp_all_range=True),
     "fp8": dict(form="fp8"), "fp8a": dict(form="fp8", lowp_all_range=True),
@@ -258,6 +267,41 @@ def burst_bench(mds, torch, wgpu, jobs, n_lo, n_hi, budget_gb, slots, max_batch,
     return out
 
 
+def _event_ms(torch, fn, reps=3):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def time_distances(mds, torch, codes, D):
+    """mds_hamming_distances writing the benchmark's D: n^2 fp32 entries
+    written, 2 n^2 (4 L) int8 MFMA operations (one-hot inner products)."""
+    n, L = codes.shape
+    ms = _event_ms(torch, lambda: mds.hamming_distances(codes, out=D))
+    wbytes, ops = 4.0 * n * n, 2.0 * n * n * 4 * L
+    return {"kernel": "k_hamming (one-hot int8 MFMA 16x16x64, D written in fp32)", "ms": ms, "n": n, "length": L,
+            "write_gbs": wbytes / ms / 1e6, "hbm_frac": wbytes / ms / 1e6 / PEAK_HBM_GBS,
+            "int8_tops": ops / ms / 1e9, "int8_frac": ops / ms / 1e9 / PEAK_INT8_TOPS}
+
+
+def time_components(mds, torch, D, theta):
+    """mds_threshold_components over the upper triangle of D: 2 n (n - 1)
+    bytes of fp32 entries read."""
+    n = D.shape[0]
+    out = {}
+    ms = _event_ms(torch, lambda: out.update(r=mds.threshold_components(D, theta)))
+    nbytes = 2.0 * n * (n - 1)
+    return {"kernel": "k_cc_tiles (LDS + global union-find over the upper triangle)", "ms": ms,
+            "threshold": theta, "components": int(out["r"][1].item()), "read_gbs": nbytes / ms / 1e6,
+            "hbm_frac": nbytes / ms / 1e6 / PEAK_HBM_GBS}
+
+
 def cpu_baseline(D, n, k, p, q, sample_rows):
     """The FP64 row-blocked oracle, as it stands, on a bounded sample of the
     benchmark workload itself (n = the benchmark's n, the same D copied to
@@ -344,6 +388,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--cc-threshold", type=float, default=0.03,
+                    help="threshold of the components measurement (distance units)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only time a plain device-to-device copy of MIB MiB (stream bandwidth, and the "
                          "known-size reference for the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -368,8 +414,17 @@ def main():
     l = k + p
     log(f"[bench] generating amplicon D n={n} refs={args.refs} on the GPU")
     t0 = time.perf_counter()
-    D = wgpu.amplicon_distances(n, args.refs, seed=0)
+    from workloads import amplicon_reads
+
+    reads, _ = amplicon_reads(n, args.refs, seed=0)
+    codes = torch.from_numpy(reads).cuda()
+    D = mds.hamming_distances(codes)
+    torch.cuda.synchronize()
     log(f"[bench] D ready in {time.perf_counter() - t0:.1f} s")
+    distances = time_distances(mds, torch, codes, D)
+    log(f"[bench] hamming distances: {distances}")
+    components = time_components(mds, torch, D, args.cc_threshold)
+    log(f"[bench] threshold components: {components}")
 
     forms = [f for f in args.forms.split(",") if f]
     for f in forms:
@@ -398,16 +453,17 @@ def main():
     # padded l_pad only in the executed MFMA counts):
     #   stats      reads the tiles of D on and above the diagonal: 2 n^2 bytes
     #   write      fused centring write + first range pass (bf16 form): reads
-    #              D (4 n^2), writes the bf16 G (2 n^2); the pass is fp32 as a
-    #              three-term split (6 bf16 products per entry) by default,
-    #              a bf16 pass in the bf16a variant
+    #              D (4 n^2), writes the bf16 G (2 n^2); the pass is 16-bit
+    #              (two-term split, 3 bf16 products per entry) by default, a
+    #              bf16 pass in the bf16a variant
     #   gpass      a range pass over the stored G (bf16 2 n^2 / fp8 n^2 bytes)
     #              or over D recentred on the fly (fp32, fp64 forms: 4 n^2)
-    #   gpass_f32  an fp32 end range pass of the bf16/fp8 forms from D
-    #              (4 n^2 bytes, 6 bf16 products per entry)
+    #   gpass_f32  the 16-bit last range pass of the bf16/fp8 forms from D
+    #              (4 n^2 bytes, 3 bf16 products per entry)
     #   gpass_ref  the symmetric projection: the upper triangle of D (2 n^2
-    #              bytes), n^2 l useful flops (six bf16 products per entry
-    #              when split)
+    #              bytes), n^2 l useful flops (3 bf16 products per entry for
+    #              the 16-bit projection of the bf16/fp8 forms, 6 for the
+    #              fp32 split of fp32s)
     # plus the tall operand and the fp32 split-K partials per pass
     # (n l (x_bytes + 4)).
     l_pad = (l + 15) // 16 * 16
@@ -417,35 +473,43 @@ def main():
         return form in ("bf16", "bf16a", "fp8", "fp8a", "fp32s")
 
     def kernel_model(form, phase):
-        """(bytes, algorithmic flops, executed MFMA flops, MFMA dtype, label) per launch."""
+        """(bytes, algorithmic flops, executed MFMA flops, MFMA dtype, label) per launch.  Algorithmic
+        flops are the method's (2 n^2 l per range product, n^2 l for the symmetric projection);
+        executed MFMA flops count the padded l and every product of a split (3 for two terms, 6 for
+        three)."""
         base = VARIANTS[form]["form"]
+        lowp = base in ("bf16", "fp8")
         if phase == "stats":
-            return 2.0 * n * n, 0.0, 0.0, None, "k_stats (centring statistics)"
+            return 2.0 * n * n, 0.0, 0.0, None, "k_stats (centring statistics, upper-triangle tiles)"
         if phase == "write":
             if form == "bf16":
-                return (6.0 * n * n + n * l * (6 + 4), 6 * 2.0 * n * n * l, 6 * 2.0 * n * n * l_pad, "bf16",
-                        "k_gpass_x3<WG> (fused centring write + fp32 split range pass 1)")
+                return (6.0 * n * n + n * l * (6 + 4), 2.0 * n * n * l, 3 * 2.0 * n * n * l_pad, "bf16",
+                        "k_split<kWrite, 2 terms> (fused centring write + 16-bit range pass 1)")
             if form == "bf16a":
                 return (6.0 * n * n + n * l * (2 + 4), 2.0 * n * n * l, 2.0 * n * n * l_pad, "bf16",
                         "k_gpass<bf16, from D> (fused centring write + bf16 range pass 1)")
             return 5.0 * n * n, 0.0, 0.0, None, "k_center_write_fp8"
         if phase == "gpass":
-            if base in ("bf16", "fp8"):
+            if lowp:
                 gb = 2 if base == "bf16" else 1
-                return (gb * n * n + n * l * (2 + 4), 2.0 * n * n * l, 2.0 * n * n * l_pad, "bf16",
-                        f"k_gpass<{base}> (range pass over the stored G)")
+                label = "k_gstream (range pass over the stored bf16 G)" if base == "bf16" else \
+                    "k_gpass<fp8> (range pass over the stored fp8 G)"
+                return (gb * n * n + n * l * (2 + 4), 2.0 * n * n * l, 2.0 * n * n * l_pad, "bf16", label)
             if form == "fp32s":
-                return (4.0 * n * n + n * l * (6 + 4), 6 * 2.0 * n * n * l, 6 * 2.0 * n * n * l_pad, "bf16",
-                        "k_gpass_x3 (fp32 range pass as three-term split)")
+                return (4.0 * n * n + n * l * (6 + 4), 2.0 * n * n * l, 6 * 2.0 * n * n * l_pad, "bf16",
+                        "k_split<kFull, 3 terms> (fp32 range pass as three-term split)")
             return (4.0 * n * n + n * l * (x_bytes[base] + 4 * (2 if base == "fp64" else 1)), 2.0 * n * n * l,
                     2.0 * n * n * l_pad, base, f"k_gpass<{base}, from D> (range pass)")
         if phase == "gpass_f32":
-            return (4.0 * n * n + n * l * (6 + 4), 6 * 2.0 * n * n * l, 6 * 2.0 * n * n * l_pad, "bf16",
-                    "k_gpass_x3 (fp32 end range pass as three-term split)")
+            return (4.0 * n * n + n * l * (6 + 4), 2.0 * n * n * l, 3 * 2.0 * n * n * l_pad, "bf16",
+                    "k_split<kFull, 2 terms> (16-bit end range pass from D)")
         if phase == "gpass_ref":
-            if split_of(form):
-                return (2.0 * n * n + n * l * (6 + 4), 6.0 * n * n * l, 6.0 * n * n * l_pad, "bf16",
-                        "k_gpass_x3d (symmetric projection, fp32 as three-term split)")
+            if lowp:
+                return (2.0 * n * n + n * l * (6 + 4), 1.0 * n * n * l, 3.0 * n * n * l_pad, "bf16",
+                        "k_split<kSym, 2 terms> (16-bit symmetric projection)")
+            if form == "fp32s":
+                return (2.0 * n * n + n * l * (6 + 4), 1.0 * n * n * l, 6.0 * n * n * l_pad, "bf16",
+                        "k_split<kSym, 3 terms> (fp32 symmetric projection as three-term split)")
             return (2.0 * n * n + n * l * (x_bytes[base] + 4 * (2 if base == "fp64" else 1)), 1.0 * n * n * l,
                     1.0 * n * n * l_pad, base, f"k_gpass<{base}> (symmetric projection)")
         return None
@@ -544,6 +608,8 @@ def main():
         "speedup_bf16_vs_fp32": (res["fp32"]["ms"] / res["bf16"]["ms"]) if ("bf16" in res and "fp32" in res)
         else None,
         "roofline": roof,
+        "distances": distances,
+        "components": components,
     }
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: row-blocked oracle at n={n}, {args.cpu_sample_rows} sample rows")
