@@ -626,8 +626,14 @@ def main():
         log(f"[bench] serving: {line['serving']}")
         line["p99_ms_serving"] = line["serving"]["p99_ms"]
     if args.burst_jobs > 0:
+        # the low end of the serving mix's sizes (batching does not pay there: one workgroup per
+        # instance against whole-device plans) and small instances, where it does
         line["serving_burst"] = burst_bench(mds, torch, wgpu, args.burst_jobs, 500, 2048, args.serve_budget_gib,
                                             args.serve_slots, 64)
+        log(f"[burst] n 500-2048: {line['serving_burst']}")
+        line["serving_burst_small"] = burst_bench(mds, torch, wgpu, 4 * args.burst_jobs, 48, 400,
+                                                  args.serve_budget_gib, args.serve_slots, 256)
+        log(f"[burst] n 48-400: {line['serving_burst_small']}")
     print(json.dumps(line), flush=True)
 
 

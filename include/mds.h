@@ -254,6 +254,7 @@ typedef struct mds_info {
   double trace;              /* tr(G) */
   int64_t asym_pairs;        /* MDS_FLAG_CHECK_INPUT: pairs i < j with d_ij != d_ji */
   int64_t diag_nonzero;      /* MDS_FLAG_CHECK_INPUT: entries d_ii != 0 */
+  int32_t tuned_from_cache;  /* 1: the splits came from the MDS_TUNE_CACHE file */
 } mds_info;
 
 /* Synchronise `stream`, then report the plan's last-run diagnostics. */
@@ -301,6 +302,13 @@ typedef struct mds_tune_result {
   int32_t candidates;                        /* configurations timed */
 } mds_tune_result;
 mds_status mds_autotune(mds_plan_t plan, const void* D, void* stream, mds_tune_result* out);
+/* Persisted choices: when the environment variable MDS_TUNE_CACHE names a
+ * file, mds_autotune records the splits it chose there (one text line per
+ * key: device architecture and CU count, form, flags, D dtype, n, l_pad, q),
+ * and mds_plan / mds_plan_ex start a plan whose splits are all automatic
+ * from the recorded choice of its key (mds_info.tuned_from_cache = 1).  The
+ * file is rewritten whole through a rename; an unreadable or missing file is
+ * ignored. */
 
 void mds_destroy(mds_plan_t plan);
 

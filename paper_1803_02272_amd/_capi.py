@@ -71,7 +71,8 @@ class MdsInfo(ctypes.Structure):
                 ("q", ctypes.c_int32), ("form", ctypes.c_int32), ("gpass_split", ctypes.c_int32),
                 ("n", ctypes.c_int64), ("ldg", ctypes.c_int64),
                 ("sum_sq", ctypes.c_double), ("frob2", ctypes.c_double), ("trace", ctypes.c_double),
-                ("asym_pairs", ctypes.c_int64), ("diag_nonzero", ctypes.c_int64)]
+                ("asym_pairs", ctypes.c_int64), ("diag_nonzero", ctypes.c_int64),
+                ("tuned_from_cache", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -464,6 +464,17 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
   // FP32 form with every pass as the three-term bf16 split
   if (o.form == MDS_FORM_FP32 && (o.flags & MDS_FLAG_SPLIT_FP32)) P->gk = P->ref_gk = GK_F32S;
   P->flags = o.flags;
+  // splits all automatic: a recorded autotune choice for this key, if any
+  if (!P->opts.gpass_split && !P->opts.proj_split && !P->opts.write_split && !P->opts.f32_split) {
+    int s[4];
+    if (tune_cache_lookup(TuneKey{o.form, o.flags, o.d_dtype, P->l_pad, P->q, P->n}, s)) {
+      P->opts.gpass_split = s[0];
+      P->opts.proj_split = s[1];
+      P->opts.write_split = s[2];
+      P->opts.f32_split = s[3];
+      P->tuned_from_cache = 1;
+    }
+  }
   configure(P);
   *out = P;
   return MDS_OK;
@@ -562,6 +573,7 @@ mds_status mds_get_info(mds_plan_t plan, mds_info* out, void* stream) {
   info.q = plan->q;
   info.form = plan->form;
   info.gpass_split = plan->cfg.split;
+  info.tuned_from_cache = plan->tuned_from_cache;
   info.n = plan->n;
   info.ldg = plan->ldg;
   info.status = MDS_OK;
@@ -736,6 +748,8 @@ mds_status mds_autotune(mds_plan_t P, const void* D, void* stream, mds_tune_resu
   out->write_ms = P->fused ? best_ms[kWrite] : 0.f;
   out->f32_ms = P->refine ? best_ms[kF32] : 0.f;
   out->candidates = timed;
+  const int rec[4] = {P->opts.gpass_split, P->opts.proj_split, P->opts.write_split, P->opts.f32_split};
+  tune_cache_store(TuneKey{P->opts.form, P->opts.flags, P->opts.d_dtype, P->l_pad, P->q, P->n}, rec);
   return finish(MDS_OK);
 }
 

@@ -141,6 +141,14 @@ int split_pass_rows();
 int gstream_rows();
 hipError_t launch_gstream(const void* G, int64_t ldg, const void* Xt, int l_pad, const GPassCfg& cfg, int64_t n,
                           int64_t blocks, void* Yp, hipStream_t s);
+// Persisted autotune choices (tune_cache.hip, MDS_TUNE_CACHE): splits are
+// range, projection, fused write, end passes.
+struct TuneKey {
+  int form, flags, d_dtype, l_pad, q;
+  int64_t n;
+};
+bool tune_cache_lookup(const TuneKey& k, int (&splits)[4]);
+bool tune_cache_store(const TuneKey& k, const int (&splits)[4]);
 // Pairwise distances (k_dist.hip): D row-major n x n in fp32 or fp64.
 constexpr int kMaxHammingLength = 2048;
 constexpr int64_t kMaxDistanceN = 4000000;

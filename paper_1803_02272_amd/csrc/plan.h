@@ -22,6 +22,7 @@ struct mds_plan_s {
   int k = 0, p = 0, q = 0, l = 0, l_pad = 0;
   uint64_t seed = 0;
   mds_opts opts{};      // options the plan was created with
+  int tuned_from_cache = 0;  // splits taken from the MDS_TUNE_CACHE file
   int form = MDS_FORM_FP32;
   int d_dtype = MDS_DTYPE_F32;
   int gk = mds::GK_F32;      // dtype of G and of the range passes
