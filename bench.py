@@ -83,7 +83,8 @@ def percentile(xs, p):
 
 # Benchmark variants: name -> Plan keyword arguments.  "bf16" and "fp8" are
 # the library's default schedules (16-bit first and last range pass and
-# projection, two-term bf16 splits); "bf16a" and "fp8a" run every range pass
+# projection: two-term bf16 split of G, of X too except in the last range
+# pass, which rounds X to bf16); "bf16a" and "fp8a" run every range pass
 # on the stored G (MDS_FLAG_LOWP_ALL_RANGE); "fp32s" is the fp32 form with
 # every pass as the three-term bf16 split.
 VARIANTS = {
@@ -459,7 +460,9 @@ def main():
     #   gpass      a range pass over the stored G (bf16 2 n^2 / fp8 n^2 bytes)
     #              or over D recentred on the fly (fp32, fp64 forms: 4 n^2)
     #   gpass_f32  the 16-bit last range pass of the bf16/fp8 forms from D
-    #              (4 n^2 bytes, 3 bf16 products per entry)
+    #              (4 n^2 bytes, bf16 X, 2 bf16 products per entry; the fp8
+    #              form's first range pass, with two-term X and 3 products,
+    #              is counted here too)
     #   gpass_ref  the symmetric projection: the upper triangle of D (2 n^2
     #              bytes), n^2 l useful flops (3 bf16 products per entry for
     #              the 16-bit projection of the bf16/fp8 forms, 6 for the
@@ -501,8 +504,11 @@ def main():
             return (4.0 * n * n + n * l * (x_bytes[base] + 4 * (2 if base == "fp64" else 1)), 2.0 * n * n * l,
                     2.0 * n * n * l_pad, base, f"k_gpass<{base}, from D> (range pass)")
         if phase == "gpass_f32":
-            return (4.0 * n * n + n * l * (6 + 4), 2.0 * n * n * l, 3 * 2.0 * n * n * l_pad, "bf16",
-                    "k_split<kFull, 2 terms> (16-bit end range pass from D)")
+            if base == "bf16":
+                return (4.0 * n * n + n * l * (2 + 4), 2.0 * n * n * l, 2 * 2.0 * n * n * l_pad, "bf16",
+                        "k_split<kFull, 2 + 1 terms> (16-bit last range pass from D, bf16 X)")
+            return (4.0 * n * n + n * l * (4 + 4), 2.0 * n * n * l, 2.5 * 2.0 * n * n * l_pad, "bf16",
+                    "k_split<kFull, 2 + 2 / 2 + 1 terms> (16-bit first and last range passes from D)")
         if phase == "gpass_ref":
             if lowp:
                 return (2.0 * n * n + n * l * (6 + 4), 1.0 * n * n * l, 3.0 * n * n * l_pad, "bf16",

@@ -58,11 +58,12 @@ typedef enum mds_status {
  *         range passes, the first and the last are 16-bit passes over D and
  *         the q*2-1 between them run on the stored bf16 G against bf16 X
  *         (bf16 MFMA, fp32 accumulation); the projection pass
- *         ("refinement") is a 16-bit pass too.  A 16-bit pass takes each
- *         operand's fp32 value a as the two-term bf16 expansion a0 + a1
+ *         ("refinement") is a 16-bit pass too.  A 16-bit pass takes the fp32
+ *         value a of each G entry as the two-term bf16 expansion a0 + a1
  *         (a0 = bf16(a), a1 = bf16(a - a0), nearest even: about 16
- *         significant bits) and accumulates a0 b0 + a0 b1 + a1 b0 on bf16
- *         MFMA in fp32.  The first range pass also writes the stored G
+ *         significant bits) and X as b = bf16(x), and accumulates a1 b + a0 b
+ *         on bf16 MFMA in fp32 (each product exact).  The first range pass
+ *         also writes the stored G
  *         (fused centring write, fp32 D).  Running the two end passes at 16
  *         bits keeps the bf16 rounding of G out of the sketch of Omega and
  *         out of the final basis: the Ritz values then stay within 1e-3
@@ -70,8 +71,10 @@ typedef enum mds_status {
  *         eigenvalue lies in a near-degenerate bulk, where a sketch made
  *         entirely of bf16 passes moves them by about 1e-3
  *         (MDS_FLAG_LOWP_ALL_RANGE restores that faster schedule).  The
- *         16-bit projection adds a few 1e-6 at most to the Ritz values
- *         (MDS_FLAG_FP32_PROJECTION makes it an fp32 pass).
+ *         bf16 rounding of X enters the Ritz values only through inner
+ *         products over n rows, which average it: about 1e-4 relative at
+ *         most in the parity cases (MDS_FLAG_FP32_PROJECTION makes the
+ *         projection an fp32 pass).
  *         An fp32 pass (the FP32 form with MDS_FLAG_SPLIT_FP32, the
  *         projection with MDS_FLAG_FP32_PROJECTION) multiplies fp32 G
  *         entries with fp32 X to fp32 accuracy: each fp32 operand is split
@@ -87,7 +90,7 @@ typedef enum mds_status {
  *         accumulation; the first and last range passes and the projection
  *         are 16-bit passes as in the bf16 form.
  * G is stored only in the bf16 and fp8 forms (and only when q >= 1: with q = 0
- * the one range pass is an fp32 pass).  Every other pass recomputes each
+ * the one range pass is a 16-bit pass from D).  Every other pass recomputes each
  * entry from D: fp64 passes with the centring equation in fp64 (the values a
  * stored fp64 G would hold), fp32 passes as fma(-1/2, fl32(d^2),
  * fl32(c_j/2) + fl32((r_i - m)/2)) in fp32, within a few fp32 ulps of the
@@ -138,14 +141,15 @@ typedef enum mds_dtype { MDS_DTYPE_F32 = 0, MDS_DTYPE_F64 = 1 } mds_dtype;
  *   MDS_FLAG_FULL_PROJECTION).  A NaN entry counts as asymmetric. */
 #define MDS_FLAG_CHECK_INPUT 16
 /*   MDS_FLAG_LOWP_ALL_RANGE: BF16 and FP8 forms, run all 2q+1 range passes
- *   on the stored low-precision G (no fp32 first and last range pass): faster
- *   by about two fp32 passes less, with Ritz values that may move by ~1e-3
+ *   on the stored low-precision G (no 16-bit first and last range pass):
+ *   faster by two passes over D less, with Ritz values that may move by ~1e-3
  *   relative when the k-th eigenvalue lies in a near-degenerate bulk (bf16;
  *   ~1e-1 for fp8).  No effect in the other forms. */
 #define MDS_FLAG_LOWP_ALL_RANGE 32
 /*   MDS_FLAG_FP32_PROJECTION: BF16 and FP8 forms, run the projection as an
- *   fp32 pass (three-term bf16 split, six products) instead of the 16-bit
- *   pass (two terms, three products).  No effect in the other forms. */
+ *   fp32 pass (three-term bf16 split of both operands, six products) instead
+ *   of the 16-bit pass (two-term G, bf16 X, two products).  No effect in the
+ *   other forms. */
 #define MDS_FLAG_FP32_PROJECTION 64
 
 typedef struct mds_opts {

@@ -351,24 +351,29 @@ def fp8_operand(G: np.ndarray) -> np.ndarray:
 
 # Dtype of (G, X) in the range passes and in the projection pass of each
 # form.  The low-precision forms ("bf16", "fp8") run the first and the last
-# range pass with both operands to about 16 significant bits (two-term
-# bfloat16 expansions of their float32 values) and only the passes between
-# them on the stored low-precision G (the sketch of Omega and the final basis
-# then carry no bf16/fp8 rounding of G); "bf16_all" and "fp8_all" run every
-# range pass on the stored G.  Their projection (the "refinement" pass) is a
-# 16-bit pass as well; "bf16_p32" and "fp8_p32" make it an fp32 pass.
+# range pass with G to about 16 significant bits (the two-term bfloat16
+# expansion of its float32 value) and only the passes between them on the
+# stored low-precision G (the sketch of Omega and the final basis then carry
+# no bf16/fp8 rounding of G); "bf16_all" and "fp8_all" run every range pass
+# on the stored G.  X takes 16 bits as well in the sketch of Omega and is
+# rounded to bfloat16 in the last range pass.  Their projection (the
+# "refinement" pass) takes both operands to 16 bits; "bf16_p32" and
+# "fp8_p32" make it an fp32 pass.  "bf16_f32g" takes float32 in place of the
+# two-term expansions (the batched kernel's arithmetic).
 _F32 = ("f32", "f32")
-_X2 = ("bf16x2", "bf16x2")
+_X2 = ("bf16x2", "bf16x2")  # 16-bit sketch of Omega and projection
+_X1 = ("bf16x2", "bf16")    # last 16-bit range pass
 FORMS = {
     "fp64": {"first": ("f64", "f64"), "range": ("f64", "f64"), "last": ("f64", "f64"), "proj": ("f64", "f64")},
     "fp32": {"first": _F32, "range": _F32, "last": _F32, "proj": _F32},
-    "bf16": {"first": _X2, "range": ("bf16", "bf16"), "last": _X2, "proj": _X2},
-    "fp8": {"first": _X2, "range": ("fp8blk", "bf16"), "last": _X2, "proj": _X2},
-    "bf16_p32": {"first": _X2, "range": ("bf16", "bf16"), "last": _X2, "proj": _F32},
-    "fp8_p32": {"first": _X2, "range": ("fp8blk", "bf16"), "last": _X2, "proj": _F32},
+    "bf16": {"first": _X2, "range": ("bf16", "bf16"), "last": _X1, "proj": _X2},
+    "fp8": {"first": _X2, "range": ("fp8blk", "bf16"), "last": _X1, "proj": _X2},
+    "bf16_p32": {"first": _X2, "range": ("bf16", "bf16"), "last": _X1, "proj": _F32},
+    "fp8_p32": {"first": _X2, "range": ("fp8blk", "bf16"), "last": _X1, "proj": _F32},
     "bf16_all": {"first": ("bf16", "bf16"), "range": ("bf16", "bf16"), "last": ("bf16", "bf16"), "proj": _X2},
     "fp8_all": {"first": ("fp8blk", "bf16"), "range": ("fp8blk", "bf16"), "last": ("fp8blk", "bf16"),
                 "proj": _X2},
+    "bf16_f32g": {"first": _F32, "range": ("bf16", "bf16"), "last": ("f32", "bf16"), "proj": _F32},
 }
 
 

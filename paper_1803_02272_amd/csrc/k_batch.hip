@@ -18,9 +18,11 @@
 // entries from the centring equation in fp64, fp32 entries as
 // fma(-1/2, fl32(d^2), fl32(c_j/2) + fl32((r_i - m)/2)), bf16 entries as the
 // bf16 rounding of the fp32 rounding of the fp64 entry; the bf16 form's
-// first and last range passes and its projection use the fp32 entries.  Sums
-// run in a different order, so results agree with a single-instance run to
-// rounding, not bit for bit.
+// first range pass and its projection multiply the fp32 entries with fp32 X,
+// its last range pass with X rounded to bf16 (the single-instance path's
+// 16-bit passes with fp32 in place of the two-term expansions, within 2^-17
+// of them).  Sums run in a different order, so results agree with a
+// single-instance run to rounding, not bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -104,6 +106,8 @@ __device__ __forceinline__ bf16_t to_bf16(float f) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return (bf16_t)(u >> 16);
 }
+// the bf16 rounding of f as an fp32 value (X of the bf16 form's fp32 passes)
+__device__ __forceinline__ float bf16_value(float f) { return __uint_as_float((uint32_t)to_bf16(f) << 16); }
 
 // ---- centring sums with many loads in flight per thread ---------------------
 constexpr int kUnroll = 16;  // independent loads issued before they are used
@@ -337,6 +341,8 @@ __device__ void block_apply(const double* In, double* Out, int64_t np, int64_t n
         ((double*)X)[(int64_t)b * np + i] = v;
       else if (xk == GK_F32)
         ((float*)X)[(int64_t)b * np + i] = (float)v;
+      else if (xk == GK_S2)  // fp32 storage of bf16(fl32(v))
+        ((float*)X)[(int64_t)b * np + i] = bf16_value((float)v);
       else if (xk == GK_BF16)
         ((bf16_t*)X)[(int64_t)b * np + i] = to_bf16((float)v);
     }
@@ -517,7 +523,8 @@ __device__ void batch_instance(const BJob& J, BShared& S) {
   constexpr int GK = FORM == MDS_FORM_FP64 ? GK_F64 : (FORM == MDS_FORM_FP32 ? GK_F32 : GK_BF16);
   constexpr int PK = FORM == MDS_FORM_FP64 ? GK_F64 : GK_F32;  // projection operand
   // the bf16 form's first and last range passes recentre D in fp32 (like its
-  // projection); the passes between them read the stored bf16 G
+  // projection), the last with bf16-valued X; the passes between them read
+  // the stored bf16 G
   const int passes = 2 * J.q + 1;
   auto f32_pass = [&](int it) { return FORM == MDS_FORM_BF16 && (it == 0 || it == passes - 1); };
   const bool store_g = !(FORM == MDS_FORM_BF16 && J.q == 0);
@@ -574,7 +581,7 @@ __device__ void batch_instance(const BJob& J, BShared& S) {
       block_gpass<GK_F32, true, KU>(J, nullptr, X, Yt, hc, hr);
     else
       block_gpass<GK, false, KU>(J, G, X, Yt, hc, hr);
-    const int next = it == passes - 1 ? PK : (f32_pass(it + 1) ? (int)GK_F32 : GK);
+    const int next = it == passes - 1 ? PK : (f32_pass(it + 1) ? (int)GK_S2 : GK);
     block_orth(S, J, Yt, Qt, X, next);
   }
   // ---- projection B = Q^T G Q ------------------------------------------------

@@ -537,9 +537,11 @@ __device__ __forceinline__ void split3(const float (&g)[8], u32x4 (&w)[3]) {
 // in fp64 as in the centring equation, g = fl32(gamma) is stored into the
 // bf16 G as bf16(g) (the stored-G value of the bf16 form) and split for the
 // pass, so that the first range pass takes fl32(gamma) itself.
-// NT: terms of the split (3: six products, fp32 accuracy; 2: the first two
-// terms of each operand and three products, a0 b0 + a0 b1 + a1 b0).
-template <int RG, int CG, typename DT, bool SYM, bool WG = false, int NT = 3>
+// NT, NTB: terms of the G and X operands (3, 3: six products, fp32
+// accuracy; 2, 2: three products a1 b0 + a0 b1 + a0 b0, the 16-bit sketch
+// of Omega and projection; 2, 1: two products a1 b0 + a0 b0, each exact in
+// fp32, the last 16-bit range pass).
+template <int RG, int CG, typename DT, bool SYM, bool WG = false, int NT = 3, int NTB = 3>
 __global__ __launch_bounds__(256, 2) void k_gpass_x3(const uint16_t* __restrict__ X3, int64_t ldg, int split,
                                                      int64_t steps_total, int64_t steps_per_split,
                                                      float* __restrict__ Ypart, GPassDSrc src, int64_t sym_nbx,
@@ -724,10 +726,10 @@ __global__ __launch_bounds__(256, 2) void k_gpass_x3(const uint16_t* __restrict_
             bb[h][1] = *reinterpret_cast<const u32x4*>(bp + 64);
             bb[h][2] = *reinterpret_cast<const u32x4*>(bp + 128);
           }
-        // products smallest first: six for three terms, three for two
-        constexpr int NPR = NT == 3 ? 6 : 3;
+        // products smallest first: six for three terms, three or two for two
+        constexpr int NPR = NT == 3 ? 6 : (NTB == 2 ? 3 : 2);
         constexpr int PA[6] = {NT == 3 ? 2 : 1, NT == 3 ? 1 : 0, 0, 1, 0, 0};
-        constexpr int PB[6] = {0, 1, NT == 3 ? 2 : 0, 0, 1, 0};
+        constexpr int PB[6] = {0, NTB >= 2 ? 1 : 0, NT == 3 ? 2 : 0, 0, 1, 0};
 #pragma unroll
         for (int pr = 0; pr < NPR; ++pr)
 #pragma unroll
@@ -846,52 +848,63 @@ hipError_t launch_cg(const void* G, int64_t ldg, const void* Xt, const GPassCfg&
   return hipGetLastError();
 }
 
-template <int CG, typename DT, bool SYM, bool WG = false, int NT = 3>
+template <int CG, typename DT, bool SYM, bool WG, int NT, int NTB>
 void launch_x3_one(const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t n_pad, void* Yp, const GPassDSrc& src,
                    hipStream_t s, void* Gw = nullptr) {
   constexpr int RG = rg_x3(CG, sizeof(DT) == 8);
-  hipLaunchKernelGGL((k_gpass_x3<RG, CG, DT, SYM, WG, NT>), dim3((unsigned)gpass_blocks(cfg, n_pad)), dim3(256), 0,
+  hipLaunchKernelGGL((k_gpass_x3<RG, CG, DT, SYM, WG, NT, NTB>), dim3((unsigned)gpass_blocks(cfg, n_pad)), dim3(256), 0,
                      s, (const uint16_t*)Xt, ldg, cfg.split, cfg.steps_total, cfg.steps_per_split, (float*)Yp, src,
                      cfg.sym_nbx, (uint16_t*)Gw);
 }
 
-template <int CG, int NT>
+// the term combinations (G, X) of each use: (3, 3) everywhere, (2, 2) in
+// every mode (the 16-bit sketch of Omega, fused with the centring write or
+// not, and the 16-bit projection), (2, 1) in the full pass (the last 16-bit
+// range pass)
+template <int CG, int NT, int NTB>
 hipError_t launch_x3_nt(const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t n_pad, void* Yp,
                         const GPassDSrc& src, hipStream_t s, void* Gw) {
+  constexpr bool kWriteOk = NTB != 1, kSymOk = NTB != 1;
   if (Gw) {  // fused centring write: full pass over fp32 D
-    if (cfg.sym || src.d_is_f64 || cfg.rg != rg_x3(CG, false)) return hipErrorInvalidValue;
-    launch_x3_one<CG, float, false, true, NT>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
+    if (!kWriteOk || cfg.sym || src.d_is_f64 || cfg.rg != rg_x3(CG, false)) return hipErrorInvalidValue;
+    if constexpr (kWriteOk) launch_x3_one<CG, float, false, true, NT, NTB>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
     return hipGetLastError();
   }
-  if (cfg.rg != rg_x3(CG, src.d_is_f64 != 0)) return hipErrorInvalidValue;
+  if (cfg.rg != rg_x3(CG, src.d_is_f64 != 0) || (cfg.sym && !kSymOk)) return hipErrorInvalidValue;
   if (src.d_is_f64) {
-    if (cfg.sym)
-      launch_x3_one<CG, double, true, false, NT>(Xt, ldg, cfg, n_pad, Yp, src, s);
-    else
-      launch_x3_one<CG, double, false, false, NT>(Xt, ldg, cfg, n_pad, Yp, src, s);
+    if constexpr (kSymOk)
+      if (cfg.sym) {
+        launch_x3_one<CG, double, true, false, NT, NTB>(Xt, ldg, cfg, n_pad, Yp, src, s);
+        return hipGetLastError();
+      }
+    launch_x3_one<CG, double, false, false, NT, NTB>(Xt, ldg, cfg, n_pad, Yp, src, s);
   } else {
-    if (cfg.sym)
-      launch_x3_one<CG, float, true, false, NT>(Xt, ldg, cfg, n_pad, Yp, src, s);
-    else
-      launch_x3_one<CG, float, false, false, NT>(Xt, ldg, cfg, n_pad, Yp, src, s);
+    if constexpr (kSymOk)
+      if (cfg.sym) {
+        launch_x3_one<CG, float, true, false, NT, NTB>(Xt, ldg, cfg, n_pad, Yp, src, s);
+        return hipGetLastError();
+      }
+    launch_x3_one<CG, float, false, false, NT, NTB>(Xt, ldg, cfg, n_pad, Yp, src, s);
   }
   return hipGetLastError();
 }
 
 template <int CG>
-hipError_t launch_x3_cg(int nt, const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t n_pad, void* Yp,
+hipError_t launch_x3_cg(int gt, int xt, const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t n_pad, void* Yp,
                         const GPassDSrc& src, hipStream_t s, void* Gw) {
   if (!src.D) return hipErrorInvalidValue;
-  if (cfg.dma) return launch_split_pass(nt, Xt, ldg, CG * 16, cfg, gpass_blocks(cfg, n_pad), Yp, src, Gw, s);
-  return nt == 2 ? launch_x3_nt<CG, 2>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw)
-                 : launch_x3_nt<CG, 3>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
+  if (cfg.dma) return launch_split_pass(gt, xt, Xt, ldg, CG * 16, cfg, gpass_blocks(cfg, n_pad), Yp, src, Gw, s);
+  if (gt == 3 && xt == 3) return launch_x3_nt<CG, 3, 3>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
+  if (gt == 2 && xt == 1) return launch_x3_nt<CG, 2, 1>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
+  if (gt == 2 && xt == 2) return launch_x3_nt<CG, 2, 2>(Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_x3(int nt, const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t n_pad, void* Yp,
-                     const GPassDSrc& src, hipStream_t s, void* Gw) {
+hipError_t launch_x3(int gt, int xt, const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t n_pad,
+                     void* Yp, const GPassDSrc& src, hipStream_t s, void* Gw) {
   switch (l_pad / 16) {
 #define MDS_CG(N) \
-  case N: return launch_x3_cg<N>(nt, Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
+  case N: return launch_x3_cg<N>(gt, xt, Xt, ldg, cfg, n_pad, Yp, src, s, Gw);
     MDS_CG(1) MDS_CG(2) MDS_CG(3) MDS_CG(4) MDS_CG(5) MDS_CG(6) MDS_CG(7) MDS_CG(8)
     MDS_CG(9) MDS_CG(10) MDS_CG(11) MDS_CG(12) MDS_CG(13) MDS_CG(14) MDS_CG(15) MDS_CG(16)
 #undef MDS_CG
@@ -985,8 +998,11 @@ hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const
     case GK_FP8:
       if (!src.g8_scales || (cfg.bm > kF8Block) || (kF8Block % cfg.bm)) return hipErrorInvalidValue;
       return launch_gk<GK_FP8>(G, ldg, Xt, l_pad, cfg, n_pad, Ypart, src, s);
-    case GK_F32S: return launch_x3(3, Xt, ldg, l_pad, cfg, n_pad, Ypart, src, s, const_cast<void*>(G));
-    case GK_S2: return launch_x3(2, Xt, ldg, l_pad, cfg, n_pad, Ypart, src, s, const_cast<void*>(G));
+    case GK_F32S:
+    case GK_S2:
+    case GK_S2X:
+      return launch_x3(gk_g_terms(gk), gk_x_terms(gk), Xt, ldg, l_pad, cfg, n_pad, Ypart, src, s,
+                       const_cast<void*>(G));
     default: return hipErrorInvalidValue;
   }
 }

@@ -1,15 +1,19 @@
-// fp32 G-passes on bf16 MFMA with both operands as exact three-term bf16
-// splits (Sec. 3.2-3.3: the products Y = G X of the range finder and of the
+// fp32 G-passes on bf16 MFMA with the G operand as an exact bf16 expansion
+// (Sec. 3.2-3.3: the products Y = G X of the range finder and of the
 // projection), streamed from the fp32 distance matrix D and recentred on the
 // fly (Sec. 6.2, step 1), software-pipelined for gfx950.
 //
 // Arithmetic (the same as k_gpass_x3): an fp32 value a is the exact sum
-// a0 + a1 + a2 of three bf16 terms (each rounded to nearest even); the six
-// products a_p b_q with p + q <= 2 are accumulated in fp32, the three
-// dropped ones are below 2^-22 |a b|.  With two terms (NT = 2: the 16-bit
-// range passes and projection) the products are a0 b0 + a0 b1 + a1 b0: each
-// operand within 2^-17 of its fp32 value, the result within 2^-15 |a b| per
-// product, in half the MFMA and much less of the splitting work.  Three modes:
+// a0 + a1 + a2 of three bf16 terms (each rounded to nearest even).  With
+// three terms (NT = 3, the fp32 passes) both operands are split and the six
+// products a_p b_q with p + q <= 2 are accumulated in fp32; the three
+// dropped ones are below 2^-22 |a b|.  With two terms (NT = 2) G is carried
+// as a0 + a1 (within 2^-17 of its fp32 value): the sketch of Omega and the
+// projection split X into two terms as well (NTB = 2) and take a1 b0 +
+// a0 b1 + a0 b0, within 2^-15 |a b| per product; the last range pass rounds
+// X once (NTB = 1, b0 = bf16(x)) and takes a1 b0 + a0 b0, each product
+// exact in fp32, with two thirds of those MFMAs and one plane of X.  Both
+// need much less of the splitting work than three terms.  Three modes:
 //   kFull  Y = G X over all of D, gamma = fma(-1/2, fl32(d^2), hc_k + hr_i)
 //          with hc_k = fl32(c_k / 2), hr_i = fl32((r_i - m) / 2);
 //   kSym   the projection's symmetric pass, 2 (W o G) X over the upper
@@ -27,7 +31,7 @@
 //     nontemporal hint, issued three steps before the step they feed; the
 //     pieces of a row are placed in XOR-swizzled slots so that the reads in
 //     the MFMA operand layout are free of bank conflicts;
-//   * the X tile of a step (three bf16 planes, 192 bytes per row), and with
+//   * the X tile of a step (the pass's bf16 planes, 64 bytes per row each), and with
 //     it the recentring terms of the following step (c_k / 2, or c_k in
 //     fp64), are loaded the same way into one of two LDS buffers shared by
 //     the eight waves; the tile is swizzled so that 16 consecutive rows read
@@ -109,7 +113,7 @@ __device__ __forceinline__ void mma(floatx4_t& c, const u32x4& a, const u32x4& b
                                               0, 0, 0);
 }
 
-template <int CG, int MODE, int NT>
+template <int CG, int MODE, int NT, int NTB>
 __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X3, int64_t ldg, int split,
                                                   int64_t steps_total, int64_t steps_per_split,
                                                   float* __restrict__ Ypart, GPassDSrc src, int64_t sym_nbx,
@@ -117,7 +121,8 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
   constexpr bool SYM = MODE == kSym;
   constexpr bool WG = MODE == kWrite;
   constexpr int LPAD = CG * 16;
-  constexpr int XINS = CG * NT;                         // 1 KB loads per X step tile (NT planes)
+  static_assert((NT == 3 && NTB == 3) || (NT == 2 && (NTB == 1 || NTB == 2)), "term counts");
+  constexpr int XINS = CG * NTB;                        // 1 KB loads per X step tile (NTB planes)
   constexpr int XBYTES = XINS * 1024 + kAux;
   constexpr int DSTAGE = kRG * 2 * 1024;               // one wave's D stage (32 rows x 32 fp32)
   constexpr int64_t kStepsPerBlock = kBM / kBK;
@@ -377,10 +382,10 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
     dma_x(s1, s2, xw);
     dma_d(s3, dw);
     // products smallest first: a2 b0, a1 b1, a0 b2, a1 b0, a0 b1, a0 b0 (three
-    // terms) or a1 b0, a0 b1, a0 b0 (two terms)
-    constexpr int NPR = NT == 3 ? 6 : 3;
+    // terms), a1 b0, a0 b1, a0 b0 (two and two) or a1 b0, a0 b0 (two and one)
+    constexpr int NPR = NT == 3 ? 6 : (NTB == 2 ? 3 : 2);
     constexpr int PA[6] = {NT == 3 ? 2 : 1, NT == 3 ? 1 : 0, 0, 1, 0, 0};
-    constexpr int PB[6] = {0, 1, NT == 3 ? 2 : 0, 0, 1, 0};
+    constexpr int PB[6] = {0, NTB >= 2 ? 1 : 0, NT == 3 ? 2 : 0, 0, 1, 0};
 #pragma unroll
     for (int cp = 0; cp < NCP; ++cp) {
       // One column-group pair: its B operands and the inputs of its share of
@@ -392,14 +397,14 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
       constexpr int kMaxSl = 4;
       const int sl0 = (cp * 4) / NCP, sl1 = ((cp + 1) * 4) / NCP;  // slices of this pair
       __builtin_amdgcn_sched_barrier(0);
-      u32x4 bb[2][NT];
+      u32x4 bb[2][NTB];
 #pragma unroll
       for (int h = 0; h < 2; ++h)
         if (cg0 + h < CG) {
           const int row = (cg0 + h) * 16 + (lane & 15);
           const int kgs = (lane >> 4) ^ ((row >> 2) & 3);
 #pragma unroll
-          for (int p = 0; p < NT; ++p)
+          for (int p = 0; p < NTB; ++p)
             bb[h][p] = *reinterpret_cast<const u32x4*>(&xr[(p * LPAD * 4 + row * 4 + kgs) * 16]);
         }
       Slice S[kMaxSl];
@@ -494,19 +499,33 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
   }
 }
 
-template <int CG, int NT>
-hipError_t launch_cg(int mode, const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t blocks, void* Yp,
-                     const GPassDSrc& src, void* Gw, hipStream_t s) {
-  const dim3 grid((unsigned)blocks), block(64 * kWaves);
-  if (mode == kSym)
-    hipLaunchKernelGGL((k_split<CG, kSym, NT>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split,
-                       cfg.steps_total, cfg.steps_per_split, (float*)Yp, src, cfg.sym_nbx, (uint16_t*)nullptr);
-  else if (mode == kWrite)
-    hipLaunchKernelGGL((k_split<CG, kWrite, NT>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split,
-                       cfg.steps_total, cfg.steps_per_split, (float*)Yp, src, cfg.sym_nbx, (uint16_t*)Gw);
-  else
-    hipLaunchKernelGGL((k_split<CG, kFull, NT>), grid, block, 0, s, (const uint16_t*)Xt, ldg, cfg.split,
-                       cfg.steps_total, cfg.steps_per_split, (float*)Yp, src, cfg.sym_nbx, (uint16_t*)nullptr);
+template <int CG, int MODE, int NT, int NTB>
+void launch_one(const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t blocks, void* Yp, const GPassDSrc& src,
+                void* Gw, hipStream_t s) {
+  hipLaunchKernelGGL((k_split<CG, MODE, NT, NTB>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, s,
+                     (const uint16_t*)Xt, ldg, cfg.split, cfg.steps_total, cfg.steps_per_split, (float*)Yp, src,
+                     cfg.sym_nbx, (uint16_t*)(MODE == kWrite ? Gw : nullptr));
+}
+
+// term combinations per mode: the fp32 passes (3, 3) and the 16-bit sketch
+// of Omega and projection (2, 2) in every mode, the last 16-bit range pass
+// (2, 1) in the full pass
+template <int CG>
+hipError_t launch_cg(int mode, int gt, int xt, const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t blocks,
+                     void* Yp, const GPassDSrc& src, void* Gw, hipStream_t s) {
+  if (gt == 3 && xt == 3) {
+    if (mode == kSym) launch_one<CG, kSym, 3, 3>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
+    else if (mode == kWrite) launch_one<CG, kWrite, 3, 3>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
+    else launch_one<CG, kFull, 3, 3>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
+  } else if (gt == 2 && xt == 2) {
+    if (mode == kSym) launch_one<CG, kSym, 2, 2>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
+    else if (mode == kWrite) launch_one<CG, kWrite, 2, 2>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
+    else launch_one<CG, kFull, 2, 2>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
+  } else if (gt == 2 && xt == 1 && mode == kFull) {
+    launch_one<CG, kFull, 2, 1>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -535,10 +554,9 @@ hipError_t launch_split_zero_pad(void* G, int64_t n, int64_t n_pad, int64_t ldg,
 
 int split_pass_rows() { return kBM; }
 
-hipError_t launch_split_pass(int nterms, const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t blocks,
-                             void* Yp, const GPassDSrc& src, void* Gw, hipStream_t s) {
-  if (!src.D || src.d_is_f64 || !src.vec || src.n % 4 != 0 || cfg.bm != kBM || l_pad % 16 != 0 || l_pad > 128 ||
-      (nterms != 2 && nterms != 3))
+hipError_t launch_split_pass(int gterms, int xterms, const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg,
+                             int64_t blocks, void* Yp, const GPassDSrc& src, void* Gw, hipStream_t s) {
+  if (!src.D || src.d_is_f64 || !src.vec || src.n % 4 != 0 || cfg.bm != kBM || l_pad % 16 != 0 || l_pad > 128)
     return hipErrorInvalidValue;
   if (Gw && cfg.sym) return hipErrorInvalidValue;
   // the fused write stores aligned pairs of steps: every K range starts on an
@@ -546,10 +564,8 @@ hipError_t launch_split_pass(int nterms, const void* Xt, int64_t ldg, int l_pad,
   if (Gw && (cfg.steps_per_split % 2 != 0 || cfg.steps_total % 2 != 0)) return hipErrorInvalidValue;
   const int mode = cfg.sym ? kSym : (Gw ? kWrite : kFull);
   switch (l_pad / 16) {
-#define MDS_CG(N)                                                                              \
-  case N:                                                                                      \
-    return nterms == 2 ? launch_cg<N, 2>(mode, Xt, ldg, cfg, blocks, Yp, src, Gw, s)           \
-                       : launch_cg<N, 3>(mode, Xt, ldg, cfg, blocks, Yp, src, Gw, s);
+#define MDS_CG(N) \
+  case N: return launch_cg<N>(mode, gterms, xterms, Xt, ldg, cfg, blocks, Yp, src, Gw, s);
     MDS_CG(1) MDS_CG(2) MDS_CG(3) MDS_CG(4) MDS_CG(5) MDS_CG(6) MDS_CG(7) MDS_CG(8)
 #undef MDS_CG
     default: return hipErrorInvalidValue;

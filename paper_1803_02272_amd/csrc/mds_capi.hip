@@ -30,8 +30,8 @@ int gk_size(int gk) {
   return gk == GK_F64 ? 8 : (gk == GK_F32 ? 4 : (gk == GK_BF16 ? 2 : (gk_split(gk) ? 6 : 1)));
 }
 // Element kind of the X operand of a pass with G of kind gk (FP8 G meets bf16 X).
-// (the two-term split pass reads the first two planes of the split layout)
-int x_kind(int gk) { return gk == GK_FP8 ? GK_BF16 : (gk == GK_S2 ? GK_F32S : gk); }
+// (the two-term split passes read the first one or two planes of the split layout)
+int x_kind(int gk) { return gk == GK_FP8 ? GK_BF16 : ((gk == GK_S2 || gk == GK_S2X) ? GK_F32S : gk); }
 bool stores_g(int form) { return form == MDS_FORM_BF16 || form == MDS_FORM_FP8; }
 }  // namespace
 
@@ -58,10 +58,13 @@ void add(mds_plan_s* P, Region& reg, size_t bytes) {
 }
 
 // Kind of range pass `it` (0-based, of 2q + 1): the BF16/FP8 forms run the
-// first and the last from D with two-term bf16 splits of both operands
-// (about 16 significant bits) unless MDS_FLAG_LOWP_ALL_RANGE.
+// first and the last from D with G as a two-term bf16 split (about 16
+// significant bits) unless MDS_FLAG_LOWP_ALL_RANGE; the sketch of Omega
+// splits Omega into two terms as well, the last pass rounds X to bf16 (a
+// pass that is both takes the first kind).
 int pass_kind(const mds_plan_s* P, int it) {
-  return (P->refine && (it == 0 || it == 2 * P->q)) ? GK_S2 : P->gk;
+  if (!P->refine) return P->gk;
+  return it == 0 ? GK_S2X : (it == 2 * P->q ? GK_S2 : P->gk);
 }
 
 void layout(mds_plan_s* P) {
@@ -147,7 +150,7 @@ void configure(mds_plan_s* P) {
   // pass (an fp32 split pass when refining, else a bf16 pass)
   P->fused = o.form == MDS_FORM_BF16 && !d8 && P->needs_g;
   if (P->fused)
-    P->wcfg = gpass_config(P->refine ? GK_S2 : GK_BF16, P->l_pad, P->n_pad, P->ldg,
+    P->wcfg = gpass_config(P->refine ? GK_S2X : GK_BF16, P->l_pad, P->n_pad, P->ldg,
                            o.write_split ? o.write_split : o.gpass_split, true, false, false, P->n % 4 == 0);
   layout(P);
 }
@@ -275,7 +278,7 @@ mds_status range_pass(mds_plan_s* P, hipStream_t s, int it, bool fused, const vo
       e = hip_check(launch_split_zero_pad(P->at<void>(P->G), P->n, P->n_pad, P->ldg, s), "zero padding of G");
     return e;
   }
-  if (gk == GK_S2) return gpass(P, s, gk, P->fcfg, true, D, nullptr, MDS_PH_GPASS_F32);
+  if (gk == GK_S2 || gk == GK_S2X) return gpass(P, s, gk, P->fcfg, true, D, nullptr, MDS_PH_GPASS_F32);
   return gpass(P, s, gk, P->cfg, !stores_g(P->form), D, nullptr, MDS_PH_GPASS);
 }
 
@@ -456,11 +459,12 @@ mds_status mds_plan_ex(mds_plan_t* out, int64_t n, int32_t k, int32_t oversample
   P->gk = o.form == MDS_FORM_FP64 ? GK_F64
           : (o.form == MDS_FORM_FP32 ? GK_F32 : (o.form == MDS_FORM_BF16 ? GK_BF16 : GK_FP8));
   // projection ("refinement") of the stored-G forms: a 16-bit pass (two-term
-  // bf16 split) by default, else fp32 as the three-term split or on fp32 MFMA
+  // bf16 splits of G and X) by default, else fp32 as the three-term split or
+  // on fp32 MFMA
   P->ref_gk = !stores_g(o.form)                             ? P->gk
               : (o.flags & MDS_FLAG_FP32_MFMA_PROJECTION) ? GK_F32
               : (o.flags & MDS_FLAG_FP32_PROJECTION)      ? GK_F32S
-                                                          : GK_S2;
+                                                          : GK_S2X;
   // FP32 form with every pass as the three-term bf16 split
   if (o.form == MDS_FORM_FP32 && (o.flags & MDS_FLAG_SPLIT_FP32)) P->gk = P->ref_gk = GK_F32S;
   P->flags = o.flags;
@@ -642,7 +646,7 @@ mds_status mds_autotune(mds_plan_t P, const void* D, void* stream, mds_tune_resu
   auto gk_of = [&](int kind) {
     if (kind == kRange) return P->gk;
     if (kind == kProj) return P->ref_gk;
-    if (kind == kWrite) return P->refine ? (int)GK_S2 : (int)GK_BF16;
+    if (kind == kWrite) return P->refine ? (int)GK_S2X : (int)GK_BF16;
     return (int)GK_S2;
   };
   auto cfg_of = [&](int kind, int split) {

@@ -27,11 +27,16 @@ typedef __attribute__((__vector_size__(4 * sizeof(double)))) double doublex4_t;
 // scale per 256 x 256 block, multiplied on bf16 MFMA (the X operand is bf16).
 // GK_F32S: the fp32 pass (recentring D) computed on bf16 MFMA from exact
 // three-term bf16 splits of both operands; X is stored split (see k_gpass).
-// GK_S2: the same pass with the two-term splits (the first two terms: about
-// 16 significant bits per operand) and three products instead of six; it
-// reads the first two planes of the same split X layout.
-enum GKind { GK_F64 = 0, GK_F32 = 1, GK_BF16 = 2, GK_FP8 = 3, GK_F32S = 4, GK_S2 = 5 };
-inline bool gk_split(int gk) { return gk == GK_F32S || gk == GK_S2; }
+// GK_S2: the same pass with G as its two-term split (about 16 significant
+// bits) and X as bf16 (the first plane of the same split X layout): two
+// products instead of six, each exact in fp32 (the 16-bit range passes).
+// GK_S2X: G and X both as two-term splits (the first two planes of X) and
+// three products, a0 b0 + a0 b1 + a1 b0 (the 16-bit projection).
+enum GKind { GK_F64 = 0, GK_F32 = 1, GK_BF16 = 2, GK_FP8 = 3, GK_F32S = 4, GK_S2 = 5, GK_S2X = 6 };
+inline bool gk_split(int gk) { return gk == GK_F32S || gk == GK_S2 || gk == GK_S2X; }
+// terms of the G and X operands of a split pass kind
+inline int gk_g_terms(int gk) { return gk == GK_F32S ? 3 : 2; }
+inline int gk_x_terms(int gk) { return gk == GK_F32S ? 3 : (gk == GK_S2X ? 2 : 1); }
 constexpr int kF8Block = 256;  // side of the blocks sharing one FP8 scale
 
 constexpr int kPadN = 256;     // padding granule of n (rows and ld of G)
@@ -173,8 +178,9 @@ __device__ inline void upper_tile(int64_t t, int64_t nt, int64_t& I, int64_t& J)
 }
 // Zero the padding of the bf16 G (rows >= n, columns >= n) left by the fused write.
 hipError_t launch_split_zero_pad(void* G, int64_t n, int64_t n_pad, int64_t ldg, hipStream_t s);
-hipError_t launch_split_pass(int nterms, const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg, int64_t blocks,
-                             void* Yp, const GPassDSrc& src, void* Gw, hipStream_t s);
+// gterms / xterms: terms of the G and X operands, (3, 3), (2, 1) or (2, 2)
+hipError_t launch_split_pass(int gterms, int xterms, const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg,
+                             int64_t blocks, void* Yp, const GPassDSrc& src, void* Gw, hipStream_t s);
 hipError_t launch_gpass(int gk, const void* G, int64_t ldg, int64_t n_pad, const void* Xt, int l_pad,
                         const GPassCfg& cfg, void* Ypart, const GPassDSrc& src, hipStream_t s);
 // Y (fp64, l_pad x ldg) = sum_s Ypart[s] in split order (symmetric mode:

@@ -232,7 +232,7 @@ def test_omega_stage(form):
     plan.run_stages(torch.from_numpy(D).cuda(), _capi.STAGE_OMEGA)
     torch.cuda.synchronize()
     Xt = plan.buffer(_capi.BUF_X).double().cpu().numpy()
-    if form == "bf16":  # Omega as the exact three-term split of fl32(Omega); the first range pass reads two terms
+    if form == "bf16":  # Omega as the exact three-term split of fl32(Omega); the sketch reads two terms
         Xt = split_sum(Xt)
     Om = O.omega(seed, n, l)
     got = Xt[:l, :n].T
@@ -314,6 +314,42 @@ def test_gpass_and_cholqr2_unit(name, form):
     assert np.max(np.abs(Q.T @ Q - np.eye(l))) < 1e-12
     Qy = np.linalg.qr(Y)[0]
     assert span_cos_min(Q, Qy) > 1 - 1e-10
+
+
+@pytest.mark.parametrize("form", ["bf16", "fp8"])
+def test_last_range_pass_unit(form):
+    """The last range pass of the low-precision forms, Y = G Q from D with G
+    as its two-term bfloat16 expansion and Q rounded once to bfloat16 (two
+    products a1 b + a0 b, each exact in fp32), against the fp64 product of
+    those rounded operands, Q taken from the device after the pass before."""
+    D, k, p, q = case("amp1237_f32")
+    n = D.shape[0]
+    l = k + p
+    say(f"[last pass] form={form} n={n} l={l} q={q}")
+    plan = mds.Plan(n, k, p, q, 9, form=form)
+    Dg = torch.from_numpy(D).cuda()
+    plan.run_stages(Dg, _capi.STAGE_RANGE, 2 * q)
+    torch.cuda.synchronize()
+    Qp = plan.buffer(_capi.BUF_Q).cpu().numpy()[:l, :n].T
+    plan.run_stages(Dg, _capi.STAGE_RANGE, 2 * q + 1)
+    torch.cuda.synchronize()
+    Yt = plan.buffer(_capi.BUF_Y).cpu().numpy()
+    Y = Yt[:l, :n].T
+    G = O.gram_matrix(D)
+    G2, Qb = O.round_to(G, "bf16x2"), O.round_to(Qp, "bf16")
+    want = G2 @ Qb
+    mag = np.abs(G2) @ np.abs(Qb)
+    u = 2.0 ** -24
+    r, c, m = O.centring_stats(D)
+    H = 0.5 * (D.astype(np.float64) ** 2 + c[None, :] + np.abs(r - m)[:, None])
+    # fp32 accumulation; the kernel's fl32 entries (one fma from fl32(d^2),
+    # fl32(c/2), fl32((r-m)/2)) within a few ulps of those terms, and the
+    # two-term expansions of such nearby values within 2^-16
+    bound = 2 * n * u * mag + 2.0 ** -16 * mag + 4 * u * (H @ np.abs(Qb))
+    assert np.all(np.abs(Y - want) <= bound + 1e-300)
+    # the operand really is bf16 X: the product with two-term X leaves the bound
+    assert np.any(np.abs(Y - G2 @ O.round_to(Qp, "bf16x2")) > bound)
+    assert np.all(Yt[l:] == 0) and np.all(Yt[:, n:] == 0)
 
 
 def test_range_passes_span_fp64():

@@ -177,9 +177,10 @@ def test_bf16_form_perturbs_like_its_storage():
 
 
 def test_low_precision_schedule_has_16_bit_end_passes():
-    # The bf16/fp8 forms take their first and last range application with
-    # 16-bit operands (two-term bfloat16 expansions): with q = 0 that single
-    # application is the whole range finder, so both forms are the same
+    # The bf16/fp8 forms take their first and last range application with G
+    # to 16 bits (two-term bfloat16 expansion), X to 16 bits in the sketch of
+    # Omega and bf16 in the last one: with q = 0 that single application is
+    # the sketch and the whole range finder, so both forms are the same
     # method and stay within the 16-bit operand precision of the fp32 form;
     # with q >= 1 the bf16 form differs from the variant that runs every
     # application on the stored bf16 G.
@@ -190,7 +191,8 @@ def test_low_precision_schedule_has_16_bit_end_passes():
     assert np.array_equal(O.rand_mds(D, 8, 4, 0, 1, form="fp8")["eigvals"], b16)
     assert 0 < np.max(np.abs(b16 - f32) / f32) < 1e-5
     assert [O.pass_dtypes("bf16", it, 2) for it in range(5)] == [
-        ("bf16x2", "bf16x2"), ("bf16", "bf16"), ("bf16", "bf16"), ("bf16", "bf16"), ("bf16x2", "bf16x2")]
+        ("bf16x2", "bf16x2"), ("bf16", "bf16"), ("bf16", "bf16"), ("bf16", "bf16"), ("bf16x2", "bf16")]
+    assert O.pass_dtypes("bf16", 0, 0) == ("bf16x2", "bf16x2")
     assert all(O.pass_dtypes("bf16_all", it, 2) == ("bf16", "bf16") for it in range(5))
     a = O.rand_mds(D, 8, 4, 1, 1, form="bf16")["eigvals"]
     b = O.rand_mds(D, 8, 4, 1, 1, form="bf16_all")["eigvals"]
