@@ -771,8 +771,10 @@ __global__ __launch_bounds__(256, 2) void k_gpass_x3(const uint16_t* __restrict_
 }
 
 // The split passes that stream D through LDS (fp32 D, n % 4 == 0, aligned D,
-// l_pad <= 128) run in k_split.hip: 8 waves of 2 row groups per workgroup.
-constexpr int kDmaMaxL = 128;
+// l_pad <= 128 with three terms, <= 224 with two) run in k_split.hip: 8 waves
+// of 2 row groups per workgroup.  The pass over the stored bf16 G streams
+// up to l_pad = 128 (k_gstream).
+constexpr int kDmaMaxL = 128, kDmaMaxL2 = 224;
 
 // Symmetric mode: row block mb has partials only in the splits whose K
 // range reaches its diagonal, k >= first_split(row) = (mb * bm) / cols_per_split.
@@ -932,7 +934,8 @@ GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_h
   GPassCfg c{};
   c.rg = gk_split(gk) ? rg_x3(l_pad / 16, d8) : (from_d ? rg_fd(gk, l_pad / 16, d8) : rg_for(gk, l_pad / 16));
   c.bm = 64 * c.rg;
-  if (gk_split(gk) && dma_ok && from_d && !d8 && l_pad <= kDmaMaxL && n_pad % split_pass_rows() == 0) {
+  if (gk_split(gk) && dma_ok && from_d && !d8 && l_pad <= (gk == GK_F32S ? kDmaMaxL : kDmaMaxL2) &&
+      n_pad % split_pass_rows() == 0) {
     c.dma = 1;  // k_split: 8 waves of 2 row groups, row blocks dealt to XCDs (see sym_nbx)
     c.rg = 2;
     c.bm = split_pass_rows();

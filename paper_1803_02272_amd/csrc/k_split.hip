@@ -46,7 +46,8 @@
 // Every LDS buffer is its own __shared__ array and the step loop is unrolled
 // six ways (2 X buffers x 3 ring stages), so each LDS access names a fixed
 // array and the compiler's wait counts stay as precise as the explicit ones.
-// Requires fp32 D, n % 4 == 0, a 16-byte aligned D and l_pad <= 128.
+// Requires fp32 D, n % 4 == 0, a 16-byte aligned D and l_pad <= 128 (three
+// terms) or <= 224 (two terms).
 #include <type_traits>
 
 #include "mds_internal.h"
@@ -499,6 +500,11 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
   }
 }
 
+// Widest X tile per term count: the LDS holds two X buffers of CG * NTB KB
+// beside the three 32 KB D stages (three-term passes up to l_pad = 128,
+// two-term ones up to 224).
+constexpr int kMaxCG3 = 8, kMaxCG2 = 14;
+
 template <int CG, int MODE, int NT, int NTB>
 void launch_one(const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t blocks, void* Yp, const GPassDSrc& src,
                 void* Gw, hipStream_t s) {
@@ -514,9 +520,13 @@ template <int CG>
 hipError_t launch_cg(int mode, int gt, int xt, const void* Xt, int64_t ldg, const GPassCfg& cfg, int64_t blocks,
                      void* Yp, const GPassDSrc& src, void* Gw, hipStream_t s) {
   if (gt == 3 && xt == 3) {
-    if (mode == kSym) launch_one<CG, kSym, 3, 3>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
-    else if (mode == kWrite) launch_one<CG, kWrite, 3, 3>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
-    else launch_one<CG, kFull, 3, 3>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
+    if constexpr (CG <= kMaxCG3) {
+      if (mode == kSym) launch_one<CG, kSym, 3, 3>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
+      else if (mode == kWrite) launch_one<CG, kWrite, 3, 3>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
+      else launch_one<CG, kFull, 3, 3>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else if (gt == 2 && xt == 2) {
     if (mode == kSym) launch_one<CG, kSym, 2, 2>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
     else if (mode == kWrite) launch_one<CG, kWrite, 2, 2>(Xt, ldg, cfg, blocks, Yp, src, Gw, s);
@@ -556,7 +566,8 @@ int split_pass_rows() { return kBM; }
 
 hipError_t launch_split_pass(int gterms, int xterms, const void* Xt, int64_t ldg, int l_pad, const GPassCfg& cfg,
                              int64_t blocks, void* Yp, const GPassDSrc& src, void* Gw, hipStream_t s) {
-  if (!src.D || src.d_is_f64 || !src.vec || src.n % 4 != 0 || cfg.bm != kBM || l_pad % 16 != 0 || l_pad > 128)
+  if (!src.D || src.d_is_f64 || !src.vec || src.n % 4 != 0 || cfg.bm != kBM || l_pad % 16 != 0 ||
+      l_pad > 16 * (gterms == 3 ? kMaxCG3 : kMaxCG2))
     return hipErrorInvalidValue;
   if (Gw && cfg.sym) return hipErrorInvalidValue;
   // the fused write stores aligned pairs of steps: every K range starts on an
@@ -567,6 +578,7 @@ hipError_t launch_split_pass(int gterms, int xterms, const void* Xt, int64_t ldg
 #define MDS_CG(N) \
   case N: return launch_cg<N>(mode, gterms, xterms, Xt, ldg, cfg, blocks, Yp, src, Gw, s);
     MDS_CG(1) MDS_CG(2) MDS_CG(3) MDS_CG(4) MDS_CG(5) MDS_CG(6) MDS_CG(7) MDS_CG(8)
+    MDS_CG(9) MDS_CG(10) MDS_CG(11) MDS_CG(12) MDS_CG(13) MDS_CG(14)
 #undef MDS_CG
     default: return hipErrorInvalidValue;
   }

@@ -495,6 +495,33 @@ def test_large_l_global_scratch_path():
     assert procrustes_err(X, ref["coords"]) < 1e-8
 
 
+@pytest.mark.parametrize("k,form,full", [(150, "bf16", False), (200, "bf16", False), (200, "bf16", True),
+                                         (200, "fp8", False)])
+def test_wide_l_streaming_passes(k, form, full):
+    """l_pad in (128, 224]: the 16-bit passes from D stream D through LDS with
+    up to 14 column groups (fused write and sketch of Omega, last range pass,
+    symmetric or full projection), against the oracle with the form's
+    roundings and against the plain fp64 method."""
+    n, p, q = 3000, 20, 1
+    say(f"[wide l] n={n} l={k + p} form={form} full_projection={full}")
+    X, _ = W.gaussian_mixture(n, 200, 50, 9.0, 5)
+    D = W.euclidean_distances(X, dtype=np.float32)
+    ref = O.rand_mds(D, k, p, q, 4, form=form)
+    plain = O.rand_mds(D, k, p, q, 4)
+    plan = mds.Plan(n, k, p, q, 4, form=form, full_projection=full)
+    coords, eig = plan.run(torch.from_numpy(D).cuda())
+    info = plan.info()
+    torch.cuda.synchronize()
+    eig = eig.cpu().numpy()
+    err, perr = rel_eig_err(eig, ref["eigvals"]), rel_eig_err(eig, plain["eigvals"])
+    say(f"    eig vs matched oracle {err:.2e}, vs plain {perr:.2e}")
+    assert info["status"] == 0
+    assert err < MATCHED_EIG_BAR[form]
+    if form == "bf16":
+        assert perr < EIG_BAR["bf16"]
+    assert procrustes_err(coords.cpu().numpy(), ref["coords"]) < COORD_BAR[form]
+
+
 def test_tiny_problem():
     say("[edge] n = 2")
     D = np.array([[0.0, 3.0], [3.0, 0.0]], dtype=np.float32)
