@@ -773,7 +773,7 @@ __global__ __launch_bounds__(256, 2) void k_gpass_x3(const uint16_t* __restrict_
 // The split passes that stream D through LDS (fp32 D, n % 4 == 0, aligned D,
 // l_pad <= 128 with three terms, <= 224 with two) run in k_split.hip: 8 waves
 // of 2 row groups per workgroup.  The pass over the stored bf16 G streams
-// up to l_pad = 128 (k_gstream).
+// up to l_pad = 224 as well (k_gstream).
 constexpr int kDmaMaxL = 128, kDmaMaxL2 = 224;
 
 // Symmetric mode: row block mb has partials only in the splits whose K
@@ -940,7 +940,7 @@ GPassCfg gpass_config(int gk, int l_pad, int64_t n_pad, int64_t ldg, int split_h
     c.rg = 2;
     c.bm = split_pass_rows();
   }
-  if (gk == GK_BF16 && !from_d && dma_ok && l_pad <= kDmaMaxL && n_pad % gstream_rows() == 0 && ldg == n_pad) {
+  if (gk == GK_BF16 && !from_d && dma_ok && l_pad <= kDmaMaxL2 && n_pad % gstream_rows() == 0 && ldg == n_pad) {
     c.dma = 1;  // k_gstream: the stored bf16 G through an LDS ring, same work mapping
     c.rg = 2;
     c.bm = gstream_rows();

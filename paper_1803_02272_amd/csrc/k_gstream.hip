@@ -17,11 +17,12 @@
 //     ring needs no workgroup barrier;
 //   * the X tile of a step (l_pad rows of 128 bytes) is loaded the same way,
 //     two steps ahead, into a three-buffer ring shared by the eight waves
-//     (one barrier per step);
+//     (one barrier per step); above l_pad = 128 the ring has two buffers
+//     and the tile is loaded one step ahead;
 //   * 16-byte pieces of a 128-byte row r sit in slot piece ^ f(r),
 //     f(r) = (r % 8) ^ ((r / 8) % 2): the MFMA operand reads (16 rows at one
 //     piece) then fall on distinct banks for 8 and for 16 lanes at a time.
-// Requires l_pad <= 128, ldg a multiple of 256 and n_pad = ldg rows of G.
+// Requires l_pad <= 224, ldg a multiple of 256 and n_pad = ldg rows of G.
 #include "mds_internal.h"
 
 namespace mds {
@@ -47,7 +48,10 @@ __device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t r, uint32_t voff, v
 }
 __device__ __forceinline__ int swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
-template <int CG>
+// XB: X buffers, 3 (X loaded two steps ahead) up to l_pad = 128; 2 (one
+// step ahead) for the wider tiles, whose three buffers would not fit in LDS
+// beside the G stages.
+template <int CG, int XB>
 __global__ __launch_bounds__(512, 1) void k_gstream(const uint16_t* __restrict__ G, int64_t ldg,
                                                     const uint16_t* __restrict__ Xt, int64_t steps_total,
                                                     int64_t steps_per_split, float* __restrict__ Ypart, int64_t n,
@@ -60,7 +64,7 @@ __global__ __launch_bounds__(512, 1) void k_gstream(const uint16_t* __restrict__
   __shared__ __attribute__((aligned(16))) unsigned char gs2[kWaves * kStage];
   __shared__ __attribute__((aligned(16))) unsigned char xs0[LPAD * 128];
   __shared__ __attribute__((aligned(16))) unsigned char xs1[LPAD * 128];
-  __shared__ __attribute__((aligned(16))) unsigned char xs2[LPAD * 128];
+  __shared__ __attribute__((aligned(16))) unsigned char xs2[XB == 3 ? LPAD * 128 : 16];
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -119,11 +123,13 @@ __global__ __launch_bounds__(512, 1) void k_gstream(const uint16_t* __restrict__
   const int64_t last = st1 - 1;
   auto clamp = [&](int64_t st) { return st < st1 ? st : last; };
   // G(st) and X(st) landed and every wave's part of X(st) visible; no wave
-  // reads X(st - 1) any more.  After X(st) each wave issued G(st + 1),
-  // X(st + 1) and G(st + 2) (in this order: the loads of step st - 1 are
-  // X(st + 1), then G(st + 2) at its end).
+  // reads X(st - 1) any more.  With three X buffers, after X(st) each wave
+  // issued G(st + 1), X(st + 1) and G(st + 2) (in this order: the loads of
+  // step st - 1 are X(st + 1), then G(st + 2) at its end); with two, G(st + 1)
+  // and G(st + 2) come before X(st), and only G(st + 3) after it.
+  constexpr int kAfter = XB == 3 ? 8 + XPW : 4;  // loads allowed in flight
   auto settle = [&]() {
-    __builtin_amdgcn_s_waitcnt(0x0F70 | (8 + XPW));
+    __builtin_amdgcn_s_waitcnt(0x0F70 | kAfter);
     __asm__ volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     __asm__ volatile("" ::: "memory");
@@ -131,16 +137,24 @@ __global__ __launch_bounds__(512, 1) void k_gstream(const uint16_t* __restrict__
   dma_g(st0, gs0);
   dma_x(st0, xs0);
   dma_g(clamp(st0 + 1), gs1);
-  dma_x(clamp(st0 + 1), xs1);
-  dma_g(clamp(st0 + 2), gs2);
-  settle();
+  if constexpr (XB == 3) {
+    dma_x(clamp(st0 + 1), xs1);
+    dma_g(clamp(st0 + 2), gs2);
+    settle();
+  } else {
+    dma_g(clamp(st0 + 2), gs2);
+    __builtin_amdgcn_s_waitcnt(0x0F70 | 8);  // G(st0) and X(st0)
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+  }
 
-  // One step: G(st) in gb, X(st) in xb; X(st + 2) goes to xn (which held
-  // X(st - 1)) and G(st + 3) to gb once this wave has read it; then the
+  // One step: G(st) in gb, X(st) in xb; X(st + XB - 1) goes to xn (which
+  // held X(st - 1)) and G(st + 3) to gb once this wave has read it; then the
   // state above for st + 1 (the wait ends the step, so that the loop closes
   // after it and the compiler's own wait counts stay exact).
   auto step = [&](int64_t st, GBuf& gb, XBuf& xb, XBuf& xn) {
-    dma_x(clamp(st + 2), xn);
+    dma_x(clamp(st + XB - 1), xn);
     // the X load goes out first.  (At the top of the loop the compiler adds a
     // wait for the older loads: it does not carry the ring's state across
     // the back edge.  Six steps per trip make that one step in six.)
@@ -171,18 +185,34 @@ __global__ __launch_bounds__(512, 1) void k_gstream(const uint16_t* __restrict__
     dma_g(clamp(st + 3), gb);
     settle();
   };
-  for (int64_t st = st0; st < st1; st += 6) {
-    step(st, gs0, xs0, xs2);
-    if (st + 1 >= st1) break;
-    step(st + 1, gs1, xs1, xs0);
-    if (st + 2 >= st1) break;
-    step(st + 2, gs2, xs2, xs1);
-    if (st + 3 >= st1) break;
-    step(st + 3, gs0, xs0, xs2);
-    if (st + 4 >= st1) break;
-    step(st + 4, gs1, xs1, xs0);
-    if (st + 5 >= st1) break;
-    step(st + 5, gs2, xs2, xs1);
+  if constexpr (XB == 3) {
+    for (int64_t st = st0; st < st1; st += 6) {
+      step(st, gs0, xs0, xs2);
+      if (st + 1 >= st1) break;
+      step(st + 1, gs1, xs1, xs0);
+      if (st + 2 >= st1) break;
+      step(st + 2, gs2, xs2, xs1);
+      if (st + 3 >= st1) break;
+      step(st + 3, gs0, xs0, xs2);
+      if (st + 4 >= st1) break;
+      step(st + 4, gs1, xs1, xs0);
+      if (st + 5 >= st1) break;
+      step(st + 5, gs2, xs2, xs1);
+    }
+  } else {
+    for (int64_t st = st0; st < st1; st += 6) {
+      step(st, gs0, xs0, xs1);
+      if (st + 1 >= st1) break;
+      step(st + 1, gs1, xs1, xs0);
+      if (st + 2 >= st1) break;
+      step(st + 2, gs2, xs0, xs1);
+      if (st + 3 >= st1) break;
+      step(st + 3, gs0, xs1, xs0);
+      if (st + 4 >= st1) break;
+      step(st + 4, gs1, xs0, xs1);
+      if (st + 5 >= st1) break;
+      step(st + 5, gs2, xs1, xs0);
+    }
   }
   __builtin_amdgcn_s_waitcnt(0x0F70);  // no load into LDS outstanding at exit
 
@@ -211,17 +241,19 @@ int gstream_rows() { return kBM; }
 
 hipError_t launch_gstream(const void* G, int64_t ldg, const void* Xt, int l_pad, const GPassCfg& cfg, int64_t n,
                           int64_t blocks, void* Yp, hipStream_t s) {
-  if (!G || !Xt || !Yp || l_pad % 16 != 0 || l_pad < 16 || l_pad > 128 || ldg % kBM != 0 || cfg.bm != kBM ||
+  if (!G || !Xt || !Yp || l_pad % 16 != 0 || l_pad < 16 || l_pad > 224 || ldg % kBM != 0 || cfg.bm != kBM ||
       !cfg.dma || cfg.steps_total * 64 != ldg || blocks != 8 * cfg.sym_nbx * cfg.split)
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks), block(64 * kWaves);
   switch (l_pad / 16) {
 #define MDS_CG(N)                                                                                           \
   case N:                                                                                                   \
-    hipLaunchKernelGGL(k_gstream<N>, grid, block, 0, s, (const uint16_t*)G, ldg, (const uint16_t*)Xt,      \
+    hipLaunchKernelGGL((k_gstream<N, (N <= 8 ? 3 : 2)>), grid, block, 0, s, (const uint16_t*)G, ldg,      \
+                       (const uint16_t*)Xt,                                                                \
                        cfg.steps_total, cfg.steps_per_split, (float*)Yp, n, cfg.sym_nbx);                  \
     return hipGetLastError();
     MDS_CG(1) MDS_CG(2) MDS_CG(3) MDS_CG(4) MDS_CG(5) MDS_CG(6) MDS_CG(7) MDS_CG(8)
+    MDS_CG(9) MDS_CG(10) MDS_CG(11) MDS_CG(12) MDS_CG(13) MDS_CG(14)
 #undef MDS_CG
     default: return hipErrorInvalidValue;
   }
