@@ -109,7 +109,9 @@ void layout(mds_plan_s* P) {
   add(P, P->V, (size_t)lp * lp * 8);
   add(P, P->theta, (size_t)lp * 8);
   add(P, P->Tc, (size_t)lp * P->k * 8);
-  add(P, P->small, (size_t)2 * lp * lp * 8);
+  // the eigensolve's working copies (l_pad > 128: A and Q) and the blocked factor's blocks
+  const size_t small = (size_t)2 * lp * lp * 8;
+  add(P, P->small, small > orth_factor_scratch_bytes(lp) ? small : orth_factor_scratch_bytes(lp));
   add(P, P->rot, small_eig_rot_bytes(P->l));
   add(P, P->meta, (size_t)(P->l + 1) * sizeof(int));
   const int64_t nch = coords_anchor_chunks(n);

@@ -204,12 +204,14 @@ hipError_t launch_coords(const double* Qt, int l, int64_t n, int64_t ldg, const 
                          double* Ct, double* coords, double* sign_part, int64_t* idx_part, hipStream_t s);
 
 // ---- small dense kernels (one workgroup) ------------------------------------
-// T such that Y T has orthonormal columns, from W = Y^T Y (Cholesky, or an
-// eigen-based inverse square root when Cholesky breaks down).
+// T such that Y T has orthonormal columns, from W = Y^T Y (deflating
+// Cholesky, T = R^{-1}; for l_pad > 128 as two diagonal blocks).
 // near_identity: W is the Gram matrix of an almost orthonormal basis (second
 // CholeskyQR step); a first-order factor is used when W is within 1e-9 of I.
+// scratch: orth_factor_scratch_bytes(l_pad) bytes of device memory.
 hipError_t launch_orth_factor(const double* W, int l, int l_pad, double* T, double* scratch,
                               DevStatus* st, int near_identity, hipStream_t s);
+size_t orth_factor_scratch_bytes(int l_pad);
 // Eigenpairs of the symmetrised B (algebraic descending); Tc = V_k diag(sqrt(max(theta,0))).
 size_t small_eig_rot_bytes(int l);
 hipError_t launch_small_eig(const double* B, int l, int l_pad, int k, double* theta, double* V,

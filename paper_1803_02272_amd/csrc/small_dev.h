@@ -11,7 +11,6 @@ namespace mds {
 namespace small {
 
 constexpr int kEigThreads = 1024;  // small_eig workgroup
-constexpr int kOrthThreads = 256;  // orth_factor workgroup, l_pad > 128 (global scratch)
 constexpr int kOrthRegThreads = 1024;  // orth_factor workgroup, l_pad <= 128 (register-resident factor)
 constexpr int kSmallLMax = 64;              // l_pad up to which orth_factor runs a quarter of the threads
 constexpr int kOrthRegThreadsSmall = 256;   // orth_factor workgroup, l_pad <= kSmallLMax

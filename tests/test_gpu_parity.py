@@ -473,6 +473,31 @@ def test_rank_deficient_matches_exact():
     assert np.allclose(Xg @ Xg.T, full["coords"] @ full["coords"].T, atol=1e-8 * full["eigvals"][0])
 
 
+def test_rank_deficient_wide_l():
+    """l = 150 > 128 on a rank-60 cloud: the factor of the orthonormalisation
+    runs as two diagonal blocks and drops columns in both, and the
+    eigensolve is the tridiagonal QL; the top 60 eigenpairs are exact."""
+    say("[edge] rank 60 < l = 150")
+    X, _ = W.gaussian_mixture(700, 60, 5, 9.0, seed=6)
+    D = W.euclidean_distances(X)
+    full = O.full_mds(D, 60)
+    plan, Xg, eig, info = gpu_run(D, 60, 90, 1, 0, "fp64")
+    say(f"    fallbacks {info['orth_fallbacks']}, QL steps {info['jacobi_sweeps']}")
+    assert info["status"] == 0
+    assert info["orth_fallbacks"] > 0
+    assert rel_eig_err(eig, full["eigvals"]) < 1e-10
+    assert procrustes_err(Xg, full["coords"]) < 1e-8
+
+
+def test_zero_distance_matrix_wide_l():
+    say("[edge] all-zero D, l = 140")
+    D = np.zeros((400, 400), dtype=np.float32)
+    _, X, eig, info = gpu_run(D, 100, 40, 1, 0, "fp32")
+    assert info["status"] == 0
+    assert np.all(eig == 0) and np.all(X == 0)
+    assert info["orth_fallbacks"] > 0
+
+
 @pytest.mark.parametrize("k,p,q", [(7, 6, 1), (10, 0, 1), (6, 6, 0), (1, 1, 2)])
 def test_shapes_odd_l_no_oversample_no_power(k, p, q):
     say(f"[edge] k={k} p={p} q={q}")
