@@ -36,18 +36,18 @@ METRIC = "n=1e5 k=100 MDS time & MFMA util, BF16 vs FP32 @1e-3 eig err; p99 late
 # workload, bf16 form.  Valid only while the kernel source is the one
 # measured: the sha256 prefix of the file is checked and `traffic` is null
 # otherwise.
-_KS = {"source": "paper_1803_02272_amd/csrc/k_split.hip", "sha256_16": "6e44ddec6afe3c5b",
+_KS = {"source": "paper_1803_02272_amd/csrc/k_split.hip", "sha256_16": "c7df2a39625cda63",
        "n": 100000, "l_pad": 128, "form": "bf16"}
 TRAFFIC = {
-    # fused centring write + 16-bit range pass 1 (k_split<kWrite, 2 terms>)
-    "write": dict(_KS, fetch_gb=42.487, write_gb=20.952),
-    # 16-bit last range pass from D (k_split<kFull, 2 terms>)
-    "gpass_f32": dict(_KS, fetch_gb=41.853, write_gb=0.684),
-    # 16-bit symmetric projection (k_split<kSym, 2 terms>)
-    "gpass_ref": dict(_KS, fetch_gb=22.141, write_gb=0.443),
+    # fused centring write + 16-bit range pass 1 (k_split<kWrite, 2 + 2 terms>)
+    "write": dict(_KS, fetch_gb=42.513, write_gb=20.932),
+    # 16-bit last range pass from D (k_split<kFull, 2 + 1 terms>)
+    "gpass_f32": dict(_KS, fetch_gb=41.373, write_gb=0.629),
+    # 16-bit symmetric projection (k_split<kSym, 2 + 2 terms>)
+    "gpass_ref": dict(_KS, fetch_gb=22.712, write_gb=0.649),
     # range pass over the stored bf16 G (k_gstream)
-    "gpass": {"source": "paper_1803_02272_amd/csrc/k_gstream.hip", "sha256_16": "52fc14276cfd36ee",
-              "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 20.588, "write_gb": 0.155},
+    "gpass": {"source": "paper_1803_02272_amd/csrc/k_gstream.hip", "sha256_16": "4ea1c0b75ff05063",
+              "n": 100000, "l_pad": 128, "form": "bf16", "fetch_gb": 20.587, "write_gb": 0.155},
 }
 
 # MI355X published peaks
@@ -487,7 +487,7 @@ def main():
         if phase == "write":
             if form == "bf16":
                 return (6.0 * n * n + n * l * (6 + 4), 2.0 * n * n * l, 3 * 2.0 * n * n * l_pad, "bf16",
-                        "k_split<kWrite, 2 terms> (fused centring write + 16-bit range pass 1)")
+                        "k_split<kWrite, 2 + 2 terms> (fused centring write + 16-bit range pass 1)")
             if form == "bf16a":
                 return (6.0 * n * n + n * l * (2 + 4), 2.0 * n * n * l, 2.0 * n * n * l_pad, "bf16",
                         "k_gpass<bf16, from D> (fused centring write + bf16 range pass 1)")
@@ -512,7 +512,7 @@ def main():
         if phase == "gpass_ref":
             if lowp:
                 return (2.0 * n * n + n * l * (6 + 4), 1.0 * n * n * l, 3.0 * n * n * l_pad, "bf16",
-                        "k_split<kSym, 2 terms> (16-bit symmetric projection)")
+                        "k_split<kSym, 2 + 2 terms> (16-bit symmetric projection)")
             if form == "fp32s":
                 return (2.0 * n * n + n * l * (6 + 4), 1.0 * n * n * l, 6.0 * n * n * l_pad, "bf16",
                         "k_split<kSym, 3 terms> (fp32 symmetric projection as three-term split)")
