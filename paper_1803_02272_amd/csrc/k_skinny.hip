@@ -25,19 +25,19 @@ __device__ __forceinline__ uint16_t bf16_rne(double v) {
 
 constexpr int kGramChunk = 512;   // most columns of the transposed layout per gram workgroup
 constexpr int kGramStep = 32;     // columns staged in LDS per step
-constexpr int kGramRow = kGramStep + 1;  // LDS row stride (doubles)
 constexpr int kGramThreads = 512;
 
 // Wpart[p] = A_p B_p^T over column chunk p (chunk columns, a multiple of 64):
-// every workgroup stages 32-column slices of all l_pad rows of A (and B) in
+// every workgroup stages STEP-column slices of all l_pad rows of A (and B) in
 // LDS (double-buffered, 16-byte loads), and each of its 8 waves accumulates
 // a share of the 16 x 16 output
 // tiles with fp64 MFMA (16x16x4).  sym (A == B): only tiles on or above the
 // diagonal are computed; k_sum_parts mirrors them.
-template <int CG, bool SYM>
+template <int CG, bool SYM, int STEP>
 __global__ __launch_bounds__(kGramThreads) void k_gram(const double* __restrict__ A, const double* __restrict__ B,
                                                        int64_t ldg, int l_pad, double* __restrict__ Wpart,
                                                        int64_t chunk) {
+  constexpr int kGramRow = STEP + 1;  // LDS row stride (doubles)
   constexpr int NT = SYM ? CG * (CG + 1) / 2 : CG * CG;  // output tiles
   constexpr int NW = kGramThreads / 64;
   constexpr int TPW = (NT + NW - 1) / NW;  // tiles per wave (at most)
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const double* __restrict_
 #pragma unroll
   for (int u = 0; u < TPW; ++u) acc[u] = doublex4_t{0.0, 0.0, 0.0, 0.0};
   // staging: LP rows x 32 doubles per matrix = LP * 16 pieces of 16 bytes
-  constexpr int PIECES = LP * (kGramStep / 2);
+  constexpr int PIECES = LP * (STEP / 2);
   constexpr int PPT = (PIECES + kGramThreads - 1) / kGramThreads;
   double2 rg[NB][PPT];
   auto load = [&](int64_t k0) {
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const double* __restrict_
       for (int u = 0; u < PPT; ++u) {
         const int pc = tid + kGramThreads * u;
         if (PIECES % kGramThreads == 0 || pc < PIECES) {
-          const int row = pc / (kGramStep / 2), c2 = pc % (kGramStep / 2);
+          const int row = pc / (STEP / 2), c2 = pc % (STEP / 2);
           const double* src = (m == 0 ? A : B) + (int64_t)row * ldg + k0 + 2 * c2;
           rg[m][u] = k0 < i1 ? *reinterpret_cast<const double2*>(src) : double2{0.0, 0.0};
         }
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const double* __restrict_
       for (int u = 0; u < PPT; ++u) {
         const int pc = tid + kGramThreads * u;
         if (PIECES % kGramThreads == 0 || pc < PIECES) {
-          const int row = pc / (kGramStep / 2), c2 = pc % (kGramStep / 2);
+          const int row = pc / (STEP / 2), c2 = pc % (STEP / 2);
           st[buf][m][row * kGramRow + 2 * c2] = rg[m][u].x;
           st[buf][m][row * kGramRow + 2 * c2 + 1] = rg[m][u].y;
         }
@@ -102,13 +102,13 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const double* __restrict_
   store(0);
   __syncthreads();
   int buf = 0;
-  for (int64_t k0 = i0; k0 < i1; k0 += kGramStep) {
-    const bool more = k0 + kGramStep < i1;
-    if (more) load(k0 + kGramStep);
+  for (int64_t k0 = i0; k0 < i1; k0 += STEP) {
+    const bool more = k0 + STEP < i1;
+    if (more) load(k0 + STEP);
     const double* SA = st[buf][0];
     const double* SB = st[buf][NB - 1];
 #pragma unroll
-    for (int kg = 0; kg < kGramStep; kg += 4) {
+    for (int kg = 0; kg < STEP; kg += 4) {
 #pragma unroll
       for (int u = 0; u < TPW; ++u) {
         // fp64 MFMA operands: lane supplies row l % 16 and K index l / 16
@@ -133,8 +133,11 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const double* __restrict_
 }
 
 // Register-streamed variant for l_pad > 128 (the LDS tiles of k_gram would
-// not fit): each wave owns a 16-row tile strip over one column chunk.
-template <int CG>
+// need too many accumulators per wave): each wave owns a 16-row tile strip
+// over one column chunk; SYM (A == B): only the tiles on or above the
+// diagonal are computed (the strip's B loads and MFMAs left of it are
+// skipped), as in k_gram.
+template <int CG, bool SYM>
 __global__ __launch_bounds__(256) void k_gram_wide(const double* __restrict__ A, const double* __restrict__ B,
                                               int64_t ldg, int l_pad, double* __restrict__ Wpart, int64_t chunk) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -152,31 +155,36 @@ __global__ __launch_bounds__(256) void k_gram_wide(const double* __restrict__ A,
   double2 a = *reinterpret_cast<const double2*>(Ar + i0);
   double2 b[CG];
 #pragma unroll
-  for (int cg = 0; cg < CG; ++cg) b[cg] = *reinterpret_cast<const double2*>(Br + (int64_t)cg * 16 * ldg + i0);
+  for (int cg = 0; cg < CG; ++cg)
+    if (!SYM || cg >= tr) b[cg] = *reinterpret_cast<const double2*>(Br + (int64_t)cg * 16 * ldg + i0);
   for (int64_t k = i0; k < i1; k += 8) {
     const bool more = k + 8 < i1;
     double2 an = a, bn[CG];
     if (more) {
       an = *reinterpret_cast<const double2*>(Ar + k + 8);
 #pragma unroll
-      for (int cg = 0; cg < CG; ++cg) bn[cg] = *reinterpret_cast<const double2*>(Br + (int64_t)cg * 16 * ldg + k + 8);
+      for (int cg = 0; cg < CG; ++cg)
+        if (!SYM || cg >= tr) bn[cg] = *reinterpret_cast<const double2*>(Br + (int64_t)cg * 16 * ldg + k + 8);
     }
 #pragma unroll
-    for (int cg = 0; cg < CG; ++cg) {
-      acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[cg].x, acc[cg], 0, 0, 0);
-      acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b[cg].y, acc[cg], 0, 0, 0);
-    }
+    for (int cg = 0; cg < CG; ++cg)
+      if (!SYM || cg >= tr) {
+        acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[cg].x, acc[cg], 0, 0, 0);
+        acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b[cg].y, acc[cg], 0, 0, 0);
+      }
     if (more) {
       a = an;
 #pragma unroll
-      for (int cg = 0; cg < CG; ++cg) b[cg] = bn[cg];
+      for (int cg = 0; cg < CG; ++cg)
+        if (!SYM || cg >= tr) b[cg] = bn[cg];
     }
   }
   double* W = Wpart + p * (int64_t)l_pad * l_pad;
 #pragma unroll
   for (int cg = 0; cg < CG; ++cg)
+    if (!SYM || cg >= tr)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < 4; ++r)
       // fp64 MFMA accumulator: register r of lane group g is row g + 4r
       W[(int64_t)(tr * 16 + (lane >> 4) + 4 * r) * l_pad + cg * 16 + (lane & 15)] = acc[cg][r];
 }
@@ -431,13 +439,18 @@ template <int CG>
 void gram_one(const double* A, const double* B, int l_pad, int64_t ldg, double* Wpart, hipStream_t s) {
   const int64_t chunk = gram_chunk_cols(ldg);
   dim3 grid((unsigned)((ldg + chunk - 1) / chunk));
-  if constexpr (CG > 8)
-    hipLaunchKernelGGL(k_gram_wide<CG>, dim3(grid.x, (unsigned)((CG + 3) / 4)), dim3(256), 0, s, A, B, ldg, l_pad,
-                       Wpart, chunk);
-  else if (A == B)
-    hipLaunchKernelGGL((k_gram<CG, true>), grid, dim3(kGramThreads), 0, s, A, B, ldg, l_pad, Wpart, chunk);
-  else
-    hipLaunchKernelGGL((k_gram<CG, false>), grid, dim3(kGramThreads), 0, s, A, B, ldg, l_pad, Wpart, chunk);
+  if constexpr (CG > 8) {
+    const dim3 wg(grid.x, (unsigned)((CG + 3) / 4));
+    if (A == B)
+      hipLaunchKernelGGL((k_gram_wide<CG, true>), wg, dim3(256), 0, s, A, B, ldg, l_pad, Wpart, chunk);
+    else
+      hipLaunchKernelGGL((k_gram_wide<CG, false>), wg, dim3(256), 0, s, A, B, ldg, l_pad, Wpart, chunk);
+  } else if (A == B) {
+    hipLaunchKernelGGL((k_gram<CG, true, kGramStep>), grid, dim3(kGramThreads), 0, s, A, B, ldg, l_pad, Wpart, chunk);
+  } else {
+    hipLaunchKernelGGL((k_gram<CG, false, kGramStep>), grid, dim3(kGramThreads), 0, s, A, B, ldg, l_pad, Wpart,
+                       chunk);
+  }
 }
 
 }  // namespace
@@ -460,7 +473,7 @@ hipError_t launch_gram(const double* A, const double* B, int l_pad, int64_t ldg,
   }
   const int64_t elems = (int64_t)l_pad * l_pad;
   hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((elems + kSumEntries - 1) / kSumEntries)), dim3(256), 0, s, Wpart,
-                     gram_chunks(ldg), elems, W, l_pad, (A == B && l_pad <= 128) ? 1 : 0);
+                     gram_chunks(ldg), elems, W, l_pad, A == B ? 1 : 0);
   return hipGetLastError();
 }
 
