@@ -69,8 +69,8 @@ def test_c4_full_size_against_point_cloud_spectrum():
             # rounding of D; the stated fp32 bar applies
             assert errs[form] < 1e-5
         else:
-            # bf16 and fp8 storage of G (fp32 first and last range passes and
-            # projection): the stated 1e-3 bar of the low-precision forms
+            # bf16 and fp8 storage of G (16-bit first and last range passes
+            # and projection): the stated 1e-3 bar of the low-precision forms
             assert errs[form] < 1e-3
         plan.close()
         del coords, eig
