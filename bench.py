@@ -53,7 +53,7 @@ TRAFFIC = {
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
-PEAK_INT8_TOPS = 5000.0
+PEAK_FP4_TFLOPS = 10100.0
 
 
 def measured_traffic(name, n, l_pad, form):
@@ -282,13 +282,13 @@ def _event_ms(torch, fn, reps=3):
 
 def time_distances(mds, torch, codes, D):
     """mds_hamming_distances writing the benchmark's D: n^2 fp32 entries
-    written, 2 n^2 (4 L) int8 MFMA operations (one-hot inner products)."""
+    written, 2 n^2 (4 L) fp4 MFMA operations (one-hot inner products)."""
     n, L = codes.shape
     ms = _event_ms(torch, lambda: mds.hamming_distances(codes, out=D))
     wbytes, ops = 4.0 * n * n, 2.0 * n * n * 4 * L
-    return {"kernel": "k_hamming (one-hot int8 MFMA 16x16x64, D written in fp32)", "ms": ms, "n": n, "length": L,
-            "write_gbs": wbytes / ms / 1e6, "hbm_frac": wbytes / ms / 1e6 / PEAK_HBM_GBS,
-            "int8_tops": ops / ms / 1e9, "int8_frac": ops / ms / 1e9 / PEAK_INT8_TOPS}
+    return {"kernel": "k_hamming (fp4 one-hot, scaled MFMA 16x16x128, D written in fp32)", "ms": ms, "n": n,
+            "length": L, "write_gbs": wbytes / ms / 1e6, "hbm_frac": wbytes / ms / 1e6 / PEAK_HBM_GBS,
+            "fp4_tflops": ops / ms / 1e9, "fp4_frac": ops / ms / 1e9 / PEAK_FP4_TFLOPS}
 
 
 def time_components(mds, torch, D, theta):

@@ -5,9 +5,12 @@
 // Hamming distance of reads (the stand-in for the alignment-based
 // dissimilarity: substitutions only).  Reads are base codes 0..3; the number
 // of matching positions of reads i and j is the inner product of their
-// one-hot encodings (4 bytes per position), an exact integer GEMM on int8
-// MFMA (16x16x64, int32 accumulation).  d_ij = (L - matches) / L as the fp64
-// quotient rounded to the output type, looked up in a per-workgroup table.
+// one-hot encodings, 4 fp4 (e2m1) values per position with 1.0 (code 0x2)
+// at the base's slot: an exact GEMM on gfx950's scaled MFMA 16x16x128 with
+// fp4 operands (unit scales, fp32 accumulation of integer counts <= 2048),
+// 32 positions per instruction, half the instructions and half the operand
+// bytes of the int8 form.  d_ij = (L - matches) / L as the fp64 quotient
+// rounded to the output type, looked up in a per-workgroup table.
 // A code outside 0..3 matches nothing (an unknown base counts as a mismatch,
 // also against itself).  The one-hot operands are expanded from the codes
 // into LDS per K-step, so the call needs no workspace and reads each code
@@ -25,18 +28,27 @@
 namespace mds {
 namespace {
 
-typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // ---- Hamming ---------------------------------------------------------------
 constexpr int kHI = 256;      // rows (i) per tile
 constexpr int kHJ = 128;      // columns (j) per tile
 constexpr int kHThreads = 512;  // 8 waves: 4 (i) x 2 (j), 64 x 64 outputs each
-constexpr int kHBases = 16;   // bases per K-step: 64 one-hot bytes per row
+constexpr int kHBases = 32;   // bases per K-step: 64 bytes of fp4 one-hot per row
 constexpr int kHRows = kHI + kHJ;  // code rows loaded per step
 
-// one-hot bytes of four codes (code c -> byte c set to 1; other codes -> 0)
-__device__ __forceinline__ uint32_t onehot1(uint32_t c) { return c < 4 ? (1u << (8 * c)) : 0u; }
+constexpr int kHStgRow = 68;  // floats per staged output row (64 + 4 of padding)
+static_assert(kHThreads / 64 * 16 * kHStgRow * 4 <= 2 * kHRows * 64, "the output stage fits the one-hot buffers");
+
+// LDS writes of this wave visible to its other lanes
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// fp4 one-hot of a code: nibble c holds 1.0 (e2m1 0x2); other codes -> 0
+__device__ __forceinline__ uint32_t onehot4(uint32_t c) { return c < 4 ? (0x2u << (4 * c)) : 0u; }
 
 // 16-byte slot of piece p (0..3) of a 64-byte operand row r: rows 4m .. 4m+3
 // are rotated by m so that 16 consecutive rows at one piece fall on distinct
@@ -59,20 +71,26 @@ __global__ __launch_bounds__(kHThreads, 1) void k_hamming(const uint8_t* __restr
   const bool crow_ok = loader && crow < n;
   const uint8_t* cp = codes + (crow_ok ? crow : 0) * (int64_t)L;
   const int steps = (L + kHBases - 1) / kHBases;
-  // 16 codes of step s (positions past L and rows past n read as 0xFF)
-  auto load_codes = [&](int s, uint32_t (&w)[4]) {
+  // 32 codes of step s, 4 per word (positions past L and rows past n read as 0xFF)
+  auto load_codes = [&](int s, uint32_t (&w)[8]) {
     const int p0 = s * kHBases;
     if (p0 >= L) {  // past the last step
-      w[0] = w[1] = w[2] = w[3] = 0xFFFFFFFFu;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) w[q] = 0xFFFFFFFFu;
       return;
     }
     if (VEC == 16 && crow_ok && p0 + kHBases <= L) {
-      const u32x4 v = *reinterpret_cast<const u32x4*>(cp + p0);
-      w[0] = v[0]; w[1] = v[1]; w[2] = v[2]; w[3] = v[3];
+      const u32x4 v0 = *reinterpret_cast<const u32x4*>(cp + p0);
+      const u32x4 v1 = *reinterpret_cast<const u32x4*>(cp + p0 + 16);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        w[q] = v0[q];
+        w[4 + q] = v1[q];
+      }
       return;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       uint32_t x = 0;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
@@ -83,37 +101,42 @@ __global__ __launch_bounds__(kHThreads, 1) void k_hamming(const uint8_t* __restr
       w[q] = x;
     }
   };
-  // one-hot row of the 16 codes into buffer buf: 4 positions per 16-byte piece
-  auto store_onehot = [&](const uint32_t (&w)[4], int buf) {
+  // fp4 one-hot row of the 32 codes into buffer buf: piece q (16 bytes) holds
+  // positions 8q .. 8q + 7, two per word (16 bits each, the lower position in
+  // the low half)
+  auto store_onehot = [&](const uint32_t (&w)[8], int buf) {
     if (!loader) return;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       u32x4 o;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) o[b] = onehot1((w[q] >> (8 * b)) & 0xFFu);
+      for (int d = 0; d < 4; ++d) {
+        const uint32_t word = w[2 * q + d / 2], sh = 16 * (d % 2);
+        o[d] = onehot4((word >> sh) & 0xFFu) | (onehot4((word >> (sh + 8)) & 0xFFu) << 16);
+      }
       *reinterpret_cast<u32x4*>(&oh[buf][hslot(tid, q)]) = o;
     }
   };
 
   // wave (wi, wj): rows i0 + 64 wi .., columns j0 + 64 wj ..
   const int wi = wave >> 1, wj = wave & 1;
-  i32x4 acc[4][4];  // [j tile][i tile]
+  floatx4_t acc[4][4];  // [j tile][i tile]
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = i32x4{0, 0, 0, 0};
+    for (int b = 0; b < 4; ++b) acc[a][b] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
 
   // The codes of step s + 1 are loaded while step s runs.  (A deeper
   // register prefetch was slower: the step is bound by LDS bandwidth, the
   // operand reads of 16 MFMAs per wave, not by the load latency.)
-  uint32_t w[4];
+  uint32_t w[8];
   load_codes(0, w);
   store_onehot(w, 0);
   __syncthreads();
   for (int s = 0; s < steps; ++s) {
     const int buf = s & 1;
     if (s + 1 < steps) load_codes(s + 1, w);
-    const int pc = lane >> 4;  // operand piece: K bytes 16 pc .. 16 pc + 15
+    const int pc = lane >> 4;  // operand piece: positions 8 pc .. 8 pc + 7 of the step
     u32x4 bi[4], aj[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -123,39 +146,80 @@ __global__ __launch_bounds__(kHThreads, 1) void k_hamming(const uint8_t* __restr
       aj[t] = *reinterpret_cast<const u32x4*>(&oh[buf][hslot(rj, pc)]);
     }
     // A = j rows, B = i rows: lane l then holds matches(j = 4 (l / 16) + e,
-    // i = l % 16) of each tile, four consecutive j of one row i of D
+    // i = l % 16) of each tile, four consecutive j of one row i of D.  The
+    // fp4 operand is the first four words of the 8-word register (format 4 =
+    // e2m1 for both, scale exponents 127 = 1.0)
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(__builtin_bit_cast(i32x4, aj[a]),
-                                                          __builtin_bit_cast(i32x4, bi[b]), acc[a][b], 0, 0, 0);
+      for (int b = 0; b < 4; ++b) {
+        const i32x8 av = {(int)aj[a][0], (int)aj[a][1], (int)aj[a][2], (int)aj[a][3], 0, 0, 0, 0};
+        const i32x8 bv = {(int)bi[b][0], (int)bi[b][1], (int)bi[b][2], (int)bi[b][3], 0, 0, 0, 0};
+        acc[a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc[a][b], 4, 4, 0, 127, 0, 127);
+      }
     if (s + 1 < steps) store_onehot(w, buf ^ 1);
     __syncthreads();
   }
 
+  // (the last step ended with a barrier: the one-hot buffers are free)
+  if constexpr (sizeof(OT) == 4) {
+    // fp32 D: 16 rows of the wave's 64 x 64 block at a time are staged in
+    // its share of the one-hot buffers (rows padded to 68 floats, so that
+    // the 16 rows written at one column fall on distinct banks) and stored
+    // as 256-byte row segments, 4 rows per instruction: whole 128-byte lines
+    float* stg = reinterpret_cast<float*>(&oh[0][0]) + wave * (16 * kHStgRow);
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int64_t i = i0 + wi * 64 + b * 16 + (lane & 15);
-    if (i >= n) continue;
+    for (int b = 0; b < 4; ++b) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int64_t j = j0 + wj * 64 + a * 16 + 4 * (lane >> 4);
-      OT v[4];
+      for (int a = 0; a < 4; ++a) {
+        float4 v;
+        v.x = table[L - (int)acc[a][b][0]];
+        v.y = table[L - (int)acc[a][b][1]];
+        v.z = table[L - (int)acc[a][b][2]];
+        v.w = table[L - (int)acc[a][b][3]];
+        *reinterpret_cast<float4*>(&stg[(lane & 15) * kHStgRow + a * 16 + 4 * (lane >> 4)]) = v;
+      }
+      wave_lds_sync();
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = table[L - acc[a][b][e]];
-      OT* dst = D + i * n + j;
-      if (vec_out && j + 3 < n) {
-        if constexpr (sizeof(OT) == 4) {
-          *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
-        } else {
+      for (int t = 0; t < 4; ++t) {
+        const int r = (lane >> 4) + 4 * t;
+        const int64_t i = i0 + wi * 64 + b * 16 + r;
+        const int64_t j = j0 + wj * 64 + 4 * (lane & 15);
+        const float4 v = *reinterpret_cast<const float4*>(&stg[r * kHStgRow + 4 * (lane & 15)]);
+        if (i < n) {
+          OT* dst = D + i * n + j;
+          if (vec_out && j + 3 < n) {
+            *reinterpret_cast<float4*>(dst) = v;
+          } else {
+            const float e4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (j + e < n) dst[e] = e4[e];
+          }
+        }
+      }
+      wave_lds_sync();  // the stage is read before the next rows are written
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int64_t i = i0 + wi * 64 + b * 16 + (lane & 15);
+      if (i >= n) continue;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int64_t j = j0 + wj * 64 + a * 16 + 4 * (lane >> 4);
+        OT v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = table[L - (int)acc[a][b][e]];
+        OT* dst = D + i * n + j;
+        if (vec_out && j + 3 < n) {
           reinterpret_cast<double2*>(dst)[0] = make_double2(v[0], v[1]);
           reinterpret_cast<double2*>(dst)[1] = make_double2(v[2], v[3]);
-        }
-      } else {
+        } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (j + e < n) dst[e] = v[e];
+          for (int e = 0; e < 4; ++e)
+            if (j + e < n) dst[e] = v[e];
+        }
       }
     }
   }

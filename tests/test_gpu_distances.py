@@ -106,7 +106,7 @@ def test_hamming_full_size_against_generator_and_oracle_rows():
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     say(f"[hamming full] {ms:.2f} ms: {n * n * 4 / ms / 1e6:.0f} GB/s written, "
-        f"{2.0 * n * n * 4 * L / ms / 1e9:.0f} TOPS (one-hot int8)")
+        f"{2.0 * n * n * 4 * L / ms / 1e9:.0f} TFLOP/s (fp4 one-hot)")
     assert torch.equal(D, ref)
     del ref
     rng = np.random.default_rng(5)
