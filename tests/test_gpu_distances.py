@@ -36,7 +36,7 @@ def _codes(n, L, seed, unknown=0):
 
 
 @pytest.mark.parametrize("n,L,unknown", [(1, 400, 0), (2, 16, 0), (7, 1, 0), (300, 400, 5), (1001, 37, 9),
-                                         (513, 400, 0), (260, 2048, 3)])
+                                         (513, 400, 0), (260, 2048, 3), (129, 48, 2), (64, 32, 0)])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_hamming_matches_oracle(n, L, unknown, dtype):
     say(f"[hamming] n={n} L={L} unknown={unknown} dtype={dtype}")
