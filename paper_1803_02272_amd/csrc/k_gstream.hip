@@ -157,7 +157,7 @@ __global__ __launch_bounds__(512, 1) void k_gstream(const uint16_t* __restrict__
     dma_x(clamp(st + XB - 1), xn);
     // the X load goes out first.  (At the top of the loop the compiler adds a
     // wait for the older loads: it does not carry the ring's state across
-    // the back edge.  Six steps per trip make that one step in six.)
+    // the back edge.  Twelve steps per trip make that one step in twelve.)
     __builtin_amdgcn_sched_barrier(0);
     const unsigned char* ga = &gb[wave * kStage];
 #pragma unroll
@@ -186,32 +186,34 @@ __global__ __launch_bounds__(512, 1) void k_gstream(const uint16_t* __restrict__
     settle();
   };
   if constexpr (XB == 3) {
-    for (int64_t st = st0; st < st1; st += 6) {
-      step(st, gs0, xs0, xs2);
-      if (st + 1 >= st1) break;
-      step(st + 1, gs1, xs1, xs0);
-      if (st + 2 >= st1) break;
-      step(st + 2, gs2, xs2, xs1);
-      if (st + 3 >= st1) break;
-      step(st + 3, gs0, xs0, xs2);
-      if (st + 4 >= st1) break;
-      step(st + 4, gs1, xs1, xs0);
-      if (st + 5 >= st1) break;
-      step(st + 5, gs2, xs2, xs1);
+    for (int64_t st = st0; st < st1; st += 12) {
+#pragma unroll
+      for (int u = 0; u < 12; u += 3) {
+        if (st + u >= st1) break;
+        step(st + u, gs0, xs0, xs2);
+        if (st + u + 1 >= st1) break;
+        step(st + u + 1, gs1, xs1, xs0);
+        if (st + u + 2 >= st1) break;
+        step(st + u + 2, gs2, xs2, xs1);
+      }
     }
   } else {
-    for (int64_t st = st0; st < st1; st += 6) {
-      step(st, gs0, xs0, xs1);
-      if (st + 1 >= st1) break;
-      step(st + 1, gs1, xs1, xs0);
-      if (st + 2 >= st1) break;
-      step(st + 2, gs2, xs0, xs1);
-      if (st + 3 >= st1) break;
-      step(st + 3, gs0, xs1, xs0);
-      if (st + 4 >= st1) break;
-      step(st + 4, gs1, xs0, xs1);
-      if (st + 5 >= st1) break;
-      step(st + 5, gs2, xs1, xs0);
+    for (int64_t st = st0; st < st1; st += 12) {
+#pragma unroll
+      for (int u = 0; u < 12; u += 6) {
+        if (st + u >= st1) break;
+        step(st + u, gs0, xs0, xs1);
+        if (st + u + 1 >= st1) break;
+        step(st + u + 1, gs1, xs1, xs0);
+        if (st + u + 2 >= st1) break;
+        step(st + u + 2, gs2, xs0, xs1);
+        if (st + u + 3 >= st1) break;
+        step(st + u + 3, gs0, xs1, xs0);
+        if (st + u + 4 >= st1) break;
+        step(st + u + 4, gs1, xs0, xs1);
+        if (st + u + 5 >= st1) break;
+        step(st + u + 5, gs2, xs1, xs0);
+      }
     }
   }
   __builtin_amdgcn_s_waitcnt(0x0F70);  // no load into LDS outstanding at exit

@@ -168,6 +168,7 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
   }
   const int64_t diag_end = (mb + 1) * kStepsPerBlock;
   const int64_t row0 = mb * kBM + (int64_t)wave * (kRG * 16);
+  const int64_t row0s = mb * kBM + (int64_t)__builtin_amdgcn_readfirstlane(wave) * (kRG * 16);  // in SGPRs
 
   floatx4_t acc[kRG][CG];
 #pragma unroll
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
     float g[4];
     bf16x2v_t v[2][NT];  // planes of the two value pairs
     f32x2 r[2];
-    int64_t i, k0;
+    float fd;  // symmetric mode: K-value of dv[0] minus the row index, clamped to +-64
     int rg, half;
   };
   constexpr int kSliceOps = 4 + 2 * NT - 2;  // 4 recentring + (NT - 1) split phases per value pair
@@ -270,8 +271,11 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
     __builtin_memcpy(S.dv, &dw, 16);
     const int kk = (lane >> 4) * 8 + S.half * 4;  // K-value of dv[0] within the step
     __builtin_memcpy(S.cv, &xa[XINS * 1024 + kk * sizeof(CT)], 4 * sizeof(CT));
-    S.i = row0 + S.rg * 16 + (lane & 15);
-    S.k0 = st * kBK + kk;
+    if constexpr (SYM) {  // a wave-uniform part (scalar) and a lane part
+      const int64_t u = st * kBK - (row0s + S.rg * 16);
+      const int uc = u < -64 ? -64 : (u > 64 ? 64 : (int)u);
+      S.fd = (float)(uc + kk - (lane & 15));
+    }
   };
   // fused write: bf16 G of the lane's row and K-values 8j .. 8j + 7 (j = lane / 16)
   // of the step being split (gcur) and of the step before it (gprev)
@@ -299,10 +303,8 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
         const float d2 = S.dv[t] * S.dv[t];
         const float c = SYM ? S.cv[t] + S.cv[t] : S.cv[t];
         float g = __builtin_fmaf(SYM ? -1.0f : -0.5f, d2, c + ri[S.rg]);
-        if (SYM) {  // weights 1, 1/2, 0 right of, on and left of the diagonal
-          const int64_t jj = S.k0 + t;
-          g = jj > S.i ? g : (jj == S.i ? 0.5f * g : 0.0f);
-        }
+        if (SYM)  // weights 1, 1/2, 0 right of, on and left of the diagonal: clamp(k - i + 1/2, 0, 1)
+          g *= __builtin_fminf(__builtin_fmaxf(S.fd + (t + 0.5f), 0.0f), 1.0f);
         S.g[t] = g;
       }
     } else {
