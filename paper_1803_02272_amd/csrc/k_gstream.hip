@@ -19,9 +19,10 @@
 //     two steps ahead, into a three-buffer ring shared by the eight waves
 //     (one barrier per step); above l_pad = 128 the ring has two buffers
 //     and the tile is loaded one step ahead;
-//   * 16-byte pieces of a 128-byte row r sit in slot piece ^ f(r),
-//     f(r) = (r % 8) ^ ((r / 8) % 2): the MFMA operand reads (16 rows at one
-//     piece) then fall on distinct banks for 8 and for 16 lanes at a time.
+//   * 16-byte pieces of a 128-byte row r sit in slot piece ^ (r % 8): the
+//     MFMA operand reads (lane l: row l % 16, piece l / 16) then run at the
+//     full rate of gfx950's 64-bank LDS (measured on MI355X: with slot
+//     piece ^ (r % 8) ^ ((r / 8) % 2) the same reads take 1.6 times as long).
 // Requires l_pad <= 224, ldg a multiple of 256 and n_pad = ldg rows of G.
 #include "mds_internal.h"
 
@@ -46,7 +47,7 @@ template <int AUX>
 __device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t r, uint32_t voff, void* l) {
   __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)l, 16, voff, 0, 0, AUX);
 }
-__device__ __forceinline__ int swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+__device__ __forceinline__ int swz(int r) { return r & 7; }
 
 // XB: X buffers, 3 (X loaded two steps ahead) up to l_pad = 128; 2 (one
 // step ahead) for the wider tiles, whose three buffers would not fit in LDS

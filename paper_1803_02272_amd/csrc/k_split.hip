@@ -34,8 +34,8 @@
 //   * the X tile of a step (the pass's bf16 planes, 64 bytes per row each), and with
 //     it the recentring terms of the following step (c_k / 2, or c_k in
 //     fp64), are loaded the same way into one of two LDS buffers shared by
-//     the eight waves; the tile is swizzled so that 16 consecutive rows read
-//     distinct banks;
+//     the eight waves; K-group kg of row r sits in slot kg ^ ((r / 2) % 4),
+//     so that the B-operand reads run at the LDS's full rate;
 //   * the split A operands of step st + 1 are computed during step st, in
 //     slices placed between the MFMAs of step st, so that the recentring
 //     and splitting VALU work runs in the MFMA shadow rather than between
@@ -203,12 +203,14 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
   // per-lane offsets of step 0.  D: load q (0..3) of a wave covers its rows
   // 8q .. 8q + 7 as whole 128-byte lines (8 lanes per row); lane l lands at
   // LDS slot l = 8 (row % 8) + slot and brings piece (16 bytes, 4 K-values)
-  // slot ^ (row % 8) of its row, so that the A-operand reads below, 16 rows
-  // at one K-piece, fall on distinct banks.
+  // slot ^ f(row) of its row, f(r) = (r % 8) ^ ((r / 8) % 2), so that the
+  // A-operand reads below (lane l: row l % 16, piece 2 (l / 16) + half) run at
+  // the full rate of gfx950's 64-bank LDS (measured on MI355X: with
+  // f(r) = r % 8 they take 1.6 times as long).
   uint32_t d_off[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int rr = lane >> 3, piece = (lane & 7) ^ rr;
+    const int rr = lane >> 3, piece = (lane & 7) ^ rr ^ (q & 1);
     d_off[q] = (uint32_t)((((int64_t)wave * (kRG * 16) + q * 8 + rr) * n + piece * 4) * 4);
   }
   constexpr int XPW = (XINS + kWaves - 1) / kWaves;  // X tile loads per wave
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
     const int q = wave + u * kWaves;
     const int S = q * 64 + lane;
     const int p = S / (LPAD * 4), rem = S % (LPAD * 4);
-    const int row = rem >> 2, kg = (rem & 3) ^ ((row >> 2) & 3);
+    const int row = rem >> 2, kg = (rem & 3) ^ ((row >> 1) & 3);
     x_off[u] = (uint32_t)((int64_t)row * ldg * 6 + p * 64 + kg * 16);
   }
 
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
       dma16(rC, (uint32_t)(stc * kBK * (int)sizeof(CT)) + lane * 16, &xd[XINS * 1024]);
   };
   // X tile of step st: slot S = q * 64 + lane holds plane p, row, K-group kg
-  // at S = p * 4 LPAD + 4 row + (kg ^ ((row >> 2) & 3)); then the terms of stc
+  // at S = p * 4 LPAD + 4 row + (kg ^ ((row >> 1) & 3)); then the terms of stc
   auto dma_x = [&](int64_t st, int64_t stc, unsigned char (&xd)[XBYTES]) {
 #pragma unroll
     for (int u = 0; u < XPW; ++u) {
@@ -267,7 +269,7 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
     // this lane's row r of the wave's 32 and K-piece pc (see d_off)
     const int r = S.rg * 16 + (lane & 15), pc = 2 * (lane >> 4) + S.half;
     const u32x4 dw = *reinterpret_cast<const u32x4*>(
-        &dd[wave * DSTAGE + (r >> 3) * 1024 + (r & 7) * 128 + ((pc ^ (r & 7)) * 16)]);
+        &dd[wave * DSTAGE + (r >> 3) * 1024 + (r & 7) * 128 + ((pc ^ (r & 7) ^ ((r >> 3) & 1)) * 16)]);
     __builtin_memcpy(S.dv, &dw, 16);
     const int kk = (lane >> 4) * 8 + S.half * 4;  // K-value of dv[0] within the step
     __builtin_memcpy(S.cv, &xa[XINS * 1024 + kk * sizeof(CT)], 4 * sizeof(CT));
@@ -405,7 +407,7 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
       for (int h = 0; h < 2; ++h)
         if (cg0 + h < CG) {
           const int row = (cg0 + h) * 16 + (lane & 15);
-          const int kgs = (lane >> 4) ^ ((row >> 2) & 3);
+          const int kgs = (lane >> 4) ^ ((row >> 1) & 3);
 #pragma unroll
           for (int p = 0; p < NTB; ++p)
             bb[h][p] = *reinterpret_cast<const u32x4*>(&xr[(p * LPAD * 4 + row * 4 + kgs) * 16]);
