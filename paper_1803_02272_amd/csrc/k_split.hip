@@ -17,7 +17,9 @@
 //   kFull  Y = G X over all of D, gamma = fma(-1/2, fl32(d^2), hc_k + hr_i)
 //          with hc_k = fl32(c_k / 2), hr_i = fl32((r_i - m) / 2);
 //   kSym   the projection's symmetric pass, 2 (W o G) X over the upper
-//          triangle of D (W = 1 above, 1/2 on, 0 below the diagonal);
+//          triangle of D (W = 1 above, 1/2 on, 0 below the diagonal),
+//          accumulated as (W o G) X from the kFull gamma and doubled at the
+//          end (exactly the doubled terms' sum: scaling by 2 is exact);
 //   kWrite the fused centring write: gamma in fp64 from the centring
 //          equation, g = fl32(gamma) stored as bf16(g) into G (the padding
 //          outside n x n is zeroed by a separate small kernel) and split for
@@ -181,13 +183,13 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
   const float* Dp = reinterpret_cast<const float*>(src.D);
   const int64_t n = src.n;
   const double mval = src.m[0];
-  float ri[kRG];   // hr_i = fl32((r_i - m) / 2) (symmetric mode: 2 hr_i, exact)
+  float ri[kRG];   // hr_i = fl32((r_i - m) / 2)
   double rd[kRG];  // fused write: (r_i - m) / 2 in fp64
 #pragma unroll
   for (int rg = 0; rg < kRG; ++rg) {
     const int64_t i = row0 + rg * 16 + (lane & 15);
     const float h = (i < n) ? (float)(0.5 * (src.r[i] - mval)) : 0.0f;
-    ri[rg] = SYM ? h + h : h;
+    ri[rg] = h;
     rd[rg] = (WG && i < n) ? 0.5 * (src.r[i] - mval) : 0.0;
   }
   // Buffer resources (32-bit offsets, reads past the end return zeros):
@@ -303,8 +305,7 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
         }
       } else {
         const float d2 = S.dv[t] * S.dv[t];
-        const float c = SYM ? S.cv[t] + S.cv[t] : S.cv[t];
-        float g = __builtin_fmaf(SYM ? -1.0f : -0.5f, d2, c + ri[S.rg]);
+        float g = __builtin_fmaf(-0.5f, d2, S.cv[t] + ri[S.rg]);
         if (SYM)  // weights 1, 1/2, 0 right of, on and left of the diagonal: clamp(k - i + 1/2, 0, 1)
           g *= __builtin_fminf(__builtin_fmaxf(S.fd + (t + 0.5f), 0.0f), 1.0f);
         S.g[t] = g;
@@ -493,6 +494,7 @@ __global__ __launch_bounds__(512, 1) void k_split(const uint16_t* __restrict__ X
       float* dst = Ypart + ((int64_t)s * LPAD + col) * ldg + row0 + rg * 16;
       const int64_t i4 = row0 + rg * 16 + 4 * (lane >> 4);
       float4 o = make_float4(acc[rg][cg][0], acc[rg][cg][1], acc[rg][cg][2], acc[rg][cg][3]);
+      if constexpr (SYM) o = o + o;  // 2 (W o G) X: the doubling is exact, as in every term
       if (i4 + 3 >= n) {
         o.x = i4 < n ? o.x : 0.0f;
         o.y = i4 + 1 < n ? o.y : 0.0f;
