@@ -274,6 +274,7 @@ __global__ __launch_bounds__(256) void k_cast(const double* __restrict__ In, int
 // tile (64 columns) spread the work over more CUs.
 constexpr int kApJ = 64;
 constexpr int kApRow = kApJ + 2;  // LDS row stride (doubles)
+constexpr int kApPf = 8;          // steps of In rows in flight
 
 template <int NN, int NTH>
 __global__ __launch_bounds__(NTH) void k_apply(const double* __restrict__ In, int l, int64_t ldg,
@@ -296,24 +297,32 @@ __global__ __launch_bounds__(NTH) void k_apply(const double* __restrict__ In, in
     for (int t = 0; t < 4; ++t) acc[nt][t] = doublex4_t{0.0, 0.0, 0.0, 0.0};
   const double* Ib = In + (int64_t)(lane >> 4) * ldg + i0 + (lane & 15);
   const int ar = lane >> 4, jc = lane & 15;
-  // software pipeline: the In rows of step a0 + 4 load while step a0 runs
-  double b[NN];
+  // software pipeline: a ring of kApPf steps of In rows in registers, step
+  // a + 4 kApPf loading while step a runs (the loop is latency-bound: a step
+  // is 4 NN MFMAs against a round trip to memory)
+  double b[kApPf][NN];
 #pragma unroll
-  for (int nt = 0; nt < NN; ++nt) b[nt] = Ib[nt * 16];
-  for (int a0 = 0; a0 < la; a0 += 4) {
-    double bn[NN];
-    const bool more = a0 + 4 < la;
+  for (int p = 0; p < kApPf; ++p)
 #pragma unroll
-    for (int nt = 0; nt < NN; ++nt) bn[nt] = more ? Ib[(int64_t)(a0 + 4) * ldg + nt * 16] : 0.0;
+    for (int nt = 0; nt < NN; ++nt) b[p][nt] = Ib[(int64_t)(4 * p < la ? 4 * p : la - 4) * ldg + nt * 16];
+  for (int a0 = 0; a0 < la; a0 += 4 * kApPf) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const double av = Ts[(a0 + ar) * kApRow + t * 16 + jc];
+    for (int p = 0; p < kApPf; ++p) {
+      const int a = a0 + 4 * p;
+      if (a >= la) break;
 #pragma unroll
-      for (int nt = 0; nt < NN; ++nt)
-        acc[nt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[nt], acc[nt][t], 0, 0, 0);
+      for (int t = 0; t < 4; ++t) {
+        const double av = Ts[(a + ar) * kApRow + t * 16 + jc];
+#pragma unroll
+        for (int nt = 0; nt < NN; ++nt)
+          acc[nt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[p][nt], acc[nt][t], 0, 0, 0);
+      }
+      // past the end the last step is loaded again (rows < la exist): the
+      // loads stay unconditional, so the compiler keeps exact wait counts
+      const int an = a + 4 * kApPf < la ? a + 4 * kApPf : la - 4;
+#pragma unroll
+      for (int nt = 0; nt < NN; ++nt) b[p][nt] = Ib[(int64_t)an * ldg + nt * 16];
     }
-#pragma unroll
-    for (int nt = 0; nt < NN; ++nt) b[nt] = bn[nt];
   }
   // fp64 accumulator layout: register r of lane group g is row g + 4r
 #pragma unroll
