@@ -505,7 +505,12 @@ __global__ __launch_bounds__(256) void k_tri_ql(int l, int l_pad, int k, double*
       int i = m - 1;
       bool split = false;
       for (; i >= l0; --i) {
-        const double en = i > l0 ? ee[i - 1] : 0.0, dn = i > l0 ? dd[i - 1] : 0.0;
+        // the next rotation's inputs, loaded unconditionally (index clamped,
+        // the value replaced by 0 at the end of the block) so that the load
+        // overlaps this rotation instead of being waited for at its start
+        const bool more = i > l0;
+        const int inx = more ? i - 1 : i;
+        const double en_l = ee[inx], dn_l = dd[inx];
         const double f = s * ei, bb = c * ei;
         const double t2 = f * f + g * g;
         if (t2 == 0.0) {  // the block splits at i + 1: finish with the rotations so far
@@ -527,8 +532,8 @@ __global__ __launch_bounds__(256) void k_tri_ql(int l, int l_pad, int k, double*
         g = c * r - bb;
         rot[nrot++] = make_double2(c, s);
         di1 = di;
-        di = dn;
-        ei = en;
+        di = more ? dn_l : 0.0;
+        ei = more ? en_l : 0.0;
       }
       if (!split) {
         dd[l0] -= p;
