@@ -133,60 +133,68 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(const double* __restrict_
 }
 
 // Register-streamed variant for l_pad > 128 (the LDS tiles of k_gram would
-// need too many accumulators per wave): each wave owns a 16-row tile strip
-// over one column chunk; SYM (A == B): only the tiles on or above the
+// need too many accumulators per wave): each wave owns half of a 16-row tile
+// strip over one column chunk; SYM (A == B): only the tiles on or above the
 // diagonal are computed (the strip's B loads and MFMAs left of it are
 // skipped), as in k_gram.
 template <int CG, bool SYM>
 __global__ __launch_bounds__(256) void k_gram_wide(const double* __restrict__ A, const double* __restrict__ B,
                                               int64_t ldg, int l_pad, double* __restrict__ Wpart, int64_t chunk) {
+  // each wave owns half of a 16-row tile strip (HALF tiles of 16 columns):
+  // the accumulators and operand registers of half a strip let three waves
+  // share a SIMD, which hides the operand loads of one another
+  constexpr int HALF = (CG + 1) / 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tr = blockIdx.y * 4 + wave;  // 16-row tile of W
-  if (tr * 16 >= l_pad) return;          // no barriers below
+  const int w = blockIdx.y * 4 + wave;
+  const int tr = w >> 1;              // 16-row tile of W
+  const int c0 = (w & 1) * HALF;      // first 16-column tile of this half
+  if (tr * 16 >= l_pad) return;       // no barriers below
+  if (SYM && c0 + HALF <= tr) return;  // the half lies left of the diagonal
   const int64_t p = blockIdx.x;
   const int64_t i0 = p * chunk;
   const int64_t i1 = (i0 + chunk < ldg) ? i0 + chunk : ldg;
-  doublex4_t acc[CG];
+  doublex4_t acc[HALF];
 #pragma unroll
-  for (int cg = 0; cg < CG; ++cg) acc[cg] = doublex4_t{0.0, 0.0, 0.0, 0.0};
+  for (int h = 0; h < HALF; ++h) acc[h] = doublex4_t{0.0, 0.0, 0.0, 0.0};
+  auto live = [&](int h) { return c0 + h < CG && (!SYM || c0 + h >= tr); };
   const double* Ar = A + (int64_t)(tr * 16 + (lane & 15)) * ldg + (lane >> 4) * 2;
-  const double* Br = B + (int64_t)(lane & 15) * ldg + (lane >> 4) * 2;
+  const double* Br = B + (int64_t)(c0 * 16 + (lane & 15)) * ldg + (lane >> 4) * 2;
   // software pipeline: the operands of step k+8 are loaded while step k runs
   double2 a = *reinterpret_cast<const double2*>(Ar + i0);
-  double2 b[CG];
+  double2 b[HALF];
 #pragma unroll
-  for (int cg = 0; cg < CG; ++cg)
-    if (!SYM || cg >= tr) b[cg] = *reinterpret_cast<const double2*>(Br + (int64_t)cg * 16 * ldg + i0);
+  for (int h = 0; h < HALF; ++h)
+    if (live(h)) b[h] = *reinterpret_cast<const double2*>(Br + (int64_t)h * 16 * ldg + i0);
   for (int64_t k = i0; k < i1; k += 8) {
     const bool more = k + 8 < i1;
-    double2 an = a, bn[CG];
+    double2 an = a, bn[HALF];
     if (more) {
       an = *reinterpret_cast<const double2*>(Ar + k + 8);
 #pragma unroll
-      for (int cg = 0; cg < CG; ++cg)
-        if (!SYM || cg >= tr) bn[cg] = *reinterpret_cast<const double2*>(Br + (int64_t)cg * 16 * ldg + k + 8);
+      for (int h = 0; h < HALF; ++h)
+        if (live(h)) bn[h] = *reinterpret_cast<const double2*>(Br + (int64_t)h * 16 * ldg + k + 8);
     }
 #pragma unroll
-    for (int cg = 0; cg < CG; ++cg)
-      if (!SYM || cg >= tr) {
-        acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[cg].x, acc[cg], 0, 0, 0);
-        acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b[cg].y, acc[cg], 0, 0, 0);
+    for (int h = 0; h < HALF; ++h)
+      if (live(h)) {
+        acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b[h].x, acc[h], 0, 0, 0);
+        acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b[h].y, acc[h], 0, 0, 0);
       }
     if (more) {
       a = an;
 #pragma unroll
-      for (int cg = 0; cg < CG; ++cg)
-        if (!SYM || cg >= tr) b[cg] = bn[cg];
+      for (int h = 0; h < HALF; ++h)
+        if (live(h)) b[h] = bn[h];
     }
   }
   double* W = Wpart + p * (int64_t)l_pad * l_pad;
 #pragma unroll
-  for (int cg = 0; cg < CG; ++cg)
-    if (!SYM || cg >= tr)
+  for (int h = 0; h < HALF; ++h)
+    if (live(h))
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-      // fp64 MFMA accumulator: register r of lane group g is row g + 4r
-      W[(int64_t)(tr * 16 + (lane >> 4) + 4 * r) * l_pad + cg * 16 + (lane & 15)] = acc[cg][r];
+        // fp64 MFMA accumulator: register r of lane group g is row g + 4r
+        W[(int64_t)(tr * 16 + (lane >> 4) + 4 * r) * l_pad + (c0 + h) * 16 + (lane & 15)] = acc[h][r];
 }
 
 // out[i][j] = sum_p parts[p][i][j]; sym: only entries of tiles on or above the
@@ -449,7 +457,7 @@ void gram_one(const double* A, const double* B, int l_pad, int64_t ldg, double* 
   const int64_t chunk = gram_chunk_cols(ldg);
   dim3 grid((unsigned)((ldg + chunk - 1) / chunk));
   if constexpr (CG > 8) {
-    const dim3 wg(grid.x, (unsigned)((CG + 3) / 4));
+    const dim3 wg(grid.x, (unsigned)((2 * CG + 3) / 4));  // two waves (half strips) per 16-row tile strip
     if (A == B)
       hipLaunchKernelGGL((k_gram_wide<CG, true>), wg, dim3(256), 0, s, A, B, ldg, l_pad, Wpart, chunk);
     else
