@@ -287,12 +287,18 @@ constexpr int kApPf = 8;          // steps of In rows in flight
 template <int NN, int NTH>
 __global__ __launch_bounds__(NTH) void k_apply(const double* __restrict__ In, int l, int64_t ldg,
                                                const double* __restrict__ T, int ldt, int lt, int l_out,
-                                               double* __restrict__ Out) {
+                                               double* __restrict__ Out, int gx, int jb) {
   extern __shared__ double Ts[];  // la x kApRow
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int la = (l + 3) & ~3;
-  const int j0 = blockIdx.y * kApJ;
-  const int64_t i0 = (int64_t)blockIdx.x * ((NTH / 64) * 16 * NN) + wave * (16 * NN);
+  // the jb column blocks of one strip of rows i go to one XCD (workgroup wg
+  // runs on XCD wg % 8) one after another in dispatch order, so all but the
+  // first read that strip of In from the XCD's L2
+  const int wg = blockIdx.x, wq = wg >> 3;
+  const int bx = (wq / jb) * 8 + (wg & 7), by = wq % jb;
+  if (bx >= gx) return;  // uniform: the grid is padded to a multiple of 8 strips
+  const int j0 = by * kApJ;
+  const int64_t i0 = (int64_t)bx * ((NTH / 64) * 16 * NN) + wave * (16 * NN);
   for (int e = tid; e < la * kApJ; e += NTH) {
     const int a = e / kApJ, jj = e % kApJ, j = j0 + jj;
     Ts[a * kApRow + jj] = (a < l && j < lt) ? T[(int64_t)a * ldt + j] : 0.0;
@@ -507,13 +513,14 @@ hipError_t launch_apply(const double* In, int l, int64_t ldg, const double* T, i
     (void)hipFuncSetAttribute((const void*)k_apply<1, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     attr_set = true;
   }
-  const unsigned jb = (unsigned)((l_pad + kApJ - 1) / kApJ);
-  if (ldg / kWide >= 128)
-    hipLaunchKernelGGL((k_apply<2, 512>), dim3((unsigned)(ldg / kWide), jb), dim3(512), shm, s, In, l, ldg, T, ldt,
-                       lt, l_pad, Out);
+  const int jb = (l_pad + kApJ - 1) / kApJ;
+  const bool wide = ldg / kWide >= 128;
+  const int gx = (int)(ldg / (wide ? kWide : kNarrow));
+  const dim3 grid((unsigned)(((gx + 7) / 8) * 8 * jb));
+  if (wide)
+    hipLaunchKernelGGL((k_apply<2, 512>), grid, dim3(512), shm, s, In, l, ldg, T, ldt, lt, l_pad, Out, gx, jb);
   else
-    hipLaunchKernelGGL((k_apply<1, 256>), dim3((unsigned)(ldg / kNarrow), jb), dim3(256), shm, s, In, l, ldg, T, ldt,
-                       lt, l_pad, Out);
+    hipLaunchKernelGGL((k_apply<1, 256>), grid, dim3(256), shm, s, In, l, ldg, T, ldt, lt, l_pad, Out, gx, jb);
   if (Xc) {
     // the cast copy in its own elementwise kernel (fewer registers in k_apply)
     const int64_t elems = (int64_t)l_pad * ldg;
