@@ -791,12 +791,39 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const AccS* __restrict__ 
     const int64_t row = e % ldg;  // e..e+3 share the row block (ldg and bm are multiples of 4)
     k0 = (int)(((row / sym_bm) * sym_bm) / sym_cols_per_split);
   }
-  for (int k = k0; k < split; ++k) {
+  // the four entries of a partial as one vector load (partials start on
+  // 256-byte boundaries and e is a multiple of 4); four partials' loads are
+  // issued before their sums, which still run in split order
+  auto ld4 = [&](int k, double (&v)[4]) {
     const AccS* p = Yp + (int64_t)k * elems + e;
-    s0 += (double)p[0];
-    s1 += (double)p[1];
-    s2 += (double)p[2];
-    s3 += (double)p[3];
+    if constexpr (sizeof(AccS) == 4) {
+      const float4 f = *reinterpret_cast<const float4*>(p);
+      v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+    } else {
+      const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+      v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    }
+  };
+  int k = k0;
+  for (; k + 4 <= split; k += 4) {
+    double v[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ld4(k + u, v[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      s0 += v[u][0];
+      s1 += v[u][1];
+      s2 += v[u][2];
+      s3 += v[u][3];
+    }
+  }
+  for (; k < split; ++k) {
+    double v[4];
+    ld4(k, v);
+    s0 += v[0];
+    s1 += v[1];
+    s2 += v[2];
+    s3 += v[3];
   }
   reinterpret_cast<double2*>(Y + e)[0] = make_double2(s0, s1);
   reinterpret_cast<double2*>(Y + e)[1] = make_double2(s2, s3);
