@@ -54,6 +54,7 @@ TRAFFIC = {
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
 PEAK_FP4_TFLOPS = 10100.0
+PEAK_FP64_VECTOR_TOPS = 39.3216  # Tops/s of non-fused fp64 vector ops: 256 CUs x 64 lanes x 2.4 GHz
 
 
 def measured_traffic(name, n, l_pad, form):
@@ -291,6 +292,26 @@ def time_distances(mds, torch, codes, D):
             "fp4_tflops": ops / ms / 1e9, "fp4_frac": ops / ms / 1e9 / PEAK_FP4_TFLOPS}
 
 
+def time_euclidean(mds, torch, D, dim, comps, var):
+    """mds_euclidean_distances at the low-precision stress shape (n points of
+    a Gaussian mixture in dim dimensions), written into D's memory: n^2 fp32
+    entries written; 3 n^2 dim / 2 fp64 vector operations over the tiles on
+    and above the diagonal (a subtraction, a square and an add per
+    coordinate, no fused multiply-add), against the non-fused fp64 vector
+    rate of 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 Tops/s."""
+    from workloads import gaussian_mixture
+
+    n = D.shape[0]
+    X, _ = gaussian_mixture(n, dim, comps, var, seed=0)
+    xt = torch.from_numpy(X).cuda()
+    ms = _event_ms(torch, lambda: mds.euclidean_distances(xt, out=D))
+    del xt
+    wbytes, ops = 4.0 * n * n, 1.5 * n * n * dim
+    return {"kernel": "k_euclid (64 x 64 tiles on and above the diagonal, fp64 vector, D written in fp32)",
+            "ms": ms, "n": n, "dim": dim, "write_gbs": wbytes / ms / 1e6, "hbm_frac": wbytes / ms / 1e6 / PEAK_HBM_GBS,
+            "fp64_vector_tops": ops / ms / 1e9, "alu_frac": ops / ms / 1e9 / PEAK_FP64_VECTOR_TOPS}
+
+
 def time_components(mds, torch, D, theta):
     """mds_threshold_components over the upper triangle of D: 2 n (n - 1)
     bytes of fp32 entries read."""
@@ -389,6 +410,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--euclid-dim", type=int, default=200,
+                    help="dimension of the points for the Euclidean distance timing (0: skip)")
     ap.add_argument("--cc-threshold", type=float, default=0.03,
                     help="threshold of the components measurement (distance units)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -623,6 +646,12 @@ def main():
         log(f"[bench] cpu baseline: {line['cpu_baseline']}")
     else:
         line["cpu_baseline"] = None
+    line["distances_euclidean"] = None
+    if args.euclid_dim > 0:
+        # last use of D's memory (after the MDS runs and the CPU baseline):
+        # the Euclidean kernel overwrites it
+        line["distances_euclidean"] = time_euclidean(mds, torch, D, args.euclid_dim, 50, 9.0)
+        log(f"[bench] euclidean distances: {line['distances_euclidean']}")
     del D
     torch.cuda.empty_cache()
     if args.serve_seconds > 0:
