@@ -29,7 +29,6 @@ if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_1803_02272_amd as mds  # noqa: E402
-from workloads import gpu as WG  # noqa: E402
 
 N, DIM, COMPS, VAR, K, P, Q = 240000, 100, 20, 9.0, 100, 20, 1
 
@@ -45,8 +44,10 @@ def test_fp32_form_beyond_stored_g_capacity():
     X, _ = W.gaussian_mixture(N, DIM, COMPS, VAR, seed=5)
     Xc = X - X.mean(axis=0, keepdims=True)
     sig2 = np.sort(np.linalg.eigvalsh(Xc.T @ Xc))[::-1]  # nonzero spectrum of G = Xc Xc^T
-    D = WG.euclidean_from_points(X)
-    say(f"[scale] cloud spectrum {sig2[0]:.4e} .. {sig2[-1]:.4e}; D generated ({time.time() - t0:.0f} s)")
+    D = mds.euclidean_distances(torch.from_numpy(X).cuda())  # the library's distance kernel
+    torch.cuda.synchronize()
+    say(f"[scale] cloud spectrum {sig2[0]:.4e} .. {sig2[-1]:.4e}; D by mds_euclidean_distances "
+        f"({time.time() - t0:.0f} s)")
     for split in (False, True):
         plan = mds.Plan(N, K, P, Q, 0, form="fp32", split_fp32=split)
         ws = plan.workspace_size()
