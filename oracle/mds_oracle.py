@@ -50,6 +50,7 @@ __all__ = [
     "gram_matrix",
     "gram_entries",
     "full_mds",
+    "jacobi_eigh",
     "rand_mds",
     "orthonormal_basis",
     "normalise_column_signs",
@@ -413,6 +414,47 @@ def _sorted_eigh(A: np.ndarray):
     return w[order], V[:, order]
 
 
+def jacobi_eigh(A: np.ndarray, tol: float = 1e-15, max_sweeps: int = 60):
+    """Eigenpairs of a symmetric matrix by the cyclic Jacobi method, for small
+    matrices (pure Python loops over the pairs).
+
+    Each sweep visits the pairs (p, q), p < q, row by row; for a nonzero
+    a_pq the 2 x 2 symmetric Schur rotation J (c = 1 / sqrt(1 + t^2),
+    s = t c, t the smaller root of t^2 + 2 tau t - 1 = 0 with
+    tau = (a_qq - a_pp) / (2 a_pq)) zeroes a_pq in A <- J^T A J, and the
+    rotations accumulate in V <- V J (Golub and Van Loan, Matrix
+    Computations, the symmetric Schur decomposition and the cyclic Jacobi
+    method).  Sweeps stop once the off-diagonal Frobenius norm is at most
+    tol times the Frobenius norm of A.  Returns the eigenvalues in algebraic
+    descending order (stable on ties) and the eigenvectors as columns."""
+    A = np.array(A, dtype=np.float64, copy=True)
+    n = A.shape[0]
+    V = np.eye(n)
+    scale = np.sqrt(np.sum(A * A))
+    for _ in range(max_sweeps):
+        off = np.sqrt(2.0 * np.sum(np.triu(A, 1) ** 2))  # summed directly: no cancellation
+        if off <= tol * scale:
+            break
+        for p in range(n - 1):
+            for q in range(p + 1, n):
+                apq = A[p, q]
+                if apq == 0.0:
+                    continue
+                tau = (A[q, q] - A[p, p]) / (2.0 * apq)
+                t = (1.0 if tau >= 0.0 else -1.0) / (abs(tau) + np.sqrt(1.0 + tau * tau))
+                c = 1.0 / np.sqrt(1.0 + t * t)
+                s = t * c
+                cp, cq = A[:, p].copy(), A[:, q].copy()  # A J
+                A[:, p], A[:, q] = c * cp - s * cq, s * cp + c * cq
+                rp, rq = A[p, :].copy(), A[q, :].copy()  # J^T (A J)
+                A[p, :], A[q, :] = c * rp - s * rq, s * rp + c * rq
+                vp, vq = V[:, p].copy(), V[:, q].copy()
+                V[:, p], V[:, q] = c * vp - s * vq, s * vp + c * vq
+    w = np.diag(A).copy()
+    order = np.argsort(-w, kind="stable")
+    return w[order], V[:, order]
+
+
 def orthonormal_basis(Y: np.ndarray) -> np.ndarray:
     """Orthonormal basis of range(Y) by Householder QR (LAPACK geqrf/orgqr).
     Only span(Q) matters to the method; the GPU library may use another
@@ -425,13 +467,20 @@ def orthonormal_basis(Y: np.ndarray) -> np.ndarray:
 # Exact classical MDS (Sec. 6.2, steps 1-3)
 # ---------------------------------------------------------------------------
 
-def full_mds(D, k: int):
-    """Exact classical MDS through a full symmetric eigendecomposition of G.
+def full_mds(D, k: int, method: str = "eigh"):
+    """Exact classical MDS through a full symmetric eigendecomposition of G
+    (LAPACK, or with method="jacobi" the cyclic Jacobi method of
+    ``jacobi_eigh``, for small n).
 
     Returns dict with eigvals (top k, algebraic descending), all eigenvalues,
     coords X_k = U_k diag(sqrt(max(lambda, 0))) (sign-normalised), and G."""
     G = gram_matrix(D)
-    lam, U = _sorted_eigh(G)
+    if method == "jacobi":
+        lam, U = jacobi_eigh(G)
+    elif method == "eigh":
+        lam, U = _sorted_eigh(G)
+    else:
+        raise ValueError(f"unknown method {method!r}")
     X = U[:, :k] * np.sqrt(np.maximum(lam[:k], 0.0))[None, :]
     return {"eigvals": lam[:k].copy(), "eigvals_all": lam, "coords": normalise_column_signs(X),
             "G": G}
